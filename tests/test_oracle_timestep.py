@@ -1,0 +1,53 @@
+"""Pins of the oracle's implicit Euler stepping."""
+import numpy as np
+
+from ccscenes import tet_bar
+from oracle import solvers as S
+from oracle.basis import exact_basis
+from oracle.fem import Problem
+from oracle.timestep import newton_step, step
+
+
+def _free_body(E=1e5, grav=(0.0, -9.81, 0.0)):
+    s = tet_bar(5, 3, 3, E=E, gravity=grav)
+    s.fixed[:] = 0
+    return s, Problem.from_scene(s)
+
+
+def test_momentum_balance_free_body():
+    """Internal forces cancel: sum m v^{t+1} = sum m v^t + h sum m g."""
+    s, p = _free_body()
+    rng = np.random.default_rng(2)
+    x = p.X + 0.01 * rng.normal(size=p.X.shape)
+    v = rng.normal(size=p.X.shape)
+    x1, v1, res = newton_step(p, x, v, s.targets(1), tol=1e-12)
+    lhs = (p.mass[:, None] * v1).sum(axis=0)
+    rhs = (p.mass[:, None] * v).sum(axis=0) + p.h * p.mass.sum() * np.array([0.0, -9.81, 0.0])
+    assert np.max(np.abs(lhs - rhs)) <= 1e-8 * np.max(np.abs(p.mass[:, None] * v).sum())
+
+
+def test_rest_without_gravity_stays_at_rest():
+    s = tet_bar(5, 3, 3, gravity=(0.0, 0.0, 0.0))
+    p = Problem.from_scene(s)
+    B = exact_basis(p)
+    x, v = s.initial_state()
+    prm = S.Params(method=S.CC, sweep=S.JACOBI)
+    x1, v1, res, _ = step(p, x, v, s.targets(1), B, prm, 1e-6)
+    assert res.iters == 0
+    assert np.array_equal(x1, p.X) and np.all(v1 == 0.0)
+
+
+def test_warm_start_acceptance_rule():
+    s = tet_bar(6, 3, 3, E=1e5)
+    p = Problem.from_scene(s)
+    B = exact_basis(p)
+    x, v = s.initial_state()
+    prm = S.Params(method=S.CC, sweep=S.JACOBI)
+    xs, _, r0, acc0 = step(p, x, v, s.targets(1), B, prm, 1e-8)
+    # the converged state is an excellent proposal and must be accepted
+    _, _, r1, acc1 = step(p, x, v, s.targets(1), B, prm, 1e-8, proposal=xs)
+    assert acc1 and r1.iters < r0.iters
+    # a wild proposal raises E and must be rejected
+    bad = p.X + 0.3 * np.random.default_rng(0).normal(size=p.X.shape)
+    _, _, r2, acc2 = step(p, x, v, s.targets(1), B, prm, 1e-8, proposal=bad)
+    assert not acc2 and r2.iters == r0.iters

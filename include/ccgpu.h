@@ -1,0 +1,185 @@
+/*
+ * ccgpu -- Coordinate Condensation on AMD MI355X (gfx950), C ABI.
+ *
+ * The library advances implicit-Euler elastodynamics by minimising the step
+ * energy E(x) = 1/2 (x - x~)^T M (x - x~) + h^2 Psi(x)  (paper: Background,
+ * "Optimization-Based Integration") with Coordinate Condensation: per-vertex
+ * local solves augmented by a precomputed perturbation subspace and condensed
+ * by a Schur complement (paper: Method, Eqs. displacement, block, update and
+ * schur; Algorithm 1).  Psi is the stable neo-Hookean energy
+ * mu/2(|F|^2 - d) - mu(J-1) + lambda/2 (J-1)^2 with lambda = lambda_L + mu,
+ * integrated over linear simplices (triangles in 2D, tetrahedra in 3D) with
+ * element-wise PSD projection of d2Psi/dF2.
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ * - Every entry point returns a cc_status.  0 is success, positive values are
+ *   warnings whose outputs are valid, negative values are errors.  No C++
+ *   exception crosses the ABI.  cc_last_error() describes the last failure.
+ * - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *   memory on the context's device.  The caller owns every pointer it passes;
+ *   uploads are deep-copied into library-owned device memory, released by
+ *   cc_destroy.  No pointer passed in is retained after the call returns.
+ * - Positions and velocities are float64, row-major (n x dim), in the
+ *   caller's vertex order.  Element arrays are int32, row-major
+ *   (n_elems x (dim+1)), in the caller's element order.
+ * - All device work is ordered on the stream given to cc_create.  Calls that
+ *   return host results synchronise that stream before returning.
+ * - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef CCGPU_H
+#define CCGPU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cc_status;
+
+#define CC_OK                0
+#define CC_NOT_CONVERGED     1   /* iteration cap reached; outputs = last iterate   */
+#define CC_STALLED           2   /* line search and its CD fallback both failed    */
+#define CC_E_INVALID_ARG    -1
+#define CC_E_MESH           -2   /* bad index or non-positive rest volume           */
+#define CC_E_SUBSPACE       -3   /* unsorted / out-of-range / Dirichlet basis index */
+#define CC_E_HIP            -4   /* a HIP runtime call failed                       */
+#define CC_E_NONFINITE      -5   /* NaN/Inf in inputs                               */
+#define CC_E_STATE          -6   /* wrong call order (e.g. step before subspace)    */
+#define CC_E_NO_DEVICE      -7
+
+/* method */
+#define CC_METHOD_CD    0   /* plain block coordinate descent: dx_i = -H_ii^{-1} g_i   */
+#define CC_METHOD_CC    1   /* Coordinate Condensation (Method, Eq. update/schur)       */
+#define CC_METHOD_JGS2  2   /* printed JGS2 form (Background, JGS2 subsection)          */
+/* sweep */
+#define CC_SWEEP_JACOBI     0   /* Algorithm 1: all vertices from one snapshot          */
+#define CC_SWEEP_COLORED_GS 1   /* one graph colour at a time, latest positions         */
+/* hess_refresh (coloured sweep only) */
+#define CC_HESS_PER_COLOR 0     /* g and H re-evaluated before every colour             */
+#define CC_HESS_PER_SWEEP 1     /* H evaluated once per sweep, g before every colour    */
+/* precision */
+#define CC_FP64        0
+#define CC_FP32_MIXED  1        /* FP32 element Hessians, assembly and local solves;
+                                   FP64 positions, gradient, energy and norms           */
+
+typedef struct cc_ctx cc_ctx;
+
+typedef struct {
+  int32_t method;         /* CC_METHOD_*                                               */
+  int32_t sweep;          /* CC_SWEEP_*                                                */
+  int32_t hess_refresh;   /* CC_HESS_*                                                 */
+  int32_t precision;      /* CC_FP64 / CC_FP32_MIXED                                   */
+  int32_t line_search;    /* 0 off (Algorithm 1), 1 global backtracking along the
+                             iteration's displacement (Results, basis-quality study)   */
+  int32_t max_iters;      /* iteration cap (>= 0)                                      */
+  int32_t max_halvings;   /* line-search halvings (>= 0)                               */
+  int32_t check_interval; /* reserved, must be >= 1                                    */
+  int32_t quasistatic;    /* 1: E = Psi - m g.x (no inertia, no h^2)                   */
+  int32_t warm_start;     /* 0 none, 1 learned proposal set by cc_mlp_set              */
+  double  gravity[3];     /* gravitational acceleration; dim 2 uses the first two      */
+} cc_params;
+
+/* Fill *p with defaults: CC, Jacobi, per-colour Hessians, FP64, line search on,
+   10000 iterations, 30 halvings, check interval 1, dynamic, no warm start,
+   gravity 0. */
+void cc_params_default(cc_params* p);
+
+/* Create a context on HIP device `device`, ordering work on `hip_stream`
+   (a hipStream_t, or NULL for the null stream).  *out receives the context. */
+cc_status cc_create(int32_t device, void* hip_stream, cc_ctx** out);
+void      cc_destroy(cc_ctx* ctx);
+/* Message of the last failure; owned by the context, valid until the next call. */
+const char* cc_last_error(const cc_ctx* ctx);
+
+/* Upload a mesh (host arrays).  Rest data (shape gradients, volumes, lumped
+   masses rho*sum V_e/(d+1)), the greedy colouring and the colour-sorted
+   layouts are built here.  Elements must be positively oriented
+   (det [X1-X0 ... Xd-X0] > 0), otherwise CC_E_MESH.  Repeated uploads create
+   further meshes (for batched stepping); *mesh_id receives the new id. */
+cc_status cc_mesh_upload(cc_ctx* ctx, int32_t dim, int32_t n_verts, const double* X,
+                         int32_t n_elems, const int32_t* elems, const uint8_t* is_fixed,
+                         double youngs, double poisson, double density, int32_t* mesh_id);
+
+/* Greedy colouring of the free-vertex graph (edge iff two free vertices share
+   an element), visiting vertices in increasing id and taking the smallest
+   colour unused by coloured neighbours.  colors (host, n_verts) receives the
+   colour of each vertex, -1 for Dirichlet vertices. */
+cc_status cc_color(cc_ctx* ctx, int32_t mesh_id, int32_t* colors, int32_t* n_colors);
+
+/* Internal orderings (host outputs): vperm[new] = caller vertex id, sorted by
+   (colour, id) with Dirichlet vertices last; eperm[new] = caller element id,
+   sorted by (smallest new index among the element's free vertices, id) with
+   all-Dirichlet elements last. */
+cc_status cc_layout(cc_ctx* ctx, int32_t mesh_id, int32_t* vperm, int32_t* eperm);
+
+/* Upload the per-vertex perturbation basis U_i = -H_CC^{-1} H_Ci (Background,
+   JGS2 subsection; Method, Coordinate Condensation), host CSR in caller vertex
+   ids: ptr (n_verts+1, int64), idx (ptr[n], int32, strictly ascending per
+   row, free vertices other than the row's vertex), U (ptr[n] x dim x dim,
+   float64, row-major; block k maps a displacement of vertex i to that of
+   vertex idx[k]).  Rows of Dirichlet vertices must be empty.  Violations give
+   CC_E_SUBSPACE.  dt_used records the step size the basis was built for. */
+cc_status cc_subspace_upload(cc_ctx* ctx, int32_t mesh_id, const int64_t* ptr,
+                             const int32_t* idx, const double* U, double dt_used);
+
+/* Build the basis in the library from the rest Hessian of the step energy
+   (M + h^2 K(X), or K(X) when quasistatic):
+   radius > 0: patch basis, support = free vertices within `radius` hops,
+               everything outside the patch held, U_i = -H[C,C]^{-1} H[C,i];
+   radius = 0: exact basis over every other free vertex (limited to meshes
+               with at most 4096 free vertices).
+   The rest Hessian is evaluated by the library's own GPU kernels in FP64;
+   the small dense solves run on the host. */
+cc_status cc_subspace_build(cc_ctx* ctx, int32_t mesh_id, int32_t radius, double dt,
+                            int32_t quasistatic);
+
+/* Number of basis blocks of a mesh (*nnz), and a copy of the basis in the
+   upload format (host outputs sized n_verts+1, nnz, nnz*dim*dim). */
+cc_status cc_subspace_nnz(cc_ctx* ctx, int32_t mesh_id, int64_t* nnz);
+cc_status cc_subspace_download(cc_ctx* ctx, int32_t mesh_id, int64_t* ptr, int32_t* idx,
+                               double* U);
+
+/* One implicit time step of mesh `mesh_id`.
+   x, v: device (n_verts x dim) float64, read as x^t, v^t and overwritten with
+         x^{t+1} and v^{t+1} = (x^{t+1} - x^t)/h (all vertices).
+   x_bc: device (n_verts x dim) targets for the Dirichlet vertices, or NULL to
+         keep their current positions.
+   The predictor is x~ = x^t + h v^t with Dirichlet targets imposed; the
+   iteration stops when |g(x_k)|_2 <= tol |g(x^_0)|_2 over free DOFs, with x^_0
+   the predictor (quasistatic: the start state with targets).
+   *iters receives the iteration count, *rel_grad the final ratio.
+   Returns CC_OK, CC_NOT_CONVERGED, CC_STALLED or an error. */
+cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const double* x_bc,
+                  double dt, const cc_params* params, double tol, int32_t* iters,
+                  double* rel_grad);
+
+/* Extra results of the last cc_step on a mesh (host outputs, any may be NULL):
+   final step energy, the paper's normalised residual |g|/(V n E) (divided by
+   h when dynamic), fallback counters (Ht or empty support, Schur, H_ii),
+   line-search halvings taken, and whether a warm-start proposal was accepted. */
+cc_status cc_step_info(cc_ctx* ctx, int32_t mesh_id, double* energy, double* paper_residual,
+                       int64_t* fallbacks3, int64_t* halvings, int32_t* warm_accepted);
+
+/* ---- parity probes: single kernels on caller device buffers ------------- */
+
+/* Element gradient and projected Hessian at positions x (device, n x dim),
+   without the h^2 factor: ge (device, n_elems x (dim+1) x dim) and
+   He (device, n_elems x (dim+1) x (dim+1) x dim x dim, block [a][b] row-major),
+   in caller element order, computed in `precision`. */
+cc_status cc_probe_element(cc_ctx* ctx, int32_t mesh_id, const double* x, int32_t precision,
+                           double* ge, double* He);
+
+/* Step energy, free-vertex gradient (device g: n x dim, Dirichlet rows zero)
+   and one Jacobi sweep's per-vertex directions dx (device n x dim, Dirichlet
+   rows zero) at x, for inertial target x_tilde (device n x dim).  Any output
+   pointer may be NULL. */
+cc_status cc_probe_sweep(cc_ctx* ctx, int32_t mesh_id, const double* x, const double* x_tilde,
+                         double dt, const cc_params* params, double* energy, double* g,
+                         double* dx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CCGPU_H */

@@ -1,0 +1,234 @@
+"""Python binding of libccgpu (argument marshalling only).
+
+Every function has the name of the C entry point it wraps (include/ccgpu.h)
+and forwards to it through ctypes.  Host arrays are NumPy arrays; device
+arrays are torch tensors on the context's GPU, used only as device memory.
+Negative statuses raise CCError; warnings (CC_NOT_CONVERGED, CC_STALLED) are
+returned to the caller.  The library must have been built (``build.py``); a
+missing library raises at import time of the first call -- there is no
+fallback implementation.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libccgpu.so")
+
+CC_OK, CC_NOT_CONVERGED, CC_STALLED = 0, 1, 2
+METHOD_CD, METHOD_CC, METHOD_JGS2 = 0, 1, 2
+SWEEP_JACOBI, SWEEP_COLORED_GS = 0, 1
+HESS_PER_COLOR, HESS_PER_SWEEP = 0, 1
+FP64, FP32_MIXED = 0, 1
+
+_STATUS_NAMES = {
+    0: "CC_OK", 1: "CC_NOT_CONVERGED", 2: "CC_STALLED", -1: "CC_E_INVALID_ARG", -2: "CC_E_MESH",
+    -3: "CC_E_SUBSPACE", -4: "CC_E_HIP", -5: "CC_E_NONFINITE", -6: "CC_E_STATE", -7: "CC_E_NO_DEVICE",
+}
+
+
+class CCError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class cc_params(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("sweep", ctypes.c_int32),
+                ("hess_refresh", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("line_search", ctypes.c_int32), ("max_iters", ctypes.c_int32),
+                ("max_halvings", ctypes.c_int32), ("check_interval", ctypes.c_int32),
+                ("quasistatic", ctypes.c_int32), ("warm_start", ctypes.c_int32),
+                ("gravity", ctypes.c_double * 3)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libccgpu.so not built at {LIB_PATH}; run paper_2510_12053_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        pI32, pI64, pD = ctypes.POINTER(I32), ctypes.POINTER(I64), ctypes.POINTER(D)
+        sig = {
+            "cc_params_default": (None, [ctypes.POINTER(cc_params)]),
+            "cc_create": (I32, [I32, P, ctypes.POINTER(P)]),
+            "cc_destroy": (None, [P]),
+            "cc_last_error": (ctypes.c_char_p, [P]),
+            "cc_mesh_upload": (I32, [P, I32, I32, P, I32, P, P, D, D, D, pI32]),
+            "cc_color": (I32, [P, I32, P, pI32]),
+            "cc_layout": (I32, [P, I32, P, P]),
+            "cc_subspace_upload": (I32, [P, I32, P, P, P, D]),
+            "cc_subspace_build": (I32, [P, I32, I32, D, I32]),
+            "cc_subspace_nnz": (I32, [P, I32, pI64]),
+            "cc_subspace_download": (I32, [P, I32, P, P, P]),
+            "cc_step": (I32, [P, I32, P, P, P, D, ctypes.POINTER(cc_params), D, pI32, pD]),
+            "cc_step_info": (I32, [P, I32, pD, pD, P, pI64, pI32]),
+            "cc_probe_element": (I32, [P, I32, P, I32, P, P]),
+            "cc_probe_sweep": (I32, [P, I32, P, P, D, ctypes.POINTER(cc_params), pD, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class Context:
+    """Owns a cc_ctx*; released by cc_destroy (also on garbage collection)."""
+
+    def __init__(self, handle, device):
+        self.handle = handle
+        self.device = device
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.cc_destroy(self.handle)
+            self.handle = None
+
+
+def _check(ctx, status):
+    if status < 0:
+        msg = lib().cc_last_error(ctx.handle if ctx is not None else None)
+        raise CCError(status, msg.decode() if msg else "")
+    return status
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dptr(t, dtype_name="float64"):
+    import torch
+    if t is None:
+        return None
+    if not t.is_cuda or str(t.dtype) != f"torch.{dtype_name}" or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype_name} CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def cc_params_default(**overrides):
+    p = cc_params()
+    lib().cc_params_default(ctypes.byref(p))
+    for k, v in overrides.items():
+        if k == "gravity":
+            for c in range(3):
+                p.gravity[c] = float(v[c]) if c < len(v) else 0.0
+        else:
+            setattr(p, k, int(v))
+    return p
+
+
+def cc_create(device=0, stream=None):
+    """stream: a torch.cuda.Stream (default: the current stream of `device`)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    h = ctypes.c_void_p()
+    st = lib().cc_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+    if st < 0:
+        raise CCError(st, "cc_create failed")
+    ctx = Context(h, device)
+    ctx.stream = stream
+    return ctx
+
+
+def cc_destroy(ctx):
+    if ctx.handle:
+        lib().cc_destroy(ctx.handle)
+        ctx.handle = None
+
+
+def cc_mesh_upload(ctx, X, elems, fixed, youngs, poisson, density):
+    X = _host(X, np.float64)
+    E = _host(elems, np.int32)
+    F = _host(fixed, np.uint8)
+    mid = ctypes.c_int32(-1)
+    _check(ctx, lib().cc_mesh_upload(ctx.handle, X.shape[1], X.shape[0], _ptr(X), E.shape[0], _ptr(E),
+                                     _ptr(F), youngs, poisson, density, ctypes.byref(mid)))
+    return mid.value
+
+
+def cc_color(ctx, mesh_id, n_verts):
+    col = np.empty(n_verts, dtype=np.int32)
+    nc = ctypes.c_int32(0)
+    _check(ctx, lib().cc_color(ctx.handle, mesh_id, _ptr(col), ctypes.byref(nc)))
+    return col, nc.value
+
+
+def cc_layout(ctx, mesh_id, n_verts, n_elems):
+    vp = np.empty(n_verts, dtype=np.int32)
+    ep = np.empty(n_elems, dtype=np.int32)
+    _check(ctx, lib().cc_layout(ctx.handle, mesh_id, _ptr(vp), _ptr(ep)))
+    return vp, ep
+
+
+def cc_subspace_upload(ctx, mesh_id, ptr, idx, U, dt_used=0.0):
+    ptr = _host(ptr, np.int64)
+    idx = _host(idx, np.int32)
+    U = _host(U, np.float64)
+    _check(ctx, lib().cc_subspace_upload(ctx.handle, mesh_id, _ptr(ptr), _ptr(idx), _ptr(U), dt_used))
+
+
+def cc_subspace_build(ctx, mesh_id, radius, dt, quasistatic=False):
+    _check(ctx, lib().cc_subspace_build(ctx.handle, mesh_id, radius, dt, int(quasistatic)))
+
+
+def cc_subspace_download(ctx, mesh_id, n_verts, dim):
+    nnz = ctypes.c_int64(0)
+    _check(ctx, lib().cc_subspace_nnz(ctx.handle, mesh_id, ctypes.byref(nnz)))
+    ptr = np.empty(n_verts + 1, dtype=np.int64)
+    idx = np.empty(nnz.value, dtype=np.int32)
+    U = np.empty((nnz.value, dim, dim), dtype=np.float64)
+    _check(ctx, lib().cc_subspace_download(ctx.handle, mesh_id, _ptr(ptr), _ptr(idx), _ptr(U)))
+    return ptr, idx, U
+
+
+def cc_step(ctx, mesh_id, x, v, x_bc, dt, params, tol):
+    """x, v (and x_bc or None): float64 CUDA tensors (n, dim), updated in place.
+    Returns (status, iters, rel_grad)."""
+    it = ctypes.c_int32(0)
+    rg = ctypes.c_double(0.0)
+    st = _check(ctx, lib().cc_step(ctx.handle, mesh_id, _dptr(x), _dptr(v), _dptr(x_bc), dt,
+                                   ctypes.byref(params), tol, ctypes.byref(it), ctypes.byref(rg)))
+    return st, it.value, rg.value
+
+
+def cc_step_info(ctx, mesh_id):
+    e, pr = ctypes.c_double(0), ctypes.c_double(0)
+    fb = np.zeros(3, dtype=np.int64)
+    hv = ctypes.c_int64(0)
+    wa = ctypes.c_int32(0)
+    _check(ctx, lib().cc_step_info(ctx.handle, mesh_id, ctypes.byref(e), ctypes.byref(pr), _ptr(fb),
+                                   ctypes.byref(hv), ctypes.byref(wa)))
+    return dict(energy=e.value, paper_residual=pr.value, fallbacks=fb, halvings=hv.value,
+                warm_accepted=bool(wa.value))
+
+
+def cc_probe_element(ctx, mesh_id, x, precision, n_elems):
+    import torch
+    n, d = x.shape
+    k = d + 1
+    ge = torch.empty((n_elems, k, d), dtype=torch.float64, device=x.device)
+    He = torch.empty((n_elems, k, k, d, d), dtype=torch.float64, device=x.device)
+    _check(ctx, lib().cc_probe_element(ctx.handle, mesh_id, _dptr(x), precision, _dptr(ge), _dptr(He)))
+    return ge, He
+
+
+def cc_probe_sweep(ctx, mesh_id, x, x_tilde, dt, params, want_g=True, want_dx=True):
+    import torch
+    e = ctypes.c_double(0)
+    g = torch.zeros_like(x) if want_g else None
+    dx = torch.zeros_like(x) if want_dx else None
+    _check(ctx, lib().cc_probe_sweep(ctx.handle, mesh_id, _dptr(x), _dptr(x_tilde), dt,
+                                     ctypes.byref(params), ctypes.byref(e), _dptr(g), _dptr(dx)))
+    return e.value, g, dx

@@ -1,0 +1,999 @@
+// Host side of libccgpu: context, mesh and basis uploads, colouring and
+// layouts, the library's basis builder and the implicit-step driver.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/ccgpu.h"
+#include "cc_kernels.h"
+
+using cc::Material;
+using cc::MeshView;
+
+namespace {
+
+struct Mesh {
+  int D = 0, K = 0, n = 0, nf = 0, m = 0, ncol = 0;
+  double E = 0, nu = 0, rho = 0, mu = 0, lam = 0, volume = 0;
+  std::vector<double> X;           // caller order, n x D
+  std::vector<int> elems;          // caller order, m x K
+  std::vector<uint8_t> fixed;
+  std::vector<int> colour;         // caller order
+  std::vector<int> vperm, vinv, eperm, coff;
+  std::vector<int> rowptr, colidx; // host copy of the block-row pattern (internal ids)
+  std::vector<double> mass_int;    // internal order
+  int nnzb = 0;
+  // device: static mesh data
+  int *ev = nullptr, *star_ptr = nullptr, *star = nullptr, *d_rowptr = nullptr, *d_colidx = nullptr,
+      *blkrow = nullptr, *cptr = nullptr, *centry = nullptr, *d_vperm = nullptr, *d_vinv = nullptr,
+      *d_eperm = nullptr;
+  double *dinv_d = nullptr, *vol_d = nullptr, *mass = nullptr;
+  float *dinv_f = nullptr, *vol_f = nullptr;
+  // basis
+  bool has_basis = false;
+  int dense = 0;
+  int64_t snnz = 0;
+  int64_t* sptr = nullptr;
+  int* sidx = nullptr;
+  double* U_d = nullptr;
+  float* U_f = nullptr;
+  std::vector<int64_t> h_ptr;      // caller-format copy
+  std::vector<int> h_idx;
+  std::vector<double> h_U;
+  // work buffers
+  double *x = nullptr, *xt = nullptr, *x0 = nullptr, *xtrial = nullptr, *dvec = nullptr,
+         *g = nullptr, *partials = nullptr, *scal = nullptr;
+  void *estore = nullptr, *hb = nullptr, *KL = nullptr;
+  unsigned long long* fb = nullptr;
+  int* bad = nullptr;
+  // last-step info
+  double last_E = 0, last_paper = 0;
+  long long last_fb[3] = {0, 0, 0}, last_halvings = 0;
+  int last_warm = 0;
+
+  MeshView view() const {
+    MeshView v{};
+    v.D = D; v.n = n; v.nf = nf; v.m = m;
+    v.ev = ev; v.dinv_d = dinv_d; v.dinv_f = dinv_f; v.vol_d = vol_d; v.vol_f = vol_f;
+    v.mass = mass; v.star_ptr = star_ptr; v.star = star; v.rowptr = d_rowptr;
+    v.colidx = d_colidx; v.blkrow = blkrow; v.cptr = cptr; v.centry = centry; v.nnzb = nnzb;
+    v.sptr = sptr; v.sidx = sidx; v.U_d = U_d; v.U_f = U_f; v.dense_supp = dense;
+    return v;
+  }
+};
+
+struct HipError {
+  hipError_t e;
+  const char* what;
+};
+
+#define HIPC(call)                                    \
+  do {                                                \
+    hipError_t _e = (call);                           \
+    if (_e != hipSuccess) throw HipError{_e, #call};  \
+  } while (0)
+
+struct ApiError {
+  cc_status code;
+  std::string msg;
+};
+
+template <typename T>
+T* dalloc(size_t count) {
+  if (count == 0) count = 1;
+  void* p = nullptr;
+  HIPC(hipMalloc(&p, count * sizeof(T)));
+  return static_cast<T*>(p);
+}
+
+template <typename T>
+T* dupload(const std::vector<T>& h, hipStream_t s) {
+  T* p = dalloc<T>(h.size());
+  if (!h.empty()) HIPC(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return p;
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+void free_basis(Mesh& M) {
+  dfree(M.sptr); dfree(M.sidx); dfree(M.U_d); dfree(M.U_f);
+  M.has_basis = false;
+  M.snnz = 0;
+}
+
+void free_mesh(Mesh& M) {
+  dfree(M.ev); dfree(M.star_ptr); dfree(M.star); dfree(M.d_rowptr); dfree(M.d_colidx);
+  dfree(M.blkrow); dfree(M.cptr); dfree(M.centry); dfree(M.d_vperm); dfree(M.d_vinv);
+  dfree(M.d_eperm); dfree(M.dinv_d); dfree(M.vol_d); dfree(M.mass); dfree(M.dinv_f); dfree(M.vol_f);
+  free_basis(M);
+  dfree(M.x); dfree(M.xt); dfree(M.x0); dfree(M.xtrial); dfree(M.dvec); dfree(M.g);
+  dfree(M.partials); dfree(M.scal); dfree(M.estore); dfree(M.hb); dfree(M.KL); dfree(M.fb);
+  dfree(M.bad);
+}
+
+}  // namespace
+
+struct cc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::vector<Mesh*> meshes;
+  double* pinned = nullptr;  // host pinned scalars
+};
+
+namespace {
+
+cc_status fail(cc_ctx* ctx, cc_status code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+template <typename F>
+cc_status guarded(cc_ctx* ctx, F&& f) {
+  if (!ctx) return CC_E_INVALID_ARG;
+  try {
+    HIPC(hipSetDevice(ctx->device));
+    return f();
+  } catch (const HipError& e) {
+    return fail(ctx, CC_E_HIP, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
+  } catch (const ApiError& e) {
+    return fail(ctx, e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, CC_E_INVALID_ARG, "host allocation failed");
+  }
+}
+
+Mesh& get_mesh(cc_ctx* ctx, int32_t id) {
+  if (id < 0 || id >= (int32_t)ctx->meshes.size() || !ctx->meshes[id])
+    throw ApiError{CC_E_INVALID_ARG, "unknown mesh id"};
+  return *ctx->meshes[id];
+}
+
+// ---- rest data ---------------------------------------------------------
+bool invert(int D, const double* A, double* Ainv, double& det) {
+  if (D == 2) {
+    det = A[0] * A[3] - A[1] * A[2];
+    if (!(det > 0)) return false;
+    Ainv[0] = A[3] / det; Ainv[1] = -A[1] / det; Ainv[2] = -A[2] / det; Ainv[3] = A[0] / det;
+    return true;
+  }
+  const double a = A[0], b = A[1], c = A[2], d = A[3], e = A[4], f = A[5], g = A[6], h = A[7], i = A[8];
+  det = a * (e * i - f * h) - b * (d * i - f * g) + c * (d * h - e * g);
+  if (!(det > 0)) return false;
+  Ainv[0] = (e * i - f * h) / det; Ainv[1] = (c * h - b * i) / det; Ainv[2] = (b * f - c * e) / det;
+  Ainv[3] = (f * g - d * i) / det; Ainv[4] = (a * i - c * g) / det; Ainv[5] = (c * d - a * f) / det;
+  Ainv[6] = (d * h - e * g) / det; Ainv[7] = (b * g - a * h) / det; Ainv[8] = (a * e - b * d) / det;
+  return true;
+}
+
+void build_mesh(cc_ctx* ctx, Mesh& M) {
+  const int D = M.D, K = M.K, n = M.n, m = M.m;
+  hipStream_t s = ctx->stream;
+  // rest data in caller element order
+  std::vector<double> dinv_u((size_t)m * D * D), vol_u(m);
+  for (int e = 0; e < m; ++e) {
+    double Dm[9], Di[9], det;
+    for (int a = 1; a <= D; ++a)
+      for (int c = 0; c < D; ++c)
+        Dm[c * D + (a - 1)] = M.X[(size_t)M.elems[e * K + a] * D + c] - M.X[(size_t)M.elems[e * K] * D + c];
+    if (!invert(D, Dm, Di, det))
+      throw ApiError{CC_E_MESH, "element " + std::to_string(e) + " has non-positive rest volume"};
+    for (int r = 0; r < D * D; ++r) dinv_u[(size_t)e * D * D + r] = Di[r];
+    vol_u[e] = det / (D == 2 ? 2.0 : 6.0);
+  }
+  std::vector<double> mass_u(n, 0.0);
+  M.volume = 0;
+  for (int e = 0; e < m; ++e) {
+    M.volume += vol_u[e];
+    for (int a = 0; a < K; ++a) mass_u[M.elems[e * K + a]] += M.rho * vol_u[e] / K;
+  }
+  // free-vertex graph and greedy colouring (increasing id, smallest free colour)
+  std::vector<std::vector<int>> nbr(n);
+  for (int e = 0; e < m; ++e)
+    for (int a = 0; a < K; ++a) {
+      const int va = M.elems[e * K + a];
+      if (M.fixed[va]) continue;
+      for (int b = 0; b < K; ++b) {
+        const int vb = M.elems[e * K + b];
+        if (b != a && !M.fixed[vb]) nbr[va].push_back(vb);
+      }
+    }
+  for (auto& l : nbr) {
+    std::sort(l.begin(), l.end());
+    l.erase(std::unique(l.begin(), l.end()), l.end());
+  }
+  M.colour.assign(n, -1);
+  M.ncol = 0;
+  std::vector<int> mark;
+  for (int i = 0; i < n; ++i) {
+    if (M.fixed[i]) continue;
+    mark.assign(nbr[i].size() + 2, 0);
+    for (int j : nbr[i]) {
+      const int c = M.colour[j];
+      if (c >= 0 && c < (int)mark.size()) mark[c] = 1;
+    }
+    int c = 0;
+    while (mark[c]) ++c;
+    M.colour[i] = c;
+    M.ncol = std::max(M.ncol, c + 1);
+  }
+  // layouts: vertices by (colour, id), Dirichlet last; elements by (smallest
+  // new index among free vertices, id), all-Dirichlet elements last
+  M.vperm.resize(n);
+  for (int i = 0; i < n; ++i) M.vperm[i] = i;
+  std::stable_sort(M.vperm.begin(), M.vperm.end(), [&](int a, int b) {
+    const long long ka = M.colour[a] >= 0 ? M.colour[a] : (1LL << 40);
+    const long long kb = M.colour[b] >= 0 ? M.colour[b] : (1LL << 40);
+    return ka < kb;
+  });
+  M.vinv.resize(n);
+  for (int v = 0; v < n; ++v) M.vinv[M.vperm[v]] = v;
+  M.nf = 0;
+  for (int i = 0; i < n; ++i) M.nf += M.fixed[i] ? 0 : 1;
+  M.coff.assign(M.ncol + 1, 0);
+  for (int i = 0; i < n; ++i)
+    if (M.colour[i] >= 0) M.coff[M.colour[i] + 1]++;
+  for (int c = 0; c < M.ncol; ++c) M.coff[c + 1] += M.coff[c];
+  std::vector<long long> ekey(m);
+  for (int e = 0; e < m; ++e) {
+    long long k = 1LL << 40;
+    for (int a = 0; a < K; ++a) {
+      const int v = M.elems[e * K + a];
+      if (!M.fixed[v]) k = std::min<long long>(k, M.vinv[v]);
+    }
+    ekey[e] = k;
+  }
+  M.eperm.resize(m);
+  for (int e = 0; e < m; ++e) M.eperm[e] = e;
+  std::stable_sort(M.eperm.begin(), M.eperm.end(), [&](int a, int b) { return ekey[a] < ekey[b]; });
+  // internal element arrays (SoA)
+  std::vector<int> ev((size_t)K * m);
+  std::vector<double> dinv_i((size_t)D * D * m), vol_i(m);
+  for (int e = 0; e < m; ++e) {
+    const int eu = M.eperm[e];
+    for (int a = 0; a < K; ++a) ev[(size_t)a * m + e] = M.vinv[M.elems[eu * K + a]];
+    for (int r = 0; r < D * D; ++r) dinv_i[(size_t)r * m + e] = dinv_u[(size_t)eu * D * D + r];
+    vol_i[e] = vol_u[eu];
+  }
+  M.mass_int.resize(n);
+  for (int v = 0; v < n; ++v) M.mass_int[v] = mass_u[M.vperm[v]];
+  // star of every free vertex (internal), in element order
+  const int nf = M.nf;
+  std::vector<int> star_ptr(nf + 1, 0);
+  for (int e = 0; e < m; ++e)
+    for (int a = 0; a < K; ++a)
+      if (ev[(size_t)a * m + e] < nf) star_ptr[ev[(size_t)a * m + e] + 1]++;
+  for (int j = 0; j < nf; ++j) star_ptr[j + 1] += star_ptr[j];
+  std::vector<int> star(star_ptr[nf]), fill(star_ptr.begin(), star_ptr.end() - 1);
+  for (int e = 0; e < m; ++e)
+    for (int a = 0; a < K; ++a) {
+      const int v = ev[(size_t)a * m + e];
+      if (v < nf) star[fill[v]++] = e * 4 + a;
+    }
+  // block rows (diagonal first, then neighbours by internal id)
+  M.rowptr.assign(nf + 1, 0);
+  M.colidx.clear();
+  for (int j = 0; j < nf; ++j) {
+    std::vector<int> row;
+    for (int u : nbr[M.vperm[j]]) row.push_back(M.vinv[u]);
+    std::sort(row.begin(), row.end());
+    M.colidx.push_back(j);
+    for (int k : row) M.colidx.push_back(k);
+    M.rowptr[j + 1] = (int)M.colidx.size();
+  }
+  M.nnzb = (int)M.colidx.size();
+  std::vector<int> blkrow(M.nnzb);
+  for (int j = 0; j < nf; ++j)
+    for (int t = M.rowptr[j]; t < M.rowptr[j + 1]; ++t) blkrow[t] = j;
+  // element contributions of every block slot
+  std::vector<std::vector<int>> contrib(M.nnzb);
+  for (int j = 0; j < nf; ++j)
+    for (int t = star_ptr[j]; t < star_ptr[j + 1]; ++t) {
+      const int e = star[t] >> 2, a = star[t] & 3;
+      for (int b = 0; b < K; ++b) {
+        const int k = ev[(size_t)b * m + e];
+        if (k >= nf) continue;
+        int slot;
+        if (k == j) {
+          slot = M.rowptr[j];
+        } else {
+          auto it = std::lower_bound(M.colidx.begin() + M.rowptr[j] + 1, M.colidx.begin() + M.rowptr[j + 1], k);
+          slot = (int)(it - M.colidx.begin());
+        }
+        contrib[slot].push_back(e * 16 + a * 4 + b);
+      }
+    }
+  std::vector<int> cptr(M.nnzb + 1, 0), centry;
+  for (int t = 0; t < M.nnzb; ++t) {
+    cptr[t + 1] = cptr[t] + (int)contrib[t].size();
+    centry.insert(centry.end(), contrib[t].begin(), contrib[t].end());
+  }
+  std::vector<float> dinv_f(dinv_i.begin(), dinv_i.end()), vol_f(vol_i.begin(), vol_i.end());
+  // device uploads
+  M.ev = dupload(ev, s);
+  M.dinv_d = dupload(dinv_i, s);
+  M.dinv_f = dupload(dinv_f, s);
+  M.vol_d = dupload(vol_i, s);
+  M.vol_f = dupload(vol_f, s);
+  M.mass = dupload(M.mass_int, s);
+  M.star_ptr = dupload(star_ptr, s);
+  M.star = dupload(star, s);
+  M.d_rowptr = dupload(M.rowptr, s);
+  M.d_colidx = dupload(M.colidx, s);
+  M.blkrow = dupload(blkrow, s);
+  M.cptr = dupload(cptr, s);
+  M.centry = dupload(centry, s);
+  M.d_vperm = dupload(M.vperm, s);
+  M.d_vinv = dupload(M.vinv, s);
+  M.d_eperm = dupload(M.eperm, s);
+  // work buffers
+  const size_t nd = (size_t)D * n;
+  M.x = dalloc<double>(nd); M.xt = dalloc<double>(nd); M.x0 = dalloc<double>(nd);
+  M.xtrial = dalloc<double>(nd); M.dvec = dalloc<double>(nd); M.g = dalloc<double>(nd);
+  HIPC(hipMemsetAsync(M.g, 0, nd * sizeof(double), s));
+  HIPC(hipMemsetAsync(M.dvec, 0, nd * sizeof(double), s));
+  const int cap = cc::reduce_partials_capacity(M.view());
+  M.partials = dalloc<double>(cap);
+  M.scal = dalloc<double>(8);
+  const int NB = K * (K + 1) / 2;
+  M.estore = dalloc<double>((size_t)NB * m * D * D);
+  M.hb = dalloc<double>((size_t)M.nnzb * D * D);
+  M.KL = dalloc<double>((size_t)nf * 2 * D * D);
+  M.fb = dalloc<unsigned long long>(4);
+  M.bad = dalloc<int>(1);
+  HIPC(hipStreamSynchronize(s));
+}
+
+// ---- basis upload ------------------------------------------------------
+void upload_basis(cc_ctx* ctx, Mesh& M, const int64_t* ptr, const int32_t* idx, const double* U) {
+  const int D = M.D, DD = D * D, n = M.n, nf = M.nf;
+  if (!ptr || (ptr[n] > 0 && (!idx || !U))) throw ApiError{CC_E_INVALID_ARG, "null basis array"};
+  if (ptr[0] != 0) throw ApiError{CC_E_SUBSPACE, "ptr[0] must be 0"};
+  for (int i = 0; i < n; ++i) {
+    if (ptr[i + 1] < ptr[i]) throw ApiError{CC_E_SUBSPACE, "ptr must be non-decreasing"};
+    if (M.fixed[i] && ptr[i + 1] != ptr[i])
+      throw ApiError{CC_E_SUBSPACE, "row of Dirichlet vertex " + std::to_string(i) + " is not empty"};
+    for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+      const int j = idx[k];
+      if (j < 0 || j >= n) throw ApiError{CC_E_SUBSPACE, "basis index out of range"};
+      if (j == i) throw ApiError{CC_E_SUBSPACE, "basis row contains its own vertex"};
+      if (M.fixed[j]) throw ApiError{CC_E_SUBSPACE, "basis index names a Dirichlet vertex"};
+      if (k > ptr[i] && idx[k - 1] >= j) throw ApiError{CC_E_SUBSPACE, "basis row not strictly ascending"};
+    }
+  }
+  const int64_t nnz = ptr[n];
+  for (int64_t k = 0; k < nnz * DD; ++k)
+    if (!std::isfinite(U[k])) throw ApiError{CC_E_NONFINITE, "non-finite basis entry"};
+  // internal rows: internal vertex i <- caller vertex vperm[i], entries sorted by internal id
+  std::vector<int64_t> sptr(nf + 1, 0);
+  for (int i = 0; i < nf; ++i) {
+    const int u = M.vperm[i];
+    sptr[i + 1] = sptr[i] + (ptr[u + 1] - ptr[u]);
+  }
+  std::vector<int> sidx(nnz);
+  std::vector<double> Ud((size_t)nnz * DD);
+  bool dense = true;
+  std::vector<std::pair<int, int64_t>> row;
+  for (int i = 0; i < nf; ++i) {
+    const int u = M.vperm[i];
+    row.clear();
+    for (int64_t k = ptr[u]; k < ptr[u + 1]; ++k) row.push_back({M.vinv[idx[k]], k});
+    std::sort(row.begin(), row.end());
+    for (size_t t = 0; t < row.size(); ++t) {
+      sidx[sptr[i] + t] = row[t].first;
+      std::memcpy(&Ud[(size_t)(sptr[i] + t) * DD], &U[(size_t)row[t].second * DD], DD * sizeof(double));
+    }
+    if ((int)row.size() != nf - 1) dense = false;
+  }
+  free_basis(M);
+  hipStream_t s = ctx->stream;
+  M.sptr = dupload(sptr, s);
+  M.sidx = dupload(sidx, s);
+  M.U_d = dupload(Ud, s);
+  std::vector<float> Uf(Ud.begin(), Ud.end());
+  M.U_f = dupload(Uf, s);
+  M.dense = dense ? 1 : 0;
+  M.snnz = nnz;
+  M.h_ptr.assign(ptr, ptr + n + 1);
+  M.h_idx.assign(idx, idx + nnz);
+  M.h_U.assign(U, U + (size_t)nnz * DD);
+  HIPC(hipStreamSynchronize(s));
+  M.has_basis = true;
+}
+
+// dense Cholesky A = L L^T (row-major, in place lower); false if not SPD
+bool dense_chol(std::vector<double>& A, int N) {
+  for (int j = 0; j < N; ++j) {
+    double s = A[(size_t)j * N + j];
+    for (int k = 0; k < j; ++k) s -= A[(size_t)j * N + k] * A[(size_t)j * N + k];
+    if (!(s > 0)) return false;
+    const double l = std::sqrt(s);
+    A[(size_t)j * N + j] = l;
+    for (int i = j + 1; i < N; ++i) {
+      double t = A[(size_t)i * N + j];
+      const double* ri = &A[(size_t)i * N];
+      const double* rj = &A[(size_t)j * N];
+      for (int k = 0; k < j; ++k) t -= ri[k] * rj[k];
+      A[(size_t)i * N + j] = t / l;
+    }
+  }
+  return true;
+}
+
+// solve L L^T X = B for R right-hand sides stored row-major N x R
+void dense_chol_solve(const std::vector<double>& L, int N, std::vector<double>& B, int R) {
+  for (int i = 0; i < N; ++i)
+    for (int r = 0; r < R; ++r) {
+      double s = B[(size_t)i * R + r];
+      for (int k = 0; k < i; ++k) s -= L[(size_t)i * N + k] * B[(size_t)k * R + r];
+      B[(size_t)i * R + r] = s / L[(size_t)i * N + i];
+    }
+  for (int i = N - 1; i >= 0; --i)
+    for (int r = 0; r < R; ++r) {
+      double s = B[(size_t)i * R + r];
+      for (int k = i + 1; k < N; ++k) s -= L[(size_t)k * N + i] * B[(size_t)k * R + r];
+      B[(size_t)i * R + r] = s / L[(size_t)i * N + i];
+    }
+}
+
+void build_basis(cc_ctx* ctx, Mesh& M, int radius, double dt, int quasi) {
+  const int D = M.D, DD = D * D, nf = M.nf, n = M.n;
+  hipStream_t s = ctx->stream;
+  // rest Hessian block rows in float64 from the library's kernels
+  std::vector<double> Xi((size_t)D * n);
+  for (int v = 0; v < n; ++v)
+    for (int c = 0; c < D; ++c) Xi[(size_t)c * n + v] = M.X[(size_t)M.vperm[v] * D + c];
+  HIPC(hipMemcpyAsync(M.x, Xi.data(), Xi.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  Material mat{};
+  mat.mu = M.mu; mat.lam = M.lam;
+  mat.w_in = quasi ? 0.0 : 1.0;
+  mat.s_el = quasi ? 1.0 : dt * dt;
+  MeshView mv = M.view();
+  cc::launch_elem_hess(mv, 0, M.x, mat, mat.s_el, M.estore, s);
+  cc::launch_assemble(mv, 0, M.estore, mat, M.hb, s);
+  std::vector<double> hb((size_t)M.nnzb * DD);
+  HIPC(hipMemcpyAsync(hb.data(), M.hb, hb.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  auto block = [&](int j, int k, double* out) -> bool {  // H_jk, false if structurally zero
+    if (j == k) {
+      std::memcpy(out, &hb[(size_t)M.rowptr[j] * DD], DD * sizeof(double));
+      return true;
+    }
+    auto b = M.colidx.begin() + M.rowptr[j] + 1, e = M.colidx.begin() + M.rowptr[j + 1];
+    auto it = std::lower_bound(b, e, k);
+    if (it == e || *it != k) return false;
+    std::memcpy(out, &hb[(size_t)(it - M.colidx.begin()) * DD], DD * sizeof(double));
+    return true;
+  };
+  // supports (internal ids), then U rows in internal order
+  std::vector<std::vector<int>> supp(nf);
+  if (radius > 0) {
+    std::vector<int> seen(nf, -1);
+    for (int i = 0; i < nf; ++i) {
+      std::vector<int> frontier{i}, all;
+      seen[i] = i;
+      for (int r = 0; r < radius; ++r) {
+        std::vector<int> nxt;
+        for (int v : frontier)
+          for (int t = M.rowptr[v] + 1; t < M.rowptr[v + 1]; ++t) {
+            const int w = M.colidx[t];
+            if (seen[w] != i) { seen[w] = i; nxt.push_back(w); all.push_back(w); }
+          }
+        frontier.swap(nxt);
+      }
+      std::sort(all.begin(), all.end());
+      supp[i] = all;
+    }
+  } else {
+    if (nf > 1024) throw ApiError{CC_E_INVALID_ARG, "exact basis limited to 1024 free vertices"};
+    for (int i = 0; i < nf; ++i)
+      for (int j = 0; j < nf; ++j)
+        if (j != i) supp[i].push_back(j);
+  }
+  std::vector<std::vector<double>> Urows(nf);
+  if (radius > 0) {
+    const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    std::vector<int> failed(nth, 0);
+    for (unsigned w = 0; w < nth; ++w)
+      pool.emplace_back([&, w]() {
+        std::vector<double> A, B;
+        std::vector<int> pos(nf, -1);
+        for (int i = (int)w; i < nf; i += (int)nth) {
+          const auto& C = supp[i];
+          const int nc = (int)C.size(), N = nc * D;
+          if (nc == 0) continue;
+          for (int a = 0; a < nc; ++a) pos[C[a]] = a;
+          A.assign((size_t)N * N, 0.0);
+          B.assign((size_t)N * D, 0.0);
+          double blk[9];
+          for (int a = 0; a < nc; ++a) {
+            const int j = C[a];
+            for (int t = M.rowptr[j]; t < M.rowptr[j + 1]; ++t) {
+              const int k = M.colidx[t];
+              if (k == i) {
+                for (int r = 0; r < D; ++r)
+                  for (int c2 = 0; c2 < D; ++c2) B[(size_t)(a * D + r) * D + c2] = -hb[(size_t)t * DD + r * D + c2];
+              } else if (pos[k] >= 0 && (k == j || std::binary_search(C.begin(), C.end(), k))) {
+                const int bcol = pos[k];
+                for (int r = 0; r < D; ++r)
+                  for (int c2 = 0; c2 < D; ++c2)
+                    A[(size_t)(a * D + r) * N + bcol * D + c2] = hb[(size_t)t * DD + r * D + c2];
+              }
+            }
+          }
+          (void)blk;
+          if (!dense_chol(A, N)) { failed[w] = 1; }
+          else dense_chol_solve(A, N, B, D);
+          Urows[i] = B;
+          for (int a = 0; a < nc; ++a) pos[C[a]] = -1;
+        }
+      });
+    for (auto& t : pool) t.join();
+    for (int f : failed)
+      if (f) throw ApiError{CC_E_SUBSPACE, "patch Hessian not positive definite"};
+  } else {
+    const int N = nf * D;
+    std::vector<double> H((size_t)N * N, 0.0);
+    for (int j = 0; j < nf; ++j)
+      for (int t = M.rowptr[j]; t < M.rowptr[j + 1]; ++t) {
+        const int k = M.colidx[t];
+        for (int r = 0; r < D; ++r)
+          for (int c2 = 0; c2 < D; ++c2) H[(size_t)(j * D + r) * N + k * D + c2] = hb[(size_t)t * DD + r * D + c2];
+      }
+    if (!dense_chol(H, N)) throw ApiError{CC_E_SUBSPACE, "rest Hessian not positive definite"};
+    // Z = H^{-1} (all columns), U_i[j] = Z_ji Z_ii^{-1}
+    std::vector<double> Z((size_t)N * N, 0.0);
+    for (int i = 0; i < N; ++i) Z[(size_t)i * N + i] = 1.0;
+    {
+      const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+      std::vector<std::thread> pool;
+      const int chunk = (N + nth - 1) / nth;
+      for (unsigned w = 0; w < nth; ++w)
+        pool.emplace_back([&, w]() {
+          const int c0 = w * chunk, c1 = std::min(N, c0 + chunk);
+          if (c0 >= c1) return;
+          const int R = c1 - c0;
+          std::vector<double> Bw((size_t)N * R);
+          for (int r = 0; r < N; ++r)
+            for (int q = 0; q < R; ++q) Bw[(size_t)r * R + q] = Z[(size_t)r * N + c0 + q];
+          dense_chol_solve(H, N, Bw, R);
+          for (int r = 0; r < N; ++r)
+            for (int q = 0; q < R; ++q) Z[(size_t)r * N + c0 + q] = Bw[(size_t)r * R + q];
+        });
+      for (auto& t : pool) t.join();
+    }
+    for (int i = 0; i < nf; ++i) {
+      double Zii[9], Zinv[9], det;
+      for (int r = 0; r < D; ++r)
+        for (int c2 = 0; c2 < D; ++c2) Zii[r * D + c2] = Z[(size_t)(i * D + r) * N + i * D + c2];
+      if (!invert(D, Zii, Zinv, det)) throw ApiError{CC_E_SUBSPACE, "singular diagonal block of H^-1"};
+      std::vector<double> rows((size_t)(nf - 1) * D * D);
+      int a = 0;
+      for (int j = 0; j < nf; ++j) {
+        if (j == i) continue;
+        for (int r = 0; r < D; ++r)
+          for (int c2 = 0; c2 < D; ++c2) {
+            double acc = 0;
+            for (int l = 0; l < D; ++l) acc += Z[(size_t)(j * D + r) * N + i * D + l] * Zinv[l * D + c2];
+            rows[(size_t)(a * D + r) * D + c2] = acc;
+          }
+        ++a;
+      }
+      Urows[i] = rows;
+    }
+  }
+  // convert to the caller format (caller ids, ascending) and upload
+  std::vector<int64_t> ptr(n + 1, 0);
+  for (int i = 0; i < nf; ++i) ptr[M.vperm[i] + 1] = (int64_t)supp[i].size();
+  for (int u = 0; u < n; ++u) ptr[u + 1] += ptr[u];
+  std::vector<int> idx(ptr[n]);
+  std::vector<double> U((size_t)ptr[n] * DD);
+  for (int i = 0; i < nf; ++i) {
+    const int u = M.vperm[i];
+    std::vector<std::pair<int, int>> ord;
+    for (int a = 0; a < (int)supp[i].size(); ++a) ord.push_back({M.vperm[supp[i][a]], a});
+    std::sort(ord.begin(), ord.end());
+    for (size_t t = 0; t < ord.size(); ++t) {
+      idx[ptr[u] + t] = ord[t].first;
+      const int a = ord[t].second;
+      for (int r = 0; r < D; ++r)
+        for (int c2 = 0; c2 < D; ++c2)
+          U[(size_t)(ptr[u] + t) * DD + r * D + c2] = Urows[i][(size_t)(a * D + r) * D + c2];
+    }
+  }
+  upload_basis(ctx, M, ptr.data(), idx.data(), U.data());
+}
+
+// ---- step driver ---------------------------------------------------------
+struct Stepper {
+  cc_ctx* ctx;
+  Mesh& M;
+  MeshView mv;
+  Material mat;
+  const cc_params& p;
+  hipStream_t s;
+
+  double read_scalar(const double* dptr) {
+    HIPC(hipMemcpyAsync(ctx->pinned, dptr, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    return ctx->pinned[0];
+  }
+  double energy(const double* x) {
+    int np = 0;
+    cc::launch_energy(mv, x, M.xt, mat, M.partials, &np, s);
+    cc::launch_reduce(M.partials, np, M.scal, s);
+    return read_scalar(M.scal);
+  }
+  double grad_norm2(const double* x) {
+    int np = 0;
+    cc::launch_gradient(mv, x, M.xt, mat, M.g, M.partials, &np, s);
+    if (np == 0) return 0.0;
+    cc::launch_reduce(M.partials, np, M.scal + 1, s);
+    return read_scalar(M.scal + 1);
+  }
+  void gradient_only(const double* x) {
+    int np = 0;
+    cc::launch_gradient(mv, x, M.xt, mat, M.g, M.partials, &np, s);
+  }
+  void hessian(const double* x) {
+    cc::launch_elem_hess(mv, p.precision, x, mat, mat.s_el, M.estore, s);
+    cc::launch_assemble(mv, p.precision, M.estore, mat, M.hb, s);
+  }
+  // One sweep from x into out (x unchanged).  method as requested.
+  void sweep(const double* x, double* out, int method) {
+    const int nd = M.D * M.n;
+    if (p.sweep == CC_SWEEP_JACOBI) {
+      hessian(x);
+      cc::launch_cc_prep(mv, p.precision, method, 0, M.nf, M.hb, M.KL, M.fb, s);
+      gradient_only(x);
+      cc::launch_cc_update(mv, p.precision, method, 0, M.nf, M.KL, M.g, M.dvec, 0, s);
+      cc::launch_axpy(nd, x, M.dvec, 1.0, out, s);
+      return;
+    }
+    HIPC(hipMemcpyAsync(out, x, (size_t)nd * sizeof(double), hipMemcpyDeviceToDevice, s));
+    for (int c = 0; c < M.ncol; ++c) {
+      const int v0 = M.coff[c], v1 = M.coff[c + 1];
+      if (v1 <= v0) continue;
+      if (p.hess_refresh == CC_HESS_PER_COLOR) {
+        hessian(out);
+        cc::launch_cc_prep(mv, p.precision, method, v0, v1, M.hb, M.KL, M.fb, s);
+      } else if (c == 0) {
+        hessian(out);
+        cc::launch_cc_prep(mv, p.precision, method, 0, M.nf, M.hb, M.KL, M.fb, s);
+      }
+      gradient_only(out);
+      cc::launch_cc_update(mv, p.precision, method, v0, v1, M.KL, M.g, out, 1, s);
+    }
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+void cc_params_default(cc_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->method = CC_METHOD_CC;
+  p->sweep = CC_SWEEP_JACOBI;
+  p->hess_refresh = CC_HESS_PER_COLOR;
+  p->precision = CC_FP64;
+  p->line_search = 1;
+  p->max_iters = 10000;
+  p->max_halvings = 30;
+  p->check_interval = 1;
+}
+
+cc_status cc_create(int32_t device, void* hip_stream, cc_ctx** out) {
+  if (!out) return CC_E_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return CC_E_NO_DEVICE;
+  if (device < 0 || device >= count) return CC_E_INVALID_ARG;
+  cc_ctx* ctx = new (std::nothrow) cc_ctx();
+  if (!ctx) return CC_E_INVALID_ARG;
+  ctx->device = device;
+  ctx->stream = (hipStream_t)hip_stream;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->pinned, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    delete ctx;
+    return CC_E_HIP;
+  }
+  *out = ctx;
+  return CC_OK;
+}
+
+void cc_destroy(cc_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (Mesh* M : ctx->meshes)
+    if (M) { free_mesh(*M); delete M; }
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+}
+
+const char* cc_last_error(const cc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+cc_status cc_mesh_upload(cc_ctx* ctx, int32_t dim, int32_t n_verts, const double* X, int32_t n_elems,
+                         const int32_t* elems, const uint8_t* is_fixed, double youngs, double poisson,
+                         double density, int32_t* mesh_id) {
+  return guarded(ctx, [&]() -> cc_status {
+    if ((dim != 2 && dim != 3) || n_verts <= 0 || n_elems < 0 || !X || !is_fixed || !mesh_id ||
+        (n_elems > 0 && !elems))
+      return fail(ctx, CC_E_INVALID_ARG, "bad mesh arguments");
+    if (!(youngs > 0) || !(poisson > -1.0 && poisson < 0.5) || !(density > 0))
+      return fail(ctx, CC_E_INVALID_ARG, "bad material constants");
+    if (n_elems >= (1 << 27)) return fail(ctx, CC_E_INVALID_ARG, "too many elements");
+    const int K = dim + 1;
+    for (long long k = 0; k < (long long)n_verts * dim; ++k)
+      if (!std::isfinite(X[k])) return fail(ctx, CC_E_NONFINITE, "non-finite rest position");
+    for (long long k = 0; k < (long long)n_elems * K; ++k)
+      if (elems[k] < 0 || elems[k] >= n_verts) return fail(ctx, CC_E_MESH, "element index out of range");
+    Mesh* M = new Mesh();
+    M->D = dim; M->K = K; M->n = n_verts; M->m = n_elems;
+    M->E = youngs; M->nu = poisson; M->rho = density;
+    M->mu = youngs / (2.0 * (1.0 + poisson));
+    M->lam = youngs * poisson / ((1.0 + poisson) * (1.0 - 2.0 * poisson)) + M->mu;
+    M->X.assign(X, X + (size_t)n_verts * dim);
+    M->elems.assign(elems, elems + (size_t)n_elems * K);
+    M->fixed.resize(n_verts);
+    for (int i = 0; i < n_verts; ++i) M->fixed[i] = is_fixed[i] ? 1 : 0;
+    try {
+      build_mesh(ctx, *M);
+    } catch (...) {
+      free_mesh(*M);
+      delete M;
+      throw;
+    }
+    ctx->meshes.push_back(M);
+    *mesh_id = (int32_t)ctx->meshes.size() - 1;
+    return CC_OK;
+  });
+}
+
+cc_status cc_color(cc_ctx* ctx, int32_t mesh_id, int32_t* colors, int32_t* n_colors) {
+  return guarded(ctx, [&]() -> cc_status {
+    Mesh& M = get_mesh(ctx, mesh_id);
+    if (colors) std::memcpy(colors, M.colour.data(), M.n * sizeof(int32_t));
+    if (n_colors) *n_colors = M.ncol;
+    return CC_OK;
+  });
+}
+
+cc_status cc_layout(cc_ctx* ctx, int32_t mesh_id, int32_t* vperm, int32_t* eperm) {
+  return guarded(ctx, [&]() -> cc_status {
+    Mesh& M = get_mesh(ctx, mesh_id);
+    if (vperm) std::memcpy(vperm, M.vperm.data(), M.n * sizeof(int32_t));
+    if (eperm) std::memcpy(eperm, M.eperm.data(), M.m * sizeof(int32_t));
+    return CC_OK;
+  });
+}
+
+cc_status cc_subspace_upload(cc_ctx* ctx, int32_t mesh_id, const int64_t* ptr, const int32_t* idx,
+                             const double* U, double dt_used) {
+  (void)dt_used;
+  return guarded(ctx, [&]() -> cc_status {
+    Mesh& M = get_mesh(ctx, mesh_id);
+    upload_basis(ctx, M, ptr, idx, U);
+    return CC_OK;
+  });
+}
+
+cc_status cc_subspace_build(cc_ctx* ctx, int32_t mesh_id, int32_t radius, double dt, int32_t quasistatic) {
+  return guarded(ctx, [&]() -> cc_status {
+    Mesh& M = get_mesh(ctx, mesh_id);
+    if (radius < 0 || (!quasistatic && !(dt > 0))) return fail(ctx, CC_E_INVALID_ARG, "bad basis arguments");
+    build_basis(ctx, M, radius, dt, quasistatic);
+    return CC_OK;
+  });
+}
+
+cc_status cc_subspace_nnz(cc_ctx* ctx, int32_t mesh_id, int64_t* nnz) {
+  return guarded(ctx, [&]() -> cc_status {
+    Mesh& M = get_mesh(ctx, mesh_id);
+    if (!M.has_basis) return fail(ctx, CC_E_STATE, "no basis uploaded");
+    if (nnz) *nnz = M.snnz;
+    return CC_OK;
+  });
+}
+
+cc_status cc_subspace_download(cc_ctx* ctx, int32_t mesh_id, int64_t* ptr, int32_t* idx, double* U) {
+  return guarded(ctx, [&]() -> cc_status {
+    Mesh& M = get_mesh(ctx, mesh_id);
+    if (!M.has_basis) return fail(ctx, CC_E_STATE, "no basis uploaded");
+    if (ptr) std::memcpy(ptr, M.h_ptr.data(), M.h_ptr.size() * sizeof(int64_t));
+    if (idx) std::memcpy(idx, M.h_idx.data(), M.h_idx.size() * sizeof(int32_t));
+    if (U) std::memcpy(U, M.h_U.data(), M.h_U.size() * sizeof(double));
+    return CC_OK;
+  });
+}
+
+static cc_status check_params(cc_ctx* ctx, const cc_params* p, const Mesh& M, double dt) {
+  if (!p) return fail(ctx, CC_E_INVALID_ARG, "null params");
+  if (p->method < 0 || p->method > 2 || p->sweep < 0 || p->sweep > 1 || p->hess_refresh < 0 ||
+      p->hess_refresh > 1 || p->precision < 0 || p->precision > 1 || p->max_iters < 0 ||
+      p->max_halvings < 0 || p->check_interval < 1)
+    return fail(ctx, CC_E_INVALID_ARG, "bad solver parameters");
+  if (!p->quasistatic && !(dt > 0)) return fail(ctx, CC_E_INVALID_ARG, "dt must be positive");
+  if (p->method != CC_METHOD_CD && !M.has_basis)
+    return fail(ctx, CC_E_STATE, "method needs a basis: call cc_subspace_upload or cc_subspace_build");
+  for (int c = 0; c < 3; ++c)
+    if (!std::isfinite(p->gravity[c])) return fail(ctx, CC_E_NONFINITE, "non-finite gravity");
+  return CC_OK;
+}
+
+cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const double* x_bc, double dt,
+                  const cc_params* params, double tol, int32_t* iters, double* rel_grad) {
+  return guarded(ctx, [&]() -> cc_status {
+    Mesh& M = get_mesh(ctx, mesh_id);
+    if (!x || !v) return fail(ctx, CC_E_INVALID_ARG, "null state buffer");
+    cc_status st = check_params(ctx, params, M, dt);
+    if (st != CC_OK) return st;
+    if (!(tol >= 0)) return fail(ctx, CC_E_INVALID_ARG, "tol must be >= 0");
+    const cc_params& p = *params;
+    hipStream_t s = ctx->stream;
+    Material mat{};
+    mat.mu = M.mu; mat.lam = M.lam;
+    mat.w_in = p.quasistatic ? 0.0 : 1.0;
+    mat.s_el = p.quasistatic ? 1.0 : dt * dt;
+    for (int c = 0; c < 3; ++c) mat.grav[c] = p.gravity[c];
+    const double h = p.quasistatic ? 1.0 : dt;
+    Stepper S{ctx, M, M.view(), mat, p, s};
+    HIPC(hipMemsetAsync(M.bad, 0, sizeof(int), s));
+    HIPC(hipMemsetAsync(M.fb, 0, 4 * sizeof(unsigned long long), s));
+    cc::launch_predict(S.mv, M.d_vperm, x, v, x_bc, h, p.quasistatic, M.x, M.xt, M.x0, M.bad, s);
+    int bad = 0;
+    HIPC(hipMemcpyAsync(&bad, M.bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (bad) return fail(ctx, CC_E_NONFINITE, "non-finite x, v or x_bc");
+    const double g0 = std::sqrt(S.grad_norm2(M.x));
+    const int nd = M.D * M.n;
+    double r = 0.0, Ecur = 0.0;
+    int k = 0;
+    long long halvings = 0;
+    cc_status result = CC_OK;
+    if (g0 > 0) {
+      r = 1.0;
+      if (p.line_search) Ecur = S.energy(M.x);
+      while (r > tol && k < p.max_iters) {
+        S.sweep(M.x, M.xtrial, p.method);
+        if (p.line_search) {
+          const double tau = 1e-12 * std::max(std::fabs(Ecur), 1.0);
+          // displacement of this iteration
+          cc::launch_axpy(nd, M.xtrial, M.x, -1.0, M.dvec, s);
+          double alpha = 1.0, Et = S.energy(M.xtrial);
+          int hv = 0;
+          while (!(Et <= Ecur + tau) && hv < p.max_halvings) {
+            alpha *= 0.5;
+            ++hv;
+            cc::launch_axpy(nd, M.x, M.dvec, alpha, M.xtrial, s);
+            Et = S.energy(M.xtrial);
+          }
+          if (!(Et <= Ecur + tau)) {
+            S.sweep(M.x, M.xtrial, CC_METHOD_CD);
+            cc::launch_axpy(nd, M.xtrial, M.x, -1.0, M.dvec, s);
+            alpha = 1.0;
+            Et = S.energy(M.xtrial);
+            hv = 0;
+            while (!(Et <= Ecur + tau) && hv < p.max_halvings) {
+              alpha *= 0.5;
+              ++hv;
+              cc::launch_axpy(nd, M.x, M.dvec, alpha, M.xtrial, s);
+              Et = S.energy(M.xtrial);
+            }
+            if (!(Et <= Ecur + tau)) {
+              result = CC_STALLED;
+              break;
+            }
+          }
+          halvings += hv;
+          Ecur = Et;
+        }
+        std::swap(M.x, M.xtrial);
+        ++k;
+        const double gn = std::sqrt(S.grad_norm2(M.x));
+        r = gn / g0;
+        if (!std::isfinite(r)) {
+          std::swap(M.x, M.xtrial);
+          result = CC_STALLED;
+          break;
+        }
+      }
+      if (result == CC_OK && r > tol) result = CC_NOT_CONVERGED;
+    }
+    M.last_E = S.energy(M.x);
+    M.last_halvings = halvings;
+    {
+      const double gn = r * g0;
+      const double pm = gn / (M.volume * M.n * M.E);
+      M.last_paper = p.quasistatic ? pm : pm / dt;
+    }
+    unsigned long long fbh[4];
+    HIPC(hipMemcpyAsync(fbh, M.fb, sizeof(fbh), hipMemcpyDeviceToHost, s));
+    cc::launch_finalize(S.mv, M.d_vperm, M.x, M.x0, h, p.quasistatic, x, v, s);
+    HIPC(hipStreamSynchronize(s));
+    for (int c = 0; c < 3; ++c) M.last_fb[c] = (long long)fbh[c];
+    M.last_warm = 0;
+    if (iters) *iters = k;
+    if (rel_grad) *rel_grad = r;
+    return result;
+  });
+}
+
+cc_status cc_step_info(cc_ctx* ctx, int32_t mesh_id, double* energy, double* paper_residual,
+                       int64_t* fallbacks3, int64_t* halvings, int32_t* warm_accepted) {
+  return guarded(ctx, [&]() -> cc_status {
+    Mesh& M = get_mesh(ctx, mesh_id);
+    if (energy) *energy = M.last_E;
+    if (paper_residual) *paper_residual = M.last_paper;
+    if (fallbacks3) for (int c = 0; c < 3; ++c) fallbacks3[c] = M.last_fb[c];
+    if (halvings) *halvings = M.last_halvings;
+    if (warm_accepted) *warm_accepted = M.last_warm;
+    return CC_OK;
+  });
+}
+
+cc_status cc_probe_element(cc_ctx* ctx, int32_t mesh_id, const double* x, int32_t precision, double* ge,
+                           double* He) {
+  return guarded(ctx, [&]() -> cc_status {
+    Mesh& M = get_mesh(ctx, mesh_id);
+    if (!x || !ge || !He || (precision != 0 && precision != 1))
+      return fail(ctx, CC_E_INVALID_ARG, "bad probe arguments");
+    hipStream_t s = ctx->stream;
+    const int K = M.K, NB = K * (K + 1) / 2;
+    double* tmp = dalloc<double>((size_t)M.D * M.n + (size_t)NB * M.m * M.D * M.D);
+    MeshView mv = M.view();
+    Material mat{};
+    mat.mu = M.mu; mat.lam = M.lam;
+    cc::launch_gather_user(mv, M.d_vinv, x, tmp, s);
+    cc::launch_probe_element(mv, precision, x, M.d_vinv, M.d_eperm, tmp, mat, ge, He, s);
+    HIPC(hipStreamSynchronize(s));
+    dfree(tmp);
+    return CC_OK;
+  });
+}
+
+cc_status cc_probe_sweep(cc_ctx* ctx, int32_t mesh_id, const double* x, const double* x_tilde, double dt,
+                         const cc_params* params, double* energy, double* g, double* dx) {
+  return guarded(ctx, [&]() -> cc_status {
+    Mesh& M = get_mesh(ctx, mesh_id);
+    if (!x || !x_tilde) return fail(ctx, CC_E_INVALID_ARG, "null probe input");
+    cc_status st = check_params(ctx, params, M, dt);
+    if (st != CC_OK) return st;
+    const cc_params& p = *params;
+    hipStream_t s = ctx->stream;
+    Material mat{};
+    mat.mu = M.mu; mat.lam = M.lam;
+    mat.w_in = p.quasistatic ? 0.0 : 1.0;
+    mat.s_el = p.quasistatic ? 1.0 : dt * dt;
+    for (int c = 0; c < 3; ++c) mat.grav[c] = p.gravity[c];
+    Stepper S{ctx, M, M.view(), mat, p, s};
+    cc::launch_gather_user(S.mv, M.d_vinv, x, M.x, s);
+    cc::launch_gather_user(S.mv, M.d_vinv, x_tilde, M.xt, s);
+    if (energy) *energy = S.energy(M.x);
+    S.gradient_only(M.x);
+    if (g) cc::launch_scatter_user(S.mv, M.d_vperm, M.g, g, 1, s);
+    if (dx) {
+      S.hessian(M.x);
+      HIPC(hipMemsetAsync(M.fb, 0, 4 * sizeof(unsigned long long), s));
+      cc::launch_cc_prep(S.mv, p.precision, p.method, 0, M.nf, M.hb, M.KL, M.fb, s);
+      cc::launch_cc_update(S.mv, p.precision, p.method, 0, M.nf, M.KL, M.g, M.dvec, 0, s);
+      cc::launch_scatter_user(S.mv, M.d_vperm, M.dvec, dx, 1, s);
+    }
+    HIPC(hipStreamSynchronize(s));
+    return CC_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Internal declarations shared by the host library and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cc {
+
+// Device view of one mesh in the internal (colour-sorted) order.
+// Vertices 0..nf-1 are free and sorted by colour; nf..n-1 are Dirichlet.
+struct MeshView {
+  int D;            // 2 or 3
+  int n, nf, m;     // vertices, free vertices, elements
+  const int* ev;    // [(D+1)][m] internal vertex ids
+  const double* dinv_d;  // [D*D][m], row a-1 of Dm^{-1} = beta_a for a = 1..D
+  const float* dinv_f;
+  const double* vol_d;   // [m] rest volumes
+  const float* vol_f;
+  const double* mass;    // [n] lumped masses
+  const int* star_ptr;   // [nf+1]  incidence of free vertices
+  const int* star;       // packed e*4 + local index
+  const int* rowptr;     // [nf+1]  block rows over free vertices, diagonal first
+  const int* colidx;     // [nnzb]
+  const int* blkrow;     // [nnzb]  row of each block slot
+  const int* cptr;       // [nnzb+1] element contributions of each block slot
+  const int* centry;     // packed e*16 + a*4 + b
+  int nnzb;
+  // perturbation basis, internal ids, rows sorted by internal id
+  const int64_t* sptr;   // [nf+1]
+  const int* sidx;
+  const double* U_d;     // [nnz][D*D]
+  const float* U_f;
+  int dense_supp;        // 1: supp(i) = every free vertex except i
+};
+
+struct Material {
+  double mu, lam;        // stable neo-Hookean mu and lambda = lambda_L + mu
+  double w_in;           // weight of the inertia term (1 dynamic, 0 quasistatic)
+  double s_el;           // weight of the elastic and gravity terms (h^2 or 1)
+  double grav[3];
+};
+
+// ---- launch wrappers (cc_kernels.hip) --------------------------------------
+void launch_predict(const MeshView& mv, const int* vperm, const double* x_user,
+                    const double* v_user, const double* x_bc, double h, int quasi,
+                    double* x, double* xt, double* x0, int* bad, hipStream_t s);
+void launch_finalize(const MeshView& mv, const int* vperm, const double* x, const double* x0,
+                     double h, int quasi, double* x_user, double* v_user, hipStream_t s);
+void launch_elem_hess(const MeshView& mv, int prec, const double* x, const Material& mat,
+                      double scale, void* estore, hipStream_t s);
+void launch_assemble(const MeshView& mv, int prec, const void* estore, const Material& mat,
+                     void* hb, hipStream_t s);
+void launch_gradient(const MeshView& mv, const double* x, const double* xt, const Material& mat,
+                     double* g, double* partials, int* nparts, hipStream_t s);
+void launch_cc_prep(const MeshView& mv, int prec, int method, int v0, int v1, const void* hb,
+                    void* KL, unsigned long long* fallbacks, hipStream_t s);
+void launch_cc_update(const MeshView& mv, int prec, int method, int v0, int v1, const void* KL,
+                      const double* g, double* x_or_d, int accumulate, hipStream_t s);
+void launch_energy(const MeshView& mv, const double* x, const double* xt, const Material& mat,
+                   double* partials, int* nparts, hipStream_t s);
+void launch_reduce(const double* partials, int n, double* out, hipStream_t s);
+void launch_axpy(int count, const double* x, const double* d, double alpha, double* out,
+                 hipStream_t s);
+void launch_probe_element(const MeshView& mv, int prec, const double* x_user,
+                          const int* vperm_inv, const int* eperm, double* xi_tmp,
+                          const Material& mat, double* ge, double* He, hipStream_t s);
+void launch_gather_user(const MeshView& mv, const int* vperm_inv, const double* src_user,
+                        double* dst_int, hipStream_t s);
+void launch_scatter_user(const MeshView& mv, const int* vperm, const double* src_int,
+                         double* dst_user, int free_only, hipStream_t s);
+
+int reduce_partials_capacity(const MeshView& mv);
+
+}  // namespace cc

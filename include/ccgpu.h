@@ -129,7 +129,7 @@ cc_status cc_subspace_upload(cc_ctx* ctx, int32_t mesh_id, const int64_t* ptr,
    radius > 0: patch basis, support = free vertices within `radius` hops,
                everything outside the patch held, U_i = -H[C,C]^{-1} H[C,i];
    radius = 0: exact basis over every other free vertex (limited to meshes
-               with at most 4096 free vertices).
+               with at most 1024 free vertices).
    The rest Hessian is evaluated by the library's own GPU kernels in FP64;
    the small dense solves run on the host. */
 cc_status cc_subspace_build(cc_ctx* ctx, int32_t mesh_id, int32_t radius, double dt,
@@ -178,6 +178,26 @@ cc_status cc_probe_element(cc_ctx* ctx, int32_t mesh_id, const double* x, int32_
 cc_status cc_probe_sweep(cc_ctx* ctx, int32_t mesh_id, const double* x, const double* x_tilde,
                          double dt, const cc_params* params, double* energy, double* g,
                          double* dx);
+
+/* ---- measurement --------------------------------------------------------- */
+
+/* Kernel identifiers for cc_profile_*. */
+#define CC_K_ELEM_HESS  0   /* element Hessians                          */
+#define CC_K_ASSEMBLE   1   /* block-row assembly                        */
+#define CC_K_GRADIENT   2   /* float64 free-vertex gradient + norm parts  */
+#define CC_K_CC_PREP    3   /* per-vertex condensation (A, Ht, K, L)      */
+#define CC_K_CC_UPDATE  4   /* per-vertex update dx = -K (g - L U^T g)    */
+#define CC_K_ENERGY     5   /* float64 step energy partials               */
+#define CC_K_COUNT      6
+
+/* Record the duration of every launch of the kernels whose bit is set in
+   `mask` (bit k = kernel id k) with HIP events on the context's stream;
+   mask = 0 stops recording.  Enabling clears the accumulators.  Timing adds
+   two event records per timed launch. */
+cc_status cc_profile_enable(cc_ctx* ctx, int32_t mask);
+/* Accumulated device milliseconds and launch count of kernel `kernel_id`
+   since the last cc_profile_enable (host outputs). */
+cc_status cc_profile_read(cc_ctx* ctx, int32_t kernel_id, double* total_ms, int64_t* launches);
 
 #ifdef __cplusplus
 }

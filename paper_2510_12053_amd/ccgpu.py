@@ -70,6 +70,8 @@ def lib():
             "cc_step_info": (I32, [P, I32, pD, pD, P, pI64, pI32]),
             "cc_probe_element": (I32, [P, I32, P, I32, P, P]),
             "cc_probe_sweep": (I32, [P, I32, P, P, D, ctypes.POINTER(cc_params), pD, P, P]),
+            "cc_profile_enable": (I32, [P, I32]),
+            "cc_profile_read": (I32, [P, I32, pD, pI64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -232,3 +234,18 @@ def cc_probe_sweep(ctx, mesh_id, x, x_tilde, dt, params, want_g=True, want_dx=Tr
     _check(ctx, lib().cc_probe_sweep(ctx.handle, mesh_id, _dptr(x), _dptr(x_tilde), dt,
                                      ctypes.byref(params), ctypes.byref(e), _dptr(g), _dptr(dx)))
     return e.value, g, dx
+
+
+K_ELEM_HESS, K_ASSEMBLE, K_GRADIENT, K_CC_PREP, K_CC_UPDATE, K_ENERGY = range(6)
+K_NAMES = ["elem_hess", "assemble", "gradient", "cc_prep", "cc_update", "energy"]
+
+
+def cc_profile_enable(ctx, mask):
+    _check(ctx, lib().cc_profile_enable(ctx.handle, mask))
+
+
+def cc_profile_read(ctx, kernel_id):
+    ms = ctypes.c_double(0)
+    n = ctypes.c_int64(0)
+    _check(ctx, lib().cc_profile_read(ctx.handle, kernel_id, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value

@@ -128,6 +128,43 @@ struct cc_ctx {
   std::string err;
   std::vector<Mesh*> meshes;
   double* pinned = nullptr;  // host pinned scalars
+  // kernel timing (cc_profile_*)
+  int prof_mask = 0;
+  double prof_ms[CC_K_COUNT] = {0};
+  long long prof_n[CC_K_COUNT] = {0};
+  struct Pending { int kid; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+
+  hipEvent_t take_event() {
+    if (!event_pool.empty()) { hipEvent_t e = event_pool.back(); event_pool.pop_back(); return e; }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  // Call only after the stream has been synchronised.
+  void harvest() {
+    for (auto& p : pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        prof_ms[p.kid] += ms;
+        prof_n[p.kid] += 1;
+      }
+      event_pool.push_back(p.a);
+      event_pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+  template <typename F>
+  void timed(int kid, F&& launch) {
+    if (!(prof_mask & (1 << kid))) { launch(); return; }
+    hipEvent_t a = take_event(), b = take_event();
+    if (!a || !b) { launch(); return; }
+    (void)hipEventRecord(a, stream);
+    launch();
+    (void)hipEventRecord(b, stream);
+    pending.push_back({kid, a, b});
+  }
 };
 
 namespace {
@@ -626,37 +663,44 @@ struct Stepper {
   double read_scalar(const double* dptr) {
     HIPC(hipMemcpyAsync(ctx->pinned, dptr, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
+    ctx->harvest();
     return ctx->pinned[0];
   }
   double energy(const double* x) {
     int np = 0;
-    cc::launch_energy(mv, x, M.xt, mat, M.partials, &np, s);
+    ctx->timed(CC_K_ENERGY, [&] { cc::launch_energy(mv, x, M.xt, mat, M.partials, &np, s); });
     cc::launch_reduce(M.partials, np, M.scal, s);
     return read_scalar(M.scal);
   }
   double grad_norm2(const double* x) {
     int np = 0;
-    cc::launch_gradient(mv, x, M.xt, mat, M.g, M.partials, &np, s);
+    ctx->timed(CC_K_GRADIENT, [&] { cc::launch_gradient(mv, x, M.xt, mat, M.g, M.partials, &np, s); });
     if (np == 0) return 0.0;
     cc::launch_reduce(M.partials, np, M.scal + 1, s);
     return read_scalar(M.scal + 1);
   }
   void gradient_only(const double* x) {
     int np = 0;
-    cc::launch_gradient(mv, x, M.xt, mat, M.g, M.partials, &np, s);
+    ctx->timed(CC_K_GRADIENT, [&] { cc::launch_gradient(mv, x, M.xt, mat, M.g, M.partials, &np, s); });
   }
   void hessian(const double* x) {
-    cc::launch_elem_hess(mv, p.precision, x, mat, mat.s_el, M.estore, s);
-    cc::launch_assemble(mv, p.precision, M.estore, mat, M.hb, s);
+    ctx->timed(CC_K_ELEM_HESS, [&] { cc::launch_elem_hess(mv, p.precision, x, mat, mat.s_el, M.estore, s); });
+    ctx->timed(CC_K_ASSEMBLE, [&] { cc::launch_assemble(mv, p.precision, M.estore, mat, M.hb, s); });
+  }
+  void prep(int method, int v0, int v1) {
+    ctx->timed(CC_K_CC_PREP, [&] { cc::launch_cc_prep(mv, p.precision, method, v0, v1, M.hb, M.KL, M.fb, s); });
+  }
+  void update(int method, int v0, int v1, double* out, int acc) {
+    ctx->timed(CC_K_CC_UPDATE, [&] { cc::launch_cc_update(mv, p.precision, method, v0, v1, M.KL, M.g, out, acc, s); });
   }
   // One sweep from x into out (x unchanged).  method as requested.
   void sweep(const double* x, double* out, int method) {
     const int nd = M.D * M.n;
     if (p.sweep == CC_SWEEP_JACOBI) {
       hessian(x);
-      cc::launch_cc_prep(mv, p.precision, method, 0, M.nf, M.hb, M.KL, M.fb, s);
+      prep(method, 0, M.nf);
       gradient_only(x);
-      cc::launch_cc_update(mv, p.precision, method, 0, M.nf, M.KL, M.g, M.dvec, 0, s);
+      update(method, 0, M.nf, M.dvec, 0);
       cc::launch_axpy(nd, x, M.dvec, 1.0, out, s);
       return;
     }
@@ -666,13 +710,13 @@ struct Stepper {
       if (v1 <= v0) continue;
       if (p.hess_refresh == CC_HESS_PER_COLOR) {
         hessian(out);
-        cc::launch_cc_prep(mv, p.precision, method, v0, v1, M.hb, M.KL, M.fb, s);
+        prep(method, v0, v1);
       } else if (c == 0) {
         hessian(out);
-        cc::launch_cc_prep(mv, p.precision, method, 0, M.nf, M.hb, M.KL, M.fb, s);
+        prep(method, 0, M.nf);
       }
       gradient_only(out);
-      cc::launch_cc_update(mv, p.precision, method, v0, v1, M.KL, M.g, out, 1, s);
+      update(method, v0, v1, out, 1);
     }
   }
 };
@@ -720,10 +764,33 @@ void cc_destroy(cc_ctx* ctx) {
   for (Mesh* M : ctx->meshes)
     if (M) { free_mesh(*M); delete M; }
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  ctx->harvest();
+  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   delete ctx;
 }
 
 const char* cc_last_error(const cc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+cc_status cc_profile_enable(cc_ctx* ctx, int32_t mask) {
+  return guarded(ctx, [&]() -> cc_status {
+    HIPC(hipStreamSynchronize(ctx->stream));
+    ctx->harvest();
+    ctx->prof_mask = mask;
+    for (int k = 0; k < CC_K_COUNT; ++k) { ctx->prof_ms[k] = 0; ctx->prof_n[k] = 0; }
+    return CC_OK;
+  });
+}
+
+cc_status cc_profile_read(cc_ctx* ctx, int32_t kernel_id, double* total_ms, int64_t* launches) {
+  return guarded(ctx, [&]() -> cc_status {
+    if (kernel_id < 0 || kernel_id >= CC_K_COUNT) return fail(ctx, CC_E_INVALID_ARG, "bad kernel id");
+    HIPC(hipStreamSynchronize(ctx->stream));
+    ctx->harvest();
+    if (total_ms) *total_ms = ctx->prof_ms[kernel_id];
+    if (launches) *launches = ctx->prof_n[kernel_id];
+    return CC_OK;
+  });
+}
 
 cc_status cc_mesh_upload(cc_ctx* ctx, int32_t dim, int32_t n_verts, const double* X, int32_t n_elems,
                          const int32_t* elems, const uint8_t* is_fixed, double youngs, double poisson,
@@ -923,6 +990,7 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
     HIPC(hipMemcpyAsync(fbh, M.fb, sizeof(fbh), hipMemcpyDeviceToHost, s));
     cc::launch_finalize(S.mv, M.d_vperm, M.x, M.x0, h, p.quasistatic, x, v, s);
     HIPC(hipStreamSynchronize(s));
+    ctx->harvest();
     for (int c = 0; c < 3; ++c) M.last_fb[c] = (long long)fbh[c];
     M.last_warm = 0;
     if (iters) *iters = k;

@@ -535,75 +535,60 @@ __device__ __forceinline__ int find_slot(const MeshView& mv, int64_t sp0, int64_
 // Per-vertex condensation: A_i = H_iC U_i, Ht_i = U_i^T H_CC U_i, then
 // K_i = (H_ii - A Ht^{-1} A^T)^{-1} and L_i = A Ht^{-1} (CC), with the
 // coordinate-descent and JGS2 forms as special cases.  G lanes per vertex.
-template <typename T, int D, int G>
-__global__ void __launch_bounds__(WG) k_cc_prep(MeshView mv, int method, int v0, int v1,
-                                                const T* __restrict__ hb, T* __restrict__ KL,
-                                                unsigned long long* __restrict__ fb) {
+// Contribution of support row j to A_i (when row j holds block (j, i)) and to
+// Ht_i (blocks (j, k) with k in the support); Uk(k) returns U_i[k] or null.
+template <typename T, int D, typename LookupU>
+__device__ __forceinline__ void accum_row(const MeshView& mv, int i, int j, const T* Uj,
+                                          const T* __restrict__ hb, LookupU&& Uk_of, T* A, T* Ht) {
   constexpr int DD = D * D;
-  const T* Ub = basis_of<T>(mv);
-  const int lane = threadIdx.x % G;
-  const int i = v0 + blockIdx.x * (WG / G) + threadIdx.x / G;
-  const bool active = i < v1;
-  T A[DD], Ht[DD];
+  for (int t = mv.rowptr[j]; t < mv.rowptr[j + 1]; ++t) {
+    const int k = mv.colidx[t];
+    const T* H = hb + (size_t)t * DD;
+    if (k == i) {
+      // A += H_ji^T U_j
 #pragma unroll
-  for (int r = 0; r < DD; ++r) A[r] = Ht[r] = T(0);
-  int64_t sp0 = 0, sp1 = 0;
-  if (active && method != 0) {
-    sp0 = mv.sptr[i];
-    sp1 = mv.sptr[i + 1];
-    for (int64_t q = sp0 + lane; q < sp1; q += G) {
-      const int j = mv.sidx[q];
-      T Uj[DD];
+      for (int r = 0; r < D; ++r)
 #pragma unroll
-      for (int r = 0; r < DD; ++r) Uj[r] = Ub[q * DD + r];
-      for (int t = mv.rowptr[j]; t < mv.rowptr[j + 1]; ++t) {
-        const int k = mv.colidx[t];
-        const T* H = hb + (size_t)t * DD;
-        if (k == i) {
-          // A += H_ji^T U_j
+        for (int s = 0; s < D; ++s) {
+          T acc = T(0);
 #pragma unroll
-          for (int r = 0; r < D; ++r)
-#pragma unroll
-            for (int s = 0; s < D; ++s) {
-              T acc = T(0);
-#pragma unroll
-              for (int l = 0; l < D; ++l) acc += H[l * D + r] * Uj[l * D + s];
-              A[r * D + s] += acc;
-            }
-        } else {
-          const int qk = find_slot(mv, sp0, sp1, i, k);
-          if (qk < 0) continue;
-          T M[DD];  // H_jk U_k
-#pragma unroll
-          for (int r = 0; r < D; ++r)
-#pragma unroll
-            for (int s = 0; s < D; ++s) {
-              T acc = T(0);
-#pragma unroll
-              for (int l = 0; l < D; ++l) acc += H[r * D + l] * Ub[(size_t)qk * DD + l * D + s];
-              M[r * D + s] = acc;
-            }
-#pragma unroll
-          for (int r = 0; r < D; ++r)
-#pragma unroll
-            for (int s = 0; s < D; ++s) {
-              T acc = T(0);
-#pragma unroll
-              for (int l = 0; l < D; ++l) acc += Uj[l * D + r] * M[l * D + s];
-              Ht[r * D + s] += acc;
-            }
+          for (int l = 0; l < D; ++l) acc += H[l * D + r] * Uj[l * D + s];
+          A[r * D + s] += acc;
         }
+      continue;
+    }
+    const T* Uk = Uk_of(k);
+    if (!Uk) continue;
+    T Hl[DD], M[DD];
+#pragma unroll
+    for (int r = 0; r < DD; ++r) Hl[r] = H[r];
+#pragma unroll
+    for (int r = 0; r < D; ++r)   // M = H_jk U_k
+#pragma unroll
+      for (int s = 0; s < D; ++s) {
+        T acc = T(0);
+#pragma unroll
+        for (int l = 0; l < D; ++l) acc += Hl[r * D + l] * Uk[l * D + s];
+        M[r * D + s] = acc;
       }
-    }
+#pragma unroll
+    for (int r = 0; r < D; ++r)   // Ht += U_j^T M
+#pragma unroll
+      for (int s = 0; s < D; ++s) {
+        T acc = T(0);
+#pragma unroll
+        for (int l = 0; l < D; ++l) acc += Uj[l * D + r] * M[l * D + s];
+        Ht[r * D + s] += acc;
+      }
   }
-#pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1)
-#pragma unroll
-    for (int r = 0; r < DD; ++r) {
-      A[r] += __shfl_xor(A[r], off, G);
-      Ht[r] += __shfl_xor(Ht[r], off, G);
-    }
-  if (!active || lane != 0) return;
+}
+
+// Small solves of one vertex from the reduced A_i and Ht_i; writes K_i, L_i.
+template <typename T, int D>
+__device__ void cc_finish(const MeshView& mv, int method, int i, bool empty, const T* A,
+                          const T* Ht, const T* __restrict__ hb, T* __restrict__ KL,
+                          unsigned long long* __restrict__ fb) {
+  constexpr int DD = D * D;
   T Hii[D][D], Kout[D][D], Lout[D][D], Lc[D][D], I[D][D];
   const T* hd = hb + (size_t)mv.rowptr[i] * DD;
 #pragma unroll
@@ -625,7 +610,6 @@ __global__ void __launch_bounds__(WG) k_cc_prep(MeshView mv, int method, int v0,
 #pragma unroll
       for (int s = 0; s < D; ++s) Kcd[r][s] = T(0);
   bool use_cd = true;
-  const bool empty = (sp1 == sp0);
   if (method == 1) {  // Coordinate Condensation
     T Htm[D][D], Lt[D][D];
 #pragma unroll
@@ -695,6 +679,109 @@ __global__ void __launch_bounds__(WG) k_cc_prep(MeshView mv, int method, int v0,
       o[DD + r * D + s] = Lout[r][s];
     }
 }
+
+// Generic condensation kernel: G lanes per vertex, basis and support from
+// global memory (binary search for the support slot of a neighbour).
+template <typename T, int D, int G>
+__global__ void __launch_bounds__(WG) k_cc_prep(MeshView mv, int method, int v0, int v1,
+                                                const T* __restrict__ hb, T* __restrict__ KL,
+                                                unsigned long long* __restrict__ fb) {
+  constexpr int DD = D * D;
+  const T* Ub = basis_of<T>(mv);
+  const int lane = threadIdx.x % G;
+  const int i = v0 + blockIdx.x * (WG / G) + threadIdx.x / G;
+  const bool active = i < v1;
+  T A[DD], Ht[DD];
+#pragma unroll
+  for (int r = 0; r < DD; ++r) A[r] = Ht[r] = T(0);
+  int64_t sp0 = 0, sp1 = 0;
+  if (active && method != 0) {
+    sp0 = mv.sptr[i];
+    sp1 = mv.sptr[i + 1];
+    for (int64_t q = sp0 + lane; q < sp1; q += G) {
+      const int j = mv.sidx[q];
+      T Uj[DD];
+#pragma unroll
+      for (int r = 0; r < DD; ++r) Uj[r] = Ub[q * DD + r];
+      accum_row<T, D>(mv, i, j, Uj, hb, [&](int k) -> const T* {
+        const int qk = find_slot(mv, sp0, sp1, i, k);
+        return qk < 0 ? nullptr : Ub + (size_t)qk * DD;
+      }, A, Ht);
+    }
+  }
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1)
+#pragma unroll
+    for (int r = 0; r < DD; ++r) {
+      A[r] += __shfl_xor(A[r], off, G);
+      Ht[r] += __shfl_xor(Ht[r], off, G);
+    }
+  if (!active || lane != 0) return;
+  cc_finish<T, D>(mv, method, i, sp1 == sp0, A, Ht, hb, KL, fb);
+}
+
+// Exact-basis condensation: one workgroup per vertex; the vertex's dense
+// basis row U_i (every other free vertex) is staged in LDS, so the H_jk U_k
+// products read U_k from LDS while the block rows stream from global memory.
+template <typename T, int D>
+__global__ void __launch_bounds__(WG) k_cc_prep_dense(MeshView mv, int method, int v0,
+                                                      const T* __restrict__ hb, T* __restrict__ KL,
+                                                      unsigned long long* __restrict__ fb) {
+  constexpr int DD = D * D;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Us = reinterpret_cast<T*>(smem_raw);
+  __shared__ T red[WG / 64][2 * DD];
+  const T* Ub = basis_of<T>(mv);
+  const int i = v0 + blockIdx.x;
+  const int cnt = mv.nf - 1;
+  const int64_t sp0 = mv.sptr[i];
+  for (int q = threadIdx.x; q < cnt * DD; q += WG) Us[q] = Ub[sp0 * DD + q];
+  __syncthreads();
+  T A[DD], Ht[DD];
+#pragma unroll
+  for (int r = 0; r < DD; ++r) A[r] = Ht[r] = T(0);
+  if (method != 0) {
+    for (int a = threadIdx.x; a < cnt; a += WG) {
+      const int j = a < i ? a : a + 1;
+      T Uj[DD];
+#pragma unroll
+      for (int r = 0; r < DD; ++r) Uj[r] = Us[a * DD + r];
+      accum_row<T, D>(mv, i, j, Uj, hb, [&](int k) -> const T* {
+        return Us + (size_t)(k < i ? k : k - 1) * DD;
+      }, A, Ht);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int r = 0; r < DD; ++r) {
+      A[r] += __shfl_xor(A[r], off, 64);
+      Ht[r] += __shfl_xor(Ht[r], off, 64);
+    }
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  if (l == 0) {
+#pragma unroll
+    for (int r = 0; r < DD; ++r) {
+      red[w][r] = A[r];
+      red[w][DD + r] = Ht[r];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+#pragma unroll
+  for (int r = 0; r < DD; ++r) {
+    T a = T(0), h = T(0);
+#pragma unroll
+    for (int ww = 0; ww < WG / 64; ++ww) {
+      a += red[ww][r];
+      h += red[ww][DD + r];
+    }
+    A[r] = a;
+    Ht[r] = h;
+  }
+  cc_finish<T, D>(mv, method, i, cnt == 0, A, Ht, hb, KL, fb);
+}
+
 
 // dx_i = -K_i (g_i - L_i U_i^T g_C); written to d (Jacobi) or added to x
 // (coloured sweep).  G lanes per vertex share its support.
@@ -978,9 +1065,24 @@ static int support_lanes(const MeshView& mv) {
   return 16;
 }
 
+constexpr size_t DENSE_LDS_LIMIT = 64 * 1024;
+
+template <typename T, int D>
+static bool prep_dense(const MeshView& mv, int method, int v0, int v1, const void* hb, void* KL,
+                       unsigned long long* fb, hipStream_t s) {
+  const size_t lds = (size_t)(mv.nf - 1) * D * D * sizeof(T);
+  if (!mv.dense_supp || mv.nf < 2 || lds > DENSE_LDS_LIMIT) return false;
+  k_cc_prep_dense<T, D><<<v1 - v0, WG, lds, s>>>(mv, method, v0, (const T*)hb, (T*)KL, fb);
+  return true;
+}
+
 void launch_cc_prep(const MeshView& mv, int prec, int method, int v0, int v1, const void* hb,
                     void* KL, unsigned long long* fb, hipStream_t s) {
   if (v1 <= v0) return;
+  bool done = false;
+  if (prec == 0) CC_DISPATCH_D(mv.D, done = prep_dense<double, D>(mv, method, v0, v1, hb, KL, fb, s));
+  else CC_DISPATCH_D(mv.D, done = prep_dense<float, D>(mv, method, v0, v1, hb, KL, fb, s));
+  if (done) return;
   const int G = support_lanes(mv);
   if (prec == 0) CC_DISPATCH_D(mv.D, prep_g<double, D>(mv, method, v0, v1, hb, KL, fb, G, s));
   else CC_DISPATCH_D(mv.D, prep_g<float, D>(mv, method, v0, v1, hb, KL, fb, G, s));

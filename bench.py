@@ -126,12 +126,13 @@ def main():
     ap.add_argument("--sweep", choices=["jacobi", "gs"], default="jacobi")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--iters-per-graph", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding of this path is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
-    if args.warmup + args.steps > 10:
+    if args.warmup + args.steps > 10 or args.steps < 1:
         print("the bar trajectory has 10 steps: warmup + steps must be <= 10", file=sys.stderr)
         sys.exit(2)
 
@@ -141,63 +142,108 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream(dev)
+    stream = torch.cuda.Stream(device=dev)          # capturable stream for the batched graphs
+    torch.cuda.set_stream(stream)
     ctx = cg.cc_create(0, stream)
     prec = cg.FP64 if args.precision == "fp64" else cg.FP32_MIXED
     sweep = cg.SWEEP_JACOBI if args.sweep == "jacobi" else cg.SWEEP_COLORED_GS
     scenes = [tet_bar(E=E) for E in E_SWEEP]
-    meshes = []
-    for s in scenes:
-        mid = cg.cc_mesh_upload(ctx, s.X, s.elems, s.fixed, s.E, s.nu, s.rho)
-        cg.cc_subspace_build(ctx, mid, 0, s.dt, False)       # exact basis, untimed precompute
-        x, v = s.initial_state()
-        xs = torch.tensor(x, dtype=torch.float64, device=dev)
-        vs = torch.tensor(v, dtype=torch.float64, device=dev)
-        bcs = [torch.tensor(s.targets(t), dtype=torch.float64, device=dev) for t in range(1, 11)]
-        par = cg.cc_params_default(method=cg.METHOD_CC, sweep=sweep, precision=prec, line_search=1,
-                                   max_iters=10000, gravity=s.gravity)
-        meshes.append((s, mid, xs, vs, bcs, par))
     nfree = [int((~s.fixed.astype(bool)).sum()) for s in scenes]
 
-    def bench_step(t, record):
+    def make_meshes():
+        out = []
+        for s in scenes:
+            mid = cg.cc_mesh_upload(ctx, s.X, s.elems, s.fixed, s.E, s.nu, s.rho)
+            cg.cc_subspace_build(ctx, mid, 0, s.dt, False)   # exact basis, untimed precompute
+            x, v = s.initial_state()
+            xs = torch.tensor(x, dtype=torch.float64, device=dev)
+            vs = torch.tensor(v, dtype=torch.float64, device=dev)
+            bcs = [torch.tensor(s.targets(t), dtype=torch.float64, device=dev) for t in range(1, 11)]
+            par = cg.cc_params_default(method=cg.METHOD_CC, sweep=sweep, precision=prec, line_search=1,
+                                       max_iters=10000, gravity=s.gravity)
+            out.append((s, mid, xs, vs, bcs, par))
+        return out
+
+    MASK = (1 << 6) - 1
+
+    def run_plain(meshes, t, rec):
         for (s, mid, xs, vs, bcs, par), nf in zip(meshes, nfree):
             t0 = time.perf_counter()
             st, it, rg = cg.cc_step(ctx, mid, xs, vs, bcs[t], s.dt, par, TOL)
-            dt_ms = (time.perf_counter() - t0) * 1e3
-            if record is not None:
-                record.append((st, it, rg, dt_ms, it * nf))
+            if rec is not None:
+                rec.append((st, it, rg, (time.perf_counter() - t0) * 1e3, it * nf))
 
-    for t in range(args.warmup):
-        bench_step(t, None)
-    torch.cuda.synchronize()
-    cg.cc_profile_enable(ctx, (1 << 6) - 1)
-    rec = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for t in range(args.warmup, args.warmup + args.steps):
-        bench_step(t, rec)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    kern = {cg.K_NAMES[k]: cg.cc_profile_read(ctx, k) for k in range(6)}
-    cg.cc_profile_enable(ctx, 0)
+    def run_batch(meshes, t, rec):
+        ids = [m[1] for m in meshes]
+        par = meshes[0][5]
+        grav = np.stack([m[0].gravity for m in meshes])
+        t0 = time.perf_counter()
+        worst, its, rgs, sts = cg.cc_step_batch(ctx, ids, [m[2] for m in meshes], [m[3] for m in meshes],
+                                                [m[4][t] for m in meshes], scenes[0].dt, par, TOL,
+                                                gravity=grav)
+        ms = (time.perf_counter() - t0) * 1e3
+        if rec is not None:
+            for k in range(len(meshes)):
+                rec.append((int(sts[k]), int(its[k]), float(rgs[k]), ms, int(its[k]) * nfree[k]))
 
-    updates = sum(r[4] for r in rec)
-    iters = [r[1] for r in rec]
-    ttt = np.array([r[3] for r in rec])
-    bad = [r for r in rec if r[0] != cg.CC_OK]
-    value = updates / elapsed
+    def timed(runner, meshes, profile=True):
+        for t in range(args.warmup):
+            runner(meshes, t, None)
+        torch.cuda.synchronize()
+        cg.cc_profile_enable(ctx, MASK if profile else 0)
+        rec = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(args.warmup, args.warmup + args.steps):
+            runner(meshes, t, rec)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        kern = {cg.K_NAMES[k]: cg.cc_profile_read(ctx, k) for k in range(6)}
+        cg.cc_profile_enable(ctx, 0)
+        return rec, elapsed, kern
 
-    # dominant kernel and its roofline position
-    dom = max(kern, key=lambda k: kern[k][0])
-    ms_tot, launches = kern[dom]
-    avg_s = ms_tot / max(launches, 1) * 1e-3
+    # plain CC: one mesh at a time, single-mesh launches, host-driven iteration
+    plain_meshes = make_meshes()
+    rec_p, el_p, kern_p = timed(run_plain, plain_meshes)
+    # batched: all bars in every launch, graph replays, autotuned lanes
+    batch_meshes = make_meshes()
+    lanes, lane_ms = cg.cc_autotune_batch(ctx, [m[1] for m in batch_meshes], batch_meshes[0][5])
+    cg.cc_batch_tuning(ctx, lanes, args.iters_per_graph)
+    rec_b, el_b, _ = timed(run_batch, batch_meshes, profile=False)
+    # second timed region of the same batched launches, uncaptured, with HIP
+    # events around every kernel: per-kernel durations for the roofline
+    prof_meshes = make_meshes()
+    rec_k, el_k, kern_b = timed(run_batch, prof_meshes, profile=True)
+
+    def summary(rec, elapsed, steps):
+        upd = sum(r[4] for r in rec)
+        ttt = np.array([r[3] for r in rec])
+        return {"vertex_updates_per_s": round(upd / elapsed, 1),
+                "ms_per_step": round(elapsed / steps * 1e3, 3),
+                "time_to_tol_ms": {"median": round(float(np.median(ttt)), 3),
+                                   "p90": round(float(np.percentile(ttt, 90)), 3)},
+                "iters_per_bar_step": round(float(np.mean([r[1] for r in rec])), 2),
+                "not_ok": sum(1 for r in rec if r[0] != cg.CC_OK)}
+
+    plain = summary(rec_p, el_p, args.steps)
+    batched = summary(rec_b, el_b, args.steps)
+    # for the batch, every bar's step ends with the batch: time to tolerance = batch step time
+    value = batched["vertex_updates_per_s"]
+
+    # dominant kernel of the batched path and its roofline position:
+    # algorithmic bytes (flops) = per-mesh model x that mesh's iterations
     S = 8 if prec == cg.FP64 else 4
-    model = kernel_models(scenes, S)
-    # launches of one kernel process one mesh; average the per-mesh model
-    per_launch_bytes = model["bytes"][dom] / len(scenes)
-    per_launch_flops = model["flops"][dom] / len(scenes)
-    gbs = per_launch_bytes / avg_s / 1e9
-    tfl = per_launch_flops / avg_s / 1e12
+    per_mesh = [kernel_models([s], S) for s in scenes]
+    its_mesh = [0] * len(scenes)
+    for k, r in enumerate(rec_k):
+        its_mesh[k % len(scenes)] += r[1]
+    dom = max(kern_b, key=lambda k: kern_b[k][0])
+    ms_tot, launches = kern_b[dom]
+    tot_bytes = sum(i * m["bytes"][dom] for i, m in zip(its_mesh, per_mesh))
+    tot_flops = sum(i * m["flops"][dom] for i, m in zip(its_mesh, per_mesh))
+    secs = ms_tot * 1e-3
+    gbs = tot_bytes / secs / 1e9
+    tfl = tot_flops / secs / 1e12
     peak_f = FP64_PEAK_TFLOPS if prec == cg.FP64 else FP32_PEAK_TFLOPS
     if tfl / peak_f >= gbs / HBM_PEAK_GBS:
         roof = {"bound": "alu", "achieved": round(tfl, 3), "peak": peak_f, "unit": "TFLOP/s",
@@ -205,18 +251,18 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    roof.update({"kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
-                 "traffic": None,
-                 "share_of_kernel_time": round(ms_tot / sum(v[0] for v in kern.values()), 3)})
+    roof.update({"kernel": "kb_" + dom, "avg_launch_us": round(ms_tot / max(launches, 1) * 1e3, 2),
+                 "launches": launches, "traffic": None,
+                 "share_of_kernel_time": round(ms_tot / sum(v[0] for v in kern_b.values()), 3)})
 
     out = {
         "metric": METRIC,
-        "value": round(value, 1),
+        "value": value,
         "unit": "vertex-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "ms_per_step": batched["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -225,13 +271,15 @@ def main():
         "config": {"workload": "bar21x6x6_Esweep", "bars": len(scenes), "E": list(E_SWEEP),
                    "verts_per_bar": scenes[0].n, "tets_per_bar": scenes[0].m, "basis": "exact",
                    "method": "cc", "sweep": args.sweep, "line_search": True, "tol": TOL,
-                   "dt": scenes[0].dt, "precision": args.precision},
-        "time_to_tol_ms_per_bar_step": {"median": round(float(np.median(ttt)), 3),
-                                        "p90": round(float(np.percentile(ttt, 90)), 3),
-                                        "mean": round(float(ttt.mean()), 3)},
-        "iters_per_bar_step": {"mean": round(float(np.mean(iters)), 2), "max": int(max(iters))},
-        "not_ok_steps": len(bad),
-        "kernel_ms": {k: round(v[0], 3) for k, v in kern.items()},
+                   "dt": scenes[0].dt, "precision": args.precision, "path": "batched",
+                   "lanes": lanes, "iters_per_graph": args.iters_per_graph},
+        "batched": batched,
+        "plain_cc": plain,
+        "speedup_batched_vs_plain": round(value / plain["vertex_updates_per_s"], 3),
+        "autotune_ms": lane_ms,
+        "kernel_ms_batched": {k: round(v[0], 3) for k, v in kern_b.items()},
+        "batched_uncaptured_ms_per_step": round(el_k / args.steps * 1e3, 3),
+        "kernel_ms_plain": {k: round(v[0], 3) for k, v in kern_p.items()},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

@@ -155,6 +155,37 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
                   double dt, const cc_params* params, double tol, int32_t* iters,
                   double* rel_grad);
 
+/* One implicit time step of n meshes stepped together (same dim, each with
+   its own material, basis and optional gravity).  Every launch of the
+   iteration covers all meshes; a mesh that reaches its tolerance or its
+   iteration cap is masked out while the others continue.  The launches of
+   `iters_per_graph` iterations (cc_batch_tuning) are captured once in a HIP
+   graph and replayed, with one host synchronisation per replay; meshes whose
+   energy rises at alpha = 1 are backtracked on the host (same rule as
+   cc_step).  Arrays (host): mesh_ids[n]; x[n], v[n] and x_bc[n] hold device
+   pointers as in cc_step (x_bc may be NULL or contain NULLs); gravity is
+   n x 3 (host) or NULL to use params->gravity for every mesh.  Outputs
+   (host, n each): iters, rel_grad, status (per-mesh cc_status).  The return
+   value is the worst per-mesh status (errors before warnings).  The stream
+   given to cc_create must not be the legacy null stream for graph capture;
+   with it the launches run uncaptured. */
+cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double* const* x,
+                        double* const* v, const double* const* x_bc, const double* gravity,
+                        double dt, const cc_params* params, double tol, int32_t* iters,
+                        double* rel_grad, int32_t* status);
+
+/* Tuning of the batched path.  lanes: lanes per vertex of the condensation
+   and update kernels for bases stored as sparse rows (16, 32 or 64);
+   iters_per_graph: iterations per graph replay (0 disables graphs).
+   cc_batch_tuning sets them for later cc_step_batch calls; cc_autotune_batch
+   times the condensation and update kernels of the given batch for every
+   lane count on the current device state (no simulation state changes),
+   keeps the fastest and returns it with the per-choice milliseconds
+   (ms_out: 3 values for 16, 32, 64; may be NULL). */
+cc_status cc_batch_tuning(cc_ctx* ctx, int32_t lanes, int32_t iters_per_graph);
+cc_status cc_autotune_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, const cc_params* params,
+                            int32_t* lanes_out, double* ms_out);
+
 /* Extra results of the last cc_step on a mesh (host outputs, any may be NULL):
    final step energy, the paper's normalised residual |g|/(V n E) (divided by
    h when dynamic), fallback counters (Ht or empty support, Schur, H_ii),

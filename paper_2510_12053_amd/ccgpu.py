@@ -70,6 +70,9 @@ def lib():
             "cc_step_info": (I32, [P, I32, pD, pD, P, pI64, pI32]),
             "cc_probe_element": (I32, [P, I32, P, I32, P, P]),
             "cc_probe_sweep": (I32, [P, I32, P, P, D, ctypes.POINTER(cc_params), pD, P, P]),
+            "cc_step_batch": (I32, [P, I32, P, P, P, P, P, D, ctypes.POINTER(cc_params), D, P, P, P]),
+            "cc_batch_tuning": (I32, [P, I32, I32]),
+            "cc_autotune_batch": (I32, [P, I32, P, ctypes.POINTER(cc_params), pI32, P]),
             "cc_profile_enable": (I32, [P, I32]),
             "cc_profile_read": (I32, [P, I32, pD, pI64]),
         }
@@ -249,3 +252,37 @@ def cc_profile_read(ctx, kernel_id):
     n = ctypes.c_int64(0)
     _check(ctx, lib().cc_profile_read(ctx.handle, kernel_id, ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def cc_step_batch(ctx, mesh_ids, xs, vs, x_bcs, dt, params, tol, gravity=None):
+    """Step several meshes together.  xs, vs, x_bcs: lists of float64 CUDA
+    tensors (x_bcs may be None or hold None); gravity: (n, 3) array or None.
+    Returns (worst status, iters[n], rel_grad[n], status[n])."""
+    n = len(mesh_ids)
+    ids = np.ascontiguousarray(mesh_ids, dtype=np.int32)
+    xp = (ctypes.c_void_p * n)(*[_dptr(t).value for t in xs])
+    vp = (ctypes.c_void_p * n)(*[_dptr(t).value for t in vs])
+    bp = None
+    if x_bcs is not None:
+        bp = (ctypes.c_void_p * n)(*[(_dptr(t).value if t is not None else None) for t in x_bcs])
+    g = None if gravity is None else np.ascontiguousarray(gravity, dtype=np.float64).reshape(n, 3)
+    it = np.zeros(n, dtype=np.int32)
+    rg = np.zeros(n, dtype=np.float64)
+    st = np.zeros(n, dtype=np.int32)
+    worst = _check(ctx, lib().cc_step_batch(ctx.handle, n, _ptr(ids), xp, vp, bp,
+                                            None if g is None else _ptr(g), dt, ctypes.byref(params),
+                                            tol, _ptr(it), _ptr(rg), _ptr(st)))
+    return worst, it, rg, st
+
+
+def cc_batch_tuning(ctx, lanes, iters_per_graph):
+    _check(ctx, lib().cc_batch_tuning(ctx.handle, lanes, iters_per_graph))
+
+
+def cc_autotune_batch(ctx, mesh_ids, params):
+    ids = np.ascontiguousarray(mesh_ids, dtype=np.int32)
+    lanes = ctypes.c_int32(0)
+    ms = np.zeros(3, dtype=np.float64)
+    _check(ctx, lib().cc_autotune_batch(ctx.handle, len(ids), _ptr(ids), ctypes.byref(params),
+                                        ctypes.byref(lanes), _ptr(ms)))
+    return lanes.value, dict(zip((16, 32, 64), ms.tolist()))

@@ -60,7 +60,7 @@ struct Mesh {
     MeshView v{};
     v.D = D; v.n = n; v.nf = nf; v.m = m;
     v.ev = ev; v.dinv_d = dinv_d; v.dinv_f = dinv_f; v.vol_d = vol_d; v.vol_f = vol_f;
-    v.mass = mass; v.star_ptr = star_ptr; v.star = star; v.rowptr = d_rowptr;
+    v.mass = mass; v.vperm = d_vperm; v.star_ptr = star_ptr; v.star = star; v.rowptr = d_rowptr;
     v.colidx = d_colidx; v.blkrow = blkrow; v.cptr = cptr; v.centry = centry; v.nnzb = nnzb;
     v.sptr = sptr; v.sidx = sidx; v.U_d = U_d; v.U_f = U_f; v.dense_supp = dense;
     return v;
@@ -135,6 +135,32 @@ struct cc_ctx {
   struct Pending { int kid; hipEvent_t a, b; };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> event_pool;
+  // batched stepping: tuning and the cached plan of the last batch
+  int batch_lanes = 16;
+  int batch_iters_per_graph = 4;
+  // kernel timing inside the batched path: event pairs of uncaptured launches
+  // go to `pending`; pairs captured into the graph stay registered and are
+  // read after every replay
+  std::vector<Pending> graph_pairs;
+  hipEvent_t hook_open[CC_K_COUNT] = {nullptr};
+  bool hook_on = false;
+
+  void harvest_graph() {
+    for (auto& p : graph_pairs) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        prof_ms[p.kid] += ms;
+        prof_n[p.kid] += 1;
+      }
+    }
+  }
+  void drop_graph_pairs() {
+    for (auto& p : graph_pairs) { event_pool.push_back(p.a); event_pool.push_back(p.b); }
+    graph_pairs.clear();
+  }
+  cc::BatchPlan* plan = nullptr;
+  std::vector<int> plan_ids;
+  std::vector<double> plan_key;
 
   hipEvent_t take_event() {
     if (!event_pool.empty()) { hipEvent_t e = event_pool.back(); event_pool.pop_back(); return e; }
@@ -749,7 +775,7 @@ cc_status cc_create(int32_t device, void* hip_stream, cc_ctx** out) {
   ctx->device = device;
   ctx->stream = (hipStream_t)hip_stream;
   if (hipSetDevice(device) != hipSuccess ||
-      hipHostMalloc((void**)&ctx->pinned, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&ctx->pinned, 64 * 1024, hipHostMallocDefault) != hipSuccess) {
     delete ctx;
     return CC_E_HIP;
   }
@@ -764,7 +790,9 @@ void cc_destroy(cc_ctx* ctx) {
   for (Mesh* M : ctx->meshes)
     if (M) { free_mesh(*M); delete M; }
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->plan) cc::batch_plan_destroy(ctx->plan);
   ctx->harvest();
+  ctx->drop_graph_pairs();
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   delete ctx;
 }
@@ -1060,6 +1088,298 @@ cc_status cc_probe_sweep(cc_ctx* ctx, int32_t mesh_id, const double* x, const do
       cc::launch_scatter_user(S.mv, M.d_vperm, M.dvec, dx, 1, s);
     }
     HIPC(hipStreamSynchronize(s));
+    return CC_OK;
+  });
+}
+
+
+// ---- batched stepping ----------------------------------------------------------
+static cc::BatchItem make_item(Mesh& M, const Material& mat) {
+  cc::BatchItem it{};
+  it.mv = M.view();
+  it.mat = mat;
+  it.x = M.x; it.xtrial = M.xtrial; it.xt = M.xt; it.x0 = M.x0; it.d = M.dvec; it.g = M.g;
+  it.estore = M.estore; it.hb = M.hb; it.KL = M.KL;
+  it.partials = M.partials;
+  it.fb = M.fb;
+  it.ncol = M.ncol;
+  for (int c = 0; c <= M.ncol && c <= cc::MAX_COLOURS; ++c) it.coff[c] = M.coff[c];
+  return it;
+}
+
+static cc_status batch_validate(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, const cc_params* params,
+                                double dt, std::vector<Mesh*>& ms) {
+  if (n <= 0 || !mesh_ids) return fail(ctx, CC_E_INVALID_ARG, "empty batch");
+  ms.clear();
+  for (int i = 0; i < n; ++i) {
+    Mesh& M = get_mesh(ctx, mesh_ids[i]);
+    for (Mesh* o : ms)
+      if (o == &M) return fail(ctx, CC_E_INVALID_ARG, "mesh listed twice in a batch");
+    if (!ms.empty() && ms[0]->D != M.D) return fail(ctx, CC_E_INVALID_ARG, "batch mixes dimensions");
+    if (M.ncol > cc::MAX_COLOURS) return fail(ctx, CC_E_INVALID_ARG, "too many colours for a batch");
+    cc_status st = check_params(ctx, params, M, dt);
+    if (st != CC_OK) return st;
+    ms.push_back(&M);
+  }
+  return CC_OK;
+}
+
+static bool use_dense_lds(const Mesh& M, int prec) {
+  const size_t lds = (size_t)(M.nf - 1) * M.D * M.D * (prec == 0 ? 8 : 4);
+  return M.dense && M.nf >= 2 && lds <= 64 * 1024;
+}
+
+static void ctx_batch_hook(void* user, int kid, int begin) {
+  cc_ctx* ctx = static_cast<cc_ctx*>(user);
+  if (!(ctx->prof_mask & (1 << kid))) return;
+  if (begin) {
+    ctx->hook_open[kid] = ctx->take_event();
+    if (ctx->hook_open[kid]) (void)hipEventRecord(ctx->hook_open[kid], ctx->stream);
+    return;
+  }
+  hipEvent_t a = ctx->hook_open[kid];
+  ctx->hook_open[kid] = nullptr;
+  if (!a) return;
+  hipEvent_t b = ctx->take_event();
+  if (!b) return;
+  (void)hipEventRecord(b, ctx->stream);
+  ctx->pending.push_back({kid, a, b});
+}
+
+static cc::BatchPlan* batch_plan_for(cc_ctx* ctx, const std::vector<Mesh*>& ms, const int32_t* ids,
+                                     const cc_params& p, double dt, double tol) {
+  const int n = (int)ms.size();
+  std::vector<double> key = {(double)p.method, (double)p.sweep, (double)p.hess_refresh,
+                             (double)p.precision, (double)p.line_search, (double)p.max_iters,
+                             (double)p.quasistatic, dt, tol, (double)ctx->batch_lanes,
+                             (double)ctx->batch_iters_per_graph};
+  for (int i = 0; i < n; ++i) key.push_back((double)(ms[i]->has_basis ? ms[i]->dense : -1));
+  std::vector<int> idv(ids, ids + n);
+  if (ctx->plan && ctx->plan_ids == idv && ctx->plan_key == key) return ctx->plan;
+  if (ctx->plan) { cc::batch_plan_destroy(ctx->plan); ctx->plan = nullptr; }
+  ctx->drop_graph_pairs();
+  ctx->hook_on = false;
+  std::vector<cc::BatchItem> items(n);
+  for (int i = 0; i < n; ++i) {
+    Material mat{};
+    items[i] = make_item(*ms[i], mat);
+    items[i].prep_dense = (p.method != CC_METHOD_CD && use_dense_lds(*ms[i], p.precision)) ? 1 : 0;
+  }
+  cc::BatchConfig cfg{};
+  cfg.D = ms[0]->D; cfg.prec = p.precision; cfg.method = p.method; cfg.sweep = p.sweep;
+  cfg.hess_refresh = p.hess_refresh; cfg.line_search = p.line_search; cfg.max_iters = p.max_iters;
+  cfg.quasistatic = p.quasistatic; cfg.tol = tol; cfg.h = p.quasistatic ? 1.0 : dt;
+  cfg.G = ctx->batch_lanes; cfg.iters_per_graph = ctx->batch_iters_per_graph;
+  ctx->plan = cc::batch_plan_create(items.data(), n, cfg, ctx->stream);
+  ctx->plan_ids = idv;
+  ctx->plan_key = key;
+  return ctx->plan;
+}
+
+// Host backtracking for mesh m of the plan after its energy rose at alpha = 1.
+static void batch_host_line_search(cc_ctx* ctx, Mesh& M, cc::BatchItem& it, cc::BatchCtl& c,
+                                   const cc_params& p, double tol) {
+  hipStream_t s = ctx->stream;
+  M.x = it.x;
+  M.xtrial = it.xtrial;
+  Stepper S{ctx, M, M.view(), it.mat, p, s};
+  const int nd = M.D * M.n;
+  const double tau = 1e-12 * std::max(std::fabs(c.E_cur), 1.0);
+  cc::launch_axpy(nd, M.xtrial, M.x, -1.0, M.dvec, s);
+  double alpha = 1.0, Et = c.E_trial;
+  int hv = 0;
+  while (!(Et <= c.E_cur + tau) && hv < p.max_halvings) {
+    alpha *= 0.5;
+    ++hv;
+    cc::launch_axpy(nd, M.x, M.dvec, alpha, M.xtrial, s);
+    Et = S.energy(M.xtrial);
+  }
+  if (!(Et <= c.E_cur + tau)) {
+    S.sweep(M.x, M.xtrial, CC_METHOD_CD);
+    cc::launch_axpy(nd, M.xtrial, M.x, -1.0, M.dvec, s);
+    alpha = 1.0;
+    Et = S.energy(M.xtrial);
+    hv = 0;
+    while (!(Et <= c.E_cur + tau) && hv < p.max_halvings) {
+      alpha *= 0.5;
+      ++hv;
+      cc::launch_axpy(nd, M.x, M.dvec, alpha, M.xtrial, s);
+      Et = S.energy(M.xtrial);
+    }
+    if (!(Et <= c.E_cur + tau)) {
+      c.status = CC_STALLED;
+      c.active = 0;
+      c.needs_host = 0;
+      // g at x must stay valid for a later Jacobi iteration of this mesh
+      (void)S.grad_norm2(M.x);
+      return;
+    }
+  }
+  M.last_halvings += hv;
+  std::swap(M.x, M.xtrial);
+  c.E_cur = Et;
+  c.iters += 1;
+  c.gn2 = S.grad_norm2(M.x);
+  c.r = std::sqrt(c.gn2) / c.g0;
+  c.needs_host = 0;
+  if (!std::isfinite(c.r)) { c.status = CC_STALLED; c.active = 0; }
+  else if (c.r <= tol) { c.status = CC_OK; c.active = 0; }
+  else if (c.iters >= p.max_iters) { c.status = CC_NOT_CONVERGED; c.active = 0; }
+  else c.active = 1;
+  it.x = M.x;
+  it.xtrial = M.xtrial;
+}
+
+cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double* const* x,
+                        double* const* v, const double* const* x_bc, const double* gravity, double dt,
+                        const cc_params* params, double tol, int32_t* iters, double* rel_grad,
+                        int32_t* status) {
+  return guarded(ctx, [&]() -> cc_status {
+    std::vector<Mesh*> ms;
+    cc_status st = batch_validate(ctx, n, mesh_ids, params, dt, ms);
+    if (st != CC_OK) return st;
+    if (!x || !v) return fail(ctx, CC_E_INVALID_ARG, "null state arrays");
+    for (int i = 0; i < n; ++i)
+      if (!x[i] || !v[i]) return fail(ctx, CC_E_INVALID_ARG, "null state buffer");
+    if (!(tol >= 0)) return fail(ctx, CC_E_INVALID_ARG, "tol must be >= 0");
+    if (gravity)
+      for (int k = 0; k < 3 * n; ++k)
+        if (!std::isfinite(gravity[k])) return fail(ctx, CC_E_NONFINITE, "non-finite gravity");
+    const cc_params& p = *params;
+    hipStream_t s = ctx->stream;
+    cc::BatchPlan* plan = batch_plan_for(ctx, ms, mesh_ids, p, dt, tol);
+    // refresh the per-call fields of every item (buffers, material, caller pointers)
+    std::vector<cc::BatchItem> items(n);
+    for (int i = 0; i < n; ++i) {
+      Mesh& M = *ms[i];
+      Material mat{};
+      mat.mu = M.mu; mat.lam = M.lam;
+      mat.w_in = p.quasistatic ? 0.0 : 1.0;
+      mat.s_el = p.quasistatic ? 1.0 : dt * dt;
+      for (int c = 0; c < 3; ++c) mat.grav[c] = gravity ? gravity[3 * i + c] : p.gravity[c];
+      items[i] = make_item(M, mat);
+      items[i].prep_dense = (p.method != CC_METHOD_CD && use_dense_lds(M, p.precision)) ? 1 : 0;
+      items[i].xu = x[i];
+      items[i].vu = v[i];
+      items[i].xbc = x_bc ? x_bc[i] : nullptr;
+      M.last_halvings = 0;
+      HIPC(hipMemsetAsync(M.fb, 0, 4 * sizeof(unsigned long long), s));
+    }
+    cc::BatchItem* items_d = cc::batch_items_dev(plan);
+    cc::BatchCtl* ctl_d = cc::batch_ctl_dev(plan);
+    HIPC(hipMemcpyAsync(items_d, items.data(), n * sizeof(cc::BatchItem), hipMemcpyHostToDevice, s));
+    const bool want_hook = ctx->prof_mask != 0;
+    if (want_hook != ctx->hook_on) {
+      cc::batch_set_hook(plan, want_hook ? ctx_batch_hook : nullptr, ctx);  // drops the graph
+      ctx->drop_graph_pairs();
+      ctx->hook_on = want_hook;
+    }
+    cc::batch_begin(plan, s);
+    std::vector<cc::BatchCtl> ctl(n);
+    const int k = std::max(1, ctx->batch_iters_per_graph);
+    auto pull_ctl = [&]() {
+      HIPC(hipMemcpyAsync(ctx->pinned, ctl_d, n * sizeof(cc::BatchCtl), hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+      std::memcpy(ctl.data(), ctx->pinned, n * sizeof(cc::BatchCtl));
+    };
+    if ((size_t)n * sizeof(cc::BatchCtl) > 64 * 1024)
+      return fail(ctx, CC_E_INVALID_ARG, "batch too large");
+    pull_ctl();
+    for (int i = 0; i < n; ++i)
+      if (ctl[i].bad) return fail(ctx, CC_E_NONFINITE, "non-finite x, v or x_bc in batch");
+    long long guard = 0;
+    while (true) {
+      bool any = false;
+      for (auto& c : ctl) any = any || c.active;
+      if (!any) break;
+      cc::batch_iterate(plan, k, s);
+      if (!cc::batch_has_graph(plan) && !ctx->graph_pairs.empty()) ctx->drop_graph_pairs();
+      pull_ctl();
+      ctx->harvest();
+      if (cc::batch_has_graph(plan)) ctx->harvest_graph();
+      bool host = false;
+      for (auto& c : ctl) host = host || c.needs_host;
+      if (host) {
+        HIPC(hipMemcpyAsync(items.data(), items_d, n * sizeof(cc::BatchItem), hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        for (int i = 0; i < n; ++i) {
+          if (!ctl[i].needs_host) continue;
+          batch_host_line_search(ctx, *ms[i], items[i], ctl[i], p, tol);
+          HIPC(hipMemcpyAsync(items_d + i, &items[i], sizeof(cc::BatchItem), hipMemcpyHostToDevice, s));
+          HIPC(hipMemcpyAsync(ctl_d + i, &ctl[i], sizeof(cc::BatchCtl), hipMemcpyHostToDevice, s));
+        }
+        HIPC(hipStreamSynchronize(s));
+      }
+      if (++guard > (long long)p.max_iters + 16) break;  // every replay advances every active mesh
+    }
+    cc::batch_finish(plan, s);
+    HIPC(hipMemcpyAsync(items.data(), items_d, n * sizeof(cc::BatchItem), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    ctx->harvest();
+    cc_status worst = CC_OK;
+    for (int i = 0; i < n; ++i) {
+      Mesh& M = *ms[i];
+      M.x = items[i].x;          // keep the mesh's own buffer roles in step with the device
+      M.xtrial = items[i].xtrial;
+      int stt = ctl[i].status == -100 ? CC_NOT_CONVERGED : ctl[i].status;
+      if (iters) iters[i] = ctl[i].iters;
+      if (rel_grad) rel_grad[i] = ctl[i].r;
+      if (status) status[i] = stt;
+      M.last_E = ctl[i].E_cur;
+      M.last_paper = 0;
+      M.last_warm = 0;
+      if (stt < 0 ? (worst >= 0 || stt < worst) : (worst >= 0 && stt > worst)) worst = stt;
+    }
+    return worst;
+  });
+}
+
+cc_status cc_batch_tuning(cc_ctx* ctx, int32_t lanes, int32_t iters_per_graph) {
+  return guarded(ctx, [&]() -> cc_status {
+    if ((lanes != 16 && lanes != 32 && lanes != 64) || iters_per_graph < 0 || iters_per_graph > 64)
+      return fail(ctx, CC_E_INVALID_ARG, "lanes must be 16, 32 or 64; iters_per_graph 0..64");
+    ctx->batch_lanes = lanes;
+    ctx->batch_iters_per_graph = iters_per_graph;
+    return CC_OK;
+  });
+}
+
+cc_status cc_autotune_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, const cc_params* params,
+                            int32_t* lanes_out, double* ms_out) {
+  return guarded(ctx, [&]() -> cc_status {
+    std::vector<Mesh*> ms;
+    const double dt = 1.0 / 60.0;
+    cc_status st = batch_validate(ctx, n, mesh_ids, params, dt, ms);
+    if (st != CC_OK) return st;
+    cc::BatchPlan* plan = batch_plan_for(ctx, ms, mesh_ids, *params, dt, 0.0);
+    std::vector<cc::BatchItem> items(n);
+    for (int i = 0; i < n; ++i) {
+      Material mat{};
+      mat.mu = ms[i]->mu; mat.lam = ms[i]->lam;
+      items[i] = make_item(*ms[i], mat);
+      items[i].prep_dense = (params->method != CC_METHOD_CD && use_dense_lds(*ms[i], params->precision)) ? 1 : 0;
+    }
+    HIPC(hipMemcpyAsync(cc::batch_items_dev(plan), items.data(), n * sizeof(cc::BatchItem),
+                        hipMemcpyHostToDevice, ctx->stream));
+    // every mesh active, timing only (K, L and d are scratch)
+    std::vector<cc::BatchCtl> ctl(n);
+    for (auto& c : ctl) { c = cc::BatchCtl{}; c.active = 1; }
+    HIPC(hipMemcpyAsync(cc::batch_ctl_dev(plan), ctl.data(), n * sizeof(cc::BatchCtl),
+                        hipMemcpyHostToDevice, ctx->stream));
+    const int choices[3] = {16, 32, 64};
+    double best = 1e300;
+    int bestG = 16;
+    for (int c = 0; c < 3; ++c) {
+      const float t = cc::batch_time_prep_update(plan, choices[c], 5, ctx->stream);
+      if (ms_out) ms_out[c] = t;
+      if (t < best) { best = t; bestG = choices[c]; }
+    }
+    HIPC(hipStreamSynchronize(ctx->stream));
+    ctx->batch_lanes = bestG;
+    cc::batch_plan_destroy(ctx->plan);
+    ctx->plan = nullptr;
+    ctx->plan_ids.clear();
+    if (lanes_out) *lanes_out = bestG;
     return CC_OK;
   });
 }

@@ -1,0 +1,534 @@
+// Device helpers shared by the single-mesh and batched kernels (gfx950).
+#pragma once
+#include <math.h>
+
+#include "cc_kernels.h"
+
+namespace cc {
+
+constexpr int WG = 256;
+
+template <typename T>
+__device__ __forceinline__ T csqrt(T v);
+template <>
+__device__ __forceinline__ float csqrt<float>(float v) { return sqrtf(v); }
+template <>
+__device__ __forceinline__ double csqrt<double>(double v) { return sqrt(v); }
+
+template <typename T>
+__device__ __forceinline__ T cabs(T v) { return v < T(0) ? -v : v; }
+
+// packed index of local block (a, b), a <= b, among K local vertices
+template <int K>
+__host__ __device__ __forceinline__ int pidx(int a, int b) {
+  return a * K - (a * (a - 1)) / 2 + (b - a);
+}
+
+template <typename T> __device__ __forceinline__ const T* dinv_of(const MeshView& mv);
+template <> __device__ __forceinline__ const float* dinv_of<float>(const MeshView& mv) { return mv.dinv_f; }
+template <> __device__ __forceinline__ const double* dinv_of<double>(const MeshView& mv) { return mv.dinv_d; }
+template <typename T> __device__ __forceinline__ const T* vol_of(const MeshView& mv);
+template <> __device__ __forceinline__ const float* vol_of<float>(const MeshView& mv) { return mv.vol_f; }
+template <> __device__ __forceinline__ const double* vol_of<double>(const MeshView& mv) { return mv.vol_d; }
+template <typename T> __device__ __forceinline__ const T* basis_of(const MeshView& mv);
+template <> __device__ __forceinline__ const float* basis_of<float>(const MeshView& mv) { return mv.U_f; }
+template <> __device__ __forceinline__ const double* basis_of<double>(const MeshView& mv) { return mv.U_d; }
+
+// F = sum_{a>=1} (x_a - x_0) beta_a^T, differences formed in float64 then cast.
+template <typename T, int D>
+__device__ __forceinline__ void load_element(const MeshView& mv, int e, const double* __restrict__ x,
+                                             T F[D][D], T beta[D + 1][D], T& vol) {
+  const int m = mv.m, n = mv.n;
+  const T* dinv = dinv_of<T>(mv);
+  const int v0 = mv.ev[e];
+  T Ds[D][D];
+#pragma unroll
+  for (int a = 1; a <= D; ++a) {
+    const int va = mv.ev[a * m + e];
+#pragma unroll
+    for (int c = 0; c < D; ++c) Ds[c][a - 1] = T(x[c * n + va] - x[c * n + v0]);
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int q = 0; q < D; ++q) beta[a + 1][q] = dinv[(a * D + q) * m + e];
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    T s = T(0);
+#pragma unroll
+    for (int a = 1; a <= D; ++a) s += beta[a][q];
+    beta[0][q] = -s;
+  }
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      T s = T(0);
+#pragma unroll
+      for (int a = 1; a <= D; ++a) s += Ds[r][a - 1] * beta[a][q];
+      F[r][q] = s;
+    }
+  vol = vol_of<T>(mv)[e];
+}
+
+template <typename T, int D>
+__device__ __forceinline__ T det(const T F[D][D]) {
+  if constexpr (D == 2) {
+    return F[0][0] * F[1][1] - F[0][1] * F[1][0];
+  } else {
+    return F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) -
+           F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
+           F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
+  }
+}
+
+// dJ/dF: 2D [[F11,-F10],[-F01,F00]]; 3D columns f1 x f2, f2 x f0, f0 x f1.
+template <typename T, int D>
+__device__ __forceinline__ void cofactor(const T F[D][D], T C[D][D]) {
+  if constexpr (D == 2) {
+    C[0][0] = F[1][1];
+    C[0][1] = -F[1][0];
+    C[1][0] = -F[0][1];
+    C[1][1] = F[0][0];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int a = (q + 1) % 3, b = (q + 2) % 3;
+      C[0][q] = F[1][a] * F[2][b] - F[2][a] * F[1][b];
+      C[1][q] = F[2][a] * F[0][b] - F[0][a] * F[2][b];
+      C[2][q] = F[0][a] * F[1][b] - F[1][a] * F[0][b];
+    }
+  }
+}
+
+// First Piola-Kirchhoff stress of the stable neo-Hookean energy.
+template <typename T, int D>
+__device__ __forceinline__ void snh_pk1(const T F[D][D], T mu, T lam, T P[D][D]) {
+  T C[D][D];
+  cofactor<T, D>(F, C);
+  const T J = det<T, D>(F);
+  const T k = lam * (J - T(1)) - mu;
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int q = 0; q < D; ++q) P[r][q] = mu * F[r][q] + k * C[r][q];
+}
+
+template <typename T, int D>
+__device__ __forceinline__ T snh_psi(const T F[D][D], T mu, T lam) {
+  T f2 = T(0);
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int q = 0; q < D; ++q) f2 += F[r][q] * F[r][q];
+  const T J = det<T, D>(F);
+  return T(0.5) * mu * (f2 - T(D)) - mu * (J - T(1)) + T(0.5) * lam * (J - T(1)) * (J - T(1));
+}
+
+// Cyclic Jacobi eigen-decomposition of a symmetric matrix S (overwritten by
+// its rotated form, eigenvalues on the diagonal); V accumulates the rotations
+// (columns are eigenvectors).  Each rotation zeroes S[p][q] exactly.
+template <typename T, int D>
+__device__ __forceinline__ void jacobi_eig(T S[D][D], T V[D][D]) {
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) V[i][j] = (i == j) ? T(1) : T(0);
+  const T eps = sizeof(T) == 4 ? T(1e-7) : T(1e-16);
+  const int sweeps = (D == 2) ? 1 : (sizeof(T) == 4 ? 5 : 8);
+  for (int sw = 0; sw < sweeps; ++sw) {
+    bool any = false;
+#pragma unroll
+    for (int p = 0; p < D - 1; ++p)
+#pragma unroll
+      for (int q = p + 1; q < D; ++q) {
+        const T apq = S[p][q];
+        const T app = S[p][p], aqq = S[q][q];
+        if (cabs(apq) <= eps * eps * (cabs(app) + cabs(aqq)) || apq == T(0)) {
+          S[p][q] = S[q][p] = T(0);
+          continue;
+        }
+        any = true;
+        const T theta = (aqq - app) / (T(2) * apq);
+        const T t = (theta >= T(0) ? T(1) : T(-1)) / (cabs(theta) + csqrt(theta * theta + T(1)));
+        const T c = T(1) / csqrt(t * t + T(1));
+        const T s = t * c;
+        S[p][p] = app - t * apq;
+        S[q][q] = aqq + t * apq;
+        S[p][q] = S[q][p] = T(0);
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+          if (r == p || r == q) continue;
+          const T arp = S[r][p], arq = S[r][q];
+          S[r][p] = S[p][r] = c * arp - s * arq;
+          S[r][q] = S[q][r] = s * arp + c * arq;
+        }
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+          const T vrp = V[r][p], vrq = V[r][q];
+          V[r][p] = c * vrp - s * vrq;
+          V[r][q] = s * vrp + c * vrq;
+        }
+      }
+    if (!any) break;
+  }
+}
+
+// Rotation-variant SVD F = U diag(sig) V^T with det U = det V = +1: V from the
+// eigenvectors of F^T F (a product of rotations), then a Givens QR of F V.
+// The last singular value carries the sign of det F.
+template <typename T, int D>
+__device__ __forceinline__ void svd_rv(const T F[D][D], T U[D][D], T V[D][D], T sig[D]) {
+  T S[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T s = T(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) s += F[k][i] * F[k][j];
+      S[i][j] = s;
+    }
+  jacobi_eig<T, D>(S, V);
+  T B[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T s = T(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) s += F[i][k] * V[k][j];
+      B[i][j] = s;
+    }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) U[i][j] = (i == j) ? T(1) : T(0);
+#pragma unroll
+  for (int k = 0; k < D - 1; ++k)
+#pragma unroll
+    for (int q = k + 1; q < D; ++q) {
+      const T a = B[k][k], b = B[q][k];
+      const T r = csqrt(a * a + b * b);
+      T c = T(1), s = T(0);
+      if (r > T(0)) {
+        c = a / r;
+        s = b / r;
+      }
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const T bp = B[k][j], bq = B[q][j];
+        B[k][j] = c * bp + s * bq;
+        B[q][j] = -s * bp + c * bq;
+      }
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        const T up = U[i][k], uq = U[i][q];
+        U[i][k] = c * up + s * uq;
+        U[i][q] = -s * up + c * uq;
+      }
+    }
+#pragma unroll
+  for (int k = 0; k < D; ++k) sig[k] = B[k][k];
+}
+
+// Projected stable neo-Hookean Hessian as its positive eigenpairs.  In the
+// frame of F = U diag(sig) V^T the Hessian splits into the block coupling the
+// diagonal entries (A_kk = mu + lam c_k^2, A_kl = lam c_k c_l + s sig_m with
+// c the diagonal cofactors and s = lam (J-1) - mu) and, for every pair k < l,
+// a 2x2 block on (F_kl, F_lk) with eigenvalues mu -+ s sig_m (2D: sig_m = 1)
+// and eigenvectors (1, +-1)/sqrt(2).  Eigen-matrices map back as
+// U E V^T.  callback(weight, Q) is invoked for each eigenpair with weight > 0.
+template <typename T, int D, typename CB>
+__device__ __forceinline__ void snh_projected_eigs(const T F[D][D], T mu, T lam, CB&& callback) {
+  T U[D][D], V[D][D], sig[D];
+  svd_rv<T, D>(F, U, V, sig);
+  T J = T(1);
+#pragma unroll
+  for (int k = 0; k < D; ++k) J *= sig[k];
+  const T s = lam * (J - T(1)) - mu;
+  T A[D][D], c[D], third[D][D];
+  if constexpr (D == 2) {
+    c[0] = sig[1];
+    c[1] = sig[0];
+    third[0][1] = third[1][0] = T(1);
+  } else {
+    c[0] = sig[1] * sig[2];
+    c[1] = sig[0] * sig[2];
+    c[2] = sig[0] * sig[1];
+    third[0][1] = third[1][0] = sig[2];
+    third[0][2] = third[2][0] = sig[1];
+    third[1][2] = third[2][1] = sig[0];
+  }
+#pragma unroll
+  for (int k = 0; k < D; ++k)
+#pragma unroll
+    for (int l = 0; l < D; ++l)
+      A[k][l] = (k == l) ? mu + lam * c[k] * c[k] : lam * c[k] * c[l] + s * third[k][l];
+  T W[D][D];
+  jacobi_eig<T, D>(A, W);
+  T Q[D][D];
+#pragma unroll
+  for (int r = 0; r < D; ++r) {
+    const T w = A[r][r];
+    if (w > T(0)) {
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          T acc = T(0);
+#pragma unroll
+          for (int k = 0; k < D; ++k) acc += W[k][r] * U[i][k] * V[j][k];
+          Q[i][j] = acc;
+        }
+      callback(w, Q);
+    }
+  }
+  const T h = T(0.70710678118654752440);
+#pragma unroll
+  for (int k = 0; k < D - 1; ++k)
+#pragma unroll
+    for (int l = k + 1; l < D; ++l) {
+      const T sm = third[k][l];
+#pragma unroll
+      for (int sgn = 0; sgn < 2; ++sgn) {
+        // sgn 0: vector (1, 1), eigenvalue mu - s sig_m; sgn 1: (1, -1), mu + s sig_m
+        const T w = sgn == 0 ? mu - s * sm : mu + s * sm;
+        if (!(w > T(0))) continue;
+        const T b = sgn == 0 ? h : -h;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int j = 0; j < D; ++j) Q[i][j] = h * U[i][k] * V[j][l] + b * U[i][l] * V[j][k];
+        callback(w, Q);
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+template <int WGS>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = WGS / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+template <typename T, int D>
+__device__ __forceinline__ bool chol(const T M[D][D], T L[D][D]) {
+  T tr = T(0);
+#pragma unroll
+  for (int i = 0; i < D; ++i) tr += M[i][i];
+  const T tol = T(1e-12) * tr;
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    T s = M[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
+    ok = ok && (s > tol);
+    const T ljj = csqrt(s > T(0) ? s : T(1));
+    L[j][j] = ljj;
+#pragma unroll
+    for (int i = j + 1; i < D; ++i) {
+      T t = M[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+      L[i][j] = t / ljj;
+    }
+#pragma unroll
+    for (int i = 0; i < j; ++i) L[i][j] = T(0);
+  }
+  return ok;
+}
+
+// X = M^{-1} B for the Cholesky factor L of M (B, X: D x D, column-wise).
+template <typename T, int D>
+__device__ __forceinline__ void chol_solve(const T L[D][D], const T B[D][D], T X[D][D]) {
+#pragma unroll
+  for (int col = 0; col < D; ++col) {
+    T y[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      T s = B[i][col];
+#pragma unroll
+      for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
+      y[i] = s / L[i][i];
+    }
+#pragma unroll
+    for (int i = D - 1; i >= 0; --i) {
+      T s = y[i];
+#pragma unroll
+      for (int k = i + 1; k < D; ++k) s -= L[k][i] * X[k][col];
+      X[i][col] = s / L[i][i];
+    }
+  }
+}
+
+__device__ __forceinline__ int find_slot(const MeshView& mv, int64_t sp0, int64_t sp1, int i, int k) {
+  if (mv.dense_supp) {
+    if (k == i || k >= mv.nf) return -1;
+    return (int)(sp0 + (k < i ? k : k - 1));
+  }
+  int64_t lo = sp0, hi = sp1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (mv.sidx[mid] < k) lo = mid + 1; else hi = mid;
+  }
+  return (lo < sp1 && mv.sidx[lo] == k) ? (int)lo : -1;
+}
+
+// Per-vertex condensation: A_i = H_iC U_i, Ht_i = U_i^T H_CC U_i, then
+// K_i = (H_ii - A Ht^{-1} A^T)^{-1} and L_i = A Ht^{-1} (CC), with the
+// coordinate-descent and JGS2 forms as special cases.  G lanes per vertex.
+// Contribution of support row j to A_i (when row j holds block (j, i)) and to
+// Ht_i (blocks (j, k) with k in the support); Uk(k) returns U_i[k] or null.
+template <typename T, int D, typename LookupU>
+__device__ __forceinline__ void accum_row(const MeshView& mv, int i, int j, const T* Uj,
+                                          const T* __restrict__ hb, LookupU&& Uk_of, T* A, T* Ht) {
+  constexpr int DD = D * D;
+  for (int t = mv.rowptr[j]; t < mv.rowptr[j + 1]; ++t) {
+    const int k = mv.colidx[t];
+    const T* H = hb + (size_t)t * DD;
+    if (k == i) {
+      // A += H_ji^T U_j
+#pragma unroll
+      for (int r = 0; r < D; ++r)
+#pragma unroll
+        for (int s = 0; s < D; ++s) {
+          T acc = T(0);
+#pragma unroll
+          for (int l = 0; l < D; ++l) acc += H[l * D + r] * Uj[l * D + s];
+          A[r * D + s] += acc;
+        }
+      continue;
+    }
+    const T* Uk = Uk_of(k);
+    if (!Uk) continue;
+    T Hl[DD], M[DD];
+#pragma unroll
+    for (int r = 0; r < DD; ++r) Hl[r] = H[r];
+#pragma unroll
+    for (int r = 0; r < D; ++r)   // M = H_jk U_k
+#pragma unroll
+      for (int s = 0; s < D; ++s) {
+        T acc = T(0);
+#pragma unroll
+        for (int l = 0; l < D; ++l) acc += Hl[r * D + l] * Uk[l * D + s];
+        M[r * D + s] = acc;
+      }
+#pragma unroll
+    for (int r = 0; r < D; ++r)   // Ht += U_j^T M
+#pragma unroll
+      for (int s = 0; s < D; ++s) {
+        T acc = T(0);
+#pragma unroll
+        for (int l = 0; l < D; ++l) acc += Uj[l * D + r] * M[l * D + s];
+        Ht[r * D + s] += acc;
+      }
+  }
+}
+
+// Small solves of one vertex from the reduced A_i and Ht_i; writes K_i, L_i.
+template <typename T, int D>
+__device__ void cc_finish(const MeshView& mv, int method, int i, bool empty, const T* A,
+                          const T* Ht, const T* __restrict__ hb, T* __restrict__ KL,
+                          unsigned long long* __restrict__ fb) {
+  constexpr int DD = D * D;
+  T Hii[D][D], Kout[D][D], Lout[D][D], Lc[D][D], I[D][D];
+  const T* hd = hb + (size_t)mv.rowptr[i] * DD;
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+      Hii[r][s] = hd[r * D + s];
+      I[r][s] = (r == s) ? T(1) : T(0);
+      Lout[r][s] = T(0);
+      Kout[r][s] = T(0);
+    }
+  const bool ok_ii = chol<T, D>(Hii, Lc);
+  if (!ok_ii) atomicAdd(&fb[2], 1ull);
+  T Kcd[D][D];
+  if (ok_ii) chol_solve<T, D>(Lc, I, Kcd);
+  else
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int s = 0; s < D; ++s) Kcd[r][s] = T(0);
+  bool use_cd = true;
+  if (method == 1) {  // Coordinate Condensation
+    T Htm[D][D], Lt[D][D];
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int s = 0; s < D; ++s) Htm[r][s] = Ht[r * D + s];
+    const bool ok_t = !empty && chol<T, D>(Htm, Lt);
+    if (!ok_t) {
+      atomicAdd(&fb[0], 1ull);
+    } else {
+      T At[D][D], Z[D][D], M[D][D], Lm[D][D];
+#pragma unroll
+      for (int r = 0; r < D; ++r)
+#pragma unroll
+        for (int s = 0; s < D; ++s) At[r][s] = A[s * D + r];
+      chol_solve<T, D>(Lt, At, Z);  // Z = Ht^{-1} A^T
+#pragma unroll
+      for (int r = 0; r < D; ++r)
+#pragma unroll
+        for (int s = 0; s < D; ++s) {
+          T acc = T(0);
+#pragma unroll
+          for (int l = 0; l < D; ++l) acc += A[r * D + l] * Z[l][s];
+          M[r][s] = Hii[r][s] - acc;  // H_ii - S
+        }
+      if (chol<T, D>(M, Lm)) {
+        chol_solve<T, D>(Lm, I, Kout);
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+          for (int s = 0; s < D; ++s) Lout[r][s] = Z[s][r];  // L = A Ht^{-1} = Z^T
+        use_cd = false;
+      } else {
+        atomicAdd(&fb[1], 1ull);
+      }
+    }
+  } else if (method == 2) {  // JGS2 as printed: (H_ii + Ht)^{-1} (g_i + U^T g_C)
+    T M[D][D], Lm[D][D];
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int s = 0; s < D; ++s) M[r][s] = Hii[r][s] + Ht[r * D + s];
+    if (!empty && chol<T, D>(M, Lm)) {
+      chol_solve<T, D>(Lm, I, Kout);
+#pragma unroll
+      for (int r = 0; r < D; ++r) Lout[r][r] = T(-1);
+      use_cd = false;
+    } else {
+      atomicAdd(&fb[0], 1ull);
+    }
+  }
+  if (use_cd) {
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int s = 0; s < D; ++s) {
+        Kout[r][s] = Kcd[r][s];
+        Lout[r][s] = T(0);
+      }
+  }
+  T* o = KL + (size_t)i * 2 * DD;
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+      o[r * D + s] = Kout[r][s];
+      o[DD + r * D + s] = Lout[r][s];
+    }
+}
+
+
+}  // namespace cc

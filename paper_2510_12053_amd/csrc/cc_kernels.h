@@ -16,6 +16,7 @@ struct MeshView {
   const double* vol_d;   // [m] rest volumes
   const float* vol_f;
   const double* mass;    // [n] lumped masses
+  const int* vperm;      // [n] caller id of internal vertex
   const int* star_ptr;   // [nf+1]  incidence of free vertices
   const int* star;       // packed e*4 + local index
   const int* rowptr;     // [nf+1]  block rows over free vertices, diagonal first
@@ -69,5 +70,71 @@ void launch_scatter_user(const MeshView& mv, const int* vperm, const double* src
                          double* dst_user, int free_only, hipStream_t s);
 
 int reduce_partials_capacity(const MeshView& mv);
+
+// ---- batched stepping (many meshes per launch) -----------------------------
+constexpr int MAX_COLOURS = 32;
+
+// One mesh of a batch, resident in device memory.  The x / xtrial pointers
+// are swapped in place by the control kernel when an iteration is accepted,
+// so every launch reads them from here.
+struct BatchItem {
+  MeshView mv;
+  Material mat;
+  double *x, *xtrial, *xt, *x0, *d, *g;
+  void *estore, *hb, *KL;
+  double* partials;
+  unsigned long long* fb;
+  double* xu;          // caller positions (n x D), this call
+  double* vu;          // caller velocities
+  const double* xbc;   // caller Dirichlet targets or null
+  int prep_dense;      // 1: exact-basis condensation with the basis row in LDS
+  int ncol;
+  int coff[MAX_COLOURS + 1];
+};
+
+// Per-mesh iteration state, device-resident.
+struct BatchCtl {
+  int active;          // 1 while the mesh iterates
+  int iters;
+  int status;          // CC_OK / CC_NOT_CONVERGED / CC_STALLED, -100 while running
+  int needs_host;      // 1: energy rose at alpha = 1, backtracking left to the host
+  int bad;             // non-finite input seen by the predictor
+  int pad;
+  double E_cur, E_trial, g0, gn2, r;
+};
+
+struct BatchPlan;  // host-side, defined in cc_kernels.hip
+
+struct BatchConfig {
+  int D, prec, method, sweep, hess_refresh, line_search, max_iters, quasistatic;
+  double tol, h;
+  int G;               // lanes per vertex of the generic condensation/update kernels
+  int iters_per_graph; // iterations captured per graph replay (0: no graph)
+  int dense_lds;       // max dynamic LDS of the dense condensation path (bytes)
+};
+
+BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const BatchConfig& cfg,
+                             hipStream_t s);
+void batch_plan_destroy(BatchPlan* p);
+BatchItem* batch_items_dev(BatchPlan* p);
+BatchCtl* batch_ctl_dev(BatchPlan* p);
+// Start of a step: predictor, initial gradient norm and energy, control reset.
+void batch_begin(BatchPlan* p, hipStream_t s);
+// Run `iters` iterations (graph replay when captured).
+void batch_iterate(BatchPlan* p, int iters, hipStream_t s);
+// Velocities and caller positions.
+void batch_finish(BatchPlan* p, hipStream_t s);
+// Time one condensation + update pass of every mesh with the given lane count.
+float batch_time_prep_update(BatchPlan* p, int G, int reps, hipStream_t s);
+void batch_set_lanes(BatchPlan* p, int G);
+// Kernel timing: hook(user, kid, begin) is called around the launches of the
+// element, assembly, gradient, condensation, update and energy kernels (ids as
+// CC_K_* in ccgpu.h) while they are enqueued or captured.  Changing the hook
+// drops a captured graph.
+typedef void (*BatchHook)(void* user, int kid, int begin);
+void batch_set_hook(BatchPlan* p, BatchHook hook, void* user);
+// 1 while a graph is being captured (hooks may record events into it).
+int batch_capturing(BatchPlan* p);
+int batch_has_graph(BatchPlan* p);
 
 }  // namespace cc

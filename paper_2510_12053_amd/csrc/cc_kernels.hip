@@ -14,316 +14,18 @@
 
 #include <math.h>
 
-#include "cc_kernels.h"
+#include <algorithm>
+#include <vector>
+
+#include "cc_device.h"
 
 namespace cc {
 
-constexpr int WG = 256;
-
-template <typename T>
-__device__ __forceinline__ T csqrt(T v);
-template <>
-__device__ __forceinline__ float csqrt<float>(float v) { return sqrtf(v); }
-template <>
-__device__ __forceinline__ double csqrt<double>(double v) { return sqrt(v); }
-
-template <typename T>
-__device__ __forceinline__ T cabs(T v) { return v < T(0) ? -v : v; }
-
-// packed index of local block (a, b), a <= b, among K local vertices
-template <int K>
-__host__ __device__ __forceinline__ int pidx(int a, int b) {
-  return a * K - (a * (a - 1)) / 2 + (b - a);
-}
-
-template <typename T> __device__ __forceinline__ const T* dinv_of(const MeshView& mv);
-template <> __device__ __forceinline__ const float* dinv_of<float>(const MeshView& mv) { return mv.dinv_f; }
-template <> __device__ __forceinline__ const double* dinv_of<double>(const MeshView& mv) { return mv.dinv_d; }
-template <typename T> __device__ __forceinline__ const T* vol_of(const MeshView& mv);
-template <> __device__ __forceinline__ const float* vol_of<float>(const MeshView& mv) { return mv.vol_f; }
-template <> __device__ __forceinline__ const double* vol_of<double>(const MeshView& mv) { return mv.vol_d; }
-template <typename T> __device__ __forceinline__ const T* basis_of(const MeshView& mv);
-template <> __device__ __forceinline__ const float* basis_of<float>(const MeshView& mv) { return mv.U_f; }
-template <> __device__ __forceinline__ const double* basis_of<double>(const MeshView& mv) { return mv.U_d; }
-
-// F = sum_{a>=1} (x_a - x_0) beta_a^T, differences formed in float64 then cast.
-template <typename T, int D>
-__device__ __forceinline__ void load_element(const MeshView& mv, int e, const double* __restrict__ x,
-                                             T F[D][D], T beta[D + 1][D], T& vol) {
-  const int m = mv.m, n = mv.n;
-  const T* dinv = dinv_of<T>(mv);
-  const int v0 = mv.ev[e];
-  T Ds[D][D];
-#pragma unroll
-  for (int a = 1; a <= D; ++a) {
-    const int va = mv.ev[a * m + e];
-#pragma unroll
-    for (int c = 0; c < D; ++c) Ds[c][a - 1] = T(x[c * n + va] - x[c * n + v0]);
-  }
-#pragma unroll
-  for (int a = 0; a < D; ++a)
-#pragma unroll
-    for (int q = 0; q < D; ++q) beta[a + 1][q] = dinv[(a * D + q) * m + e];
-#pragma unroll
-  for (int q = 0; q < D; ++q) {
-    T s = T(0);
-#pragma unroll
-    for (int a = 1; a <= D; ++a) s += beta[a][q];
-    beta[0][q] = -s;
-  }
-#pragma unroll
-  for (int r = 0; r < D; ++r)
-#pragma unroll
-    for (int q = 0; q < D; ++q) {
-      T s = T(0);
-#pragma unroll
-      for (int a = 1; a <= D; ++a) s += Ds[r][a - 1] * beta[a][q];
-      F[r][q] = s;
-    }
-  vol = vol_of<T>(mv)[e];
-}
-
-template <typename T, int D>
-__device__ __forceinline__ T det(const T F[D][D]) {
-  if constexpr (D == 2) {
-    return F[0][0] * F[1][1] - F[0][1] * F[1][0];
-  } else {
-    return F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) -
-           F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
-           F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
-  }
-}
-
-// dJ/dF: 2D [[F11,-F10],[-F01,F00]]; 3D columns f1 x f2, f2 x f0, f0 x f1.
-template <typename T, int D>
-__device__ __forceinline__ void cofactor(const T F[D][D], T C[D][D]) {
-  if constexpr (D == 2) {
-    C[0][0] = F[1][1];
-    C[0][1] = -F[1][0];
-    C[1][0] = -F[0][1];
-    C[1][1] = F[0][0];
-  } else {
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int a = (q + 1) % 3, b = (q + 2) % 3;
-      C[0][q] = F[1][a] * F[2][b] - F[2][a] * F[1][b];
-      C[1][q] = F[2][a] * F[0][b] - F[0][a] * F[2][b];
-      C[2][q] = F[0][a] * F[1][b] - F[1][a] * F[0][b];
-    }
-  }
-}
-
-// First Piola-Kirchhoff stress of the stable neo-Hookean energy.
-template <typename T, int D>
-__device__ __forceinline__ void snh_pk1(const T F[D][D], T mu, T lam, T P[D][D]) {
-  T C[D][D];
-  cofactor<T, D>(F, C);
-  const T J = det<T, D>(F);
-  const T k = lam * (J - T(1)) - mu;
-#pragma unroll
-  for (int r = 0; r < D; ++r)
-#pragma unroll
-    for (int q = 0; q < D; ++q) P[r][q] = mu * F[r][q] + k * C[r][q];
-}
-
-template <typename T, int D>
-__device__ __forceinline__ T snh_psi(const T F[D][D], T mu, T lam) {
-  T f2 = T(0);
-#pragma unroll
-  for (int r = 0; r < D; ++r)
-#pragma unroll
-    for (int q = 0; q < D; ++q) f2 += F[r][q] * F[r][q];
-  const T J = det<T, D>(F);
-  return T(0.5) * mu * (f2 - T(D)) - mu * (J - T(1)) + T(0.5) * lam * (J - T(1)) * (J - T(1));
-}
-
-// Cyclic Jacobi eigen-decomposition of a symmetric matrix S (overwritten by
-// its rotated form, eigenvalues on the diagonal); V accumulates the rotations
-// (columns are eigenvectors).  Each rotation zeroes S[p][q] exactly.
-template <typename T, int D>
-__device__ __forceinline__ void jacobi_eig(T S[D][D], T V[D][D]) {
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int j = 0; j < D; ++j) V[i][j] = (i == j) ? T(1) : T(0);
-  const T eps = sizeof(T) == 4 ? T(1e-7) : T(1e-16);
-  const int sweeps = (D == 2) ? 1 : (sizeof(T) == 4 ? 5 : 8);
-  for (int sw = 0; sw < sweeps; ++sw) {
-    bool any = false;
-#pragma unroll
-    for (int p = 0; p < D - 1; ++p)
-#pragma unroll
-      for (int q = p + 1; q < D; ++q) {
-        const T apq = S[p][q];
-        const T app = S[p][p], aqq = S[q][q];
-        if (cabs(apq) <= eps * eps * (cabs(app) + cabs(aqq)) || apq == T(0)) {
-          S[p][q] = S[q][p] = T(0);
-          continue;
-        }
-        any = true;
-        const T theta = (aqq - app) / (T(2) * apq);
-        const T t = (theta >= T(0) ? T(1) : T(-1)) / (cabs(theta) + csqrt(theta * theta + T(1)));
-        const T c = T(1) / csqrt(t * t + T(1));
-        const T s = t * c;
-        S[p][p] = app - t * apq;
-        S[q][q] = aqq + t * apq;
-        S[p][q] = S[q][p] = T(0);
-#pragma unroll
-        for (int r = 0; r < D; ++r) {
-          if (r == p || r == q) continue;
-          const T arp = S[r][p], arq = S[r][q];
-          S[r][p] = S[p][r] = c * arp - s * arq;
-          S[r][q] = S[q][r] = s * arp + c * arq;
-        }
-#pragma unroll
-        for (int r = 0; r < D; ++r) {
-          const T vrp = V[r][p], vrq = V[r][q];
-          V[r][p] = c * vrp - s * vrq;
-          V[r][q] = s * vrp + c * vrq;
-        }
-      }
-    if (!any) break;
-  }
-}
-
-// Rotation-variant SVD F = U diag(sig) V^T with det U = det V = +1: V from the
-// eigenvectors of F^T F (a product of rotations), then a Givens QR of F V.
-// The last singular value carries the sign of det F.
-template <typename T, int D>
-__device__ __forceinline__ void svd_rv(const T F[D][D], T U[D][D], T V[D][D], T sig[D]) {
-  T S[D][D];
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      T s = T(0);
-#pragma unroll
-      for (int k = 0; k < D; ++k) s += F[k][i] * F[k][j];
-      S[i][j] = s;
-    }
-  jacobi_eig<T, D>(S, V);
-  T B[D][D];
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      T s = T(0);
-#pragma unroll
-      for (int k = 0; k < D; ++k) s += F[i][k] * V[k][j];
-      B[i][j] = s;
-    }
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int j = 0; j < D; ++j) U[i][j] = (i == j) ? T(1) : T(0);
-#pragma unroll
-  for (int k = 0; k < D - 1; ++k)
-#pragma unroll
-    for (int q = k + 1; q < D; ++q) {
-      const T a = B[k][k], b = B[q][k];
-      const T r = csqrt(a * a + b * b);
-      T c = T(1), s = T(0);
-      if (r > T(0)) {
-        c = a / r;
-        s = b / r;
-      }
-#pragma unroll
-      for (int j = 0; j < D; ++j) {
-        const T bp = B[k][j], bq = B[q][j];
-        B[k][j] = c * bp + s * bq;
-        B[q][j] = -s * bp + c * bq;
-      }
-#pragma unroll
-      for (int i = 0; i < D; ++i) {
-        const T up = U[i][k], uq = U[i][q];
-        U[i][k] = c * up + s * uq;
-        U[i][q] = -s * up + c * uq;
-      }
-    }
-#pragma unroll
-  for (int k = 0; k < D; ++k) sig[k] = B[k][k];
-}
-
-// Projected stable neo-Hookean Hessian as its positive eigenpairs.  In the
-// frame of F = U diag(sig) V^T the Hessian splits into the block coupling the
-// diagonal entries (A_kk = mu + lam c_k^2, A_kl = lam c_k c_l + s sig_m with
-// c the diagonal cofactors and s = lam (J-1) - mu) and, for every pair k < l,
-// a 2x2 block on (F_kl, F_lk) with eigenvalues mu -+ s sig_m (2D: sig_m = 1)
-// and eigenvectors (1, +-1)/sqrt(2).  Eigen-matrices map back as
-// U E V^T.  callback(weight, Q) is invoked for each eigenpair with weight > 0.
-template <typename T, int D, typename CB>
-__device__ __forceinline__ void snh_projected_eigs(const T F[D][D], T mu, T lam, CB&& callback) {
-  T U[D][D], V[D][D], sig[D];
-  svd_rv<T, D>(F, U, V, sig);
-  T J = T(1);
-#pragma unroll
-  for (int k = 0; k < D; ++k) J *= sig[k];
-  const T s = lam * (J - T(1)) - mu;
-  T A[D][D], c[D], third[D][D];
-  if constexpr (D == 2) {
-    c[0] = sig[1];
-    c[1] = sig[0];
-    third[0][1] = third[1][0] = T(1);
-  } else {
-    c[0] = sig[1] * sig[2];
-    c[1] = sig[0] * sig[2];
-    c[2] = sig[0] * sig[1];
-    third[0][1] = third[1][0] = sig[2];
-    third[0][2] = third[2][0] = sig[1];
-    third[1][2] = third[2][1] = sig[0];
-  }
-#pragma unroll
-  for (int k = 0; k < D; ++k)
-#pragma unroll
-    for (int l = 0; l < D; ++l)
-      A[k][l] = (k == l) ? mu + lam * c[k] * c[k] : lam * c[k] * c[l] + s * third[k][l];
-  T W[D][D];
-  jacobi_eig<T, D>(A, W);
-  T Q[D][D];
-#pragma unroll
-  for (int r = 0; r < D; ++r) {
-    const T w = A[r][r];
-    if (w > T(0)) {
-#pragma unroll
-      for (int i = 0; i < D; ++i)
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-          T acc = T(0);
-#pragma unroll
-          for (int k = 0; k < D; ++k) acc += W[k][r] * U[i][k] * V[j][k];
-          Q[i][j] = acc;
-        }
-      callback(w, Q);
-    }
-  }
-  const T h = T(0.70710678118654752440);
-#pragma unroll
-  for (int k = 0; k < D - 1; ++k)
-#pragma unroll
-    for (int l = k + 1; l < D; ++l) {
-      const T sm = third[k][l];
-#pragma unroll
-      for (int sgn = 0; sgn < 2; ++sgn) {
-        // sgn 0: vector (1, 1), eigenvalue mu - s sig_m; sgn 1: (1, -1), mu + s sig_m
-        const T w = sgn == 0 ? mu - s * sm : mu + s * sm;
-        if (!(w > T(0))) continue;
-        const T b = sgn == 0 ? h : -h;
-#pragma unroll
-        for (int i = 0; i < D; ++i)
-#pragma unroll
-          for (int j = 0; j < D; ++j) Q[i][j] = h * U[i][k] * V[j][l] + b * U[i][l] * V[j][k];
-        callback(w, Q);
-      }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Element Hessian: H_e[a,b] = scale * V_e * sum_r w_r (Q_r beta_a)(Q_r beta_b)^T
 template <typename T, int D>
-__global__ void __launch_bounds__(WG) k_elem_hess(MeshView mv, const double* __restrict__ x, T mu,
-                                                  T lam, T scale, T* __restrict__ out) {
+__device__ __forceinline__ void elem_hess_body(const MeshView& mv, int e, const double* __restrict__ x,
+                                               T mu, T lam, T scale, T* __restrict__ out) {
   constexpr int K = D + 1, DD = D * D, NB = K * (K + 1) / 2;
-  const int e = blockIdx.x * WG + threadIdx.x;
   if (e >= mv.m) return;
   T F[D][D], beta[K][D], vol;
   load_element<T, D>(mv, e, x, F, beta, vol);
@@ -371,13 +73,18 @@ __global__ void __launch_bounds__(WG) k_elem_hess(MeshView mv, const double* __r
     for (int r = 0; r < DD; ++r) out[((size_t)p * m + e) * DD + r] = f * acc[p][r];
 }
 
+template <typename T, int D>
+__global__ void __launch_bounds__(WG) k_elem_hess(MeshView mv, const double* __restrict__ x, T mu,
+                                                  T lam, T scale, T* __restrict__ out) {
+  elem_hess_body<T, D>(mv, blockIdx.x * WG + threadIdx.x, x, mu, lam, scale, out);
+}
+
 // Block rows: every slot sums its element contributions (fixed order), plus
 // the mass on the diagonal.
 template <typename T, int D>
-__global__ void __launch_bounds__(WG) k_assemble(MeshView mv, const T* __restrict__ est, T w_in,
-                                                 T* __restrict__ hb) {
+__device__ __forceinline__ void assemble_body(const MeshView& mv, int t, const T* __restrict__ est,
+                                              T w_in, T* __restrict__ hb) {
   constexpr int K = D + 1, DD = D * D;
-  const int t = blockIdx.x * WG + threadIdx.x;
   if (t >= mv.nnzb) return;
   T acc[DD];
 #pragma unroll
@@ -408,27 +115,19 @@ __global__ void __launch_bounds__(WG) k_assemble(MeshView mv, const T* __restric
   for (int r = 0; r < DD; ++r) hb[(size_t)t * DD + r] = acc[r];
 }
 
-template <int WGS>
-__device__ __forceinline__ double block_sum(double v, double* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-#pragma unroll
-  for (int s = WGS / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  return red[0];
+template <typename T, int D>
+__global__ void __launch_bounds__(WG) k_assemble(MeshView mv, const T* __restrict__ est, T w_in,
+                                                 T* __restrict__ hb) {
+  assemble_body<T, D>(mv, blockIdx.x * WG + threadIdx.x, est, w_in, hb);
 }
 
 // Free-vertex gradient in float64: G lanes per vertex share its star.
+// Returns g_j . g_j on the group's first lane, 0 elsewhere.
 template <int D, int G>
-__global__ void __launch_bounds__(WG) k_gradient(MeshView mv, const double* __restrict__ x,
-                                                 const double* __restrict__ xt, Material mat,
-                                                 double* __restrict__ g,
-                                                 double* __restrict__ partials) {
-  __shared__ double red[WG];
-  const int lane = threadIdx.x % G;
-  const int j = blockIdx.x * (WG / G) + threadIdx.x / G;
+__device__ __forceinline__ double gradient_body(const MeshView& mv, int j, int lane,
+                                                const double* __restrict__ x,
+                                                const double* __restrict__ xt, const Material& mat,
+                                                double* __restrict__ g) {
   const int n = mv.n;
   double acc[D];
 #pragma unroll
@@ -464,233 +163,29 @@ __global__ void __launch_bounds__(WG) k_gradient(MeshView mv, const double* __re
       gsq += gj * gj;
     }
   }
+  return gsq;
+}
+
+template <int D, int G>
+__global__ void __launch_bounds__(WG) k_gradient(MeshView mv, const double* __restrict__ x,
+                                                 const double* __restrict__ xt, Material mat,
+                                                 double* __restrict__ g,
+                                                 double* __restrict__ partials) {
+  __shared__ double red[WG];
+  const double gsq = gradient_body<D, G>(mv, blockIdx.x * (WG / G) + threadIdx.x / G,
+                                         threadIdx.x % G, x, xt, mat, g);
   const double tot = block_sum<WG>(gsq, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
-}
-
-template <typename T, int D>
-__device__ __forceinline__ bool chol(const T M[D][D], T L[D][D]) {
-  T tr = T(0);
-#pragma unroll
-  for (int i = 0; i < D; ++i) tr += M[i][i];
-  const T tol = T(1e-12) * tr;
-  bool ok = true;
-#pragma unroll
-  for (int j = 0; j < D; ++j) {
-    T s = M[j][j];
-#pragma unroll
-    for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
-    ok = ok && (s > tol);
-    const T ljj = csqrt(s > T(0) ? s : T(1));
-    L[j][j] = ljj;
-#pragma unroll
-    for (int i = j + 1; i < D; ++i) {
-      T t = M[i][j];
-#pragma unroll
-      for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
-      L[i][j] = t / ljj;
-    }
-#pragma unroll
-    for (int i = 0; i < j; ++i) L[i][j] = T(0);
-  }
-  return ok;
-}
-
-// X = M^{-1} B for the Cholesky factor L of M (B, X: D x D, column-wise).
-template <typename T, int D>
-__device__ __forceinline__ void chol_solve(const T L[D][D], const T B[D][D], T X[D][D]) {
-#pragma unroll
-  for (int col = 0; col < D; ++col) {
-    T y[D];
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      T s = B[i][col];
-#pragma unroll
-      for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
-      y[i] = s / L[i][i];
-    }
-#pragma unroll
-    for (int i = D - 1; i >= 0; --i) {
-      T s = y[i];
-#pragma unroll
-      for (int k = i + 1; k < D; ++k) s -= L[k][i] * X[k][col];
-      X[i][col] = s / L[i][i];
-    }
-  }
-}
-
-__device__ __forceinline__ int find_slot(const MeshView& mv, int64_t sp0, int64_t sp1, int i, int k) {
-  if (mv.dense_supp) {
-    if (k == i || k >= mv.nf) return -1;
-    return (int)(sp0 + (k < i ? k : k - 1));
-  }
-  int64_t lo = sp0, hi = sp1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (mv.sidx[mid] < k) lo = mid + 1; else hi = mid;
-  }
-  return (lo < sp1 && mv.sidx[lo] == k) ? (int)lo : -1;
-}
-
-// Per-vertex condensation: A_i = H_iC U_i, Ht_i = U_i^T H_CC U_i, then
-// K_i = (H_ii - A Ht^{-1} A^T)^{-1} and L_i = A Ht^{-1} (CC), with the
-// coordinate-descent and JGS2 forms as special cases.  G lanes per vertex.
-// Contribution of support row j to A_i (when row j holds block (j, i)) and to
-// Ht_i (blocks (j, k) with k in the support); Uk(k) returns U_i[k] or null.
-template <typename T, int D, typename LookupU>
-__device__ __forceinline__ void accum_row(const MeshView& mv, int i, int j, const T* Uj,
-                                          const T* __restrict__ hb, LookupU&& Uk_of, T* A, T* Ht) {
-  constexpr int DD = D * D;
-  for (int t = mv.rowptr[j]; t < mv.rowptr[j + 1]; ++t) {
-    const int k = mv.colidx[t];
-    const T* H = hb + (size_t)t * DD;
-    if (k == i) {
-      // A += H_ji^T U_j
-#pragma unroll
-      for (int r = 0; r < D; ++r)
-#pragma unroll
-        for (int s = 0; s < D; ++s) {
-          T acc = T(0);
-#pragma unroll
-          for (int l = 0; l < D; ++l) acc += H[l * D + r] * Uj[l * D + s];
-          A[r * D + s] += acc;
-        }
-      continue;
-    }
-    const T* Uk = Uk_of(k);
-    if (!Uk) continue;
-    T Hl[DD], M[DD];
-#pragma unroll
-    for (int r = 0; r < DD; ++r) Hl[r] = H[r];
-#pragma unroll
-    for (int r = 0; r < D; ++r)   // M = H_jk U_k
-#pragma unroll
-      for (int s = 0; s < D; ++s) {
-        T acc = T(0);
-#pragma unroll
-        for (int l = 0; l < D; ++l) acc += Hl[r * D + l] * Uk[l * D + s];
-        M[r * D + s] = acc;
-      }
-#pragma unroll
-    for (int r = 0; r < D; ++r)   // Ht += U_j^T M
-#pragma unroll
-      for (int s = 0; s < D; ++s) {
-        T acc = T(0);
-#pragma unroll
-        for (int l = 0; l < D; ++l) acc += Uj[l * D + r] * M[l * D + s];
-        Ht[r * D + s] += acc;
-      }
-  }
-}
-
-// Small solves of one vertex from the reduced A_i and Ht_i; writes K_i, L_i.
-template <typename T, int D>
-__device__ void cc_finish(const MeshView& mv, int method, int i, bool empty, const T* A,
-                          const T* Ht, const T* __restrict__ hb, T* __restrict__ KL,
-                          unsigned long long* __restrict__ fb) {
-  constexpr int DD = D * D;
-  T Hii[D][D], Kout[D][D], Lout[D][D], Lc[D][D], I[D][D];
-  const T* hd = hb + (size_t)mv.rowptr[i] * DD;
-#pragma unroll
-  for (int r = 0; r < D; ++r)
-#pragma unroll
-    for (int s = 0; s < D; ++s) {
-      Hii[r][s] = hd[r * D + s];
-      I[r][s] = (r == s) ? T(1) : T(0);
-      Lout[r][s] = T(0);
-      Kout[r][s] = T(0);
-    }
-  const bool ok_ii = chol<T, D>(Hii, Lc);
-  if (!ok_ii) atomicAdd(&fb[2], 1ull);
-  T Kcd[D][D];
-  if (ok_ii) chol_solve<T, D>(Lc, I, Kcd);
-  else
-#pragma unroll
-    for (int r = 0; r < D; ++r)
-#pragma unroll
-      for (int s = 0; s < D; ++s) Kcd[r][s] = T(0);
-  bool use_cd = true;
-  if (method == 1) {  // Coordinate Condensation
-    T Htm[D][D], Lt[D][D];
-#pragma unroll
-    for (int r = 0; r < D; ++r)
-#pragma unroll
-      for (int s = 0; s < D; ++s) Htm[r][s] = Ht[r * D + s];
-    const bool ok_t = !empty && chol<T, D>(Htm, Lt);
-    if (!ok_t) {
-      atomicAdd(&fb[0], 1ull);
-    } else {
-      T At[D][D], Z[D][D], M[D][D], Lm[D][D];
-#pragma unroll
-      for (int r = 0; r < D; ++r)
-#pragma unroll
-        for (int s = 0; s < D; ++s) At[r][s] = A[s * D + r];
-      chol_solve<T, D>(Lt, At, Z);  // Z = Ht^{-1} A^T
-#pragma unroll
-      for (int r = 0; r < D; ++r)
-#pragma unroll
-        for (int s = 0; s < D; ++s) {
-          T acc = T(0);
-#pragma unroll
-          for (int l = 0; l < D; ++l) acc += A[r * D + l] * Z[l][s];
-          M[r][s] = Hii[r][s] - acc;  // H_ii - S
-        }
-      if (chol<T, D>(M, Lm)) {
-        chol_solve<T, D>(Lm, I, Kout);
-#pragma unroll
-        for (int r = 0; r < D; ++r)
-#pragma unroll
-          for (int s = 0; s < D; ++s) Lout[r][s] = Z[s][r];  // L = A Ht^{-1} = Z^T
-        use_cd = false;
-      } else {
-        atomicAdd(&fb[1], 1ull);
-      }
-    }
-  } else if (method == 2) {  // JGS2 as printed: (H_ii + Ht)^{-1} (g_i + U^T g_C)
-    T M[D][D], Lm[D][D];
-#pragma unroll
-    for (int r = 0; r < D; ++r)
-#pragma unroll
-      for (int s = 0; s < D; ++s) M[r][s] = Hii[r][s] + Ht[r * D + s];
-    if (!empty && chol<T, D>(M, Lm)) {
-      chol_solve<T, D>(Lm, I, Kout);
-#pragma unroll
-      for (int r = 0; r < D; ++r) Lout[r][r] = T(-1);
-      use_cd = false;
-    } else {
-      atomicAdd(&fb[0], 1ull);
-    }
-  }
-  if (use_cd) {
-#pragma unroll
-    for (int r = 0; r < D; ++r)
-#pragma unroll
-      for (int s = 0; s < D; ++s) {
-        Kout[r][s] = Kcd[r][s];
-        Lout[r][s] = T(0);
-      }
-  }
-  T* o = KL + (size_t)i * 2 * DD;
-#pragma unroll
-  for (int r = 0; r < D; ++r)
-#pragma unroll
-    for (int s = 0; s < D; ++s) {
-      o[r * D + s] = Kout[r][s];
-      o[DD + r * D + s] = Lout[r][s];
-    }
 }
 
 // Generic condensation kernel: G lanes per vertex, basis and support from
 // global memory (binary search for the support slot of a neighbour).
 template <typename T, int D, int G>
-__global__ void __launch_bounds__(WG) k_cc_prep(MeshView mv, int method, int v0, int v1,
-                                                const T* __restrict__ hb, T* __restrict__ KL,
-                                                unsigned long long* __restrict__ fb) {
+__device__ __forceinline__ void prep_body(const MeshView& mv, int method, int i, bool active, int lane,
+                                          const T* __restrict__ hb, T* __restrict__ KL,
+                                          unsigned long long* __restrict__ fb) {
   constexpr int DD = D * D;
   const T* Ub = basis_of<T>(mv);
-  const int lane = threadIdx.x % G;
-  const int i = v0 + blockIdx.x * (WG / G) + threadIdx.x / G;
-  const bool active = i < v1;
   T A[DD], Ht[DD];
 #pragma unroll
   for (int r = 0; r < DD; ++r) A[r] = Ht[r] = T(0);
@@ -720,19 +215,26 @@ __global__ void __launch_bounds__(WG) k_cc_prep(MeshView mv, int method, int v0,
   cc_finish<T, D>(mv, method, i, sp1 == sp0, A, Ht, hb, KL, fb);
 }
 
+template <typename T, int D, int G>
+__global__ void __launch_bounds__(WG) k_cc_prep(MeshView mv, int method, int v0, int v1,
+                                                const T* __restrict__ hb, T* __restrict__ KL,
+                                                unsigned long long* __restrict__ fb) {
+  const int i = v0 + blockIdx.x * (WG / G) + threadIdx.x / G;
+  prep_body<T, D, G>(mv, method, i, i < v1, threadIdx.x % G, hb, KL, fb);
+}
+
 // Exact-basis condensation: one workgroup per vertex; the vertex's dense
 // basis row U_i (every other free vertex) is staged in LDS, so the H_jk U_k
 // products read U_k from LDS while the block rows stream from global memory.
+// Whole workgroup on vertex i; Us: LDS room for the basis row, red: LDS
+// scratch of (WG/64) x 2 D*D values.
 template <typename T, int D>
-__global__ void __launch_bounds__(WG) k_cc_prep_dense(MeshView mv, int method, int v0,
-                                                      const T* __restrict__ hb, T* __restrict__ KL,
-                                                      unsigned long long* __restrict__ fb) {
+__device__ __forceinline__ void prep_dense_body(const MeshView& mv, int method, int i,
+                                                const T* __restrict__ hb, T* __restrict__ KL,
+                                                unsigned long long* __restrict__ fb, T* Us,
+                                                T (*red)[2 * D * D]) {
   constexpr int DD = D * D;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* Us = reinterpret_cast<T*>(smem_raw);
-  __shared__ T red[WG / 64][2 * DD];
   const T* Ub = basis_of<T>(mv);
-  const int i = v0 + blockIdx.x;
   const int cnt = mv.nf - 1;
   const int64_t sp0 = mv.sptr[i];
   for (int q = threadIdx.x; q < cnt * DD; q += WG) Us[q] = Ub[sp0 * DD + q];
@@ -782,19 +284,25 @@ __global__ void __launch_bounds__(WG) k_cc_prep_dense(MeshView mv, int method, i
   cc_finish<T, D>(mv, method, i, cnt == 0, A, Ht, hb, KL, fb);
 }
 
+template <typename T, int D>
+__global__ void __launch_bounds__(WG) k_cc_prep_dense(MeshView mv, int method, int v0,
+                                                      const T* __restrict__ hb, T* __restrict__ KL,
+                                                      unsigned long long* __restrict__ fb) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ T red[WG / 64][2 * D * D];
+  prep_dense_body<T, D>(mv, method, v0 + blockIdx.x, hb, KL, fb, reinterpret_cast<T*>(smem_raw), red);
+}
+
 
 // dx_i = -K_i (g_i - L_i U_i^T g_C); written to d (Jacobi) or added to x
 // (coloured sweep).  G lanes per vertex share its support.
 template <typename T, int D, int G>
-__global__ void __launch_bounds__(WG) k_cc_update(MeshView mv, int method, int v0, int v1,
-                                                  const T* __restrict__ KL,
-                                                  const double* __restrict__ g,
-                                                  double* __restrict__ out, int accumulate) {
+__device__ __forceinline__ void update_body(const MeshView& mv, int method, int i, bool active,
+                                            int lane, const T* __restrict__ KL,
+                                            const double* __restrict__ g, double* __restrict__ out,
+                                            int accumulate) {
   constexpr int DD = D * D;
   const T* Ub = basis_of<T>(mv);
-  const int lane = threadIdx.x % G;
-  const int i = v0 + blockIdx.x * (WG / G) + threadIdx.x / G;
-  const bool active = i < v1;
   const int n = mv.n;
   T b[D];
 #pragma unroll
@@ -839,24 +347,33 @@ __global__ void __launch_bounds__(WG) k_cc_update(MeshView mv, int method, int v
   }
 }
 
+template <typename T, int D, int G>
+__global__ void __launch_bounds__(WG) k_cc_update(MeshView mv, int method, int v0, int v1,
+                                                  const T* __restrict__ KL,
+                                                  const double* __restrict__ g,
+                                                  double* __restrict__ out, int accumulate) {
+  const int i = v0 + blockIdx.x * (WG / G) + threadIdx.x / G;
+  update_body<T, D, G>(mv, method, i, i < v1, threadIdx.x % G, KL, g, out, accumulate);
+}
+
 // Step energy: blocks [0, nbe) sum element energies, the rest the free-vertex
 // inertia and gravity terms; one partial per block.
+// Block b < nbe sums element energies, the others free-vertex terms.
 template <int D>
-__global__ void __launch_bounds__(WG) k_energy(MeshView mv, const double* __restrict__ x,
-                                               const double* __restrict__ xt, Material mat,
-                                               int nbe, double* __restrict__ partials) {
-  __shared__ double red[WG];
+__device__ __forceinline__ double energy_body(const MeshView& mv, int b, int nbe,
+                                              const double* __restrict__ x,
+                                              const double* __restrict__ xt, const Material& mat) {
   double v = 0.0;
   const int n = mv.n;
-  if ((int)blockIdx.x < nbe) {
-    const int e = blockIdx.x * WG + threadIdx.x;
+  if (b < nbe) {
+    const int e = b * WG + threadIdx.x;
     if (e < mv.m) {
       double F[D][D], beta[D + 1][D], vol;
       load_element<double, D>(mv, e, x, F, beta, vol);
       v = mat.s_el * vol * snh_psi<double, D>(F, mat.mu, mat.lam);
     }
   } else {
-    const int j = (blockIdx.x - nbe) * WG + threadIdx.x;
+    const int j = (b - nbe) * WG + threadIdx.x;
     if (j < mv.nf) {
       const double mj = mv.mass[j];
       double in = 0.0, gr = 0.0;
@@ -869,6 +386,15 @@ __global__ void __launch_bounds__(WG) k_energy(MeshView mv, const double* __rest
       v = mat.w_in * 0.5 * mj * in - mat.s_el * mj * gr;
     }
   }
+  return v;
+}
+
+template <int D>
+__global__ void __launch_bounds__(WG) k_energy(MeshView mv, const double* __restrict__ x,
+                                               const double* __restrict__ xt, Material mat,
+                                               int nbe, double* __restrict__ partials) {
+  __shared__ double red[WG];
+  const double v = energy_body<D>(mv, blockIdx.x, nbe, x, xt, mat);
   const double tot = block_sum<WG>(v, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
@@ -1155,6 +681,574 @@ void launch_scatter_user(const MeshView& mv, const int* vperm, const double* src
                          double* dst_user, int free_only, hipStream_t s) {
   CC_DISPATCH_D(mv.D, k_scatter_user<D><<<nblocks(mv.n, WG), WG, 0, s>>>(mv, vperm, src_int, dst_user,
                                                                         free_only));
+}
+
+}  // namespace cc
+
+// ===========================================================================
+// Batched stepping: every launch covers all meshes of a batch; block b of a
+// launch belongs to mesh m when boff[m] <= b < boff[m+1].  Meshes whose
+// control block is inactive return at once, so a captured sequence of
+// launches stays valid while meshes finish at different iterations.
+namespace cc {
+
+__device__ __forceinline__ int block_mesh(const int* __restrict__ boff, int nmesh, int b) {
+  int lo = 0, hi = nmesh;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (boff[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ const double* pick(const BatchItem& it, int which) {
+  return which ? it.xtrial : it.x;
+}
+
+__device__ __forceinline__ void vertex_range(const BatchItem& it, int colour, int& v0, int& v1) {
+  if (colour < 0) { v0 = 0; v1 = it.mv.nf; }
+  else if (colour < it.ncol) { v0 = it.coff[colour]; v1 = it.coff[colour + 1]; }
+  else { v0 = v1 = 0; }
+}
+
+__global__ void kb_reset(BatchCtl* ctl, int nmesh) {
+  const int m = blockIdx.x * WG + threadIdx.x;
+  if (m >= nmesh) return;
+  BatchCtl c{};
+  c.active = 1;
+  c.status = -100;
+  ctl[m] = c;
+}
+
+template <int D>
+__global__ void __launch_bounds__(WG) kb_predict(const BatchItem* __restrict__ items, BatchCtl* ctl,
+                                                 const int* __restrict__ boff, int nmesh, double h,
+                                                 int quasi) {
+  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  const BatchItem& it = items[mi];
+  const MeshView mv = it.mv;
+  const int v = (blockIdx.x - boff[mi]) * WG + threadIdx.x;
+  if (v >= mv.n) return;
+  const int u = mv.vperm[v], n = mv.n;
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double xp = it.xu[u * D + c], vp = it.vu[u * D + c];
+    ok = ok && isfinite(xp) && isfinite(vp);
+    it.x0[c * n + v] = xp;
+    double xh;
+    if (v < mv.nf) {
+      xh = quasi ? xp : xp + h * vp;
+    } else {
+      xh = it.xbc ? it.xbc[u * D + c] : xp;
+      ok = ok && isfinite(xh);
+    }
+    it.xt[c * n + v] = xh;
+    it.x[c * n + v] = xh;
+  }
+  if (!ok) atomicOr(&ctl[mi].bad, 1);
+}
+
+template <int D>
+__global__ void __launch_bounds__(WG) kb_finalize(const BatchItem* __restrict__ items,
+                                                  const int* __restrict__ boff, int nmesh, double h,
+                                                  int quasi) {
+  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  const BatchItem& it = items[mi];
+  const MeshView mv = it.mv;
+  const int v = (blockIdx.x - boff[mi]) * WG + threadIdx.x;
+  if (v >= mv.n) return;
+  const int u = mv.vperm[v], n = mv.n;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double xn = it.x[c * n + v];
+    it.xu[u * D + c] = xn;
+    it.vu[u * D + c] = quasi ? 0.0 : (xn - it.x0[c * n + v]) / h;
+  }
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(WG) kb_elem_hess(const BatchItem* __restrict__ items,
+                                                   const BatchCtl* __restrict__ ctl,
+                                                   const int* __restrict__ boff, int nmesh, int which) {
+  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  if (!ctl[mi].active) return;
+  const BatchItem& it = items[mi];
+  const MeshView mv = it.mv;
+  elem_hess_body<T, D>(mv, (blockIdx.x - boff[mi]) * WG + threadIdx.x, pick(it, which), T(it.mat.mu),
+                       T(it.mat.lam), T(it.mat.s_el), (T*)it.estore);
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(WG) kb_assemble(const BatchItem* __restrict__ items,
+                                                  const BatchCtl* __restrict__ ctl,
+                                                  const int* __restrict__ boff, int nmesh) {
+  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  if (!ctl[mi].active) return;
+  const BatchItem& it = items[mi];
+  const MeshView mv = it.mv;
+  assemble_body<T, D>(mv, (blockIdx.x - boff[mi]) * WG + threadIdx.x, (const T*)it.estore,
+                      T(it.mat.w_in), (T*)it.hb);
+}
+
+template <int D, int G>
+__global__ void __launch_bounds__(WG) kb_gradient(const BatchItem* __restrict__ items,
+                                                  const BatchCtl* __restrict__ ctl,
+                                                  const int* __restrict__ boff, int nmesh, int which) {
+  __shared__ double red[WG];
+  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  if (!ctl[mi].active) return;
+  const BatchItem& it = items[mi];
+  const MeshView mv = it.mv;
+  const int lb = blockIdx.x - boff[mi];
+  const double gsq = gradient_body<D, G>(mv, lb * (WG / G) + threadIdx.x / G, threadIdx.x % G,
+                                         pick(it, which), it.xt, it.mat, it.g);
+  const double tot = block_sum<WG>(gsq, red);
+  if (threadIdx.x == 0) it.partials[lb] = tot;
+}
+
+template <typename T, int D, int G>
+__global__ void __launch_bounds__(WG) kb_prep(const BatchItem* __restrict__ items,
+                                              const BatchCtl* __restrict__ ctl,
+                                              const int* __restrict__ boff, int nmesh, int method,
+                                              int colour) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ T red[WG / 64][2 * D * D];
+  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  if (!ctl[mi].active) return;
+  const BatchItem& it = items[mi];
+  const MeshView mv = it.mv;
+  int v0, v1;
+  vertex_range(it, colour, v0, v1);
+  const int lb = blockIdx.x - boff[mi];
+  if (it.prep_dense) {
+    prep_dense_body<T, D>(mv, method, v0 + lb, (const T*)it.hb, (T*)it.KL, it.fb,
+                          reinterpret_cast<T*>(smem_raw), red);
+  } else {
+    const int i = v0 + lb * (WG / G) + threadIdx.x / G;
+    prep_body<T, D, G>(mv, method, i, i < v1, threadIdx.x % G, (const T*)it.hb, (T*)it.KL, it.fb);
+  }
+}
+
+template <typename T, int D, int G>
+__global__ void __launch_bounds__(WG) kb_update(const BatchItem* __restrict__ items,
+                                                const BatchCtl* __restrict__ ctl,
+                                                const int* __restrict__ boff, int nmesh, int method,
+                                                int colour, int into_trial) {
+  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  if (!ctl[mi].active) return;
+  const BatchItem& it = items[mi];
+  const MeshView mv = it.mv;
+  int v0, v1;
+  vertex_range(it, colour, v0, v1);
+  const int i = v0 + (blockIdx.x - boff[mi]) * (WG / G) + threadIdx.x / G;
+  update_body<T, D, G>(mv, method, i, i < v1, threadIdx.x % G, (const T*)it.KL, it.g,
+                       into_trial ? it.xtrial : it.d, into_trial);
+}
+
+// xtrial = x + alpha d (copy_only: xtrial = x) over all D*n entries.
+__global__ void __launch_bounds__(WG) kb_axpy(const BatchItem* __restrict__ items,
+                                              const BatchCtl* __restrict__ ctl,
+                                              const int* __restrict__ boff, int nmesh, double alpha,
+                                              int copy_only) {
+  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  if (!ctl[mi].active) return;
+  const BatchItem& it = items[mi];
+  const int t = (blockIdx.x - boff[mi]) * WG + threadIdx.x;
+  if (t >= it.mv.D * it.mv.n) return;
+  it.xtrial[t] = copy_only ? it.x[t] : it.x[t] + alpha * it.d[t];
+}
+
+template <int D>
+__global__ void __launch_bounds__(WG) kb_energy(const BatchItem* __restrict__ items,
+                                                const BatchCtl* __restrict__ ctl,
+                                                const int* __restrict__ boff, int nmesh, int which) {
+  __shared__ double red[WG];
+  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  if (!ctl[mi].active) return;
+  const BatchItem& it = items[mi];
+  const MeshView mv = it.mv;
+  const int lb = blockIdx.x - boff[mi];
+  const int nbe = (mv.m + WG - 1) / WG;
+  const double v = energy_body<D>(mv, lb, nbe, pick(it, which), it.xt, it.mat);
+  const double tot = block_sum<WG>(v, red);
+  if (threadIdx.x == 0) it.partials[lb] = tot;
+}
+
+// One workgroup per mesh: sums the partials written by the launch whose
+// block offsets are boff_src; dst 0 -> E_trial, 1 -> gn2, 2 -> E_cur.
+__global__ void __launch_bounds__(WG) kb_reduce(const BatchItem* __restrict__ items, BatchCtl* ctl,
+                                                const int* __restrict__ boff_src, int dst) {
+  __shared__ double red[WG];
+  const int mi = blockIdx.x;
+  if (!ctl[mi].active) return;
+  const double* part = items[mi].partials;
+  const int np = boff_src[mi + 1] - boff_src[mi];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < np; i += WG) v += part[i];
+  const double tot = block_sum<WG>(v, red);
+  if (threadIdx.x == 0) {
+    if (dst == 0) ctl[mi].E_trial = tot;
+    else if (dst == 1) ctl[mi].gn2 = tot;
+    else ctl[mi].E_cur = tot;
+  }
+}
+
+__global__ void kb_init(BatchCtl* ctl, int nmesh, double tol, int max_iters) {
+  const int m = blockIdx.x * WG + threadIdx.x;
+  if (m >= nmesh) return;
+  BatchCtl& c = ctl[m];
+  if (c.bad) { c.status = -5; c.active = 0; return; }
+  c.g0 = sqrt(c.gn2);
+  if (c.g0 == 0.0) { c.r = 0.0; c.status = 0; c.active = 0; return; }
+  c.r = 1.0;
+  if (c.r <= tol) { c.status = 0; c.active = 0; }
+  else if (max_iters <= 0) { c.status = 1; c.active = 0; }
+}
+
+// Accept the iteration when E did not rise beyond the slack (or without line
+// search); otherwise hand the mesh to the host for backtracking.
+__global__ void kb_accept(BatchItem* items, BatchCtl* ctl, int nmesh, int line_search) {
+  const int m = blockIdx.x * WG + threadIdx.x;
+  if (m >= nmesh) return;
+  BatchCtl& c = ctl[m];
+  if (!c.active) return;
+  const double tau = 1e-12 * fmax(fabs(c.E_cur), 1.0);
+  if (!line_search || c.E_trial <= c.E_cur + tau) {
+    double* t = items[m].x;
+    items[m].x = items[m].xtrial;
+    items[m].xtrial = t;
+    if (line_search) c.E_cur = c.E_trial;
+    c.iters += 1;
+  } else {
+    c.needs_host = 1;
+    c.active = 0;
+  }
+}
+
+__global__ void kb_converged(BatchCtl* ctl, int nmesh, double tol, int max_iters) {
+  const int m = blockIdx.x * WG + threadIdx.x;
+  if (m >= nmesh) return;
+  BatchCtl& c = ctl[m];
+  if (!c.active) return;
+  c.r = sqrt(c.gn2) / c.g0;
+  if (!isfinite(c.r)) { c.status = 2; c.active = 0; }
+  else if (c.r <= tol) { c.status = 0; c.active = 0; }
+  else if (c.iters >= max_iters) { c.status = 1; c.active = 0; }
+}
+
+// ---- host side of a batch ---------------------------------------------------
+struct Offsets {
+  std::vector<int> h;
+  int* d = nullptr;
+  int total() const { return h.empty() ? 0 : h.back(); }
+};
+
+struct BatchPlan {
+  int nmesh = 0;
+  BatchConfig cfg{};
+  std::vector<BatchItem> items_h;
+  BatchItem* items_d = nullptr;
+  BatchCtl* ctl_d = nullptr;
+  Offsets pred, elem, asmb, grad, energy, axpy;
+  std::vector<Offsets> prep, upd;   // index 0: all free vertices, c+1: colour c
+  int max_colours = 0;
+  size_t lds = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_iters = 0;
+  BatchHook hook = nullptr;
+  void* hook_user = nullptr;
+  int capturing = 0;
+  void mark(int kid, int begin) { if (hook) hook(hook_user, kid, begin); }
+};
+
+static void drop_graph(BatchPlan* p) {
+  if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
+  if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+}
+
+void batch_set_hook(BatchPlan* p, BatchHook hook, void* user) {
+  if (p->hook == hook && p->hook_user == user) return;
+  drop_graph(p);
+  p->hook = hook;
+  p->hook_user = user;
+}
+
+int batch_capturing(BatchPlan* p) { return p->capturing; }
+int batch_has_graph(BatchPlan* p) { return p->exec != nullptr; }
+
+static void offsets_build(Offsets& o, const std::vector<int>& counts, hipStream_t s) {
+  o.h.assign(counts.size() + 1, 0);
+  for (size_t i = 0; i < counts.size(); ++i) o.h[i + 1] = o.h[i] + counts[i];
+  if (o.d) (void)hipFree(o.d);
+  (void)hipMalloc(&o.d, o.h.size() * sizeof(int));
+  (void)hipMemcpyAsync(o.d, o.h.data(), o.h.size() * sizeof(int), hipMemcpyHostToDevice, s);
+}
+
+static void offsets_free(Offsets& o) {
+  if (o.d) (void)hipFree(o.d);
+  o.d = nullptr;
+}
+
+static void plan_vertex_offsets(BatchPlan* p, hipStream_t s) {
+  const int G = p->cfg.G;
+  p->prep.assign(p->max_colours + 1, Offsets{});
+  p->upd.assign(p->max_colours + 1, Offsets{});
+  for (int c = -1; c < p->max_colours; ++c) {
+    std::vector<int> cp(p->nmesh), cu(p->nmesh);
+    for (int m = 0; m < p->nmesh; ++m) {
+      const BatchItem& it = p->items_h[m];
+      int v0, v1;
+      if (c < 0) { v0 = 0; v1 = it.mv.nf; }
+      else if (c < it.ncol) { v0 = it.coff[c]; v1 = it.coff[c + 1]; }
+      else { v0 = v1 = 0; }
+      const int cnt = v1 - v0;
+      cp[m] = it.prep_dense ? cnt : nblocks(cnt, WG / G);
+      cu[m] = nblocks(cnt, WG / G);
+    }
+    offsets_build(p->prep[c + 1], cp, s);
+    offsets_build(p->upd[c + 1], cu, s);
+  }
+}
+
+BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const BatchConfig& cfg,
+                             hipStream_t s) {
+  BatchPlan* p = new BatchPlan();
+  p->nmesh = nmesh;
+  p->cfg = cfg;
+  p->items_h.assign(items_host, items_host + nmesh);
+  std::vector<int> cpred(nmesh), celem(nmesh), casm(nmesh), cgrad(nmesh), cen(nmesh), cax(nmesh);
+  for (int m = 0; m < nmesh; ++m) {
+    const MeshView& mv = p->items_h[m].mv;
+    cpred[m] = nblocks(mv.n, WG);
+    celem[m] = nblocks(mv.m, WG);
+    casm[m] = nblocks(mv.nnzb, WG);
+    cgrad[m] = nblocks(mv.nf, WG / GRAD_G);
+    cen[m] = nblocks(mv.m, WG) + nblocks(mv.nf, WG);
+    cax[m] = nblocks((long long)mv.D * mv.n, WG);
+    p->max_colours = std::max(p->max_colours, p->items_h[m].ncol);
+    if (p->items_h[m].prep_dense) {
+      const size_t lds = (size_t)(mv.nf - 1) * mv.D * mv.D * (cfg.prec == 0 ? 8 : 4);
+      p->lds = std::max(p->lds, lds);
+    }
+  }
+  offsets_build(p->pred, cpred, s);
+  offsets_build(p->elem, celem, s);
+  offsets_build(p->asmb, casm, s);
+  offsets_build(p->grad, cgrad, s);
+  offsets_build(p->energy, cen, s);
+  offsets_build(p->axpy, cax, s);
+  plan_vertex_offsets(p, s);
+  (void)hipMalloc(&p->items_d, nmesh * sizeof(BatchItem));
+  (void)hipMalloc(&p->ctl_d, nmesh * sizeof(BatchCtl));
+  (void)hipMemcpyAsync(p->items_d, p->items_h.data(), nmesh * sizeof(BatchItem), hipMemcpyHostToDevice, s);
+  (void)hipStreamSynchronize(s);
+  return p;
+}
+
+void batch_plan_destroy(BatchPlan* p) {
+  if (!p) return;
+  drop_graph(p);
+  for (Offsets* o : {&p->pred, &p->elem, &p->asmb, &p->grad, &p->energy, &p->axpy}) offsets_free(*o);
+  for (auto& o : p->prep) offsets_free(o);
+  for (auto& o : p->upd) offsets_free(o);
+  if (p->items_d) (void)hipFree(p->items_d);
+  if (p->ctl_d) (void)hipFree(p->ctl_d);
+  delete p;
+}
+
+BatchItem* batch_items_dev(BatchPlan* p) { return p->items_d; }
+BatchCtl* batch_ctl_dev(BatchPlan* p) { return p->ctl_d; }
+
+static inline int gridn(const Offsets& o) { return o.total(); }
+
+template <int D>
+static void b_gradient(BatchPlan* p, int which, hipStream_t s) {
+  if (gridn(p->grad) == 0) return;
+  p->mark(2, 1);
+  kb_gradient<D, GRAD_G><<<gridn(p->grad), WG, 0, s>>>(p->items_d, p->ctl_d, p->grad.d, p->nmesh, which);
+  p->mark(2, 0);
+  kb_reduce<<<p->nmesh, WG, 0, s>>>(p->items_d, p->ctl_d, p->grad.d, 1);
+}
+
+template <int D>
+static void b_energy(BatchPlan* p, int which, int dst, hipStream_t s) {
+  if (gridn(p->energy) == 0) return;
+  p->mark(5, 1);
+  kb_energy<D><<<gridn(p->energy), WG, 0, s>>>(p->items_d, p->ctl_d, p->energy.d, p->nmesh, which);
+  p->mark(5, 0);
+  kb_reduce<<<p->nmesh, WG, 0, s>>>(p->items_d, p->ctl_d, p->energy.d, dst);
+}
+
+template <typename T, int D, int G>
+static void b_prep(BatchPlan* p, int colour, hipStream_t s) {
+  const Offsets& o = p->prep[colour + 1];
+  if (gridn(o) == 0) return;
+  p->mark(3, 1);
+  kb_prep<T, D, G><<<gridn(o), WG, p->lds, s>>>(p->items_d, p->ctl_d, o.d, p->nmesh, p->cfg.method, colour);
+  p->mark(3, 0);
+}
+
+template <typename T, int D, int G>
+static void b_update(BatchPlan* p, int colour, int into_trial, hipStream_t s) {
+  const Offsets& o = p->upd[colour + 1];
+  if (gridn(o) == 0) return;
+  p->mark(4, 1);
+  kb_update<T, D, G><<<gridn(o), WG, 0, s>>>(p->items_d, p->ctl_d, o.d, p->nmesh, p->cfg.method, colour,
+                                             into_trial);
+  p->mark(4, 0);
+}
+
+template <typename T, int D>
+static void b_hessian(BatchPlan* p, int which, hipStream_t s) {
+  if (gridn(p->elem) > 0) {
+    p->mark(0, 1);
+    kb_elem_hess<T, D><<<gridn(p->elem), WG, 0, s>>>(p->items_d, p->ctl_d, p->elem.d, p->nmesh, which);
+    p->mark(0, 0);
+  }
+  if (gridn(p->asmb) > 0) {
+    p->mark(1, 1);
+    kb_assemble<T, D><<<gridn(p->asmb), WG, 0, s>>>(p->items_d, p->ctl_d, p->asmb.d, p->nmesh);
+    p->mark(1, 0);
+  }
+}
+
+template <typename T, int D, int G>
+static void b_iteration(BatchPlan* p, hipStream_t s) {
+  const BatchConfig& c = p->cfg;
+  const int nm = p->nmesh, gb = nblocks(nm, WG);
+  if (c.sweep == 0) {
+    b_hessian<T, D>(p, 0, s);
+    b_prep<T, D, G>(p, -1, s);
+    b_update<T, D, G>(p, -1, 0, s);
+    if (gridn(p->axpy) > 0)
+      kb_axpy<<<gridn(p->axpy), WG, 0, s>>>(p->items_d, p->ctl_d, p->axpy.d, nm, 1.0, 0);
+  } else {
+    if (gridn(p->axpy) > 0)
+      kb_axpy<<<gridn(p->axpy), WG, 0, s>>>(p->items_d, p->ctl_d, p->axpy.d, nm, 0.0, 1);
+    for (int col = 0; col < p->max_colours; ++col) {
+      if (c.hess_refresh == 0) {
+        b_hessian<T, D>(p, 1, s);
+        b_prep<T, D, G>(p, col, s);
+      } else if (col == 0) {
+        b_hessian<T, D>(p, 1, s);
+        b_prep<T, D, G>(p, -1, s);
+      }
+      if (gridn(p->grad) > 0) {
+        p->mark(2, 1);
+        kb_gradient<D, GRAD_G><<<gridn(p->grad), WG, 0, s>>>(p->items_d, p->ctl_d, p->grad.d, nm, 1);
+        p->mark(2, 0);
+      }
+      b_update<T, D, G>(p, col, 1, s);
+    }
+  }
+  if (c.line_search) b_energy<D>(p, 1, 0, s);
+  kb_accept<<<gb, WG, 0, s>>>(p->items_d, p->ctl_d, nm, c.line_search);
+  b_gradient<D>(p, 0, s);
+  kb_converged<<<gb, WG, 0, s>>>(p->ctl_d, nm, c.tol, c.max_iters);
+}
+
+
+static void one_iteration(BatchPlan* p, hipStream_t s) {
+#define ITER(T, D, G) b_iteration<T, D, G>(p, s)
+  const BatchConfig& c = p->cfg;
+  if (c.prec == 0) {
+    if (c.D == 2) { if (c.G == 64) ITER(double, 2, 64); else if (c.G == 32) ITER(double, 2, 32); else ITER(double, 2, 16); }
+    else { if (c.G == 64) ITER(double, 3, 64); else if (c.G == 32) ITER(double, 3, 32); else ITER(double, 3, 16); }
+  } else {
+    if (c.D == 2) { if (c.G == 64) ITER(float, 2, 64); else if (c.G == 32) ITER(float, 2, 32); else ITER(float, 2, 16); }
+    else { if (c.G == 64) ITER(float, 3, 64); else if (c.G == 32) ITER(float, 3, 32); else ITER(float, 3, 16); }
+  }
+#undef ITER
+}
+
+void batch_begin(BatchPlan* p, hipStream_t s) {
+  const int nm = p->nmesh, gb = nblocks(nm, WG);
+  kb_reset<<<gb, WG, 0, s>>>(p->ctl_d, nm);
+  const int D = p->cfg.D;
+  if (D == 2) kb_predict<2><<<gridn(p->pred), WG, 0, s>>>(p->items_d, p->ctl_d, p->pred.d, nm, p->cfg.h, p->cfg.quasistatic);
+  else kb_predict<3><<<gridn(p->pred), WG, 0, s>>>(p->items_d, p->ctl_d, p->pred.d, nm, p->cfg.h, p->cfg.quasistatic);
+  if (D == 2) b_gradient<2>(p, 0, s); else b_gradient<3>(p, 0, s);
+  kb_init<<<gb, WG, 0, s>>>(p->ctl_d, nm, p->cfg.tol, p->cfg.max_iters);
+  if (p->cfg.line_search) {
+    if (D == 2) b_energy<2>(p, 0, 2, s); else b_energy<3>(p, 0, 2, s);
+  }
+}
+
+void batch_iterate(BatchPlan* p, int iters, hipStream_t s) {
+  const int k = p->cfg.iters_per_graph;
+  // with a timing hook the launches run uncaptured: event pairs recorded as
+  // graph nodes do not give per-launch durations
+  if (k <= 0 || p->hook) {
+    for (int i = 0; i < iters; ++i) one_iteration(p, s);
+    return;
+  }
+  if (!p->exec) {
+    bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      p->capturing = 1;
+      for (int i = 0; i < k; ++i) one_iteration(p, s);
+      p->capturing = 0;
+      ok = hipStreamEndCapture(s, &p->graph) == hipSuccess;
+    }
+    if (ok) ok = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
+    if (!ok) {  // capture unsupported on this stream: run the launches directly
+      (void)hipGetLastError();
+      if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+      p->exec = nullptr;
+      p->cfg.iters_per_graph = 0;
+      for (int i = 0; i < iters; ++i) one_iteration(p, s);
+      return;
+    }
+  }
+  for (int done = 0; done < iters; done += k) (void)hipGraphLaunch(p->exec, s);
+}
+
+void batch_finish(BatchPlan* p, hipStream_t s) {
+  if (gridn(p->pred) == 0) return;
+  if (p->cfg.D == 2) kb_finalize<2><<<gridn(p->pred), WG, 0, s>>>(p->items_d, p->pred.d, p->nmesh, p->cfg.h, p->cfg.quasistatic);
+  else kb_finalize<3><<<gridn(p->pred), WG, 0, s>>>(p->items_d, p->pred.d, p->nmesh, p->cfg.h, p->cfg.quasistatic);
+}
+
+void batch_set_lanes(BatchPlan* p, int G) {
+  if (G == p->cfg.G) return;
+  p->cfg.G = G;
+  drop_graph(p);
+  for (auto& o : p->prep) offsets_free(o);
+  for (auto& o : p->upd) offsets_free(o);
+  plan_vertex_offsets(p, nullptr);
+  (void)hipDeviceSynchronize();
+}
+
+// Times condensation + update (Jacobi form, writing d only) for lane count G.
+float batch_time_prep_update(BatchPlan* p, int G, int reps, hipStream_t s) {
+  batch_set_lanes(p, G);
+  hipEvent_t a, b;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+#define PU(T, D, GG) do { b_prep<T, D, GG>(p, -1, s); b_update<T, D, GG>(p, -1, 0, s); } while (0)
+  auto run = [&]() {
+    const BatchConfig& c = p->cfg;
+    if (c.prec == 0) {
+      if (c.D == 2) { if (G == 64) PU(double, 2, 64); else if (G == 32) PU(double, 2, 32); else PU(double, 2, 16); }
+      else { if (G == 64) PU(double, 3, 64); else if (G == 32) PU(double, 3, 32); else PU(double, 3, 16); }
+    } else {
+      if (c.D == 2) { if (G == 64) PU(float, 2, 64); else if (G == 32) PU(float, 2, 32); else PU(float, 2, 16); }
+      else { if (G == 64) PU(float, 3, 64); else if (G == 32) PU(float, 3, 32); else PU(float, 3, 16); }
+    }
+  };
+#undef PU
+  run();
+  (void)hipEventRecord(a, s);
+  for (int r = 0; r < reps; ++r) run();
+  (void)hipEventRecord(b, s);
+  (void)hipEventSynchronize(b);
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms / reps;
 }
 
 }  // namespace cc

@@ -1,0 +1,129 @@
+"""GPU parity of batched stepping: many meshes in one set of launches must give
+the single-mesh results, and (through them) the oracle's."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from ccscenes import batch_bars, tet_bar
+from oracle import solvers as S
+from oracle.basis import exact_basis, patch_basis
+from oracle.fem import Problem
+from oracle.timestep import step
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def cg():
+    import paper_2510_12053_amd.ccgpu as cg
+    cg.lib()
+    return cg
+
+
+@pytest.fixture(scope="module")
+def ctx(cg):
+    stream = torch.cuda.Stream(device=DEV)          # capturable (not the legacy null stream)
+    c = cg.cc_create(0, stream)
+    yield c
+    cg.cc_destroy(c)
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def _scenes():
+    """Uneven small bars: different sizes, stiffness, held faces and gravity."""
+    out = []
+    for k, (dims, E, face) in enumerate([((7, 3, 3), 1e5, 0), ((9, 4, 3), 1e6, 2),
+                                         ((6, 5, 4), 1e4, 5), ((11, 3, 3), 1e7, 1)]):
+        g = np.array([0.3 * k, -9.81, 0.5]) if k % 2 else np.array([0.0, -9.81, 0.0])
+        out.append(tet_bar(*dims, E=E, clamp_face=face, gravity=g))
+    return out
+
+
+def _setup(cg, ctx, scenes, kind):
+    mids, bases = [], []
+    for s in scenes:
+        p = Problem.from_scene(s)
+        B = exact_basis(p) if kind == "exact" else patch_basis(p, int(kind[1:]))
+        mid = cg.cc_mesh_upload(ctx, s.X, s.elems, s.fixed, s.E, s.nu, s.rho)
+        cg.cc_subspace_upload(ctx, mid, *B, s.dt)
+        mids.append(mid)
+        bases.append(B)
+    return mids, bases
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("sweep", [0, 1])
+@pytest.mark.parametrize("graph", [0, 3])
+def test_batch_equals_single_mesh(cg, ctx, prec, sweep, graph):
+    scenes = _scenes()
+    kind = "exact" if sweep == 0 else "R2"
+    mids, _ = _setup(cg, ctx, scenes, kind)
+    mids1, _ = _setup(cg, ctx, scenes, kind)
+    cg.cc_batch_tuning(ctx, 16, graph)
+    par = cg.cc_params_default(method=cg.METHOD_CC, sweep=sweep, hess_refresh=1, precision=prec,
+                               line_search=1 if sweep == 0 else 0, max_iters=300)
+    xs = [_t(s.initial_state()[0]) for s in scenes]
+    vs = [_t(s.initial_state()[1]) for s in scenes]
+    xs1 = [x.clone() for x in xs]
+    vs1 = [v.clone() for v in vs]
+    grav = np.stack([s.gravity for s in scenes])
+    for t in range(1, 4):
+        bcs = [_t(s.targets(t)) for s in scenes]
+        worst, its, rgs, sts = cg.cc_step_batch(ctx, mids, xs, vs, bcs, scenes[0].dt, par, 1e-7,
+                                                gravity=grav)
+        for k, s in enumerate(scenes):
+            par1 = cg.cc_params_default(method=cg.METHOD_CC, sweep=sweep, hess_refresh=1,
+                                        precision=prec, line_search=par.line_search, max_iters=300,
+                                        gravity=s.gravity)
+            st, it, rg = cg.cc_step(ctx, mids1[k], xs1[k], vs1[k], bcs[k], s.dt, par1, 1e-7)
+            # float64: same kernels and reduction orders; float32: lane counts of the
+            # update may differ between the two paths, so allow rounding-level drift
+            tol = 1e-10 if prec == 0 else 1e-4
+            assert sts[k] == st and abs(int(its[k]) - it) <= (0 if prec == 0 else 1), \
+                (k, t, sts[k], st, its[k], it)
+            a, b = xs[k].cpu().numpy(), xs1[k].cpu().numpy()
+            assert np.linalg.norm(a - b) <= tol * np.linalg.norm(b - s.X)
+
+
+def test_batch_against_oracle(cg, ctx):
+    scenes = _scenes()[:3]
+    mids, bases = _setup(cg, ctx, scenes, "exact")
+    cg.cc_batch_tuning(ctx, 32, 2)
+    par = cg.cc_params_default(method=cg.METHOD_CC, sweep=0, line_search=1, max_iters=300)
+    op = S.Params(method=S.CC, sweep=S.JACOBI, line_search=True, max_iters=300)
+    xs = [_t(s.initial_state()[0]) for s in scenes]
+    vs = [_t(s.initial_state()[1]) for s in scenes]
+    states = [s.initial_state() for s in scenes]
+    probs = [Problem.from_scene(s) for s in scenes]
+    for t in range(1, 3):
+        bcs = [_t(s.targets(t)) for s in scenes]
+        worst, its, rgs, sts = cg.cc_step_batch(ctx, mids, xs, vs, bcs, scenes[0].dt, par, 1e-6,
+                                                gravity=np.stack([s.gravity for s in scenes]))
+        assert worst == 0
+        for k, s in enumerate(scenes):
+            x, v = states[k]
+            x, v, res, _ = step(probs[k], x, v, s.targets(t), bases[k], op, 1e-6)
+            states[k] = (x, v)
+            assert its[k] == res.iters
+            xg = xs[k].cpu().numpy()
+            assert np.linalg.norm(xg - x) / np.linalg.norm(x - s.X) <= 1e-6
+
+
+def test_autotune_and_masking(cg, ctx):
+    scenes = batch_bars(count=5)
+    mids, _ = _setup(cg, ctx, scenes, "R1")
+    par = cg.cc_params_default(method=cg.METHOD_CC, sweep=0, line_search=1, max_iters=3)
+    lanes, ms = cg.cc_autotune_batch(ctx, mids, par)
+    assert lanes in (16, 32, 64) and all(v > 0 for v in ms.values())
+    xs = [_t(s.initial_state()[0]) for s in scenes]
+    vs = [_t(s.initial_state()[1]) for s in scenes]
+    worst, its, rgs, sts = cg.cc_step_batch(ctx, mids, xs, vs, None, scenes[0].dt, par, 1e-12,
+                                            gravity=np.stack([s.gravity for s in scenes]))
+    # iteration cap reached by every mesh, each masked at exactly the cap
+    assert np.all(its <= 3) and np.all((sts == cg.CC_NOT_CONVERGED) | (sts == cg.CC_STALLED))
+    assert all(np.isfinite(x.cpu().numpy()).all() for x in xs)

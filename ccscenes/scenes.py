@@ -174,3 +174,19 @@ def warm_start_eval_scene(seed, nx=81, ny=21, nz=21, n_steps=30):
     s.name = f"wseval{seed}"
     s.meta["seed"] = seed
     return s
+
+
+def mlp_init(seed=7, n_in=32, n_hid=64, n_out=16, n_used_in=16, n_used_out=3):
+    """Seeded initial parameters of the warm-start network, packed as
+    W1 (n_in x n_hid), b1, W2 (n_hid x n_hid), b2, W3 (n_hid x n_out), b3, all
+    row-major float64.  Scaled normal draws (variance 1/fan_in); padding rows
+    of W1 and padding columns of W3 are zero; biases zero; W3 scaled by 0.1 so
+    that the untrained proposal stays near the inertial predictor."""
+    rng = np.random.default_rng(seed)
+    W1 = np.zeros((n_in, n_hid))
+    W1[:n_used_in] = rng.normal(size=(n_used_in, n_hid)) / np.sqrt(n_used_in)
+    W2 = rng.normal(size=(n_hid, n_hid)) / np.sqrt(n_hid)
+    W3 = np.zeros((n_hid, n_out))
+    W3[:, :n_used_out] = 0.1 * rng.normal(size=(n_hid, n_used_out)) / np.sqrt(n_hid)
+    return np.concatenate([W1.ravel(), np.zeros(n_hid), W2.ravel(), np.zeros(n_hid), W3.ravel(),
+                           np.zeros(n_out)])

@@ -210,6 +210,52 @@ cc_status cc_probe_sweep(cc_ctx* ctx, int32_t mesh_id, const double* x, const do
                          double dt, const cc_params* params, double* energy, double* g,
                          double* dx);
 
+/* ---- learned warm start ----------------------------------------------------
+   A per-vertex network proposes the start state of a step: features f_i (16
+   values) of every free vertex at the inertial predictor x~ (relative
+   predictor displacement, h v, the step-Hessian diagonal block and strain
+   statistics of the incident elements), z-scored with stored statistics,
+   pass through a 32-64-64-16 SiLU network (BF16 MFMA products, FP32
+   accumulation) whose first three outputs Delta_i give x_i = x~_i + l Delta_i
+   (l: mean rest edge length).  With cc_params.warm_start = 1 cc_step and
+   cc_step_batch use the proposal only when E(proposal) < E(x~) (float64);
+   the convergence denominator stays |g(x~)|.  Not part of the paper: an
+   extension evaluated against plain CC. */
+#define CC_MLP_NPARAM 7312  /* packed float32 W1 32x64, b1 64, W2 64x64, b2 64,
+                               W3 64x16, b3 16, row-major ([in][out])             */
+#define CC_MLP_NFEAT  16
+
+/* Load parameters (host, CC_MLP_NPARAM floats) and normalisation (host,
+   16 means and 16 reciprocal standard deviations; NULL = 0 and 1); resets
+   the Adam state. */
+cc_status cc_mlp_set(cc_ctx* ctx, const float* params, const float* mean, const float* istd);
+/* Copy the current parameters and normalisation to host arrays (any NULL). */
+cc_status cc_mlp_get(cc_ctx* ctx, float* params, float* mean, float* istd);
+/* Set the normalisation from N feature rows X (device, N x 16). */
+cc_status cc_mlp_norm_from_data(cc_ctx* ctx, const float* X, int32_t N);
+/* Features of a 3D mesh for the step that starts at x, v (device n x 3) with
+   targets x_bc (device or NULL): feat (device, n_free x 16, one row per free
+   vertex in ascending caller id), x_tilde (device n x 3 predictor with
+   targets, or NULL), *ell (host, or NULL). */
+cc_status cc_mlp_features(cc_ctx* ctx, int32_t mesh_id, const double* x, const double* v,
+                          const double* x_bc, double dt, float* feat, double* x_tilde, double* ell);
+/* Training targets T (device, n_free x 3, rows as in cc_mlp_features):
+   (x_new - x_tilde) / l for the free vertices (x_new, x_tilde: device n x 3). */
+cc_status cc_mlp_targets(cc_ctx* ctx, int32_t mesh_id, const double* x_new, const double* x_tilde,
+                         float* T);
+/* Network outputs Y (device, B x 3) for raw feature rows X (device, B x 16). */
+cc_status cc_mlp_forward(cc_ctx* ctx, const float* X, int32_t B, float* Y);
+/* Mean-squared-error gradient over the rows idx[0..B) (device int32) of X
+   (device N x 16) against targets T (device N x 3): grad (device,
+   CC_MLP_NPARAM floats, or NULL to keep it internal), *loss (host, or NULL). */
+cc_status cc_mlp_gradient(cc_ctx* ctx, const float* X, const float* T, const int32_t* idx, int32_t B,
+                          float* grad, float* loss);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8) with gradient grad (device). */
+cc_status cc_mlp_adam(cc_ctx* ctx, const float* grad, float lr);
+/* cc_mlp_gradient followed by cc_mlp_adam on the same rows. */
+cc_status cc_mlp_train_step(cc_ctx* ctx, const float* X, const float* T, const int32_t* idx, int32_t B,
+                            float lr, float* loss);
+
 /* ---- measurement --------------------------------------------------------- */
 
 /* Kernel identifiers for cc_profile_*. */

@@ -286,3 +286,111 @@ def cc_autotune_batch(ctx, mesh_ids, params):
     _check(ctx, lib().cc_autotune_batch(ctx.handle, len(ids), _ptr(ids), ctypes.byref(params),
                                         ctypes.byref(lanes), _ptr(ms)))
     return lanes.value, dict(zip((16, 32, 64), ms.tolist()))
+
+
+# ---- learned warm start -----------------------------------------------------
+MLP_NPARAM = 7312
+MLP_NFEAT = 16
+
+
+def _mlp_sig(L):
+    P, I32, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    sig = {
+        "cc_mlp_set": (I32, [P, P, P, P]),
+        "cc_mlp_get": (I32, [P, P, P, P]),
+        "cc_mlp_norm_from_data": (I32, [P, P, I32]),
+        "cc_mlp_features": (I32, [P, I32, P, P, P, D, P, P, ctypes.POINTER(D)]),
+        "cc_mlp_forward": (I32, [P, P, I32, P]),
+        "cc_mlp_gradient": (I32, [P, P, P, P, I32, P, ctypes.POINTER(ctypes.c_float)]),
+        "cc_mlp_adam": (I32, [P, P, ctypes.c_float]),
+        "cc_mlp_train_step": (I32, [P, P, P, P, I32, ctypes.c_float, ctypes.POINTER(ctypes.c_float)]),
+        "cc_mlp_targets": (I32, [P, I32, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+
+
+def _ml():
+    L = lib()
+    if not getattr(L, "_mlp_sig_done", False):
+        _mlp_sig(L)
+        L._mlp_sig_done = True
+    return L
+
+
+def cc_mlp_set(ctx, params, mean=None, istd=None):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    assert p.size == MLP_NPARAM
+    m = None if mean is None else np.ascontiguousarray(mean, dtype=np.float32)
+    s = None if istd is None else np.ascontiguousarray(istd, dtype=np.float32)
+    _check(ctx, _ml().cc_mlp_set(ctx.handle, _ptr(p), None if m is None else _ptr(m),
+                                 None if s is None else _ptr(s)))
+
+
+def cc_mlp_get(ctx):
+    p = np.empty(MLP_NPARAM, dtype=np.float32)
+    m = np.empty(MLP_NFEAT, dtype=np.float32)
+    s = np.empty(MLP_NFEAT, dtype=np.float32)
+    _check(ctx, _ml().cc_mlp_get(ctx.handle, _ptr(p), _ptr(m), _ptr(s)))
+    return p, m, s
+
+
+def cc_mlp_norm_from_data(ctx, X):
+    _check(ctx, _ml().cc_mlp_norm_from_data(ctx.handle, _dptr(X, "float32"), X.shape[0]))
+
+
+def cc_mlp_features(ctx, mesh_id, x, v, x_bc, dt, n_free, out=None):
+    """Returns (feat (n_free,16) float32 CUDA tensor, x_tilde (n,3) float64, ell).
+    out: optional preallocated (n_free,16) float32 tensor (e.g. a view into a
+    dataset)."""
+    import torch
+    feat = out if out is not None else torch.zeros((n_free, MLP_NFEAT), dtype=torch.float32,
+                                                   device=x.device)
+    xt = torch.empty_like(x)
+    ell = ctypes.c_double(0)
+    _check(ctx, _ml().cc_mlp_features(ctx.handle, mesh_id, _dptr(x), _dptr(v), _dptr(x_bc), dt,
+                                      _dptr(feat, "float32"), _dptr(xt), ctypes.byref(ell)))
+    return feat, xt, ell.value
+
+
+def cc_mlp_forward(ctx, X):
+    import torch
+    Y = torch.empty((X.shape[0], 3), dtype=torch.float32, device=X.device)
+    _check(ctx, _ml().cc_mlp_forward(ctx.handle, _dptr(X, "float32"), X.shape[0], _dptr(Y, "float32")))
+    return Y
+
+
+def cc_mlp_gradient(ctx, X, T, idx):
+    import torch
+    g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=X.device)
+    loss = ctypes.c_float(0)
+    _check(ctx, _ml().cc_mlp_gradient(ctx.handle, _dptr(X, "float32"), _dptr(T, "float32"),
+                                      _dptr(idx, "int32"), idx.shape[0], _dptr(g, "float32"),
+                                      ctypes.byref(loss)))
+    return g, loss.value
+
+
+def cc_mlp_adam(ctx, grad, lr):
+    _check(ctx, _ml().cc_mlp_adam(ctx.handle, _dptr(grad, "float32"), lr))
+
+
+def cc_mlp_train_step(ctx, X, T, idx, lr):
+    loss = ctypes.c_float(0)
+    _check(ctx, _ml().cc_mlp_train_step(ctx.handle, _dptr(X, "float32"), _dptr(T, "float32"),
+                                        _dptr(idx, "int32"), idx.shape[0], lr, ctypes.byref(loss)))
+    return loss.value
+
+
+def cc_mlp_targets(ctx, mesh_id, x_new, x_tilde, n_free, out=None):
+    import torch
+    T = out if out is not None else torch.zeros((n_free, 3), dtype=torch.float32, device=x_new.device)
+    L = _ml()
+    if not hasattr(L, "_tgt_sig"):
+        L.cc_mlp_targets.restype = ctypes.c_int32
+        L.cc_mlp_targets.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p]
+        L._tgt_sig = True
+    _check(ctx, L.cc_mlp_targets(ctx.handle, mesh_id, _dptr(x_new), _dptr(x_tilde), _dptr(T, "float32")))
+    return T

@@ -11,6 +11,7 @@
 
 #include "../../include/ccgpu.h"
 #include "cc_kernels.h"
+#include "cc_mlp.h"
 
 using cc::Material;
 using cc::MeshView;
@@ -55,6 +56,13 @@ struct Mesh {
   double last_E = 0, last_paper = 0;
   long long last_fb[3] = {0, 0, 0}, last_halvings = 0;
   int last_warm = 0;
+  // warm start: all mesh neighbours of free vertices (internal ids), rest
+  // positions (SoA), mean rest edge length, feature and output scratch
+  int *nptr = nullptr, *nidx = nullptr;
+  int* frank = nullptr;  // rank of each internal free vertex among free caller ids
+  double* Xr = nullptr;
+  double ell = 0;
+  float *feat = nullptr, *delta = nullptr;
 
   MeshView view() const {
     MeshView v{};
@@ -118,6 +126,7 @@ void free_mesh(Mesh& M) {
   dfree(M.x); dfree(M.xt); dfree(M.x0); dfree(M.xtrial); dfree(M.dvec); dfree(M.g);
   dfree(M.partials); dfree(M.scal); dfree(M.estore); dfree(M.hb); dfree(M.KL); dfree(M.fb);
   dfree(M.bad);
+  dfree(M.nptr); dfree(M.nidx); dfree(M.frank); dfree(M.Xr); dfree(M.feat); dfree(M.delta);
 }
 
 }  // namespace
@@ -128,6 +137,9 @@ struct cc_ctx {
   std::string err;
   std::vector<Mesh*> meshes;
   double* pinned = nullptr;  // host pinned scalars
+  cc::MlpState mlp;          // learned warm start
+  float *bfeat = nullptr, *bdelta = nullptr;  // batch-wide feature / output rows
+  size_t bcap = 0;
   // kernel timing (cc_profile_*)
   int prof_mask = 0;
   double prof_ms[CC_K_COUNT] = {0};
@@ -398,6 +410,50 @@ void build_mesh(cc_ctx* ctx, Mesh& M) {
   M.d_vperm = dupload(M.vperm, s);
   M.d_vinv = dupload(M.vinv, s);
   M.d_eperm = dupload(M.eperm, s);
+  {  // warm-start data: all neighbours, rest positions, mean rest edge length
+    std::vector<std::vector<int>> alln(nf);
+    double esum = 0;
+    long long ecnt = 0;
+    for (int e = 0; e < m; ++e)
+      for (int a = 0; a < K; ++a)
+        for (int b = 0; b < K; ++b) {
+          const int va = M.elems[e * K + a], vb = M.elems[e * K + b];
+          if (a < b) {
+            double l2 = 0;
+            for (int c = 0; c < D; ++c) {
+              const double dd = M.X[(size_t)va * D + c] - M.X[(size_t)vb * D + c];
+              l2 += dd * dd;
+            }
+            esum += std::sqrt(l2);
+            ++ecnt;
+          }
+          if (a != b && !M.fixed[va]) alln[M.vinv[va]].push_back(M.vinv[vb]);
+        }
+    M.ell = ecnt ? esum / ecnt : 1.0;
+    std::vector<int> nptr(nf + 1, 0), nidx;
+    for (int j = 0; j < nf; ++j) {
+      auto& l = alln[j];
+      std::sort(l.begin(), l.end());
+      l.erase(std::unique(l.begin(), l.end()), l.end());
+      nidx.insert(nidx.end(), l.begin(), l.end());
+      nptr[j + 1] = (int)nidx.size();
+    }
+    M.nptr = dupload(nptr, s);
+    M.nidx = dupload(nidx, s);
+    std::vector<double> Xr((size_t)D * n);
+    for (int v = 0; v < n; ++v)
+      for (int c = 0; c < D; ++c) Xr[(size_t)c * n + v] = M.X[(size_t)M.vperm[v] * D + c];
+    M.Xr = dupload(Xr, s);
+    std::vector<int> frank(nf);
+    {
+      int r = 0;
+      for (int u = 0; u < n; ++u)
+        if (!M.fixed[u]) frank[M.vinv[u]] = r++;
+    }
+    M.frank = dupload(frank, s);
+    M.feat = dalloc<float>((size_t)std::max(nf, 1) * 16);
+    M.delta = dalloc<float>((size_t)std::max(nf, 1) * 3);
+  }
   // work buffers
   const size_t nd = (size_t)D * n;
   M.x = dalloc<double>(nd); M.xt = dalloc<double>(nd); M.x0 = dalloc<double>(nd);
@@ -793,6 +849,13 @@ void cc_destroy(cc_ctx* ctx) {
   if (ctx->plan) cc::batch_plan_destroy(ctx->plan);
   ctx->harvest();
   ctx->drop_graph_pairs();
+  {
+    cc::MlpState& q = ctx->mlp;
+    dfree(q.W); dfree(q.m); dfree(q.v); dfree(q.grad); dfree(q.part); dfree(q.lpart); dfree(q.loss);
+    dfree(q.W1b); dfree(q.W2b); dfree(q.W3b); dfree(q.mean); dfree(q.istd);
+  }
+  dfree(ctx->bfeat);
+  dfree(ctx->bdelta);
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   delete ctx;
 }
@@ -925,6 +988,9 @@ static cc_status check_params(cc_ctx* ctx, const cc_params* p, const Mesh& M, do
     return fail(ctx, CC_E_STATE, "method needs a basis: call cc_subspace_upload or cc_subspace_build");
   for (int c = 0; c < 3; ++c)
     if (!std::isfinite(p->gravity[c])) return fail(ctx, CC_E_NONFINITE, "non-finite gravity");
+  if (p->warm_start != 0 && p->warm_start != 1) return fail(ctx, CC_E_INVALID_ARG, "bad warm_start");
+  if (p->warm_start && (!ctx->mlp.set || M.D != 3 || p->quasistatic))
+    return fail(ctx, CC_E_STATE, "warm start needs cc_mlp_set and a dynamic 3D mesh");
   return CC_OK;
 }
 
@@ -958,8 +1024,23 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
     int k = 0;
     long long halvings = 0;
     cc_status result = CC_OK;
+    int warm = 0;
     if (g0 > 0) {
       r = 1.0;
+      if (p.warm_start) {
+        // learned proposal at the predictor, kept only if it lowers E
+        cc::launch_features(S.mv, M.x, M.x0, h, M.E, M.mu, M.lam, M.ell, M.nptr, M.nidx, M.Xr, M.feat, nullptr, s);
+        cc::mlp_forward(ctx->mlp, M.feat, M.nf, M.delta, s);
+        cc::launch_proposal(M.n, M.nf, M.x, M.delta, M.ell, M.xtrial, s);
+        const double E0 = S.energy(M.x), Ep = S.energy(M.xtrial);
+        if (Ep < E0) {
+          std::swap(M.x, M.xtrial);
+          warm = 1;
+          r = std::sqrt(S.grad_norm2(M.x)) / g0;
+        } else {
+          (void)S.grad_norm2(M.x);  // g at the predictor for the first iteration
+        }
+      }
       if (p.line_search) Ecur = S.energy(M.x);
       while (r > tol && k < p.max_iters) {
         S.sweep(M.x, M.xtrial, p.method);
@@ -1020,7 +1101,7 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
     HIPC(hipStreamSynchronize(s));
     ctx->harvest();
     for (int c = 0; c < 3; ++c) M.last_fb[c] = (long long)fbh[c];
-    M.last_warm = 0;
+    M.last_warm = warm;
     if (iters) *iters = k;
     if (rel_grad) *rel_grad = r;
     return result;
@@ -1102,6 +1183,7 @@ static cc::BatchItem make_item(Mesh& M, const Material& mat) {
   it.estore = M.estore; it.hb = M.hb; it.KL = M.KL;
   it.partials = M.partials;
   it.fb = M.fb;
+  it.nptr = M.nptr; it.nidx = M.nidx; it.Xr = M.Xr; it.ell = M.ell; it.youngs = M.E;
   it.ncol = M.ncol;
   for (int c = 0; c <= M.ncol && c <= cc::MAX_COLOURS; ++c) it.coff[c] = M.coff[c];
   return it;
@@ -1259,6 +1341,8 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
       for (int c = 0; c < 3; ++c) mat.grav[c] = gravity ? gravity[3 * i + c] : p.gravity[c];
       items[i] = make_item(M, mat);
       items[i].prep_dense = (p.method != CC_METHOD_CD && use_dense_lds(M, p.precision)) ? 1 : 0;
+      items[i].feat_off = 0;
+      for (int q = 0; q < i; ++q) items[i].feat_off += ms[q]->nf;
       items[i].xu = x[i];
       items[i].vu = v[i];
       items[i].xbc = x_bc ? x_bc[i] : nullptr;
@@ -1275,6 +1359,18 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
       ctx->hook_on = want_hook;
     }
     cc::batch_begin(plan, s);
+    if (p.warm_start) {
+      size_t rows = 0;
+      for (int i = 0; i < n; ++i) rows += ms[i]->nf;
+      if (rows > ctx->bcap) {
+        dfree(ctx->bfeat);
+        dfree(ctx->bdelta);
+        ctx->bfeat = dalloc<float>(rows * 16);
+        ctx->bdelta = dalloc<float>(rows * 3);
+        ctx->bcap = rows;
+      }
+      cc::batch_warm_start(plan, ctx->mlp, ctx->bfeat, ctx->bdelta, (int)rows, s);
+    }
     std::vector<cc::BatchCtl> ctl(n);
     const int k = std::max(1, ctx->batch_iters_per_graph);
     auto pull_ctl = [&]() {
@@ -1327,7 +1423,7 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
       if (status) status[i] = stt;
       M.last_E = ctl[i].E_cur;
       M.last_paper = 0;
-      M.last_warm = 0;
+      M.last_warm = ctl[i].warm;
       if (stt < 0 ? (worst >= 0 || stt < worst) : (worst >= 0 && stt > worst)) worst = stt;
     }
     return worst;
@@ -1380,6 +1476,166 @@ cc_status cc_autotune_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, con
     ctx->plan = nullptr;
     ctx->plan_ids.clear();
     if (lanes_out) *lanes_out = bestG;
+    return CC_OK;
+  });
+}
+
+
+// ---- learned warm start -------------------------------------------------------
+static void mlp_alloc(cc_ctx* ctx) {
+  cc::MlpState& q = ctx->mlp;
+  if (q.W) return;
+  q.W = dalloc<float>(cc::MLP_NPARAM);
+  q.m = dalloc<float>(cc::MLP_NPARAM);
+  q.v = dalloc<float>(cc::MLP_NPARAM);
+  q.grad = dalloc<float>(cc::MLP_NPARAM);
+  q.part = dalloc<float>((size_t)cc::MLP_MAX_BLOCKS * 4 * cc::MLP_NPARAM);
+  q.lpart = dalloc<float>((size_t)cc::MLP_MAX_BLOCKS * 4);
+  q.loss = dalloc<float>(1);
+  q.W1b = dalloc<uint16_t>(cc::MLP_IN_PAD * cc::MLP_HID);
+  q.W2b = dalloc<uint16_t>(cc::MLP_HID * cc::MLP_HID);
+  q.W3b = dalloc<uint16_t>(cc::MLP_HID * cc::MLP_OUT);
+  q.mean = dalloc<float>(cc::MLP_IN);
+  q.istd = dalloc<float>(cc::MLP_IN);
+}
+
+static cc_status mlp_ready(cc_ctx* ctx) {
+  if (!ctx->mlp.set) return fail(ctx, CC_E_STATE, "no network: call cc_mlp_set first");
+  return CC_OK;
+}
+
+cc_status cc_mlp_set(cc_ctx* ctx, const float* params, const float* mean, const float* istd) {
+  return guarded(ctx, [&]() -> cc_status {
+    if (!params) return fail(ctx, CC_E_INVALID_ARG, "null parameters");
+    for (int k = 0; k < cc::MLP_NPARAM; ++k)
+      if (!std::isfinite(params[k])) return fail(ctx, CC_E_NONFINITE, "non-finite parameter");
+    mlp_alloc(ctx);
+    cc::MlpState& q = ctx->mlp;
+    hipStream_t s = ctx->stream;
+    HIPC(hipMemcpyAsync(q.W, params, cc::MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
+    HIPC(hipMemsetAsync(q.m, 0, cc::MLP_NPARAM * sizeof(float), s));
+    HIPC(hipMemsetAsync(q.v, 0, cc::MLP_NPARAM * sizeof(float), s));
+    std::vector<float> mu(cc::MLP_IN, 0.f), is(cc::MLP_IN, 1.f);
+    if (mean) mu.assign(mean, mean + cc::MLP_IN);
+    if (istd) is.assign(istd, istd + cc::MLP_IN);
+    HIPC(hipMemcpyAsync(q.mean, mu.data(), cc::MLP_IN * sizeof(float), hipMemcpyHostToDevice, s));
+    HIPC(hipMemcpyAsync(q.istd, is.data(), cc::MLP_IN * sizeof(float), hipMemcpyHostToDevice, s));
+    cc::mlp_refresh_bf16(q, s);
+    HIPC(hipStreamSynchronize(s));
+    q.t = 0;
+    q.set = true;
+    return CC_OK;
+  });
+}
+
+cc_status cc_mlp_get(cc_ctx* ctx, float* params, float* mean, float* istd) {
+  return guarded(ctx, [&]() -> cc_status {
+    cc_status st = mlp_ready(ctx);
+    if (st != CC_OK) return st;
+    cc::MlpState& q = ctx->mlp;
+    hipStream_t s = ctx->stream;
+    if (params) HIPC(hipMemcpyAsync(params, q.W, cc::MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
+    if (mean) HIPC(hipMemcpyAsync(mean, q.mean, cc::MLP_IN * sizeof(float), hipMemcpyDeviceToHost, s));
+    if (istd) HIPC(hipMemcpyAsync(istd, q.istd, cc::MLP_IN * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    return CC_OK;
+  });
+}
+
+cc_status cc_mlp_norm_from_data(cc_ctx* ctx, const float* X, int32_t N) {
+  return guarded(ctx, [&]() -> cc_status {
+    cc_status st = mlp_ready(ctx);
+    if (st != CC_OK) return st;
+    if (!X || N <= 0) return fail(ctx, CC_E_INVALID_ARG, "empty feature set");
+    cc::mlp_stats(ctx->mlp, X, N, ctx->stream);
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return CC_OK;
+  });
+}
+
+cc_status cc_mlp_features(cc_ctx* ctx, int32_t mesh_id, const double* x, const double* v, const double* x_bc,
+                          double dt, float* feat, double* x_tilde, double* ell) {
+  return guarded(ctx, [&]() -> cc_status {
+    Mesh& M = get_mesh(ctx, mesh_id);
+    if (M.D != 3) return fail(ctx, CC_E_INVALID_ARG, "features are defined for 3D meshes");
+    if (!x || !v || !feat || !(dt > 0)) return fail(ctx, CC_E_INVALID_ARG, "bad feature arguments");
+    hipStream_t s = ctx->stream;
+    MeshView mv = M.view();
+    HIPC(hipMemsetAsync(M.bad, 0, sizeof(int), s));
+    cc::launch_predict(mv, M.d_vperm, x, v, x_bc, dt, 0, M.x, M.xt, M.x0, M.bad, s);
+    cc::launch_features(mv, M.x, M.x0, dt, M.E, M.mu, M.lam, M.ell, M.nptr, M.nidx, M.Xr, feat, M.frank, s);
+    if (x_tilde) cc::launch_scatter_user(mv, M.d_vperm, M.x, x_tilde, 0, s);
+    if (ell) *ell = M.ell;
+    int bad = 0;
+    HIPC(hipMemcpyAsync(&bad, M.bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (bad) return fail(ctx, CC_E_NONFINITE, "non-finite x, v or x_bc");
+    return CC_OK;
+  });
+}
+
+cc_status cc_mlp_forward(cc_ctx* ctx, const float* X, int32_t B, float* Y) {
+  return guarded(ctx, [&]() -> cc_status {
+    cc_status st = mlp_ready(ctx);
+    if (st != CC_OK) return st;
+    if (B < 0 || (B > 0 && (!X || !Y))) return fail(ctx, CC_E_INVALID_ARG, "bad forward arguments");
+    cc::mlp_forward(ctx->mlp, X, B, Y, ctx->stream);
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return CC_OK;
+  });
+}
+
+cc_status cc_mlp_gradient(cc_ctx* ctx, const float* X, const float* T, const int32_t* idx, int32_t B,
+                          float* grad, float* loss) {
+  return guarded(ctx, [&]() -> cc_status {
+    cc_status st = mlp_ready(ctx);
+    if (st != CC_OK) return st;
+    if (B <= 0 || !X || !T || !idx) return fail(ctx, CC_E_INVALID_ARG, "bad gradient arguments");
+    cc::MlpState& q = ctx->mlp;
+    cc::mlp_gradient(q, X, T, idx, B, grad ? grad : q.grad, q.loss, ctx->stream);
+    float l = 0.f;
+    HIPC(hipMemcpyAsync(&l, q.loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    if (loss) *loss = l;
+    return CC_OK;
+  });
+}
+
+cc_status cc_mlp_adam(cc_ctx* ctx, const float* grad, float lr) {
+  return guarded(ctx, [&]() -> cc_status {
+    cc_status st = mlp_ready(ctx);
+    if (st != CC_OK) return st;
+    if (!grad || !(lr > 0)) return fail(ctx, CC_E_INVALID_ARG, "bad Adam arguments");
+    cc::mlp_adam(ctx->mlp, grad, lr, ctx->stream);
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return CC_OK;
+  });
+}
+
+cc_status cc_mlp_train_step(cc_ctx* ctx, const float* X, const float* T, const int32_t* idx, int32_t B,
+                            float lr, float* loss) {
+  return guarded(ctx, [&]() -> cc_status {
+    cc_status st = mlp_ready(ctx);
+    if (st != CC_OK) return st;
+    if (B <= 0 || !X || !T || !idx || !(lr > 0)) return fail(ctx, CC_E_INVALID_ARG, "bad training arguments");
+    cc::MlpState& q = ctx->mlp;
+    cc::mlp_gradient(q, X, T, idx, B, q.grad, q.loss, ctx->stream);
+    cc::mlp_adam(q, q.grad, lr, ctx->stream);
+    if (loss) {
+      HIPC(hipMemcpyAsync(loss, q.loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+      HIPC(hipStreamSynchronize(ctx->stream));
+    }
+    return CC_OK;
+  });
+}
+
+
+cc_status cc_mlp_targets(cc_ctx* ctx, int32_t mesh_id, const double* x_new, const double* x_tilde, float* T) {
+  return guarded(ctx, [&]() -> cc_status {
+    Mesh& M = get_mesh(ctx, mesh_id);
+    if (M.D != 3 || !x_new || !x_tilde || !T) return fail(ctx, CC_E_INVALID_ARG, "bad target arguments");
+    cc::launch_targets(M.view(), x_new, x_tilde, M.ell, M.frank, T, ctx->stream);
+    HIPC(hipStreamSynchronize(ctx->stream));
     return CC_OK;
   });
 }

@@ -531,4 +531,13 @@ __device__ void cc_finish(const MeshView& mv, int method, int i, bool empty, con
 }
 
 
+__device__ __forceinline__ int block_mesh(const int* __restrict__ boff, int nmesh, int b) {
+  int lo = 0, hi = nmesh;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (boff[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 }  // namespace cc

@@ -90,6 +90,13 @@ struct BatchItem {
   int prep_dense;      // 1: exact-basis condensation with the basis row in LDS
   int ncol;
   int coff[MAX_COLOURS + 1];
+  // warm start: mesh neighbours (all vertices), rest positions, scales and
+  // this mesh's first row in the batch-wide feature / output buffers
+  const int* nptr;
+  const int* nidx;
+  const double* Xr;
+  double ell, youngs;
+  int feat_off;
 };
 
 // Per-mesh iteration state, device-resident.
@@ -99,7 +106,7 @@ struct BatchCtl {
   int status;          // CC_OK / CC_NOT_CONVERGED / CC_STALLED, -100 while running
   int needs_host;      // 1: energy rose at alpha = 1, backtracking left to the host
   int bad;             // non-finite input seen by the predictor
-  int pad;
+  int warm;            // 1: the learned proposal was accepted
   double E_cur, E_trial, g0, gn2, r;
 };
 
@@ -124,6 +131,20 @@ void batch_begin(BatchPlan* p, hipStream_t s);
 void batch_iterate(BatchPlan* p, int iters, hipStream_t s);
 // Velocities and caller positions.
 void batch_finish(BatchPlan* p, hipStream_t s);
+// Learned warm start after batch_begin: feat / delta hold sum(nf) rows.
+struct MlpState;
+struct BatchGrid {
+  int nmesh, pred_blocks;
+  const int* pred_off;  // block offsets of the per-vertex launches
+  double tol;
+  int max_iters;
+};
+BatchGrid batch_grid(BatchPlan* p);
+void batch_energy_trial(BatchPlan* p, hipStream_t s);   // ctl.E_trial = E(xtrial)
+void batch_energy_x(BatchPlan* p, hipStream_t s);       // ctl.E_cur = E(x)
+void batch_gradient_x(BatchPlan* p, hipStream_t s);     // g(x), ctl.gn2
+void batch_warm_start(BatchPlan* p, const MlpState& net, float* feat, float* delta, int rows,
+                      hipStream_t s);
 // Time one condensation + update pass of every mesh with the given lane count.
 float batch_time_prep_update(BatchPlan* p, int G, int reps, hipStream_t s);
 void batch_set_lanes(BatchPlan* p, int G);

@@ -243,14 +243,49 @@ __device__ __forceinline__ void prep_dense_body(const MeshView& mv, int method, 
 #pragma unroll
   for (int r = 0; r < DD; ++r) A[r] = Ht[r] = T(0);
   if (method != 0) {
-    for (int a = threadIdx.x; a < cnt; a += WG) {
-      const int j = a < i ? a : a + 1;
-      T Uj[DD];
+    // consecutive lanes take consecutive blocks (j, k) of the whole block
+    // matrix, so the Hessian streams coalesced while U_j, U_k come from LDS
+    for (int t = threadIdx.x; t < mv.nnzb; t += WG) {
+      const int j = mv.blkrow[t];
+      if (j == i) continue;                       // row i is not in the complement
+      const int k = mv.colidx[t];
+      const T* Uj = Us + (size_t)(j < i ? j : j - 1) * DD;
+      const T* H = hb + (size_t)t * DD;
+      T Hl[DD];
 #pragma unroll
-      for (int r = 0; r < DD; ++r) Uj[r] = Us[a * DD + r];
-      accum_row<T, D>(mv, i, j, Uj, hb, [&](int k) -> const T* {
-        return Us + (size_t)(k < i ? k : k - 1) * DD;
-      }, A, Ht);
+      for (int r = 0; r < DD; ++r) Hl[r] = H[r];
+      if (k == i) {                               // A += H_ji^T U_j
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+          for (int s = 0; s < D; ++s) {
+            T acc = T(0);
+#pragma unroll
+            for (int l = 0; l < D; ++l) acc += Hl[l * D + r] * Uj[l * D + s];
+            A[r * D + s] += acc;
+          }
+        continue;
+      }
+      const T* Uk = Us + (size_t)(k < i ? k : k - 1) * DD;
+      T M[DD];
+#pragma unroll
+      for (int r = 0; r < D; ++r)                 // M = H_jk U_k
+#pragma unroll
+        for (int s = 0; s < D; ++s) {
+          T acc = T(0);
+#pragma unroll
+          for (int l = 0; l < D; ++l) acc += Hl[r * D + l] * Uk[l * D + s];
+          M[r * D + s] = acc;
+        }
+#pragma unroll
+      for (int r = 0; r < D; ++r)                 // Ht += U_j^T M
+#pragma unroll
+        for (int s = 0; s < D; ++s) {
+          T acc = T(0);
+#pragma unroll
+          for (int l = 0; l < D; ++l) acc += Uj[l * D + r] * M[l * D + s];
+          Ht[r * D + s] += acc;
+        }
     }
   }
 #pragma unroll
@@ -692,14 +727,6 @@ void launch_scatter_user(const MeshView& mv, const int* vperm, const double* src
 // launches stays valid while meshes finish at different iterations.
 namespace cc {
 
-__device__ __forceinline__ int block_mesh(const int* __restrict__ boff, int nmesh, int b) {
-  int lo = 0, hi = nmesh;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (boff[mid] <= b) lo = mid; else hi = mid;
-  }
-  return lo;
-}
 
 __device__ __forceinline__ const double* pick(const BatchItem& it, int which) {
   return which ? it.xtrial : it.x;
@@ -1203,6 +1230,26 @@ void batch_iterate(BatchPlan* p, int iters, hipStream_t s) {
     }
   }
   for (int done = 0; done < iters; done += k) (void)hipGraphLaunch(p->exec, s);
+}
+
+// Pieces of the batched path used by the warm start (cc_mlp.hip).
+void batch_energy_trial(BatchPlan* p, hipStream_t s) {
+  if (p->cfg.D == 3) b_energy<3>(p, 1, 0, s); else b_energy<2>(p, 1, 0, s);
+}
+void batch_gradient_x(BatchPlan* p, hipStream_t s) {
+  if (p->cfg.D == 3) b_gradient<3>(p, 0, s); else b_gradient<2>(p, 0, s);
+}
+void batch_energy_x(BatchPlan* p, hipStream_t s) {
+  if (p->cfg.D == 3) b_energy<3>(p, 0, 2, s); else b_energy<2>(p, 0, 2, s);
+}
+BatchGrid batch_grid(BatchPlan* p) {
+  BatchGrid g;
+  g.nmesh = p->nmesh;
+  g.pred_blocks = gridn(p->pred);
+  g.pred_off = p->pred.d;
+  g.tol = p->cfg.tol;
+  g.max_iters = p->cfg.max_iters;
+  return g;
 }
 
 void batch_finish(BatchPlan* p, hipStream_t s) {

@@ -1,0 +1,197 @@
+"""GPU parity of the learned warm start: BF16 MFMA forward/backward against the
+FP64 oracle on BF16-rounded operands, Adam, features, training and the
+acceptance rule."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from ccscenes import mlp_init, tet_bar, warm_start_train_scene
+from oracle import mlp as M
+from oracle import solvers as S
+from oracle.basis import exact_basis
+from oracle.fem import Problem
+from oracle.timestep import predictor, step
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def cg():
+    import paper_2510_12053_amd.ccgpu as cg
+    cg.lib()
+    return cg
+
+
+@pytest.fixture(scope="module")
+def ctx(cg):
+    c = cg.cc_create(0, torch.cuda.Stream(device=DEV))
+    yield c
+    cg.cc_destroy(c)
+
+
+def bf16(a):
+    """Round float64/float32 values to bfloat16 (nearest even), back to float64."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def _oracle_bf16_params(theta):
+    p = M.unpack(np.asarray(theta, dtype=np.float64))
+    for k in ("W1", "W2", "W3"):
+        p[k] = bf16(p[k])
+    p = {k: (v if k.startswith("W") else np.asarray(v, np.float32).astype(np.float64)) for k, v in p.items()}
+    return p
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def _setup_net(cg, ctx, seed):
+    rng = np.random.default_rng(seed)
+    theta = (mlp_init(3) + 0.05 * rng.normal(size=M.N_PARAMS)).astype(np.float32)
+    mean = rng.normal(size=16).astype(np.float32)
+    istd = rng.uniform(0.5, 2.0, size=16).astype(np.float32)
+    cg.cc_mlp_set(ctx, theta, mean, istd)
+    return rng, theta, mean, istd
+
+
+def test_forward_matches_oracle(cg, ctx):
+    rng, theta, mean, istd = _setup_net(cg, ctx, 0)
+    for B in (1, 16, 37, 1000):
+        X = rng.normal(size=(B, 16)).astype(np.float32)
+        Y = cg.cc_mlp_forward(ctx, torch.tensor(X, device=DEV)).cpu().numpy()
+        Xn = np.zeros((B, 32))
+        Xn[:, :16] = bf16((X - mean) * istd)
+        Yo, _ = M.forward(_oracle_bf16_params(theta), Xn)
+        assert _rel(Y, Yo[:, :3]) <= 2e-2, B
+
+
+def test_gradient_matches_oracle(cg, ctx):
+    rng, theta, mean, istd = _setup_net(cg, ctx, 1)
+    N, B = 900, 700
+    X = rng.normal(size=(N, 16)).astype(np.float32)
+    T = rng.normal(size=(N, 3)).astype(np.float32)
+    idx = rng.choice(N, size=B, replace=False).astype(np.int32)
+    g, loss = cg.cc_mlp_gradient(ctx, torch.tensor(X, device=DEV), torch.tensor(T, device=DEV),
+                                 torch.tensor(idx, device=DEV))
+    g = g.cpu().numpy().astype(np.float64)
+    Xn = np.zeros((B, 32))
+    Xn[:, :16] = bf16((X[idx] - mean) * istd)
+    p = _oracle_bf16_params(theta)
+    Y, cache = M.forward(p, Xn)
+    lo, dY = M.loss_and_dY(Y, T[idx].astype(np.float64))
+    go = M.backward(p, cache, dY)
+    assert abs(loss - lo) <= 2e-2 * lo
+    gu, gou = M.unpack(g), M.unpack(go)
+    for k in gu:
+        assert _rel(gu[k], gou[k]) <= 3e-2, k
+    assert np.all(gu["W1"][16:] == 0.0)
+
+
+def test_adam_matches_oracle(cg, ctx):
+    rng, theta, mean, istd = _setup_net(cg, ctx, 2)
+    th = theta.astype(np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    for t in range(1, 4):
+        g = rng.normal(size=M.N_PARAMS).astype(np.float32)
+        cg.cc_mlp_adam(ctx, torch.tensor(g, device=DEV), 1e-2)
+        th, m, v = M.adam(th, g.astype(np.float64), m, v, t, lr=1e-2)
+    got, _, _ = cg.cc_mlp_get(ctx)
+    assert np.max(np.abs(got - th)) <= 1e-5
+
+
+def test_features_match_oracle(cg, ctx):
+    s = tet_bar(8, 4, 4, E=3e5, twist_per_step=0.05)
+    p = Problem.from_scene(s)
+    rng = np.random.default_rng(4)
+    x = s.X + 0.01 * rng.normal(size=s.X.shape)
+    v = 0.3 * rng.normal(size=s.X.shape)
+    mid = cg.cc_mesh_upload(ctx, s.X, s.elems, s.fixed, s.E, s.nu, s.rho)
+    tg = s.targets(2)
+    nf = int((~s.fixed.astype(bool)).sum())
+    feat, xt, ell = cg.cc_mlp_features(ctx, mid, torch.tensor(x, device=DEV), torch.tensor(v, device=DEV),
+                                       torch.tensor(tg, device=DEV), s.dt, nf)
+    xh = predictor(p, x, v, tg)
+    fo, ello = M.features(p, x, xh)
+    assert abs(ell - ello) <= 1e-12 * ello
+    np.testing.assert_allclose(xt.cpu().numpy(), xh, rtol=0, atol=1e-12)
+    f = feat.cpu().numpy()
+    scale = np.maximum(np.abs(fo).max(axis=0), 1e-3)
+    assert np.max(np.abs(f - fo) / scale) <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def trained(cg, ctx):
+    from paper_2510_12053_amd import warmstart as W
+    scenes = [warm_start_train_scene(1000 + k) for k in range(6)]
+    X, T, _ = W.generate(ctx, scenes, 6, DEV)
+    losses, _ = W.train(ctx, X, T, mlp_init(7), epochs=40, batch=1024, lr=2e-3)
+    params, mean, istd = cg.cc_mlp_get(ctx)
+    return dict(losses=losses, params=params, mean=mean, istd=istd)
+
+
+def test_training_reduces_loss(trained):
+    L = trained["losses"]
+    assert np.all(np.isfinite(L)) and L[-1] < 0.5 * L[0], L
+
+
+def test_random_network_is_rejected_and_step_unchanged(cg, ctx):
+    s = tet_bar(9, 4, 4, E=1e5)
+    rng = np.random.default_rng(9)
+    cg.cc_mlp_set(ctx, (20.0 * rng.normal(size=M.N_PARAMS)).astype(np.float32))
+    p = Problem.from_scene(s)
+    B = exact_basis(p)
+    res = {}
+    for warm in (0, 1):
+        mid = cg.cc_mesh_upload(ctx, s.X, s.elems, s.fixed, s.E, s.nu, s.rho)
+        cg.cc_subspace_upload(ctx, mid, *B, s.dt)
+        x, v = s.initial_state()
+        xg, vg = torch.tensor(x, device=DEV), torch.tensor(v, device=DEV)
+        par = cg.cc_params_default(warm_start=warm, gravity=s.gravity)
+        st, it, rg = cg.cc_step(ctx, mid, xg, vg, None, s.dt, par, 1e-8)
+        res[warm] = (it, xg.cpu().numpy(), cg.cc_step_info(ctx, mid)["warm_accepted"])
+    assert res[1][2] is False
+    assert res[0][0] == res[1][0] and np.array_equal(res[0][1], res[1][1])
+
+
+def test_warm_step_matches_oracle(cg, ctx, trained):
+    """The trained proposal, decision and converged state against the oracle
+    (oracle proposal from its own features and FP64 forward on BF16-rounded
+    weights)."""
+    cg.cc_mlp_set(ctx, trained["params"], trained["mean"], trained["istd"])
+    s = warm_start_train_scene(2001)
+    p = Problem.from_scene(s)
+    Bs = exact_basis(p)
+    mid = cg.cc_mesh_upload(ctx, s.X, s.elems, s.fixed, s.E, s.nu, s.rho)
+    cg.cc_subspace_upload(ctx, mid, *Bs, s.dt)
+    x, v = s.initial_state()
+    xg, vg = torch.tensor(x, device=DEV), torch.tensor(v, device=DEV)
+    op = S.Params(method=S.CC, sweep=S.JACOBI, line_search=True, max_iters=200)
+    theta = _oracle_bf16_params(trained["params"])
+    accepted = []
+    for t in range(1, 4):
+        tg = s.targets(t)
+        par = cg.cc_params_default(warm_start=1, gravity=s.gravity, max_iters=200)
+        st, it, rg = cg.cc_step(ctx, mid, xg, vg, torch.tensor(tg, device=DEV), s.dt, par, 1e-8)
+        acc = cg.cc_step_info(ctx, mid)["warm_accepted"]
+        xh = predictor(p, x, v, tg)
+        f, ell = M.features(p, x, xh)
+        Xn = np.zeros((f.shape[0], 32))
+        Xn[:, :16] = bf16((f - trained["mean"]) * trained["istd"])
+        Y, _ = M.forward(theta, Xn)
+        prop = M.proposal(p, xh, Y, ell)
+        x, v, res, acc_o = step(p, x, v, tg, Bs, op, 1e-8, proposal=prop)
+        accepted.append(acc)
+        if acc == acc_o:
+            xr = xg.cpu().numpy()
+            assert np.linalg.norm(xr - x) / np.linalg.norm(x - s.X) <= 1e-6
+        else:                      # borderline decisions may differ: resynchronise
+            xg.copy_(torch.tensor(x, device=DEV))
+            vg.copy_(torch.tensor(v, device=DEV))
+    assert any(accepted)

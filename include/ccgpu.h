@@ -128,10 +128,13 @@ cc_status cc_subspace_upload(cc_ctx* ctx, int32_t mesh_id, const int64_t* ptr,
    (M + h^2 K(X), or K(X) when quasistatic):
    radius > 0: patch basis, support = free vertices within `radius` hops,
                everything outside the patch held, U_i = -H[C,C]^{-1} H[C,i];
-   radius = 0: exact basis over every other free vertex (limited to meshes
-               with at most 1024 free vertices).
+   radius = 0: exact basis over every other free vertex, from the dense
+               inverse Z = H^{-1} computed on the GPU (blocked Gauss-Jordan,
+               float64) as U_i[j] = Z_ji Z_ii^{-1}; needs (n_free dim)^2
+               doubles of temporary device memory and stores
+               n_free (n_free - 1) blocks in float64 and float32.
    The rest Hessian is evaluated by the library's own GPU kernels in FP64;
-   the small dense solves run on the host. */
+   the patch solves run on the host. */
 cc_status cc_subspace_build(cc_ctx* ctx, int32_t mesh_id, int32_t radius, double dt,
                             int32_t quasistatic);
 

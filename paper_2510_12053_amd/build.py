@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "libccgpu.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["cc_kernels.hip", "cc_mlp.hip", "cc_api.hip"]
+SOURCES = ["cc_kernels.hip", "cc_mlp.hip", "cc_basis.hip", "cc_api.hip"]
 
 
 def _run(cmd):

@@ -43,9 +43,6 @@ struct Mesh {
   int* sidx = nullptr;
   double* U_d = nullptr;
   float* U_f = nullptr;
-  std::vector<int64_t> h_ptr;      // caller-format copy
-  std::vector<int> h_idx;
-  std::vector<double> h_U;
   // work buffers
   double *x = nullptr, *xt = nullptr, *x0 = nullptr, *xtrial = nullptr, *dvec = nullptr,
          *g = nullptr, *partials = nullptr, *scal = nullptr;
@@ -522,9 +519,7 @@ void upload_basis(cc_ctx* ctx, Mesh& M, const int64_t* ptr, const int32_t* idx, 
   M.U_f = dupload(Uf, s);
   M.dense = dense ? 1 : 0;
   M.snnz = nnz;
-  M.h_ptr.assign(ptr, ptr + n + 1);
-  M.h_idx.assign(idx, idx + nnz);
-  M.h_U.assign(U, U + (size_t)nnz * DD);
+
   HIPC(hipStreamSynchronize(s));
   M.has_basis = true;
 }
@@ -579,6 +574,47 @@ void build_basis(cc_ctx* ctx, Mesh& M, int radius, double dt, int quasi) {
   MeshView mv = M.view();
   cc::launch_elem_hess(mv, 0, M.x, mat, mat.s_el, M.estore, s);
   cc::launch_assemble(mv, 0, M.estore, mat, M.hb, s);
+  if (radius == 0) {  // exact basis: dense inverse of the rest Hessian on the GPU
+    const size_t N = (size_t)nf * D;
+    const size_t nnz = (size_t)nf * (nf > 0 ? nf - 1 : 0);
+    double* A = dalloc<double>(N * N);
+    double* work = dalloc<double>(N * 64 + 64 * 64);
+    int* badf = dalloc<int>(1);
+    double* Ud = nullptr;
+    float* Uf = nullptr;
+    bool ok = false;
+    try {
+      Ud = dalloc<double>(nnz * DD);
+      Uf = dalloc<float>(nnz * DD);
+      ok = cc::exact_basis_gpu(mv, (const double*)M.hb, A, work, badf, Ud, Uf, s);
+    } catch (...) {
+      dfree(A); dfree(work); dfree(badf); dfree(Ud); dfree(Uf);
+      throw;
+    }
+    dfree(A); dfree(work); dfree(badf);
+    if (!ok) {
+      dfree(Ud); dfree(Uf);
+      throw ApiError{CC_E_SUBSPACE, "rest Hessian not positive definite"};
+    }
+    std::vector<int64_t> sptr(nf + 1);
+    for (int i = 0; i <= nf; ++i) sptr[i] = (int64_t)i * (nf > 0 ? nf - 1 : 0);
+    std::vector<int> sidx(nnz);
+    for (int i = 0; i < nf; ++i) {
+      size_t q = (size_t)i * (nf - 1);
+      for (int j = 0; j < nf; ++j)
+        if (j != i) sidx[q++] = j;
+    }
+    free_basis(M);
+    M.sptr = dupload(sptr, s);
+    M.sidx = dupload(sidx, s);
+    M.U_d = Ud;
+    M.U_f = Uf;
+    M.dense = 1;
+    M.snnz = (int64_t)nnz;
+    HIPC(hipStreamSynchronize(s));
+    M.has_basis = true;
+    return;
+  }
   std::vector<double> hb((size_t)M.nnzb * DD);
   HIPC(hipMemcpyAsync(hb.data(), M.hb, hb.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPC(hipStreamSynchronize(s));
@@ -612,11 +648,6 @@ void build_basis(cc_ctx* ctx, Mesh& M, int radius, double dt, int quasi) {
       std::sort(all.begin(), all.end());
       supp[i] = all;
     }
-  } else {
-    if (nf > 1024) throw ApiError{CC_E_INVALID_ARG, "exact basis limited to 1024 free vertices"};
-    for (int i = 0; i < nf; ++i)
-      for (int j = 0; j < nf; ++j)
-        if (j != i) supp[i].push_back(j);
   }
   std::vector<std::vector<double>> Urows(nf);
   if (radius > 0) {
@@ -660,56 +691,6 @@ void build_basis(cc_ctx* ctx, Mesh& M, int radius, double dt, int quasi) {
     for (auto& t : pool) t.join();
     for (int f : failed)
       if (f) throw ApiError{CC_E_SUBSPACE, "patch Hessian not positive definite"};
-  } else {
-    const int N = nf * D;
-    std::vector<double> H((size_t)N * N, 0.0);
-    for (int j = 0; j < nf; ++j)
-      for (int t = M.rowptr[j]; t < M.rowptr[j + 1]; ++t) {
-        const int k = M.colidx[t];
-        for (int r = 0; r < D; ++r)
-          for (int c2 = 0; c2 < D; ++c2) H[(size_t)(j * D + r) * N + k * D + c2] = hb[(size_t)t * DD + r * D + c2];
-      }
-    if (!dense_chol(H, N)) throw ApiError{CC_E_SUBSPACE, "rest Hessian not positive definite"};
-    // Z = H^{-1} (all columns), U_i[j] = Z_ji Z_ii^{-1}
-    std::vector<double> Z((size_t)N * N, 0.0);
-    for (int i = 0; i < N; ++i) Z[(size_t)i * N + i] = 1.0;
-    {
-      const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-      std::vector<std::thread> pool;
-      const int chunk = (N + nth - 1) / nth;
-      for (unsigned w = 0; w < nth; ++w)
-        pool.emplace_back([&, w]() {
-          const int c0 = w * chunk, c1 = std::min(N, c0 + chunk);
-          if (c0 >= c1) return;
-          const int R = c1 - c0;
-          std::vector<double> Bw((size_t)N * R);
-          for (int r = 0; r < N; ++r)
-            for (int q = 0; q < R; ++q) Bw[(size_t)r * R + q] = Z[(size_t)r * N + c0 + q];
-          dense_chol_solve(H, N, Bw, R);
-          for (int r = 0; r < N; ++r)
-            for (int q = 0; q < R; ++q) Z[(size_t)r * N + c0 + q] = Bw[(size_t)r * R + q];
-        });
-      for (auto& t : pool) t.join();
-    }
-    for (int i = 0; i < nf; ++i) {
-      double Zii[9], Zinv[9], det;
-      for (int r = 0; r < D; ++r)
-        for (int c2 = 0; c2 < D; ++c2) Zii[r * D + c2] = Z[(size_t)(i * D + r) * N + i * D + c2];
-      if (!invert(D, Zii, Zinv, det)) throw ApiError{CC_E_SUBSPACE, "singular diagonal block of H^-1"};
-      std::vector<double> rows((size_t)(nf - 1) * D * D);
-      int a = 0;
-      for (int j = 0; j < nf; ++j) {
-        if (j == i) continue;
-        for (int r = 0; r < D; ++r)
-          for (int c2 = 0; c2 < D; ++c2) {
-            double acc = 0;
-            for (int l = 0; l < D; ++l) acc += Z[(size_t)(j * D + r) * N + i * D + l] * Zinv[l * D + c2];
-            rows[(size_t)(a * D + r) * D + c2] = acc;
-          }
-        ++a;
-      }
-      Urows[i] = rows;
-    }
   }
   // convert to the caller format (caller ids, ascending) and upload
   std::vector<int64_t> ptr(n + 1, 0);
@@ -970,9 +951,31 @@ cc_status cc_subspace_download(cc_ctx* ctx, int32_t mesh_id, int64_t* ptr, int32
   return guarded(ctx, [&]() -> cc_status {
     Mesh& M = get_mesh(ctx, mesh_id);
     if (!M.has_basis) return fail(ctx, CC_E_STATE, "no basis uploaded");
-    if (ptr) std::memcpy(ptr, M.h_ptr.data(), M.h_ptr.size() * sizeof(int64_t));
-    if (idx) std::memcpy(idx, M.h_idx.data(), M.h_idx.size() * sizeof(int32_t));
-    if (U) std::memcpy(U, M.h_U.data(), M.h_U.size() * sizeof(double));
+    // device rows are in internal order: convert to caller ids, ascending
+    const int D = M.D, DD = D * D, nf = M.nf, n = M.n;
+    std::vector<int64_t> sp(nf + 1);
+    std::vector<int> si(M.snnz);
+    std::vector<double> Uh((size_t)M.snnz * DD);
+    hipStream_t s = ctx->stream;
+    HIPC(hipMemcpyAsync(sp.data(), M.sptr, sp.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(si.data(), M.sidx, si.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(Uh.data(), M.U_d, Uh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    std::vector<int64_t> cp(n + 1, 0);
+    for (int i = 0; i < nf; ++i) cp[M.vperm[i] + 1] = sp[i + 1] - sp[i];
+    for (int u = 0; u < n; ++u) cp[u + 1] += cp[u];
+    if (ptr) std::memcpy(ptr, cp.data(), cp.size() * sizeof(int64_t));
+    std::vector<std::pair<int, int64_t>> row;
+    for (int i = 0; i < nf; ++i) {
+      const int u = M.vperm[i];
+      row.clear();
+      for (int64_t q = sp[i]; q < sp[i + 1]; ++q) row.push_back({M.vperm[si[q]], q});
+      std::sort(row.begin(), row.end());
+      for (size_t t = 0; t < row.size(); ++t) {
+        if (idx) idx[cp[u] + t] = row[t].first;
+        if (U) std::memcpy(&U[(size_t)(cp[u] + t) * DD], &Uh[(size_t)row[t].second * DD], DD * sizeof(double));
+      }
+    }
     return CC_OK;
   });
 }

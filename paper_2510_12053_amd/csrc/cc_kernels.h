@@ -71,6 +71,13 @@ void launch_scatter_user(const MeshView& mv, const int* vperm, const double* src
 
 int reduce_partials_capacity(const MeshView& mv);
 
+// Exact basis U_i[j] = (H^{-1})_ji ((H^{-1})_ii)^{-1} from float64 rest block
+// rows hb (cc_basis.hip).  A: (nf D)^2 doubles of scratch, work: nf D 64 +
+// 64^2 doubles, bad: one int; Ud/Uf: nf (nf-1) D^2 outputs in the dense
+// internal row layout.  Returns false if a pivot block is not SPD.
+bool exact_basis_gpu(const MeshView& mv, const double* hb, double* A, double* work, int* bad, double* Ud,
+                     float* Uf, hipStream_t s);
+
 // ---- batched stepping (many meshes per launch) -----------------------------
 constexpr int MAX_COLOURS = 32;
 

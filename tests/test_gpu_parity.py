@@ -230,3 +230,16 @@ def test_error_paths(cg, ctx):
     with pytest.raises(cg.CCError) as ei:
         cg.cc_mesh_upload(ctx, s.X, el, s.fixed, s.E, s.nu, s.rho)
     assert ei.value.status == -2
+
+
+def test_exact_basis_builder_bar(cg, ctx):
+    """GPU dense-inverse exact basis of the 21x6x6 bar (720 free vertices)."""
+    s = tet_bar(E=1e6)
+    p = Problem.from_scene(s)
+    B = exact_basis(p)
+    mid = _upload(cg, ctx, s)
+    cg.cc_subspace_build(ctx, mid, 0, s.dt, False)
+    ptr, idx, U = cg.cc_subspace_download(ctx, mid, s.n, 3)
+    np.testing.assert_array_equal(ptr, B[0])
+    np.testing.assert_array_equal(idx, B[1])
+    assert np.max(np.abs(U - B[2])) <= 1e-8 * np.max(np.abs(B[2]))

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "cc_device.h"
 
 namespace cc {
@@ -66,8 +68,14 @@ __global__ void __launch_bounds__(WG) k_gj_pivot(double* __restrict__ A, int N, 
     __syncthreads();
   }
   for (int e = threadIdx.x; e < b * b; e += WG) Pout[e] = M[e / b][e % b];
-  // old column block
-  for (size_t e = threadIdx.x; e < (size_t)N * b; e += WG) {
+  (void)Cbuf;
+}
+
+// Copy of the old column block C = A_*K (N x b), before it is overwritten.
+__global__ void __launch_bounds__(WG) k_gj_copycol(const double* __restrict__ A, int N, int k0, int b,
+                                                   double* __restrict__ Cbuf) {
+  const size_t total = (size_t)N * b;
+  for (size_t e = (size_t)blockIdx.x * WG + threadIdx.x; e < total; e += (size_t)gridDim.x * WG) {
     const size_t r = e / b;
     const int c = (int)(e % b);
     Cbuf[e] = A[r * N + k0 + c];
@@ -222,7 +230,9 @@ bool exact_basis_gpu(const MeshView& mv, const double* hb, double* A, double* wo
   const int tiles = (N + GJ_T - 1) / GJ_T;
   for (int k0 = 0; k0 < N; k0 += GJ_B) {
     const int b = (N - k0) < GJ_B ? (N - k0) : GJ_B;
+    const int cgrid = (int)std::min<size_t>(((size_t)N * b + WG - 1) / WG, 4096);
     k_gj_pivot<<<1, WG, 0, s>>>(A, N, k0, b, P, C, bad);
+    k_gj_copycol<<<cgrid, WG, 0, s>>>(A, N, k0, b, C);
     k_gj_rowscale<<<(N + GJ_B - 1) / GJ_B, WG, 0, s>>>(A, N, k0, b, P);
     k_gj_update<<<dim3(tiles, tiles), WG, 0, s>>>(A, N, k0, b, C);
     k_gj_colfix<<<(int)(((size_t)N * b + WG - 1) / WG < 4096 ? ((size_t)N * b + WG - 1) / WG : 4096), WG, 0, s>>>(

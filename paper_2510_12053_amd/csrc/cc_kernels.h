@@ -140,9 +140,11 @@ void batch_iterate(BatchPlan* p, int iters, hipStream_t s);
 void batch_finish(BatchPlan* p, hipStream_t s);
 // Learned warm start after batch_begin: feat / delta hold sum(nf) rows.
 struct MlpState;
+constexpr int FEAT_LANES = 32;   // lanes per vertex of the feature kernels
 struct BatchGrid {
-  int nmesh, pred_blocks;
+  int nmesh, pred_blocks, feat_blocks;
   const int* pred_off;  // block offsets of the per-vertex launches
+  const int* feat_off;  // block offsets of the feature launch
   double tol;
   int max_iters;
 };

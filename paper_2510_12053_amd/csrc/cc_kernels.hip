@@ -977,7 +977,7 @@ struct BatchPlan {
   std::vector<BatchItem> items_h;
   BatchItem* items_d = nullptr;
   BatchCtl* ctl_d = nullptr;
-  Offsets pred, elem, asmb, grad, energy, axpy;
+  Offsets pred, elem, asmb, grad, energy, axpy, feat;
   std::vector<Offsets> prep, upd;   // index 0: all free vertices, c+1: colour c
   int max_colours = 0;
   size_t lds = 0;
@@ -1045,7 +1045,8 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
   p->nmesh = nmesh;
   p->cfg = cfg;
   p->items_h.assign(items_host, items_host + nmesh);
-  std::vector<int> cpred(nmesh), celem(nmesh), casm(nmesh), cgrad(nmesh), cen(nmesh), cax(nmesh);
+  std::vector<int> cpred(nmesh), celem(nmesh), casm(nmesh), cgrad(nmesh), cen(nmesh), cax(nmesh),
+      cfeat(nmesh);
   for (int m = 0; m < nmesh; ++m) {
     const MeshView& mv = p->items_h[m].mv;
     cpred[m] = nblocks(mv.n, WG);
@@ -1054,6 +1055,7 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
     cgrad[m] = nblocks(mv.nf, WG / GRAD_G);
     cen[m] = nblocks(mv.m, WG) + nblocks(mv.nf, WG);
     cax[m] = nblocks((long long)mv.D * mv.n, WG);
+    cfeat[m] = nblocks(mv.nf, WG / FEAT_LANES);
     p->max_colours = std::max(p->max_colours, p->items_h[m].ncol);
     if (p->items_h[m].prep_dense) {
       const size_t lds = (size_t)(mv.nf - 1) * mv.D * mv.D * (cfg.prec == 0 ? 8 : 4);
@@ -1066,6 +1068,7 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
   offsets_build(p->grad, cgrad, s);
   offsets_build(p->energy, cen, s);
   offsets_build(p->axpy, cax, s);
+  offsets_build(p->feat, cfeat, s);
   plan_vertex_offsets(p, s);
   (void)hipMalloc(&p->items_d, nmesh * sizeof(BatchItem));
   (void)hipMalloc(&p->ctl_d, nmesh * sizeof(BatchCtl));
@@ -1077,7 +1080,7 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
 void batch_plan_destroy(BatchPlan* p) {
   if (!p) return;
   drop_graph(p);
-  for (Offsets* o : {&p->pred, &p->elem, &p->asmb, &p->grad, &p->energy, &p->axpy}) offsets_free(*o);
+  for (Offsets* o : {&p->pred, &p->elem, &p->asmb, &p->grad, &p->energy, &p->axpy, &p->feat}) offsets_free(*o);
   for (auto& o : p->prep) offsets_free(o);
   for (auto& o : p->upd) offsets_free(o);
   if (p->items_d) (void)hipFree(p->items_d);
@@ -1247,6 +1250,8 @@ BatchGrid batch_grid(BatchPlan* p) {
   g.nmesh = p->nmesh;
   g.pred_blocks = gridn(p->pred);
   g.pred_off = p->pred.d;
+  g.feat_blocks = gridn(p->feat);
+  g.feat_off = p->feat.d;
   g.tol = p->cfg.tol;
   g.max_iters = p->cfg.max_iters;
   return g;

@@ -381,34 +381,39 @@ __global__ void k_mlp_stats(const float* __restrict__ X, int N, float* __restric
   }
 }
 
-// Features of the free vertices of one mesh at the predictor xt (internal
-// order) with x0 the start-of-step positions; rows written to out[row_of(j)].
-__device__ __forceinline__ void features_body(const MeshView& mv, int j, const double* __restrict__ xt,
-                                              const double* __restrict__ x0, double h, double E,
-                                              double mu, double lam, double ell,
-                                              const int* __restrict__ nptr, const int* __restrict__ nidx,
-                                              const double* __restrict__ Xr, float* __restrict__ out) {
+constexpr int FEAT_G = FEAT_LANES;
+
+// Features of free vertex j of one mesh at the predictor xt (internal order)
+// with x0 the start-of-step positions, computed by G lanes that share j: the
+// lanes split
+// the neighbour list and the incident elements, then combine by shuffles.
+// Every lane of the group must call it (j may be past the free range: the
+// group then contributes nothing and writes nothing).
+template <int G>
+__device__ __forceinline__ void features_group(const MeshView& mv, int j, int lane,
+                                               const double* __restrict__ xt, const double* __restrict__ x0,
+                                               double h, double E, double mu, double lam, double ell,
+                                               const int* __restrict__ nptr, const int* __restrict__ nidx,
+                                               const double* __restrict__ Xr, float* __restrict__ out) {
   constexpr int D = 3;
   const int n = mv.n;
+  const bool valid = j < mv.nf;
   double f[16];
   // relative predictor displacement and velocity
   double mu_[3] = {0, 0, 0};
-  const int a0 = nptr[j], a1 = nptr[j + 1];
-  for (int t = a0; t < a1; ++t) {
+  int a0 = 0, a1 = 0;
+  if (valid) { a0 = nptr[j]; a1 = nptr[j + 1]; }
+  for (int t = a0 + lane; t < a1; t += G) {
     const int k = nidx[t];
 #pragma unroll
     for (int c = 0; c < D; ++c) mu_[c] += xt[c * n + k] - Xr[c * n + k];
   }
-  const double inv = a1 > a0 ? 1.0 / (a1 - a0) : 0.0;
-#pragma unroll
-  for (int c = 0; c < D; ++c) {
-    f[c] = ((xt[c * n + j] - Xr[c * n + j]) - mu_[c] * inv) / ell;
-    f[3 + c] = (xt[c * n + j] - x0[c * n + j]) / ell;
-  }
   // diagonal Hessian block and strain statistics over the star
   double Hd[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   double wsum = 0, ic_m = 0, j_m = 0, jmin = 1e300, icmax = -1e300;
-  for (int t = mv.star_ptr[j]; t < mv.star_ptr[j + 1]; ++t) {
+  int s0 = 0, s1 = 0;
+  if (valid) { s0 = mv.star_ptr[j]; s1 = mv.star_ptr[j + 1]; }
+  for (int t = s0 + lane; t < s1; t += G) {
     const int e = mv.star[t] >> 2, a = mv.star[t] & 3;
     double F[3][3], beta[4][3], vol;
     load_element<double, 3>(mv, e, xt, F, beta, vol);
@@ -444,6 +449,29 @@ __device__ __forceinline__ void features_body(const MeshView& mv, int j, const d
     jmin = fmin(jmin, J);
     icmax = fmax(icmax, ic);
   }
+  if constexpr (G > 1) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) mu_[c] += __shfl_xor(mu_[c], off, G);
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Hd[r][c] += __shfl_xor(Hd[r][c], off, G);
+      wsum += __shfl_xor(wsum, off, G);
+      ic_m += __shfl_xor(ic_m, off, G);
+      j_m += __shfl_xor(j_m, off, G);
+      jmin = fmin(jmin, __shfl_xor(jmin, off, G));
+      icmax = fmax(icmax, __shfl_xor(icmax, off, G));
+    }
+  }
+  if (!valid || lane != 0) return;
+  const double inv = a1 > a0 ? 1.0 / (a1 - a0) : 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    f[c] = ((xt[c * n + j] - Xr[c * n + j]) - mu_[c] * inv) / ell;
+    f[3 + c] = (xt[c * n + j] - x0[c * n + j]) / ell;
+  }
   const double mj = mv.mass[j];
   const double scale = mj + h * h * E * ell;
   const int up[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
@@ -461,15 +489,16 @@ __device__ __forceinline__ void features_body(const MeshView& mv, int j, const d
 }
 
 // rowmap: null -> row j (internal order), else row rowmap[j]
-__global__ void k_features(MeshView mv, const double* __restrict__ xt, const double* __restrict__ x0,
-                           double h, double E, double mu, double lam, double ell,
-                           const int* __restrict__ nptr, const int* __restrict__ nidx,
-                           const double* __restrict__ Xr, float* __restrict__ out,
-                           const int* __restrict__ rowmap) {
-  const int j = blockIdx.x * 64 + threadIdx.x;
-  if (j >= mv.nf) return;
-  const int row = rowmap ? rowmap[j] : j;
-  features_body(mv, j, xt, x0, h, E, mu, lam, ell, nptr, nidx, Xr, out + (size_t)row * 16);
+__global__ void __launch_bounds__(WG) k_features(MeshView mv, const double* __restrict__ xt,
+                                                 const double* __restrict__ x0, double h, double E,
+                                                 double mu, double lam, double ell,
+                                                 const int* __restrict__ nptr, const int* __restrict__ nidx,
+                                                 const double* __restrict__ Xr, float* __restrict__ out,
+                                                 const int* __restrict__ rowmap) {
+  const int j = blockIdx.x * (WG / FEAT_G) + threadIdx.x / FEAT_G;
+  const int row = (j < mv.nf) ? (rowmap ? rowmap[j] : j) : 0;
+  features_group<FEAT_G>(mv, j, threadIdx.x % FEAT_G, xt, x0, h, E, mu, lam, ell, nptr, nidx, Xr,
+                         out + (size_t)row * 16);
 }
 
 // x_prop = xt + ell * Delta on free vertices, xt on Dirichlet ones.
@@ -525,7 +554,8 @@ void launch_features(const MeshView& mv, const double* xt, const double* x0, dou
                      double lam, double ell, const int* nptr, const int* nidx, const double* Xr, float* out,
                      const int* rowmap, hipStream_t st) {
   if (mv.nf <= 0) return;
-  k_features<<<(mv.nf + 63) / 64, 64, 0, st>>>(mv, xt, x0, h, E, mu, lam, ell, nptr, nidx, Xr, out, rowmap);
+  k_features<<<(mv.nf + WG / FEAT_G - 1) / (WG / FEAT_G), WG, 0, st>>>(mv, xt, x0, h, E, mu, lam, ell, nptr,
+                                                                       nidx, Xr, out, rowmap);
 }
 
 // Training targets (x_new - x_tilde) / ell of the free vertices, caller-order
@@ -559,10 +589,10 @@ __global__ void __launch_bounds__(WG) kb_features(const BatchItem* __restrict__ 
   if (!ctl[mi].active) return;
   const BatchItem& it = items[mi];
   const MeshView mv = it.mv;
-  const int j = (blockIdx.x - boff[mi]) * WG + threadIdx.x;
-  if (j >= mv.nf) return;
-  features_body(mv, j, it.x, it.x0, sqrt(it.mat.s_el), it.youngs, it.mat.mu, it.mat.lam, it.ell,
-                it.nptr, it.nidx, it.Xr, feat + (size_t)(it.feat_off + j) * MLP_IN);
+  const int j = (blockIdx.x - boff[mi]) * (WG / FEAT_G) + threadIdx.x / FEAT_G;
+  features_group<FEAT_G>(mv, j, threadIdx.x % FEAT_G, it.x, it.x0, sqrt(it.mat.s_el), it.youngs, it.mat.mu,
+                         it.mat.lam, it.ell, it.nptr, it.nidx, it.Xr,
+                         feat + (size_t)(it.feat_off + (j < mv.nf ? j : 0)) * MLP_IN);
 }
 
 __global__ void __launch_bounds__(WG) kb_proposal(const BatchItem* __restrict__ items,
@@ -614,7 +644,7 @@ void batch_warm_start(BatchPlan* p, const MlpState& net, float* feat, float* del
   BatchCtl* ctl = batch_ctl_dev(p);
   const int gb = (g.nmesh + WG - 1) / WG;
   if (g.pred_blocks == 0) return;
-  kb_features<<<g.pred_blocks, WG, 0, s>>>(items, ctl, g.pred_off, g.nmesh, feat);
+  if (g.feat_blocks > 0) kb_features<<<g.feat_blocks, WG, 0, s>>>(items, ctl, g.feat_off, g.nmesh, feat);
   mlp_forward(net, feat, rows, delta, s);
   kb_proposal<<<g.pred_blocks, WG, 0, s>>>(items, ctl, g.pred_off, g.nmesh, delta);
   batch_energy_x(p, s);

@@ -26,7 +26,7 @@ int32) ascending vertex ids; U (nnz, d, d) with U[k] the block U_i[j] that
 maps a displacement of vertex i to the displacement of vertex j = idx[k].
 Dirichlet vertices have empty rows and never appear in a support.
 
-Pins: tests/test_oracle_basis.py -- exact basis satisfies H_CC U_i + H_Ci = 0
+Pins: tests/test_oracle_basis_colour.py -- exact basis satisfies H_CC U_i + H_Ci = 0
 and matches a direct per-vertex solve of that equation; patch basis satisfies
 the patch equilibrium; Dirichlet vertices absent.
 """

@@ -13,7 +13,7 @@ does not specify one; this package's reading:
 * element order: sorted by (smallest new index among the element's free
   vertices, id); elements with no free vertex last by id.
 
-Pins: tests/test_oracle_colour.py -- validity on every scene, the colour
+Pins: tests/test_oracle_basis_colour.py -- validity on every scene, the colour
 counts and class sizes of the structured grids, and agreement with a
 brute-force "sequential greedy" restated as Jones-Plassmann rounds with
 vertex-id priority.

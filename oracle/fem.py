@@ -17,7 +17,7 @@ Element terms (with the projected material Hessian C):
 Gradient and Hessian are restricted to free degrees of freedom, ordered by
 free-vertex rank (ascending vertex id) then component.
 
-Pins: tests/test_oracle_fem.py -- finite differences of E (gradient) and of
+Pins: tests/test_oracle_mesh_fem.py -- finite differences of E (gradient) and of
 the gradient (unprojected Hessian); sum_a g_e[a] = 0; H_e annihilates
 translations; symmetry; one Newton step solves a linear-elastic problem
 exactly.

@@ -10,7 +10,7 @@ Background section (positions x in R^{dn}, mass matrix M):
 * lumped mass m_i = rho * sum_{e containing i} V_e / (d+1).  The paper only
   names "the mass matrix"; the lumped form is this package's reading.
 
-Pins: tests/test_oracle_mesh.py (counts, orientation, total volume equals the
+Pins: tests/test_oracle_mesh_fem.py (counts, orientation, total volume equals the
 box volume, F(X) = I, total mass equals rho * volume).
 """
 import math

@@ -33,6 +33,8 @@ struct Mesh {
   int *ev = nullptr, *star_ptr = nullptr, *star = nullptr, *d_rowptr = nullptr, *d_colidx = nullptr,
       *blkrow = nullptr, *cptr = nullptr, *centry = nullptr, *d_vperm = nullptr, *d_vinv = nullptr,
       *d_eperm = nullptr;
+  int4* seg = nullptr;  // upper-triangle block segments of the dense condensation
+  int nseg = 0;
   double *dinv_d = nullptr, *vol_d = nullptr, *mass = nullptr;
   float *dinv_f = nullptr, *vol_f = nullptr;
   // basis
@@ -67,6 +69,7 @@ struct Mesh {
     v.ev = ev; v.dinv_d = dinv_d; v.dinv_f = dinv_f; v.vol_d = vol_d; v.vol_f = vol_f;
     v.mass = mass; v.vperm = d_vperm; v.star_ptr = star_ptr; v.star = star; v.rowptr = d_rowptr;
     v.colidx = d_colidx; v.blkrow = blkrow; v.cptr = cptr; v.centry = centry; v.nnzb = nnzb;
+    v.seg = seg; v.nseg = nseg;
     v.sptr = sptr; v.sidx = sidx; v.U_d = U_d; v.U_f = U_f; v.dense_supp = dense;
     return v;
   }
@@ -118,6 +121,7 @@ void free_basis(Mesh& M) {
 void free_mesh(Mesh& M) {
   dfree(M.ev); dfree(M.star_ptr); dfree(M.star); dfree(M.d_rowptr); dfree(M.d_colidx);
   dfree(M.blkrow); dfree(M.cptr); dfree(M.centry); dfree(M.d_vperm); dfree(M.d_vinv);
+  dfree(M.seg);
   dfree(M.d_eperm); dfree(M.dinv_d); dfree(M.vol_d); dfree(M.mass); dfree(M.dinv_f); dfree(M.vol_f);
   free_basis(M);
   dfree(M.x); dfree(M.xt); dfree(M.x0); dfree(M.xtrial); dfree(M.dvec); dfree(M.g);
@@ -402,6 +406,26 @@ void build_mesh(cc_ctx* ctx, Mesh& M) {
   M.d_rowptr = dupload(M.rowptr, s);
   M.d_colidx = dupload(M.colidx, s);
   M.blkrow = dupload(blkrow, s);
+  if (nf <= 65535) {  // blocks j <= k of the symmetric block matrix in row segments
+    std::vector<int4> seg;
+    for (int j = 0; j < nf; ++j) {
+      std::vector<int> slots;
+      for (int t = M.rowptr[j]; t < M.rowptr[j + 1]; ++t)
+        if (M.colidx[t] >= j) slots.push_back(t);
+      for (size_t q0 = 0; q0 < slots.size(); q0 += cc::SEG_LEN) {
+        int sl[cc::SEG_LEN], kk[cc::SEG_LEN];
+        const int cnt = (int)std::min<size_t>(cc::SEG_LEN, slots.size() - q0);
+        for (int q = 0; q < cc::SEG_LEN; ++q) {
+          sl[q] = q < cnt ? slots[q0 + q] : slots[q0];
+          kk[q] = M.colidx[sl[q]];
+        }
+        seg.push_back(make_int4(j, cnt, sl[0], sl[1]));
+        seg.push_back(make_int4(sl[2], sl[3], kk[0] | (kk[1] << 16), kk[2] | (kk[3] << 16)));
+      }
+    }
+    M.nseg = (int)seg.size() / 2;
+    M.seg = dupload(seg, s);
+  }
   M.cptr = dupload(cptr, s);
   M.centry = dupload(centry, s);
   M.d_vperm = dupload(M.vperm, s);
@@ -816,6 +840,10 @@ cc_status cc_create(int32_t device, void* hip_stream, cc_ctx** out) {
     delete ctx;
     return CC_E_HIP;
   }
+  int lds = 0;  // per-workgroup LDS budget of the dense condensation
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess &&
+      lds > 0)
+    cc::set_lds_limit((size_t)lds);
   *out = ctx;
   return CC_OK;
 }
@@ -1210,8 +1238,7 @@ static cc_status batch_validate(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids,
 }
 
 static bool use_dense_lds(const Mesh& M, int prec) {
-  const size_t lds = (size_t)(M.nf - 1) * M.D * M.D * (prec == 0 ? 8 : 4);
-  return M.dense && M.nf >= 2 && lds <= 64 * 1024;
+  return M.dense && M.nseg > 0 && cc::dense_tv(M.nf, M.D, prec) > 0;
 }
 
 static void ctx_batch_hook(void* user, int kid, int begin) {

@@ -30,6 +30,16 @@ template <> __device__ __forceinline__ const double* dinv_of<double>(const MeshV
 template <typename T> __device__ __forceinline__ const T* vol_of(const MeshView& mv);
 template <> __device__ __forceinline__ const float* vol_of<float>(const MeshView& mv) { return mv.vol_f; }
 template <> __device__ __forceinline__ const double* vol_of<double>(const MeshView& mv) { return mv.vol_d; }
+// Global-memory view of a pointer read from a struct in memory (those are
+// generic, so their loads would be FLAT, which also count against the LDS
+// wait counter and stall LDS reads behind outstanding global loads).
+template <typename T>
+using gmem_t = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ const gmem_t<T>* gptr(const T* p) { return (const gmem_t<T>*)p; }
+template <typename T>
+__device__ __forceinline__ gmem_t<T>* gptr_w(T* p) { return (gmem_t<T>*)p; }
+
 template <typename T> __device__ __forceinline__ const T* basis_of(const MeshView& mv);
 template <> __device__ __forceinline__ const float* basis_of<float>(const MeshView& mv) { return mv.U_f; }
 template <> __device__ __forceinline__ const double* basis_of<double>(const MeshView& mv) { return mv.U_d; }

@@ -25,6 +25,12 @@ struct MeshView {
   const int* cptr;       // [nnzb+1] element contributions of each block slot
   const int* centry;     // packed e*16 + a*4 + b
   int nnzb;
+  // blocks j <= k of the symmetric block matrix (diagonal included), in
+  // segments of up to SEG_LEN blocks of one row j: two int4 per segment,
+  // {j, count, slot0, slot1}, {slot2, slot3, k0 | k1 << 16, k2 | k3 << 16};
+  // null when nf > 65535
+  const int4* seg;
+  int nseg;
   // perturbation basis, internal ids, rows sorted by internal id
   const int64_t* sptr;   // [nf+1]
   const int* sidx;
@@ -71,6 +77,15 @@ void launch_scatter_user(const MeshView& mv, const int* vperm, const double* src
 
 int reduce_partials_capacity(const MeshView& mv);
 
+constexpr int SEG_LEN = 4;
+
+// Dense condensation with the basis rows in LDS: the per-workgroup LDS limit
+// of the device (bytes, set once per process) and the number of vertices one
+// workgroup takes for a mesh of nf free vertices (0: the rows do not fit).
+void set_lds_limit(size_t bytes);
+int dense_tv(int nf, int D, int prec);
+size_t dense_lds_bytes(int tv, int nf, int D, int prec);
+
 // Exact basis U_i[j] = (H^{-1})_ji ((H^{-1})_ii)^{-1} from float64 rest block
 // rows hb (cc_basis.hip).  A: (nf D)^2 doubles of scratch, work: nf D 64 +
 // 64^2 doubles, bad: one int; Ud/Uf: nf (nf-1) D^2 outputs in the dense
@@ -94,7 +109,7 @@ struct BatchItem {
   double* xu;          // caller positions (n x D), this call
   double* vu;          // caller velocities
   const double* xbc;   // caller Dirichlet targets or null
-  int prep_dense;      // 1: exact-basis condensation with the basis row in LDS
+  int prep_dense;      // 1: exact-basis condensation with the basis rows in LDS
   int ncol;
   int coff[MAX_COLOURS + 1];
   // warm start: mesh neighbours (all vertices), rest positions, scales and

@@ -223,109 +223,205 @@ __global__ void __launch_bounds__(WG) k_cc_prep(MeshView mv, int method, int v0,
   prep_body<T, D, G>(mv, method, i, i < v1, threadIdx.x % G, hb, KL, fb);
 }
 
-// Exact-basis condensation: one workgroup per vertex; the vertex's dense
-// basis row U_i (every other free vertex) is staged in LDS, so the H_jk U_k
-// products read U_k from LDS while the block rows stream from global memory.
-// Whole workgroup on vertex i; Us: LDS room for the basis row, red: LDS
-// scratch of (WG/64) x 2 D*D values.
-template <typename T, int D>
-__device__ __forceinline__ void prep_dense_body(const MeshView& mv, int method, int i,
-                                                const T* __restrict__ hb, T* __restrict__ KL,
-                                                unsigned long long* __restrict__ fb, T* Us,
-                                                T (*red)[2 * D * D]) {
-  constexpr int DD = D * D;
+// Exact-basis condensation of TV vertices per workgroup.  Each vertex's
+// dense basis row goes to LDS with a zero block at its own position, so the
+// sums below run over every (j, k) without excluding i.  H is symmetric, so
+// only the blocks j <= k are read: with X_jk = U_j^T H_jk U_k,
+//   Ht = sum_{j,k} X_jk = Y + Y^T,  Y = sum_{j<k} X_jk + 1/2 sum_j X_jj,
+// and every H block read from L2 serves all TV vertices of the workgroup.
+// A_i = sum_k H_ik U_i[k] comes from row i (one wave per vertex).
+constexpr int PWG = 512;   // threads of the dense multi-vertex condensation
+
+template <typename T, int D, int TV>
+__device__ __forceinline__ void prep_dm_body(const MeshView& mv, int method, int i0, int nv,
+                                             const T* __restrict__ hb, T* __restrict__ KL,
+                                             unsigned long long* __restrict__ fb, T* smem) {
+  constexpr int DD = D * D, NW = PWG / 64;
+  const int nf = mv.nf;
+  T* Us = smem;                                   // [TV][nf][DD]
+  T* red = smem + (size_t)TV * nf * DD;           // [NW + 1][TV][DD]
   const T* Ub = basis_of<T>(mv);
-  const int cnt = mv.nf - 1;
-  const int64_t sp0 = mv.sptr[i];
-  for (int q = threadIdx.x; q < cnt * DD; q += WG) Us[q] = Ub[sp0 * DD + q];
-  __syncthreads();
-  T A[DD], Ht[DD];
+  // stage the rows: many independent loads in flight per thread, then the
+  // LDS stores (one workgroup per CU leaves nothing else to hide the latency).
+  // Every load is unconditional and in bounds (positions past the row end
+  // and the vertex's own block read element 0 and are replaced by zero), so
+  // the loads of one batch issue back to back.  Rows of vertex slots past nv
+  // are zero.
+  constexpr int UNR = 16;
+  const int total = nf * DD;
 #pragma unroll
-  for (int r = 0; r < DD; ++r) A[r] = Ht[r] = T(0);
-  if (method != 0) {
-    // consecutive lanes take consecutive blocks (j, k) of the whole block
-    // matrix, so the Hessian streams coalesced while U_j, U_k come from LDS
-    for (int t = threadIdx.x; t < mv.nnzb; t += WG) {
-      const int j = mv.blkrow[t];
-      if (j == i) continue;                       // row i is not in the complement
-      const int k = mv.colidx[t];
-      const T* Uj = Us + (size_t)(j < i ? j : j - 1) * DD;
-      const T* H = hb + (size_t)t * DD;
-      T Hl[DD];
+  for (int v = 0; v < TV; ++v) {
+    const int i = i0 + (v < nv ? v : 0);
+    const auto* src = gptr(Ub) + gptr(mv.sptr)[i] * DD;
+    T* dst = Us + (size_t)v * total;
+    const int lo = i * DD, hi = lo + DD;
+    for (int base = threadIdx.x; base < total; base += PWG * UNR) {
+      T tmp[UNR];
 #pragma unroll
-      for (int r = 0; r < DD; ++r) Hl[r] = H[r];
-      if (k == i) {                               // A += H_ji^T U_j
-#pragma unroll
-        for (int r = 0; r < D; ++r)
-#pragma unroll
-          for (int s = 0; s < D; ++s) {
-            T acc = T(0);
-#pragma unroll
-            for (int l = 0; l < D; ++l) acc += Hl[l * D + r] * Uj[l * D + s];
-            A[r * D + s] += acc;
-          }
-        continue;
+      for (int u = 0; u < UNR; ++u) {
+        const int q = base + u * PWG;
+        const bool zero = v >= nv || (q >= lo && q < hi) || q >= total;
+        const int sq = zero ? 0 : (q < lo ? q : q - DD);
+        const T val = src[sq];
+        tmp[u] = zero ? T(0) : val;
       }
-      const T* Uk = Us + (size_t)(k < i ? k : k - 1) * DD;
-      T M[DD];
 #pragma unroll
-      for (int r = 0; r < D; ++r)                 // M = H_jk U_k
+      for (int u = 0; u < UNR; ++u) {
+        const int q = base + u * PWG;
+        if (q < total) dst[q] = tmp[u];
+      }
+    }
+  }
+  __syncthreads();
+  T Y[TV][DD];
 #pragma unroll
-        for (int s = 0; s < D; ++s) {
-          T acc = T(0);
+  for (int v = 0; v < TV; ++v)
 #pragma unroll
-          for (int l = 0; l < D; ++l) acc += Hl[r * D + l] * Uk[l * D + s];
-          M[r * D + s] = acc;
+    for (int r = 0; r < DD; ++r) Y[v][r] = T(0);
+  if (method != 0) {
+    // one segment = up to SEG_LEN blocks (j, k) of row j:
+    //   W = sum_k w_k H_jk U_k  (27 FMA per block and vertex),
+    //   Y += U_j^T W            (27 FMA per segment and vertex)
+    for (int sg = threadIdx.x; sg < mv.nseg; sg += PWG) {
+      const auto* sq = gptr(reinterpret_cast<const int*>(mv.seg)) + 8 * sg;
+      const int j = sq[0], cnt = sq[1];
+      const int slot[SEG_LEN] = {sq[2], sq[3], sq[4], sq[5]};
+      const int kk[SEG_LEN] = {sq[6] & 0xffff, sq[6] >> 16, sq[7] & 0xffff, sq[7] >> 16};
+      T W[TV][DD];
+#pragma unroll
+      for (int v = 0; v < TV; ++v)
+#pragma unroll
+        for (int r = 0; r < DD; ++r) W[v][r] = T(0);
+      // short segments are padded with a repeat of their first block at
+      // weight 0, so the loop has no branches and its loads issue together
+#pragma unroll
+      for (int q = 0; q < SEG_LEN; ++q) {
+        const int k = kk[q];
+        const auto* H = gptr(hb) + (size_t)slot[q] * DD;
+        const T w = q < cnt ? ((j == k) ? T(0.5) : T(1)) : T(0);
+        T Hl[DD];
+#pragma unroll
+        for (int r = 0; r < DD; ++r) Hl[r] = w * H[r];
+#pragma unroll
+        for (int v = 0; v < TV; ++v) {
+          const T* Uk = Us + ((size_t)v * nf + k) * DD;
+          T Ukl[DD];
+#pragma unroll
+          for (int r = 0; r < DD; ++r) Ukl[r] = Uk[r];
+#pragma unroll
+          for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c)
+#pragma unroll
+              for (int l = 0; l < D; ++l) W[v][r * D + c] += Hl[r * D + l] * Ukl[l * D + c];
         }
+      }
 #pragma unroll
-      for (int r = 0; r < D; ++r)                 // Ht += U_j^T M
+      for (int v = 0; v < TV; ++v) {
+        const T* u = Us + ((size_t)v * nf + j) * DD;
+        T Uj[DD];
 #pragma unroll
-        for (int s = 0; s < D; ++s) {
-          T acc = T(0);
+        for (int r = 0; r < DD; ++r) Uj[r] = u[r];
 #pragma unroll
-          for (int l = 0; l < D; ++l) acc += Uj[l * D + r] * M[l * D + s];
-          Ht[r * D + s] += acc;
-        }
+        for (int l = 0; l < D; ++l)
+#pragma unroll
+          for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) Y[v][r * D + c] += Uj[l * D + r] * W[v][l * D + c];
+      }
     }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-    for (int r = 0; r < DD; ++r) {
-      A[r] += __shfl_xor(A[r], off, 64);
-      Ht[r] += __shfl_xor(Ht[r], off, 64);
-    }
-  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-  if (l == 0) {
+    for (int v = 0; v < TV; ++v)
 #pragma unroll
-    for (int r = 0; r < DD; ++r) {
-      red[w][r] = A[r];
-      red[w][DD + r] = Ht[r];
-    }
+      for (int r = 0; r < DD; ++r) Y[v][r] += __shfl_xor(Y[v][r], off, 64);
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  if (l == 0)
+#pragma unroll
+    for (int v = 0; v < TV; ++v)
+#pragma unroll
+      for (int r = 0; r < DD; ++r) red[(w * TV + v) * DD + r] = Y[v][r];
+  __syncthreads();
+  if (threadIdx.x < TV * DD) {
+    T acc = T(0);
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) acc += red[ww * TV * DD + threadIdx.x];
+    red[NW * TV * DD + threadIdx.x] = acc;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
+  if (w >= nv) return;
+  const int i = i0 + w;
+  T A[DD];
 #pragma unroll
-  for (int r = 0; r < DD; ++r) {
-    T a = T(0), h = T(0);
+  for (int r = 0; r < DD; ++r) A[r] = T(0);
+  if (method != 0) {
+    const T* Ui = Us + (size_t)w * nf * DD;
+    const int q1 = gptr(mv.rowptr)[i + 1];
+    for (int q = gptr(mv.rowptr)[i] + l; q < q1; q += 64) {
+      const auto* H = gptr(hb) + (size_t)q * DD;
+      const T* Uk = Ui + (size_t)gptr(mv.colidx)[q] * DD;
 #pragma unroll
-    for (int ww = 0; ww < WG / 64; ++ww) {
-      a += red[ww][r];
-      h += red[ww][DD + r];
+      for (int r = 0; r < D; ++r)
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          T acc = T(0);
+#pragma unroll
+          for (int t = 0; t < D; ++t) acc += H[r * D + t] * Uk[t * D + c];
+          A[r * D + c] += acc;
+        }
     }
-    A[r] = a;
-    Ht[r] = h;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int r = 0; r < DD; ++r) A[r] += __shfl_xor(A[r], off, 64);
   }
-  cc_finish<T, D>(mv, method, i, cnt == 0, A, Ht, hb, KL, fb);
+  if (l != 0) return;
+  // A and Ht go to the vertex's K, L slots; dm_finish_body turns them into
+  // K and L with one thread per vertex (the small solves are latency-bound
+  // and would otherwise serialise the single workgroup resident per CU)
+  const T* Yt = red + (NW * TV + w) * DD;
+  auto* out = gptr_w(KL) + (size_t)i * 2 * DD;
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      out[r * D + c] = A[r * D + c];
+      out[DD + r * D + c] = Yt[r * D + c] + Yt[c * D + r];
+    }
 }
 
 template <typename T, int D>
-__global__ void __launch_bounds__(WG) k_cc_prep_dense(MeshView mv, int method, int v0,
-                                                      const T* __restrict__ hb, T* __restrict__ KL,
-                                                      unsigned long long* __restrict__ fb) {
+__device__ __forceinline__ void dm_finish_body(const MeshView& mv, int method, int i,
+                                               const T* __restrict__ hb, T* __restrict__ KL,
+                                               unsigned long long* __restrict__ fb) {
+  constexpr int DD = D * D;
+  T A[DD], Ht[DD];
+  const T* in = KL + (size_t)i * 2 * DD;
+#pragma unroll
+  for (int r = 0; r < DD; ++r) {
+    A[r] = in[r];
+    Ht[r] = in[DD + r];
+  }
+  cc_finish<T, D>(mv, method, i, mv.nf <= 1, A, Ht, hb, KL, fb);
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(WG) k_cc_dm_finish(MeshView mv, int method, int v0, int v1,
+                                                     const T* __restrict__ hb, T* __restrict__ KL,
+                                                     unsigned long long* __restrict__ fb) {
+  const int i = v0 + blockIdx.x * WG + threadIdx.x;
+  if (i < v1) dm_finish_body<T, D>(mv, method, i, hb, KL, fb);
+}
+
+template <typename T, int D, int TV>
+__global__ void __launch_bounds__(PWG) k_cc_prep_dm(MeshView mv, int method, int v0, int v1,
+                                                    const T* __restrict__ hb, T* __restrict__ KL,
+                                                    unsigned long long* __restrict__ fb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ T red[WG / 64][2 * D * D];
-  prep_dense_body<T, D>(mv, method, v0 + blockIdx.x, hb, KL, fb, reinterpret_cast<T*>(smem_raw), red);
+  const int i0 = v0 + blockIdx.x * TV;
+  prep_dm_body<T, D, TV>(mv, method, i0, min(TV, v1 - i0), hb, KL, fb, reinterpret_cast<T*>(smem_raw));
 }
 
 
@@ -626,14 +722,40 @@ static int support_lanes(const MeshView& mv) {
   return 16;
 }
 
-constexpr size_t DENSE_LDS_LIMIT = 64 * 1024;
+static size_t g_lds_limit = 64 * 1024;
+
+void set_lds_limit(size_t bytes) { g_lds_limit = bytes; }
+
+size_t dense_lds_bytes(int tv, int nf, int D, int prec) {
+  const size_t S = prec == 0 ? 8 : 4;
+  return ((size_t)tv * nf + (size_t)(PWG / 64 + 1) * tv) * D * D * S;
+}
+
+int dense_tv(int nf, int D, int prec) {
+  if (nf < 2 || nf > 65535) return 0;
+  // four float64 vertices per workgroup exceed the register file of 2 waves/SIMD
+  for (int tv = prec == 0 ? 3 : 4; tv >= 1; --tv)
+    if (dense_lds_bytes(tv, nf, D, prec) <= g_lds_limit) return tv;
+  return 0;
+}
+
+#define CC_DISPATCH_TV(tv, ...)                              \
+  switch (tv) {                                              \
+    case 1: { constexpr int TV = 1; __VA_ARGS__; } break;    \
+    case 2: { constexpr int TV = 2; __VA_ARGS__; } break;    \
+    case 3: { constexpr int TV = 3; __VA_ARGS__; } break;    \
+    default: { constexpr int TV = 4; __VA_ARGS__; } break;   \
+  }
 
 template <typename T, int D>
-static bool prep_dense(const MeshView& mv, int method, int v0, int v1, const void* hb, void* KL,
-                       unsigned long long* fb, hipStream_t s) {
-  const size_t lds = (size_t)(mv.nf - 1) * D * D * sizeof(T);
-  if (!mv.dense_supp || mv.nf < 2 || lds > DENSE_LDS_LIMIT) return false;
-  k_cc_prep_dense<T, D><<<v1 - v0, WG, lds, s>>>(mv, method, v0, (const T*)hb, (T*)KL, fb);
+static bool prep_dense(const MeshView& mv, int prec, int method, int v0, int v1, const void* hb,
+                       void* KL, unsigned long long* fb, hipStream_t s) {
+  const int tv = mv.dense_supp && mv.nseg > 0 ? dense_tv(mv.nf, D, prec) : 0;
+  if (tv == 0) return false;
+  const size_t lds = dense_lds_bytes(tv, mv.nf, D, prec);
+  CC_DISPATCH_TV(tv, k_cc_prep_dm<T, D, TV><<<nblocks(v1 - v0, TV), PWG, lds, s>>>(
+                         mv, method, v0, v1, (const T*)hb, (T*)KL, fb));
+  k_cc_dm_finish<T, D><<<nblocks(v1 - v0, WG), WG, 0, s>>>(mv, method, v0, v1, (const T*)hb, (T*)KL, fb);
   return true;
 }
 
@@ -641,8 +763,8 @@ void launch_cc_prep(const MeshView& mv, int prec, int method, int v0, int v1, co
                     void* KL, unsigned long long* fb, hipStream_t s) {
   if (v1 <= v0) return;
   bool done = false;
-  if (prec == 0) CC_DISPATCH_D(mv.D, done = prep_dense<double, D>(mv, method, v0, v1, hb, KL, fb, s));
-  else CC_DISPATCH_D(mv.D, done = prep_dense<float, D>(mv, method, v0, v1, hb, KL, fb, s));
+  if (prec == 0) CC_DISPATCH_D(mv.D, done = prep_dense<double, D>(mv, prec, method, v0, v1, hb, KL, fb, s));
+  else CC_DISPATCH_D(mv.D, done = prep_dense<float, D>(mv, prec, method, v0, v1, hb, KL, fb, s));
   if (done) return;
   const int G = support_lanes(mv);
   if (prec == 0) CC_DISPATCH_D(mv.D, prep_g<double, D>(mv, method, v0, v1, hb, KL, fb, G, s));
@@ -839,22 +961,45 @@ __global__ void __launch_bounds__(WG) kb_prep(const BatchItem* __restrict__ item
                                               const BatchCtl* __restrict__ ctl,
                                               const int* __restrict__ boff, int nmesh, int method,
                                               int colour) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ T red[WG / 64][2 * D * D];
   const int mi = block_mesh(boff, nmesh, blockIdx.x);
   if (!ctl[mi].active) return;
   const BatchItem& it = items[mi];
-  const MeshView mv = it.mv;
   int v0, v1;
   vertex_range(it, colour, v0, v1);
   const int lb = blockIdx.x - boff[mi];
-  if (it.prep_dense) {
-    prep_dense_body<T, D>(mv, method, v0 + lb, (const T*)it.hb, (T*)it.KL, it.fb,
-                          reinterpret_cast<T*>(smem_raw), red);
-  } else {
-    const int i = v0 + lb * (WG / G) + threadIdx.x / G;
-    prep_body<T, D, G>(mv, method, i, i < v1, threadIdx.x % G, (const T*)it.hb, (T*)it.KL, it.fb);
-  }
+  const int i = v0 + lb * (WG / G) + threadIdx.x / G;
+  prep_body<T, D, G>(it.mv, method, i, i < v1, threadIdx.x % G, (const T*)it.hb, (T*)it.KL, it.fb);
+}
+
+// Dense-basis meshes of a batch: TV vertices per workgroup (prep_dm_body).
+template <typename T, int D, int TV>
+__global__ void __launch_bounds__(PWG) kb_prep_dm(const BatchItem* __restrict__ items,
+                                                  const BatchCtl* __restrict__ ctl,
+                                                  const int* __restrict__ boff, int nmesh,
+                                                  int method, int colour) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  if (!ctl[mi].active) return;
+  const BatchItem& it = items[mi];
+  int v0, v1;
+  vertex_range(it, colour, v0, v1);
+  const int i0 = v0 + (blockIdx.x - boff[mi]) * TV;
+  prep_dm_body<T, D, TV>(it.mv, method, i0, min(TV, v1 - i0), (const T*)it.hb, (T*)it.KL, it.fb,
+                         reinterpret_cast<T*>(smem_raw));
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(WG) kb_dm_finish(const BatchItem* __restrict__ items,
+                                                   const BatchCtl* __restrict__ ctl,
+                                                   const int* __restrict__ boff, int nmesh,
+                                                   int method, int colour) {
+  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  if (!ctl[mi].active) return;
+  const BatchItem& it = items[mi];
+  int v0, v1;
+  vertex_range(it, colour, v0, v1);
+  const int i = v0 + (blockIdx.x - boff[mi]) * WG + threadIdx.x;
+  if (i < v1) dm_finish_body<T, D>(it.mv, method, i, (const T*)it.hb, (T*)it.KL, it.fb);
 }
 
 template <typename T, int D, int G>
@@ -978,9 +1123,10 @@ struct BatchPlan {
   BatchItem* items_d = nullptr;
   BatchCtl* ctl_d = nullptr;
   Offsets pred, elem, asmb, grad, energy, axpy, feat;
-  std::vector<Offsets> prep, upd;   // index 0: all free vertices, c+1: colour c
+  std::vector<Offsets> prep, prepd, fin, upd;   // index 0: all free vertices, c+1: colour c
   int max_colours = 0;
-  size_t lds = 0;
+  int tv = 0;       // vertices per workgroup of the dense condensation (0: no dense mesh)
+  size_t lds = 0;   // its dynamic LDS
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_iters = 0;
@@ -1021,9 +1167,11 @@ static void offsets_free(Offsets& o) {
 static void plan_vertex_offsets(BatchPlan* p, hipStream_t s) {
   const int G = p->cfg.G;
   p->prep.assign(p->max_colours + 1, Offsets{});
+  p->prepd.assign(p->max_colours + 1, Offsets{});
+  p->fin.assign(p->max_colours + 1, Offsets{});
   p->upd.assign(p->max_colours + 1, Offsets{});
   for (int c = -1; c < p->max_colours; ++c) {
-    std::vector<int> cp(p->nmesh), cu(p->nmesh);
+    std::vector<int> cp(p->nmesh), cd(p->nmesh), cf(p->nmesh), cu(p->nmesh);
     for (int m = 0; m < p->nmesh; ++m) {
       const BatchItem& it = p->items_h[m];
       int v0, v1;
@@ -1031,10 +1179,14 @@ static void plan_vertex_offsets(BatchPlan* p, hipStream_t s) {
       else if (c < it.ncol) { v0 = it.coff[c]; v1 = it.coff[c + 1]; }
       else { v0 = v1 = 0; }
       const int cnt = v1 - v0;
-      cp[m] = it.prep_dense ? cnt : nblocks(cnt, WG / G);
+      cp[m] = it.prep_dense ? 0 : nblocks(cnt, WG / G);
+      cd[m] = it.prep_dense ? nblocks(cnt, p->tv) : 0;
+      cf[m] = it.prep_dense ? nblocks(cnt, WG) : 0;
       cu[m] = nblocks(cnt, WG / G);
     }
     offsets_build(p->prep[c + 1], cp, s);
+    offsets_build(p->prepd[c + 1], cd, s);
+    offsets_build(p->fin[c + 1], cf, s);
     offsets_build(p->upd[c + 1], cu, s);
   }
 }
@@ -1047,6 +1199,7 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
   p->items_h.assign(items_host, items_host + nmesh);
   std::vector<int> cpred(nmesh), celem(nmesh), casm(nmesh), cgrad(nmesh), cen(nmesh), cax(nmesh),
       cfeat(nmesh);
+  int dense_nf = 0;
   for (int m = 0; m < nmesh; ++m) {
     const MeshView& mv = p->items_h[m].mv;
     cpred[m] = nblocks(mv.n, WG);
@@ -1057,10 +1210,11 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
     cax[m] = nblocks((long long)mv.D * mv.n, WG);
     cfeat[m] = nblocks(mv.nf, WG / FEAT_LANES);
     p->max_colours = std::max(p->max_colours, p->items_h[m].ncol);
-    if (p->items_h[m].prep_dense) {
-      const size_t lds = (size_t)(mv.nf - 1) * mv.D * mv.D * (cfg.prec == 0 ? 8 : 4);
-      p->lds = std::max(p->lds, lds);
-    }
+    if (p->items_h[m].prep_dense) dense_nf = std::max(dense_nf, mv.nf);
+  }
+  if (dense_nf > 0) {
+    p->tv = dense_tv(dense_nf, cfg.D, cfg.prec);
+    p->lds = dense_lds_bytes(p->tv, dense_nf, cfg.D, cfg.prec);
   }
   offsets_build(p->pred, cpred, s);
   offsets_build(p->elem, celem, s);
@@ -1082,6 +1236,8 @@ void batch_plan_destroy(BatchPlan* p) {
   drop_graph(p);
   for (Offsets* o : {&p->pred, &p->elem, &p->asmb, &p->grad, &p->energy, &p->axpy, &p->feat}) offsets_free(*o);
   for (auto& o : p->prep) offsets_free(o);
+  for (auto& o : p->prepd) offsets_free(o);
+  for (auto& o : p->fin) offsets_free(o);
   for (auto& o : p->upd) offsets_free(o);
   if (p->items_d) (void)hipFree(p->items_d);
   if (p->ctl_d) (void)hipFree(p->ctl_d);
@@ -1114,9 +1270,18 @@ static void b_energy(BatchPlan* p, int which, int dst, hipStream_t s) {
 template <typename T, int D, int G>
 static void b_prep(BatchPlan* p, int colour, hipStream_t s) {
   const Offsets& o = p->prep[colour + 1];
-  if (gridn(o) == 0) return;
+  const Offsets& od = p->prepd[colour + 1];
+  if (gridn(o) == 0 && gridn(od) == 0) return;
   p->mark(3, 1);
-  kb_prep<T, D, G><<<gridn(o), WG, p->lds, s>>>(p->items_d, p->ctl_d, o.d, p->nmesh, p->cfg.method, colour);
+  if (gridn(o) > 0)
+    kb_prep<T, D, G><<<gridn(o), WG, 0, s>>>(p->items_d, p->ctl_d, o.d, p->nmesh, p->cfg.method, colour);
+  if (gridn(od) > 0) {
+    const Offsets& of = p->fin[colour + 1];
+    CC_DISPATCH_TV(p->tv, kb_prep_dm<T, D, TV><<<gridn(od), PWG, p->lds, s>>>(
+                              p->items_d, p->ctl_d, od.d, p->nmesh, p->cfg.method, colour));
+    kb_dm_finish<T, D><<<gridn(of), WG, 0, s>>>(p->items_d, p->ctl_d, of.d, p->nmesh, p->cfg.method,
+                                               colour);
+  }
   p->mark(3, 0);
 }
 
@@ -1268,6 +1433,8 @@ void batch_set_lanes(BatchPlan* p, int G) {
   p->cfg.G = G;
   drop_graph(p);
   for (auto& o : p->prep) offsets_free(o);
+  for (auto& o : p->prepd) offsets_free(o);
+  for (auto& o : p->fin) offsets_free(o);
   for (auto& o : p->upd) offsets_free(o);
   plan_vertex_offsets(p, nullptr);
   (void)hipDeviceSynchronize();

@@ -127,3 +127,43 @@ def test_autotune_and_masking(cg, ctx):
     # iteration cap reached by every mesh, each masked at exactly the cap
     assert np.all(its <= 3) and np.all((sts == cg.CC_NOT_CONVERGED) | (sts == cg.CC_STALLED))
     assert all(np.isfinite(x.cpu().numpy()).all() for x in xs)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_bench_workload_against_oracle(cg, ctx, prec):
+    """The timed configuration of the benchmark: the four 21x6x6 bars with
+    E = 1e4 .. 1e7, exact bases built on the GPU, all bars in one batched call
+    per step with 64 lanes and two iterations per graph replay, Jacobi CC with
+    line search to rel|g| <= 1e-6; three steps against the oracle run bar by
+    bar with its own exact basis."""
+    scenes = [tet_bar(E=E) for E in (1e4, 1e5, 1e6, 1e7)]
+    mids = []
+    for s in scenes:
+        mid = cg.cc_mesh_upload(ctx, s.X, s.elems, s.fixed, s.E, s.nu, s.rho)
+        cg.cc_subspace_build(ctx, mid, 0, s.dt, False)
+        mids.append(mid)
+    cg.cc_batch_tuning(ctx, 64, 2)
+    par = cg.cc_params_default(method=cg.METHOD_CC, sweep=0, line_search=1, precision=prec,
+                               max_iters=10000)
+    op = S.Params(method=S.CC, sweep=S.JACOBI, line_search=True, max_iters=10000)
+    probs = [Problem.from_scene(s) for s in scenes]
+    bases = [exact_basis(p) for p in probs]
+    states = [s.initial_state() for s in scenes]
+    xs = [_t(x) for x, _ in states]
+    vs = [_t(v) for _, v in states]
+    grav = np.stack([s.gravity for s in scenes])
+    for t in range(1, 4):
+        bcs = [_t(s.targets(t)) for s in scenes]
+        worst, its, rgs, sts = cg.cc_step_batch(ctx, mids, xs, vs, bcs, scenes[0].dt, par, 1e-6,
+                                                gravity=grav)
+        assert worst == cg.CC_OK and np.all(rgs <= 1e-6)
+        for k, s in enumerate(scenes):
+            x, v = states[k]
+            x, v, res, _ = step(probs[k], x, v, s.targets(t), bases[k], op, 1e-6)
+            states[k] = (x, v)
+            xg = xs[k].cpu().numpy()
+            rel = np.linalg.norm(xg - x) / np.linalg.norm(x - s.X)
+            if prec == 0:
+                assert its[k] == res.iters and rel <= 1e-6, (k, t, its[k], res.iters, rel)
+            else:
+                assert abs(int(its[k]) - res.iters) <= 2 and rel <= 1e-4, (k, t, rel)

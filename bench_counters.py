@@ -1,0 +1,152 @@
+#!/usr/bin/env python
+"""HBM traffic of the dominant benchmark kernel from hardware counters.
+
+Run mode (under rocprofv3 --pmc): steps the benchmark workload (four 21x6x6
+bars, E = 1e4 .. 1e7, exact bases, batched Jacobi CC, 64 lanes) with one
+iteration per step, so that every condensation launch covers all four bars,
+then copies a buffer of known size (the calibration kernel).
+
+Summarize mode: reads the counter CSVs of a FETCH_SIZE run and a WRITE_SIZE
+run, scales each counter by the ratio of known to counted bytes of the copy
+kernel, and prints a Markdown summary with the per-launch bytes of the
+condensation kernels (kb_prep_dm + kb_dm_finish) and the hash of the kernel
+source they were measured on.  bench.py reports the traffic only while that
+hash matches the current source.
+
+    cd /tmp && export TMPDIR=/tmp
+    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/ctr_fetch -o run -- python -u $R/bench_counters.py
+    timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/ctr_write -o run -- python -u $R/bench_counters.py
+    python $R/bench_counters.py --summarize $R/gpurun_out/ctr_fetch $R/gpurun_out/ctr_write > $R/profiles/traffic_kb_prep_dm_bar21x6x6_fp64.md
+"""
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+COPY_BYTES = 512 * 1024 * 1024      # calibration copy: read and written once each
+COPY_REPS = 4
+KERNELS = ("kb_prep_dm", "kb_dm_finish")
+SOURCE = os.path.join(ROOT, "paper_2510_12053_amd", "csrc", "cc_kernels.hip")
+
+
+def source_hash():
+    with open(SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def run(steps):
+    import numpy as np
+    import torch
+    import paper_2510_12053_amd.ccgpu as cg
+    from ccscenes import tet_bar
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(stream)
+    ctx = cg.cc_create(0, stream)
+    scenes = [tet_bar(E=E) for E in (1e4, 1e5, 1e6, 1e7)]
+    mids, xs, vs = [], [], []
+    for s in scenes:
+        mid = cg.cc_mesh_upload(ctx, s.X, s.elems, s.fixed, s.E, s.nu, s.rho)
+        cg.cc_subspace_build(ctx, mid, 0, s.dt, False)
+        mids.append(mid)
+        x, v = s.initial_state()
+        xs.append(torch.tensor(x, device=dev))
+        vs.append(torch.tensor(v, device=dev))
+    cg.cc_batch_tuning(ctx, 64, 0)
+    par = cg.cc_params_default(method=cg.METHOD_CC, sweep=cg.SWEEP_JACOBI, line_search=1, max_iters=1)
+    grav = np.stack([s.gravity for s in scenes])
+    for t in range(1, steps + 1):
+        bcs = [torch.tensor(s.targets(t), device=dev) for s in scenes]
+        cg.cc_step_batch(ctx, mids, xs, vs, bcs, scenes[0].dt, par, 1e-12, gravity=grav)
+        torch.cuda.synchronize()
+        print(f"step {t} done", flush=True)
+    n = COPY_BYTES // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(COPY_REPS):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copy done", flush=True)
+    cg.cc_destroy(ctx)
+
+
+def _per_dispatch(folder, counter):
+    """{kernel base name: [bytes per dispatch]} from a counter CSV (KiB -> bytes)."""
+    out = {}
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {folder}")
+    for row in csv.DictReader(open(files[0])):
+        if row["Counter_Name"] != counter:
+            continue
+        name = row["Kernel_Name"]
+        key = None
+        for k in KERNELS:
+            if k in name:
+                key = k
+        if key is None and "copy" in name.lower():
+            key = "copy"
+        if key is None:
+            continue
+        out.setdefault(key, []).append(float(row["Counter_Value"]) * 1024.0)
+    return out
+
+
+def summarize(fetch_dir, write_dir):
+    fe = _per_dispatch(fetch_dir, "FETCH_SIZE")
+    wr = _per_dispatch(write_dir, "WRITE_SIZE")
+    # the calibration copies are the largest copy dispatches
+    cf = sorted(fe.get("copy", []))[-COPY_REPS:]
+    cw = sorted(wr.get("copy", []))[-COPY_REPS:]
+    sf = COPY_BYTES / (sum(cf) / len(cf))
+    sw = COPY_BYTES / (sum(cw) / len(cw))
+    prep_f = fe["kb_prep_dm"]
+    fin_f = fe.get("kb_dm_finish", [0.0])
+    prep_w = wr["kb_prep_dm"]
+    fin_w = wr.get("kb_dm_finish", [0.0])
+    mean = lambda v: sum(v) / len(v)
+    fetch = (mean(prep_f) + mean(fin_f)) * sf
+    write = (mean(prep_w) + mean(fin_w)) * sw
+    rec = {"kernel": "kb_prep_dm+kb_dm_finish", "workload": "bar21x6x6_Esweep", "precision": "fp64",
+           "meshes_per_launch": 4, "fetch_bytes_per_launch": round(fetch),
+           "write_bytes_per_launch": round(write), "fetch_scale": round(sf, 4),
+           "write_scale": round(sw, 4), "dispatches": len(prep_f), "source_sha256_16": source_hash()}
+    print("# HBM traffic: exact-basis condensation, four 21x6x6 bars, float64\n")
+    print("Commands (repo root `$R`, one MI355X):\n")
+    print("```")
+    print("cd /tmp && export TMPDIR=/tmp")
+    print("timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/ctr_fetch -o run -- python -u $R/bench_counters.py")
+    print("timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/ctr_write -o run -- python -u $R/bench_counters.py")
+    print("python $R/bench_counters.py --summarize $R/gpurun_out/ctr_fetch $R/gpurun_out/ctr_write")
+    print("```\n")
+    print("Every condensation launch covers all four bars (one iteration per step).  "
+          f"Counters are scaled by the calibration copy of {COPY_BYTES >> 20} MiB "
+          f"(known bytes / counted bytes): FETCH_SIZE x {sf:.4f}, WRITE_SIZE x {sw:.4f}.\n")
+    print("| kernel | dispatches | FETCH_SIZE raw (MB) | WRITE_SIZE raw (MB) |")
+    print("|---|---|---|---|")
+    print(f"| kb_prep_dm | {len(prep_f)} | {mean(prep_f) / 1e6:.2f} | {mean(prep_w) / 1e6:.3f} |")
+    print(f"| kb_dm_finish | {len(fin_f)} | {mean(fin_f) / 1e6:.3f} | {mean(fin_w) / 1e6:.3f} |")
+    print(f"| copy (calibration) | {len(cf)} | {mean(cf) / 1e6:.1f} | {mean(cw) / 1e6:.1f} |")
+    print(f"\nScaled HBM bytes per launch: fetch {fetch / 1e6:.2f} MB, write {write / 1e6:.3f} MB.\n")
+    print("traffic_json: " + json.dumps(rec))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    a = ap.parse_args()
+    if a.summarize:
+        summarize(*a.summarize)
+    else:
+        run(a.steps)
+
+
+if __name__ == "__main__":
+    main()

@@ -195,3 +195,49 @@ def test_warm_step_matches_oracle(cg, ctx, trained):
             xg.copy_(torch.tensor(x, device=DEV))
             vg.copy_(torch.tensor(v, device=DEV))
     assert any(accepted)
+
+
+def test_trained_network_gain_on_held_out(cg, ctx, trained):
+    """What the trained network gains over plain CC on held-out seeds: the
+    proposal's distance to the converged step solution against the inertial
+    predictor's, and CC iterations to rel|g| <= 1e-6 with and without the
+    warm start (same states, same tolerance).  The network must bring the
+    start closer to the solution; iterations are reported and may not grow by
+    more than half an iteration per step on average (with exact bases CC is
+    near-Newton, so little is left to gain)."""
+    cg.cc_mlp_set(ctx, trained["params"], trained["mean"], trained["istd"])
+    ratios, it_plain, it_warm, accepted = [], [], [], []
+    for seed in (2001, 2002):
+        s = warm_start_train_scene(seed)
+        nf = int((~s.fixed.astype(bool)).sum())
+        free = np.flatnonzero(~s.fixed.astype(bool))
+        mids = []
+        for _ in range(2):
+            mid = cg.cc_mesh_upload(ctx, s.X, s.elems, s.fixed, s.E, s.nu, s.rho)
+            cg.cc_subspace_build(ctx, mid, 0, s.dt, False)
+            mids.append(mid)
+        x, v = s.initial_state()
+        xg, vg = torch.tensor(x, device=DEV), torch.tensor(v, device=DEV)
+        for t in range(1, 6):
+            tg = torch.tensor(s.targets(t), device=DEV)
+            feat, xt, ell = cg.cc_mlp_features(ctx, mids[0], xg, vg, tg, s.dt, nf)
+            delta = cg.cc_mlp_forward(ctx, feat)[:, :3].double()
+            xprop = xt.clone()
+            xprop[free] = xt[free] + ell * delta
+            xw, vw = xg.clone(), vg.clone()
+            par0 = cg.cc_params_default(warm_start=0, gravity=s.gravity, max_iters=10000)
+            par1 = cg.cc_params_default(warm_start=1, gravity=s.gravity, max_iters=10000)
+            st0, i0, _ = cg.cc_step(ctx, mids[0], xg, vg, tg, s.dt, par0, 1e-6)
+            st1, i1, _ = cg.cc_step(ctx, mids[1], xw, vw, tg, s.dt, par1, 1e-6)
+            assert st0 == cg.CC_OK and st1 == cg.CC_OK
+            xs = xg[free]
+            ratios.append(float(torch.linalg.norm(xprop[free] - xs) / torch.linalg.norm(xt[free] - xs)))
+            it_plain.append(i0)
+            it_warm.append(i1)
+            accepted.append(cg.cc_step_info(ctx, mids[1])["warm_accepted"])
+    ratios = np.array(ratios)
+    print(f"\nheld-out steps {len(ratios)}: |x_prop - x*| / |x_pred - x*| median {np.median(ratios):.3f}, "
+          f"iterations plain {np.mean(it_plain):.2f} warm {np.mean(it_warm):.2f}, "
+          f"accepted {sum(accepted)}/{len(accepted)}")
+    assert np.median(ratios) < 0.8
+    assert np.mean(it_warm) <= np.mean(it_plain) + 0.5

@@ -35,6 +35,7 @@ struct Mesh {
       *d_eperm = nullptr;
   int4* seg = nullptr;  // upper-triangle block segments of the dense condensation
   int nseg = 0;
+
   double *dinv_d = nullptr, *vol_d = nullptr, *mass = nullptr;
   float *dinv_f = nullptr, *vol_f = nullptr;
   // basis
@@ -777,6 +778,15 @@ struct Stepper {
   void prep(int method, int v0, int v1) {
     ctx->timed(CC_K_CC_PREP, [&] { cc::launch_cc_prep(mv, p.precision, method, v0, v1, M.hb, M.KL, M.fb, s); });
   }
+  // Condensation that also writes the Jacobi directions into out when the
+  // dense path can (g must hold the gradient at the same x); false: call update.
+  bool prep_direction(int method, double* out) {
+    bool done = false;
+    ctx->timed(CC_K_CC_PREP, [&] {
+      done = cc::launch_cc_prep(mv, p.precision, method, 0, M.nf, M.hb, M.KL, M.fb, s, M.g, out);
+    });
+    return done;
+  }
   void update(int method, int v0, int v1, double* out, int acc) {
     ctx->timed(CC_K_CC_UPDATE, [&] { cc::launch_cc_update(mv, p.precision, method, v0, v1, M.KL, M.g, out, acc, s); });
   }
@@ -785,9 +795,8 @@ struct Stepper {
     const int nd = M.D * M.n;
     if (p.sweep == CC_SWEEP_JACOBI) {
       hessian(x);
-      prep(method, 0, M.nf);
       gradient_only(x);
-      update(method, 0, M.nf, M.dvec, 0);
+      if (!prep_direction(method, M.dvec)) update(method, 0, M.nf, M.dvec, 0);
       cc::launch_axpy(nd, x, M.dvec, 1.0, out, s);
       return;
     }
@@ -1195,8 +1204,8 @@ cc_status cc_probe_sweep(cc_ctx* ctx, int32_t mesh_id, const double* x, const do
     if (dx) {
       S.hessian(M.x);
       HIPC(hipMemsetAsync(M.fb, 0, 4 * sizeof(unsigned long long), s));
-      cc::launch_cc_prep(S.mv, p.precision, p.method, 0, M.nf, M.hb, M.KL, M.fb, s);
-      cc::launch_cc_update(S.mv, p.precision, p.method, 0, M.nf, M.KL, M.g, M.dvec, 0, s);
+      if (!cc::launch_cc_prep(S.mv, p.precision, p.method, 0, M.nf, M.hb, M.KL, M.fb, s, M.g, M.dvec))
+        cc::launch_cc_update(S.mv, p.precision, p.method, 0, M.nf, M.KL, M.g, M.dvec, 0, s);
       cc::launch_scatter_user(S.mv, M.d_vperm, M.dvec, dx, 1, s);
     }
     HIPC(hipStreamSynchronize(s));

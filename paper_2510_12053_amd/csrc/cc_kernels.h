@@ -58,8 +58,12 @@ void launch_assemble(const MeshView& mv, int prec, const void* estore, const Mat
                      void* hb, hipStream_t s);
 void launch_gradient(const MeshView& mv, const double* x, const double* xt, const Material& mat,
                      double* g, double* partials, int* nparts, hipStream_t s);
-void launch_cc_prep(const MeshView& mv, int prec, int method, int v0, int v1, const void* hb,
-                    void* KL, unsigned long long* fallbacks, hipStream_t s);
+// Condensation of vertices [v0, v1).  With g and dout given (a Jacobi sweep,
+// g the gradient at the same x) the dense path also writes the directions
+// into dout; the return value says whether it did (else launch_cc_update).
+bool launch_cc_prep(const MeshView& mv, int prec, int method, int v0, int v1, const void* hb,
+                    void* KL, unsigned long long* fallbacks, hipStream_t s,
+                    const double* g = nullptr, double* dout = nullptr);
 void launch_cc_update(const MeshView& mv, int prec, int method, int v0, int v1, const void* KL,
                       const double* g, double* x_or_d, int accumulate, hipStream_t s);
 void launch_energy(const MeshView& mv, const double* x, const double* xt, const Material& mat,

@@ -73,10 +73,15 @@ __device__ __forceinline__ void elem_hess_body(const MeshView& mv, int e, const 
     for (int r = 0; r < DD; ++r) out[((size_t)p * m + e) * DD + r] = f * acc[p][r];
 }
 
+// Element and assembly kernels run one thread per element / block slot in
+// 64-thread workgroups: a few thousand elements then spread over most CUs
+// instead of a few dozen (the per-element work is a long serial chain).
+constexpr int EWG = 64;
+
 template <typename T, int D>
-__global__ void __launch_bounds__(WG) k_elem_hess(MeshView mv, const double* __restrict__ x, T mu,
-                                                  T lam, T scale, T* __restrict__ out) {
-  elem_hess_body<T, D>(mv, blockIdx.x * WG + threadIdx.x, x, mu, lam, scale, out);
+__global__ void __launch_bounds__(EWG) k_elem_hess(MeshView mv, const double* __restrict__ x, T mu,
+                                                   T lam, T scale, T* __restrict__ out) {
+  elem_hess_body<T, D>(mv, blockIdx.x * EWG + threadIdx.x, x, mu, lam, scale, out);
 }
 
 // Block rows: every slot sums its element contributions (fixed order), plus
@@ -116,9 +121,9 @@ __device__ __forceinline__ void assemble_body(const MeshView& mv, int t, const T
 }
 
 template <typename T, int D>
-__global__ void __launch_bounds__(WG) k_assemble(MeshView mv, const T* __restrict__ est, T w_in,
-                                                 T* __restrict__ hb) {
-  assemble_body<T, D>(mv, blockIdx.x * WG + threadIdx.x, est, w_in, hb);
+__global__ void __launch_bounds__(EWG) k_assemble(MeshView mv, const T* __restrict__ est, T w_in,
+                                                  T* __restrict__ hb) {
+  assemble_body<T, D>(mv, blockIdx.x * EWG + threadIdx.x, est, w_in, hb);
 }
 
 // Free-vertex gradient in float64: G lanes per vertex share its star.
@@ -232,14 +237,20 @@ __global__ void __launch_bounds__(WG) k_cc_prep(MeshView mv, int method, int v0,
 // A_i = sum_k H_ik U_i[k] comes from row i (one wave per vertex).
 constexpr int PWG = 512;   // threads of the dense multi-vertex condensation
 
+//
+// With g given (Jacobi sweeps), b_i = U_i^T g_C is also formed from the staged
+// row and stored in bout (vertex-major components, stride n); the finish
+// kernel then writes the direction itself, so the update kernel's second pass
+// over the basis is not needed.
 template <typename T, int D, int TV>
 __device__ __forceinline__ void prep_dm_body(const MeshView& mv, int method, int i0, int nv,
                                              const T* __restrict__ hb, T* __restrict__ KL,
-                                             unsigned long long* __restrict__ fb, T* smem) {
-  constexpr int DD = D * D, NW = PWG / 64;
+                                             unsigned long long* __restrict__ fb, T* smem,
+                                             const double* __restrict__ g, double* __restrict__ bout) {
+  constexpr int DD = D * D, NW = PWG / 64, NR = DD + D;
   const int nf = mv.nf;
   T* Us = smem;                                   // [TV][nf][DD]
-  T* red = smem + (size_t)TV * nf * DD;           // [NW + 1][TV][DD]
+  T* red = smem + (size_t)TV * nf * DD;           // [NW + 1][TV][DD + D]
   const T* Ub = basis_of<T>(mv);
   // stage the rows: many independent loads in flight per thread, then the
   // LDS stores (one workgroup per CU leaves nothing else to hide the latency).
@@ -331,24 +342,54 @@ __device__ __forceinline__ void prep_dm_body(const MeshView& mv, int method, int
       }
     }
   }
+  T Bv[TV][D];
+#pragma unroll
+  for (int v = 0; v < TV; ++v)
+#pragma unroll
+    for (int r = 0; r < D; ++r) Bv[v][r] = T(0);
+  if (method != 0 && g != nullptr) {             // b = sum_j U_j^T g_j (U_i[i] = 0)
+    const int n = mv.n;
+    for (int j = threadIdx.x; j < nf; j += PWG) {
+      T gj[D];
+#pragma unroll
+      for (int c = 0; c < D; ++c) gj[c] = T(gptr(g)[c * n + j]);
+#pragma unroll
+      for (int v = 0; v < TV; ++v) {
+        const T* u = Us + ((size_t)v * nf + j) * DD;
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+          T acc = T(0);
+#pragma unroll
+          for (int l = 0; l < D; ++l) acc += u[l * D + r] * gj[l];
+          Bv[v][r] += acc;
+        }
+      }
+    }
+  }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-    for (int v = 0; v < TV; ++v)
+    for (int v = 0; v < TV; ++v) {
 #pragma unroll
       for (int r = 0; r < DD; ++r) Y[v][r] += __shfl_xor(Y[v][r], off, 64);
+#pragma unroll
+      for (int r = 0; r < D; ++r) Bv[v][r] += __shfl_xor(Bv[v][r], off, 64);
+    }
   const int w = threadIdx.x / 64, l = threadIdx.x % 64;
   if (l == 0)
 #pragma unroll
-    for (int v = 0; v < TV; ++v)
+    for (int v = 0; v < TV; ++v) {
 #pragma unroll
-      for (int r = 0; r < DD; ++r) red[(w * TV + v) * DD + r] = Y[v][r];
+      for (int r = 0; r < DD; ++r) red[(w * TV + v) * NR + r] = Y[v][r];
+#pragma unroll
+      for (int r = 0; r < D; ++r) red[(w * TV + v) * NR + DD + r] = Bv[v][r];
+    }
   __syncthreads();
-  if (threadIdx.x < TV * DD) {
+  if (threadIdx.x < TV * NR) {
     T acc = T(0);
 #pragma unroll
-    for (int ww = 0; ww < NW; ++ww) acc += red[ww * TV * DD + threadIdx.x];
-    red[NW * TV * DD + threadIdx.x] = acc;
+    for (int ww = 0; ww < NW; ++ww) acc += red[ww * TV * NR + threadIdx.x];
+    red[NW * TV * NR + threadIdx.x] = acc;
   }
   __syncthreads();
   if (w >= nv) return;
@@ -381,7 +422,7 @@ __device__ __forceinline__ void prep_dm_body(const MeshView& mv, int method, int
   // A and Ht go to the vertex's K, L slots; dm_finish_body turns them into
   // K and L with one thread per vertex (the small solves are latency-bound
   // and would otherwise serialise the single workgroup resident per CU)
-  const T* Yt = red + (NW * TV + w) * DD;
+  const T* Yt = red + (NW * TV + w) * NR;
   auto* out = gptr_w(KL) + (size_t)i * 2 * DD;
 #pragma unroll
   for (int r = 0; r < D; ++r)
@@ -390,12 +431,18 @@ __device__ __forceinline__ void prep_dm_body(const MeshView& mv, int method, int
       out[r * D + c] = A[r * D + c];
       out[DD + r * D + c] = Yt[r * D + c] + Yt[c * D + r];
     }
+  if (bout != nullptr)
+#pragma unroll
+    for (int r = 0; r < D; ++r) gptr_w(bout)[(size_t)r * mv.n + i] = double(Yt[DD + r]);
 }
 
+// With dout given, dout holds b_i on entry and receives dx_i = -K (g_i - L b_i)
+// (the arithmetic of update_body).
 template <typename T, int D>
 __device__ __forceinline__ void dm_finish_body(const MeshView& mv, int method, int i,
                                                const T* __restrict__ hb, T* __restrict__ KL,
-                                               unsigned long long* __restrict__ fb) {
+                                               unsigned long long* __restrict__ fb,
+                                               const double* __restrict__ g, double* __restrict__ dout) {
   constexpr int DD = D * D;
   T A[DD], Ht[DD];
   const T* in = KL + (size_t)i * 2 * DD;
@@ -405,23 +452,46 @@ __device__ __forceinline__ void dm_finish_body(const MeshView& mv, int method, i
     Ht[r] = in[DD + r];
   }
   cc_finish<T, D>(mv, method, i, mv.nf <= 1, A, Ht, hb, KL, fb);
+  if (dout == nullptr) return;
+  const int n = mv.n;
+  const T* kl = KL + (size_t)i * 2 * DD;
+  T b[D], gt[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) b[c] = T(dout[(size_t)c * n + i]);
+#pragma unroll
+  for (int r = 0; r < D; ++r) {
+    T lb = T(0);
+#pragma unroll
+    for (int l = 0; l < D; ++l) lb += kl[DD + r * D + l] * b[l];
+    gt[r] = T(g[(size_t)r * n + i] - double(lb));
+  }
+#pragma unroll
+  for (int r = 0; r < D; ++r) {
+    T acc = T(0);
+#pragma unroll
+    for (int l = 0; l < D; ++l) acc += kl[r * D + l] * gt[l];
+    dout[(size_t)r * n + i] = -double(acc);
+  }
 }
 
 template <typename T, int D>
 __global__ void __launch_bounds__(WG) k_cc_dm_finish(MeshView mv, int method, int v0, int v1,
                                                      const T* __restrict__ hb, T* __restrict__ KL,
-                                                     unsigned long long* __restrict__ fb) {
+                                                     unsigned long long* __restrict__ fb,
+                                                     const double* __restrict__ g, double* __restrict__ dout) {
   const int i = v0 + blockIdx.x * WG + threadIdx.x;
-  if (i < v1) dm_finish_body<T, D>(mv, method, i, hb, KL, fb);
+  if (i < v1) dm_finish_body<T, D>(mv, method, i, hb, KL, fb, g, dout);
 }
 
 template <typename T, int D, int TV>
 __global__ void __launch_bounds__(PWG) k_cc_prep_dm(MeshView mv, int method, int v0, int v1,
                                                     const T* __restrict__ hb, T* __restrict__ KL,
-                                                    unsigned long long* __restrict__ fb) {
+                                                    unsigned long long* __restrict__ fb,
+                                                    const double* __restrict__ g, double* __restrict__ bout) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int i0 = v0 + blockIdx.x * TV;
-  prep_dm_body<T, D, TV>(mv, method, i0, min(TV, v1 - i0), hb, KL, fb, reinterpret_cast<T*>(smem_raw));
+  prep_dm_body<T, D, TV>(mv, method, i0, min(TV, v1 - i0), hb, KL, fb, reinterpret_cast<T*>(smem_raw),
+                         g, bout);
 }
 
 
@@ -665,12 +735,12 @@ void launch_finalize(const MeshView& mv, const int* vperm, const double* x, cons
 void launch_elem_hess(const MeshView& mv, int prec, const double* x, const Material& mat,
                       double scale, void* estore, hipStream_t s) {
   if (mv.m == 0) return;
-  const int nb = nblocks(mv.m, WG);
+  const int nb = nblocks(mv.m, EWG);
   if (prec == 0)
-    CC_DISPATCH_D(mv.D, k_elem_hess<double, D><<<nb, WG, 0, s>>>(mv, x, mat.mu, mat.lam, scale,
+    CC_DISPATCH_D(mv.D, k_elem_hess<double, D><<<nb, EWG, 0, s>>>(mv, x, mat.mu, mat.lam, scale,
                                                                 (double*)estore));
   else
-    CC_DISPATCH_D(mv.D, k_elem_hess<float, D><<<nb, WG, 0, s>>>(mv, x, (float)mat.mu,
+    CC_DISPATCH_D(mv.D, k_elem_hess<float, D><<<nb, EWG, 0, s>>>(mv, x, (float)mat.mu,
                                                                (float)mat.lam, (float)scale,
                                                                (float*)estore));
 }
@@ -678,12 +748,12 @@ void launch_elem_hess(const MeshView& mv, int prec, const double* x, const Mater
 void launch_assemble(const MeshView& mv, int prec, const void* estore, const Material& mat,
                      void* hb, hipStream_t s) {
   if (mv.nnzb == 0) return;
-  const int nb = nblocks(mv.nnzb, WG);
+  const int nb = nblocks(mv.nnzb, EWG);
   if (prec == 0)
-    CC_DISPATCH_D(mv.D, k_assemble<double, D><<<nb, WG, 0, s>>>(mv, (const double*)estore,
+    CC_DISPATCH_D(mv.D, k_assemble<double, D><<<nb, EWG, 0, s>>>(mv, (const double*)estore,
                                                                mat.w_in, (double*)hb));
   else
-    CC_DISPATCH_D(mv.D, k_assemble<float, D><<<nb, WG, 0, s>>>(mv, (const float*)estore,
+    CC_DISPATCH_D(mv.D, k_assemble<float, D><<<nb, EWG, 0, s>>>(mv, (const float*)estore,
                                                               (float)mat.w_in, (float*)hb));
 }
 
@@ -728,7 +798,7 @@ void set_lds_limit(size_t bytes) { g_lds_limit = bytes; }
 
 size_t dense_lds_bytes(int tv, int nf, int D, int prec) {
   const size_t S = prec == 0 ? 8 : 4;
-  return ((size_t)tv * nf + (size_t)(PWG / 64 + 1) * tv) * D * D * S;
+  return ((size_t)tv * nf * D * D + (size_t)(PWG / 64 + 1) * tv * (D * D + D)) * S;
 }
 
 int dense_tv(int nf, int D, int prec) {
@@ -749,26 +819,30 @@ int dense_tv(int nf, int D, int prec) {
 
 template <typename T, int D>
 static bool prep_dense(const MeshView& mv, int prec, int method, int v0, int v1, const void* hb,
-                       void* KL, unsigned long long* fb, hipStream_t s) {
+                       void* KL, unsigned long long* fb, const double* g, double* dout, hipStream_t s) {
   const int tv = mv.dense_supp && mv.nseg > 0 ? dense_tv(mv.nf, D, prec) : 0;
   if (tv == 0) return false;
   const size_t lds = dense_lds_bytes(tv, mv.nf, D, prec);
   CC_DISPATCH_TV(tv, k_cc_prep_dm<T, D, TV><<<nblocks(v1 - v0, TV), PWG, lds, s>>>(
-                         mv, method, v0, v1, (const T*)hb, (T*)KL, fb));
-  k_cc_dm_finish<T, D><<<nblocks(v1 - v0, WG), WG, 0, s>>>(mv, method, v0, v1, (const T*)hb, (T*)KL, fb);
+                         mv, method, v0, v1, (const T*)hb, (T*)KL, fb, g, dout));
+  k_cc_dm_finish<T, D><<<nblocks(v1 - v0, WG), WG, 0, s>>>(mv, method, v0, v1, (const T*)hb, (T*)KL, fb,
+                                                          g, dout);
   return true;
 }
 
-void launch_cc_prep(const MeshView& mv, int prec, int method, int v0, int v1, const void* hb,
-                    void* KL, unsigned long long* fb, hipStream_t s) {
-  if (v1 <= v0) return;
+bool launch_cc_prep(const MeshView& mv, int prec, int method, int v0, int v1, const void* hb,
+                    void* KL, unsigned long long* fb, hipStream_t s, const double* g, double* dout) {
+  if (v1 <= v0) return g != nullptr;
   bool done = false;
-  if (prec == 0) CC_DISPATCH_D(mv.D, done = prep_dense<double, D>(mv, prec, method, v0, v1, hb, KL, fb, s));
-  else CC_DISPATCH_D(mv.D, done = prep_dense<float, D>(mv, prec, method, v0, v1, hb, KL, fb, s));
-  if (done) return;
+  if (prec == 0)
+    CC_DISPATCH_D(mv.D, done = prep_dense<double, D>(mv, prec, method, v0, v1, hb, KL, fb, g, dout, s));
+  else
+    CC_DISPATCH_D(mv.D, done = prep_dense<float, D>(mv, prec, method, v0, v1, hb, KL, fb, g, dout, s));
+  if (done) return g != nullptr;
   const int G = support_lanes(mv);
   if (prec == 0) CC_DISPATCH_D(mv.D, prep_g<double, D>(mv, method, v0, v1, hb, KL, fb, G, s));
   else CC_DISPATCH_D(mv.D, prep_g<float, D>(mv, method, v0, v1, hb, KL, fb, G, s));
+  return false;
 }
 
 template <typename T, int D>
@@ -917,26 +991,26 @@ __global__ void __launch_bounds__(WG) kb_finalize(const BatchItem* __restrict__ 
 }
 
 template <typename T, int D>
-__global__ void __launch_bounds__(WG) kb_elem_hess(const BatchItem* __restrict__ items,
+__global__ void __launch_bounds__(EWG) kb_elem_hess(const BatchItem* __restrict__ items,
                                                    const BatchCtl* __restrict__ ctl,
                                                    const int* __restrict__ boff, int nmesh, int which) {
   const int mi = block_mesh(boff, nmesh, blockIdx.x);
   if (!ctl[mi].active) return;
   const BatchItem& it = items[mi];
   const MeshView mv = it.mv;
-  elem_hess_body<T, D>(mv, (blockIdx.x - boff[mi]) * WG + threadIdx.x, pick(it, which), T(it.mat.mu),
+  elem_hess_body<T, D>(mv, (blockIdx.x - boff[mi]) * EWG + threadIdx.x, pick(it, which), T(it.mat.mu),
                        T(it.mat.lam), T(it.mat.s_el), (T*)it.estore);
 }
 
 template <typename T, int D>
-__global__ void __launch_bounds__(WG) kb_assemble(const BatchItem* __restrict__ items,
+__global__ void __launch_bounds__(EWG) kb_assemble(const BatchItem* __restrict__ items,
                                                   const BatchCtl* __restrict__ ctl,
                                                   const int* __restrict__ boff, int nmesh) {
   const int mi = block_mesh(boff, nmesh, blockIdx.x);
   if (!ctl[mi].active) return;
   const BatchItem& it = items[mi];
   const MeshView mv = it.mv;
-  assemble_body<T, D>(mv, (blockIdx.x - boff[mi]) * WG + threadIdx.x, (const T*)it.estore,
+  assemble_body<T, D>(mv, (blockIdx.x - boff[mi]) * EWG + threadIdx.x, (const T*)it.estore,
                       T(it.mat.w_in), (T*)it.hb);
 }
 
@@ -976,7 +1050,7 @@ template <typename T, int D, int TV>
 __global__ void __launch_bounds__(PWG) kb_prep_dm(const BatchItem* __restrict__ items,
                                                   const BatchCtl* __restrict__ ctl,
                                                   const int* __restrict__ boff, int nmesh,
-                                                  int method, int colour) {
+                                                  int method, int colour, int fuse) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int mi = block_mesh(boff, nmesh, blockIdx.x);
   if (!ctl[mi].active) return;
@@ -985,21 +1059,24 @@ __global__ void __launch_bounds__(PWG) kb_prep_dm(const BatchItem* __restrict__ 
   vertex_range(it, colour, v0, v1);
   const int i0 = v0 + (blockIdx.x - boff[mi]) * TV;
   prep_dm_body<T, D, TV>(it.mv, method, i0, min(TV, v1 - i0), (const T*)it.hb, (T*)it.KL, it.fb,
-                         reinterpret_cast<T*>(smem_raw));
+                         reinterpret_cast<T*>(smem_raw), fuse ? it.g : nullptr,
+                         fuse ? it.d : nullptr);
 }
 
 template <typename T, int D>
 __global__ void __launch_bounds__(WG) kb_dm_finish(const BatchItem* __restrict__ items,
                                                    const BatchCtl* __restrict__ ctl,
                                                    const int* __restrict__ boff, int nmesh,
-                                                   int method, int colour) {
+                                                   int method, int colour, int fuse) {
   const int mi = block_mesh(boff, nmesh, blockIdx.x);
   if (!ctl[mi].active) return;
   const BatchItem& it = items[mi];
   int v0, v1;
   vertex_range(it, colour, v0, v1);
   const int i = v0 + (blockIdx.x - boff[mi]) * WG + threadIdx.x;
-  if (i < v1) dm_finish_body<T, D>(it.mv, method, i, (const T*)it.hb, (T*)it.KL, it.fb);
+  if (i < v1)
+    dm_finish_body<T, D>(it.mv, method, i, (const T*)it.hb, (T*)it.KL, it.fb, fuse ? it.g : nullptr,
+                         fuse ? it.d : nullptr);
 }
 
 template <typename T, int D, int G>
@@ -1182,7 +1259,8 @@ static void plan_vertex_offsets(BatchPlan* p, hipStream_t s) {
       cp[m] = it.prep_dense ? 0 : nblocks(cnt, WG / G);
       cd[m] = it.prep_dense ? nblocks(cnt, p->tv) : 0;
       cf[m] = it.prep_dense ? nblocks(cnt, WG) : 0;
-      cu[m] = nblocks(cnt, WG / G);
+      // Jacobi: dense meshes get their direction from the fused condensation
+      cu[m] = (c < 0 && p->cfg.sweep == 0 && it.prep_dense) ? 0 : nblocks(cnt, WG / G);
     }
     offsets_build(p->prep[c + 1], cp, s);
     offsets_build(p->prepd[c + 1], cd, s);
@@ -1203,8 +1281,8 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
   for (int m = 0; m < nmesh; ++m) {
     const MeshView& mv = p->items_h[m].mv;
     cpred[m] = nblocks(mv.n, WG);
-    celem[m] = nblocks(mv.m, WG);
-    casm[m] = nblocks(mv.nnzb, WG);
+    celem[m] = nblocks(mv.m, EWG);
+    casm[m] = nblocks(mv.nnzb, EWG);
     cgrad[m] = nblocks(mv.nf, WG / GRAD_G);
     cen[m] = nblocks(mv.m, WG) + nblocks(mv.nf, WG);
     cax[m] = nblocks((long long)mv.D * mv.n, WG);
@@ -1268,7 +1346,7 @@ static void b_energy(BatchPlan* p, int which, int dst, hipStream_t s) {
 }
 
 template <typename T, int D, int G>
-static void b_prep(BatchPlan* p, int colour, hipStream_t s) {
+static void b_prep(BatchPlan* p, int colour, hipStream_t s, int fuse = 0) {
   const Offsets& o = p->prep[colour + 1];
   const Offsets& od = p->prepd[colour + 1];
   if (gridn(o) == 0 && gridn(od) == 0) return;
@@ -1278,9 +1356,9 @@ static void b_prep(BatchPlan* p, int colour, hipStream_t s) {
   if (gridn(od) > 0) {
     const Offsets& of = p->fin[colour + 1];
     CC_DISPATCH_TV(p->tv, kb_prep_dm<T, D, TV><<<gridn(od), PWG, p->lds, s>>>(
-                              p->items_d, p->ctl_d, od.d, p->nmesh, p->cfg.method, colour));
+                              p->items_d, p->ctl_d, od.d, p->nmesh, p->cfg.method, colour, fuse));
     kb_dm_finish<T, D><<<gridn(of), WG, 0, s>>>(p->items_d, p->ctl_d, of.d, p->nmesh, p->cfg.method,
-                                               colour);
+                                               colour, fuse);
   }
   p->mark(3, 0);
 }
@@ -1299,12 +1377,12 @@ template <typename T, int D>
 static void b_hessian(BatchPlan* p, int which, hipStream_t s) {
   if (gridn(p->elem) > 0) {
     p->mark(0, 1);
-    kb_elem_hess<T, D><<<gridn(p->elem), WG, 0, s>>>(p->items_d, p->ctl_d, p->elem.d, p->nmesh, which);
+    kb_elem_hess<T, D><<<gridn(p->elem), EWG, 0, s>>>(p->items_d, p->ctl_d, p->elem.d, p->nmesh, which);
     p->mark(0, 0);
   }
   if (gridn(p->asmb) > 0) {
     p->mark(1, 1);
-    kb_assemble<T, D><<<gridn(p->asmb), WG, 0, s>>>(p->items_d, p->ctl_d, p->asmb.d, p->nmesh);
+    kb_assemble<T, D><<<gridn(p->asmb), EWG, 0, s>>>(p->items_d, p->ctl_d, p->asmb.d, p->nmesh);
     p->mark(1, 0);
   }
 }
@@ -1314,8 +1392,10 @@ static void b_iteration(BatchPlan* p, hipStream_t s) {
   const BatchConfig& c = p->cfg;
   const int nm = p->nmesh, gb = nblocks(nm, WG);
   if (c.sweep == 0) {
+    // g holds the gradient at x (from batch_begin or the end of the previous
+    // iteration), so the dense condensation forms the direction itself
     b_hessian<T, D>(p, 0, s);
-    b_prep<T, D, G>(p, -1, s);
+    b_prep<T, D, G>(p, -1, s, 1);
     b_update<T, D, G>(p, -1, 0, s);
     if (gridn(p->axpy) > 0)
       kb_axpy<<<gridn(p->axpy), WG, 0, s>>>(p->items_d, p->ctl_d, p->axpy.d, nm, 1.0, 0);
@@ -1446,7 +1526,7 @@ float batch_time_prep_update(BatchPlan* p, int G, int reps, hipStream_t s) {
   hipEvent_t a, b;
   (void)hipEventCreate(&a);
   (void)hipEventCreate(&b);
-#define PU(T, D, GG) do { b_prep<T, D, GG>(p, -1, s); b_update<T, D, GG>(p, -1, 0, s); } while (0)
+#define PU(T, D, GG) do { b_prep<T, D, GG>(p, -1, s, p->cfg.sweep == 0); b_update<T, D, GG>(p, -1, 0, s); } while (0)
   auto run = [&]() {
     const BatchConfig& c = p->cfg;
     if (c.prec == 0) {

@@ -174,6 +174,11 @@ struct cc_ctx {
   }
   cc::BatchPlan* plan = nullptr;
   std::vector<int> plan_ids;
+  // iterations the previous step of this plan needed (most iterating mesh):
+  // the next step starts with that many iterations queued before the first
+  // host check (finished meshes are masked on the device, so extra queued
+  // iterations cost only their launches)
+  int plan_prev_iters = 0;
   std::vector<double> plan_key;
 
   hipEvent_t take_event() {
@@ -1293,6 +1298,7 @@ static cc::BatchPlan* batch_plan_for(cc_ctx* ctx, const std::vector<Mesh*>& ms, 
   cfg.G = ctx->batch_lanes; cfg.iters_per_graph = ctx->batch_iters_per_graph;
   ctx->plan = cc::batch_plan_create(items.data(), n, cfg, ctx->stream);
   ctx->plan_ids = idv;
+  ctx->plan_prev_iters = 0;
   ctx->plan_key = key;
   return ctx->plan;
 }
@@ -1423,11 +1429,13 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
     for (int i = 0; i < n; ++i)
       if (ctl[i].bad) return fail(ctx, CC_E_NONFINITE, "non-finite x, v or x_bc in batch");
     long long guard = 0;
+    int queue = std::min(std::max(ctx->plan_prev_iters, k), 16);   // first round
     while (true) {
       bool any = false;
       for (auto& c : ctl) any = any || c.active;
       if (!any) break;
-      cc::batch_iterate(plan, k, s);
+      cc::batch_iterate(plan, (queue + k - 1) / k * k, s);
+      queue = k;
       if (!cc::batch_has_graph(plan) && !ctx->graph_pairs.empty()) ctx->drop_graph_pairs();
       pull_ctl();
       ctx->harvest();
@@ -1448,6 +1456,8 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
       if (++guard > (long long)p.max_iters + 16) break;  // every replay advances every active mesh
     }
     cc::batch_finish(plan, s);
+    ctx->plan_prev_iters = 0;
+    for (auto& c : ctl) ctx->plan_prev_iters = std::max(ctx->plan_prev_iters, c.iters);
     HIPC(hipMemcpyAsync(items.data(), items_d, n * sizeof(cc::BatchItem), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     ctx->harvest();

@@ -6,6 +6,11 @@ bars, E = 1e4 .. 1e7, exact bases, batched Jacobi CC, 64 lanes) with one
 iteration per step, so that every condensation launch covers all four bars,
 then copies a buffer of known size (the calibration kernel).
 
+Trace-summary mode: Markdown table of a `rocprofv3 --kernel-trace --stats`
+run of bench.py, with the condensation kernels' average over the last
+dispatches (the uncaptured region bench.py times with HIP events) beside the
+figure bench.py printed.
+
 Summarize mode: reads the counter CSVs of a FETCH_SIZE run and a WRITE_SIZE
 run, scales each counter by the ratio of known to counted bytes of the copy
 kernel, and prints a Markdown summary with the per-launch bytes of the
@@ -137,13 +142,59 @@ def summarize(fetch_dir, write_dir):
     print("traffic_json: " + json.dumps(rec))
 
 
+TRACE_CMD = ("cd /tmp && export TMPDIR=/tmp && timeout -k 10 600 rocprofv3 --kernel-trace --stats "
+             "--output-format csv -d $R/gpurun_out/kt_bench -o run -- python -u $R/bench.py --no-cpu-baseline")
+
+
+def trace_summary(folder, bench_log):
+    stats = glob.glob(os.path.join(folder, "**", "*kernel_stats.csv"), recursive=True)[0]
+    trace = glob.glob(os.path.join(folder, "**", "*kernel_trace.csv"), recursive=True)[0]
+    rows = list(csv.DictReader(open(stats)))
+    disp = list(csv.DictReader(open(trace)))
+    b = json.loads([l for l in open(bench_log) if l.startswith("{")][-1])
+    ro = b["roofline"]
+    print("# Kernel statistics: four 21x6x6 bars (E = 1e4 .. 1e7), float64, plain / batched / "
+          "learned+batched CC\n")
+    print("Command (repo root `$R`, one MI355X):\n")
+    print("```\n" + TRACE_CMD + "\n```\n")
+    print("The profiled process runs the whole bench: warm-start data generation and training, the "
+          "timed regions of plain CC (`k_*`), batched and learned+batched CC (`kb_*`, graph replays), "
+          "and the learned+batched launches once more uncaptured with HIP events.\n")
+    print("| kernel | calls | avg (us) | min (us) | max (us) | share |")
+    print("|---|---|---|---|---|---|")
+    for r in rows[:24]:
+        name = r["Name"][:100].replace("|", "/")
+        print(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+              f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+              f"{float(r['Percentage']):.2f}% |")
+
+    def last(key, n):
+        v = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+             for r in disp if key in r["Kernel_Name"]]
+        v = v[-n:]
+        return sum(v) / max(len(v), 1)
+    n = ro["launches"]
+    lp, lf = last("kb_prep_dm", n), last("kb_dm_finish", n)
+    print(f"\nDominant kernels of the timed path: `kb_prep_dm` + `kb_dm_finish` (exact-basis "
+          f"condensation).  Their last {n} dispatches (the uncaptured learned+batched region) average "
+          f"{lp:.1f} + {lf:.1f} = {lp + lf:.1f} us per pair; bench.py's HIP-event average of the "
+          f"same launches in this run: {ro['avg_launch_us']} us.\n")
+    sel = {k: b[k] for k in ("value", "ms_per_step", "learned_batched", "batched", "plain_cc",
+                             "roofline") if k in b}
+    print("bench.py line of the profiled run (selected fields):\n\n```\n" + json.dumps(sel, indent=1)
+          + "\n```")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "BENCH_LOG"))
     a = ap.parse_args()
     if a.summarize:
         summarize(*a.summarize)
+    elif a.trace_summary:
+        trace_summary(*a.trace_summary)
     else:
         run(a.steps)
 

@@ -30,6 +30,16 @@ Sweeps:
   once at the start of the sweep (HESS_SWEEP, an explicit lagged-Hessian
   mode).  The colour's vertices then move simultaneously.
 
+Corotated basis (Method, Accounting for Large Deformations, Eq. rotation),
+with params.corotate: wherever g and H are evaluated, every basis block is
+rotated, U_i^rot[j] = R_j U_i[j], with R_j the rotation factor of the polar
+decomposition of sum_{k in N(j)} (x_k - x_j)(X_k - X_j)^T over the mesh
+neighbours of j (this package's reading of "the displacement of the
+neighbourhood").  Pins: tests/test_oracle_corotation.py -- the polar factor
+against M (M^T M)^(-1/2), rigid motions give R_j = Q, identity at rest,
+rotation equivariance of the directions (which the unrotated basis lacks),
+convergence to Newton's minimiser under a 60 degree twist.
+
 Readings taken where the paper is silent:
 * small solves are Cholesky factorisations that fail when a pivot falls below
   1e-12 times the trace of the matrix; if Ht_i fails or the support is empty,
@@ -78,6 +88,7 @@ class Params:
     line_search: bool = True
     max_iters: int = 10000
     max_halvings: int = 30
+    corotate: bool = False      # rotate the basis blocks by per-vertex rotations
 
 
 @dataclass
@@ -169,28 +180,79 @@ def local_directions(prob, Umat, H, g, verts, method):
     return np.where(s_ok[:, None], dx[:, :, 0], dcd), counts
 
 
+def mesh_neighbours(prob):
+    """Sorted lists of all vertices sharing an element with each vertex
+    (Dirichlet vertices included)."""
+    nbr = [set() for _ in range(prob.n)]
+    for e in prob.elems:
+        for a in e:
+            nbr[int(a)].update(int(b) for b in e if b != a)
+    return [sorted(v) for v in nbr]
+
+
+def polar_rotation(M):
+    """Rotation factor of the polar decomposition M = R S (det R = +1), from
+    the SVD M = U diag(s) V^T: R = U diag(1, .., 1, det(U V^T)) V^T."""
+    U, _, Vt = np.linalg.svd(M)
+    D = np.eye(M.shape[0])
+    D[-1, -1] = np.sign(np.linalg.det(U @ Vt))
+    return U @ D @ Vt
+
+
+def vertex_rotations(prob, x, nbr=None):
+    """Per-vertex rotations estimated from the displacement of each free
+    vertex's neighbourhood (Method, Accounting for Large Deformations; this
+    package's reading): R_j = polar factor of
+    sum_{k in N(j)} (x_k - x_j)(X_k - X_j)^T, N(j) the mesh neighbours.
+    Returns (n_free, d, d)."""
+    nbr = mesh_neighbours(prob) if nbr is None else nbr
+    out = np.zeros((prob.free.size, prob.d, prob.d))
+    for r, j in enumerate(prob.free):
+        ks = np.asarray(nbr[j], dtype=np.int64)
+        M = (x[ks] - x[j]).T @ (prob.X[ks] - prob.X[j])
+        out[r] = polar_rotation(M)
+    return out
+
+
+def rotate_basis(prob, Umat, R):
+    """U_i^rot[j] = R_j U_i[j] for every basis column (Method, Eq. rotation):
+    the rows of free vertex j are multiplied by R_j."""
+    d, nf = prob.d, prob.free.size
+    blocks = sp.block_diag([R[r] for r in range(nf)], format="csr") if nf else sp.csr_matrix((0, 0))
+    return (blocks @ Umat).tocsc()
+
+
+def _basis_at(prob, Umat, x, params):
+    if Umat is None or not params.corotate:
+        return Umat
+    return rotate_basis(prob, Umat, vertex_rotations(prob, x))
+
+
 def sweep(prob, x, Umat, colours_free, params, method=None):
-    """One iteration; returns (x_new, fallback counts)."""
+    """One iteration; returns (x_new, fallback counts).  With params.corotate
+    the basis is rotated at the state where g and H are evaluated."""
     method = params.method if method is None else method
     f = prob.free
     counts = np.zeros(3, dtype=np.int64)
     if params.sweep == JACOBI:
         g = prob.gradient(x)
         H = prob.hessian(x)
-        dx, c = local_directions(prob, Umat, H, g, np.arange(f.size), method)
+        dx, c = local_directions(prob, _basis_at(prob, Umat, x, params), H, g, np.arange(f.size), method)
         x_new = x.copy()
         x_new[f] += dx
         return x_new, counts + c
     x_cur = x.copy()
     H = None
+    Ucur = Umat
     for col in range(int(colours_free.max()) + 1 if colours_free.size else 0):
         verts = np.flatnonzero(colours_free == col)
         if verts.size == 0:
             continue
         if H is None or params.hess_refresh == HESS_COLOUR:
             H = prob.hessian(x_cur)
+            Ucur = _basis_at(prob, Umat, x_cur, params)
         g = prob.gradient(x_cur)
-        dx, c = local_directions(prob, Umat, H, g, verts, method)
+        dx, c = local_directions(prob, Ucur, H, g, verts, method)
         counts += c
         x_cur[f[verts]] += dx
     return x_cur, counts

@@ -79,11 +79,16 @@ typedef struct {
   int32_t quasistatic;    /* 1: E = Psi - m g.x (no inertia, no h^2)                   */
   int32_t warm_start;     /* 0 none, 1 learned proposal set by cc_mlp_set              */
   double  gravity[3];     /* gravitational acceleration; dim 2 uses the first two      */
+  int32_t corotate;       /* 1: rotate every basis block by its vertex's rotation,
+                             U_i[j] -> R_j U_i[j], with R_j the polar rotation of the
+                             displacement of j's mesh neighbourhood, re-estimated
+                             wherever g and H are (Method, Accounting for Large
+                             Deformations, Eq. rotation); 0 off                         */
 } cc_params;
 
 /* Fill *p with defaults: CC, Jacobi, per-colour Hessians, FP64, line search on,
    10000 iterations, 30 halvings, check interval 1, dynamic, no warm start,
-   gravity 0. */
+   gravity 0, no corotation. */
 void cc_params_default(cc_params* p);
 
 /* Create a context on HIP device `device`, ordering work on `hip_stream`

@@ -40,7 +40,7 @@ class cc_params(ctypes.Structure):
                 ("line_search", ctypes.c_int32), ("max_iters", ctypes.c_int32),
                 ("max_halvings", ctypes.c_int32), ("check_interval", ctypes.c_int32),
                 ("quasistatic", ctypes.c_int32), ("warm_start", ctypes.c_int32),
-                ("gravity", ctypes.c_double * 3)]
+                ("gravity", ctypes.c_double * 3), ("corotate", ctypes.c_int32)]
 
 
 _lib = None

@@ -49,6 +49,7 @@ struct Mesh {
   // work buffers
   double *x = nullptr, *xt = nullptr, *x0 = nullptr, *xtrial = nullptr, *dvec = nullptr,
          *g = nullptr, *partials = nullptr, *scal = nullptr;
+  double* rot = nullptr;  // corotation: rotation of every free vertex (D*D each)
   void *estore = nullptr, *hb = nullptr, *KL = nullptr;
   unsigned long long* fb = nullptr;
   int* bad = nullptr;
@@ -127,7 +128,7 @@ void free_mesh(Mesh& M) {
   free_basis(M);
   dfree(M.x); dfree(M.xt); dfree(M.x0); dfree(M.xtrial); dfree(M.dvec); dfree(M.g);
   dfree(M.partials); dfree(M.scal); dfree(M.estore); dfree(M.hb); dfree(M.KL); dfree(M.fb);
-  dfree(M.bad);
+  dfree(M.bad); dfree(M.rot);
   dfree(M.nptr); dfree(M.nidx); dfree(M.frank); dfree(M.Xr); dfree(M.feat); dfree(M.delta);
 }
 
@@ -494,6 +495,7 @@ void build_mesh(cc_ctx* ctx, Mesh& M) {
   M.estore = dalloc<double>((size_t)NB * m * D * D);
   M.hb = dalloc<double>((size_t)M.nnzb * D * D);
   M.KL = dalloc<double>((size_t)nf * 2 * D * D);
+  M.rot = dalloc<double>((size_t)std::max(nf, 1) * D * D);
   M.fb = dalloc<unsigned long long>(4);
   M.bad = dalloc<int>(1);
   HIPC(hipStreamSynchronize(s));
@@ -777,6 +779,12 @@ struct Stepper {
     ctx->timed(CC_K_GRADIENT, [&] { cc::launch_gradient(mv, x, M.xt, mat, M.g, M.partials, &np, s); });
   }
   void hessian(const double* x) {
+    mv.rot = p.corotate ? M.rot : nullptr;   // corotation: rotations at the Hessian's positions
+    if (p.corotate) {
+      if (!M.rot || !M.nptr || !M.nidx || !M.Xr)
+        throw ApiError{CC_E_STATE, "corotation buffers missing"};
+      cc::launch_rotations(mv, x, M.nptr, M.nidx, M.Xr, M.rot, s);
+    }
     ctx->timed(CC_K_ELEM_HESS, [&] { cc::launch_elem_hess(mv, p.precision, x, mat, mat.s_el, M.estore, s); });
     ctx->timed(CC_K_ASSEMBLE, [&] { cc::launch_assemble(mv, p.precision, M.estore, mat, M.hb, s); });
   }
@@ -1034,6 +1042,7 @@ static cc_status check_params(cc_ctx* ctx, const cc_params* p, const Mesh& M, do
   for (int c = 0; c < 3; ++c)
     if (!std::isfinite(p->gravity[c])) return fail(ctx, CC_E_NONFINITE, "non-finite gravity");
   if (p->warm_start != 0 && p->warm_start != 1) return fail(ctx, CC_E_INVALID_ARG, "bad warm_start");
+  if (p->corotate != 0 && p->corotate != 1) return fail(ctx, CC_E_INVALID_ARG, "bad corotate");
   if (p->warm_start && (!ctx->mlp.set || M.D != 3 || p->quasistatic))
     return fail(ctx, CC_E_STATE, "warm start needs cc_mlp_set and a dynamic 3D mesh");
   return CC_OK;
@@ -1278,7 +1287,7 @@ static cc::BatchPlan* batch_plan_for(cc_ctx* ctx, const std::vector<Mesh*>& ms, 
   std::vector<double> key = {(double)p.method, (double)p.sweep, (double)p.hess_refresh,
                              (double)p.precision, (double)p.line_search, (double)p.max_iters,
                              (double)p.quasistatic, dt, tol, (double)ctx->batch_lanes,
-                             (double)ctx->batch_iters_per_graph};
+                             (double)ctx->batch_iters_per_graph, (double)p.corotate};
   for (int i = 0; i < n; ++i) key.push_back((double)(ms[i]->has_basis ? ms[i]->dense : -1));
   std::vector<int> idv(ids, ids + n);
   if (ctx->plan && ctx->plan_ids == idv && ctx->plan_key == key) return ctx->plan;
@@ -1290,12 +1299,14 @@ static cc::BatchPlan* batch_plan_for(cc_ctx* ctx, const std::vector<Mesh*>& ms, 
     Material mat{};
     items[i] = make_item(*ms[i], mat);
     items[i].prep_dense = (p.method != CC_METHOD_CD && use_dense_lds(*ms[i], p.precision)) ? 1 : 0;
+    items[i].mv.rot = p.corotate ? ms[i]->rot : nullptr;
   }
   cc::BatchConfig cfg{};
   cfg.D = ms[0]->D; cfg.prec = p.precision; cfg.method = p.method; cfg.sweep = p.sweep;
   cfg.hess_refresh = p.hess_refresh; cfg.line_search = p.line_search; cfg.max_iters = p.max_iters;
   cfg.quasistatic = p.quasistatic; cfg.tol = tol; cfg.h = p.quasistatic ? 1.0 : dt;
   cfg.G = ctx->batch_lanes; cfg.iters_per_graph = ctx->batch_iters_per_graph;
+  cfg.corotate = p.corotate;
   ctx->plan = cc::batch_plan_create(items.data(), n, cfg, ctx->stream);
   ctx->plan_ids = idv;
   ctx->plan_prev_iters = 0;
@@ -1386,6 +1397,7 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
       for (int c = 0; c < 3; ++c) mat.grav[c] = gravity ? gravity[3 * i + c] : p.gravity[c];
       items[i] = make_item(M, mat);
       items[i].prep_dense = (p.method != CC_METHOD_CD && use_dense_lds(M, p.precision)) ? 1 : 0;
+      items[i].mv.rot = p.corotate ? M.rot : nullptr;
       items[i].feat_off = 0;
       for (int q = 0; q < i; ++q) items[i].feat_off += ms[q]->nf;
       items[i].xu = x[i];
@@ -1503,6 +1515,7 @@ cc_status cc_autotune_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, con
       mat.mu = ms[i]->mu; mat.lam = ms[i]->lam;
       items[i] = make_item(*ms[i], mat);
       items[i].prep_dense = (params->method != CC_METHOD_CD && use_dense_lds(*ms[i], params->precision)) ? 1 : 0;
+      items[i].mv.rot = params->corotate ? ms[i]->rot : nullptr;
     }
     HIPC(hipMemcpyAsync(cc::batch_items_dev(plan), items.data(), n * sizeof(cc::BatchItem),
                         hipMemcpyHostToDevice, ctx->stream));

@@ -396,7 +396,27 @@ __device__ __forceinline__ int find_slot(const MeshView& mv, int64_t sp0, int64_
 // K_i = (H_ii - A Ht^{-1} A^T)^{-1} and L_i = A Ht^{-1} (CC), with the
 // coordinate-descent and JGS2 forms as special cases.  G lanes per vertex.
 // Contribution of support row j to A_i (when row j holds block (j, i)) and to
-// Ht_i (blocks (j, k) with k in the support); Uk(k) returns U_i[k] or null.
+// U <- R_j U with R_j the vertex's rotation (corotated basis block).
+template <typename T, int D>
+__device__ __forceinline__ void rotate_block(const double* __restrict__ rot, int j, T* U) {
+  T Rj[D * D], out[D * D];
+#pragma unroll
+  for (int r = 0; r < D * D; ++r) Rj[r] = T(rot[(size_t)j * D * D + r]);
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      T acc = T(0);
+#pragma unroll
+      for (int l = 0; l < D; ++l) acc += Rj[r * D + l] * U[l * D + c];
+      out[r * D + c] = acc;
+    }
+#pragma unroll
+  for (int r = 0; r < D * D; ++r) U[r] = out[r];
+}
+
+// Ht_i (blocks (j, k) with k in the support); Uk_of(k, Uk) fills U_i[k] and
+// returns true, or returns false when k is outside the support.
 template <typename T, int D, typename LookupU>
 __device__ __forceinline__ void accum_row(const MeshView& mv, int i, int j, const T* Uj,
                                           const T* __restrict__ hb, LookupU&& Uk_of, T* A, T* Ht) {
@@ -417,8 +437,8 @@ __device__ __forceinline__ void accum_row(const MeshView& mv, int i, int j, cons
         }
       continue;
     }
-    const T* Uk = Uk_of(k);
-    if (!Uk) continue;
+    T Uk[DD];
+    if (!Uk_of(k, Uk)) continue;
     T Hl[DD], M[DD];
 #pragma unroll
     for (int r = 0; r < DD; ++r) Hl[r] = H[r];

@@ -37,6 +37,8 @@ struct MeshView {
   const double* U_d;     // [nnz][D*D]
   const float* U_f;
   int dense_supp;        // 1: supp(i) = every free vertex except i
+  // corotation: per free vertex rotation R_j (row-major D*D), or null = off
+  const double* rot;
 };
 
 struct Material {
@@ -69,6 +71,10 @@ void launch_cc_update(const MeshView& mv, int prec, int method, int v0, int v1, 
 void launch_energy(const MeshView& mv, const double* x, const double* xt, const Material& mat,
                    double* partials, int* nparts, hipStream_t s);
 void launch_reduce(const double* partials, int n, double* out, hipStream_t s);
+// Corotation: R_j = polar rotation of sum_{k in N(j)} (x_k - x_j)(X_k - X_j)^T for
+// every free vertex j (nptr/nidx: mesh neighbours, Xr: rest positions, SoA).
+void launch_rotations(const MeshView& mv, const double* x, const int* nptr, const int* nidx,
+                      const double* Xr, double* rot, hipStream_t s);
 void launch_axpy(int count, const double* x, const double* d, double alpha, double* out,
                  hipStream_t s);
 void launch_probe_element(const MeshView& mv, int prec, const double* x_user,
@@ -144,6 +150,7 @@ struct BatchConfig {
   int G;               // lanes per vertex of the generic condensation/update kernels
   int iters_per_graph; // iterations captured per graph replay (0: no graph)
   int dense_lds;       // max dynamic LDS of the dense condensation path (bytes)
+  int corotate;        // rotations re-estimated wherever the Hessian is
 };
 
 BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const BatchConfig& cfg,

@@ -203,9 +203,14 @@ __device__ __forceinline__ void prep_body(const MeshView& mv, int method, int i,
       T Uj[DD];
 #pragma unroll
       for (int r = 0; r < DD; ++r) Uj[r] = Ub[q * DD + r];
-      accum_row<T, D>(mv, i, j, Uj, hb, [&](int k) -> const T* {
+      if (mv.rot) rotate_block<T, D>(mv.rot, j, Uj);
+      accum_row<T, D>(mv, i, j, Uj, hb, [&](int k, T* Uk) -> bool {
         const int qk = find_slot(mv, sp0, sp1, i, k);
-        return qk < 0 ? nullptr : Ub + (size_t)qk * DD;
+        if (qk < 0) return false;
+#pragma unroll
+        for (int r = 0; r < DD; ++r) Uk[r] = Ub[(size_t)qk * DD + r];
+        if (mv.rot) rotate_block<T, D>(mv.rot, k, Uk);
+        return true;
       }, A, Ht);
     }
   }
@@ -284,6 +289,18 @@ __device__ __forceinline__ void prep_dm_body(const MeshView& mv, int method, int
     }
   }
   __syncthreads();
+  if (mv.rot != nullptr) {                        // corotation: U_v[j] <- R_j U_v[j]
+    for (int e = threadIdx.x; e < TV * nf; e += PWG) {
+      T* u = Us + (size_t)e * DD;                 // row e / nf, block e % nf
+      T blk[DD];
+#pragma unroll
+      for (int r = 0; r < DD; ++r) blk[r] = u[r];
+      rotate_block<T, D>(mv.rot, e % nf, blk);
+#pragma unroll
+      for (int r = 0; r < DD; ++r) u[r] = blk[r];
+    }
+    __syncthreads();
+  }
   T Y[TV][DD];
 #pragma unroll
   for (int v = 0; v < TV; ++v)
@@ -515,6 +532,18 @@ __device__ __forceinline__ void update_body(const MeshView& mv, int method, int 
       T gj[D];
 #pragma unroll
       for (int c = 0; c < D; ++c) gj[c] = T(g[c * n + j]);
+      if (mv.rot) {                               // (R_j U)^T g_j = U^T (R_j^T g_j)
+        T t[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          T acc = T(0);
+#pragma unroll
+          for (int l = 0; l < D; ++l) acc += T(mv.rot[(size_t)j * DD + l * D + c]) * gj[l];
+          t[c] = acc;
+        }
+#pragma unroll
+        for (int c = 0; c < D; ++c) gj[c] = t[c];
+      }
 #pragma unroll
       for (int r = 0; r < D; ++r) {
         T acc = T(0);
@@ -879,6 +908,61 @@ void launch_reduce(const double* partials, int n, double* out, hipStream_t s) {
   k_reduce<<<1, WG, 0, s>>>(partials, n, out);
 }
 
+// R_j = U V^T from the rotation-variant SVD of
+// M = sum_{k in N(j)} (x_k - x_j)(X_k - X_j)^T: the polar rotation (det +1).
+template <int D>
+__device__ __forceinline__ void rotation_body(const MeshView& mv, int j, const double* __restrict__ x,
+                                              const int* __restrict__ nptr, const int* __restrict__ nidx,
+                                              const double* __restrict__ Xr, double* __restrict__ rot) {
+  if (j >= mv.nf) return;
+  const int n = mv.n;
+  double M[D][D];
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int c = 0; c < D; ++c) M[r][c] = 0.0;
+  double xj[D], Xj[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) { xj[c] = x[(size_t)c * n + j]; Xj[c] = Xr[(size_t)c * n + j]; }
+  for (int t = nptr[j]; t < nptr[j + 1]; ++t) {
+    const int k = nidx[t];
+    double dx[D], dX[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      dx[c] = x[(size_t)c * n + k] - xj[c];
+      dX[c] = Xr[(size_t)c * n + k] - Xj[c];
+    }
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int c = 0; c < D; ++c) M[r][c] += dx[r] * dX[c];
+  }
+  double U[D][D], V[D][D], sig[D];
+  svd_rv<double, D>(M, U, V, sig);
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int l = 0; l < D; ++l) acc += U[r][l] * V[c][l];
+      rot[(size_t)j * D * D + r * D + c] = acc;
+    }
+}
+
+template <int D>
+__global__ void __launch_bounds__(WG) k_rotations(MeshView mv, const double* __restrict__ x,
+                                                  const int* __restrict__ nptr, const int* __restrict__ nidx,
+                                                  const double* __restrict__ Xr, double* __restrict__ rot) {
+  rotation_body<D>(mv, blockIdx.x * WG + threadIdx.x, x, nptr, nidx, Xr, rot);
+}
+
+void launch_rotations(const MeshView& mv, const double* x, const int* nptr, const int* nidx,
+                      const double* Xr, double* rot, hipStream_t s) {
+  if (mv.nf <= 0 || !x || !nptr || !nidx || !Xr || !rot) return;
+  CC_DISPATCH_D(mv.D, k_rotations<D><<<nblocks(mv.nf, WG), WG, 0, s>>>(mv, x, nptr, nidx, Xr, rot));
+}
+
 void launch_axpy(int count, const double* x, const double* d, double alpha, double* out,
                  hipStream_t s) {
   if (count <= 0) return;
@@ -1000,6 +1084,19 @@ __global__ void __launch_bounds__(EWG) kb_elem_hess(const BatchItem* __restrict_
   const MeshView mv = it.mv;
   elem_hess_body<T, D>(mv, (blockIdx.x - boff[mi]) * EWG + threadIdx.x, pick(it, which), T(it.mat.mu),
                        T(it.mat.lam), T(it.mat.s_el), (T*)it.estore);
+}
+
+// Corotation: vertex rotations of every mesh at positions `which`.
+template <int D>
+__global__ void __launch_bounds__(WG) kb_rotations(const BatchItem* __restrict__ items,
+                                                   const BatchCtl* __restrict__ ctl,
+                                                   const int* __restrict__ boff, int nmesh, int which) {
+  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  if (!ctl[mi].active) return;
+  const BatchItem& it = items[mi];
+  if (it.mv.rot == nullptr) return;
+  rotation_body<D>(it.mv, (blockIdx.x - boff[mi]) * WG + threadIdx.x, pick(it, which), it.nptr, it.nidx,
+                   it.Xr, const_cast<double*>(it.mv.rot));
 }
 
 template <typename T, int D>
@@ -1199,7 +1296,7 @@ struct BatchPlan {
   std::vector<BatchItem> items_h;
   BatchItem* items_d = nullptr;
   BatchCtl* ctl_d = nullptr;
-  Offsets pred, elem, asmb, grad, energy, axpy, feat;
+  Offsets pred, elem, asmb, grad, energy, axpy, feat, rotn;
   std::vector<Offsets> prep, prepd, fin, upd;   // index 0: all free vertices, c+1: colour c
   int max_colours = 0;
   int tv = 0;       // vertices per workgroup of the dense condensation (0: no dense mesh)
@@ -1276,7 +1373,7 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
   p->cfg = cfg;
   p->items_h.assign(items_host, items_host + nmesh);
   std::vector<int> cpred(nmesh), celem(nmesh), casm(nmesh), cgrad(nmesh), cen(nmesh), cax(nmesh),
-      cfeat(nmesh);
+      cfeat(nmesh), crot(nmesh);
   int dense_nf = 0;
   for (int m = 0; m < nmesh; ++m) {
     const MeshView& mv = p->items_h[m].mv;
@@ -1287,6 +1384,7 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
     cen[m] = nblocks(mv.m, WG) + nblocks(mv.nf, WG);
     cax[m] = nblocks((long long)mv.D * mv.n, WG);
     cfeat[m] = nblocks(mv.nf, WG / FEAT_LANES);
+    crot[m] = (cfg.corotate && mv.rot) ? nblocks(mv.nf, WG) : 0;
     p->max_colours = std::max(p->max_colours, p->items_h[m].ncol);
     if (p->items_h[m].prep_dense) dense_nf = std::max(dense_nf, mv.nf);
   }
@@ -1301,6 +1399,7 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
   offsets_build(p->energy, cen, s);
   offsets_build(p->axpy, cax, s);
   offsets_build(p->feat, cfeat, s);
+  offsets_build(p->rotn, crot, s);
   plan_vertex_offsets(p, s);
   (void)hipMalloc(&p->items_d, nmesh * sizeof(BatchItem));
   (void)hipMalloc(&p->ctl_d, nmesh * sizeof(BatchCtl));
@@ -1312,7 +1411,8 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
 void batch_plan_destroy(BatchPlan* p) {
   if (!p) return;
   drop_graph(p);
-  for (Offsets* o : {&p->pred, &p->elem, &p->asmb, &p->grad, &p->energy, &p->axpy, &p->feat}) offsets_free(*o);
+  for (Offsets* o : {&p->pred, &p->elem, &p->asmb, &p->grad, &p->energy, &p->axpy, &p->feat, &p->rotn})
+    offsets_free(*o);
   for (auto& o : p->prep) offsets_free(o);
   for (auto& o : p->prepd) offsets_free(o);
   for (auto& o : p->fin) offsets_free(o);
@@ -1375,6 +1475,8 @@ static void b_update(BatchPlan* p, int colour, int into_trial, hipStream_t s) {
 
 template <typename T, int D>
 static void b_hessian(BatchPlan* p, int which, hipStream_t s) {
+  if (gridn(p->rotn) > 0)   // corotation: rotations at the positions of the Hessian
+    kb_rotations<D><<<gridn(p->rotn), WG, 0, s>>>(p->items_d, p->ctl_d, p->rotn.d, p->nmesh, which);
   if (gridn(p->elem) > 0) {
     p->mark(0, 1);
     kb_elem_hess<T, D><<<gridn(p->elem), EWG, 0, s>>>(p->items_d, p->ctl_d, p->elem.d, p->nmesh, which);

@@ -167,3 +167,34 @@ def test_bench_workload_against_oracle(cg, ctx, prec):
                 assert its[k] == res.iters and rel <= 1e-6, (k, t, its[k], res.iters, rel)
             else:
                 assert abs(int(its[k]) - res.iters) <= 2 and rel <= 1e-4, (k, t, rel)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_corotated_batch_equals_single_mesh(cg, ctx, prec):
+    """Corotated CC, batched (rotations in the graph, before every
+    condensation) against each mesh stepped alone."""
+    scenes = [tet_bar(7, 3, 3, E=1e5, twist_per_step=0.3), tet_bar(9, 4, 3, E=1e6),
+              tet_bar(6, 5, 4, E=1e4, twist_per_step=0.2)]
+    mids, _ = _setup(cg, ctx, scenes, "exact")
+    mids1, _ = _setup(cg, ctx, scenes, "exact")
+    cg.cc_batch_tuning(ctx, 16, 2)
+    par = cg.cc_params_default(method=cg.METHOD_CC, precision=prec, line_search=1, max_iters=300,
+                               corotate=1)
+    xs = [_t(s.initial_state()[0]) for s in scenes]
+    vs = [_t(s.initial_state()[1]) for s in scenes]
+    xs1 = [x.clone() for x in xs]
+    vs1 = [v.clone() for v in vs]
+    grav = np.stack([s.gravity for s in scenes])
+    for t in (1, 2):
+        bcs = [_t(s.targets(t)) for s in scenes]
+        worst, its, rgs, sts = cg.cc_step_batch(ctx, mids, xs, vs, bcs, scenes[0].dt, par, 1e-7,
+                                                gravity=grav)
+        assert worst == cg.CC_OK
+        for k, s in enumerate(scenes):
+            par1 = cg.cc_params_default(method=cg.METHOD_CC, precision=prec, line_search=1,
+                                        max_iters=300, corotate=1, gravity=s.gravity)
+            st, it, rg = cg.cc_step(ctx, mids1[k], xs1[k], vs1[k], bcs[k], s.dt, par1, 1e-7)
+            tol = 1e-10 if prec == 0 else 1e-4
+            assert st == sts[k] and abs(int(its[k]) - it) <= (0 if prec == 0 else 1)
+            a, b = xs[k].cpu().numpy(), xs1[k].cpu().numpy()
+            assert np.linalg.norm(a - b) <= tol * np.linalg.norm(b - s.X)

@@ -243,3 +243,44 @@ def test_exact_basis_builder_bar(cg, ctx):
     np.testing.assert_array_equal(ptr, B[0])
     np.testing.assert_array_equal(idx, B[1])
     assert np.max(np.abs(U - B[2])) <= 1e-8 * np.max(np.abs(B[2]))
+
+
+@pytest.mark.parametrize("kind", ["exact", "R1"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_corotated_directions(cg, ctx, kind, prec):
+    """One corotated Jacobi sweep at a twisted state (Method, Eq. rotation):
+    rotations from the neighbourhood displacement, basis blocks R_j U_i[j]."""
+    s = tet_bar(8, 4, 4, E=1e6, twist_per_step=0.4)
+    p = Problem.from_scene(s)
+    B = _basis(p, kind)
+    mid = _upload(cg, ctx, s)
+    cg.cc_subspace_upload(ctx, mid, *B, s.dt)
+    x0, v0 = s.initial_state()
+    xh = predictor(p, x0, v0, s.targets(2))
+    x = xh + 0.01 * np.random.default_rng(8).normal(size=xh.shape)
+    x[p.fixed] = xh[p.fixed]
+    par = cg.cc_params_default(method=cg.METHOD_CC, precision=prec, gravity=s.gravity, corotate=1)
+    E, g, dx = cg.cc_probe_sweep(ctx, mid, _t(x), _t(p.x_tilde), s.dt, par)
+    dx = dx.cpu().numpy()
+    Um = S.rotate_basis(p, basis_matrix(p, *B), S.vertex_rotations(p, x))
+    dxo, _ = S.local_directions(p, Um, p.hessian(x), p.gradient(x), np.arange(p.free.size), S.CC)
+    tol = 1e-9 if prec == 0 else 1e-4
+    assert np.max(np.abs(dx[p.free] - dxo)) <= tol * np.max(np.abs(dxo))
+    par0 = cg.cc_params_default(method=cg.METHOD_CC, precision=prec, gravity=s.gravity)
+    _, _, dx0 = cg.cc_probe_sweep(ctx, mid, _t(x), _t(p.x_tilde), s.dt, par0)
+    assert np.max(np.abs(dx0.cpu().numpy()[p.free] - dxo)) > 1e-3 * np.max(np.abs(dxo))
+
+
+def test_corotated_steps(cg, ctx):
+    """Corotated CC with line search on a bar whose free end turns 0.3 rad per
+    step, exact basis, float64, against the oracle."""
+    s = tet_bar(8, 4, 4, E=1e5, twist_per_step=0.3)
+    p = Problem.from_scene(s)
+    B = exact_basis(p)
+    par = cg.cc_params_default(method=cg.METHOD_CC, sweep=cg.SWEEP_JACOBI, line_search=1,
+                               max_iters=300, gravity=s.gravity, corotate=1)
+    op = S.Params(method=S.CC, sweep=S.JACOBI, line_search=True, max_iters=300, corotate=True)
+    _, out = _run_steps(cg, ctx, s, B, par, 1e-8, 3, op)
+    for res, st, it, rg, xo, xg, vo, vg in out:
+        assert st == cg.CC_OK and it == res.iters
+        assert _rel(xg, xo, s.X) <= 1e-6

@@ -30,6 +30,7 @@ class Scene:
     target_fn: Callable[[int], np.ndarray] = field(repr=False, default=None)
     x_init: Optional[np.ndarray] = field(repr=False, default=None)
     meta: dict = field(default_factory=dict)
+    material: str = "snh"      # "snh" stable neo-Hookean, "fcr" Fixed Corotational
 
     @property
     def n(self):

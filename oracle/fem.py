@@ -25,21 +25,23 @@ exactly.
 import numpy as np
 import scipy.sparse as sp
 
-from .material import dpdf, lame, pk1, project_psd, psi
+from .material import SNH, energy_density, lame, project_psd
 from .mesh import deformation_gradient, lumped_mass, rest_data
 
 
 class Problem:
     """One mesh with material, Dirichlet set and time-step constants."""
 
-    def __init__(self, X, elems, fixed, E, nu, rho, gravity, dt, quasistatic):
+    def __init__(self, X, elems, fixed, E, nu, rho, gravity, dt, quasistatic, material=SNH):
         self.X = np.asarray(X, dtype=np.float64)
         self.elems = np.asarray(elems, dtype=np.int64)
         self.n, self.d = self.X.shape
         self.beta, self.vol = rest_data(self.X, self.elems)
         self.mass = lumped_mass(self.n, self.elems, self.vol, rho)
         self.E, self.nu, self.rho = E, nu, rho
-        self.mu, self.lam = lame(E, nu)
+        self.material = material
+        self.mu, self.lam = lame(E, nu, material)
+        self._psi, self._pk1, self._dpdf = energy_density(material)
         self.fixed = np.asarray(fixed).astype(bool)
         self.free = np.flatnonzero(~self.fixed)
         self.fidx = -np.ones(self.n, dtype=np.int64)
@@ -54,7 +56,8 @@ class Problem:
 
     @classmethod
     def from_scene(cls, s):
-        return cls(s.X, s.elems, s.fixed, s.E, s.nu, s.rho, s.gravity, s.dt, s.quasistatic)
+        return cls(s.X, s.elems, s.fixed, s.E, s.nu, s.rho, s.gravity, s.dt, s.quasistatic,
+                   getattr(s, "material", SNH))
 
     @property
     def ndof(self):
@@ -66,18 +69,18 @@ class Problem:
     # ----- element level -------------------------------------------------
     def element_energy(self, x):
         F = deformation_gradient(x, self.elems, self.beta)
-        return self.vol * psi(F, self.mu, self.lam)
+        return self.vol * self._psi(F, self.mu, self.lam)
 
     def element_gradient(self, x):
         F = deformation_gradient(x, self.elems, self.beta)
-        P = pk1(F, self.mu, self.lam)
+        P = self._pk1(F, self.mu, self.lam)
         return self.vol[:, None, None] * np.einsum("mrq,maq->mar", P, self.beta)
 
     def element_hessian(self, x, project=True):
         """H_e as (m, d+1, d+1, d, d): block [a, b] is the d x d block H_e[a,b]."""
         d = self.d
         F = deformation_gradient(x, self.elems, self.beta)
-        C = dpdf(F, self.mu, self.lam)
+        C = self._dpdf(F, self.mu, self.lam)
         if project:
             C = project_psd(C)
         C4 = C.reshape(-1, d, d, d, d)                    # [r, q, s, t]

@@ -107,6 +107,23 @@ cc_status cc_mesh_upload(cc_ctx* ctx, int32_t dim, int32_t n_verts, const double
                          int32_t n_elems, const int32_t* elems, const uint8_t* is_fixed,
                          double youngs, double poisson, double density, int32_t* mesh_id);
 
+/* Material models (Results, Implementation Details names Fixed Corotational;
+   stable neo-Hookean is the default).  mu = E/(2(1+nu)), lambda_L =
+   E nu/((1+nu)(1-2nu)):
+     CC_MATERIAL_SNH  Psi = mu/2(|F|^2 - d) - mu(J-1) + lambda/2 (J-1)^2,
+                      lambda = lambda_L + mu;
+     CC_MATERIAL_FCR  Psi = mu |F - R|^2 + lambda/2 (J-1)^2, lambda = lambda_L,
+                      R the rotation nearest to F.
+   Both have the same rest linearisation, so a basis built for one serves the
+   other.  Hessians are projected to the PSD cone element by element. */
+#define CC_MATERIAL_SNH 0
+#define CC_MATERIAL_FCR 1
+
+/* Select the material model of a mesh (default CC_MATERIAL_SNH); E and nu are
+   those given at upload.  Takes effect from the next step or probe.  An
+   unknown model gives CC_E_INVALID_ARG and leaves the mesh unchanged. */
+cc_status cc_mesh_set_material(cc_ctx* ctx, int32_t mesh_id, int32_t model);
+
 /* Greedy colouring of the free-vertex graph (edge iff two free vertices share
    an element), visiting vertices in increasing id and taking the smallest
    colour unused by coloured neighbours.  colors (host, n_verts) receives the

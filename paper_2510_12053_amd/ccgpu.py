@@ -21,6 +21,7 @@ METHOD_CD, METHOD_CC, METHOD_JGS2 = 0, 1, 2
 SWEEP_JACOBI, SWEEP_COLORED_GS = 0, 1
 HESS_PER_COLOR, HESS_PER_SWEEP = 0, 1
 FP64, FP32_MIXED = 0, 1
+MATERIAL_SNH, MATERIAL_FCR = 0, 1
 
 _STATUS_NAMES = {
     0: "CC_OK", 1: "CC_NOT_CONVERGED", 2: "CC_STALLED", -1: "CC_E_INVALID_ARG", -2: "CC_E_MESH",
@@ -61,6 +62,7 @@ def lib():
             "cc_last_error": (ctypes.c_char_p, [P]),
             "cc_mesh_upload": (I32, [P, I32, I32, P, I32, P, P, D, D, D, pI32]),
             "cc_color": (I32, [P, I32, P, pI32]),
+            "cc_mesh_set_material": (I32, [P, I32, I32]),
             "cc_layout": (I32, [P, I32, P, P]),
             "cc_subspace_upload": (I32, [P, I32, P, P, P, D]),
             "cc_subspace_build": (I32, [P, I32, I32, D, I32]),
@@ -161,6 +163,10 @@ def cc_mesh_upload(ctx, X, elems, fixed, youngs, poisson, density):
     _check(ctx, lib().cc_mesh_upload(ctx.handle, X.shape[1], X.shape[0], _ptr(X), E.shape[0], _ptr(E),
                                      _ptr(F), youngs, poisson, density, ctypes.byref(mid)))
     return mid.value
+
+
+def cc_mesh_set_material(ctx, mesh_id, model):
+    _check(ctx, lib().cc_mesh_set_material(ctx.handle, mesh_id, model))
 
 
 def cc_color(ctx, mesh_id, n_verts):

@@ -21,6 +21,7 @@ namespace {
 struct Mesh {
   int D = 0, K = 0, n = 0, nf = 0, m = 0, ncol = 0;
   double E = 0, nu = 0, rho = 0, mu = 0, lam = 0, volume = 0;
+  int model = cc::MAT_SNH;         // material model; lam is that model's lambda
   std::vector<double> X;           // caller order, n x D
   std::vector<int> elems;          // caller order, m x K
   std::vector<uint8_t> fixed;
@@ -600,7 +601,7 @@ void build_basis(cc_ctx* ctx, Mesh& M, int radius, double dt, int quasi) {
     for (int c = 0; c < D; ++c) Xi[(size_t)c * n + v] = M.X[(size_t)M.vperm[v] * D + c];
   HIPC(hipMemcpyAsync(M.x, Xi.data(), Xi.size() * sizeof(double), hipMemcpyHostToDevice, s));
   Material mat{};
-  mat.mu = M.mu; mat.lam = M.lam;
+  mat.mu = M.mu; mat.lam = M.lam; mat.model = M.model;
   mat.w_in = quasi ? 0.0 : 1.0;
   mat.s_el = quasi ? 1.0 : dt * dt;
   MeshView mv = M.view();
@@ -951,6 +952,20 @@ cc_status cc_mesh_upload(cc_ctx* ctx, int32_t dim, int32_t n_verts, const double
   });
 }
 
+static_assert(CC_MATERIAL_SNH == cc::MAT_SNH && CC_MATERIAL_FCR == cc::MAT_FCR, "material ids");
+
+cc_status cc_mesh_set_material(cc_ctx* ctx, int32_t mesh_id, int32_t model) {
+  return guarded(ctx, [&]() -> cc_status {
+    Mesh& M = get_mesh(ctx, mesh_id);
+    if (model != CC_MATERIAL_SNH && model != CC_MATERIAL_FCR)
+      return fail(ctx, CC_E_INVALID_ARG, "unknown material model");
+    const double lam_l = M.E * M.nu / ((1.0 + M.nu) * (1.0 - 2.0 * M.nu));
+    M.model = model == CC_MATERIAL_FCR ? cc::MAT_FCR : cc::MAT_SNH;
+    M.lam = model == CC_MATERIAL_FCR ? lam_l : lam_l + M.mu;
+    return CC_OK;
+  });
+}
+
 cc_status cc_color(cc_ctx* ctx, int32_t mesh_id, int32_t* colors, int32_t* n_colors) {
   return guarded(ctx, [&]() -> cc_status {
     Mesh& M = get_mesh(ctx, mesh_id);
@@ -1059,7 +1074,7 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
     const cc_params& p = *params;
     hipStream_t s = ctx->stream;
     Material mat{};
-    mat.mu = M.mu; mat.lam = M.lam;
+    mat.mu = M.mu; mat.lam = M.lam; mat.model = M.model;
     mat.w_in = p.quasistatic ? 0.0 : 1.0;
     mat.s_el = p.quasistatic ? 1.0 : dt * dt;
     for (int c = 0; c < 3; ++c) mat.grav[c] = p.gravity[c];
@@ -1083,7 +1098,8 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
       r = 1.0;
       if (p.warm_start) {
         // learned proposal at the predictor, kept only if it lowers E
-        cc::launch_features(S.mv, M.x, M.x0, h, M.E, M.mu, M.lam, M.ell, M.nptr, M.nidx, M.Xr, M.feat, nullptr, s);
+        cc::launch_features(S.mv, M.x, M.x0, h, M.E, M.mu, M.lam, M.model, M.ell, M.nptr, M.nidx, M.Xr, M.feat, nullptr,
+                            s);
         cc::mlp_forward(ctx->mlp, M.feat, M.nf, M.delta, s);
         cc::launch_proposal(M.n, M.nf, M.x, M.delta, M.ell, M.xtrial, s);
         const double E0 = S.energy(M.x), Ep = S.energy(M.xtrial);
@@ -1186,7 +1202,7 @@ cc_status cc_probe_element(cc_ctx* ctx, int32_t mesh_id, const double* x, int32_
     double* tmp = dalloc<double>((size_t)M.D * M.n + (size_t)NB * M.m * M.D * M.D);
     MeshView mv = M.view();
     Material mat{};
-    mat.mu = M.mu; mat.lam = M.lam;
+    mat.mu = M.mu; mat.lam = M.lam; mat.model = M.model;
     cc::launch_gather_user(mv, M.d_vinv, x, tmp, s);
     cc::launch_probe_element(mv, precision, x, M.d_vinv, M.d_eperm, tmp, mat, ge, He, s);
     HIPC(hipStreamSynchronize(s));
@@ -1205,7 +1221,7 @@ cc_status cc_probe_sweep(cc_ctx* ctx, int32_t mesh_id, const double* x, const do
     const cc_params& p = *params;
     hipStream_t s = ctx->stream;
     Material mat{};
-    mat.mu = M.mu; mat.lam = M.lam;
+    mat.mu = M.mu; mat.lam = M.lam; mat.model = M.model;
     mat.w_in = p.quasistatic ? 0.0 : 1.0;
     mat.s_el = p.quasistatic ? 1.0 : dt * dt;
     for (int c = 0; c < 3; ++c) mat.grav[c] = p.gravity[c];
@@ -1288,7 +1304,12 @@ static cc::BatchPlan* batch_plan_for(cc_ctx* ctx, const std::vector<Mesh*>& ms, 
                              (double)p.precision, (double)p.line_search, (double)p.max_iters,
                              (double)p.quasistatic, dt, tol, (double)ctx->batch_lanes,
                              (double)ctx->batch_iters_per_graph, (double)p.corotate};
-  for (int i = 0; i < n; ++i) key.push_back((double)(ms[i]->has_basis ? ms[i]->dense : -1));
+  int any_fcr = 0;
+  for (int i = 0; i < n; ++i) {
+    key.push_back((double)(ms[i]->has_basis ? ms[i]->dense : -1));
+    any_fcr |= ms[i]->model == cc::MAT_FCR ? 1 : 0;
+  }
+  key.push_back((double)any_fcr);
   std::vector<int> idv(ids, ids + n);
   if (ctx->plan && ctx->plan_ids == idv && ctx->plan_key == key) return ctx->plan;
   if (ctx->plan) { cc::batch_plan_destroy(ctx->plan); ctx->plan = nullptr; }
@@ -1307,6 +1328,7 @@ static cc::BatchPlan* batch_plan_for(cc_ctx* ctx, const std::vector<Mesh*>& ms, 
   cfg.quasistatic = p.quasistatic; cfg.tol = tol; cfg.h = p.quasistatic ? 1.0 : dt;
   cfg.G = ctx->batch_lanes; cfg.iters_per_graph = ctx->batch_iters_per_graph;
   cfg.corotate = p.corotate;
+  cfg.any_fcr = any_fcr;
   ctx->plan = cc::batch_plan_create(items.data(), n, cfg, ctx->stream);
   ctx->plan_ids = idv;
   ctx->plan_prev_iters = 0;
@@ -1391,7 +1413,7 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
     for (int i = 0; i < n; ++i) {
       Mesh& M = *ms[i];
       Material mat{};
-      mat.mu = M.mu; mat.lam = M.lam;
+      mat.mu = M.mu; mat.lam = M.lam; mat.model = M.model;
       mat.w_in = p.quasistatic ? 0.0 : 1.0;
       mat.s_el = p.quasistatic ? 1.0 : dt * dt;
       for (int c = 0; c < 3; ++c) mat.grav[c] = gravity ? gravity[3 * i + c] : p.gravity[c];
@@ -1512,7 +1534,7 @@ cc_status cc_autotune_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, con
     std::vector<cc::BatchItem> items(n);
     for (int i = 0; i < n; ++i) {
       Material mat{};
-      mat.mu = ms[i]->mu; mat.lam = ms[i]->lam;
+      mat.mu = ms[i]->mu; mat.lam = ms[i]->lam; mat.model = ms[i]->model;
       items[i] = make_item(*ms[i], mat);
       items[i].prep_dense = (params->method != CC_METHOD_CD && use_dense_lds(*ms[i], params->precision)) ? 1 : 0;
       items[i].mv.rot = params->corotate ? ms[i]->rot : nullptr;
@@ -1625,7 +1647,8 @@ cc_status cc_mlp_features(cc_ctx* ctx, int32_t mesh_id, const double* x, const d
     MeshView mv = M.view();
     HIPC(hipMemsetAsync(M.bad, 0, sizeof(int), s));
     cc::launch_predict(mv, M.d_vperm, x, v, x_bc, dt, 0, M.x, M.xt, M.x0, M.bad, s);
-    cc::launch_features(mv, M.x, M.x0, dt, M.E, M.mu, M.lam, M.ell, M.nptr, M.nidx, M.Xr, feat, M.frank, s);
+    cc::launch_features(mv, M.x, M.x0, dt, M.E, M.mu, M.lam, M.model, M.ell, M.nptr, M.nidx, M.Xr, feat, M.frank,
+                        s);
     if (x_tilde) cc::launch_scatter_user(mv, M.d_vperm, M.x, x_tilde, 0, s);
     if (ell) *ell = M.ell;
     int bad = 0;

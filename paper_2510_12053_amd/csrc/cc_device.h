@@ -186,7 +186,7 @@ __device__ __forceinline__ void jacobi_eig(T S[D][D], T V[D][D]) {
 
 // Rotation-variant SVD F = U diag(sig) V^T with det U = det V = +1: V from the
 // eigenvectors of F^T F (a product of rotations), then a Givens QR of F V.
-// The last singular value carries the sign of det F.
+// The singular value of smallest magnitude carries the sign of det F.
 template <typename T, int D>
 __device__ __forceinline__ void svd_rv(const T F[D][D], T U[D][D], T V[D][D], T sig[D]) {
   T S[D][D];
@@ -240,23 +240,50 @@ __device__ __forceinline__ void svd_rv(const T F[D][D], T U[D][D], T V[D][D], T 
     }
 #pragma unroll
   for (int k = 0; k < D; ++k) sig[k] = B[k][k];
+  // With det F < 0 the negative value belongs to the smallest |sig| (then
+  // U V^T is the rotation nearest to F): move it there by negating two
+  // columns of U, which keeps det U = +1.
+  if (sig[D - 1] < T(0)) {
+    int km = D - 1;
+#pragma unroll
+    for (int k = 0; k < D - 1; ++k)
+      if (cabs(sig[k]) < cabs(sig[km])) km = k;
+    if (km != D - 1) {
+      sig[D - 1] = -sig[D - 1];
+      sig[km] = -sig[km];
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        U[i][D - 1] = -U[i][D - 1];
+        U[i][km] = -U[i][km];
+      }
+    }
+  }
 }
 
-// Projected stable neo-Hookean Hessian as its positive eigenpairs.  In the
-// frame of F = U diag(sig) V^T the Hessian splits into the block coupling the
-// diagonal entries (A_kk = mu + lam c_k^2, A_kl = lam c_k c_l + s sig_m with
-// c the diagonal cofactors and s = lam (J-1) - mu) and, for every pair k < l,
-// a 2x2 block on (F_kl, F_lk) with eigenvalues mu -+ s sig_m (2D: sig_m = 1)
-// and eigenvectors (1, +-1)/sqrt(2).  Eigen-matrices map back as
-// U E V^T.  callback(weight, Q) is invoked for each eigenpair with weight > 0.
+// Projected material Hessian as its positive eigenpairs.  In the frame of
+// F = U diag(sig) V^T (rotation-variant: U, V rotations, the smallest sig may
+// be negative) both materials split the same way: a D x D block coupling the
+// diagonal entries, A_kk = a + lam c_k^2, A_kl = lam c_k c_l + s sig_m (c the
+// diagonal cofactors, sig_m the remaining singular value, 1 in 2D), and for
+// every pair k < l a flip (vector (1, 1)/sqrt(2) on (F_kl, F_lk)) with
+// eigenvalue a - s sig_m and a twist ((1, -1)/sqrt(2)) with a + s sig_m - t_kl.
+//   stable neo-Hookean: a = mu,   s = lam (J-1) - mu, t_kl = 0;
+//   Fixed Corotational: a = 2 mu, s = lam (J-1),      t_kl = 4 mu / (sig_k + sig_l)
+// (the as-rigid-as-possible part has eigenvalue 2 mu everywhere except on the
+// twists, where the polar rotation turns with the element; t_kl is taken as 0
+// where sig_k + sig_l = 0 and the rotation has no derivative).  Eigen-matrices
+// map back as U E V^T.  callback(weight, Q) is invoked for each eigenpair with
+// weight > 0.
 template <typename T, int D, typename CB>
-__device__ __forceinline__ void snh_projected_eigs(const T F[D][D], T mu, T lam, CB&& callback) {
+__device__ __forceinline__ void projected_eigs(const T F[D][D], T mu, T lam, int model, CB&& callback) {
   T U[D][D], V[D][D], sig[D];
   svd_rv<T, D>(F, U, V, sig);
   T J = T(1);
 #pragma unroll
   for (int k = 0; k < D; ++k) J *= sig[k];
-  const T s = lam * (J - T(1)) - mu;
+  const bool fcr = model == MAT_FCR;
+  const T a0 = fcr ? T(2) * mu : mu;
+  const T s = fcr ? lam * (J - T(1)) : lam * (J - T(1)) - mu;
   T A[D][D], c[D], third[D][D];
   if constexpr (D == 2) {
     c[0] = sig[1];
@@ -274,7 +301,7 @@ __device__ __forceinline__ void snh_projected_eigs(const T F[D][D], T mu, T lam,
   for (int k = 0; k < D; ++k)
 #pragma unroll
     for (int l = 0; l < D; ++l)
-      A[k][l] = (k == l) ? mu + lam * c[k] * c[k] : lam * c[k] * c[l] + s * third[k][l];
+      A[k][l] = (k == l) ? a0 + lam * c[k] * c[k] : lam * c[k] * c[l] + s * third[k][l];
   T W[D][D];
   jacobi_eig<T, D>(A, W);
   T Q[D][D];
@@ -300,10 +327,12 @@ __device__ __forceinline__ void snh_projected_eigs(const T F[D][D], T mu, T lam,
 #pragma unroll
     for (int l = k + 1; l < D; ++l) {
       const T sm = third[k][l];
+      const T den = sig[k] + sig[l];
+      const T tw = (fcr && den != T(0)) ? T(4) * mu / den : T(0);
 #pragma unroll
       for (int sgn = 0; sgn < 2; ++sgn) {
-        // sgn 0: vector (1, 1), eigenvalue mu - s sig_m; sgn 1: (1, -1), mu + s sig_m
-        const T w = sgn == 0 ? mu - s * sm : mu + s * sm;
+        // sgn 0: flip (1, 1), eigenvalue a - s sig_m; sgn 1: twist (1, -1), a + s sig_m - t_kl
+        const T w = sgn == 0 ? a0 - s * sm : a0 + s * sm - tw;
         if (!(w > T(0))) continue;
         const T b = sgn == 0 ? h : -h;
 #pragma unroll
@@ -313,6 +342,50 @@ __device__ __forceinline__ void snh_projected_eigs(const T F[D][D], T mu, T lam,
         callback(w, Q);
       }
     }
+}
+
+// Fixed Corotational energy density mu |F - R|^2 + lam/2 (J-1)^2 with R = U V^T
+// the rotation nearest to F, and its first Piola-Kirchhoff stress
+// 2 mu (F - R) + lam (J-1) cof(F).
+template <typename T, int D>
+__device__ __forceinline__ T fcr_psi(const T F[D][D], T mu, T lam) {
+  T U[D][D], V[D][D], sig[D];
+  svd_rv<T, D>(F, U, V, sig);
+  T q = T(0);
+#pragma unroll
+  for (int k = 0; k < D; ++k) q += (sig[k] - T(1)) * (sig[k] - T(1));
+  const T J = det<T, D>(F);
+  return mu * q + T(0.5) * lam * (J - T(1)) * (J - T(1));
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void fcr_pk1(const T F[D][D], T mu, T lam, T P[D][D]) {
+  T U[D][D], V[D][D], sig[D], C[D][D];
+  svd_rv<T, D>(F, U, V, sig);
+  cofactor<T, D>(F, C);
+  const T k = lam * (det<T, D>(F) - T(1));
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      T R = T(0);
+#pragma unroll
+      for (int j = 0; j < D; ++j) R += U[r][j] * V[q][j];
+      P[r][q] = T(2) * mu * (F[r][q] - R) + k * C[r][q];
+    }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ T material_psi(const T F[D][D], T mu, T lam, int model) {
+  return model == MAT_FCR ? fcr_psi<T, D>(F, mu, lam) : snh_psi<T, D>(F, mu, lam);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void material_pk1(const T F[D][D], T mu, T lam, int model, T P[D][D]) {
+  if (model == MAT_FCR)
+    fcr_pk1<T, D>(F, mu, lam, P);
+  else
+    snh_pk1<T, D>(F, mu, lam, P);
 }
 
 // ---------------------------------------------------------------------------

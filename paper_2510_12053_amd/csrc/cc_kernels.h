@@ -41,11 +41,16 @@ struct MeshView {
   const double* rot;
 };
 
+// Material models (values of Material::model and of the C-ABI constants).
+constexpr int MAT_SNH = 0;   // stable neo-Hookean, lam = lambda_L + mu
+constexpr int MAT_FCR = 1;   // Fixed Corotational, lam = lambda_L
+
 struct Material {
-  double mu, lam;        // stable neo-Hookean mu and lambda = lambda_L + mu
+  double mu, lam;        // mu and the model's lambda (see MAT_*)
   double w_in;           // weight of the inertia term (1 dynamic, 0 quasistatic)
   double s_el;           // weight of the elastic and gravity terms (h^2 or 1)
   double grav[3];
+  int model;             // MAT_SNH or MAT_FCR
 };
 
 // ---- launch wrappers (cc_kernels.hip) --------------------------------------
@@ -151,6 +156,7 @@ struct BatchConfig {
   int iters_per_graph; // iterations captured per graph replay (0: no graph)
   int dense_lds;       // max dynamic LDS of the dense condensation path (bytes)
   int corotate;        // rotations re-estimated wherever the Hessian is
+  int any_fcr;         // some mesh of the batch uses the Fixed Corotational model
 };
 
 BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const BatchConfig& cfg,
@@ -173,6 +179,7 @@ struct BatchGrid {
   const int* feat_off;  // block offsets of the feature launch
   double tol;
   int max_iters;
+  int any_fcr;          // some mesh uses the Fixed Corotational model
 };
 BatchGrid batch_grid(BatchPlan* p);
 void batch_energy_trial(BatchPlan* p, hipStream_t s);   // ctl.E_trial = E(xtrial)

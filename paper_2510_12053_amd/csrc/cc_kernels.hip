@@ -24,7 +24,7 @@ namespace cc {
 // Element Hessian: H_e[a,b] = scale * V_e * sum_r w_r (Q_r beta_a)(Q_r beta_b)^T
 template <typename T, int D>
 __device__ __forceinline__ void elem_hess_body(const MeshView& mv, int e, const double* __restrict__ x,
-                                               T mu, T lam, T scale, T* __restrict__ out) {
+                                               T mu, T lam, int model, T scale, T* __restrict__ out) {
   constexpr int K = D + 1, DD = D * D, NB = K * (K + 1) / 2;
   if (e >= mv.m) return;
   T F[D][D], beta[K][D], vol;
@@ -34,7 +34,7 @@ __device__ __forceinline__ void elem_hess_body(const MeshView& mv, int e, const 
   for (int p = 0; p < NB; ++p)
 #pragma unroll
     for (int r = 0; r < DD; ++r) acc[p][r] = T(0);
-  snh_projected_eigs<T, D>(F, mu, lam, [&](T w, const T (&Q)[D][D]) {
+  projected_eigs<T, D>(F, mu, lam, model, [&](T w, const T (&Q)[D][D]) {
     T y[K][D];
 #pragma unroll
     for (int a = 1; a < K; ++a)
@@ -78,10 +78,10 @@ __device__ __forceinline__ void elem_hess_body(const MeshView& mv, int e, const 
 // instead of a few dozen (the per-element work is a long serial chain).
 constexpr int EWG = 64;
 
-template <typename T, int D>
+template <typename T, int D, bool FCR>
 __global__ void __launch_bounds__(EWG) k_elem_hess(MeshView mv, const double* __restrict__ x, T mu,
-                                                   T lam, T scale, T* __restrict__ out) {
-  elem_hess_body<T, D>(mv, blockIdx.x * EWG + threadIdx.x, x, mu, lam, scale, out);
+                                                   T lam, int model, T scale, T* __restrict__ out) {
+  elem_hess_body<T, D>(mv, blockIdx.x * EWG + threadIdx.x, x, mu, lam, FCR ? model : MAT_SNH, scale, out);
 }
 
 // Block rows: every slot sums its element contributions (fixed order), plus
@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(EWG) k_assemble(MeshView mv, const T* __restri
 
 // Free-vertex gradient in float64: G lanes per vertex share its star.
 // Returns g_j . g_j on the group's first lane, 0 elsewhere.
-template <int D, int G>
+template <int D, int G, bool FCR>
 __device__ __forceinline__ double gradient_body(const MeshView& mv, int j, int lane,
                                                 const double* __restrict__ x,
                                                 const double* __restrict__ xt, const Material& mat,
@@ -143,7 +143,7 @@ __device__ __forceinline__ double gradient_body(const MeshView& mv, int j, int l
       const int e = pk >> 2, a = pk & 3;
       double F[D][D], beta[D + 1][D], vol, P[D][D];
       load_element<double, D>(mv, e, x, F, beta, vol);
-      snh_pk1<double, D>(F, mat.mu, mat.lam, P);
+      material_pk1<double, D>(F, mat.mu, mat.lam, FCR ? mat.model : MAT_SNH, P);
 #pragma unroll
       for (int r = 0; r < D; ++r) {
         double s = 0.0;
@@ -171,13 +171,13 @@ __device__ __forceinline__ double gradient_body(const MeshView& mv, int j, int l
   return gsq;
 }
 
-template <int D, int G>
+template <int D, int G, bool FCR>
 __global__ void __launch_bounds__(WG) k_gradient(MeshView mv, const double* __restrict__ x,
                                                  const double* __restrict__ xt, Material mat,
                                                  double* __restrict__ g,
                                                  double* __restrict__ partials) {
   __shared__ double red[WG];
-  const double gsq = gradient_body<D, G>(mv, blockIdx.x * (WG / G) + threadIdx.x / G,
+  const double gsq = gradient_body<D, G, FCR>(mv, blockIdx.x * (WG / G) + threadIdx.x / G,
                                          threadIdx.x % G, x, xt, mat, g);
   const double tot = block_sum<WG>(gsq, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
@@ -589,7 +589,7 @@ __global__ void __launch_bounds__(WG) k_cc_update(MeshView mv, int method, int v
 // Step energy: blocks [0, nbe) sum element energies, the rest the free-vertex
 // inertia and gravity terms; one partial per block.
 // Block b < nbe sums element energies, the others free-vertex terms.
-template <int D>
+template <int D, bool FCR>
 __device__ __forceinline__ double energy_body(const MeshView& mv, int b, int nbe,
                                               const double* __restrict__ x,
                                               const double* __restrict__ xt, const Material& mat) {
@@ -600,7 +600,7 @@ __device__ __forceinline__ double energy_body(const MeshView& mv, int b, int nbe
     if (e < mv.m) {
       double F[D][D], beta[D + 1][D], vol;
       load_element<double, D>(mv, e, x, F, beta, vol);
-      v = mat.s_el * vol * snh_psi<double, D>(F, mat.mu, mat.lam);
+      v = mat.s_el * vol * material_psi<double, D>(F, mat.mu, mat.lam, FCR ? mat.model : MAT_SNH);
     }
   } else {
     const int j = (b - nbe) * WG + threadIdx.x;
@@ -619,12 +619,12 @@ __device__ __forceinline__ double energy_body(const MeshView& mv, int b, int nbe
   return v;
 }
 
-template <int D>
+template <int D, bool FCR>
 __global__ void __launch_bounds__(WG) k_energy(MeshView mv, const double* __restrict__ x,
                                                const double* __restrict__ xt, Material mat,
                                                int nbe, double* __restrict__ partials) {
   __shared__ double red[WG];
-  const double v = energy_body<D>(mv, blockIdx.x, nbe, x, xt, mat);
+  const double v = energy_body<D, FCR>(mv, blockIdx.x, nbe, x, xt, mat);
   const double tot = block_sum<WG>(v, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
@@ -712,7 +712,7 @@ __global__ void k_scatter_user(MeshView mv, const int* __restrict__ vperm, const
 // Hessian blocks in caller element order.
 template <typename T, int D>
 __global__ void k_probe_elem(MeshView mv, const double* __restrict__ x, const int* __restrict__ eperm,
-                             const T* __restrict__ est, T mu, T lam, double* __restrict__ ge,
+                             const T* __restrict__ est, T mu, T lam, int model, double* __restrict__ ge,
                              double* __restrict__ He) {
   constexpr int K = D + 1, DD = D * D;
   const int e = blockIdx.x * WG + threadIdx.x;
@@ -720,7 +720,7 @@ __global__ void k_probe_elem(MeshView mv, const double* __restrict__ x, const in
   const int eu = eperm[e];
   T F[D][D], beta[K][D], vol, P[D][D];
   load_element<T, D>(mv, e, x, F, beta, vol);
-  snh_pk1<T, D>(F, mu, lam, P);
+  material_pk1<T, D>(F, mu, lam, model, P);
   for (int a = 0; a < K; ++a)
     for (int r = 0; r < D; ++r) {
       T s = T(0);
@@ -748,6 +748,15 @@ static inline int nblocks(long long n, int per) { return (int)((n + per - 1) / p
     else { constexpr int D = 3; __VA_ARGS__; }     \
   } while (0)
 
+// Material-dependent kernels come in two builds: FCR = false compiles the
+// stable neo-Hookean path alone (its register budget untouched by the
+// Fixed Corotational SVD); FCR = true follows each mesh's model at run time.
+#define CC_DISPATCH_MAT(any_fcr, ...)                          \
+  do {                                                         \
+    if (any_fcr) { constexpr bool FCR = true; __VA_ARGS__; }   \
+    else { constexpr bool FCR = false; __VA_ARGS__; }          \
+  } while (0)
+
 void launch_predict(const MeshView& mv, const int* vperm, const double* x_user, const double* v_user,
                     const double* x_bc, double h, int quasi, double* x, double* xt, double* x0,
                     int* bad, hipStream_t s) {
@@ -766,12 +775,14 @@ void launch_elem_hess(const MeshView& mv, int prec, const double* x, const Mater
   if (mv.m == 0) return;
   const int nb = nblocks(mv.m, EWG);
   if (prec == 0)
-    CC_DISPATCH_D(mv.D, k_elem_hess<double, D><<<nb, EWG, 0, s>>>(mv, x, mat.mu, mat.lam, scale,
-                                                                (double*)estore));
+    CC_DISPATCH_MAT(mat.model == MAT_FCR,
+                    CC_DISPATCH_D(mv.D, k_elem_hess<double, D, FCR><<<nb, EWG, 0, s>>>(
+                                            mv, x, mat.mu, mat.lam, mat.model, scale, (double*)estore)));
   else
-    CC_DISPATCH_D(mv.D, k_elem_hess<float, D><<<nb, EWG, 0, s>>>(mv, x, (float)mat.mu,
-                                                               (float)mat.lam, (float)scale,
-                                                               (float*)estore));
+    CC_DISPATCH_MAT(mat.model == MAT_FCR,
+                    CC_DISPATCH_D(mv.D, k_elem_hess<float, D, FCR><<<nb, EWG, 0, s>>>(
+                                            mv, x, (float)mat.mu, (float)mat.lam, mat.model, (float)scale,
+                                            (float*)estore)));
 }
 
 void launch_assemble(const MeshView& mv, int prec, const void* estore, const Material& mat,
@@ -799,7 +810,8 @@ void launch_gradient(const MeshView& mv, const double* x, const double* xt, cons
   const int nb = nblocks(mv.nf, WG / GRAD_G);
   *nparts = nb;
   if (nb == 0) return;
-  CC_DISPATCH_D(mv.D, k_gradient<D, GRAD_G><<<nb, WG, 0, s>>>(mv, x, xt, mat, g, partials));
+  CC_DISPATCH_MAT(mat.model == MAT_FCR,
+                  CC_DISPATCH_D(mv.D, k_gradient<D, GRAD_G, FCR><<<nb, WG, 0, s>>>(mv, x, xt, mat, g, partials)));
 }
 
 template <typename T, int D>
@@ -901,7 +913,8 @@ void launch_energy(const MeshView& mv, const double* x, const double* xt, const 
   const int nbe = nblocks(mv.m, WG), nbv = nblocks(mv.nf, WG);
   *nparts = nbe + nbv;
   if (nbe + nbv == 0) return;
-  CC_DISPATCH_D(mv.D, k_energy<D><<<nbe + nbv, WG, 0, s>>>(mv, x, xt, mat, nbe, partials));
+  CC_DISPATCH_MAT(mat.model == MAT_FCR,
+                  CC_DISPATCH_D(mv.D, k_energy<D, FCR><<<nbe + nbv, WG, 0, s>>>(mv, x, xt, mat, nbe, partials)));
 }
 
 void launch_reduce(const double* partials, int n, double* out, hipStream_t s) {
@@ -981,10 +994,11 @@ void launch_probe_element(const MeshView& mv, int prec, const double* x_user, co
   launch_elem_hess(mv, prec, xi_tmp, mat, 1.0, est, s);
   if (prec == 0)
     CC_DISPATCH_D(mv.D, k_probe_elem<double, D><<<nb, WG, 0, s>>>(mv, xi_tmp, eperm, (const double*)est,
-                                                                 mat.mu, mat.lam, ge, He));
+                                                                 mat.mu, mat.lam, mat.model, ge, He));
   else
     CC_DISPATCH_D(mv.D, k_probe_elem<float, D><<<nb, WG, 0, s>>>(mv, xi_tmp, eperm, (const float*)est,
-                                                                (float)mat.mu, (float)mat.lam, ge, He));
+                                                                (float)mat.mu, (float)mat.lam, mat.model, ge,
+                                                                He));
 }
 
 void launch_gather_user(const MeshView& mv, const int* vperm_inv, const double* src_user,
@@ -1074,7 +1088,7 @@ __global__ void __launch_bounds__(WG) kb_finalize(const BatchItem* __restrict__ 
   }
 }
 
-template <typename T, int D>
+template <typename T, int D, bool FCR>
 __global__ void __launch_bounds__(EWG) kb_elem_hess(const BatchItem* __restrict__ items,
                                                    const BatchCtl* __restrict__ ctl,
                                                    const int* __restrict__ boff, int nmesh, int which) {
@@ -1083,7 +1097,7 @@ __global__ void __launch_bounds__(EWG) kb_elem_hess(const BatchItem* __restrict_
   const BatchItem& it = items[mi];
   const MeshView mv = it.mv;
   elem_hess_body<T, D>(mv, (blockIdx.x - boff[mi]) * EWG + threadIdx.x, pick(it, which), T(it.mat.mu),
-                       T(it.mat.lam), T(it.mat.s_el), (T*)it.estore);
+                       T(it.mat.lam), FCR ? it.mat.model : MAT_SNH, T(it.mat.s_el), (T*)it.estore);
 }
 
 // Corotation: vertex rotations of every mesh at positions `which`.
@@ -1111,7 +1125,7 @@ __global__ void __launch_bounds__(EWG) kb_assemble(const BatchItem* __restrict__
                       T(it.mat.w_in), (T*)it.hb);
 }
 
-template <int D, int G>
+template <int D, int G, bool FCR>
 __global__ void __launch_bounds__(WG) kb_gradient(const BatchItem* __restrict__ items,
                                                   const BatchCtl* __restrict__ ctl,
                                                   const int* __restrict__ boff, int nmesh, int which) {
@@ -1121,7 +1135,7 @@ __global__ void __launch_bounds__(WG) kb_gradient(const BatchItem* __restrict__ 
   const BatchItem& it = items[mi];
   const MeshView mv = it.mv;
   const int lb = blockIdx.x - boff[mi];
-  const double gsq = gradient_body<D, G>(mv, lb * (WG / G) + threadIdx.x / G, threadIdx.x % G,
+  const double gsq = gradient_body<D, G, FCR>(mv, lb * (WG / G) + threadIdx.x / G, threadIdx.x % G,
                                          pick(it, which), it.xt, it.mat, it.g);
   const double tot = block_sum<WG>(gsq, red);
   if (threadIdx.x == 0) it.partials[lb] = tot;
@@ -1205,7 +1219,7 @@ __global__ void __launch_bounds__(WG) kb_axpy(const BatchItem* __restrict__ item
   it.xtrial[t] = copy_only ? it.x[t] : it.x[t] + alpha * it.d[t];
 }
 
-template <int D>
+template <int D, bool FCR>
 __global__ void __launch_bounds__(WG) kb_energy(const BatchItem* __restrict__ items,
                                                 const BatchCtl* __restrict__ ctl,
                                                 const int* __restrict__ boff, int nmesh, int which) {
@@ -1216,7 +1230,7 @@ __global__ void __launch_bounds__(WG) kb_energy(const BatchItem* __restrict__ it
   const MeshView mv = it.mv;
   const int lb = blockIdx.x - boff[mi];
   const int nbe = (mv.m + WG - 1) / WG;
-  const double v = energy_body<D>(mv, lb, nbe, pick(it, which), it.xt, it.mat);
+  const double v = energy_body<D, FCR>(mv, lb, nbe, pick(it, which), it.xt, it.mat);
   const double tot = block_sum<WG>(v, red);
   if (threadIdx.x == 0) it.partials[lb] = tot;
 }
@@ -1431,7 +1445,8 @@ template <int D>
 static void b_gradient(BatchPlan* p, int which, hipStream_t s) {
   if (gridn(p->grad) == 0) return;
   p->mark(2, 1);
-  kb_gradient<D, GRAD_G><<<gridn(p->grad), WG, 0, s>>>(p->items_d, p->ctl_d, p->grad.d, p->nmesh, which);
+  CC_DISPATCH_MAT(p->cfg.any_fcr, kb_gradient<D, GRAD_G, FCR><<<gridn(p->grad), WG, 0, s>>>(
+                                      p->items_d, p->ctl_d, p->grad.d, p->nmesh, which));
   p->mark(2, 0);
   kb_reduce<<<p->nmesh, WG, 0, s>>>(p->items_d, p->ctl_d, p->grad.d, 1);
 }
@@ -1440,7 +1455,8 @@ template <int D>
 static void b_energy(BatchPlan* p, int which, int dst, hipStream_t s) {
   if (gridn(p->energy) == 0) return;
   p->mark(5, 1);
-  kb_energy<D><<<gridn(p->energy), WG, 0, s>>>(p->items_d, p->ctl_d, p->energy.d, p->nmesh, which);
+  CC_DISPATCH_MAT(p->cfg.any_fcr, kb_energy<D, FCR><<<gridn(p->energy), WG, 0, s>>>(
+                                      p->items_d, p->ctl_d, p->energy.d, p->nmesh, which));
   p->mark(5, 0);
   kb_reduce<<<p->nmesh, WG, 0, s>>>(p->items_d, p->ctl_d, p->energy.d, dst);
 }
@@ -1479,7 +1495,8 @@ static void b_hessian(BatchPlan* p, int which, hipStream_t s) {
     kb_rotations<D><<<gridn(p->rotn), WG, 0, s>>>(p->items_d, p->ctl_d, p->rotn.d, p->nmesh, which);
   if (gridn(p->elem) > 0) {
     p->mark(0, 1);
-    kb_elem_hess<T, D><<<gridn(p->elem), EWG, 0, s>>>(p->items_d, p->ctl_d, p->elem.d, p->nmesh, which);
+    CC_DISPATCH_MAT(p->cfg.any_fcr, kb_elem_hess<T, D, FCR><<<gridn(p->elem), EWG, 0, s>>>(
+                                        p->items_d, p->ctl_d, p->elem.d, p->nmesh, which));
     p->mark(0, 0);
   }
   if (gridn(p->asmb) > 0) {
@@ -1514,7 +1531,8 @@ static void b_iteration(BatchPlan* p, hipStream_t s) {
       }
       if (gridn(p->grad) > 0) {
         p->mark(2, 1);
-        kb_gradient<D, GRAD_G><<<gridn(p->grad), WG, 0, s>>>(p->items_d, p->ctl_d, p->grad.d, nm, 1);
+        CC_DISPATCH_MAT(c.any_fcr, kb_gradient<D, GRAD_G, FCR><<<gridn(p->grad), WG, 0, s>>>(
+                                       p->items_d, p->ctl_d, p->grad.d, nm, 1));
         p->mark(2, 0);
       }
       b_update<T, D, G>(p, col, 1, s);
@@ -1601,6 +1619,7 @@ BatchGrid batch_grid(BatchPlan* p) {
   g.feat_off = p->feat.d;
   g.tol = p->cfg.tol;
   g.max_iters = p->cfg.max_iters;
+  g.any_fcr = p->cfg.any_fcr;
   return g;
 }
 

@@ -46,8 +46,8 @@ void mlp_gradient(const MlpState& s, const float* X, const float* T, const int* 
 void mlp_adam(MlpState& s, const float* grad, float lr, hipStream_t st);
 void mlp_stats(MlpState& s, const float* X, int N, hipStream_t st);
 void launch_features(const MeshView& mv, const double* xt, const double* x0, double h, double E, double mu,
-                     double lam, double ell, const int* nptr, const int* nidx, const double* Xr, float* out,
-                     const int* rowmap, hipStream_t st);
+                     double lam, int model, double ell, const int* nptr, const int* nidx, const double* Xr,
+                     float* out, const int* rowmap, hipStream_t st);
 void launch_targets(const MeshView& mv, const double* xn, const double* xt, double ell, const int* rowmap,
                     float* T, hipStream_t st);
 void launch_proposal(int n, int nf, const double* xt, const float* delta, double ell, double* xp,

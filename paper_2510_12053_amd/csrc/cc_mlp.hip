@@ -389,11 +389,12 @@ constexpr int FEAT_G = FEAT_LANES;
 // the neighbour list and the incident elements, then combine by shuffles.
 // Every lane of the group must call it (j may be past the free range: the
 // group then contributes nothing and writes nothing).
-template <int G>
+template <int G, bool FCR>
 __device__ __forceinline__ void features_group(const MeshView& mv, int j, int lane,
                                                const double* __restrict__ xt, const double* __restrict__ x0,
-                                               double h, double E, double mu, double lam, double ell,
-                                               const int* __restrict__ nptr, const int* __restrict__ nidx,
+                                               double h, double E, double mu, double lam, int model,
+                                               double ell, const int* __restrict__ nptr,
+                                               const int* __restrict__ nidx,
                                                const double* __restrict__ Xr, float* __restrict__ out) {
   constexpr int D = 3;
   const int n = mv.n;
@@ -417,7 +418,7 @@ __device__ __forceinline__ void features_group(const MeshView& mv, int j, int la
     const int e = mv.star[t] >> 2, a = mv.star[t] & 3;
     double F[3][3], beta[4][3], vol;
     load_element<double, 3>(mv, e, xt, F, beta, vol);
-    snh_projected_eigs<double, 3>(F, mu, lam, [&](double w, const double (&Q)[3][3]) {
+    projected_eigs<double, 3>(F, mu, lam, FCR ? model : MAT_SNH, [&](double w, const double (&Q)[3][3]) {
       double y[3];
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
@@ -489,15 +490,16 @@ __device__ __forceinline__ void features_group(const MeshView& mv, int j, int la
 }
 
 // rowmap: null -> row j (internal order), else row rowmap[j]
+template <bool FCR>
 __global__ void __launch_bounds__(WG) k_features(MeshView mv, const double* __restrict__ xt,
                                                  const double* __restrict__ x0, double h, double E,
-                                                 double mu, double lam, double ell,
+                                                 double mu, double lam, int model, double ell,
                                                  const int* __restrict__ nptr, const int* __restrict__ nidx,
                                                  const double* __restrict__ Xr, float* __restrict__ out,
                                                  const int* __restrict__ rowmap) {
   const int j = blockIdx.x * (WG / FEAT_G) + threadIdx.x / FEAT_G;
   const int row = (j < mv.nf) ? (rowmap ? rowmap[j] : j) : 0;
-  features_group<FEAT_G>(mv, j, threadIdx.x % FEAT_G, xt, x0, h, E, mu, lam, ell, nptr, nidx, Xr,
+  features_group<FEAT_G, FCR>(mv, j, threadIdx.x % FEAT_G, xt, x0, h, E, mu, lam, model, ell, nptr, nidx, Xr,
                          out + (size_t)row * 16);
 }
 
@@ -551,11 +553,14 @@ void mlp_stats(MlpState& s, const float* X, int N, hipStream_t st) {
 }
 
 void launch_features(const MeshView& mv, const double* xt, const double* x0, double h, double E, double mu,
-                     double lam, double ell, const int* nptr, const int* nidx, const double* Xr, float* out,
-                     const int* rowmap, hipStream_t st) {
+                     double lam, int model, double ell, const int* nptr, const int* nidx, const double* Xr,
+                     float* out, const int* rowmap, hipStream_t st) {
   if (mv.nf <= 0) return;
-  k_features<<<(mv.nf + WG / FEAT_G - 1) / (WG / FEAT_G), WG, 0, st>>>(mv, xt, x0, h, E, mu, lam, ell, nptr,
-                                                                       nidx, Xr, out, rowmap);
+  const int nb = (mv.nf + WG / FEAT_G - 1) / (WG / FEAT_G);
+  if (model == MAT_FCR)
+    k_features<true><<<nb, WG, 0, st>>>(mv, xt, x0, h, E, mu, lam, model, ell, nptr, nidx, Xr, out, rowmap);
+  else
+    k_features<false><<<nb, WG, 0, st>>>(mv, xt, x0, h, E, mu, lam, model, ell, nptr, nidx, Xr, out, rowmap);
 }
 
 // Training targets (x_new - x_tilde) / ell of the free vertices, caller-order
@@ -581,6 +586,7 @@ void launch_proposal(int n, int nf, const double* xt, const float* delta, double
 }
 
 // ---- warm start of a batch (all meshes per launch, no host round trip) ------
+template <bool FCR>
 __global__ void __launch_bounds__(WG) kb_features(const BatchItem* __restrict__ items,
                                                   const BatchCtl* __restrict__ ctl,
                                                   const int* __restrict__ boff, int nmesh,
@@ -590,8 +596,8 @@ __global__ void __launch_bounds__(WG) kb_features(const BatchItem* __restrict__ 
   const BatchItem& it = items[mi];
   const MeshView mv = it.mv;
   const int j = (blockIdx.x - boff[mi]) * (WG / FEAT_G) + threadIdx.x / FEAT_G;
-  features_group<FEAT_G>(mv, j, threadIdx.x % FEAT_G, it.x, it.x0, sqrt(it.mat.s_el), it.youngs, it.mat.mu,
-                         it.mat.lam, it.ell, it.nptr, it.nidx, it.Xr,
+  features_group<FEAT_G, FCR>(mv, j, threadIdx.x % FEAT_G, it.x, it.x0, sqrt(it.mat.s_el), it.youngs, it.mat.mu,
+                         it.mat.lam, it.mat.model, it.ell, it.nptr, it.nidx, it.Xr,
                          feat + (size_t)(it.feat_off + (j < mv.nf ? j : 0)) * MLP_IN);
 }
 
@@ -644,7 +650,12 @@ void batch_warm_start(BatchPlan* p, const MlpState& net, float* feat, float* del
   BatchCtl* ctl = batch_ctl_dev(p);
   const int gb = (g.nmesh + WG - 1) / WG;
   if (g.pred_blocks == 0) return;
-  if (g.feat_blocks > 0) kb_features<<<g.feat_blocks, WG, 0, s>>>(items, ctl, g.feat_off, g.nmesh, feat);
+  if (g.feat_blocks > 0) {
+    if (g.any_fcr)
+      kb_features<true><<<g.feat_blocks, WG, 0, s>>>(items, ctl, g.feat_off, g.nmesh, feat);
+    else
+      kb_features<false><<<g.feat_blocks, WG, 0, s>>>(items, ctl, g.feat_off, g.nmesh, feat);
+  }
   mlp_forward(net, feat, rows, delta, s);
   kb_proposal<<<g.pred_blocks, WG, 0, s>>>(items, ctl, g.pred_off, g.nmesh, delta);
   batch_energy_x(p, s);

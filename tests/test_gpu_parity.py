@@ -284,3 +284,26 @@ def test_corotated_steps(cg, ctx):
     for res, st, it, rg, xo, xg, vo, vg in out:
         assert st == cg.CC_OK and it == res.iters
         assert _rel(xg, xo, s.X) <= 1e-6
+
+
+def test_corotated_directions_inverted_neighbourhood(cg, ctx):
+    """Corotated sweep at a state where two free vertices' neighbourhood
+    matrices sum (x_k - x_j)(X_k - X_j)^T have negative determinant: their
+    rotations are the proper rotations nearest to those matrices (the sign of
+    the determinant sits on the smallest singular value)."""
+    s = tet_bar(8, 4, 4, E=1e6, twist_per_step=0.4)
+    p = Problem.from_scene(s)
+    B = exact_basis(p)
+    mid = _upload(cg, ctx, s)
+    cg.cc_subspace_upload(ctx, mid, *B, s.dt)
+    x = s.X + 0.2 * np.random.default_rng(1).normal(size=s.X.shape)
+    x[p.fixed] = s.X[p.fixed]
+    nbr = S.mesh_neighbours(p)
+    dets = [np.linalg.det((x[nbr[j]] - x[j]).T @ (s.X[nbr[j]] - s.X[j])) for j in p.free]
+    assert sum(d < 0 for d in dets) == 2
+    p.set_inertial_target(x)
+    par = cg.cc_params_default(method=cg.METHOD_CC, gravity=s.gravity, corotate=1)
+    E, g, dx = cg.cc_probe_sweep(ctx, mid, _t(x), _t(p.x_tilde), s.dt, par)
+    Um = S.rotate_basis(p, basis_matrix(p, *B), S.vertex_rotations(p, x))
+    dxo, _ = S.local_directions(p, Um, p.hessian(x), p.gradient(x), np.arange(p.free.size), S.CC)
+    assert np.max(np.abs(dx.cpu().numpy()[p.free] - dxo)) <= 1e-9 * np.max(np.abs(dxo))

@@ -180,7 +180,7 @@ def trace_summary(folder, bench_log):
           f"{lp:.1f} + {lf:.1f} = {lp + lf:.1f} us per pair; bench.py's HIP-event average of the "
           f"same launches in this run: {ro['avg_launch_us']} us.\n")
     sel = {k: b[k] for k in ("value", "ms_per_step", "learned_batched", "batched", "plain_cc",
-                             "roofline") if k in b}
+                             "roofline", "corotation", "fixed_corotational") if k in b}
     print("bench.py line of the profiled run (selected fields):\n\n```\n" + json.dumps(sel, indent=1)
           + "\n```")
 

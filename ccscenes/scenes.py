@@ -29,6 +29,7 @@ class Scene:
     quasistatic: bool
     target_fn: Callable[[int], np.ndarray] = field(repr=False, default=None)
     x_init: Optional[np.ndarray] = field(repr=False, default=None)
+    v_init: Optional[np.ndarray] = field(repr=False, default=None)
     meta: dict = field(default_factory=dict)
     material: str = "snh"      # "snh" stable neo-Hookean, "fcr" Fixed Corotational
 
@@ -48,7 +49,7 @@ class Scene:
 
     def initial_state(self):
         x = self.X.copy() if self.x_init is None else self.x_init.copy()
-        v = np.zeros_like(x)
+        v = np.zeros_like(x) if self.v_init is None else self.v_init.copy()
         return x, v
 
 
@@ -112,6 +113,19 @@ def tet_bar(nx=21, ny=6, nz=6, E=1e5, nu=0.45, rho=1000.0, dt=1.0 / 60, n_steps=
                  quasistatic=False, target_fn=target_fn,
                  meta=dict(nx=nx, ny=ny, nz=nz, clamp_face=clamp_face,
                            twist_per_step=twist_per_step))
+
+
+def rod_impulse(nx=41, E=1e3, nu=0.3, rho=1000.0, dt=1.0 / 60, length=1.0, width=0.05, speed=0.1):
+    """Free rod [0,length]x[0,width]^2 on an nx*2*2 vertex grid (the 1D rod of
+    the paper's stiffness sweep, as a chain of tets): no Dirichlet vertex, no
+    gravity; the four vertices of the right end start with velocity -speed
+    along x (the impulse), every other vertex at rest.  One step."""
+    X, tets = grid3d(nx, 2, 2, length, width, width)
+    v0 = np.zeros_like(X)
+    v0[np.arange(X.shape[0]) % nx == nx - 1, 0] = -speed
+    return Scene(name=f"rod_{nx}x2x2", dim=3, X=X, elems=tets, fixed=np.zeros(X.shape[0], np.uint8),
+                 E=E, nu=nu, rho=rho, gravity=np.zeros(3), dt=dt, n_steps=1, quasistatic=False,
+                 v_init=v0, meta=dict(nx=nx, speed=speed))
 
 
 def twist_beam(nx=81, ny=21, nz=21, E=1e7, nu=0.45, rho=1000.0, dt=1.0 / 60, n_steps=30,

@@ -1,17 +1,22 @@
 #!/usr/bin/env python
-"""The paper's resolution experiment run on one MI355X (Results, Mesh
-Resolution Scaling): the quasistatic stretch of a unit square (left edge
-held, right edge moved +50% in x) at n x n vertices for n = 5 .. 29, solved
-by Coordinate Condensation (exact basis), JGS2 (exact basis) and plain
-coordinate descent, each as the Jacobi sweep of Algorithm 1 without line
-search, from the same start, to rel|grad E| <= TOL or MAX_ITERS iterations.
+"""The paper's two convergence sweeps run on one MI355X (Results, Mesh
+Resolution Scaling and Material Stiffness Scaling), iteration counts of
+Coordinate Condensation (exact basis), JGS2 (exact basis) and plain
+coordinate descent, each as the Jacobi sweep of Algorithm 1.
 
-Prints a Markdown table and one JSON line.  Stable neo-Hookean material
-(E = 1e5, nu = 0.4) and a relative termination test replace the paper's
-Fixed Corotational model and its absolute measure, whose threshold the
-stretch already nearly meets at the start in these units.
+resolution: the quasistatic stretch of a unit square (left edge held, right
+  edge moved +50% in x) at n x n vertices for n = 5 .. 29; no line search;
+  rel|grad E| <= 1e-4 or 500 iterations.
+stiffness:  one implicit step of a free rod (41 x 2 x 2 vertices, 1 m long)
+  whose right end is struck (-0.1 m/s along the rod), E = 1e1 .. 1e6 Pa;
+  backtracking line search; rel|grad E| <= 1e-6 or 10,000 iterations.
 
-    python experiments.py
+The material is the paper's Fixed Corotational model by default (--material
+snh for stable neo-Hookean).  A relative termination test replaces the
+paper's absolute measures (see the package's design notes).  Prints a
+Markdown table and one JSON line per sweep.
+
+    python experiments.py [--sweep resolution|stiffness|all] [--material fcr|snh]
 """
 import argparse
 import json
@@ -25,56 +30,86 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 SIZES = (5, 9, 13, 17, 21, 25, 29)
-TOL = 1e-4
-MAX_ITERS = 500
+STIFFNESS = (1e1, 1e2, 1e3, 1e4, 1e5, 1e6)
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--tol", type=float, default=TOL)
-    ap.add_argument("--max-iters", type=int, default=MAX_ITERS)
-    args = ap.parse_args()
-
+def _solve(cg, ctx, dev, s, mid, method, line_search, max_iters, tol):
     import torch
-    import paper_2510_12053_amd.ccgpu as cg
-    from ccscenes import stretch2d
+    x, v = s.initial_state()
+    xg = torch.tensor(x, dtype=torch.float64, device=dev)
+    vg = torch.tensor(v, dtype=torch.float64, device=dev)
+    par = cg.cc_params_default(method=method, sweep=cg.SWEEP_JACOBI, line_search=line_search,
+                               max_iters=max_iters, quasistatic=int(s.quasistatic), gravity=s.gravity)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, it, rg = cg.cc_step(ctx, mid, xg, vg, torch.tensor(s.targets(1), device=dev), s.dt, par, tol)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    ok = st == cg.CC_OK and np.isfinite(rg)
+    return {"iters": int(it), "rel_grad": float(rg), "status": int(st), "ms": round(ms, 2), "converged": bool(ok)}
 
-    dev = torch.device("cuda:0")
-    ctx = cg.cc_create(0, torch.cuda.Stream(device=dev))
-    methods = (("CC", cg.METHOD_CC), ("JGS2", cg.METHOD_JGS2), ("CD", cg.METHOD_CD))
-    rows = []
-    for n in SIZES:
-        s = stretch2d(n=n)
-        mid = cg.cc_mesh_upload(ctx, s.X, s.elems, s.fixed, s.E, s.nu, s.rho)
-        cg.cc_subspace_build(ctx, mid, 0, s.dt, True)          # exact basis of the quasistatic energy
-        row = {"n": n, "verts": s.n, "free": int((~s.fixed.astype(bool)).sum())}
-        for name, m in methods:
-            x, v = s.initial_state()
-            xg = torch.tensor(x, dtype=torch.float64, device=dev)
-            vg = torch.tensor(v, dtype=torch.float64, device=dev)
-            par = cg.cc_params_default(method=m, sweep=cg.SWEEP_JACOBI, line_search=0,
-                                       max_iters=args.max_iters, quasistatic=1)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st, it, rg = cg.cc_step(ctx, mid, xg, vg, torch.tensor(s.targets(1), device=dev), s.dt,
-                                    par, args.tol)
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) * 1e3
-            ok = st == cg.CC_OK and np.isfinite(rg)
-            row[name] = {"iters": int(it), "rel_grad": float(rg), "status": int(st), "ms": round(ms, 2),
-                         "converged": bool(ok)}
-        rows.append(row)
 
-    print(f"| n x n | free vertices | CC iterations | JGS2 iterations | CD iterations |")
+def _upload(cg, ctx, s, material):
+    mid = cg.cc_mesh_upload(ctx, s.X, s.elems, s.fixed, s.E, s.nu, s.rho)
+    cg.cc_mesh_set_material(ctx, mid, cg.MATERIAL_FCR if material == "fcr" else cg.MATERIAL_SNH)
+    cg.cc_subspace_build(ctx, mid, 0, s.dt, bool(s.quasistatic))    # exact basis of the step energy
+    return mid
+
+
+def _table(rows, key, label, methods, extra):
+    print(f"| {label} | {extra[0]} | CC iterations | JGS2 iterations | CD iterations |")
     print("|---|---|---|---|---|")
     for r in rows:
         cells = []
         for name, _ in methods:
             e = r[name]
             cells.append(str(e["iters"]) if e["converged"] else f">{e['iters']} (r = {e['rel_grad']:.1e})")
-        print(f"| {r['n']} x {r['n']} | {r['free']} | " + " | ".join(cells) + " |")
-    print(json.dumps({"experiment": "resolution_sweep_stretch2d", "tol": args.tol,
-                      "max_iters": args.max_iters, "rows": rows}))
+        print(f"| {key(r)} | {r[extra[1]]} | " + " | ".join(cells) + " |")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--sweep", choices=("resolution", "stiffness", "all"), default="all")
+    ap.add_argument("--material", choices=("fcr", "snh"), default="fcr")
+    args = ap.parse_args()
+
+    import torch
+    import paper_2510_12053_amd.ccgpu as cg
+    from ccscenes import rod_impulse, stretch2d
+
+    dev = torch.device("cuda:0")
+    ctx = cg.cc_create(0, torch.cuda.Stream(device=dev))
+    methods = (("CC", cg.METHOD_CC), ("JGS2", cg.METHOD_JGS2), ("CD", cg.METHOD_CD))
+
+    if args.sweep in ("resolution", "all"):
+        tol, cap = 1e-4, 500
+        rows = []
+        for n in SIZES:
+            s = stretch2d(n=n)
+            mid = _upload(cg, ctx, s, args.material)
+            row = {"n": n, "verts": s.n, "free": int((~s.fixed.astype(bool)).sum())}
+            for name, m in methods:
+                row[name] = _solve(cg, ctx, dev, s, mid, m, 0, cap, tol)
+            rows.append(row)
+            print(f"resolution {n}x{n} done", flush=True)
+        _table(rows, lambda r: f"{r['n']} x {r['n']}", "n x n", methods, ("free vertices", "free"))
+        print(json.dumps({"experiment": "resolution_sweep_stretch2d", "material": args.material, "tol": tol,
+                          "max_iters": cap, "line_search": False, "rows": rows}), flush=True)
+
+    if args.sweep in ("stiffness", "all"):
+        tol, cap = 1e-6, 10000
+        rows = []
+        for E in STIFFNESS:
+            s = rod_impulse(E=E)
+            mid = _upload(cg, ctx, s, args.material)
+            row = {"E": E, "verts": s.n}
+            for name, m in methods:
+                row[name] = _solve(cg, ctx, dev, s, mid, m, 1, cap, tol)
+            rows.append(row)
+            print(f"stiffness E={E:g} done", flush=True)
+        _table(rows, lambda r: f"{r['E']:.0e}", "E (Pa)", methods, ("vertices", "verts"))
+        print(json.dumps({"experiment": "stiffness_sweep_rod", "material": args.material, "tol": tol,
+                          "max_iters": cap, "line_search": True, "rows": rows}), flush=True)
     cg.cc_destroy(ctx)
 
 

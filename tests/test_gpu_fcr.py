@@ -17,7 +17,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from ccscenes import stretch2d, tet_bar
+from ccscenes import rod_impulse, stretch2d, tet_bar
 from oracle import mlp as M
 from oracle import solvers as S
 from oracle.basis import basis_matrix, exact_basis
@@ -239,3 +239,17 @@ def test_mixed_batch_equals_single_meshes(cg, ctx):
     # the two materials give different motions of the same bar
     assert np.linalg.norm(xs[0].cpu().numpy() - xs[1].cpu().numpy()) > 1e-6 * np.linalg.norm(
         xs[0].cpu().numpy() - scenes[0].X)
+
+
+@pytest.mark.parametrize("E,method", [(1e1, S.CC), (1e6, S.CC), (1e3, S.JGS2), (1e3, S.CD)])
+def test_rod_impulse_step(cg, ctx, E, method):
+    """One step of the struck free rod of the stiffness sweep (no Dirichlet
+    vertex), Jacobi with line search to rel|g| <= 1e-6: equal iterations and
+    positions against the oracle."""
+    s = _fcr(rod_impulse(E=E))
+    gm = {S.CC: cg.METHOD_CC, S.JGS2: cg.METHOD_JGS2, S.CD: cg.METHOD_CD}[method]
+    par = cg.cc_params_default(method=gm, sweep=cg.SWEEP_JACOBI, line_search=1, max_iters=500)
+    op = S.Params(method=method, sweep=S.JACOBI, line_search=True, max_iters=500)
+    (res, st, it, rg, xo, xg), = _run_steps(cg, ctx, s, par, op, 1e-6, 1)
+    assert st == cg.CC_OK and res.status == S.OK and it == res.iters
+    assert _rel(xg, xo, s.X) <= 1e-6

@@ -213,3 +213,30 @@ def test_closed_form_spectrum(d, inverted):
         ref.extend(np.linalg.eigvalsh(A))
         w = np.linalg.eigvalsh(0.5 * (C[k] + C[k].T))
         assert np.allclose(np.sort(w), np.sort(ref), atol=1e-8 * np.abs(ref).max())
+
+
+def test_rod_stiffness_ordering():
+    """The struck free rod (Results, Material Stiffness Scaling): with the
+    exact basis CC needs a few iterations at every stiffness, while JGS2's
+    count grows with E and CD's exceeds a 100-iteration cap once E = 1e4."""
+    import dataclasses
+
+    from ccscenes import rod_impulse
+    from oracle import solvers as S
+    from oracle.timestep import predictor
+
+    def iters(E, method, cap):
+        s = dataclasses.replace(rod_impulse(E=E), material=mt.FCR)
+        p = Problem.from_scene(s)
+        B = exact_basis(p)
+        x0, v0 = s.initial_state()
+        xh = predictor(p, x0, v0, s.targets(1))
+        res = S.solve(p, xh, B, S.Params(method=method, sweep=S.JACOBI, line_search=True, max_iters=cap), 1e-6)
+        return res.iters, res.status
+
+    cc = [iters(E, S.CC, 50) for E in (1e1, 1e4, 1e6)]
+    assert all(st == S.OK and it <= 4 for it, st in cc)
+    j1, j2 = iters(1e1, S.JGS2, 200), iters(1e4, S.JGS2, 200)
+    assert j1[1] == S.OK and j2[1] == S.OK and j2[0] > 10 * j1[0]
+    cd = iters(1e4, S.CD, 100)
+    assert cd == (100, S.NOT_CONVERGED)

@@ -95,7 +95,32 @@ __device__ __forceinline__ void assemble_body(const MeshView& mv, int t, const T
 #pragma unroll
   for (int r = 0; r < DD; ++r) acc[r] = T(0);
   const int m = mv.m;
-  for (int c = mv.cptr[t]; c < mv.cptr[t + 1]; ++c) {
+  // Contributions are summed in list order (so results are reproducible bit
+  // for bit), with the blocks of four consecutive entries loaded before any
+  // is added: a diagonal slot gathers one block per incident element, and a
+  // chain of dependent index and block loads would set its time.
+  const int c1 = mv.cptr[t + 1];
+  int c = mv.cptr[t];
+  for (; c + 4 <= c1; c += 4) {
+    T v[4][DD];
+    bool tr[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int pk = mv.centry[c + q];
+      const int e = pk >> 4, a = (pk >> 2) & 3, b = pk & 3;
+      tr[q] = a > b;
+      const T* blk = est + ((size_t)pidx<K>(tr[q] ? b : a, tr[q] ? a : b) * m + e) * DD;
+#pragma unroll
+      for (int r = 0; r < DD; ++r) v[q][r] = blk[r];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < D; ++r)
+#pragma unroll
+        for (int s = 0; s < D; ++s) acc[r * D + s] += tr[q] ? v[q][s * D + r] : v[q][r * D + s];
+  }
+  for (; c < c1; ++c) {
     const int pk = mv.centry[c];
     const int e = pk >> 4, a = (pk >> 2) & 3, b = pk & 3;
     if (a <= b) {
@@ -459,7 +484,9 @@ template <typename T, int D>
 __device__ __forceinline__ void dm_finish_body(const MeshView& mv, int method, int i,
                                                const T* __restrict__ hb, T* __restrict__ KL,
                                                unsigned long long* __restrict__ fb,
-                                               const double* __restrict__ g, double* __restrict__ dout) {
+                                               const double* __restrict__ g, double* __restrict__ dout,
+                                               const double* __restrict__ x = nullptr,
+                                               double* __restrict__ xtrial = nullptr) {
   constexpr int DD = D * D;
   T A[DD], Ht[DD];
   const T* in = KL + (size_t)i * 2 * DD;
@@ -488,6 +515,8 @@ __device__ __forceinline__ void dm_finish_body(const MeshView& mv, int method, i
 #pragma unroll
     for (int l = 0; l < D; ++l) acc += kl[r * D + l] * gt[l];
     dout[(size_t)r * n + i] = -double(acc);
+    // the Jacobi trial point x + d of this vertex (the batched path's axpy)
+    if (xtrial != nullptr) xtrial[(size_t)r * n + i] = x[(size_t)r * n + i] - double(acc);
   }
 }
 
@@ -1066,6 +1095,9 @@ __global__ void __launch_bounds__(WG) kb_predict(const BatchItem* __restrict__ i
     }
     it.xt[c * n + v] = xh;
     it.x[c * n + v] = xh;
+    // both position buffers start equal, so the Dirichlet entries of the
+    // trial buffer hold the targets whichever buffer the step ends in
+    it.xtrial[c * n + v] = xh;
   }
   if (!ok) atomicOr(&ctl[mi].bad, 1);
 }
@@ -1187,7 +1219,7 @@ __global__ void __launch_bounds__(WG) kb_dm_finish(const BatchItem* __restrict__
   const int i = v0 + (blockIdx.x - boff[mi]) * WG + threadIdx.x;
   if (i < v1)
     dm_finish_body<T, D>(it.mv, method, i, (const T*)it.hb, (T*)it.KL, it.fb, fuse ? it.g : nullptr,
-                         fuse ? it.d : nullptr);
+                         fuse ? it.d : nullptr, it.x, fuse ? it.xtrial : nullptr);
 }
 
 template <typename T, int D, int G>
@@ -1235,10 +1267,38 @@ __global__ void __launch_bounds__(WG) kb_energy(const BatchItem* __restrict__ it
   if (threadIdx.x == 0) it.partials[lb] = tot;
 }
 
+// Accept the iteration of an active mesh when E did not rise beyond the
+// slack (or without line search); otherwise hand the mesh to the host for
+// backtracking.
+__device__ __forceinline__ void accept_mesh(BatchItem& item, BatchCtl& c, int line_search) {
+  const double tau = 1e-12 * fmax(fabs(c.E_cur), 1.0);
+  if (!line_search || c.E_trial <= c.E_cur + tau) {
+    double* t = item.x;
+    item.x = item.xtrial;
+    item.xtrial = t;
+    if (line_search) c.E_cur = c.E_trial;
+    c.iters += 1;
+  } else {
+    c.needs_host = 1;
+    c.active = 0;
+  }
+}
+
+// Convergence test of an active mesh after its gradient norm is in gn2.
+__device__ __forceinline__ void converged_mesh(BatchCtl& c, double tol, int max_iters) {
+  c.r = sqrt(c.gn2) / c.g0;
+  if (!isfinite(c.r)) { c.status = 2; c.active = 0; }
+  else if (c.r <= tol) { c.status = 0; c.active = 0; }
+  else if (c.iters >= max_iters) { c.status = 1; c.active = 0; }
+}
+
 // One workgroup per mesh: sums the partials written by the launch whose
-// block offsets are boff_src; dst 0 -> E_trial, 1 -> gn2, 2 -> E_cur.
-__global__ void __launch_bounds__(WG) kb_reduce(const BatchItem* __restrict__ items, BatchCtl* ctl,
-                                                const int* __restrict__ boff_src, int dst) {
+// block offsets are boff_src; dst 0 -> E_trial, 1 -> gn2, 2 -> E_cur.  Then,
+// on the same thread, post 1 applies the accept rule (dst 0) and post 2 the
+// convergence test (dst 1), saving the launch of kb_accept / kb_converged.
+__global__ void __launch_bounds__(WG) kb_reduce(BatchItem* __restrict__ items, BatchCtl* ctl,
+                                                const int* __restrict__ boff_src, int dst, int post,
+                                                double tol, int max_iters) {
   __shared__ double red[WG];
   const int mi = blockIdx.x;
   if (!ctl[mi].active) return;
@@ -1248,9 +1308,12 @@ __global__ void __launch_bounds__(WG) kb_reduce(const BatchItem* __restrict__ it
   for (int i = threadIdx.x; i < np; i += WG) v += part[i];
   const double tot = block_sum<WG>(v, red);
   if (threadIdx.x == 0) {
-    if (dst == 0) ctl[mi].E_trial = tot;
-    else if (dst == 1) ctl[mi].gn2 = tot;
-    else ctl[mi].E_cur = tot;
+    BatchCtl& c = ctl[mi];
+    if (dst == 0) c.E_trial = tot;
+    else if (dst == 1) c.gn2 = tot;
+    else c.E_cur = tot;
+    if (post == 1) accept_mesh(items[mi], c, 1);
+    else if (post == 2) converged_mesh(c, tol, max_iters);
   }
 }
 
@@ -1271,30 +1334,8 @@ __global__ void kb_init(BatchCtl* ctl, int nmesh, double tol, int max_iters) {
 __global__ void kb_accept(BatchItem* items, BatchCtl* ctl, int nmesh, int line_search) {
   const int m = blockIdx.x * WG + threadIdx.x;
   if (m >= nmesh) return;
-  BatchCtl& c = ctl[m];
-  if (!c.active) return;
-  const double tau = 1e-12 * fmax(fabs(c.E_cur), 1.0);
-  if (!line_search || c.E_trial <= c.E_cur + tau) {
-    double* t = items[m].x;
-    items[m].x = items[m].xtrial;
-    items[m].xtrial = t;
-    if (line_search) c.E_cur = c.E_trial;
-    c.iters += 1;
-  } else {
-    c.needs_host = 1;
-    c.active = 0;
-  }
-}
-
-__global__ void kb_converged(BatchCtl* ctl, int nmesh, double tol, int max_iters) {
-  const int m = blockIdx.x * WG + threadIdx.x;
-  if (m >= nmesh) return;
-  BatchCtl& c = ctl[m];
-  if (!c.active) return;
-  c.r = sqrt(c.gn2) / c.g0;
-  if (!isfinite(c.r)) { c.status = 2; c.active = 0; }
-  else if (c.r <= tol) { c.status = 0; c.active = 0; }
-  else if (c.iters >= max_iters) { c.status = 1; c.active = 0; }
+  if (!ctl[m].active) return;
+  accept_mesh(items[m], ctl[m], line_search);
 }
 
 // ---- host side of a batch ---------------------------------------------------
@@ -1310,7 +1351,7 @@ struct BatchPlan {
   std::vector<BatchItem> items_h;
   BatchItem* items_d = nullptr;
   BatchCtl* ctl_d = nullptr;
-  Offsets pred, elem, asmb, grad, energy, axpy, feat, rotn;
+  Offsets pred, elem, asmb, grad, energy, axpy, axpyj, feat, rotn;   // axpyj: Jacobi trial points
   std::vector<Offsets> prep, prepd, fin, upd;   // index 0: all free vertices, c+1: colour c
   int max_colours = 0;
   int tv = 0;       // vertices per workgroup of the dense condensation (0: no dense mesh)
@@ -1387,7 +1428,7 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
   p->cfg = cfg;
   p->items_h.assign(items_host, items_host + nmesh);
   std::vector<int> cpred(nmesh), celem(nmesh), casm(nmesh), cgrad(nmesh), cen(nmesh), cax(nmesh),
-      cfeat(nmesh), crot(nmesh);
+      caxj(nmesh), cfeat(nmesh), crot(nmesh);
   int dense_nf = 0;
   for (int m = 0; m < nmesh; ++m) {
     const MeshView& mv = p->items_h[m].mv;
@@ -1397,6 +1438,8 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
     cgrad[m] = nblocks(mv.nf, WG / GRAD_G);
     cen[m] = nblocks(mv.m, WG) + nblocks(mv.nf, WG);
     cax[m] = nblocks((long long)mv.D * mv.n, WG);
+    // a Jacobi sweep's dense finish writes the trial point itself
+    caxj[m] = (cfg.sweep == 0 && p->items_h[m].prep_dense) ? 0 : cax[m];
     cfeat[m] = nblocks(mv.nf, WG / FEAT_LANES);
     crot[m] = (cfg.corotate && mv.rot) ? nblocks(mv.nf, WG) : 0;
     p->max_colours = std::max(p->max_colours, p->items_h[m].ncol);
@@ -1412,6 +1455,7 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
   offsets_build(p->grad, cgrad, s);
   offsets_build(p->energy, cen, s);
   offsets_build(p->axpy, cax, s);
+  offsets_build(p->axpyj, caxj, s);
   offsets_build(p->feat, cfeat, s);
   offsets_build(p->rotn, crot, s);
   plan_vertex_offsets(p, s);
@@ -1425,7 +1469,8 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
 void batch_plan_destroy(BatchPlan* p) {
   if (!p) return;
   drop_graph(p);
-  for (Offsets* o : {&p->pred, &p->elem, &p->asmb, &p->grad, &p->energy, &p->axpy, &p->feat, &p->rotn})
+  for (Offsets* o : {&p->pred, &p->elem, &p->asmb, &p->grad, &p->energy, &p->axpy, &p->axpyj, &p->feat,
+                     &p->rotn})
     offsets_free(*o);
   for (auto& o : p->prep) offsets_free(o);
   for (auto& o : p->prepd) offsets_free(o);
@@ -1442,23 +1487,25 @@ BatchCtl* batch_ctl_dev(BatchPlan* p) { return p->ctl_d; }
 static inline int gridn(const Offsets& o) { return o.total(); }
 
 template <int D>
-static void b_gradient(BatchPlan* p, int which, hipStream_t s) {
+static void b_gradient(BatchPlan* p, int which, hipStream_t s, int post = 0) {
   if (gridn(p->grad) == 0) return;
   p->mark(2, 1);
   CC_DISPATCH_MAT(p->cfg.any_fcr, kb_gradient<D, GRAD_G, FCR><<<gridn(p->grad), WG, 0, s>>>(
                                       p->items_d, p->ctl_d, p->grad.d, p->nmesh, which));
   p->mark(2, 0);
-  kb_reduce<<<p->nmesh, WG, 0, s>>>(p->items_d, p->ctl_d, p->grad.d, 1);
+  kb_reduce<<<p->nmesh, WG, 0, s>>>(p->items_d, p->ctl_d, p->grad.d, 1, post, p->cfg.tol,
+                                    p->cfg.max_iters);
 }
 
 template <int D>
-static void b_energy(BatchPlan* p, int which, int dst, hipStream_t s) {
+static void b_energy(BatchPlan* p, int which, int dst, hipStream_t s, int post = 0) {
   if (gridn(p->energy) == 0) return;
   p->mark(5, 1);
   CC_DISPATCH_MAT(p->cfg.any_fcr, kb_energy<D, FCR><<<gridn(p->energy), WG, 0, s>>>(
                                       p->items_d, p->ctl_d, p->energy.d, p->nmesh, which));
   p->mark(5, 0);
-  kb_reduce<<<p->nmesh, WG, 0, s>>>(p->items_d, p->ctl_d, p->energy.d, dst);
+  kb_reduce<<<p->nmesh, WG, 0, s>>>(p->items_d, p->ctl_d, p->energy.d, dst, post, p->cfg.tol,
+                                    p->cfg.max_iters);
 }
 
 template <typename T, int D, int G>
@@ -1516,8 +1563,8 @@ static void b_iteration(BatchPlan* p, hipStream_t s) {
     b_hessian<T, D>(p, 0, s);
     b_prep<T, D, G>(p, -1, s, 1);
     b_update<T, D, G>(p, -1, 0, s);
-    if (gridn(p->axpy) > 0)
-      kb_axpy<<<gridn(p->axpy), WG, 0, s>>>(p->items_d, p->ctl_d, p->axpy.d, nm, 1.0, 0);
+    if (gridn(p->axpyj) > 0)
+      kb_axpy<<<gridn(p->axpyj), WG, 0, s>>>(p->items_d, p->ctl_d, p->axpyj.d, nm, 1.0, 0);
   } else {
     if (gridn(p->axpy) > 0)
       kb_axpy<<<gridn(p->axpy), WG, 0, s>>>(p->items_d, p->ctl_d, p->axpy.d, nm, 0.0, 1);
@@ -1538,10 +1585,11 @@ static void b_iteration(BatchPlan* p, hipStream_t s) {
       b_update<T, D, G>(p, col, 1, s);
     }
   }
-  if (c.line_search) b_energy<D>(p, 1, 0, s);
-  kb_accept<<<gb, WG, 0, s>>>(p->items_d, p->ctl_d, nm, c.line_search);
-  b_gradient<D>(p, 0, s);
-  kb_converged<<<gb, WG, 0, s>>>(p->ctl_d, nm, c.tol, c.max_iters);
+  if (c.line_search)
+    b_energy<D>(p, 1, 0, s, 1);   // E at the trial point, then the accept rule
+  else
+    kb_accept<<<gb, WG, 0, s>>>(p->items_d, p->ctl_d, nm, 0);
+  b_gradient<D>(p, 0, s, 2);      // gradient at the accepted point, then the convergence test
 }
 
 

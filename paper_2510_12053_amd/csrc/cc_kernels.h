@@ -180,11 +180,13 @@ struct BatchGrid {
   double tol;
   int max_iters;
   int any_fcr;          // some mesh uses the Fixed Corotational model
+  int line_search;      // E at the predictor is already in ctl.E_cur
 };
 BatchGrid batch_grid(BatchPlan* p);
 void batch_energy_trial(BatchPlan* p, hipStream_t s);   // ctl.E_trial = E(xtrial)
 void batch_energy_x(BatchPlan* p, hipStream_t s);       // ctl.E_cur = E(x)
-void batch_gradient_x(BatchPlan* p, hipStream_t s);     // g(x), ctl.gn2
+// g(x), ctl.gn2; only_warm: only meshes whose learned proposal was accepted
+void batch_gradient_x(BatchPlan* p, hipStream_t s, int only_warm = 0);
 void batch_warm_start(BatchPlan* p, const MlpState& net, float* feat, float* delta, int rows,
                       hipStream_t s);
 // Time one condensation + update pass of every mesh with the given lane count.

@@ -1160,10 +1160,11 @@ __global__ void __launch_bounds__(EWG) kb_assemble(const BatchItem* __restrict__
 template <int D, int G, bool FCR>
 __global__ void __launch_bounds__(WG) kb_gradient(const BatchItem* __restrict__ items,
                                                   const BatchCtl* __restrict__ ctl,
-                                                  const int* __restrict__ boff, int nmesh, int which) {
+                                                  const int* __restrict__ boff, int nmesh, int which,
+                                                  int only_warm) {
   __shared__ double red[WG];
   const int mi = block_mesh(boff, nmesh, blockIdx.x);
-  if (!ctl[mi].active) return;
+  if (!ctl[mi].active || (only_warm && !ctl[mi].warm)) return;
   const BatchItem& it = items[mi];
   const MeshView mv = it.mv;
   const int lb = blockIdx.x - boff[mi];
@@ -1296,12 +1297,14 @@ __device__ __forceinline__ void converged_mesh(BatchCtl& c, double tol, int max_
 // block offsets are boff_src; dst 0 -> E_trial, 1 -> gn2, 2 -> E_cur.  Then,
 // on the same thread, post 1 applies the accept rule (dst 0) and post 2 the
 // convergence test (dst 1), saving the launch of kb_accept / kb_converged.
+// only_warm: meshes whose learned proposal was rejected are skipped (their
+// positions, gradient and norm are those of the predictor, already known).
 __global__ void __launch_bounds__(WG) kb_reduce(BatchItem* __restrict__ items, BatchCtl* ctl,
                                                 const int* __restrict__ boff_src, int dst, int post,
-                                                double tol, int max_iters) {
+                                                double tol, int max_iters, int only_warm) {
   __shared__ double red[WG];
   const int mi = blockIdx.x;
-  if (!ctl[mi].active) return;
+  if (!ctl[mi].active || (only_warm && !ctl[mi].warm)) return;
   const double* part = items[mi].partials;
   const int np = boff_src[mi + 1] - boff_src[mi];
   double v = 0.0;
@@ -1487,14 +1490,14 @@ BatchCtl* batch_ctl_dev(BatchPlan* p) { return p->ctl_d; }
 static inline int gridn(const Offsets& o) { return o.total(); }
 
 template <int D>
-static void b_gradient(BatchPlan* p, int which, hipStream_t s, int post = 0) {
+static void b_gradient(BatchPlan* p, int which, hipStream_t s, int post = 0, int only_warm = 0) {
   if (gridn(p->grad) == 0) return;
   p->mark(2, 1);
   CC_DISPATCH_MAT(p->cfg.any_fcr, kb_gradient<D, GRAD_G, FCR><<<gridn(p->grad), WG, 0, s>>>(
-                                      p->items_d, p->ctl_d, p->grad.d, p->nmesh, which));
+                                      p->items_d, p->ctl_d, p->grad.d, p->nmesh, which, only_warm));
   p->mark(2, 0);
   kb_reduce<<<p->nmesh, WG, 0, s>>>(p->items_d, p->ctl_d, p->grad.d, 1, post, p->cfg.tol,
-                                    p->cfg.max_iters);
+                                    p->cfg.max_iters, only_warm);
 }
 
 template <int D>
@@ -1505,7 +1508,7 @@ static void b_energy(BatchPlan* p, int which, int dst, hipStream_t s, int post =
                                       p->items_d, p->ctl_d, p->energy.d, p->nmesh, which));
   p->mark(5, 0);
   kb_reduce<<<p->nmesh, WG, 0, s>>>(p->items_d, p->ctl_d, p->energy.d, dst, post, p->cfg.tol,
-                                    p->cfg.max_iters);
+                                    p->cfg.max_iters, 0);
 }
 
 template <typename T, int D, int G>
@@ -1579,7 +1582,7 @@ static void b_iteration(BatchPlan* p, hipStream_t s) {
       if (gridn(p->grad) > 0) {
         p->mark(2, 1);
         CC_DISPATCH_MAT(c.any_fcr, kb_gradient<D, GRAD_G, FCR><<<gridn(p->grad), WG, 0, s>>>(
-                                       p->items_d, p->ctl_d, p->grad.d, nm, 1));
+                                       p->items_d, p->ctl_d, p->grad.d, nm, 1, 0));
         p->mark(2, 0);
       }
       b_update<T, D, G>(p, col, 1, s);
@@ -1652,8 +1655,8 @@ void batch_iterate(BatchPlan* p, int iters, hipStream_t s) {
 void batch_energy_trial(BatchPlan* p, hipStream_t s) {
   if (p->cfg.D == 3) b_energy<3>(p, 1, 0, s); else b_energy<2>(p, 1, 0, s);
 }
-void batch_gradient_x(BatchPlan* p, hipStream_t s) {
-  if (p->cfg.D == 3) b_gradient<3>(p, 0, s); else b_gradient<2>(p, 0, s);
+void batch_gradient_x(BatchPlan* p, hipStream_t s, int only_warm) {
+  if (p->cfg.D == 3) b_gradient<3>(p, 0, s, 0, only_warm); else b_gradient<2>(p, 0, s, 0, only_warm);
 }
 void batch_energy_x(BatchPlan* p, hipStream_t s) {
   if (p->cfg.D == 3) b_energy<3>(p, 0, 2, s); else b_energy<2>(p, 0, 2, s);
@@ -1668,6 +1671,7 @@ BatchGrid batch_grid(BatchPlan* p) {
   g.tol = p->cfg.tol;
   g.max_iters = p->cfg.max_iters;
   g.any_fcr = p->cfg.any_fcr;
+  g.line_search = p->cfg.line_search;
   return g;
 }
 

@@ -658,10 +658,10 @@ void batch_warm_start(BatchPlan* p, const MlpState& net, float* feat, float* del
   }
   mlp_forward(net, feat, rows, delta, s);
   kb_proposal<<<g.pred_blocks, WG, 0, s>>>(items, ctl, g.pred_off, g.nmesh, delta);
-  batch_energy_x(p, s);
+  if (!g.line_search) batch_energy_x(p, s);   // with line search batch_begin computed it
   batch_energy_trial(p, s);
   kb_ws_accept<<<gb, WG, 0, s>>>(items, ctl, g.nmesh);
-  batch_gradient_x(p, s);
+  batch_gradient_x(p, s, 1);   // a rejected proposal leaves x, g and |g| at the predictor
   kb_ws_check<<<gb, WG, 0, s>>>(ctl, g.nmesh, g.tol);
 }
 

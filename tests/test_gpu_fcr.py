@@ -209,9 +209,11 @@ def test_features_match_oracle(cg, ctx):
     assert np.max(np.abs(fs - fo)[:, 6:12]) > 1e-6
 
 
-def test_mixed_batch_equals_single_meshes(cg, ctx):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mixed_batch_equals_single_meshes(cg, ctx, prec):
     """A batch of stable neo-Hookean and Fixed Corotational bars: every mesh
-    follows its own model and equals its single-mesh step."""
+    follows its own model and equals its single-mesh step (float64: 1e-10,
+    float32-mixed: 1e-5 relative to the displacement)."""
     scenes = [tet_bar(7, 3, 3, E=1e5), _fcr(tet_bar(7, 3, 3, E=1e5)), _fcr(tet_bar(9, 3, 3, E=1e6)),
               tet_bar(9, 3, 3, E=1e6)]
     mids, mids1 = [], []
@@ -222,7 +224,7 @@ def test_mixed_batch_equals_single_meshes(cg, ctx):
             cg.cc_subspace_upload(ctx, mid, *B, s.dt)
             lst.append(mid)
     cg.cc_batch_tuning(ctx, 16, 2)
-    par = cg.cc_params_default(max_iters=200, gravity=scenes[0].gravity)
+    par = cg.cc_params_default(max_iters=200, gravity=scenes[0].gravity, precision=prec)
     xs = [_t(s.initial_state()[0]) for s in scenes]
     vs = [_t(s.initial_state()[1]) for s in scenes]
     xs1 = [x.clone() for x in xs]
@@ -233,9 +235,11 @@ def test_mixed_batch_equals_single_meshes(cg, ctx):
         assert worst == cg.CC_OK
         for k, s in enumerate(scenes):
             st, it, rg = cg.cc_step(ctx, mids1[k], xs1[k], vs1[k], bcs[k], s.dt, par, 1e-8)
-            assert st == sts[k] and it == its[k]
+            assert st == sts[k]
+            assert it == its[k] if prec == 0 else abs(it - its[k]) <= 1
             a, b = xs[k].cpu().numpy(), xs1[k].cpu().numpy()
-            assert np.linalg.norm(a - b) <= 1e-10 * max(np.linalg.norm(b - s.X), 1e-3)
+            tol = 1e-10 if prec == 0 else 1e-5
+            assert np.linalg.norm(a - b) <= tol * max(np.linalg.norm(b - s.X), 1e-3)
     # the two materials give different motions of the same bar
     assert np.linalg.norm(xs[0].cpu().numpy() - xs[1].cpu().numpy()) > 1e-6 * np.linalg.norm(
         xs[0].cpu().numpy() - scenes[0].X)
@@ -253,3 +257,38 @@ def test_rod_impulse_step(cg, ctx, E, method):
     (res, st, it, rg, xo, xg), = _run_steps(cg, ctx, s, par, op, 1e-6, 1)
     assert st == cg.CC_OK and res.status == S.OK and it == res.iters
     assert _rel(xg, xo, s.X) <= 1e-6
+
+
+def test_material_switch_between_batch_calls(cg, ctx):
+    """Switching a mesh's material after a batch has run on it: the next
+    batched step follows the new model (its result equals the single-mesh
+    step with that model, and differs from the old model's)."""
+    scenes = [tet_bar(7, 3, 3, E=1e5), tet_bar(7, 3, 3, E=1e6)]
+    B = [exact_basis(Problem.from_scene(s)) for s in scenes]
+    mids = []
+    for s, b in zip(scenes, B):
+        mid = _upload(cg, ctx, s)
+        cg.cc_subspace_upload(ctx, mid, *b, s.dt)
+        mids.append(mid)
+    par = cg.cc_params_default(max_iters=200, gravity=scenes[0].gravity)
+    x0 = [_t(s.initial_state()[0]) for s in scenes]
+    v0 = [_t(s.initial_state()[1]) for s in scenes]
+    bcs = [_t(s.targets(1)) for s in scenes]
+    xa, va = [x.clone() for x in x0], [v.clone() for v in v0]
+    cg.cc_step_batch(ctx, mids, xa, va, bcs, scenes[0].dt, par, 1e-8)          # SNH plan
+    cg.cc_mesh_set_material(ctx, mids[1], cg.MATERIAL_FCR)
+    xb, vb = [x.clone() for x in x0], [v.clone() for v in v0]
+    worst, its, rgs, sts = cg.cc_step_batch(ctx, mids, xb, vb, bcs, scenes[0].dt, par, 1e-8)
+    assert worst == cg.CC_OK
+    # reference: fresh single meshes with the same materials
+    for k, (s, b) in enumerate(zip(scenes, B)):
+        s_k = _fcr(s) if k == 1 else s
+        mid = _upload(cg, ctx, s_k)
+        cg.cc_subspace_upload(ctx, mid, *b, s.dt)
+        x, v = x0[k].clone(), v0[k].clone()
+        st, it, rg = cg.cc_step(ctx, mid, x, v, bcs[k], s.dt, par, 1e-8)
+        assert st == sts[k] and it == its[k]
+        ref = x.cpu().numpy()
+        assert np.linalg.norm(xb[k].cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref - s.X)
+    d_old = np.linalg.norm(xa[1].cpu().numpy() - xb[1].cpu().numpy())
+    assert d_old > 1e-6 * np.linalg.norm(xb[1].cpu().numpy() - scenes[1].X)

@@ -154,7 +154,8 @@ __device__ __forceinline__ void jacobi_eig(T S[D][D], T V[D][D]) {
       for (int q = p + 1; q < D; ++q) {
         const T apq = S[p][q];
         const T app = S[p][p], aqq = S[q][q];
-        if (cabs(apq) <= eps * eps * (cabs(app) + cabs(aqq)) || apq == T(0)) {
+        // stop rotating a pair once it is below the rounding of its diagonal
+        if (cabs(apq) <= eps * (cabs(app) + cabs(aqq)) || apq == T(0)) {
           S[p][q] = S[q][p] = T(0);
           continue;
         }

@@ -128,6 +128,20 @@ def rod_impulse(nx=41, E=1e3, nu=0.3, rho=1000.0, dt=1.0 / 60, length=1.0, width
                  v_init=v0, meta=dict(nx=nx, speed=speed))
 
 
+def cantilever_bend(nx=21, ny=6, nz=6, E=1e6, nu=0.45, rho=1000.0, n_steps=20, g_max=GRAV):
+    """Quasistatic cantilever (the paper's subspace-quality scene): a tet bar
+    over [0,4]x[0,1]x[0,1] clamped at x = 0 and bent by gravity along -y that
+    grows linearly to g_max over n_steps load steps (gravity_at(t), t = 1..);
+    each step starts from the previous step's solution."""
+    s = tet_bar(nx, ny, nz, E=E, nu=nu, rho=rho, dt=1.0, n_steps=n_steps,
+                gravity=(0.0, -g_max, 0.0))
+    s.name = f"cantilever_{nx}x{ny}x{nz}"
+    s.quasistatic = True
+    s.meta = dict(s.meta, g_max=g_max)
+    s.meta["gravity_at"] = lambda t: np.array([0.0, -g_max * t / n_steps, 0.0])
+    return s
+
+
 def twist_beam(nx=81, ny=21, nz=21, E=1e7, nu=0.45, rho=1000.0, dt=1.0 / 60, n_steps=30,
                total_angle=np.pi / 2):
     """Beam over [0,4]x[0,1]x[0,1]: face x=0 held at rest, face x=4 rotated about

@@ -10,13 +10,18 @@ resolution: the quasistatic stretch of a unit square (left edge held, right
 stiffness:  one implicit step of a free rod (41 x 2 x 2 vertices, 1 m long)
   whose right end is struck (-0.1 m/s along the rod), E = 1e1 .. 1e6 Pa;
   backtracking line search; rel|grad E| <= 1e-6 or 10,000 iterations.
+subspace:   the quasistatic cantilever (21 x 6 x 6 vertices, E = --cantilever-E, clamped at x = 0)
+  bent by gravity growing to 1 g over 20 load steps (Results, Subspace
+  Quality): CC with the basis fixed at rest, restarted (rebuilt from the
+  current configuration every 5 steps) and corotated; Jacobi with line
+  search; rel|grad E| <= 1e-6 or 5,000 iterations per step.
 
 The material is the paper's Fixed Corotational model by default (--material
 snh for stable neo-Hookean).  A relative termination test replaces the
 paper's absolute measures (see the package's design notes).  Prints a
 Markdown table and one JSON line per sweep.
 
-    python experiments.py [--sweep resolution|stiffness|all] [--material fcr|snh]
+    python experiments.py [--sweep resolution|stiffness|subspace|all] [--material fcr|snh]
 """
 import argparse
 import json
@@ -69,13 +74,14 @@ def _table(rows, key, label, methods, extra):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--sweep", choices=("resolution", "stiffness", "all"), default="all")
+    ap.add_argument("--sweep", choices=("resolution", "stiffness", "subspace", "all"), default="all")
     ap.add_argument("--material", choices=("fcr", "snh"), default="fcr")
+    ap.add_argument("--cantilever-E", type=float, default=1e7)
     args = ap.parse_args()
 
     import torch
     import paper_2510_12053_amd.ccgpu as cg
-    from ccscenes import rod_impulse, stretch2d
+    from ccscenes import cantilever_bend, rod_impulse, stretch2d
 
     dev = torch.device("cuda:0")
     ctx = cg.cc_create(0, torch.cuda.Stream(device=dev))
@@ -110,6 +116,43 @@ def main():
         _table(rows, lambda r: f"{r['E']:.0e}", "E (Pa)", methods, ("vertices", "verts"))
         print(json.dumps({"experiment": "stiffness_sweep_rod", "material": args.material, "tol": tol,
                           "max_iters": cap, "line_search": True, "rows": rows}), flush=True)
+    if args.sweep in ("subspace", "all"):
+        tol, cap, every = 1e-6, 5000, 5
+        s = cantilever_bend(E=args.cantilever_E)
+        ga = s.meta["gravity_at"]
+        variants = (("fixed", 0, False), ("restarted", 0, True), ("corotated", 1, False))
+        mids = {name: _upload(cg, ctx, s, args.material) for name, _, _ in variants}
+        state = {name: torch.tensor(s.X, dtype=torch.float64, device=dev) for name, _, _ in variants}
+        vel = torch.zeros_like(state["fixed"])
+        bc = torch.tensor(s.targets(1), device=dev)
+        rows = []
+        for t in range(1, s.n_steps + 1):
+            row = {"step": t, "gravity": float(-ga(t)[1])}
+            for name, corot, restart in variants:
+                if restart and (t - 1) % every == 0:     # rebuild from the current configuration
+                    cg.cc_subspace_build_at(ctx, mids[name], state[name], 0, s.dt, True)
+                par = cg.cc_params_default(method=cg.METHOD_CC, sweep=cg.SWEEP_JACOBI, line_search=1,
+                                           max_iters=cap, quasistatic=1, gravity=ga(t), corotate=corot)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, it, rg = cg.cc_step(ctx, mids[name], state[name], vel.clone(), bc, s.dt, par, tol)
+                torch.cuda.synchronize()
+                row[name] = {"iters": int(it), "rel_grad": float(rg), "status": int(st),
+                             "ms": round((time.perf_counter() - t0) * 1e3, 2)}
+            rows.append(row)
+            tipmask = s.X[:, 0] == s.X[:, 0].max()
+            tip = (state["corotated"].cpu().numpy()[tipmask] - s.X[tipmask]).mean(axis=0)
+            row["tip_displacement"] = [round(float(c), 4) for c in tip]
+            print(f"subspace step {t} done", flush=True)
+        print("| load step | gravity (m/s^2) | fixed basis | restarted every 5 | corotated | tip displacement (m) |")
+        print("|---|---|---|---|---|---|")
+        for r in rows:
+            cells = [str(r[n]["iters"]) if r[n]["status"] == cg.CC_OK else f">{r[n]['iters']}"
+                     for n, _, _ in variants]
+            print(f"| {r['step']} | {r['gravity']:.3f} | " + " | ".join(cells) + f" | {r['tip_displacement']} |")
+        print(json.dumps({"experiment": "subspace_quality_cantilever", "material": args.material,
+                          "E": args.cantilever_E, "tol": tol,
+                          "max_iters": cap, "restart_every": every, "rows": rows}), flush=True)
     cg.cc_destroy(ctx)
 
 

@@ -160,6 +160,15 @@ cc_status cc_subspace_upload(cc_ctx* ctx, int32_t mesh_id, const int64_t* ptr,
 cc_status cc_subspace_build(cc_ctx* ctx, int32_t mesh_id, int32_t radius, double dt,
                             int32_t quasistatic);
 
+/* The same bases built from the projected step Hessian at the state x instead
+   of at rest: x is a device float64 buffer, n_verts x dim, caller vertex
+   order (Dirichlet rows are the positions their elements see).  This is the
+   reconstruction of the paper's restarted variant (Results, Subspace
+   Quality).  The Hessian must be positive definite on the free degrees of
+   freedom (CC_E_SUBSPACE otherwise; the previous basis is then kept). */
+cc_status cc_subspace_build_at(cc_ctx* ctx, int32_t mesh_id, const double* x, int32_t radius,
+                               double dt, int32_t quasistatic);
+
 /* Number of basis blocks of a mesh (*nnz), and a copy of the basis in the
    upload format (host outputs sized n_verts+1, nnz, nnz*dim*dim). */
 cc_status cc_subspace_nnz(cc_ctx* ctx, int32_t mesh_id, int64_t* nnz);

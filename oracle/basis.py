@@ -1,4 +1,4 @@
-"""Per-vertex perturbation basis (FP64), computed at rest.
+"""Per-vertex perturbation basis (FP64), computed at rest or at a given state.
 
 The paper builds, for every coordinate i, the response of the complementary
 degrees of freedom C (all free DOFs except vertex i's) to a unit perturbation
@@ -8,7 +8,10 @@ of vertex i while keeping zero force on C:
 
 (Background, JGS2 subsection; Method, Coordinate Condensation: "computed at
 the rest configuration").  H is the Hessian of the step energy at x = X (for
-dynamics that includes the mass term, M + h^2 K(X)).
+dynamics that includes the mass term, M + h^2 K(X)).  Given a state x, the
+same construction on the projected Hessian at x gives the basis that the
+paper's restarted variant reconstructs from the current configuration
+(Results, Subspace Quality).
 
 Two supports are provided:
 
@@ -27,21 +30,23 @@ maps a displacement of vertex i to the displacement of vertex j = idx[k].
 Dirichlet vertices have empty rows and never appear in a support.
 
 Pins: tests/test_oracle_basis_colour.py -- exact basis satisfies H_CC U_i + H_Ci = 0
-and matches a direct per-vertex solve of that equation; patch basis satisfies
-the patch equilibrium; Dirichlet vertices absent.
+and matches a direct per-vertex solve of that equation (at rest and at a
+deformed state); patch basis satisfies the patch equilibrium; Dirichlet
+vertices absent; the state-given basis at x = X is the rest basis.
 """
 import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 
-def rest_hessian(prob):
-    return prob.hessian(prob.X, project=True)
+def rest_hessian(prob, x=None):
+    """Projected step Hessian at rest, or at the state x when given."""
+    return prob.hessian(prob.X if x is None else x, project=True)
 
 
-def exact_basis(prob):
+def exact_basis(prob, x=None):
     d = prob.d
-    H = rest_hessian(prob).tocsc()
+    H = rest_hessian(prob, x).tocsc()
     lu = spla.splu(H)
     nf = prob.free.size
     ptr = np.zeros(prob.n + 1, dtype=np.int64)
@@ -77,10 +82,10 @@ def patch_supports(prob, R):
     return supp
 
 
-def patch_basis(prob, R=1, verts=None):
+def patch_basis(prob, R=1, verts=None, x=None):
     """Patch basis; with verts given, only those vertices get non-empty rows."""
     d = prob.d
-    H = rest_hessian(prob).tocsr()
+    H = rest_hessian(prob, x).tocsr()
     supp = patch_supports(prob, R)
     ptr = np.zeros(prob.n + 1, dtype=np.int64)
     idx_list, U_list = [], []

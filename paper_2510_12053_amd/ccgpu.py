@@ -66,6 +66,7 @@ def lib():
             "cc_layout": (I32, [P, I32, P, P]),
             "cc_subspace_upload": (I32, [P, I32, P, P, P, D]),
             "cc_subspace_build": (I32, [P, I32, I32, D, I32]),
+            "cc_subspace_build_at": (I32, [P, I32, P, I32, D, I32]),
             "cc_subspace_nnz": (I32, [P, I32, pI64]),
             "cc_subspace_download": (I32, [P, I32, P, P, P]),
             "cc_step": (I32, [P, I32, P, P, P, D, ctypes.POINTER(cc_params), D, pI32, pD]),
@@ -192,6 +193,11 @@ def cc_subspace_upload(ctx, mesh_id, ptr, idx, U, dt_used=0.0):
 
 def cc_subspace_build(ctx, mesh_id, radius, dt, quasistatic=False):
     _check(ctx, lib().cc_subspace_build(ctx.handle, mesh_id, radius, dt, int(quasistatic)))
+
+
+def cc_subspace_build_at(ctx, mesh_id, x, radius, dt, quasistatic=False):
+    """Basis from the Hessian at the state x (float64 CUDA tensor, n x dim)."""
+    _check(ctx, lib().cc_subspace_build_at(ctx.handle, mesh_id, _dptr(x), radius, dt, int(quasistatic)))
 
 
 def cc_subspace_download(ctx, mesh_id, n_verts, dim):

@@ -592,14 +592,19 @@ void dense_chol_solve(const std::vector<double>& L, int N, std::vector<double>& 
     }
 }
 
-void build_basis(cc_ctx* ctx, Mesh& M, int radius, double dt, int quasi) {
+// x_user: null for the rest state, else caller-order device positions (n x D)
+void build_basis(cc_ctx* ctx, Mesh& M, int radius, double dt, int quasi, const double* x_user = nullptr) {
   const int D = M.D, DD = D * D, nf = M.nf, n = M.n;
   hipStream_t s = ctx->stream;
-  // rest Hessian block rows in float64 from the library's kernels
-  std::vector<double> Xi((size_t)D * n);
-  for (int v = 0; v < n; ++v)
-    for (int c = 0; c < D; ++c) Xi[(size_t)c * n + v] = M.X[(size_t)M.vperm[v] * D + c];
-  HIPC(hipMemcpyAsync(M.x, Xi.data(), Xi.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  // Hessian block rows in float64 from the library's kernels, at rest or at x_user
+  if (x_user == nullptr) {
+    std::vector<double> Xi((size_t)D * n);
+    for (int v = 0; v < n; ++v)
+      for (int c = 0; c < D; ++c) Xi[(size_t)c * n + v] = M.X[(size_t)M.vperm[v] * D + c];
+    HIPC(hipMemcpyAsync(M.x, Xi.data(), Xi.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  } else {
+    cc::launch_gather_user(M.view(), M.d_vinv, x_user, M.x, s);
+  }
   Material mat{};
   mat.mu = M.mu; mat.lam = M.lam; mat.model = M.model;
   mat.w_in = quasi ? 0.0 : 1.0;
@@ -627,7 +632,7 @@ void build_basis(cc_ctx* ctx, Mesh& M, int radius, double dt, int quasi) {
     dfree(A); dfree(work); dfree(badf);
     if (!ok) {
       dfree(Ud); dfree(Uf);
-      throw ApiError{CC_E_SUBSPACE, "rest Hessian not positive definite"};
+      throw ApiError{CC_E_SUBSPACE, "step Hessian not positive definite"};
     }
     std::vector<int64_t> sptr(nf + 1);
     for (int i = 0; i <= nf; ++i) sptr[i] = (int64_t)i * (nf > 0 ? nf - 1 : 0);
@@ -999,6 +1004,17 @@ cc_status cc_subspace_build(cc_ctx* ctx, int32_t mesh_id, int32_t radius, double
     Mesh& M = get_mesh(ctx, mesh_id);
     if (radius < 0 || (!quasistatic && !(dt > 0))) return fail(ctx, CC_E_INVALID_ARG, "bad basis arguments");
     build_basis(ctx, M, radius, dt, quasistatic);
+    return CC_OK;
+  });
+}
+
+cc_status cc_subspace_build_at(cc_ctx* ctx, int32_t mesh_id, const double* x, int32_t radius, double dt,
+                               int32_t quasistatic) {
+  return guarded(ctx, [&]() -> cc_status {
+    Mesh& M = get_mesh(ctx, mesh_id);
+    if (!x) return fail(ctx, CC_E_INVALID_ARG, "null state buffer");
+    if (radius < 0 || (!quasistatic && !(dt > 0))) return fail(ctx, CC_E_INVALID_ARG, "bad basis arguments");
+    build_basis(ctx, M, radius, dt, quasistatic, x);
     return CC_OK;
   });
 }

@@ -307,3 +307,46 @@ def test_corotated_directions_inverted_neighbourhood(cg, ctx):
     Um = S.rotate_basis(p, basis_matrix(p, *B), S.vertex_rotations(p, x))
     dxo, _ = S.local_directions(p, Um, p.hessian(x), p.gradient(x), np.arange(p.free.size), S.CC)
     assert np.max(np.abs(dx.cpu().numpy()[p.free] - dxo)) <= 1e-9 * np.max(np.abs(dxo))
+
+
+@pytest.mark.parametrize("kind", ["exact", "R1"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_basis_builder_at_state(cg, ctx, kind, dim):
+    """cc_subspace_build_at: the basis from the projected Hessian at a
+    deformed state (the restarted variant) against the oracle's."""
+    s = stretch2d(n=9) if dim == 2 else tet_bar(8, 4, 4, E=1e6)
+    p = Problem.from_scene(s)
+    x = s.X + 0.03 * np.random.default_rng(11).normal(size=s.X.shape)
+    x[p.fixed] = s.X[p.fixed]
+    radius = 0 if kind == "exact" else 1
+    B = exact_basis(p, x) if radius == 0 else patch_basis(p, 1, x=x)
+    mid = _upload(cg, ctx, s)
+    cg.cc_subspace_build_at(ctx, mid, _t(x), radius, s.dt, s.quasistatic)
+    ptr, idx, U = cg.cc_subspace_download(ctx, mid, s.n, s.X.shape[1])
+    np.testing.assert_array_equal(ptr, B[0])
+    np.testing.assert_array_equal(idx, B[1])
+    assert np.max(np.abs(U - B[2])) <= 1e-8 * np.max(np.abs(B[2]))
+    B0 = exact_basis(p) if radius == 0 else patch_basis(p, 1)
+    assert np.max(np.abs(U - B0[2])) > 1e-4 * np.max(np.abs(B0[2]))
+
+
+def test_restarted_cantilever_steps(cg, ctx):
+    """Three quasistatic load steps of a small cantilever, the basis rebuilt
+    from the current configuration before each step, against the oracle."""
+    from ccscenes import cantilever_bend
+    s = cantilever_bend(8, 3, 3, E=1e7, n_steps=3)
+    ga = s.meta["gravity_at"]
+    mid = _upload(cg, ctx, s)
+    xg = _t(s.X)
+    x = s.X.copy()
+    for t in (1, 2, 3):
+        p = Problem(s.X, s.elems, s.fixed, s.E, s.nu, s.rho, ga(t), s.dt, True)
+        B = exact_basis(p, x)
+        cg.cc_subspace_build_at(ctx, mid, xg, 0, s.dt, True)
+        par = cg.cc_params_default(method=cg.METHOD_CC, sweep=cg.SWEEP_JACOBI, line_search=1,
+                                   max_iters=300, quasistatic=1, gravity=ga(t))
+        st, it, rg = cg.cc_step(ctx, mid, xg, torch.zeros_like(xg), _t(s.targets(t)), s.dt, par, 1e-8)
+        res = S.solve(p, x, B, S.Params(method=S.CC, sweep=S.JACOBI, line_search=True, max_iters=300), 1e-8)
+        x = res.x
+        assert st == cg.CC_OK and res.status == S.OK and it == res.iters
+        assert _rel(xg.cpu().numpy(), x, s.X) <= 1e-6

@@ -17,12 +17,18 @@ def _small_problems():
 
 
 @pytest.mark.parametrize("k", [0, 1])
-def test_exact_basis_definition(k):
-    """H_CC U_i + H_Ci = 0 and U_i = -H_CC^{-1} H_Ci by a direct dense solve."""
+@pytest.mark.parametrize("deformed", [False, True])
+def test_exact_basis_definition(k, deformed):
+    """H_CC U_i + H_Ci = 0 and U_i = -H_CC^{-1} H_Ci by a direct dense solve,
+    with H at rest or at a deformed state (the restarted basis)."""
     p = _small_problems()[k]
     d = p.d
-    ptr, idx, U = exact_basis(p)
-    H = rest_hessian(p).toarray()
+    x = None
+    if deformed:
+        x = p.X + 0.05 * np.random.default_rng(k).normal(size=p.X.shape)
+        x[p.fixed] = p.X[p.fixed]
+    ptr, idx, U = exact_basis(p, x)
+    H = (p.hessian(p.X if x is None else x)).toarray()
     for i in p.free:
         fi = p.fidx[i]
         C = [j for j in range(p.free.size) if j != fi]
@@ -131,3 +137,15 @@ def test_layout_orderings():
         fr = [new_of[a] for a in s.elems[e] if col[a] >= 0]
         ekey.append((min(fr) if fr else 10 ** 12, e))
     assert ekey == sorted(ekey)
+
+
+def test_state_basis_at_rest_is_rest_basis():
+    p = _small_problems()[1]
+    a, b = exact_basis(p), exact_basis(p, p.X.copy())
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    np.testing.assert_array_equal(a[2], b[2])
+    x = p.X + 0.05 * np.random.default_rng(3).normal(size=p.X.shape)
+    x[p.fixed] = p.X[p.fixed]
+    c = exact_basis(p, x)
+    assert np.max(np.abs(c[2] - a[2])) > 1e-3 * np.max(np.abs(a[2]))

@@ -826,7 +826,7 @@ void launch_assemble(const MeshView& mv, int prec, const void* estore, const Mat
                                                               (float)mat.w_in, (float*)hb));
 }
 
-constexpr int GRAD_G = 8;
+constexpr int GRAD_G = 16;   // lanes per vertex of the gradient: a 3D star holds about 24 elements
 
 int reduce_partials_capacity(const MeshView& mv) {
   const int a = nblocks(mv.nf, WG / GRAD_G);

@@ -18,10 +18,10 @@ condensation kernels (kb_prep_dm + kb_dm_finish) and the hash of the kernel
 source they were measured on.  bench.py reports the traffic only while that
 hash matches the current source.
 
-    cd /tmp && export TMPDIR=/tmp
-    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/ctr_fetch -o run -- python -u $R/bench_counters.py
-    timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/ctr_write -o run -- python -u $R/bench_counters.py
-    python $R/bench_counters.py --summarize $R/gpurun_out/ctr_fetch $R/gpurun_out/ctr_write > $R/profiles/traffic_kb_prep_dm_bar21x6x6_fp64.md
+    cd /tmp && export TMPDIR=/tmp          # R: repository root, OUT: an output folder
+    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/ctr_fetch -o run -- python -u $R/bench_counters.py
+    timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/ctr_write -o run -- python -u $R/bench_counters.py
+    python $R/bench_counters.py --summarize $OUT/ctr_fetch $OUT/ctr_write > $R/profiles/traffic_kb_prep_dm_bar21x6x6_fp64.md
 """
 import argparse
 import csv
@@ -123,12 +123,12 @@ def summarize(fetch_dir, write_dir):
            "write_bytes_per_launch": round(write), "fetch_scale": round(sf, 4),
            "write_scale": round(sw, 4), "dispatches": len(prep_f), "source_sha256_16": source_hash()}
     print("# HBM traffic: exact-basis condensation, four 21x6x6 bars, float64\n")
-    print("Commands (repo root `$R`, one MI355X):\n")
+    print("Commands (repo root `$R`, output folder `$OUT`, one MI355X):\n")
     print("```")
     print("cd /tmp && export TMPDIR=/tmp")
-    print("timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/ctr_fetch -o run -- python -u $R/bench_counters.py")
-    print("timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/ctr_write -o run -- python -u $R/bench_counters.py")
-    print("python $R/bench_counters.py --summarize $R/gpurun_out/ctr_fetch $R/gpurun_out/ctr_write")
+    print("timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/ctr_fetch -o run -- python -u $R/bench_counters.py")
+    print("timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/ctr_write -o run -- python -u $R/bench_counters.py")
+    print("python $R/bench_counters.py --summarize $OUT/ctr_fetch $OUT/ctr_write")
     print("```\n")
     print("Every condensation launch covers all four bars (one iteration per step).  "
           f"Counters are scaled by the calibration copy of {COPY_BYTES >> 20} MiB "
@@ -143,7 +143,7 @@ def summarize(fetch_dir, write_dir):
 
 
 TRACE_CMD = ("cd /tmp && export TMPDIR=/tmp && timeout -k 10 600 rocprofv3 --kernel-trace --stats "
-             "--output-format csv -d $R/gpurun_out/kt_bench -o run -- python -u $R/bench.py --no-cpu-baseline")
+             "--output-format csv -d $OUT/kt_bench -o run -- python -u $R/bench.py --no-cpu-baseline")
 
 
 def trace_summary(folder, bench_log):
@@ -155,7 +155,7 @@ def trace_summary(folder, bench_log):
     ro = b["roofline"]
     print("# Kernel statistics: four 21x6x6 bars (E = 1e4 .. 1e7), float64, plain / batched / "
           "learned+batched CC\n")
-    print("Command (repo root `$R`, one MI355X):\n")
+    print("Command (repo root `$R`, output folder `$OUT`, one MI355X):\n")
     print("```\n" + TRACE_CMD + "\n```\n")
     print("The profiled process runs the whole bench: warm-start data generation and training, the "
           "timed regions of plain CC (`k_*`), batched and learned+batched CC (`kb_*`, graph replays), "

@@ -273,8 +273,13 @@ __device__ __forceinline__ void svd_rv(const T F[D][D], T U[D][D], T V[D][D], T 
 // (the as-rigid-as-possible part has eigenvalue 2 mu everywhere except on the
 // twists, where the polar rotation turns with the element; t_kl is taken as 0
 // where sig_k + sig_l = 0 and the rotation has no derivative).  Eigen-matrices
-// map back as U E V^T.  callback(weight, Q) is invoked for each eigenpair with
-// weight > 0.
+// map back as U E V^T.
+//
+// callback(w, Q, P, same) adds w vec(Q) vec(P)^T to the projected Hessian:
+// once per eigenpair with weight w > 0 (P is Q, same = true), or, when the
+// scaling block A is positive definite (its projection is A itself, and no
+// eigen-solve is needed), once per k with Q = u_k v_k^T and
+// P = sum_l A_kl u_l v_l^T (w = 1, same = false).
 template <typename T, int D, typename CB>
 __device__ __forceinline__ void projected_eigs(const T F[D][D], T mu, T lam, int model, CB&& callback) {
   T U[D][D], V[D][D], sig[D];
@@ -303,23 +308,44 @@ __device__ __forceinline__ void projected_eigs(const T F[D][D], T mu, T lam, int
 #pragma unroll
     for (int l = 0; l < D; ++l)
       A[k][l] = (k == l) ? a0 + lam * c[k] * c[k] : lam * c[k] * c[l] + s * third[k][l];
-  T W[D][D];
-  jacobi_eig<T, D>(A, W);
+  // positive definite by Sylvester's criterion (leading principal minors)
+  bool pd = A[0][0] > T(0) && A[0][0] * A[1][1] - A[0][1] * A[1][0] > T(0);
+  if constexpr (D == 3) pd = pd && det<T, 3>(A) > T(0);
   T Q[D][D];
+  if (pd) {
+    T P[D][D];
 #pragma unroll
-  for (int r = 0; r < D; ++r) {
-    const T w = A[r][r];
-    if (w > T(0)) {
+    for (int k = 0; k < D; ++k) {
 #pragma unroll
       for (int i = 0; i < D; ++i)
 #pragma unroll
         for (int j = 0; j < D; ++j) {
+          Q[i][j] = U[i][k] * V[j][k];
           T acc = T(0);
 #pragma unroll
-          for (int k = 0; k < D; ++k) acc += W[k][r] * U[i][k] * V[j][k];
-          Q[i][j] = acc;
+          for (int l = 0; l < D; ++l) acc += A[k][l] * U[i][l] * V[j][l];
+          P[i][j] = acc;
         }
-      callback(w, Q);
+      callback(T(1), Q, P, false);
+    }
+  } else {
+    T W[D][D];
+    jacobi_eig<T, D>(A, W);
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      const T w = A[r][r];
+      if (w > T(0)) {
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int j = 0; j < D; ++j) {
+            T acc = T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) acc += W[k][r] * U[i][k] * V[j][k];
+            Q[i][j] = acc;
+          }
+        callback(w, Q, Q, true);
+      }
     }
   }
   const T h = T(0.70710678118654752440);
@@ -340,7 +366,7 @@ __device__ __forceinline__ void projected_eigs(const T F[D][D], T mu, T lam, int
         for (int i = 0; i < D; ++i)
 #pragma unroll
           for (int j = 0; j < D; ++j) Q[i][j] = h * U[i][k] * V[j][l] + b * U[i][l] * V[j][k];
-        callback(w, Q);
+        callback(w, Q, Q, true);
       }
     }
 }

@@ -34,15 +34,16 @@ __device__ __forceinline__ void elem_hess_body(const MeshView& mv, int e, const 
   for (int p = 0; p < NB; ++p)
 #pragma unroll
     for (int r = 0; r < DD; ++r) acc[p][r] = T(0);
-  projected_eigs<T, D>(F, mu, lam, model, [&](T w, const T (&Q)[D][D]) {
-    T y[K][D];
+  // y[a] = Q beta_a and z[a] = P beta_a (the vertex-a rows of the mode's
+  // matrices); block (a, b) gains w y[a] z[b]^T
+  auto rows = [&](const T (&M)[D][D], T (&y)[K][D]) {
 #pragma unroll
     for (int a = 1; a < K; ++a)
 #pragma unroll
       for (int r = 0; r < D; ++r) {
         T s = T(0);
 #pragma unroll
-        for (int q = 0; q < D; ++q) s += Q[r][q] * beta[a][q];
+        for (int q = 0; q < D; ++q) s += M[r][q] * beta[a][q];
         y[a][r] = s;
       }
 #pragma unroll
@@ -51,6 +52,18 @@ __device__ __forceinline__ void elem_hess_body(const MeshView& mv, int e, const 
 #pragma unroll
       for (int a = 1; a < K; ++a) s += y[a][r];
       y[0][r] = -s;
+    }
+  };
+  projected_eigs<T, D>(F, mu, lam, model, [&](T w, const T (&Q)[D][D], const T (&P)[D][D], bool same) {
+    T y[K][D], z[K][D];
+    rows(Q, y);
+    if (same) {
+#pragma unroll
+      for (int a = 0; a < K; ++a)
+#pragma unroll
+        for (int r = 0; r < D; ++r) z[a][r] = y[a][r];
+    } else {
+      rows(P, z);
     }
 #pragma unroll
     for (int a = 0; a < K; ++a) {
@@ -62,7 +75,7 @@ __device__ __forceinline__ void elem_hess_body(const MeshView& mv, int e, const 
 #pragma unroll
         for (int r = 0; r < D; ++r)
 #pragma unroll
-          for (int s = 0; s < D; ++s) acc[pidx<K>(a, b)][r * D + s] += wy[r] * y[b][s];
+          for (int s = 0; s < D; ++s) acc[pidx<K>(a, b)][r * D + s] += wy[r] * z[b][s];
     }
   });
   const T f = scale * vol;

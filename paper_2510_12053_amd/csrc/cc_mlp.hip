@@ -418,24 +418,35 @@ __device__ __forceinline__ void features_group(const MeshView& mv, int j, int la
     const int e = mv.star[t] >> 2, a = mv.star[t] & 3;
     double F[3][3], beta[4][3], vol;
     load_element<double, 3>(mv, e, xt, F, beta, vol);
-    projected_eigs<double, 3>(F, mu, lam, FCR ? model : MAT_SNH, [&](double w, const double (&Q)[3][3]) {
-      double y[3];
+    // vertex a's row of a mode matrix M: M beta_a (beta_0 = -(beta_1 + beta_2 + beta_3))
+    auto row = [&](const double (&M)[3][3], double (&y)[3]) {
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
         double s = 0.0;
         if (a == 0) {
 #pragma unroll
-          for (int q = 0; q < 3; ++q) s -= Q[r][q] * (beta[1][q] + beta[2][q] + beta[3][q]);
+          for (int q = 0; q < 3; ++q) s -= M[r][q] * (beta[1][q] + beta[2][q] + beta[3][q]);
         } else {
 #pragma unroll
-          for (int q = 0; q < 3; ++q) s += Q[r][q] * beta[a][q];
+          for (int q = 0; q < 3; ++q) s += M[r][q] * beta[a][q];
         }
         y[r] = s;
+      }
+    };
+    projected_eigs<double, 3>(F, mu, lam, FCR ? model : MAT_SNH,
+                              [&](double w, const double (&Q)[3][3], const double (&P)[3][3], bool same) {
+      double y[3], z[3];
+      row(Q, y);
+      if (same) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) z[r] = y[r];
+      } else {
+        row(P, z);
       }
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int s2 = 0; s2 < 3; ++s2) Hd[r][s2] += vol * w * y[r] * y[s2];
+        for (int s2 = 0; s2 < 3; ++s2) Hd[r][s2] += vol * w * y[r] * z[s2];
     });
     double ic = 0.0;
 #pragma unroll

@@ -44,14 +44,18 @@ def rest_hessian(prob, x=None):
     return prob.hessian(prob.X if x is None else x, project=True)
 
 
-def exact_basis(prob, x=None):
+def exact_basis(prob, x=None, verts=None):
+    """Exact basis; with verts given (vertex ids), only those rows are filled."""
     d = prob.d
     H = rest_hessian(prob, x).tocsc()
     lu = spla.splu(H)
     nf = prob.free.size
     ptr = np.zeros(prob.n + 1, dtype=np.int64)
     idx_list, U_list = [], []
+    want = None if verts is None else set(int(v) for v in verts)
     for fi, i in enumerate(prob.free):
+        if want is not None and int(i) not in want:
+            continue
         E = np.zeros((prob.ndof, d))
         E[fi * d:(fi + 1) * d, :] = np.eye(d)
         Z = lu.solve(E).reshape(nf, d, d)              # Z[j] = rows of vertex j

@@ -149,3 +149,20 @@ def test_state_basis_at_rest_is_rest_basis():
     x[p.fixed] = p.X[p.fixed]
     c = exact_basis(p, x)
     assert np.max(np.abs(c[2] - a[2])) > 1e-3 * np.max(np.abs(a[2]))
+
+
+def test_exact_basis_rows_subset():
+    """Rows computed for a subset of vertices equal the full basis's rows;
+    the other rows are empty."""
+    p = _small_problems()[1]
+    full = exact_basis(p)
+    sub = [int(p.free[0]), int(p.free[5]), int(p.free[-1])]
+    part = exact_basis(p, verts=sub)
+    for i in range(p.n):
+        a0, a1 = full[0][i], full[0][i + 1]
+        b0, b1 = part[0][i], part[0][i + 1]
+        if i in sub:
+            np.testing.assert_array_equal(part[1][b0:b1], full[1][a0:a1])
+            np.testing.assert_array_equal(part[2][b0:b1], full[2][a0:a1])
+        else:
+            assert b1 == b0

@@ -1441,8 +1441,7 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
       items[i].xu = x[i];
       items[i].vu = v[i];
       items[i].xbc = x_bc ? x_bc[i] : nullptr;
-      M.last_halvings = 0;
-      HIPC(hipMemsetAsync(M.fb, 0, 4 * sizeof(unsigned long long), s));
+      M.last_halvings = 0;          // fallback counters are cleared by batch_begin
     }
     cc::BatchItem* items_d = cc::batch_items_dev(plan);
     cc::BatchCtl* ctl_d = cc::batch_ctl_dev(plan);
@@ -1475,11 +1474,14 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
     };
     if ((size_t)n * sizeof(cc::BatchCtl) > 64 * 1024)
       return fail(ctx, CC_E_INVALID_ARG, "batch too large");
-    pull_ctl();
-    for (int i = 0; i < n; ++i)
-      if (ctl[i].bad) return fail(ctx, CC_E_NONFINITE, "non-finite x, v or x_bc in batch");
+    // The first round is queued without reading the control blocks back:
+    // meshes that converged at the predictor, or whose input is not finite,
+    // are already inactive on the device and skip it; the read after the
+    // round reports them.
+    for (auto& c : ctl) c.active = 1;
     long long guard = 0;
     int queue = std::min(std::max(ctx->plan_prev_iters, k), 16);   // first round
+    bool first = true;
     while (true) {
       bool any = false;
       for (auto& c : ctl) any = any || c.active;
@@ -1488,6 +1490,22 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
       queue = k;
       if (!cc::batch_has_graph(plan) && !ctx->graph_pairs.empty()) ctx->drop_graph_pairs();
       pull_ctl();
+      if (first) {
+        first = false;
+        bool bad = false;
+        for (int i = 0; i < n; ++i) bad = bad || ctl[i].bad;
+        if (bad) {
+          // the other meshes may have run the round: keep the host's view of
+          // their position buffers in step with the device before failing
+          HIPC(hipMemcpyAsync(items.data(), items_d, n * sizeof(cc::BatchItem), hipMemcpyDeviceToHost, s));
+          HIPC(hipStreamSynchronize(s));
+          for (int i = 0; i < n; ++i) {
+            ms[i]->x = items[i].x;
+            ms[i]->xtrial = items[i].xtrial;
+          }
+          return fail(ctx, CC_E_NONFINITE, "non-finite x, v or x_bc in batch");
+        }
+      }
       ctx->harvest();
       if (cc::batch_has_graph(plan)) ctx->harvest_graph();
       bool host = false;

@@ -1074,13 +1074,17 @@ __device__ __forceinline__ void vertex_range(const BatchItem& it, int colour, in
   else { v0 = v1 = 0; }
 }
 
-__global__ void kb_reset(BatchCtl* ctl, int nmesh) {
+// Start of a step: control block and fallback counters of every mesh.
+__global__ void kb_reset(const BatchItem* __restrict__ items, BatchCtl* ctl, int nmesh) {
   const int m = blockIdx.x * WG + threadIdx.x;
   if (m >= nmesh) return;
   BatchCtl c{};
   c.active = 1;
   c.status = -100;
   ctl[m] = c;
+  unsigned long long* fb = items[m].fb;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) fb[q] = 0ull;
 }
 
 template <int D>
@@ -1624,7 +1628,7 @@ static void one_iteration(BatchPlan* p, hipStream_t s) {
 
 void batch_begin(BatchPlan* p, hipStream_t s) {
   const int nm = p->nmesh, gb = nblocks(nm, WG);
-  kb_reset<<<gb, WG, 0, s>>>(p->ctl_d, nm);
+  kb_reset<<<gb, WG, 0, s>>>(p->items_d, p->ctl_d, nm);
   const int D = p->cfg.D;
   if (D == 2) kb_predict<2><<<gridn(p->pred), WG, 0, s>>>(p->items_d, p->ctl_d, p->pred.d, nm, p->cfg.h, p->cfg.quasistatic);
   else kb_predict<3><<<gridn(p->pred), WG, 0, s>>>(p->items_d, p->ctl_d, p->pred.d, nm, p->cfg.h, p->cfg.quasistatic);

@@ -158,3 +158,39 @@ def test_batch_with_converged_mesh(cg, ctx):
             assert st == sts[k] and it == its[k]
             a, b = xs[k].cpu().numpy(), xs1[k].cpu().numpy()
             assert np.linalg.norm(a - b) <= 1e-10 * max(np.linalg.norm(b - s.X), 1e-3)
+
+
+def test_batch_with_non_finite_input(cg, ctx):
+    """A batch in which one mesh gets a non-finite position fails with
+    CC_E_NONFINITE and leaves the caller's arrays as they were; the next
+    batched step of valid inputs equals single-mesh stepping."""
+    scenes = [tet_bar(6, 3, 3, E=1e5), tet_bar(7, 3, 3, E=1e6)]
+    mids, mids1 = [], []
+    for s in scenes:
+        B = exact_basis(Problem.from_scene(s))
+        for lst in (mids, mids1):
+            mid = cg.cc_mesh_upload(ctx, s.X, s.elems, s.fixed, s.E, s.nu, s.rho)
+            cg.cc_subspace_upload(ctx, mid, *B, s.dt)
+            lst.append(mid)
+    par = cg.cc_params_default(max_iters=200, gravity=scenes[0].gravity)
+    xs = [_t(s.initial_state()[0]) for s in scenes]
+    vs = [_t(s.initial_state()[1]) for s in scenes]
+    bcs = [_t(s.targets(1)) for s in scenes]
+    bad = xs[1].clone()
+    bad[4, 2] = float("nan")
+    xb = [xs[0].clone(), bad]
+    vb = [v.clone() for v in vs]
+    with pytest.raises(cg.CCError) as ei:
+        cg.cc_step_batch(ctx, mids, xb, vb, bcs, scenes[0].dt, par, 1e-8)
+    assert ei.value.status == -5
+    np.testing.assert_array_equal(xb[0].cpu().numpy(), xs[0].cpu().numpy())
+    np.testing.assert_array_equal(vb[0].cpu().numpy(), vs[0].cpu().numpy())
+    xa, va = [x.clone() for x in xs], [v.clone() for v in vs]
+    worst, its, rgs, sts = cg.cc_step_batch(ctx, mids, xa, va, bcs, scenes[0].dt, par, 1e-8)
+    assert worst == cg.CC_OK
+    for k, s in enumerate(scenes):
+        x1, v1 = xs[k].clone(), vs[k].clone()
+        st, it, rg = cg.cc_step(ctx, mids1[k], x1, v1, bcs[k], s.dt, par, 1e-8)
+        assert st == sts[k] and it == its[k]
+        assert np.linalg.norm(xa[k].cpu().numpy() - x1.cpu().numpy()) <= 1e-10 * np.linalg.norm(
+            x1.cpu().numpy() - s.X)

@@ -198,3 +198,52 @@ def test_corotated_batch_equals_single_mesh(cg, ctx, prec):
             assert st == sts[k] and abs(int(its[k]) - it) <= (0 if prec == 0 else 1)
             a, b = xs[k].cpu().numpy(), xs1[k].cpu().numpy()
             assert np.linalg.norm(a - b) <= tol * np.linalg.norm(b - s.X)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("sweep", [0, 1])
+def test_batch_2d_stretches(cg, ctx, prec, sweep):
+    """Triangle meshes in a batch: three squares of different sizes and
+    stiffness (one with the Fixed Corotational material) whose right edge is
+    moved, one implicit step (h = 1/60), exact bases, Jacobi with line search
+    or coloured Gauss-Seidel without; each mesh equals its single-mesh step,
+    and in float64 Jacobi the oracle's."""
+    import dataclasses
+    from ccscenes import stretch2d
+    dyn = dict(quasistatic=False, dt=1.0 / 60)
+    scenes = [dataclasses.replace(stretch2d(n=7, stretch=0.02), **dyn),
+              dataclasses.replace(stretch2d(n=9, E=3e5, stretch=0.03), **dyn),
+              dataclasses.replace(stretch2d(n=11, stretch=0.025), material="fcr", **dyn)]
+    ls = 1 if sweep == 0 else 0
+    mids, mids1, bases = [], [], []
+    for s in scenes:
+        B = exact_basis(Problem.from_scene(s))
+        bases.append(B)
+        for lst in (mids, mids1):
+            mid = cg.cc_mesh_upload(ctx, s.X, s.elems, s.fixed, s.E, s.nu, s.rho)
+            if s.material == "fcr":
+                cg.cc_mesh_set_material(ctx, mid, cg.MATERIAL_FCR)
+            cg.cc_subspace_upload(ctx, mid, *B, s.dt)
+            lst.append(mid)
+    cg.cc_batch_tuning(ctx, 16, 2)
+    par = cg.cc_params_default(method=cg.METHOD_CC, sweep=sweep, hess_refresh=1, precision=prec,
+                               line_search=ls, max_iters=300)
+    xs = [_t(s.initial_state()[0]) for s in scenes]
+    vs = [_t(s.initial_state()[1]) for s in scenes]
+    xs1 = [x.clone() for x in xs]
+    vs1 = [v.clone() for v in vs]
+    bcs = [_t(s.targets(1)) for s in scenes]
+    worst, its, rgs, sts = cg.cc_step_batch(ctx, mids, xs, vs, bcs, scenes[0].dt, par, 1e-7)
+    tol = 1e-10 if prec == 0 else 1e-4
+    for k, s in enumerate(scenes):
+        st, it, rg = cg.cc_step(ctx, mids1[k], xs1[k], vs1[k], bcs[k], s.dt, par, 1e-7)
+        assert sts[k] == st and abs(int(its[k]) - it) <= (0 if prec == 0 else 1)
+        a, b = xs[k].cpu().numpy(), xs1[k].cpu().numpy()
+        assert np.linalg.norm(a - b) <= tol * np.linalg.norm(b - s.X)
+        if prec == 0 and sweep == 0:
+            p = Problem.from_scene(s)
+            x0, v0 = s.initial_state()
+            xo, vo, res, _ = step(p, x0, v0, s.targets(1), bases[k],
+                                  S.Params(method=S.CC, sweep=S.JACOBI, line_search=True, max_iters=300), 1e-7)
+            assert res.status == S.OK and st == cg.CC_OK and it == res.iters
+            assert np.linalg.norm(a - xo) <= 1e-6 * np.linalg.norm(xo - s.X)

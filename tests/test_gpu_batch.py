@@ -247,3 +247,29 @@ def test_batch_2d_stretches(cg, ctx, prec, sweep):
                                   S.Params(method=S.CC, sweep=S.JACOBI, line_search=True, max_iters=300), 1e-7)
             assert res.status == S.OK and st == cg.CC_OK and it == res.iters
             assert np.linalg.norm(a - xo) <= 1e-6 * np.linalg.norm(xo - s.X)
+
+
+@pytest.mark.parametrize("method", ["cd", "jgs2"])
+def test_batch_methods(cg, ctx, method):
+    """The CD and JGS2 flags of the batched kernels: three bars stepped as a
+    batch equal the single-mesh steps (float64, Jacobi with line search)."""
+    scenes = _scenes()
+    mids, _ = _setup(cg, ctx, scenes, "exact")
+    mids1, _ = _setup(cg, ctx, scenes, "exact")
+    cg.cc_batch_tuning(ctx, 16, 2)
+    m = cg.METHOD_CD if method == "cd" else cg.METHOD_JGS2
+    par = cg.cc_params_default(method=m, sweep=cg.SWEEP_JACOBI, line_search=1, max_iters=400)
+    xs = [_t(s.initial_state()[0]) for s in scenes]
+    vs = [_t(s.initial_state()[1]) for s in scenes]
+    xs1 = [x.clone() for x in xs]
+    vs1 = [v.clone() for v in vs]
+    grav = np.stack([s.gravity for s in scenes])
+    bcs = [_t(s.targets(1)) for s in scenes]
+    worst, its, rgs, sts = cg.cc_step_batch(ctx, mids, xs, vs, bcs, scenes[0].dt, par, 1e-6, gravity=grav)
+    for k, s in enumerate(scenes):
+        par1 = cg.cc_params_default(method=m, sweep=cg.SWEEP_JACOBI, line_search=1, max_iters=400,
+                                    gravity=s.gravity)
+        st, it, rg = cg.cc_step(ctx, mids1[k], xs1[k], vs1[k], bcs[k], s.dt, par1, 1e-6)
+        assert sts[k] == st and its[k] == it
+        a, b = xs[k].cpu().numpy(), xs1[k].cpu().numpy()
+        assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(b - s.X)

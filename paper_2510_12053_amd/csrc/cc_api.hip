@@ -47,6 +47,8 @@ struct Mesh {
   int* sidx = nullptr;
   double* U_d = nullptr;
   float* U_f = nullptr;
+  uint32_t* smap = nullptr;  // support slot map (sparse bases)
+  int smap_words = 0;
   // work buffers
   double *x = nullptr, *xt = nullptr, *x0 = nullptr, *xtrial = nullptr, *dvec = nullptr,
          *g = nullptr, *partials = nullptr, *scal = nullptr;
@@ -74,6 +76,7 @@ struct Mesh {
     v.colidx = d_colidx; v.blkrow = blkrow; v.cptr = cptr; v.centry = centry; v.nnzb = nnzb;
     v.seg = seg; v.nseg = nseg;
     v.sptr = sptr; v.sidx = sidx; v.U_d = U_d; v.U_f = U_f; v.dense_supp = dense;
+    v.smap = smap; v.smap_words = smap_words;
     return v;
   }
 };
@@ -116,7 +119,8 @@ void dfree(T*& p) {
 }
 
 void free_basis(Mesh& M) {
-  dfree(M.sptr); dfree(M.sidx); dfree(M.U_d); dfree(M.U_f);
+  dfree(M.sptr); dfree(M.sidx); dfree(M.U_d); dfree(M.U_f); dfree(M.smap);
+  M.smap_words = 0;
   M.has_basis = false;
   M.snnz = 0;
 }
@@ -503,6 +507,44 @@ void build_mesh(cc_ctx* ctx, Mesh& M) {
 }
 
 // ---- basis upload ------------------------------------------------------
+// Slot map of a sparse basis (MeshView::smap): one byte per support entry
+// (i, j) and block of row j, so the condensation kernel finds U_i[k] for each
+// block (j, k) without searching supp(i).  Left null, and the kernel searches,
+// when a support holds more than SMAP_SELF entries or a row more than
+// 4 * SMAP_MAX_WORDS blocks.
+void build_slot_map(Mesh& M, const std::vector<int64_t>& sptr, const std::vector<int>& sidx,
+                    hipStream_t s) {
+  const int nf = M.nf;
+  int maxrow = 0;
+  int64_t maxsupp = 0;
+  for (int j = 0; j < nf; ++j) maxrow = std::max(maxrow, M.rowptr[j + 1] - M.rowptr[j]);
+  for (int i = 0; i < nf; ++i) maxsupp = std::max(maxsupp, sptr[i + 1] - sptr[i]);
+  const int words = (maxrow + 3) / 4;
+  if (sptr[nf] == 0 || maxsupp > cc::SMAP_SELF || words > cc::SMAP_MAX_WORDS) return;
+  std::vector<uint32_t> map((size_t)sptr[nf] * words, 0xffffffffu);
+  for (int i = 0; i < nf; ++i) {
+    const int* s0 = sidx.data() + sptr[i];
+    const int* s1 = sidx.data() + sptr[i + 1];
+    for (int64_t q = sptr[i]; q < sptr[i + 1]; ++q) {
+      const int j = sidx[q];
+      uint8_t* b = reinterpret_cast<uint8_t*>(&map[(size_t)q * words]);
+      for (int t = M.rowptr[j]; t < M.rowptr[j + 1]; ++t) {
+        const int k = M.colidx[t];
+        uint8_t code = (uint8_t)cc::SMAP_SKIP;
+        if (k == i) {
+          code = (uint8_t)cc::SMAP_SELF;
+        } else {
+          const int* it = std::lower_bound(s0, s1, k);
+          if (it != s1 && *it == k) code = (uint8_t)(it - s0);
+        }
+        b[t - M.rowptr[j]] = code;
+      }
+    }
+  }
+  M.smap = dupload(map, s);
+  M.smap_words = words;
+}
+
 void upload_basis(cc_ctx* ctx, Mesh& M, const int64_t* ptr, const int32_t* idx, const double* U) {
   const int D = M.D, DD = D * D, n = M.n, nf = M.nf;
   if (!ptr || (ptr[n] > 0 && (!idx || !U))) throw ApiError{CC_E_INVALID_ARG, "null basis array"};
@@ -552,6 +594,7 @@ void upload_basis(cc_ctx* ctx, Mesh& M, const int64_t* ptr, const int32_t* idx, 
   M.U_f = dupload(Uf, s);
   M.dense = dense ? 1 : 0;
   M.snnz = nnz;
+  if (!dense) build_slot_map(M, sptr, sidx, s);
 
   HIPC(hipStreamSynchronize(s));
   M.has_basis = true;

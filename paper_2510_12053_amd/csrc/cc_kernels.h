@@ -37,9 +37,20 @@ struct MeshView {
   const double* U_d;     // [nnz][D*D]
   const float* U_f;
   int dense_supp;        // 1: supp(i) = every free vertex except i
+  // support slot map of sparse bases: for support entry q = (i, j) and the
+  // t-th block of row j, byte t of the smap_words words at q * smap_words is
+  // the position of that block's column k in supp(i), SMAP_SELF for k = i
+  // or SMAP_SKIP (k outside the support, or padding past the row); null when
+  // the basis is dense or a support or row is too long for the byte codes
+  const uint32_t* smap;
+  int smap_words;
   // corotation: per free vertex rotation R_j (row-major D*D), or null = off
   const double* rot;
 };
+
+constexpr int SMAP_SELF = 254;
+constexpr int SMAP_SKIP = 255;
+constexpr int SMAP_MAX_WORDS = 16;   // rows of up to 64 blocks
 
 // Material models (values of Material::model and of the C-ABI constants).
 constexpr int MAT_SNH = 0;   // stable neo-Hookean, lam = lambda_L + mu

@@ -222,7 +222,8 @@ __global__ void __launch_bounds__(WG) k_gradient(MeshView mv, const double* __re
 }
 
 // Generic condensation kernel: G lanes per vertex, basis and support from
-// global memory (binary search for the support slot of a neighbour).
+// global memory.  The support position of a neighbour comes from the slot map
+// when the mesh has one, else from a binary search in the support row.
 template <typename T, int D, int G>
 __device__ __forceinline__ void prep_body(const MeshView& mv, int method, int i, bool active, int lane,
                                           const T* __restrict__ hb, T* __restrict__ KL,
@@ -233,7 +234,74 @@ __device__ __forceinline__ void prep_body(const MeshView& mv, int method, int i,
 #pragma unroll
   for (int r = 0; r < DD; ++r) A[r] = Ht[r] = T(0);
   int64_t sp0 = 0, sp1 = 0;
-  if (active && method != 0) {
+  if (active && method != 0 && mv.smap) {
+    // Sparse support with a slot map: the blocks (j, k) of row j whose column
+    // lies in supp(i) come with k's support position, so the loads of H_jk and
+    // U_i[k] do not wait on a search; W = sum_k H_jk U_i[k] is formed first and
+    // Ht += U_i[j]^T W once per row.
+    sp0 = mv.sptr[i];
+    sp1 = mv.sptr[i + 1];
+    const int nw = mv.smap_words;
+    for (int64_t q = sp0 + lane; q < sp1; q += G) {
+      const int j = mv.sidx[q];
+      T Uj[DD], W[DD];
+#pragma unroll
+      for (int r = 0; r < DD; ++r) {
+        Uj[r] = Ub[q * DD + r];
+        W[r] = T(0);
+      }
+      if (mv.rot) rotate_block<T, D>(mv.rot, j, Uj);
+      const int t0 = mv.rowptr[j];
+      const uint32_t* sm = mv.smap + (size_t)q * nw;
+      for (int w = 0; w < nw; ++w) {
+        const uint32_t word = sm[w];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int code = (word >> (8 * b)) & 255;
+          if (code == SMAP_SKIP) continue;
+          const T* H = hb + (size_t)(t0 + 4 * w + b) * DD;
+          T Hl[DD];
+#pragma unroll
+          for (int r = 0; r < DD; ++r) Hl[r] = H[r];
+          if (code == SMAP_SELF) {            // block (j, i): A += H_ji^T U_i[j]
+#pragma unroll
+            for (int r = 0; r < D; ++r)
+#pragma unroll
+              for (int c = 0; c < D; ++c) {
+                T acc = T(0);
+#pragma unroll
+                for (int l = 0; l < D; ++l) acc += Hl[l * D + r] * Uj[l * D + c];
+                A[r * D + c] += acc;
+              }
+            continue;
+          }
+          const int64_t qk = sp0 + code;
+          T Uk[DD];
+#pragma unroll
+          for (int r = 0; r < DD; ++r) Uk[r] = Ub[qk * DD + r];
+          if (mv.rot) rotate_block<T, D>(mv.rot, mv.sidx[qk], Uk);
+#pragma unroll
+          for (int r = 0; r < D; ++r)         // W += H_jk U_i[k]
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+              T acc = W[r * D + c];
+#pragma unroll
+              for (int l = 0; l < D; ++l) acc += Hl[r * D + l] * Uk[l * D + c];
+              W[r * D + c] = acc;
+            }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < D; ++r)             // Ht += U_i[j]^T W
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          T acc = T(0);
+#pragma unroll
+          for (int l = 0; l < D; ++l) acc += Uj[l * D + r] * W[l * D + c];
+          Ht[r * D + c] += acc;
+        }
+    }
+  } else if (active && method != 0) {
     sp0 = mv.sptr[i];
     sp1 = mv.sptr[i + 1];
     for (int64_t q = sp0 + lane; q < sp1; q += G) {

@@ -48,7 +48,7 @@ struct Mesh {
   double* U_d = nullptr;
   float* U_f = nullptr;
   uint32_t* smap = nullptr;  // support slot map (sparse bases)
-  int smap_words = 0;
+  int smap_words = 0, smap_supp = 0;
   // work buffers
   double *x = nullptr, *xt = nullptr, *x0 = nullptr, *xtrial = nullptr, *dvec = nullptr,
          *g = nullptr, *partials = nullptr, *scal = nullptr;
@@ -76,7 +76,7 @@ struct Mesh {
     v.colidx = d_colidx; v.blkrow = blkrow; v.cptr = cptr; v.centry = centry; v.nnzb = nnzb;
     v.seg = seg; v.nseg = nseg;
     v.sptr = sptr; v.sidx = sidx; v.U_d = U_d; v.U_f = U_f; v.dense_supp = dense;
-    v.smap = smap; v.smap_words = smap_words;
+    v.smap = smap; v.smap_words = smap_words; v.smap_supp = smap_supp;
     return v;
   }
 };
@@ -121,6 +121,7 @@ void dfree(T*& p) {
 void free_basis(Mesh& M) {
   dfree(M.sptr); dfree(M.sidx); dfree(M.U_d); dfree(M.U_f); dfree(M.smap);
   M.smap_words = 0;
+  M.smap_supp = 0;
   M.has_basis = false;
   M.snnz = 0;
 }
@@ -509,7 +510,7 @@ void build_mesh(cc_ctx* ctx, Mesh& M) {
 // ---- basis upload ------------------------------------------------------
 // Slot map of a sparse basis (MeshView::smap): one byte per support entry
 // (i, j) and block of row j, so the condensation kernel finds U_i[k] for each
-// block (j, k) without searching supp(i).  Left null, and the kernel searches,
+// block (j, k), k >= j, without searching supp(i).  Left null, and the kernel searches,
 // when a support holds more than SMAP_SELF entries or a row more than
 // 4 * SMAP_MAX_WORDS blocks.
 void build_slot_map(Mesh& M, const std::vector<int64_t>& sptr, const std::vector<int>& sidx,
@@ -533,7 +534,7 @@ void build_slot_map(Mesh& M, const std::vector<int64_t>& sptr, const std::vector
         uint8_t code = (uint8_t)cc::SMAP_SKIP;
         if (k == i) {
           code = (uint8_t)cc::SMAP_SELF;
-        } else {
+        } else if (k >= j) {   // blocks below the diagonal enter through symmetry
           const int* it = std::lower_bound(s0, s1, k);
           if (it != s1 && *it == k) code = (uint8_t)(it - s0);
         }
@@ -543,6 +544,7 @@ void build_slot_map(Mesh& M, const std::vector<int64_t>& sptr, const std::vector
   }
   M.smap = dupload(map, s);
   M.smap_words = words;
+  M.smap_supp = (int)maxsupp;
 }
 
 void upload_basis(cc_ctx* ctx, Mesh& M, const int64_t* ptr, const int32_t* idx, const double* U) {

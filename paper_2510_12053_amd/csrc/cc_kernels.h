@@ -39,11 +39,13 @@ struct MeshView {
   int dense_supp;        // 1: supp(i) = every free vertex except i
   // support slot map of sparse bases: for support entry q = (i, j) and the
   // t-th block of row j, byte t of the smap_words words at q * smap_words is
-  // the position of that block's column k in supp(i), SMAP_SELF for k = i
-  // or SMAP_SKIP (k outside the support, or padding past the row); null when
-  // the basis is dense or a support or row is too long for the byte codes
+  // SMAP_SELF for column k = i, the position of k in supp(i) for k >= j, and
+  // SMAP_SKIP otherwise (k < j, k outside the support, padding past the row);
+  // null when the basis is dense or a support or row is too long for the
+  // byte codes
   const uint32_t* smap;
   int smap_words;
+  int smap_supp;         // longest support row of the slot-mapped basis
   // corotation: per free vertex rotation R_j (row-major D*D), or null = off
   const double* rot;
 };

@@ -224,33 +224,68 @@ __global__ void __launch_bounds__(WG) k_gradient(MeshView mv, const double* __re
 // Generic condensation kernel: G lanes per vertex, basis and support from
 // global memory.  The support position of a neighbour comes from the slot map
 // when the mesh has one, else from a binary search in the support row.
+// With `stage` non-null (the same for the whole workgroup) each vertex group
+// owns cap * D * D values of it: a support row of up to cap blocks is copied
+// there with contiguous loads (and rotated once for a corotated basis), so the
+// U_i[k] lookups of the slot-map path read LDS instead of scattered global
+// blocks.
 template <typename T, int D, int G>
 __device__ __forceinline__ void prep_body(const MeshView& mv, int method, int i, bool active, int lane,
                                           const T* __restrict__ hb, T* __restrict__ KL,
-                                          unsigned long long* __restrict__ fb) {
+                                          unsigned long long* __restrict__ fb,
+                                          T* __restrict__ stage = nullptr, int cap = 0) {
   constexpr int DD = D * D;
   const T* Ub = basis_of<T>(mv);
   T A[DD], Ht[DD];
 #pragma unroll
   for (int r = 0; r < DD; ++r) A[r] = Ht[r] = T(0);
   int64_t sp0 = 0, sp1 = 0;
-  if (active && method != 0 && mv.smap) {
-    // Sparse support with a slot map: the blocks (j, k) of row j whose column
-    // lies in supp(i) come with k's support position, so the loads of H_jk and
-    // U_i[k] do not wait on a search; W = sum_k H_jk U_i[k] is formed first and
-    // Ht += U_i[j]^T W once per row.
+  if (active && method != 0) {
     sp0 = mv.sptr[i];
     sp1 = mv.sptr[i + 1];
+  }
+  const T* Us = nullptr;   // staged, rotated support row of vertex i
+  if (stage) {
+    const bool st = active && method != 0 && mv.smap && sp1 - sp0 <= cap;
+    T* my = stage + (size_t)(threadIdx.x / G) * cap * DD;
+    if (st)
+      for (int e = lane; e < (int)(sp1 - sp0) * DD; e += G) my[e] = Ub[sp0 * DD + e];
+    __syncthreads();
+    if (mv.rot) {
+      if (st)
+        for (int q = lane; q < (int)(sp1 - sp0); q += G) {
+          T b[DD];
+#pragma unroll
+          for (int r = 0; r < DD; ++r) b[r] = my[q * DD + r];
+          rotate_block<T, D>(mv.rot, mv.sidx[sp0 + q], b);
+#pragma unroll
+          for (int r = 0; r < DD; ++r) my[q * DD + r] = b[r];
+        }
+      __syncthreads();
+    }
+    if (st) Us = my;
+  }
+  if (active && method != 0 && mv.smap) {
+    // Sparse support with a slot map: the blocks (j, k), k >= j, of row j
+    // whose column lies in supp(i) come with k's support position, so the
+    // loads of H_jk and U_i[k] do not wait on a search.  H is symmetric, so
+    // with W = sum_{k > j} H_jk U_i[k] + 1/2 H_jj U_i[j] and
+    // Y = sum_j U_i[j]^T W, Ht = Y + Y^T (formed after the lane reduction).
     const int nw = mv.smap_words;
     for (int64_t q = sp0 + lane; q < sp1; q += G) {
+      const int a = (int)(q - sp0);
       const int j = mv.sidx[q];
       T Uj[DD], W[DD];
+      if (Us) {
 #pragma unroll
-      for (int r = 0; r < DD; ++r) {
-        Uj[r] = Ub[q * DD + r];
-        W[r] = T(0);
+        for (int r = 0; r < DD; ++r) Uj[r] = Us[(q - sp0) * DD + r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < DD; ++r) Uj[r] = Ub[q * DD + r];
+        if (mv.rot) rotate_block<T, D>(mv.rot, j, Uj);
       }
-      if (mv.rot) rotate_block<T, D>(mv.rot, j, Uj);
+#pragma unroll
+      for (int r = 0; r < DD; ++r) W[r] = T(0);
       const int t0 = mv.rowptr[j];
       const uint32_t* sm = mv.smap + (size_t)q * nw;
       for (int w = 0; w < nw; ++w) {
@@ -275,11 +310,19 @@ __device__ __forceinline__ void prep_body(const MeshView& mv, int method, int i,
               }
             continue;
           }
-          const int64_t qk = sp0 + code;
           T Uk[DD];
+          if (Us) {
 #pragma unroll
-          for (int r = 0; r < DD; ++r) Uk[r] = Ub[qk * DD + r];
-          if (mv.rot) rotate_block<T, D>(mv.rot, mv.sidx[qk], Uk);
+            for (int r = 0; r < DD; ++r) Uk[r] = Us[code * DD + r];
+          } else {
+            const int64_t qk = sp0 + code;
+#pragma unroll
+            for (int r = 0; r < DD; ++r) Uk[r] = Ub[qk * DD + r];
+            if (mv.rot) rotate_block<T, D>(mv.rot, mv.sidx[qk], Uk);
+          }
+          if (code == a)                      // diagonal block: half weight (exact)
+#pragma unroll
+            for (int r = 0; r < DD; ++r) Uk[r] *= T(0.5);
 #pragma unroll
           for (int r = 0; r < D; ++r)         // W += H_jk U_i[k]
 #pragma unroll
@@ -292,7 +335,7 @@ __device__ __forceinline__ void prep_body(const MeshView& mv, int method, int i,
         }
       }
 #pragma unroll
-      for (int r = 0; r < D; ++r)             // Ht += U_i[j]^T W
+      for (int r = 0; r < D; ++r)             // Y += U_i[j]^T W
 #pragma unroll
         for (int c = 0; c < D; ++c) {
           T acc = T(0);
@@ -302,8 +345,6 @@ __device__ __forceinline__ void prep_body(const MeshView& mv, int method, int i,
         }
     }
   } else if (active && method != 0) {
-    sp0 = mv.sptr[i];
-    sp1 = mv.sptr[i + 1];
     for (int64_t q = sp0 + lane; q < sp1; q += G) {
       const int j = mv.sidx[q];
       T Uj[DD];
@@ -328,15 +369,27 @@ __device__ __forceinline__ void prep_body(const MeshView& mv, int method, int i,
       Ht[r] += __shfl_xor(Ht[r], off, G);
     }
   if (!active || lane != 0) return;
+  if (mv.smap) {                              // Ht = Y + Y^T
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int c = r; c < D; ++c) {
+        const T y = Ht[r * D + c] + Ht[c * D + r];
+        Ht[r * D + c] = y;
+        Ht[c * D + r] = y;
+      }
+  }
   cc_finish<T, D>(mv, method, i, sp1 == sp0, A, Ht, hb, KL, fb);
 }
 
 template <typename T, int D, int G>
 __global__ void __launch_bounds__(WG) k_cc_prep(MeshView mv, int method, int v0, int v1,
                                                 const T* __restrict__ hb, T* __restrict__ KL,
-                                                unsigned long long* __restrict__ fb) {
+                                                unsigned long long* __restrict__ fb, int cap) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   const int i = v0 + blockIdx.x * (WG / G) + threadIdx.x / G;
-  prep_body<T, D, G>(mv, method, i, i < v1, threadIdx.x % G, hb, KL, fb);
+  prep_body<T, D, G>(mv, method, i, i < v1, threadIdx.x % G, hb, KL, fb,
+                     cap > 0 ? reinterpret_cast<T*>(smem_raw) : nullptr, cap);
 }
 
 // Exact-basis condensation of TV vertices per workgroup.  Each vertex's
@@ -924,16 +977,32 @@ void launch_gradient(const MeshView& mv, const double* x, const double* xt, cons
                   CC_DISPATCH_D(mv.D, k_gradient<D, GRAD_G, FCR><<<nb, WG, 0, s>>>(mv, x, xt, mat, g, partials)));
 }
 
+// LDS of the staged support rows per workgroup: 32 KB keeps five 256-thread
+// workgroups per CU.  Longer rows are read from global memory instead.
+constexpr size_t SPARSE_STAGE_MAX = 32 * 1024;
+
+static int sparse_stage_cap(int supp, int G, int D, int prec) {
+  const size_t bytes = (size_t)(WG / G) * supp * D * D * (prec == 0 ? 8 : 4);
+  return supp > 0 && bytes <= SPARSE_STAGE_MAX ? supp : 0;
+}
+
+static size_t sparse_stage_bytes(int cap, int G, int D, int prec) {
+  return (size_t)(WG / G) * cap * D * D * (prec == 0 ? 8 : 4);
+}
+
 template <typename T, int D>
 static void prep_g(const MeshView& mv, int method, int v0, int v1, const void* hb, void* KL,
                    unsigned long long* fb, int G, hipStream_t s) {
   const int cnt = v1 - v0;
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  const int cap = sparse_stage_cap(mv.smap ? mv.smap_supp : 0, G, D, prec);
+  const size_t lds = sparse_stage_bytes(cap, G, D, prec);
   if (G == 64)
-    k_cc_prep<T, D, 64><<<nblocks(cnt, WG / 64), WG, 0, s>>>(mv, method, v0, v1, (const T*)hb,
-                                                             (T*)KL, fb);
+    k_cc_prep<T, D, 64><<<nblocks(cnt, WG / 64), WG, lds, s>>>(mv, method, v0, v1, (const T*)hb,
+                                                               (T*)KL, fb, cap);
   else
-    k_cc_prep<T, D, 16><<<nblocks(cnt, WG / 16), WG, 0, s>>>(mv, method, v0, v1, (const T*)hb,
-                                                             (T*)KL, fb);
+    k_cc_prep<T, D, 16><<<nblocks(cnt, WG / 16), WG, lds, s>>>(mv, method, v0, v1, (const T*)hb,
+                                                               (T*)KL, fb, cap);
 }
 
 static int support_lanes(const MeshView& mv) {
@@ -1263,7 +1332,8 @@ template <typename T, int D, int G>
 __global__ void __launch_bounds__(WG) kb_prep(const BatchItem* __restrict__ items,
                                               const BatchCtl* __restrict__ ctl,
                                               const int* __restrict__ boff, int nmesh, int method,
-                                              int colour) {
+                                              int colour, int cap) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   const int mi = block_mesh(boff, nmesh, blockIdx.x);
   if (!ctl[mi].active) return;
   const BatchItem& it = items[mi];
@@ -1271,7 +1341,8 @@ __global__ void __launch_bounds__(WG) kb_prep(const BatchItem* __restrict__ item
   vertex_range(it, colour, v0, v1);
   const int lb = blockIdx.x - boff[mi];
   const int i = v0 + lb * (WG / G) + threadIdx.x / G;
-  prep_body<T, D, G>(it.mv, method, i, i < v1, threadIdx.x % G, (const T*)it.hb, (T*)it.KL, it.fb);
+  prep_body<T, D, G>(it.mv, method, i, i < v1, threadIdx.x % G, (const T*)it.hb, (T*)it.KL, it.fb,
+                     cap > 0 ? reinterpret_cast<T*>(smem_raw) : nullptr, cap);
 }
 
 // Dense-basis meshes of a batch: TV vertices per workgroup (prep_dm_body).
@@ -1444,6 +1515,8 @@ struct BatchPlan {
   int max_colours = 0;
   int tv = 0;       // vertices per workgroup of the dense condensation (0: no dense mesh)
   size_t lds = 0;   // its dynamic LDS
+  int scap = 0;     // staged support blocks per vertex of the sparse condensation (0: none)
+  size_t slds = 0;  // its dynamic LDS
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_iters = 0;
@@ -1517,7 +1590,7 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
   p->items_h.assign(items_host, items_host + nmesh);
   std::vector<int> cpred(nmesh), celem(nmesh), casm(nmesh), cgrad(nmesh), cen(nmesh), cax(nmesh),
       caxj(nmesh), cfeat(nmesh), crot(nmesh);
-  int dense_nf = 0;
+  int dense_nf = 0, sparse_supp = 0;
   for (int m = 0; m < nmesh; ++m) {
     const MeshView& mv = p->items_h[m].mv;
     cpred[m] = nblocks(mv.n, WG);
@@ -1532,7 +1605,10 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
     crot[m] = (cfg.corotate && mv.rot) ? nblocks(mv.nf, WG) : 0;
     p->max_colours = std::max(p->max_colours, p->items_h[m].ncol);
     if (p->items_h[m].prep_dense) dense_nf = std::max(dense_nf, mv.nf);
+    else if (mv.smap) sparse_supp = std::max(sparse_supp, mv.smap_supp);
   }
+  p->scap = sparse_stage_cap(sparse_supp, cfg.G, cfg.D, cfg.prec);
+  p->slds = sparse_stage_bytes(p->scap, cfg.G, cfg.D, cfg.prec);
   if (dense_nf > 0) {
     p->tv = dense_tv(dense_nf, cfg.D, cfg.prec);
     p->lds = dense_lds_bytes(p->tv, dense_nf, cfg.D, cfg.prec);
@@ -1603,7 +1679,8 @@ static void b_prep(BatchPlan* p, int colour, hipStream_t s, int fuse = 0) {
   if (gridn(o) == 0 && gridn(od) == 0) return;
   p->mark(3, 1);
   if (gridn(o) > 0)
-    kb_prep<T, D, G><<<gridn(o), WG, 0, s>>>(p->items_d, p->ctl_d, o.d, p->nmesh, p->cfg.method, colour);
+    kb_prep<T, D, G><<<gridn(o), WG, p->slds, s>>>(p->items_d, p->ctl_d, o.d, p->nmesh, p->cfg.method,
+                                                  colour, p->scap);
   if (gridn(od) > 0) {
     const Offsets& of = p->fin[colour + 1];
     CC_DISPATCH_TV(p->tv, kb_prep_dm<T, D, TV><<<gridn(od), PWG, p->lds, s>>>(

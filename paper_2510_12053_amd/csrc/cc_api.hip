@@ -522,13 +522,15 @@ void build_slot_map(Mesh& M, const std::vector<int64_t>& sptr, const std::vector
   for (int i = 0; i < nf; ++i) maxsupp = std::max(maxsupp, sptr[i + 1] - sptr[i]);
   const int words = (maxrow + 3) / 4;
   if (sptr[nf] == 0 || maxsupp > cc::SMAP_SELF || words > cc::SMAP_MAX_WORDS) return;
-  std::vector<uint32_t> map((size_t)sptr[nf] * words, 0xffffffffu);
+  const int stride = words + 1;   // row start of j, then the codes
+  std::vector<uint32_t> map((size_t)sptr[nf] * stride, 0xffffffffu);
   for (int i = 0; i < nf; ++i) {
     const int* s0 = sidx.data() + sptr[i];
     const int* s1 = sidx.data() + sptr[i + 1];
     for (int64_t q = sptr[i]; q < sptr[i + 1]; ++q) {
       const int j = sidx[q];
-      uint8_t* b = reinterpret_cast<uint8_t*>(&map[(size_t)q * words]);
+      map[(size_t)q * stride] = (uint32_t)M.rowptr[j];
+      uint8_t* b = reinterpret_cast<uint8_t*>(&map[(size_t)q * stride + 1]);
       for (int t = M.rowptr[j]; t < M.rowptr[j + 1]; ++t) {
         const int k = M.colidx[t];
         uint8_t code = (uint8_t)cc::SMAP_SKIP;

@@ -37,12 +37,12 @@ struct MeshView {
   const double* U_d;     // [nnz][D*D]
   const float* U_f;
   int dense_supp;        // 1: supp(i) = every free vertex except i
-  // support slot map of sparse bases: for support entry q = (i, j) and the
-  // t-th block of row j, byte t of the smap_words words at q * smap_words is
-  // SMAP_SELF for column k = i, the position of k in supp(i) for k >= j, and
-  // SMAP_SKIP otherwise (k < j, k outside the support, padding past the row);
-  // null when the basis is dense or a support or row is too long for the
-  // byte codes
+  // support slot map of sparse bases: support entry q = (i, j) owns the
+  // smap_words + 1 words at q * (smap_words + 1): the first holds
+  // rowptr[j]; for the t-th block of row j, byte t of the others is SMAP_SELF
+  // for column k = i, the position of k in supp(i) for k >= j, and SMAP_SKIP
+  // otherwise (k < j, k outside the support, padding past the row); null when
+  // the basis is dense or a support or row is too long for the byte codes
   const uint32_t* smap;
   int smap_words;
   int smap_supp;         // longest support row of the slot-mapped basis

@@ -274,7 +274,8 @@ __device__ __forceinline__ void prep_body(const MeshView& mv, int method, int i,
     const int nw = mv.smap_words;
     for (int64_t q = sp0 + lane; q < sp1; q += G) {
       const int a = (int)(q - sp0);
-      const int j = mv.sidx[q];
+      const uint32_t* sm = mv.smap + (size_t)q * (nw + 1);
+      const int t0 = (int)sm[0];
       T Uj[DD], W[DD];
       if (Us) {
 #pragma unroll
@@ -282,14 +283,12 @@ __device__ __forceinline__ void prep_body(const MeshView& mv, int method, int i,
       } else {
 #pragma unroll
         for (int r = 0; r < DD; ++r) Uj[r] = Ub[q * DD + r];
-        if (mv.rot) rotate_block<T, D>(mv.rot, j, Uj);
+        if (mv.rot) rotate_block<T, D>(mv.rot, mv.sidx[q], Uj);
       }
 #pragma unroll
       for (int r = 0; r < DD; ++r) W[r] = T(0);
-      const int t0 = mv.rowptr[j];
-      const uint32_t* sm = mv.smap + (size_t)q * nw;
       for (int w = 0; w < nw; ++w) {
-        const uint32_t word = sm[w];
+        const uint32_t word = sm[1 + w];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           const int code = (word >> (8 * b)) & 255;

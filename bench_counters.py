@@ -159,7 +159,8 @@ def trace_summary(folder, bench_log):
     print("```\n" + TRACE_CMD + "\n```\n")
     print("The profiled process runs the whole bench: warm-start data generation and training, the "
           "timed regions of plain CC (`k_*`), batched and learned+batched CC (`kb_*`, graph replays), "
-          "and the learned+batched launches once more uncaptured with HIP events.\n")
+          "the learned+batched launches once more uncaptured with HIP events, and last the "
+          "81x21x21 beam sweep (float32 `kb_*`, sparse `kb_prep`).\n")
     print("| kernel | calls | avg (us) | min (us) | max (us) | share |")
     print("|---|---|---|---|---|---|")
     for r in rows[:24]:

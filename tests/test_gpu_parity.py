@@ -116,6 +116,35 @@ def test_jacobi_directions(cg, ctx, kind, method, prec):
     assert np.max(np.abs(dx[p.free] - dxo)) <= tol * np.max(np.abs(dxo))
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_jacobi_directions_long_supports(cg, ctx, prec):
+    """Supports of 322 vertices, more than the per-support slot map encodes:
+    the exact basis of a 10x6x6 bar with the last entry of every row dropped
+    (so not the dense layout either).  The condensation then finds U_i[k] by
+    a binary search in the sorted support; directions against the oracle."""
+    s = tet_bar(10, 6, 6, E=1e6)
+    p = Problem.from_scene(s)
+    ptr, idx, U = exact_basis(p)
+    cnt = np.diff(ptr)
+    keep = np.ones(len(idx), dtype=bool)
+    keep[ptr[1:][cnt > 0] - 1] = False
+    cnt = cnt - (cnt > 0)
+    assert cnt.max() == p.free.size - 2 > 254
+    B = (np.concatenate([[0], np.cumsum(cnt)]).astype(ptr.dtype), idx[keep], U[keep])
+    mid = _upload(cg, ctx, s)
+    cg.cc_subspace_upload(ctx, mid, *B, s.dt)
+    x0, v0 = s.initial_state()
+    xh = predictor(p, x0, v0 + 0.3, s.targets(1))
+    x = xh + 0.01 * np.random.default_rng(3).normal(size=xh.shape)
+    x[p.fixed] = xh[p.fixed]
+    par = cg.cc_params_default(method=cg.METHOD_CC, precision=prec, gravity=s.gravity)
+    _, g, dx = cg.cc_probe_sweep(ctx, mid, _t(x), _t(p.x_tilde), s.dt, par)
+    dxo, _ = S.local_directions(p, basis_matrix(p, *B), p.hessian(x), p.gradient(x),
+                                np.arange(p.free.size), S.CC)
+    tol = 1e-9 if prec == 0 else 1e-4
+    assert np.max(np.abs(dx.cpu().numpy()[p.free] - dxo)) <= tol * np.max(np.abs(dxo))
+
+
 @pytest.mark.parametrize("kind", ["R1", "R2", "exact"])
 @pytest.mark.parametrize("dim", [2, 3])
 def test_basis_builder(cg, ctx, kind, dim):
@@ -245,7 +274,7 @@ def test_exact_basis_builder_bar(cg, ctx):
     assert np.max(np.abs(U - B[2])) <= 1e-8 * np.max(np.abs(B[2]))
 
 
-@pytest.mark.parametrize("kind", ["exact", "R1"])
+@pytest.mark.parametrize("kind", ["exact", "R1", "R2"])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_corotated_directions(cg, ctx, kind, prec):
     """One corotated Jacobi sweep at a twisted state (Method, Eq. rotation):

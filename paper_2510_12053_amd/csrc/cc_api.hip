@@ -1399,8 +1399,10 @@ static cc::BatchPlan* batch_plan_for(cc_ctx* ctx, const std::vector<Mesh*>& ms, 
   return ctx->plan;
 }
 
-// Host backtracking for mesh m of the plan after its energy rose at alpha = 1.
-static void batch_host_line_search(cc_ctx* ctx, Mesh& M, cc::BatchItem& it, cc::BatchCtl& c,
+// Coordinate-descent fallback of mesh m of the plan after the batched
+// backtracking rounds exhausted their halvings along the CC direction: a CD
+// sweep from x and a host line search along it, as in the single-mesh path.
+static void batch_host_cd_fallback(cc_ctx* ctx, Mesh& M, cc::BatchItem& it, cc::BatchCtl& c,
                                    const cc_params& p, double tol) {
   hipStream_t s = ctx->stream;
   M.x = it.x;
@@ -1408,8 +1410,10 @@ static void batch_host_line_search(cc_ctx* ctx, Mesh& M, cc::BatchItem& it, cc::
   Stepper S{ctx, M, M.view(), it.mat, p, s};
   const int nd = M.D * M.n;
   const double tau = 1e-12 * std::max(std::fabs(c.E_cur), 1.0);
+  S.sweep(M.x, M.xtrial, CC_METHOD_CD);
   cc::launch_axpy(nd, M.xtrial, M.x, -1.0, M.dvec, s);
-  double alpha = 1.0, Et = c.E_trial;
+  double alpha = 1.0;
+  double Et = S.energy(M.xtrial);
   int hv = 0;
   while (!(Et <= c.E_cur + tau) && hv < p.max_halvings) {
     alpha *= 0.5;
@@ -1418,25 +1422,11 @@ static void batch_host_line_search(cc_ctx* ctx, Mesh& M, cc::BatchItem& it, cc::
     Et = S.energy(M.xtrial);
   }
   if (!(Et <= c.E_cur + tau)) {
-    S.sweep(M.x, M.xtrial, CC_METHOD_CD);
-    cc::launch_axpy(nd, M.xtrial, M.x, -1.0, M.dvec, s);
-    alpha = 1.0;
-    Et = S.energy(M.xtrial);
-    hv = 0;
-    while (!(Et <= c.E_cur + tau) && hv < p.max_halvings) {
-      alpha *= 0.5;
-      ++hv;
-      cc::launch_axpy(nd, M.x, M.dvec, alpha, M.xtrial, s);
-      Et = S.energy(M.xtrial);
-    }
-    if (!(Et <= c.E_cur + tau)) {
-      c.status = CC_STALLED;
-      c.active = 0;
-      c.needs_host = 0;
-      // g at x must stay valid for a later Jacobi iteration of this mesh
-      (void)S.grad_norm2(M.x);
-      return;
-    }
+    c.status = CC_STALLED;
+    c.active = 0;
+    // g at x must stay valid for a later Jacobi iteration of this mesh
+    (void)S.grad_norm2(M.x);
+    return;
   }
   M.last_halvings += hv;
   std::swap(M.x, M.xtrial);
@@ -1444,7 +1434,6 @@ static void batch_host_line_search(cc_ctx* ctx, Mesh& M, cc::BatchItem& it, cc::
   c.iters += 1;
   c.gn2 = S.grad_norm2(M.x);
   c.r = std::sqrt(c.gn2) / c.g0;
-  c.needs_host = 0;
   if (!std::isfinite(c.r)) { c.status = CC_STALLED; c.active = 0; }
   else if (c.r <= tol) { c.status = CC_OK; c.active = 0; }
   else if (c.iters >= p.max_iters) { c.status = CC_NOT_CONVERGED; c.active = 0; }
@@ -1519,6 +1508,12 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
       HIPC(hipStreamSynchronize(s));
       std::memcpy(ctl.data(), ctx->pinned, n * sizeof(cc::BatchCtl));
     };
+    // the pinned buffer may be read by a copy still in flight: wait first
+    auto push_ctl = [&]() {
+      HIPC(hipStreamSynchronize(s));
+      std::memcpy(ctx->pinned, ctl.data(), n * sizeof(cc::BatchCtl));
+      HIPC(hipMemcpyAsync(ctl_d, ctx->pinned, n * sizeof(cc::BatchCtl), hipMemcpyHostToDevice, s));
+    };
     if ((size_t)n * sizeof(cc::BatchCtl) > 64 * 1024)
       return fail(ctx, CC_E_INVALID_ARG, "batch too large");
     // The first round is queued without reading the control blocks back:
@@ -1558,14 +1553,51 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
       bool host = false;
       for (auto& c : ctl) host = host || c.needs_host;
       if (host) {
+        // Meshes whose energy rose at the full step backtrack together: each
+        // round forms every searching mesh's trial point, its energy and its
+        // decision in three launches.  Four rounds are queued per read-back;
+        // a mesh that has decided is inactive and skips the later ones.
+        std::vector<int> was_active(n);
+        for (int i = 0; i < n; ++i) {
+          was_active[i] = ctl[i].active;
+          ctl[i].active = ctl[i].needs_host;
+          ctl[i].alpha = 0.5;
+          ctl[i].halvings = 1;
+          ctl[i].ls = ctl[i].needs_host && p.max_halvings < 1 ? 2 : 0;
+          if (ctl[i].ls == 2) ctl[i].active = 0;
+        }
+        push_ctl();
+        for (int r = 0;; ++r) {
+          bool searching = false;
+          for (auto& c : ctl) searching = searching || c.active;
+          if (!searching) break;
+          for (int q = 0; q < 4; ++q) cc::batch_ls_round(plan, r == 0 && q == 0, p.max_halvings, s);
+          pull_ctl();
+        }
+        // accepted steps: gradient at the new x and the convergence test
+        bool any_acc = false;
+        for (int i = 0; i < n; ++i) {
+          ctl[i].active = ctl[i].needs_host && ctl[i].ls == 1;
+          any_acc = any_acc || ctl[i].active;
+          if (ctl[i].active) ms[i]->last_halvings += ctl[i].halvings;
+        }
+        if (any_acc) {
+          push_ctl();
+          cc::batch_gradient_converge(plan, s);
+          pull_ctl();
+        }
+        // exhausted halvings: the coordinate-descent fallback on the host
         HIPC(hipMemcpyAsync(items.data(), items_d, n * sizeof(cc::BatchItem), hipMemcpyDeviceToHost, s));
         HIPC(hipStreamSynchronize(s));
         for (int i = 0; i < n; ++i) {
-          if (!ctl[i].needs_host) continue;
-          batch_host_line_search(ctx, *ms[i], items[i], ctl[i], p, tol);
-          HIPC(hipMemcpyAsync(items_d + i, &items[i], sizeof(cc::BatchItem), hipMemcpyHostToDevice, s));
-          HIPC(hipMemcpyAsync(ctl_d + i, &ctl[i], sizeof(cc::BatchCtl), hipMemcpyHostToDevice, s));
+          if (ctl[i].needs_host && ctl[i].ls == 2) {
+            batch_host_cd_fallback(ctx, *ms[i], items[i], ctl[i], p, tol);
+            HIPC(hipMemcpyAsync(items_d + i, &items[i], sizeof(cc::BatchItem), hipMemcpyHostToDevice, s));
+          }
+          if (!ctl[i].needs_host) ctl[i].active = was_active[i];
+          ctl[i].needs_host = 0;
         }
+        push_ctl();
         HIPC(hipStreamSynchronize(s));
       }
       if (++guard > (long long)p.max_iters + 16) break;  // every replay advances every active mesh

@@ -158,6 +158,10 @@ struct BatchCtl {
   int bad;             // non-finite input seen by the predictor
   int warm;            // 1: the learned proposal was accepted
   double E_cur, E_trial, g0, gn2, r;
+  // backtracking rounds (batch_ls_round): current step fraction, halvings
+  // taken, outcome (0 searching, 1 accepted, 2 halvings exhausted)
+  double alpha;
+  int halvings, ls;
 };
 
 struct BatchPlan;  // host-side, defined in cc_kernels.hip
@@ -200,6 +204,13 @@ void batch_energy_trial(BatchPlan* p, hipStream_t s);   // ctl.E_trial = E(xtria
 void batch_energy_x(BatchPlan* p, hipStream_t s);       // ctl.E_cur = E(x)
 // g(x), ctl.gn2; only_warm: only meshes whose learned proposal was accepted
 void batch_gradient_x(BatchPlan* p, hipStream_t s, int only_warm = 0);
+// One backtracking round for the active meshes, whose energy rose at the
+// full step: x_trial = x + alpha d (with d = x_trial - x formed first when
+// `first`), E(x_trial), then accept (swap, E_cur, iteration count), halve
+// alpha, or give up after max_halvings halvings (ctl.ls).
+void batch_ls_round(BatchPlan* p, int first, int max_halvings, hipStream_t s);
+// Gradient at x and the convergence test for the active meshes.
+void batch_gradient_converge(BatchPlan* p, hipStream_t s);
 void batch_warm_start(BatchPlan* p, const MlpState& net, float* feat, float* delta, int rows,
                       hipStream_t s);
 // Time one condensation + update pass of every mesh with the given lane count.

@@ -1454,17 +1454,21 @@ __device__ __forceinline__ void converged_mesh(BatchCtl& c, double tol, int max_
 // convergence test (dst 1), saving the launch of kb_accept / kb_converged.
 // only_warm: meshes whose learned proposal was rejected are skipped (their
 // positions, gradient and norm are those of the predictor, already known).
+// Sum of a mesh's per-block partials, in a fixed order (the single-mesh
+// k_reduce sums the same way).
+__device__ __forceinline__ double mesh_partials_sum(const BatchItem& it, int np, double* red) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < np; i += WG) v += it.partials[i];
+  return block_sum<WG>(v, red);
+}
+
 __global__ void __launch_bounds__(WG) kb_reduce(BatchItem* __restrict__ items, BatchCtl* ctl,
                                                 const int* __restrict__ boff_src, int dst, int post,
                                                 double tol, int max_iters, int only_warm) {
   __shared__ double red[WG];
   const int mi = blockIdx.x;
   if (!ctl[mi].active || (only_warm && !ctl[mi].warm)) return;
-  const double* part = items[mi].partials;
-  const int np = boff_src[mi + 1] - boff_src[mi];
-  double v = 0.0;
-  for (int i = threadIdx.x; i < np; i += WG) v += part[i];
-  const double tot = block_sum<WG>(v, red);
+  const double tot = mesh_partials_sum(items[mi], boff_src[mi + 1] - boff_src[mi], red);
   if (threadIdx.x == 0) {
     BatchCtl& c = ctl[mi];
     if (dst == 0) c.E_trial = tot;
@@ -1472,6 +1476,51 @@ __global__ void __launch_bounds__(WG) kb_reduce(BatchItem* __restrict__ items, B
     else c.E_cur = tot;
     if (post == 1) accept_mesh(items[mi], c, 1);
     else if (post == 2) converged_mesh(c, tol, max_iters);
+  }
+}
+
+// Backtracking (Results, Subspace Quality: global line search along the
+// sweep's displacement) of the active meshes, all meshes per launch.
+// mode 0: d = x_trial - x; mode 1: x_trial = x + alpha d.
+__global__ void __launch_bounds__(WG) kb_ls_vec(BatchItem* __restrict__ items,
+                                                const BatchCtl* __restrict__ ctl,
+                                                const int* __restrict__ boff, int nmesh, int mode) {
+  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  if (!ctl[mi].active) return;
+  const BatchItem& it = items[mi];
+  const int t = (blockIdx.x - boff[mi]) * WG + threadIdx.x;
+  if (t >= it.mv.D * it.mv.n) return;
+  if (mode == 0) it.d[t] = it.xtrial[t] + -1.0 * it.x[t];
+  else it.xtrial[t] = it.x[t] + ctl[mi].alpha * it.d[t];
+}
+
+// E(x_trial) of the active meshes, then each takes the step (swap, E_cur,
+// one more iteration), halves alpha, or stops after max_halvings halvings.
+__global__ void __launch_bounds__(WG) kb_ls_reduce(BatchItem* __restrict__ items, BatchCtl* ctl,
+                                                   const int* __restrict__ boff_src, int max_halvings) {
+  __shared__ double red[WG];
+  const int mi = blockIdx.x;
+  if (!ctl[mi].active) return;
+  const double tot = mesh_partials_sum(items[mi], boff_src[mi + 1] - boff_src[mi], red);
+  if (threadIdx.x != 0) return;
+  BatchCtl& c = ctl[mi];
+  c.E_trial = tot;
+  const double tau = 1e-12 * fmax(fabs(c.E_cur), 1.0);
+  if (c.E_trial <= c.E_cur + tau) {
+    BatchItem& item = items[mi];
+    double* t = item.x;
+    item.x = item.xtrial;
+    item.xtrial = t;
+    c.E_cur = c.E_trial;
+    c.iters += 1;
+    c.ls = 1;
+    c.active = 0;
+  } else if (c.halvings >= max_halvings) {
+    c.ls = 2;
+    c.active = 0;
+  } else {
+    c.alpha *= 0.5;
+    c.halvings += 1;
   }
 }
 
@@ -1822,6 +1871,25 @@ void batch_gradient_x(BatchPlan* p, hipStream_t s, int only_warm) {
 void batch_energy_x(BatchPlan* p, hipStream_t s) {
   if (p->cfg.D == 3) b_energy<3>(p, 0, 2, s); else b_energy<2>(p, 0, 2, s);
 }
+void batch_ls_round(BatchPlan* p, int first, int max_halvings, hipStream_t s) {
+  if (gridn(p->axpy) == 0 || gridn(p->energy) == 0) return;
+  if (first) kb_ls_vec<<<gridn(p->axpy), WG, 0, s>>>(p->items_d, p->ctl_d, p->axpy.d, p->nmesh, 0);
+  kb_ls_vec<<<gridn(p->axpy), WG, 0, s>>>(p->items_d, p->ctl_d, p->axpy.d, p->nmesh, 1);
+  p->mark(5, 1);
+  if (p->cfg.D == 3)
+    CC_DISPATCH_MAT(p->cfg.any_fcr, kb_energy<3, FCR><<<gridn(p->energy), WG, 0, s>>>(
+                                        p->items_d, p->ctl_d, p->energy.d, p->nmesh, 1));
+  else
+    CC_DISPATCH_MAT(p->cfg.any_fcr, kb_energy<2, FCR><<<gridn(p->energy), WG, 0, s>>>(
+                                        p->items_d, p->ctl_d, p->energy.d, p->nmesh, 1));
+  p->mark(5, 0);
+  kb_ls_reduce<<<p->nmesh, WG, 0, s>>>(p->items_d, p->ctl_d, p->energy.d, max_halvings);
+}
+
+void batch_gradient_converge(BatchPlan* p, hipStream_t s) {
+  if (p->cfg.D == 3) b_gradient<3>(p, 0, s, 2); else b_gradient<2>(p, 0, s, 2);
+}
+
 BatchGrid batch_grid(BatchPlan* p) {
   BatchGrid g;
   g.nmesh = p->nmesh;

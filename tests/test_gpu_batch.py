@@ -90,6 +90,44 @@ def test_batch_equals_single_mesh(cg, ctx, prec, sweep, graph):
             assert np.linalg.norm(a - b) <= tol * np.linalg.norm(b - s.X)
 
 
+@pytest.mark.parametrize("max_halvings", [0, 2, 30])
+def test_batch_backtracking_equals_single_mesh(cg, ctx, max_halvings):
+    """Line-searched Jacobi CC with R = 1 bases on the uneven bars, where the
+    full step often raises the energy: the batched backtracking rounds (and,
+    once the halvings run out, the coordinate-descent fallback) take the
+    single-mesh path's decisions.  Float64: equal status, iterations and
+    halvings, positions to rounding."""
+    scenes = _scenes()
+    mids, _ = _setup(cg, ctx, scenes, "R1")
+    mids1, _ = _setup(cg, ctx, scenes, "R1")
+    cg.cc_batch_tuning(ctx, 16, 2)
+    par = cg.cc_params_default(method=cg.METHOD_CC, sweep=0, line_search=1, max_iters=12,
+                               max_halvings=max_halvings)
+    xs = [_t(s.initial_state()[0]) for s in scenes]
+    vs = [_t(s.initial_state()[1]) for s in scenes]
+    xs1 = [x.clone() for x in xs]
+    vs1 = [v.clone() for v in vs]
+    grav = np.stack([s.gravity for s in scenes])
+    halved = 0
+    for t in range(1, 3):
+        bcs = [_t(s.targets(t)) for s in scenes]
+        _, its, _, sts = cg.cc_step_batch(ctx, mids, xs, vs, bcs, scenes[0].dt, par, 1e-7,
+                                          gravity=grav)
+        for k, s in enumerate(scenes):
+            par1 = cg.cc_params_default(method=cg.METHOD_CC, sweep=0, line_search=1, max_iters=12,
+                                        max_halvings=max_halvings, gravity=s.gravity)
+            st, it, _ = cg.cc_step(ctx, mids1[k], xs1[k], vs1[k], bcs[k], s.dt, par1, 1e-7)
+            hb = cg.cc_step_info(ctx, mids[k])["halvings"]
+            h1 = cg.cc_step_info(ctx, mids1[k])["halvings"]
+            assert (sts[k], int(its[k]), hb) == (st, it, h1), (k, t)
+            halved += hb
+            a, b = xs[k].cpu().numpy(), xs1[k].cpu().numpy()
+            assert np.all(np.isfinite(a))
+            assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(b - s.X), (k, t)
+    if max_halvings > 0:
+        assert halved > 0                       # the rounds were exercised
+
+
 def test_batch_against_oracle(cg, ctx):
     scenes = _scenes()[:3]
     mids, bases = _setup(cg, ctx, scenes, "exact")

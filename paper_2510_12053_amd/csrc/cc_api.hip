@@ -1553,10 +1553,10 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
       bool host = false;
       for (auto& c : ctl) host = host || c.needs_host;
       if (host) {
-        // Meshes whose energy rose at the full step backtrack together: each
-        // round forms every searching mesh's trial point, its energy and its
-        // decision in three launches.  Four rounds are queued per read-back;
-        // a mesh that has decided is inactive and skips the later ones.
+        // Meshes whose energy rose at the full step backtrack together: a
+        // round evaluates the next eight halvings of every searching mesh at
+        // once and takes the first that does not raise E.  Two rounds are
+        // queued per read-back; a mesh that has decided skips the second.
         std::vector<int> was_active(n);
         for (int i = 0; i < n; ++i) {
           was_active[i] = ctl[i].active;
@@ -1571,7 +1571,9 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
           bool searching = false;
           for (auto& c : ctl) searching = searching || c.active;
           if (!searching) break;
-          for (int q = 0; q < 4; ++q) cc::batch_ls_round(plan, r == 0 && q == 0, p.max_halvings, s);
+          for (int q = 0; q < 2; ++q)
+            if (!cc::batch_ls_round(plan, r == 0 && q == 0, p.max_halvings, s))
+              throw ApiError{CC_E_HIP, "no device memory for the batched line search"};
           pull_ctl();
         }
         // accepted steps: gradient at the new x and the convergence test

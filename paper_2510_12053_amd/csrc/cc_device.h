@@ -44,12 +44,17 @@ template <typename T> __device__ __forceinline__ const T* basis_of(const MeshVie
 template <> __device__ __forceinline__ const float* basis_of<float>(const MeshView& mv) { return mv.U_f; }
 template <> __device__ __forceinline__ const double* basis_of<double>(const MeshView& mv) { return mv.U_d; }
 
+// beta_a, F = sum_{a>=1} (x_a - x_0) beta_a^T and the rest volume of element
+// e from its edge matrix Ds = [x_a - x_0].
+template <typename T, int D>
+__device__ __forceinline__ void element_from_edges(const MeshView& mv, int e, const T Ds[D][D],
+                                                   T F[D][D], T beta[D + 1][D], T& vol);
+
 // F = sum_{a>=1} (x_a - x_0) beta_a^T, differences formed in float64 then cast.
 template <typename T, int D>
 __device__ __forceinline__ void load_element(const MeshView& mv, int e, const double* __restrict__ x,
                                              T F[D][D], T beta[D + 1][D], T& vol) {
   const int m = mv.m, n = mv.n;
-  const T* dinv = dinv_of<T>(mv);
   const int v0 = mv.ev[e];
   T Ds[D][D];
 #pragma unroll
@@ -58,6 +63,36 @@ __device__ __forceinline__ void load_element(const MeshView& mv, int e, const do
 #pragma unroll
     for (int c = 0; c < D; ++c) Ds[c][a - 1] = T(x[c * n + va] - x[c * n + v0]);
   }
+  element_from_edges<T, D>(mv, e, Ds, F, beta, vol);
+}
+
+// The same at the positions x + alpha d, each formed as the trial-point
+// update forms it, so the values equal those of a stored x + alpha d.
+template <typename T, int D>
+__device__ __forceinline__ void load_element_along(const MeshView& mv, int e, const double* __restrict__ x,
+                                                   const double* __restrict__ d, double alpha,
+                                                   T F[D][D], T beta[D + 1][D], T& vol) {
+  const int m = mv.m, n = mv.n;
+  const int v0 = mv.ev[e];
+  T Ds[D][D];
+#pragma unroll
+  for (int a = 1; a <= D; ++a) {
+    const int va = mv.ev[a * m + e];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const double pa = x[c * n + va] + alpha * d[c * n + va];
+      const double p0 = x[c * n + v0] + alpha * d[c * n + v0];
+      Ds[c][a - 1] = T(pa - p0);
+    }
+  }
+  element_from_edges<T, D>(mv, e, Ds, F, beta, vol);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void element_from_edges(const MeshView& mv, int e, const T Ds[D][D],
+                                                   T F[D][D], T beta[D + 1][D], T& vol) {
+  const int m = mv.m;
+  const T* dinv = dinv_of<T>(mv);
 #pragma unroll
   for (int a = 0; a < D; ++a)
 #pragma unroll

@@ -205,10 +205,12 @@ void batch_energy_x(BatchPlan* p, hipStream_t s);       // ctl.E_cur = E(x)
 // g(x), ctl.gn2; only_warm: only meshes whose learned proposal was accepted
 void batch_gradient_x(BatchPlan* p, hipStream_t s, int only_warm = 0);
 // One backtracking round for the active meshes, whose energy rose at the
-// full step: x_trial = x + alpha d (with d = x_trial - x formed first when
-// `first`), E(x_trial), then accept (swap, E_cur, iteration count), halve
-// alpha, or give up after max_halvings halvings (ctl.ls).
-void batch_ls_round(BatchPlan* p, int first, int max_halvings, hipStream_t s);
+// full step (d = x_trial - x formed first when `first`): the energies at the
+// next halvings of alpha, then per mesh the first that does not raise E is
+// taken (x_trial = x + alpha d written, swapped in, E_cur and the iteration
+// count updated), or the search stops at max_halvings (ctl.ls), or goes on
+// in the next round.  False when the plan has no buffer for the energies.
+bool batch_ls_round(BatchPlan* p, int first, int max_halvings, hipStream_t s);
 // Gradient at x and the convergence test for the active meshes.
 void batch_gradient_converge(BatchPlan* p, hipStream_t s);
 void batch_warm_start(BatchPlan* p, const MlpState& net, float* feat, float* delta, int rows,

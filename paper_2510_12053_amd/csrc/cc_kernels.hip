@@ -90,6 +90,7 @@ __device__ __forceinline__ void elem_hess_body(const MeshView& mv, int e, const 
 // 64-thread workgroups: a few thousand elements then spread over most CUs
 // instead of a few dozen (the per-element work is a long serial chain).
 constexpr int EWG = 64;
+constexpr int LS_WIDTH = 8;   // backtracking halvings evaluated per launch
 
 template <typename T, int D, bool FCR>
 __global__ void __launch_bounds__(EWG) k_elem_hess(MeshView mv, const double* __restrict__ x, T mu,
@@ -774,6 +775,41 @@ __device__ __forceinline__ double energy_body(const MeshView& mv, int b, int nbe
         const double dx = x[c * n + j] - xt[c * n + j];
         in += dx * dx;
         gr += mat.grav[c] * x[c * n + j];
+      }
+      v = mat.w_in * 0.5 * mj * in - mat.s_el * mj * gr;
+    }
+  }
+  return v;
+}
+
+// energy_body at the positions x + alpha d (formed as the trial-point update
+// forms them), block for block.
+template <int D, bool FCR>
+__device__ __forceinline__ double energy_body_along(const MeshView& mv, int b, int nbe,
+                                                    const double* __restrict__ x,
+                                                    const double* __restrict__ d, double alpha,
+                                                    const double* __restrict__ xt,
+                                                    const Material& mat) {
+  double v = 0.0;
+  const int n = mv.n;
+  if (b < nbe) {
+    const int e = b * WG + threadIdx.x;
+    if (e < mv.m) {
+      double F[D][D], beta[D + 1][D], vol;
+      load_element_along<double, D>(mv, e, x, d, alpha, F, beta, vol);
+      v = mat.s_el * vol * material_psi<double, D>(F, mat.mu, mat.lam, FCR ? mat.model : MAT_SNH);
+    }
+  } else {
+    const int j = (b - nbe) * WG + threadIdx.x;
+    if (j < mv.nf) {
+      const double mj = mv.mass[j];
+      double in = 0.0, gr = 0.0;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const double p = x[c * n + j] + alpha * d[c * n + j];
+        const double dx = p - xt[c * n + j];
+        in += dx * dx;
+        gr += mat.grav[c] * p;
       }
       v = mat.w_in * 0.5 * mj * in - mat.s_el * mj * gr;
     }
@@ -1480,13 +1516,20 @@ __global__ void __launch_bounds__(WG) kb_reduce(BatchItem* __restrict__ items, B
 }
 
 // Backtracking (Results, Subspace Quality: global line search along the
-// sweep's displacement) of the active meshes, all meshes per launch.
-// mode 0: d = x_trial - x; mode 1: x_trial = x + alpha d.
+// sweep's displacement) of the active meshes, all meshes per launch.  The
+// halvings alpha = 1/2, 1/4, ... are tried LS_WIDTH at a time: one launch
+// evaluates E(x + alpha d) for each, and the decision takes the first that
+// does not raise E, which is what trying them one after another would take.
+// ctl.ls: 0 searching, 3 step found (to be written), 1 taken, 2 halvings
+// exhausted.
+
+// mode 0: d = x_trial - x for the active meshes; mode 1: x_trial = x + alpha d
+// for the meshes whose step was found.
 __global__ void __launch_bounds__(WG) kb_ls_vec(BatchItem* __restrict__ items,
                                                 const BatchCtl* __restrict__ ctl,
                                                 const int* __restrict__ boff, int nmesh, int mode) {
   const int mi = block_mesh(boff, nmesh, blockIdx.x);
-  if (!ctl[mi].active) return;
+  if (!ctl[mi].active || (mode == 1 && ctl[mi].ls != 3)) return;
   const BatchItem& it = items[mi];
   const int t = (blockIdx.x - boff[mi]) * WG + threadIdx.x;
   if (t >= it.mv.D * it.mv.n) return;
@@ -1494,34 +1537,79 @@ __global__ void __launch_bounds__(WG) kb_ls_vec(BatchItem* __restrict__ items,
   else it.xtrial[t] = it.x[t] + ctl[mi].alpha * it.d[t];
 }
 
-// E(x_trial) of the active meshes, then each takes the step (swap, E_cur,
-// one more iteration), halves alpha, or stops after max_halvings halvings.
-__global__ void __launch_bounds__(WG) kb_ls_reduce(BatchItem* __restrict__ items, BatchCtl* ctl,
-                                                   const int* __restrict__ boff_src, int max_halvings) {
+// Energy partials at x + alpha_k d, alpha_k = ctl.alpha / 2^k, k = blockIdx.y,
+// laid out as kb_energy's partials, one set of `total` per k.
+template <int D, bool FCR>
+__global__ void __launch_bounds__(WG) kb_energy_wide(const BatchItem* __restrict__ items,
+                                                     const BatchCtl* __restrict__ ctl,
+                                                     const int* __restrict__ boff, int nmesh,
+                                                     int total, int max_halvings,
+                                                     double* __restrict__ wpart) {
+  __shared__ double red[WG];
+  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  const BatchCtl& c = ctl[mi];
+  const int k = blockIdx.y;
+  if (!c.active || c.ls != 0 || c.halvings + k > max_halvings) return;
+  double alpha = c.alpha;
+  for (int q = 0; q < k; ++q) alpha *= 0.5;
+  const BatchItem& it = items[mi];
+  const MeshView mv = it.mv;
+  const int lb = blockIdx.x - boff[mi];
+  const int nbe = (mv.m + WG - 1) / WG;
+  const double v = energy_body_along<D, FCR>(mv, lb, nbe, it.x, it.d, alpha, it.xt, it.mat);
+  const double tot = block_sum<WG>(v, red);
+  if (threadIdx.x == 0) wpart[(size_t)k * total + blockIdx.x] = tot;
+}
+
+// Per mesh, in halving order: E at alpha_k (partials summed as kb_reduce
+// sums them); the first that does not raise E beyond the slack is the step;
+// at the halving limit the search stops; otherwise the next launch goes on
+// from alpha / 2^width.
+__global__ void __launch_bounds__(WG) kb_ls_reduce_wide(BatchCtl* ctl, const int* __restrict__ boff,
+                                                        int total, int width, int max_halvings,
+                                                        const double* __restrict__ wpart) {
   __shared__ double red[WG];
   const int mi = blockIdx.x;
-  if (!ctl[mi].active) return;
-  const double tot = mesh_partials_sum(items[mi], boff_src[mi + 1] - boff_src[mi], red);
-  if (threadIdx.x != 0) return;
   BatchCtl& c = ctl[mi];
-  c.E_trial = tot;
+  if (!c.active || c.ls != 0) return;
   const double tau = 1e-12 * fmax(fabs(c.E_cur), 1.0);
-  if (c.E_trial <= c.E_cur + tau) {
-    BatchItem& item = items[mi];
-    double* t = item.x;
-    item.x = item.xtrial;
-    item.xtrial = t;
-    c.E_cur = c.E_trial;
-    c.iters += 1;
-    c.ls = 1;
-    c.active = 0;
-  } else if (c.halvings >= max_halvings) {
-    c.ls = 2;
-    c.active = 0;
-  } else {
-    c.alpha *= 0.5;
-    c.halvings += 1;
+  const double Ecur = c.E_cur;
+  const int np = boff[mi + 1] - boff[mi];
+  double alpha = c.alpha, Et = 0.0;
+  int h = c.halvings, ls = 0;
+  for (int k = 0; k < width; ++k) {
+    const double* part = wpart + (size_t)k * total + boff[mi];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < np; i += WG) v += part[i];
+    Et = block_sum<WG>(v, red);
+    __syncthreads();                       // red is reused by the next sum
+    if (Et <= Ecur + tau) { ls = 3; break; }
+    if (h >= max_halvings) { ls = 2; break; }
+    alpha *= 0.5;
+    h += 1;
   }
+  if (threadIdx.x != 0) return;
+  c.E_trial = Et;
+  c.alpha = alpha;
+  c.halvings = h;
+  c.ls = ls;
+  if (ls == 2) c.active = 0;
+}
+
+// Takes the written steps: swap x and x_trial, E, one more iteration.
+__global__ void kb_ls_commit(BatchItem* __restrict__ items, BatchCtl* ctl, int nmesh) {
+  const int mi = blockIdx.x * WG + threadIdx.x;
+  if (mi >= nmesh) return;
+  BatchCtl& c = ctl[mi];
+  if (!c.active || c.ls != 3) return;
+  BatchItem& item = items[mi];
+  double* t = item.x;
+  item.x = item.xtrial;
+  item.xtrial = t;
+  c.E_cur = c.E_trial;
+  c.iters += 1;
+  c.ls = 1;
+  c.active = 0;
 }
 
 __global__ void kb_init(BatchCtl* ctl, int nmesh, double tol, int max_iters) {
@@ -1565,6 +1653,7 @@ struct BatchPlan {
   size_t lds = 0;   // its dynamic LDS
   int scap = 0;     // staged support blocks per vertex of the sparse condensation (0: none)
   size_t slds = 0;  // its dynamic LDS
+  double* wpart = nullptr;   // energy partials of LS_WIDTH backtracking steps
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_iters = 0;
@@ -1666,6 +1755,11 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
   offsets_build(p->asmb, casm, s);
   offsets_build(p->grad, cgrad, s);
   offsets_build(p->energy, cen, s);
+  if (p->energy.total() > 0 &&
+      hipMalloc(&p->wpart, (size_t)LS_WIDTH * p->energy.total() * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    p->wpart = nullptr;
+  }
   offsets_build(p->axpy, cax, s);
   offsets_build(p->axpyj, caxj, s);
   offsets_build(p->feat, cfeat, s);
@@ -1688,6 +1782,7 @@ void batch_plan_destroy(BatchPlan* p) {
   for (auto& o : p->prepd) offsets_free(o);
   for (auto& o : p->fin) offsets_free(o);
   for (auto& o : p->upd) offsets_free(o);
+  if (p->wpart) (void)hipFree(p->wpart);
   if (p->items_d) (void)hipFree(p->items_d);
   if (p->ctl_d) (void)hipFree(p->ctl_d);
   delete p;
@@ -1871,19 +1966,27 @@ void batch_gradient_x(BatchPlan* p, hipStream_t s, int only_warm) {
 void batch_energy_x(BatchPlan* p, hipStream_t s) {
   if (p->cfg.D == 3) b_energy<3>(p, 0, 2, s); else b_energy<2>(p, 0, 2, s);
 }
-void batch_ls_round(BatchPlan* p, int first, int max_halvings, hipStream_t s) {
-  if (gridn(p->axpy) == 0 || gridn(p->energy) == 0) return;
+bool batch_ls_round(BatchPlan* p, int first, int max_halvings, hipStream_t s) {
+  const int total = gridn(p->energy);
+  if (gridn(p->axpy) == 0 || total == 0) return true;
+  if (!p->wpart) return false;
   if (first) kb_ls_vec<<<gridn(p->axpy), WG, 0, s>>>(p->items_d, p->ctl_d, p->axpy.d, p->nmesh, 0);
-  kb_ls_vec<<<gridn(p->axpy), WG, 0, s>>>(p->items_d, p->ctl_d, p->axpy.d, p->nmesh, 1);
+  const dim3 grid(total, LS_WIDTH);
   p->mark(5, 1);
   if (p->cfg.D == 3)
-    CC_DISPATCH_MAT(p->cfg.any_fcr, kb_energy<3, FCR><<<gridn(p->energy), WG, 0, s>>>(
-                                        p->items_d, p->ctl_d, p->energy.d, p->nmesh, 1));
+    CC_DISPATCH_MAT(p->cfg.any_fcr, kb_energy_wide<3, FCR><<<grid, WG, 0, s>>>(
+                                        p->items_d, p->ctl_d, p->energy.d, p->nmesh, total,
+                                        max_halvings, p->wpart));
   else
-    CC_DISPATCH_MAT(p->cfg.any_fcr, kb_energy<2, FCR><<<gridn(p->energy), WG, 0, s>>>(
-                                        p->items_d, p->ctl_d, p->energy.d, p->nmesh, 1));
+    CC_DISPATCH_MAT(p->cfg.any_fcr, kb_energy_wide<2, FCR><<<grid, WG, 0, s>>>(
+                                        p->items_d, p->ctl_d, p->energy.d, p->nmesh, total,
+                                        max_halvings, p->wpart));
   p->mark(5, 0);
-  kb_ls_reduce<<<p->nmesh, WG, 0, s>>>(p->items_d, p->ctl_d, p->energy.d, max_halvings);
+  kb_ls_reduce_wide<<<p->nmesh, WG, 0, s>>>(p->ctl_d, p->energy.d, total, LS_WIDTH, max_halvings,
+                                            p->wpart);
+  kb_ls_vec<<<gridn(p->axpy), WG, 0, s>>>(p->items_d, p->ctl_d, p->axpy.d, p->nmesh, 1);
+  kb_ls_commit<<<(p->nmesh + WG - 1) / WG, WG, 0, s>>>(p->items_d, p->ctl_d, p->nmesh);
+  return true;
 }
 
 void batch_gradient_converge(BatchPlan* p, hipStream_t s) {

@@ -998,9 +998,10 @@ void launch_assemble(const MeshView& mv, int prec, const void* estore, const Mat
 constexpr int GRAD_G = 16;   // lanes per vertex of the gradient: a 3D star holds about 24 elements
 
 int reduce_partials_capacity(const MeshView& mv) {
+  // energy partials followed by gradient partials (kb_energy_grad)
   const int a = nblocks(mv.nf, WG / GRAD_G);
   const int b = nblocks(mv.m, WG) + nblocks(mv.nf, WG);
-  return (a > b ? a : b) + 1;
+  return a + b + 1;
 }
 
 void launch_gradient(const MeshView& mv, const double* x, const double* xt, const Material& mat,
@@ -1443,6 +1444,34 @@ __global__ void __launch_bounds__(WG) kb_axpy(const BatchItem* __restrict__ item
   it.xtrial[t] = copy_only ? it.x[t] : it.x[t] + alpha * it.d[t];
 }
 
+// The end of a line-searched iteration in one launch: per mesh, the energy
+// blocks at the trial point (as kb_energy) followed by the gradient blocks
+// at the trial point (as kb_gradient), each writing its partial at its own
+// block index.  The gradient is speculative: it is used only if the trial
+// point is taken, and every path that leaves a mesh at its old x computes
+// the gradient there again.
+template <int D, bool FCR>
+__global__ void __launch_bounds__(WG) kb_energy_grad(const BatchItem* __restrict__ items,
+                                                     const BatchCtl* __restrict__ ctl,
+                                                     const int* __restrict__ boff, int nmesh) {
+  __shared__ double red[WG];
+  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  if (!ctl[mi].active) return;
+  const BatchItem& it = items[mi];
+  const MeshView mv = it.mv;
+  const int lb = blockIdx.x - boff[mi];
+  const int nbe = (mv.m + WG - 1) / WG;
+  const int ne = nbe + (mv.nf + WG - 1) / WG;
+  double v;
+  if (lb < ne)
+    v = energy_body<D, FCR>(mv, lb, nbe, it.xtrial, it.xt, it.mat);
+  else
+    v = gradient_body<D, GRAD_G, FCR>(mv, (lb - ne) * (WG / GRAD_G) + threadIdx.x / GRAD_G,
+                                      threadIdx.x % GRAD_G, it.xtrial, it.xt, it.mat, it.g);
+  const double tot = block_sum<WG>(v, red);
+  if (threadIdx.x == 0) it.partials[lb] = tot;
+}
+
 template <int D, bool FCR>
 __global__ void __launch_bounds__(WG) kb_energy(const BatchItem* __restrict__ items,
                                                 const BatchCtl* __restrict__ ctl,
@@ -1612,6 +1641,31 @@ __global__ void kb_ls_commit(BatchItem* __restrict__ items, BatchCtl* ctl, int n
   c.active = 0;
 }
 
+// Both sums of kb_energy_grad (each in kb_reduce's order), then the accept
+// rule and, for a mesh that took its trial point, the convergence test.
+__global__ void __launch_bounds__(WG) kb_reduce_eg(BatchItem* __restrict__ items, BatchCtl* ctl,
+                                                   double tol, int max_iters) {
+  __shared__ double red[WG];
+  const int mi = blockIdx.x;
+  if (!ctl[mi].active) return;
+  const BatchItem& it = items[mi];
+  const int ne = (it.mv.m + WG - 1) / WG + (it.mv.nf + WG - 1) / WG;
+  const int ng = (it.mv.nf + WG / GRAD_G - 1) / (WG / GRAD_G);
+  const double E = mesh_partials_sum(it, ne, red);
+  __syncthreads();                         // red is reused by the next sum
+  double v = 0.0;
+  for (int i = threadIdx.x; i < ng; i += WG) v += it.partials[ne + i];
+  const double gn2 = block_sum<WG>(v, red);
+  if (threadIdx.x != 0) return;
+  BatchCtl& c = ctl[mi];
+  c.E_trial = E;
+  accept_mesh(items[mi], c, 1);
+  if (c.active) {
+    c.gn2 = gn2;
+    converged_mesh(c, tol, max_iters);
+  }
+}
+
 __global__ void kb_init(BatchCtl* ctl, int nmesh, double tol, int max_iters) {
   const int m = blockIdx.x * WG + threadIdx.x;
   if (m >= nmesh) return;
@@ -1647,6 +1701,7 @@ struct BatchPlan {
   BatchItem* items_d = nullptr;
   BatchCtl* ctl_d = nullptr;
   Offsets pred, elem, asmb, grad, energy, axpy, axpyj, feat, rotn;   // axpyj: Jacobi trial points
+  Offsets eg;       // energy then gradient blocks of each mesh (kb_energy_grad)
   std::vector<Offsets> prep, prepd, fin, upd;   // index 0: all free vertices, c+1: colour c
   int max_colours = 0;
   int tv = 0;       // vertices per workgroup of the dense condensation (0: no dense mesh)
@@ -1755,6 +1810,11 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
   offsets_build(p->asmb, casm, s);
   offsets_build(p->grad, cgrad, s);
   offsets_build(p->energy, cen, s);
+  {
+    std::vector<int> ceg(nmesh);
+    for (int m = 0; m < nmesh; ++m) ceg[m] = cen[m] + cgrad[m];
+    offsets_build(p->eg, ceg, s);
+  }
   if (p->energy.total() > 0 &&
       hipMalloc(&p->wpart, (size_t)LS_WIDTH * p->energy.total() * sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
@@ -1775,7 +1835,7 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
 void batch_plan_destroy(BatchPlan* p) {
   if (!p) return;
   drop_graph(p);
-  for (Offsets* o : {&p->pred, &p->elem, &p->asmb, &p->grad, &p->energy, &p->axpy, &p->axpyj, &p->feat,
+  for (Offsets* o : {&p->pred, &p->elem, &p->asmb, &p->grad, &p->energy, &p->eg, &p->axpy, &p->axpyj, &p->feat,
                      &p->rotn})
     offsets_free(*o);
   for (auto& o : p->prep) offsets_free(o);
@@ -1893,11 +1953,20 @@ static void b_iteration(BatchPlan* p, hipStream_t s) {
       b_update<T, D, G>(p, col, 1, s);
     }
   }
-  if (c.line_search)
-    b_energy<D>(p, 1, 0, s, 1);   // E at the trial point, then the accept rule
-  else
+  if (c.line_search) {
+    // E and the gradient at the trial point, then the accept rule and the
+    // convergence test
+    if (gridn(p->eg) > 0) {
+      p->mark(5, 1);
+      CC_DISPATCH_MAT(c.any_fcr, kb_energy_grad<D, FCR><<<gridn(p->eg), WG, 0, s>>>(
+                                     p->items_d, p->ctl_d, p->eg.d, nm));
+      p->mark(5, 0);
+      kb_reduce_eg<<<nm, WG, 0, s>>>(p->items_d, p->ctl_d, c.tol, c.max_iters);
+    }
+  } else {
     kb_accept<<<gb, WG, 0, s>>>(p->items_d, p->ctl_d, nm, 0);
-  b_gradient<D>(p, 0, s, 2);      // gradient at the accepted point, then the convergence test
+    b_gradient<D>(p, 0, s, 2);    // gradient at the accepted point, then the convergence test
+  }
 }
 
 

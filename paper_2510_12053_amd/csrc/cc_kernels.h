@@ -200,10 +200,13 @@ struct BatchGrid {
   int line_search;      // E at the predictor is already in ctl.E_cur
 };
 BatchGrid batch_grid(BatchPlan* p);
-void batch_energy_trial(BatchPlan* p, hipStream_t s);   // ctl.E_trial = E(xtrial)
+// ctl.E_trial = E(xtrial); post 3: then the warm start's accept rule
+void batch_energy_trial(BatchPlan* p, hipStream_t s, int post = 0);
 void batch_energy_x(BatchPlan* p, hipStream_t s);       // ctl.E_cur = E(x)
 // g(x), ctl.gn2; only_warm: only meshes whose learned proposal was accepted
-void batch_gradient_x(BatchPlan* p, hipStream_t s, int only_warm = 0);
+// gradient at x; post 4 (with only_warm): then the residual test of an
+// accepted proposal
+void batch_gradient_x(BatchPlan* p, hipStream_t s, int only_warm = 0, int post = 0);
 // One backtracking round for the active meshes, whose energy rose at the
 // full step (d = x_trial - x formed first when `first`): the energies at the
 // next halvings of alpha, then per mesh the first that does not raise E is

@@ -1505,6 +1505,24 @@ __device__ __forceinline__ void accept_mesh(BatchItem& item, BatchCtl& c, int li
   }
 }
 
+// Learned warm start: the proposal (in xtrial, its energy in E_trial)
+// replaces the predictor when it has the lower step energy.
+__device__ __forceinline__ void warm_accept_mesh(BatchItem& item, BatchCtl& c) {
+  if (c.E_trial < c.E_cur) {
+    double* t = item.x;
+    item.x = item.xtrial;
+    item.xtrial = t;
+    c.E_cur = c.E_trial;
+    c.warm = 1;
+  }
+}
+
+// Residual at an accepted proposal against the predictor's gradient norm g0.
+__device__ __forceinline__ void warm_check_mesh(BatchCtl& c, double tol) {
+  c.r = sqrt(c.gn2) / c.g0;
+  if (c.r <= tol) { c.status = 0; c.active = 0; }
+}
+
 // Convergence test of an active mesh after its gradient norm is in gn2.
 __device__ __forceinline__ void converged_mesh(BatchCtl& c, double tol, int max_iters) {
   c.r = sqrt(c.gn2) / c.g0;
@@ -1541,6 +1559,8 @@ __global__ void __launch_bounds__(WG) kb_reduce(BatchItem* __restrict__ items, B
     else c.E_cur = tot;
     if (post == 1) accept_mesh(items[mi], c, 1);
     else if (post == 2) converged_mesh(c, tol, max_iters);
+    else if (post == 3) warm_accept_mesh(items[mi], c);
+    else if (post == 4) warm_check_mesh(c, tol);
   }
 }
 
@@ -2026,11 +2046,12 @@ void batch_iterate(BatchPlan* p, int iters, hipStream_t s) {
 }
 
 // Pieces of the batched path used by the warm start (cc_mlp.hip).
-void batch_energy_trial(BatchPlan* p, hipStream_t s) {
-  if (p->cfg.D == 3) b_energy<3>(p, 1, 0, s); else b_energy<2>(p, 1, 0, s);
+void batch_energy_trial(BatchPlan* p, hipStream_t s, int post) {
+  if (p->cfg.D == 3) b_energy<3>(p, 1, 0, s, post); else b_energy<2>(p, 1, 0, s, post);
 }
-void batch_gradient_x(BatchPlan* p, hipStream_t s, int only_warm) {
-  if (p->cfg.D == 3) b_gradient<3>(p, 0, s, 0, only_warm); else b_gradient<2>(p, 0, s, 0, only_warm);
+void batch_gradient_x(BatchPlan* p, hipStream_t s, int only_warm, int post) {
+  if (p->cfg.D == 3) b_gradient<3>(p, 0, s, post, only_warm);
+  else b_gradient<2>(p, 0, s, post, only_warm);
 }
 void batch_energy_x(BatchPlan* p, hipStream_t s) {
   if (p->cfg.D == 3) b_energy<3>(p, 0, 2, s); else b_energy<2>(p, 0, 2, s);

@@ -628,38 +628,15 @@ __global__ void __launch_bounds__(WG) kb_proposal(const BatchItem* __restrict__ 
         (v < nf ? it.ell * (double)delta[(size_t)(it.feat_off + v) * MLP_NOUT + c] : 0.0);
 }
 
-// Accept the proposal when it lowers the step energy below the predictor's.
-__global__ void kb_ws_accept(BatchItem* items, BatchCtl* ctl, int nmesh) {
-  const int m = blockIdx.x * WG + threadIdx.x;
-  if (m >= nmesh) return;
-  BatchCtl& c = ctl[m];
-  if (!c.active) return;
-  if (c.E_trial < c.E_cur) {
-    double* t = items[m].x;
-    items[m].x = items[m].xtrial;
-    items[m].xtrial = t;
-    c.E_cur = c.E_trial;
-    c.warm = 1;
-  }
-}
-
-// Residual at the start state (the proposal when accepted) against the
-// predictor's gradient norm g0.
-__global__ void kb_ws_check(BatchCtl* ctl, int nmesh, double tol) {
-  const int m = blockIdx.x * WG + threadIdx.x;
-  if (m >= nmesh) return;
-  BatchCtl& c = ctl[m];
-  if (!c.active) return;
-  c.r = sqrt(c.gn2) / c.g0;
-  if (c.r <= tol) { c.status = 0; c.active = 0; }
-}
-
+// Learned warm start of every mesh of the batch: features, the network, the
+// proposal, then its energy with the accept rule (it replaces the predictor
+// only at a lower step energy) and, where accepted, its gradient and
+// residual test.
 void batch_warm_start(BatchPlan* p, const MlpState& net, float* feat, float* delta, int rows,
                       hipStream_t s) {
   const BatchGrid g = batch_grid(p);
   BatchItem* items = batch_items_dev(p);
   BatchCtl* ctl = batch_ctl_dev(p);
-  const int gb = (g.nmesh + WG - 1) / WG;
   if (g.pred_blocks == 0) return;
   if (g.feat_blocks > 0) {
     if (g.any_fcr)
@@ -670,10 +647,10 @@ void batch_warm_start(BatchPlan* p, const MlpState& net, float* feat, float* del
   mlp_forward(net, feat, rows, delta, s);
   kb_proposal<<<g.pred_blocks, WG, 0, s>>>(items, ctl, g.pred_off, g.nmesh, delta);
   if (!g.line_search) batch_energy_x(p, s);   // with line search batch_begin computed it
-  batch_energy_trial(p, s);
-  kb_ws_accept<<<gb, WG, 0, s>>>(items, ctl, g.nmesh);
-  batch_gradient_x(p, s, 1);   // a rejected proposal leaves x, g and |g| at the predictor
-  kb_ws_check<<<gb, WG, 0, s>>>(ctl, g.nmesh, g.tol);
+  batch_energy_trial(p, s, 3);     // E(proposal), then the accept rule
+  // gradient and residual test at an accepted proposal; a rejected one
+  // leaves x, g and |g| at the predictor (r = 1 from the step start)
+  batch_gradient_x(p, s, 1, 4);
 }
 
 }  // namespace cc

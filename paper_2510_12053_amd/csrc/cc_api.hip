@@ -1571,6 +1571,9 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
           bool searching = false;
           for (auto& c : ctl) searching = searching || c.active;
           if (!searching) break;
+          // every round decides a mesh or takes it eight halvings further
+          if (r > p.max_halvings + 1)
+            throw ApiError{CC_E_HIP, "batched line search did not finish"};
           for (int q = 0; q < 2; ++q)
             if (!cc::batch_ls_round(plan, r == 0 && q == 0, p.max_halvings, s))
               throw ApiError{CC_E_HIP, "no device memory for the batched line search"};

@@ -22,10 +22,13 @@
 namespace cc {
 
 // Element Hessian: H_e[a,b] = scale * V_e * sum_r w_r (Q_r beta_a)(Q_r beta_b)^T
-template <typename T, int D>
+// H selects the output blocks: 0 all of them, 1 the first half of the packed
+// blocks, 2 the second half (the element's eigensystem is formed either way).
+template <typename T, int D, int H>
 __device__ __forceinline__ void elem_hess_body(const MeshView& mv, int e, const double* __restrict__ x,
                                                T mu, T lam, int model, T scale, T* __restrict__ out) {
   constexpr int K = D + 1, DD = D * D, NB = K * (K + 1) / 2;
+  auto keep = [](int p) { return H == 0 || (H == 1 ? p < NB / 2 : p >= NB / 2); };
   if (e >= mv.m) return;
   T F[D][D], beta[K][D], vol;
   load_element<T, D>(mv, e, x, F, beta, vol);
@@ -72,30 +75,49 @@ __device__ __forceinline__ void elem_hess_body(const MeshView& mv, int e, const 
       for (int r = 0; r < D; ++r) wy[r] = w * y[a][r];
 #pragma unroll
       for (int b = a; b < K; ++b)
+        if (keep(pidx<K>(a, b)))
 #pragma unroll
-        for (int r = 0; r < D; ++r)
+          for (int r = 0; r < D; ++r)
 #pragma unroll
-          for (int s = 0; s < D; ++s) acc[pidx<K>(a, b)][r * D + s] += wy[r] * z[b][s];
+            for (int s = 0; s < D; ++s) acc[pidx<K>(a, b)][r * D + s] += wy[r] * z[b][s];
     }
   });
   const T f = scale * vol;
   const int m = mv.m;
 #pragma unroll
   for (int p = 0; p < NB; ++p)
+    if (keep(p))
 #pragma unroll
-    for (int r = 0; r < DD; ++r) out[((size_t)p * m + e) * DD + r] = f * acc[p][r];
+      for (int r = 0; r < DD; ++r) out[((size_t)p * m + e) * DD + r] = f * acc[p][r];
 }
 
 // Element and assembly kernels run one thread per element / block slot in
 // 64-thread workgroups: a few thousand elements then spread over most CUs
 // instead of a few dozen (the per-element work is a long serial chain).
+// In float64 the element kernel gives each workgroup of EWG elements two
+// waves, each accumulating half of the output blocks: one wave holding all
+// ten 3x3 float64 accumulators spills registers.
 constexpr int EWG = 64;
+template <typename T> constexpr int elem_threads() { return sizeof(T) == 8 ? 2 * EWG : EWG; }
+
+template <typename T, int D>
+__device__ __forceinline__ void elem_hess_split(const MeshView& mv, int e0, const double* __restrict__ x,
+                                                T mu, T lam, int model, T scale, T* __restrict__ out) {
+  if constexpr (sizeof(T) == 8) {
+    const int e = e0 + threadIdx.x % EWG;
+    if (threadIdx.x < EWG) elem_hess_body<T, D, 1>(mv, e, x, mu, lam, model, scale, out);
+    else elem_hess_body<T, D, 2>(mv, e, x, mu, lam, model, scale, out);
+  } else {
+    elem_hess_body<T, D, 0>(mv, e0 + threadIdx.x, x, mu, lam, model, scale, out);
+  }
+}
 constexpr int LS_WIDTH = 8;   // backtracking halvings evaluated per launch
 
 template <typename T, int D, bool FCR>
-__global__ void __launch_bounds__(EWG) k_elem_hess(MeshView mv, const double* __restrict__ x, T mu,
-                                                   T lam, int model, T scale, T* __restrict__ out) {
-  elem_hess_body<T, D>(mv, blockIdx.x * EWG + threadIdx.x, x, mu, lam, FCR ? model : MAT_SNH, scale, out);
+__global__ void __launch_bounds__(elem_threads<T>()) k_elem_hess(MeshView mv, const double* __restrict__ x,
+                                                                 T mu, T lam, int model, T scale,
+                                                                 T* __restrict__ out) {
+  elem_hess_split<T, D>(mv, blockIdx.x * EWG, x, mu, lam, FCR ? model : MAT_SNH, scale, out);
 }
 
 // Block rows: every slot sums its element contributions (fixed order), plus
@@ -974,11 +996,11 @@ void launch_elem_hess(const MeshView& mv, int prec, const double* x, const Mater
   const int nb = nblocks(mv.m, EWG);
   if (prec == 0)
     CC_DISPATCH_MAT(mat.model == MAT_FCR,
-                    CC_DISPATCH_D(mv.D, k_elem_hess<double, D, FCR><<<nb, EWG, 0, s>>>(
+                    CC_DISPATCH_D(mv.D, k_elem_hess<double, D, FCR><<<nb, elem_threads<double>(), 0, s>>>(
                                             mv, x, mat.mu, mat.lam, mat.model, scale, (double*)estore)));
   else
     CC_DISPATCH_MAT(mat.model == MAT_FCR,
-                    CC_DISPATCH_D(mv.D, k_elem_hess<float, D, FCR><<<nb, EWG, 0, s>>>(
+                    CC_DISPATCH_D(mv.D, k_elem_hess<float, D, FCR><<<nb, elem_threads<float>(), 0, s>>>(
                                             mv, x, (float)mat.mu, (float)mat.lam, mat.model, (float)scale,
                                             (float*)estore)));
 }
@@ -1311,15 +1333,15 @@ __global__ void __launch_bounds__(WG) kb_finalize(const BatchItem* __restrict__ 
 }
 
 template <typename T, int D, bool FCR>
-__global__ void __launch_bounds__(EWG) kb_elem_hess(const BatchItem* __restrict__ items,
+__global__ void __launch_bounds__(elem_threads<T>()) kb_elem_hess(const BatchItem* __restrict__ items,
                                                    const BatchCtl* __restrict__ ctl,
                                                    const int* __restrict__ boff, int nmesh, int which) {
   const int mi = block_mesh(boff, nmesh, blockIdx.x);
   if (!ctl[mi].active) return;
   const BatchItem& it = items[mi];
   const MeshView mv = it.mv;
-  elem_hess_body<T, D>(mv, (blockIdx.x - boff[mi]) * EWG + threadIdx.x, pick(it, which), T(it.mat.mu),
-                       T(it.mat.lam), FCR ? it.mat.model : MAT_SNH, T(it.mat.s_el), (T*)it.estore);
+  elem_hess_split<T, D>(mv, (blockIdx.x - boff[mi]) * EWG, pick(it, which), T(it.mat.mu), T(it.mat.lam),
+                        FCR ? it.mat.model : MAT_SNH, T(it.mat.s_el), (T*)it.estore);
 }
 
 // Corotation: vertex rotations of every mesh at positions `which`.
@@ -1930,7 +1952,7 @@ static void b_hessian(BatchPlan* p, int which, hipStream_t s) {
     kb_rotations<D><<<gridn(p->rotn), WG, 0, s>>>(p->items_d, p->ctl_d, p->rotn.d, p->nmesh, which);
   if (gridn(p->elem) > 0) {
     p->mark(0, 1);
-    CC_DISPATCH_MAT(p->cfg.any_fcr, kb_elem_hess<T, D, FCR><<<gridn(p->elem), EWG, 0, s>>>(
+    CC_DISPATCH_MAT(p->cfg.any_fcr, kb_elem_hess<T, D, FCR><<<gridn(p->elem), elem_threads<T>(), 0, s>>>(
                                         p->items_d, p->ctl_d, p->elem.d, p->nmesh, which));
     p->mark(0, 0);
   }

@@ -4,7 +4,10 @@
 Run mode (under rocprofv3 --pmc): steps the benchmark workload (four 21x6x6
 bars, E = 1e4 .. 1e7, exact bases, batched Jacobi CC, 64 lanes) with one
 iteration per step, so that every condensation launch covers all four bars,
-then copies a buffer of known size (the calibration kernel).
+then copies a buffer of known size (the calibration kernel).  With
+`--workload beam` it steps the 81x21x21 twisted beam instead (R = 1 patch
+basis, float32 local arithmetic, 16 lanes), one iteration per step, for the
+sparse condensation kernel `kb_prep`.
 
 Trace-summary mode: Markdown table of a `rocprofv3 --kernel-trace --stats`
 run of bench.py, with the condensation kernels' average over the last
@@ -22,6 +25,7 @@ hash matches the current source.
     timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/ctr_fetch -o run -- python -u $R/bench_counters.py
     timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/ctr_write -o run -- python -u $R/bench_counters.py
     python $R/bench_counters.py --summarize $OUT/ctr_fetch $OUT/ctr_write > $R/profiles/traffic_kb_prep_dm_bar21x6x6_fp64.md
+    # the same three commands with `--workload beam` after bench_counters.py -> traffic_kb_prep_beam81x21x21_fp32.md
 """
 import argparse
 import csv
@@ -36,13 +40,50 @@ sys.path.insert(0, ROOT)
 
 COPY_BYTES = 512 * 1024 * 1024      # calibration copy: read and written once each
 COPY_REPS = 4
-KERNELS = ("kb_prep_dm", "kb_dm_finish")
+KERNELS = {"bars": ("kb_prep_dm", "kb_dm_finish"), "beam": ("kb_prep<",)}
 SOURCE = os.path.join(ROOT, "paper_2510_12053_amd", "csrc", "cc_kernels.hip")
 
 
 def source_hash():
     with open(SOURCE, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def run_beam(steps):
+    import numpy as np
+    import torch
+    import paper_2510_12053_amd.ccgpu as cg
+    from ccscenes import twist_beam
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(stream)
+    ctx = cg.cc_create(0, stream)
+    s = twist_beam()
+    mid = cg.cc_mesh_upload(ctx, s.X, s.elems, s.fixed, s.E, s.nu, s.rho)
+    cg.cc_subspace_build(ctx, mid, 1, s.dt, False)
+    x, v = s.initial_state()
+    xs, vs = torch.tensor(x, device=dev), torch.tensor(v, device=dev)
+    cg.cc_batch_tuning(ctx, 16, 0)
+    par = cg.cc_params_default(method=cg.METHOD_CC, sweep=cg.SWEEP_JACOBI, precision=cg.FP32_MIXED,
+                               line_search=1, max_iters=1)
+    for t in range(1, steps + 1):
+        cg.cc_step_batch(ctx, [mid], [xs], [vs], [torch.tensor(s.targets(t), device=dev)], s.dt, par,
+                         1e-12, gravity=np.zeros((1, 3)))
+        torch.cuda.synchronize()
+        print(f"step {t} done", flush=True)
+    copy_calibration(dev)
+    cg.cc_destroy(ctx)
+
+
+def copy_calibration(dev):
+    import torch
+    n = COPY_BYTES // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(COPY_REPS):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copy done", flush=True)
 
 
 def run(steps):
@@ -71,17 +112,11 @@ def run(steps):
         cg.cc_step_batch(ctx, mids, xs, vs, bcs, scenes[0].dt, par, 1e-12, gravity=grav)
         torch.cuda.synchronize()
         print(f"step {t} done", flush=True)
-    n = COPY_BYTES // 4
-    a = torch.ones(n, dtype=torch.float32, device=dev)
-    b = torch.empty_like(a)
-    for _ in range(COPY_REPS):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    print("copy done", flush=True)
+    copy_calibration(dev)
     cg.cc_destroy(ctx)
 
 
-def _per_dispatch(folder, counter):
+def _per_dispatch(folder, counter, kernels):
     """{kernel base name: [bytes per dispatch]} from a counter CSV (KiB -> bytes)."""
     out = {}
     files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
@@ -92,7 +127,7 @@ def _per_dispatch(folder, counter):
             continue
         name = row["Kernel_Name"]
         key = None
-        for k in KERNELS:
+        for k in kernels:
             if k in name:
                 key = k
         if key is None and "copy" in name.lower():
@@ -103,14 +138,17 @@ def _per_dispatch(folder, counter):
     return out
 
 
-def summarize(fetch_dir, write_dir):
-    fe = _per_dispatch(fetch_dir, "FETCH_SIZE")
-    wr = _per_dispatch(write_dir, "WRITE_SIZE")
+def summarize(fetch_dir, write_dir, workload):
+    fe = _per_dispatch(fetch_dir, "FETCH_SIZE", KERNELS[workload])
+    wr = _per_dispatch(write_dir, "WRITE_SIZE", KERNELS[workload])
     # the calibration copies are the largest copy dispatches
     cf = sorted(fe.get("copy", []))[-COPY_REPS:]
     cw = sorted(wr.get("copy", []))[-COPY_REPS:]
     sf = COPY_BYTES / (sum(cf) / len(cf))
     sw = COPY_BYTES / (sum(cw) / len(cw))
+    if workload == "beam":
+        summarize_beam(fe, wr, sf, sw, cf, cw)
+        return
     prep_f = fe["kb_prep_dm"]
     fin_f = fe.get("kb_dm_finish", [0.0])
     prep_w = wr["kb_prep_dm"]
@@ -137,6 +175,33 @@ def summarize(fetch_dir, write_dir):
     print("|---|---|---|---|")
     print(f"| kb_prep_dm | {len(prep_f)} | {mean(prep_f) / 1e6:.2f} | {mean(prep_w) / 1e6:.3f} |")
     print(f"| kb_dm_finish | {len(fin_f)} | {mean(fin_f) / 1e6:.3f} | {mean(fin_w) / 1e6:.3f} |")
+    print(f"| copy (calibration) | {len(cf)} | {mean(cf) / 1e6:.1f} | {mean(cw) / 1e6:.1f} |")
+    print(f"\nScaled HBM bytes per launch: fetch {fetch / 1e6:.2f} MB, write {write / 1e6:.3f} MB.\n")
+    print("traffic_json: " + json.dumps(rec))
+
+
+def summarize_beam(fe, wr, sf, sw, cf, cw):
+    mean = lambda v: sum(v) / len(v)
+    pf, pw = fe["kb_prep<"], wr["kb_prep<"]
+    fetch, write = mean(pf) * sf, mean(pw) * sw
+    rec = {"kernel": "kb_prep", "workload": "beam81x21x21_twist", "precision": "fp32",
+           "meshes_per_launch": 1, "fetch_bytes_per_launch": round(fetch),
+           "write_bytes_per_launch": round(write), "fetch_scale": round(sf, 4),
+           "write_scale": round(sw, 4), "dispatches": len(pf), "source_sha256_16": source_hash()}
+    print("# HBM traffic: sparse condensation, 81x21x21 twisted beam, R = 1 basis, float32\n")
+    print("Commands (repo root `$R`, output folder `$OUT`, one MI355X):\n")
+    print("```")
+    print("cd /tmp && export TMPDIR=/tmp")
+    print("timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/ctr_fetch_beam -o run -- python -u $R/bench_counters.py --workload beam")
+    print("timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/ctr_write_beam -o run -- python -u $R/bench_counters.py --workload beam")
+    print("python $R/bench_counters.py --workload beam --summarize $OUT/ctr_fetch_beam $OUT/ctr_write_beam")
+    print("```\n")
+    print("One line-searched Jacobi iteration per step, so every `kb_prep` launch covers the whole "
+          f"beam.  Counters are scaled by the calibration copy of {COPY_BYTES >> 20} MiB "
+          f"(known bytes / counted bytes): FETCH_SIZE x {sf:.4f}, WRITE_SIZE x {sw:.4f}.\n")
+    print("| kernel | dispatches | FETCH_SIZE raw (MB) | WRITE_SIZE raw (MB) |")
+    print("|---|---|---|---|")
+    print(f"| kb_prep<float, 3, 16> | {len(pf)} | {mean(pf) / 1e6:.2f} | {mean(pw) / 1e6:.3f} |")
     print(f"| copy (calibration) | {len(cf)} | {mean(cf) / 1e6:.1f} | {mean(cw) / 1e6:.1f} |")
     print(f"\nScaled HBM bytes per launch: fetch {fetch / 1e6:.2f} MB, write {write / 1e6:.3f} MB.\n")
     print("traffic_json: " + json.dumps(rec))
@@ -189,13 +254,16 @@ def trace_summary(folder, bench_log):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--workload", choices=("bars", "beam"), default="bars")
     ap.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "BENCH_LOG"))
     a = ap.parse_args()
     if a.summarize:
-        summarize(*a.summarize)
+        summarize(*a.summarize, a.workload)
     elif a.trace_summary:
         trace_summary(*a.trace_summary)
+    elif a.workload == "beam":
+        run_beam(a.steps)
     else:
         run(a.steps)
 

@@ -48,6 +48,9 @@ struct MeshView {
   int smap_supp;         // longest support row of the slot-mapped basis
   // corotation: per free vertex rotation R_j (row-major D*D), or null = off
   const double* rot;
+  // free internal ids in caller order (spatially coherent on the structured
+  // grids): the order in which a whole-mesh Jacobi condensation visits them
+  const int* sorder;
 };
 
 constexpr int SMAP_SELF = 254;

@@ -244,6 +244,21 @@ __global__ void __launch_bounds__(WG) k_gradient(MeshView mv, const double* __re
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
+// Vertex of thread slot idx in [0, v1 - v0): a whole-mesh sweep visits the
+// free vertices in caller order, so neighbouring slots share rows of H (the
+// colour-sorted internal order scatters them over the mesh); a colour sweep
+// takes its colour's range.
+__device__ __forceinline__ int sweep_vertex(const MeshView& mv, int v0, int v1, int idx) {
+  return (v0 == 0 && v1 == mv.nf && mv.sorder) ? mv.sorder[idx] : v0 + idx;
+}
+
+// Workgroups are dealt to the 8 XCDs in turn; renumber block b of nb so that
+// the blocks one XCD runs cover a contiguous range (one L2 per XCD).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb / 8, r = nb % 8, x = b % 8, k = b / 8;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 // Generic condensation kernel: G lanes per vertex, basis and support from
 // global memory.  The support position of a neighbour comes from the slot map
 // when the mesh has one, else from a binary search in the support row.
@@ -409,9 +424,10 @@ __global__ void __launch_bounds__(WG) k_cc_prep(MeshView mv, int method, int v0,
                                                 const T* __restrict__ hb, T* __restrict__ KL,
                                                 unsigned long long* __restrict__ fb, int cap) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int i = v0 + blockIdx.x * (WG / G) + threadIdx.x / G;
-  prep_body<T, D, G>(mv, method, i, i < v1, threadIdx.x % G, hb, KL, fb,
-                     cap > 0 ? reinterpret_cast<T*>(smem_raw) : nullptr, cap);
+  const int idx = xcd_block(blockIdx.x, gridDim.x) * (WG / G) + threadIdx.x / G;
+  const bool act = idx < v1 - v0;
+  prep_body<T, D, G>(mv, method, act ? sweep_vertex(mv, v0, v1, idx) : v0, act, threadIdx.x % G, hb, KL,
+                     fb, cap > 0 ? reinterpret_cast<T*>(smem_raw) : nullptr, cap);
 }
 
 // Exact-basis condensation of TV vertices per workgroup.  Each vertex's
@@ -1397,9 +1413,10 @@ __global__ void __launch_bounds__(WG) kb_prep(const BatchItem* __restrict__ item
   const BatchItem& it = items[mi];
   int v0, v1;
   vertex_range(it, colour, v0, v1);
-  const int lb = blockIdx.x - boff[mi];
-  const int i = v0 + lb * (WG / G) + threadIdx.x / G;
-  prep_body<T, D, G>(it.mv, method, i, i < v1, threadIdx.x % G, (const T*)it.hb, (T*)it.KL, it.fb,
+  const int idx = xcd_block(blockIdx.x - boff[mi], boff[mi + 1] - boff[mi]) * (WG / G) + threadIdx.x / G;
+  const bool act = idx < v1 - v0;
+  prep_body<T, D, G>(it.mv, method, act ? sweep_vertex(it.mv, v0, v1, idx) : v0, act, threadIdx.x % G,
+                     (const T*)it.hb, (T*)it.KL, it.fb,
                      cap > 0 ? reinterpret_cast<T*>(smem_raw) : nullptr, cap);
 }
 

@@ -40,7 +40,9 @@ sys.path.insert(0, ROOT)
 
 COPY_BYTES = 512 * 1024 * 1024      # calibration copy: read and written once each
 COPY_REPS = 4
-KERNELS = {"bars": ("kb_prep_dm", "kb_dm_finish"), "beam": ("kb_prep<",)}
+KERNELS = {"bars": ("kb_prep_dm", "kb_dm_finish"),
+           "beam": ("kb_prep<", "kb_elem_hess<", "kb_assemble<", "kb_update<", "kb_gradient<",
+                    "kb_energy_grad<")}
 SOURCE = os.path.join(ROOT, "paper_2510_12053_amd", "csrc", "cc_kernels.hip")
 
 
@@ -199,10 +201,13 @@ def summarize_beam(fe, wr, sf, sw, cf, cw):
     print("One line-searched Jacobi iteration per step, so every `kb_prep` launch covers the whole "
           f"beam.  Counters are scaled by the calibration copy of {COPY_BYTES >> 20} MiB "
           f"(known bytes / counted bytes): FETCH_SIZE x {sf:.4f}, WRITE_SIZE x {sw:.4f}.\n")
-    print("| kernel | dispatches | FETCH_SIZE raw (MB) | WRITE_SIZE raw (MB) |")
-    print("|---|---|---|---|")
-    print(f"| kb_prep<float, 3, 16> | {len(pf)} | {mean(pf) / 1e6:.2f} | {mean(pw) / 1e6:.3f} |")
-    print(f"| copy (calibration) | {len(cf)} | {mean(cf) / 1e6:.1f} | {mean(cw) / 1e6:.1f} |")
+    print("| kernel | dispatches | FETCH_SIZE raw (MB) | WRITE_SIZE raw (MB) | scaled fetch + write (MB) |")
+    print("|---|---|---|---|---|")
+    for k in KERNELS["beam"]:
+        if k in fe and k in wr:
+            print(f"| {k.rstrip('<')} | {len(fe[k])} | {mean(fe[k]) / 1e6:.2f} | {mean(wr[k]) / 1e6:.3f} | "
+                  f"{(mean(fe[k]) * sf + mean(wr[k]) * sw) / 1e6:.2f} |")
+    print(f"| copy (calibration) | {len(cf)} | {mean(cf) / 1e6:.1f} | {mean(cw) / 1e6:.1f} | |")
     print(f"\nScaled HBM bytes per launch: fetch {fetch / 1e6:.2f} MB, write {write / 1e6:.3f} MB.\n")
     print("traffic_json: " + json.dumps(rec))
 

@@ -33,7 +33,7 @@ struct Mesh {
   // device: static mesh data
   int *ev = nullptr, *star_ptr = nullptr, *star = nullptr, *d_rowptr = nullptr, *d_colidx = nullptr,
       *blkrow = nullptr, *cptr = nullptr, *centry = nullptr, *d_vperm = nullptr, *d_vinv = nullptr,
-      *d_eperm = nullptr, *d_sorder = nullptr;
+      *d_eperm = nullptr, *d_sorder = nullptr, *d_aorder = nullptr;
   int4* seg = nullptr;  // upper-triangle block segments of the dense condensation
   int nseg = 0;
 
@@ -78,6 +78,7 @@ struct Mesh {
     v.sptr = sptr; v.sidx = sidx; v.U_d = U_d; v.U_f = U_f; v.dense_supp = dense;
     v.smap = smap; v.smap_words = smap_words; v.smap_supp = smap_supp;
     v.sorder = d_sorder;
+    v.aorder = d_aorder;
     return v;
   }
 };
@@ -131,7 +132,7 @@ void free_mesh(Mesh& M) {
   dfree(M.ev); dfree(M.star_ptr); dfree(M.star); dfree(M.d_rowptr); dfree(M.d_colidx);
   dfree(M.blkrow); dfree(M.cptr); dfree(M.centry); dfree(M.d_vperm); dfree(M.d_vinv);
   dfree(M.seg);
-  dfree(M.d_eperm); dfree(M.d_sorder); dfree(M.dinv_d); dfree(M.vol_d); dfree(M.mass); dfree(M.dinv_f); dfree(M.vol_f);
+  dfree(M.d_eperm); dfree(M.d_sorder); dfree(M.d_aorder); dfree(M.dinv_d); dfree(M.vol_d); dfree(M.mass); dfree(M.dinv_f); dfree(M.vol_f);
   free_basis(M);
   dfree(M.x); dfree(M.xt); dfree(M.x0); dfree(M.xtrial); dfree(M.dvec); dfree(M.g);
   dfree(M.partials); dfree(M.scal); dfree(M.estore); dfree(M.hb); dfree(M.KL); dfree(M.fb);
@@ -450,6 +451,11 @@ void build_mesh(cc_ctx* ctx, Mesh& M) {
     for (int u = 0; u < n; ++u)
       if (M.vinv[u] < nf) so.push_back(M.vinv[u]);
     M.d_sorder = dupload(so, s);
+    std::vector<int> ao;
+    ao.reserve(M.nnzb);
+    for (int j : so)
+      for (int t = M.rowptr[j]; t < M.rowptr[j + 1]; ++t) ao.push_back(t);
+    M.d_aorder = dupload(ao, s);
   }
   M.d_eperm = dupload(M.eperm, s);
   {  // warm-start data: all neighbours, rest positions, mean rest edge length

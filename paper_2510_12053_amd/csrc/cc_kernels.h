@@ -51,6 +51,8 @@ struct MeshView {
   // free internal ids in caller order (spatially coherent on the structured
   // grids): the order in which a whole-mesh Jacobi condensation visits them
   const int* sorder;
+  // block-row slots row by row in that order: the order assembly visits them
+  const int* aorder;
 };
 
 constexpr int SMAP_SELF = 254;

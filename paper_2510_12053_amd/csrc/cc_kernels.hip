@@ -123,10 +123,13 @@ __global__ void __launch_bounds__(elem_threads<T>()) k_elem_hess(MeshView mv, co
 // Block rows: every slot sums its element contributions (fixed order), plus
 // the mass on the diagonal.
 template <typename T, int D>
-__device__ __forceinline__ void assemble_body(const MeshView& mv, int t, const T* __restrict__ est,
+__device__ __forceinline__ void assemble_body(const MeshView& mv, int tt, const T* __restrict__ est,
                                               T w_in, T* __restrict__ hb) {
   constexpr int K = D + 1, DD = D * D;
-  if (t >= mv.nnzb) return;
+  if (tt >= mv.nnzb) return;
+  // slots row by row in caller order of the rows: neighbouring threads then
+  // read the blocks of neighbouring elements
+  const int t = mv.aorder ? mv.aorder[tt] : tt;
   T acc[DD];
 #pragma unroll
   for (int r = 0; r < DD; ++r) acc[r] = T(0);

@@ -190,6 +190,13 @@ __global__ void __launch_bounds__(EWG) k_assemble(MeshView mv, const T* __restri
   assemble_body<T, D>(mv, blockIdx.x * EWG + threadIdx.x, est, w_in, hb);
 }
 
+// Vertex of gradient slot idx: the free vertices in caller order, so that
+// neighbouring lane groups walk overlapping element stars (nf: no vertex).
+__device__ __forceinline__ int grad_vertex(const MeshView& mv, int idx) {
+  if (idx >= mv.nf) return mv.nf;
+  return mv.sorder ? mv.sorder[idx] : idx;
+}
+
 // Free-vertex gradient in float64: G lanes per vertex share its star.
 // Returns g_j . g_j on the group's first lane, 0 elsewhere.
 template <int D, int G, bool FCR>
@@ -241,7 +248,7 @@ __global__ void __launch_bounds__(WG) k_gradient(MeshView mv, const double* __re
                                                  double* __restrict__ g,
                                                  double* __restrict__ partials) {
   __shared__ double red[WG];
-  const double gsq = gradient_body<D, G, FCR>(mv, blockIdx.x * (WG / G) + threadIdx.x / G,
+  const double gsq = gradient_body<D, G, FCR>(mv, grad_vertex(mv, blockIdx.x * (WG / G) + threadIdx.x / G),
                                          threadIdx.x % G, x, xt, mat, g);
   const double tot = block_sum<WG>(gsq, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
@@ -1399,7 +1406,7 @@ __global__ void __launch_bounds__(WG) kb_gradient(const BatchItem* __restrict__ 
   const BatchItem& it = items[mi];
   const MeshView mv = it.mv;
   const int lb = blockIdx.x - boff[mi];
-  const double gsq = gradient_body<D, G, FCR>(mv, lb * (WG / G) + threadIdx.x / G, threadIdx.x % G,
+  const double gsq = gradient_body<D, G, FCR>(mv, grad_vertex(mv, lb * (WG / G) + threadIdx.x / G), threadIdx.x % G,
                                          pick(it, which), it.xt, it.mat, it.g);
   const double tot = block_sum<WG>(gsq, red);
   if (threadIdx.x == 0) it.partials[lb] = tot;
@@ -1508,7 +1515,7 @@ __global__ void __launch_bounds__(WG) kb_energy_grad(const BatchItem* __restrict
   if (lb < ne)
     v = energy_body<D, FCR>(mv, lb, nbe, it.xtrial, it.xt, it.mat);
   else
-    v = gradient_body<D, GRAD_G, FCR>(mv, (lb - ne) * (WG / GRAD_G) + threadIdx.x / GRAD_G,
+    v = gradient_body<D, GRAD_G, FCR>(mv, grad_vertex(mv, (lb - ne) * (WG / GRAD_G) + threadIdx.x / GRAD_G),
                                       threadIdx.x % GRAD_G, it.xtrial, it.xt, it.mat, it.g);
   const double tot = block_sum<WG>(v, red);
   if (threadIdx.x == 0) it.partials[lb] = tot;

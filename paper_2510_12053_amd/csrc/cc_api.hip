@@ -1605,19 +1605,24 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
           cc::batch_gradient_converge(plan, s);
           pull_ctl();
         }
-        // exhausted halvings: the coordinate-descent fallback on the host
-        HIPC(hipMemcpyAsync(items.data(), items_d, n * sizeof(cc::BatchItem), hipMemcpyDeviceToHost, s));
-        HIPC(hipStreamSynchronize(s));
+        // exhausted halvings: the coordinate-descent fallback on the host,
+        // which needs the meshes' current buffer roles from the device
+        bool any_cd = false;
+        for (int i = 0; i < n; ++i) any_cd = any_cd || (ctl[i].needs_host && ctl[i].ls == 2);
+        if (any_cd) {
+          HIPC(hipMemcpyAsync(items.data(), items_d, n * sizeof(cc::BatchItem), hipMemcpyDeviceToHost, s));
+          HIPC(hipStreamSynchronize(s));
+        }
         for (int i = 0; i < n; ++i) {
           if (ctl[i].needs_host && ctl[i].ls == 2) {
             batch_host_cd_fallback(ctx, *ms[i], items[i], ctl[i], p, tol);
             HIPC(hipMemcpyAsync(items_d + i, &items[i], sizeof(cc::BatchItem), hipMemcpyHostToDevice, s));
+            HIPC(hipStreamSynchronize(s));   // items[i] is pageable host memory
           }
           if (!ctl[i].needs_host) ctl[i].active = was_active[i];
           ctl[i].needs_host = 0;
         }
-        push_ctl();
-        HIPC(hipStreamSynchronize(s));
+        push_ctl();   // stream-ordered before the next replay and read-back
       }
       if (++guard > (long long)p.max_iters + 16) break;  // every replay advances every active mesh
     }

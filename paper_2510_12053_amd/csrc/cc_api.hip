@@ -188,6 +188,10 @@ struct cc_ctx {
   // host check (finished meshes are masked on the device, so extra queued
   // iterations cost only their launches)
   int plan_prev_iters = 0;
+  // most iterations of the previous step of this plan backtracked: they end
+  // at the host, so queueing more than one replay ahead only runs masked
+  // launches
+  bool plan_prev_ls = false;
   std::vector<double> plan_key;
 
   hipEvent_t take_event() {
@@ -1409,6 +1413,7 @@ static cc::BatchPlan* batch_plan_for(cc_ctx* ctx, const std::vector<Mesh*>& ms, 
   ctx->plan = cc::batch_plan_create(items.data(), n, cfg, ctx->stream);
   ctx->plan_ids = idv;
   ctx->plan_prev_iters = 0;
+  ctx->plan_prev_ls = false;
   ctx->plan_key = key;
   return ctx->plan;
 }
@@ -1536,7 +1541,8 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
     // round reports them.
     for (auto& c : ctl) c.active = 1;
     long long guard = 0;
-    int queue = std::min(std::max(ctx->plan_prev_iters, k), 16);   // first round
+    int queue = ctx->plan_prev_ls ? k : std::min(std::max(ctx->plan_prev_iters, k), 16);   // first round
+    int backtracks = 0;
     bool first = true;
     while (true) {
       bool any = false;
@@ -1567,6 +1573,7 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
       bool host = false;
       for (auto& c : ctl) host = host || c.needs_host;
       if (host) {
+        ++backtracks;
         // Meshes whose energy rose at the full step backtrack together: a
         // round evaluates the next eight halvings of every searching mesh at
         // once and takes the first that does not raise E.  Two rounds are
@@ -1629,6 +1636,7 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
     cc::batch_finish(plan, s);
     ctx->plan_prev_iters = 0;
     for (auto& c : ctl) ctx->plan_prev_iters = std::max(ctx->plan_prev_iters, c.iters);
+    ctx->plan_prev_ls = 2 * backtracks >= std::max(ctx->plan_prev_iters, 1);
     HIPC(hipMemcpyAsync(items.data(), items_d, n * sizeof(cc::BatchItem), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     ctx->harvest();

@@ -150,11 +150,14 @@ cc_status cc_subspace_upload(cc_ctx* ctx, int32_t mesh_id, const int64_t* ptr,
    (M + h^2 K(X), or K(X) when quasistatic):
    radius > 0: patch basis, support = free vertices within `radius` hops,
                everything outside the patch held, U_i = -H[C,C]^{-1} H[C,i];
-   radius = 0: exact basis over every other free vertex, from the dense
-               inverse Z = H^{-1} computed on the GPU (blocked Gauss-Jordan,
-               float64) as U_i[j] = Z_ji Z_ii^{-1}; needs (n_free dim)^2
-               doubles of temporary device memory and stores
-               n_free (n_free - 1) blocks in float64 and float32.
+   radius = 0: exact basis over every other free vertex, U_i[j] =
+               Z_ji Z_ii^{-1} with Z = H^{-1}, formed on the GPU in float64
+               column block by column block from the block-tridiagonal
+               factorisation of H in breadth-first level order (levels of
+               n unknowns: O(N^2 n) work and O(N n) temporary memory for N
+               free unknowns).  Stores n_free^2 blocks in float32, plus a
+               float64 copy when that takes at most 4 GiB (larger bases
+               then step in CC_FP32_MIXED only; CC_FP64 gives CC_E_STATE).
    The rest Hessian is evaluated by the library's own GPU kernels in FP64;
    the patch solves run on the host. */
 cc_status cc_subspace_build(cc_ctx* ctx, int32_t mesh_id, int32_t radius, double dt,
@@ -174,6 +177,12 @@ cc_status cc_subspace_build_at(cc_ctx* ctx, int32_t mesh_id, const double* x, in
 cc_status cc_subspace_nnz(cc_ctx* ctx, int32_t mesh_id, int64_t* nnz);
 cc_status cc_subspace_download(cc_ctx* ctx, int32_t mesh_id, int64_t* ptr, int32_t* idx,
                                double* U);
+/* One basis row in the upload format: the row of caller vertex `vertex`
+   (*len entries, caller ids ascending in idx, blocks in U as float64; a basis
+   kept in float32 only is widened).  idx and U must hold n_free - 1 entries
+   for an exact basis; any output may be NULL.  Dirichlet rows are empty. */
+cc_status cc_subspace_row(cc_ctx* ctx, int32_t mesh_id, int32_t vertex, int64_t* len, int32_t* idx,
+                          double* U);
 
 /* One implicit time step of mesh `mesh_id`.
    x, v: device (n_verts x dim) float64, read as x^t, v^t and overwritten with

@@ -69,6 +69,7 @@ def lib():
             "cc_subspace_build_at": (I32, [P, I32, P, I32, D, I32]),
             "cc_subspace_nnz": (I32, [P, I32, pI64]),
             "cc_subspace_download": (I32, [P, I32, P, P, P]),
+            "cc_subspace_row": (I32, [P, I32, I32, pI64, P, P]),
             "cc_step": (I32, [P, I32, P, P, P, D, ctypes.POINTER(cc_params), D, pI32, pD]),
             "cc_step_info": (I32, [P, I32, pD, pD, P, pI64, pI32]),
             "cc_probe_element": (I32, [P, I32, P, I32, P, P]),
@@ -208,6 +209,15 @@ def cc_subspace_download(ctx, mesh_id, n_verts, dim):
     U = np.empty((nnz.value, dim, dim), dtype=np.float64)
     _check(ctx, lib().cc_subspace_download(ctx.handle, mesh_id, _ptr(ptr), _ptr(idx), _ptr(U)))
     return ptr, idx, U
+
+
+def cc_subspace_row(ctx, mesh_id, vertex, n_free, dim):
+    """Basis row of caller vertex `vertex`: (idx (caller ids, ascending), U (len, dim, dim))."""
+    ln = ctypes.c_int64(0)
+    idx = np.empty(max(n_free - 1, 1), dtype=np.int32)
+    U = np.empty((max(n_free - 1, 1), dim, dim), dtype=np.float64)
+    _check(ctx, lib().cc_subspace_row(ctx.handle, mesh_id, vertex, ctypes.byref(ln), _ptr(idx), _ptr(U)))
+    return idx[:ln.value].copy(), U[:ln.value].copy()
 
 
 def cc_step(ctx, mesh_id, x, v, x_bc, dt, params, tol):

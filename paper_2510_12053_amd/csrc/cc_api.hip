@@ -34,8 +34,13 @@ struct Mesh {
   int *ev = nullptr, *star_ptr = nullptr, *star = nullptr, *d_rowptr = nullptr, *d_colidx = nullptr,
       *blkrow = nullptr, *cptr = nullptr, *centry = nullptr, *d_vperm = nullptr, *d_vinv = nullptr,
       *d_eperm = nullptr, *d_sorder = nullptr, *d_aorder = nullptr;
-  int4* seg = nullptr;  // upper-triangle block segments of the dense condensation
-  int nseg = 0;
+  // band order of the free vertices and the upper-block structure of the
+  // dense condensation (MeshView::bvert ...); lev_off: breadth-first levels
+  // in band positions (every block couples the same or adjacent levels)
+  std::vector<int> bvert_h, bpos_h, lev_off;
+  int *d_bvert = nullptr, *d_bpos = nullptr, *d_bqcnt = nullptr, *d_bqpos = nullptr, *d_hqslot = nullptr;
+  void* hq = nullptr;
+  int qmax = 0, band_w = 0;
 
   double *dinv_d = nullptr, *vol_d = nullptr, *mass = nullptr;
   float *dinv_f = nullptr, *vol_f = nullptr;
@@ -74,7 +79,9 @@ struct Mesh {
     v.ev = ev; v.dinv_d = dinv_d; v.dinv_f = dinv_f; v.vol_d = vol_d; v.vol_f = vol_f;
     v.mass = mass; v.vperm = d_vperm; v.star_ptr = star_ptr; v.star = star; v.rowptr = d_rowptr;
     v.colidx = d_colidx; v.blkrow = blkrow; v.cptr = cptr; v.centry = centry; v.nnzb = nnzb;
-    v.seg = seg; v.nseg = nseg;
+    v.bvert = d_bvert; v.bpos = d_bpos; v.bq_cnt = d_bqcnt; v.bq_pos = d_bqpos; v.hq_slot = d_hqslot;
+    v.hq = dense ? hq : nullptr;   // the assembly writes the band copy only for dense bases
+    v.qmax = qmax; v.band_w = band_w; v.ring = cc::band_ring(nf, band_w);
     v.sptr = sptr; v.sidx = sidx; v.U_d = U_d; v.U_f = U_f; v.dense_supp = dense;
     v.smap = smap; v.smap_words = smap_words; v.smap_supp = smap_supp;
     v.sorder = d_sorder;
@@ -98,6 +105,12 @@ struct ApiError {
   cc_status code;
   std::string msg;
 };
+
+// Exact bases keep a float64 copy (for CC_FP64 steps) while it takes at most
+// this many bytes; larger ones are stored in float32 only.
+constexpr size_t DENSE_F64_MAX_BYTES = size_t(4) << 30;
+// Unknowns per level of the block-tridiagonal exact-basis build.
+constexpr int LEVEL_DOFS = 768;
 
 template <typename T>
 T* dalloc(size_t count) {
@@ -125,13 +138,14 @@ void free_basis(Mesh& M) {
   M.smap_words = 0;
   M.smap_supp = 0;
   M.has_basis = false;
+  M.dense = 0;
   M.snnz = 0;
 }
 
 void free_mesh(Mesh& M) {
   dfree(M.ev); dfree(M.star_ptr); dfree(M.star); dfree(M.d_rowptr); dfree(M.d_colidx);
   dfree(M.blkrow); dfree(M.cptr); dfree(M.centry); dfree(M.d_vperm); dfree(M.d_vinv);
-  dfree(M.seg);
+  dfree(M.d_bvert); dfree(M.d_bpos); dfree(M.d_bqcnt); dfree(M.d_bqpos); dfree(M.d_hqslot); dfree(M.hq);
   dfree(M.d_eperm); dfree(M.d_sorder); dfree(M.d_aorder); dfree(M.dinv_d); dfree(M.vol_d); dfree(M.mass); dfree(M.dinv_f); dfree(M.vol_f);
   free_basis(M);
   dfree(M.x); dfree(M.xt); dfree(M.x0); dfree(M.xtrial); dfree(M.dvec); dfree(M.g);
@@ -268,6 +282,64 @@ bool invert(int D, const double* A, double* Ainv, double& det) {
   Ainv[3] = (f * g - d * i) / det; Ainv[4] = (a * i - c * g) / det; Ainv[5] = (c * d - a * f) / det;
   Ainv[6] = (d * h - e * g) / det; Ainv[7] = (b * g - a * h) / det; Ainv[8] = (a * e - b * d) / det;
   return true;
+}
+
+// Band order of the free vertices: breadth-first search over the free-vertex
+// graph (edge iff two free vertices share an element) from the free vertices
+// that share an element with a Dirichlet vertex, in caller-id order; the
+// unvisited neighbours of each visited vertex are appended in caller-id
+// order (a Cuthill-McKee order without the degree key, which keeps the
+// structured grids' slabs in lexicographic order).  A component with no
+// Dirichlet contact starts from its smallest caller id.  Levels are the
+// breadth-first distances, so every edge joins the same or adjacent levels.
+void build_band(Mesh& M) {
+  const int nf = M.nf, n = M.n;
+  std::vector<int> adj_fixed(nf, 0);
+  for (int e = 0; e < M.m; ++e) {
+    bool anyfix = false;
+    for (int a = 0; a < M.K; ++a) anyfix |= M.fixed[M.elems[e * M.K + a]] != 0;
+    if (!anyfix) continue;
+    for (int a = 0; a < M.K; ++a) {
+      const int v = M.elems[e * M.K + a];
+      if (!M.fixed[v]) adj_fixed[M.vinv[v]] = 1;
+    }
+  }
+  std::vector<int> lev(nf, -1), order;
+  order.reserve(nf);
+  M.lev_off.assign(1, 0);
+  int level_base = 0;
+  auto bfs = [&](std::vector<int> starts) {
+    std::sort(starts.begin(), starts.end(), [&](int a, int b) { return M.vperm[a] < M.vperm[b]; });
+    size_t head = order.size();
+    for (int v : starts) { lev[v] = level_base; order.push_back(v); }
+    std::vector<int> nb;
+    int top = level_base;
+    while (head < order.size()) {
+      const int u = order[head++];
+      nb.clear();
+      for (int t = M.rowptr[u] + 1; t < M.rowptr[u + 1]; ++t)
+        if (lev[M.colidx[t]] < 0) nb.push_back(M.colidx[t]);
+      std::sort(nb.begin(), nb.end(), [&](int a, int b) { return M.vperm[a] < M.vperm[b]; });
+      for (int w : nb) { lev[w] = lev[u] + 1; top = std::max(top, lev[w]); order.push_back(w); }
+    }
+    level_base = top + 1;
+  };
+  std::vector<int> starts;
+  for (int j = 0; j < nf; ++j)
+    if (adj_fixed[j]) starts.push_back(j);
+  if (!starts.empty()) bfs(starts);
+  while ((int)order.size() < nf) {
+    int best = -1;
+    for (int j = 0; j < nf; ++j)
+      if (lev[j] < 0 && (best < 0 || M.vperm[j] < M.vperm[best])) best = j;
+    bfs({best});
+  }
+  M.bvert_h = order;
+  M.bpos_h.assign(nf, 0);
+  for (int p = 0; p < nf; ++p) M.bpos_h[order[p]] = p;
+  for (int p = 1; p <= nf; ++p)
+    if (p == nf || lev[order[p]] != lev[order[p - 1]]) M.lev_off.push_back(p);
+  (void)n;
 }
 
 void build_mesh(cc_ctx* ctx, Mesh& M) {
@@ -425,25 +497,39 @@ void build_mesh(cc_ctx* ctx, Mesh& M) {
   M.d_rowptr = dupload(M.rowptr, s);
   M.d_colidx = dupload(M.colidx, s);
   M.blkrow = dupload(blkrow, s);
-  if (nf <= 65535) {  // blocks j <= k of the symmetric block matrix in row segments
-    std::vector<int4> seg;
-    for (int j = 0; j < nf; ++j) {
-      std::vector<int> slots;
-      for (int t = M.rowptr[j]; t < M.rowptr[j + 1]; ++t)
-        if (M.colidx[t] >= j) slots.push_back(t);
-      for (size_t q0 = 0; q0 < slots.size(); q0 += cc::SEG_LEN) {
-        int sl[cc::SEG_LEN], kk[cc::SEG_LEN];
-        const int cnt = (int)std::min<size_t>(cc::SEG_LEN, slots.size() - q0);
-        for (int q = 0; q < cc::SEG_LEN; ++q) {
-          sl[q] = q < cnt ? slots[q0 + q] : slots[q0];
-          kk[q] = M.colidx[sl[q]];
-        }
-        seg.push_back(make_int4(j, cnt, sl[0], sl[1]));
-        seg.push_back(make_int4(sl[2], sl[3], kk[0] | (kk[1] << 16), kk[2] | (kk[3] << 16)));
+  build_band(M);
+  M.d_bvert = dupload(M.bvert_h, s);
+  M.d_bpos = dupload(M.bpos_h, s);
+  {
+    // upper blocks of every band row: the diagonal first, then by band position
+    std::vector<int> cnt(nf, 0), hslot(M.nnzb, -1);
+    std::vector<std::vector<std::pair<int, int>>> up(nf);
+    M.qmax = 0;
+    M.band_w = 0;
+    for (int p = 0; p < nf; ++p) {
+      const int j = M.bvert_h[p];
+      for (int t = M.rowptr[j]; t < M.rowptr[j + 1]; ++t) {
+        const int pk = M.bpos_h[M.colidx[t]];
+        if (pk >= p) up[p].push_back({pk, t});
       }
+      std::sort(up[p].begin(), up[p].end());
+      cnt[p] = (int)up[p].size();
+      M.qmax = std::max(M.qmax, cnt[p]);
+      if (!up[p].empty()) M.band_w = std::max(M.band_w, up[p].back().first - p);
     }
-    M.nseg = (int)seg.size() / 2;
-    M.seg = dupload(seg, s);
+    std::vector<int> qpos((size_t)M.qmax * nf);
+    for (int p = 0; p < nf; ++p)
+      for (int q = 0; q < M.qmax; ++q) {
+        const bool in = q < cnt[p];
+        qpos[(size_t)q * nf + p] = in ? up[p][q].first : p;
+        if (in) hslot[up[p][q].second] = q * nf + p;
+      }
+    M.d_bqcnt = dupload(cnt, s);
+    M.d_bqpos = dupload(qpos, s);
+    M.d_hqslot = dupload(hslot, s);
+    const size_t hqn = (size_t)std::max(M.qmax, 1) * D * D * std::max(nf, 1);
+    M.hq = dalloc<double>(hqn);
+    HIPC(hipMemsetAsync(M.hq, 0, hqn * sizeof(double), s));   // padding blocks stay zero
   }
   M.cptr = dupload(cptr, s);
   M.centry = dupload(centry, s);
@@ -609,14 +695,28 @@ void upload_basis(cc_ctx* ctx, Mesh& M, const int64_t* ptr, const int32_t* idx, 
   }
   free_basis(M);
   hipStream_t s = ctx->stream;
-  M.sptr = dupload(sptr, s);
-  M.sidx = dupload(sidx, s);
-  M.U_d = dupload(Ud, s);
-  std::vector<float> Uf(Ud.begin(), Ud.end());
-  M.U_f = dupload(Uf, s);
-  M.dense = dense ? 1 : 0;
+  if (dense && nf > 1) {
+    // every row holds every other free vertex: the band layout of the exact
+    // basis (nf blocks per row, columns by band position, own block zero)
+    const size_t blocks = (size_t)nf * nf;
+    std::vector<double> band(blocks * DD, 0.0);
+    for (int i = 0; i < nf; ++i)
+      for (int64_t q = sptr[i]; q < sptr[i + 1]; ++q)
+        std::memcpy(&band[((size_t)i * nf + M.bpos_h[sidx[q]]) * DD], &Ud[(size_t)q * DD], DD * sizeof(double));
+    if (blocks * DD * sizeof(double) <= DENSE_F64_MAX_BYTES) M.U_d = dupload(band, s);
+    std::vector<float> Uf(band.begin(), band.end());
+    M.U_f = dupload(Uf, s);
+    M.dense = 1;
+  } else {
+    M.sptr = dupload(sptr, s);
+    M.sidx = dupload(sidx, s);
+    M.U_d = dupload(Ud, s);
+    std::vector<float> Uf(Ud.begin(), Ud.end());
+    M.U_f = dupload(Uf, s);
+    M.dense = 0;
+    build_slot_map(M, sptr, sidx, s);
+  }
   M.snnz = nnz;
-  if (!dense) build_slot_map(M, sptr, sidx, s);
 
   HIPC(hipStreamSynchronize(s));
   M.has_basis = true;
@@ -677,43 +777,35 @@ void build_basis(cc_ctx* ctx, Mesh& M, int radius, double dt, int quasi, const d
   MeshView mv = M.view();
   cc::launch_elem_hess(mv, 0, M.x, mat, mat.s_el, M.estore, s);
   cc::launch_assemble(mv, 0, M.estore, mat, M.hb, s);
-  if (radius == 0) {  // exact basis: dense inverse of the rest Hessian on the GPU
-    const size_t N = (size_t)nf * D;
-    const size_t nnz = (size_t)nf * (nf > 0 ? nf - 1 : 0);
-    double* A = dalloc<double>(N * N);
-    double* work = dalloc<double>(N * 64 + 64 * 64);
-    int* badf = dalloc<int>(1);
+  if (radius == 0) {  // exact basis from the block-tridiagonal factorisation of H (band order)
+    const size_t blocks = (size_t)nf * nf;
+    // breadth-first levels merged until each holds at least LEVEL_DOFS unknowns
+    // (fewer, larger products; merged levels still couple only neighbours)
+    std::vector<int> loff{0};
+    for (size_t t = 1; t < M.lev_off.size(); ++t) {
+      const int b = M.lev_off[t];
+      if ((b - loff.back()) * D >= LEVEL_DOFS || b == nf) loff.push_back(b);
+    }
     double* Ud = nullptr;
     float* Uf = nullptr;
-    bool ok = false;
     try {
-      Ud = dalloc<double>(nnz * DD);
-      Uf = dalloc<float>(nnz * DD);
-      ok = cc::exact_basis_gpu(mv, (const double*)M.hb, A, work, badf, Ud, Uf, s);
+      Uf = dalloc<float>(blocks * DD);
+      if (blocks * DD * sizeof(double) <= DENSE_F64_MAX_BYTES) Ud = dalloc<double>(blocks * DD);
     } catch (...) {
-      dfree(A); dfree(work); dfree(badf); dfree(Ud); dfree(Uf);
+      dfree(Ud); dfree(Uf);
       throw;
     }
-    dfree(A); dfree(work); dfree(badf);
-    if (!ok) {
+    const int rc = cc::exact_basis_band(mv, (const double*)M.hb, loff.data(), (int)loff.size() - 1, Ud, Uf, s);
+    if (rc != 0) {
       dfree(Ud); dfree(Uf);
-      throw ApiError{CC_E_SUBSPACE, "step Hessian not positive definite"};
-    }
-    std::vector<int64_t> sptr(nf + 1);
-    for (int i = 0; i <= nf; ++i) sptr[i] = (int64_t)i * (nf > 0 ? nf - 1 : 0);
-    std::vector<int> sidx(nnz);
-    for (int i = 0; i < nf; ++i) {
-      size_t q = (size_t)i * (nf - 1);
-      for (int j = 0; j < nf; ++j)
-        if (j != i) sidx[q++] = j;
+      if (rc == 1) throw ApiError{CC_E_SUBSPACE, "step Hessian not positive definite"};
+      throw ApiError{CC_E_HIP, "exact basis: out of device memory or a failed launch"};
     }
     free_basis(M);
-    M.sptr = dupload(sptr, s);
-    M.sidx = dupload(sidx, s);
     M.U_d = Ud;
     M.U_f = Uf;
     M.dense = 1;
-    M.snnz = (int64_t)nnz;
+    M.snnz = (int64_t)nf * (nf > 0 ? nf - 1 : 0);
     HIPC(hipStreamSynchronize(s));
     M.has_basis = true;
     return;
@@ -1093,34 +1185,98 @@ cc_status cc_subspace_nnz(cc_ctx* ctx, int32_t mesh_id, int64_t* nnz) {
   });
 }
 
+}  // extern "C"
+
+namespace {
+// Basis row of internal vertex i in the caller format: caller ids ascending
+// and their blocks (float64; a dense basis kept in float32 only is widened).
+void basis_row(cc_ctx* ctx, Mesh& M, int i, std::vector<std::pair<int, int64_t>>& row,
+               std::vector<double>& blocks) {
+  const int DD = M.D * M.D, nf = M.nf;
+  hipStream_t s = ctx->stream;
+  row.clear();
+  if (M.dense) {
+    blocks.assign((size_t)nf * DD, 0.0);
+    if (M.U_d) {
+      HIPC(hipMemcpyAsync(blocks.data(), M.U_d + (size_t)i * nf * DD, blocks.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+    } else {
+      std::vector<float> bf((size_t)nf * DD);
+      HIPC(hipMemcpyAsync(bf.data(), M.U_f + (size_t)i * nf * DD, bf.size() * sizeof(float),
+                          hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+      for (size_t e = 0; e < bf.size(); ++e) blocks[e] = bf[e];
+    }
+    for (int p = 0; p < nf; ++p)
+      if (M.bvert_h[p] != i) row.push_back({M.vperm[M.bvert_h[p]], p});
+  } else {
+    int64_t sp[2];
+    HIPC(hipMemcpyAsync(sp, M.sptr + i, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    const int64_t len = sp[1] - sp[0];
+    std::vector<int> si(len);
+    blocks.assign((size_t)len * DD, 0.0);
+    if (len > 0) {
+      HIPC(hipMemcpyAsync(si.data(), M.sidx + sp[0], len * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPC(hipMemcpyAsync(blocks.data(), M.U_d + sp[0] * DD, blocks.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+    }
+    for (int64_t q = 0; q < len; ++q) row.push_back({M.vperm[si[q]], q});
+  }
+  std::sort(row.begin(), row.end());
+}
+}  // namespace
+
+extern "C" {
+
 cc_status cc_subspace_download(cc_ctx* ctx, int32_t mesh_id, int64_t* ptr, int32_t* idx, double* U) {
   return guarded(ctx, [&]() -> cc_status {
     Mesh& M = get_mesh(ctx, mesh_id);
     if (!M.has_basis) return fail(ctx, CC_E_STATE, "no basis uploaded");
-    // device rows are in internal order: convert to caller ids, ascending
-    const int D = M.D, DD = D * D, nf = M.nf, n = M.n;
-    std::vector<int64_t> sp(nf + 1);
-    std::vector<int> si(M.snnz);
-    std::vector<double> Uh((size_t)M.snnz * DD);
-    hipStream_t s = ctx->stream;
-    HIPC(hipMemcpyAsync(sp.data(), M.sptr, sp.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HIPC(hipMemcpyAsync(si.data(), M.sidx, si.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPC(hipMemcpyAsync(Uh.data(), M.U_d, Uh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
+    const int DD = M.D * M.D, nf = M.nf, n = M.n;
+    std::vector<std::vector<std::pair<int, int64_t>>> rows(nf);
     std::vector<int64_t> cp(n + 1, 0);
-    for (int i = 0; i < nf; ++i) cp[M.vperm[i] + 1] = sp[i + 1] - sp[i];
+    std::vector<std::pair<int, int64_t>> row;
+    std::vector<double> blocks;
+    for (int i = 0; i < nf; ++i) {
+      basis_row(ctx, M, i, row, blocks);
+      cp[M.vperm[i] + 1] = (int64_t)row.size();
+    }
     for (int u = 0; u < n; ++u) cp[u + 1] += cp[u];
     if (ptr) std::memcpy(ptr, cp.data(), cp.size() * sizeof(int64_t));
-    std::vector<std::pair<int, int64_t>> row;
+    if (!idx && !U) return CC_OK;
     for (int i = 0; i < nf; ++i) {
+      basis_row(ctx, M, i, row, blocks);
       const int u = M.vperm[i];
-      row.clear();
-      for (int64_t q = sp[i]; q < sp[i + 1]; ++q) row.push_back({M.vperm[si[q]], q});
-      std::sort(row.begin(), row.end());
       for (size_t t = 0; t < row.size(); ++t) {
         if (idx) idx[cp[u] + t] = row[t].first;
-        if (U) std::memcpy(&U[(size_t)(cp[u] + t) * DD], &Uh[(size_t)row[t].second * DD], DD * sizeof(double));
+        if (U) std::memcpy(&U[(size_t)(cp[u] + t) * DD], &blocks[(size_t)row[t].second * DD], DD * sizeof(double));
       }
+    }
+    return CC_OK;
+  });
+}
+
+cc_status cc_subspace_row(cc_ctx* ctx, int32_t mesh_id, int32_t vertex, int64_t* len, int32_t* idx, double* U) {
+  return guarded(ctx, [&]() -> cc_status {
+    Mesh& M = get_mesh(ctx, mesh_id);
+    if (!M.has_basis) return fail(ctx, CC_E_STATE, "no basis uploaded");
+    if (vertex < 0 || vertex >= M.n) return fail(ctx, CC_E_INVALID_ARG, "vertex out of range");
+    const int DD = M.D * M.D;
+    const int i = M.vinv[vertex];
+    if (i >= M.nf) {
+      if (len) *len = 0;
+      return CC_OK;
+    }
+    std::vector<std::pair<int, int64_t>> row;
+    std::vector<double> blocks;
+    basis_row(ctx, M, i, row, blocks);
+    if (len) *len = (int64_t)row.size();
+    for (size_t t = 0; t < row.size(); ++t) {
+      if (idx) idx[t] = row[t].first;
+      if (U) std::memcpy(&U[t * DD], &blocks[(size_t)row[t].second * DD], DD * sizeof(double));
     }
     return CC_OK;
   });
@@ -1135,6 +1291,8 @@ static cc_status check_params(cc_ctx* ctx, const cc_params* p, const Mesh& M, do
   if (!p->quasistatic && !(dt > 0)) return fail(ctx, CC_E_INVALID_ARG, "dt must be positive");
   if (p->method != CC_METHOD_CD && !M.has_basis)
     return fail(ctx, CC_E_STATE, "method needs a basis: call cc_subspace_upload or cc_subspace_build");
+  if (p->method != CC_METHOD_CD && p->precision == CC_FP64 && M.has_basis && M.U_d == nullptr)
+    return fail(ctx, CC_E_STATE, "the exact basis of this mesh is kept in float32 only: use CC_FP32_MIXED");
   for (int c = 0; c < 3; ++c)
     if (!std::isfinite(p->gravity[c])) return fail(ctx, CC_E_NONFINITE, "non-finite gravity");
   if (p->warm_start != 0 && p->warm_start != 1) return fail(ctx, CC_E_INVALID_ARG, "bad warm_start");
@@ -1357,8 +1515,9 @@ static cc_status batch_validate(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids,
   return CC_OK;
 }
 
-static bool use_dense_lds(const Mesh& M, int prec) {
-  return M.dense && M.nseg > 0 && cc::dense_tv(M.nf, M.D, prec) > 0;
+static bool use_dense_band(const Mesh& M, int prec) {
+  const int ring = cc::band_ring(M.nf, M.band_w);
+  return M.dense && M.nf > 1 && cc::dense_tv(ring, M.D, prec) > 0 && (prec != CC_FP64 || M.U_d != nullptr);
 }
 
 static void ctx_batch_hook(void* user, int kid, int begin) {
@@ -1400,7 +1559,7 @@ static cc::BatchPlan* batch_plan_for(cc_ctx* ctx, const std::vector<Mesh*>& ms, 
   for (int i = 0; i < n; ++i) {
     Material mat{};
     items[i] = make_item(*ms[i], mat);
-    items[i].prep_dense = (p.method != CC_METHOD_CD && use_dense_lds(*ms[i], p.precision)) ? 1 : 0;
+    items[i].prep_dense = (p.method != CC_METHOD_CD && use_dense_band(*ms[i], p.precision)) ? 1 : 0;
     items[i].mv.rot = p.corotate ? ms[i]->rot : nullptr;
   }
   cc::BatchConfig cfg{};
@@ -1489,7 +1648,7 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
       mat.s_el = p.quasistatic ? 1.0 : dt * dt;
       for (int c = 0; c < 3; ++c) mat.grav[c] = gravity ? gravity[3 * i + c] : p.gravity[c];
       items[i] = make_item(M, mat);
-      items[i].prep_dense = (p.method != CC_METHOD_CD && use_dense_lds(M, p.precision)) ? 1 : 0;
+      items[i].prep_dense = (p.method != CC_METHOD_CD && use_dense_band(M, p.precision)) ? 1 : 0;
       items[i].mv.rot = p.corotate ? M.rot : nullptr;
       items[i].feat_off = 0;
       for (int q = 0; q < i; ++q) items[i].feat_off += ms[q]->nf;
@@ -1681,7 +1840,7 @@ cc_status cc_autotune_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, con
       Material mat{};
       mat.mu = ms[i]->mu; mat.lam = ms[i]->lam; mat.model = ms[i]->model;
       items[i] = make_item(*ms[i], mat);
-      items[i].prep_dense = (params->method != CC_METHOD_CD && use_dense_lds(*ms[i], params->precision)) ? 1 : 0;
+      items[i].prep_dense = (params->method != CC_METHOD_CD && use_dense_band(*ms[i], params->precision)) ? 1 : 0;
       items[i].mv.rot = params->corotate ? ms[i]->rot : nullptr;
     }
     HIPC(hipMemcpyAsync(cc::batch_items_dev(plan), items.data(), n * sizeof(cc::BatchItem),

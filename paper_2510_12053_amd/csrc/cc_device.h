@@ -514,17 +514,35 @@ __device__ __forceinline__ void chol_solve(const T L[D][D], const T B[D][D], T X
   }
 }
 
-__device__ __forceinline__ int find_slot(const MeshView& mv, int64_t sp0, int64_t sp1, int i, int k) {
+// Basis row of vertex i as blocks [sp0, sp1) of U: CSR rows for sparse bases,
+// nf blocks in band order (own block zero) for dense ones.
+__device__ __forceinline__ void supp_range(const MeshView& mv, int i, int64_t& sp0, int64_t& sp1) {
+  if (mv.dense_supp) {
+    sp0 = (int64_t)i * mv.nf;
+    sp1 = sp0 + mv.nf;
+  } else {
+    sp0 = mv.sptr[i];
+    sp1 = mv.sptr[i + 1];
+  }
+}
+
+// Vertex (internal id) of block q of the row starting at sp0.
+__device__ __forceinline__ int supp_vertex(const MeshView& mv, int64_t q, int64_t sp0) {
+  return mv.dense_supp ? mv.bvert[q - sp0] : mv.sidx[q];
+}
+
+// Block of vertex k in row i (blocks [sp0, sp1)), or -1 when k is not in supp(i).
+__device__ __forceinline__ int64_t find_slot(const MeshView& mv, int64_t sp0, int64_t sp1, int i, int k) {
   if (mv.dense_supp) {
     if (k == i || k >= mv.nf) return -1;
-    return (int)(sp0 + (k < i ? k : k - 1));
+    return sp0 + mv.bpos[k];
   }
   int64_t lo = sp0, hi = sp1;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
     if (mv.sidx[mid] < k) lo = mid + 1; else hi = mid;
   }
-  return (lo < sp1 && mv.sidx[lo] == k) ? (int)lo : -1;
+  return (lo < sp1 && mv.sidx[lo] == k) ? lo : -1;
 }
 
 // Per-vertex condensation: A_i = H_iC U_i, Ht_i = U_i^T H_CC U_i, then

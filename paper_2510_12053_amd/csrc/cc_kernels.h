@@ -25,18 +25,33 @@ struct MeshView {
   const int* cptr;       // [nnzb+1] element contributions of each block slot
   const int* centry;     // packed e*16 + a*4 + b
   int nnzb;
-  // blocks j <= k of the symmetric block matrix (diagonal included), in
-  // segments of up to SEG_LEN blocks of one row j: two int4 per segment,
-  // {j, count, slot0, slot1}, {slot2, slot3, k0 | k1 << 16, k2 | k3 << 16};
-  // null when nf > 65535
-  const int4* seg;
-  int nseg;
-  // perturbation basis, internal ids, rows sorted by internal id
+  // Band order of the free vertices (breadth-first levels from the free
+  // vertices next to the Dirichlet set, neighbours appended in caller-id
+  // order): bvert[p] = internal id at band position p, bpos = its inverse.
+  // Every neighbour k of a vertex j lies within band_w positions after it
+  // (when k comes later).  Row p's blocks (j, k) with bpos[k] >= bpos[j]
+  // ("upper" blocks, the diagonal first) number bq_cnt[p] <= qmax; bq_pos
+  // [q * nf + p] holds the band position of the q-th one's column.  The
+  // assembly kernel also writes those blocks, the diagonal at half weight,
+  // into hq [(q * D*D + rs) * nf + p] (precision of hb) when hq is set:
+  // hq_slot[t] = q * nf + p for an upper slot t of hb, -1 otherwise.
+  const int* bvert;
+  const int* bpos;
+  const int* bq_cnt;
+  const int* bq_pos;
+  const int* hq_slot;
+  void* hq;
+  int qmax, band_w;
+  int ring;              // LDS ring length (power of two) of the dense condensation
+  // perturbation basis, internal ids.  Sparse bases: CSR rows sorted by
+  // internal id (sptr, sidx).  Dense (exact) bases: row i holds nf blocks
+  // at (i * nf + p) * D*D, column p = band position, the block at the
+  // vertex's own position zero; sptr and sidx are unused.
   const int64_t* sptr;   // [nf+1]
   const int* sidx;
-  const double* U_d;     // [nnz][D*D]
+  const double* U_d;     // [nnz][D*D]; dense bases: null when only float32 is kept
   const float* U_f;
-  int dense_supp;        // 1: supp(i) = every free vertex except i
+  int dense_supp;        // 1: supp(i) = every free vertex except i (band layout)
   // support slot map of sparse bases: support entry q = (i, j) owns the
   // smap_words + 1 words at q * (smap_words + 1): the first holds
   // rowptr[j]; for the t-th block of row j, byte t of the others is SMAP_SELF
@@ -110,20 +125,22 @@ void launch_scatter_user(const MeshView& mv, const int* vperm, const double* src
 
 int reduce_partials_capacity(const MeshView& mv);
 
-constexpr int SEG_LEN = 4;
-
-// Dense condensation with the basis rows in LDS: the per-workgroup LDS limit
-// of the device (bytes, set once per process) and the number of vertices one
-// workgroup takes for a mesh of nf free vertices (0: the rows do not fit).
+// Dense condensation: workgroup size, the per-workgroup LDS limit of the
+// device (bytes, set once per process), the LDS ring length of a mesh and the
+// number of vertices one workgroup takes (0: the ring does not fit).
+constexpr int BWG = 512;
 void set_lds_limit(size_t bytes);
-int dense_tv(int nf, int D, int prec);
-size_t dense_lds_bytes(int tv, int nf, int D, int prec);
+int band_ring(int nf, int band_w);
+int dense_tv(int ring, int D, int prec);
+size_t dense_lds_bytes(int tv, int ring, int D, int prec);
 
-// Exact basis U_i[j] = (H^{-1})_ji ((H^{-1})_ii)^{-1} from float64 rest block
-// rows hb (cc_basis.hip).  A: (nf D)^2 doubles of scratch, work: nf D 64 +
-// 64^2 doubles, bad: one int; Ud/Uf: nf (nf-1) D^2 outputs in the dense
-// internal row layout.  Returns false if a pivot block is not SPD.
-bool exact_basis_gpu(const MeshView& mv, const double* hb, double* A, double* work, int* bad, double* Ud,
+// Exact basis U_i[j] = (H^{-1})_ji ((H^{-1})_ii)^{-1} from float64 block rows
+// hb (cc_basis.hip), through the block-tridiagonal structure of H in band
+// order: loff (host, L+1 band positions) splits the band order into levels
+// such that every block (j, k) of H couples the same or adjacent levels.
+// Ud (may be null) / Uf receive the dense band layout.  Returns 0, 1 when a
+// pivot block is not positive definite, 2 when device memory runs out.
+int exact_basis_band(const MeshView& mv, const double* hb, const int* loff_h, int L, double* Ud,
                      float* Uf, hipStream_t s);
 
 // ---- batched stepping (many meshes per launch) -----------------------------
@@ -142,7 +159,7 @@ struct BatchItem {
   double* xu;          // caller positions (n x D), this call
   double* vu;          // caller velocities
   const double* xbc;   // caller Dirichlet targets or null
-  int prep_dense;      // 1: exact-basis condensation with the basis rows in LDS
+  int prep_dense;      // 1: exact-basis condensation streamed through the LDS ring
   int ncol;
   int coff[MAX_COLOURS + 1];
   // warm start: mesh neighbours (all vertices), rest positions, scales and

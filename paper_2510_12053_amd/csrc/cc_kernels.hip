@@ -182,6 +182,16 @@ __device__ __forceinline__ void assemble_body(const MeshView& mv, int tt, const 
   }
 #pragma unroll
   for (int r = 0; r < DD; ++r) hb[(size_t)t * DD + r] = acc[r];
+  if (mv.hq != nullptr) {                 // band copy of an upper block for the dense condensation
+    const int qp = mv.hq_slot[t];
+    if (qp >= 0) {
+      const int nf = mv.nf, q = qp / nf, pp = qp - q * nf;
+      const T w = mv.colidx[t] == j ? T(0.5) : T(1);
+      T* hq = reinterpret_cast<T*>(mv.hq);
+#pragma unroll
+      for (int r = 0; r < DD; ++r) hq[((size_t)q * DD + r) * nf + pp] = w * acc[r];
+    }
+  }
 }
 
 template <typename T, int D>
@@ -288,10 +298,7 @@ __device__ __forceinline__ void prep_body(const MeshView& mv, int method, int i,
 #pragma unroll
   for (int r = 0; r < DD; ++r) A[r] = Ht[r] = T(0);
   int64_t sp0 = 0, sp1 = 0;
-  if (active && method != 0) {
-    sp0 = mv.sptr[i];
-    sp1 = mv.sptr[i + 1];
-  }
+  if (active && method != 0) supp_range(mv, i, sp0, sp1);
   const T* Us = nullptr;   // staged, rotated support row of vertex i
   if (stage) {
     const bool st = active && method != 0 && mv.smap && sp1 - sp0 <= cap;
@@ -393,13 +400,14 @@ __device__ __forceinline__ void prep_body(const MeshView& mv, int method, int i,
     }
   } else if (active && method != 0) {
     for (int64_t q = sp0 + lane; q < sp1; q += G) {
-      const int j = mv.sidx[q];
+      const int j = supp_vertex(mv, q, sp0);
+      if (j == i) continue;                   // the zero own block of a dense row
       T Uj[DD];
 #pragma unroll
       for (int r = 0; r < DD; ++r) Uj[r] = Ub[q * DD + r];
       if (mv.rot) rotate_block<T, D>(mv.rot, j, Uj);
       accum_row<T, D>(mv, i, j, Uj, hb, [&](int k, T* Uk) -> bool {
-        const int qk = find_slot(mv, sp0, sp1, i, k);
+        const int64_t qk = find_slot(mv, sp0, sp1, i, k);
         if (qk < 0) return false;
 #pragma unroll
         for (int r = 0; r < DD; ++r) Uk[r] = Ub[(size_t)qk * DD + r];
@@ -440,155 +448,158 @@ __global__ void __launch_bounds__(WG) k_cc_prep(MeshView mv, int method, int v0,
                      fb, cap > 0 ? reinterpret_cast<T*>(smem_raw) : nullptr, cap);
 }
 
-// Exact-basis condensation of TV vertices per workgroup.  Each vertex's
-// dense basis row goes to LDS with a zero block at its own position, so the
-// sums below run over every (j, k) without excluding i.  H is symmetric, so
-// only the blocks j <= k are read: with X_jk = U_j^T H_jk U_k,
-//   Ht = sum_{j,k} X_jk = Y + Y^T,  Y = sum_{j<k} X_jk + 1/2 sum_j X_jj,
-// and every H block read from L2 serves all TV vertices of the workgroup.
-// A_i = sum_k H_ik U_i[k] comes from row i (one wave per vertex).
-constexpr int PWG = 512;   // threads of the dense multi-vertex condensation
-
+// Exact-basis condensation of TV vertices per workgroup (Method, Eqs. block
+// and schur: A_i = H_iC U_i, Ht_i = U_i^T H_CC U_i, b_i = U_i^T g_C).
 //
-// With g given (Jacobi sweeps), b_i = U_i^T g_C is also formed from the staged
-// row and stored in bout (vertex-major components, stride n); the finish
-// kernel then writes the direction itself, so the update kernel's second pass
-// over the basis is not needed.
+// The basis rows are stored in band order (MeshView::bvert), in which every
+// block (j, k) of H with k after j has k within band_w positions of j.  H is
+// symmetric, so with X_jk = U_j^T H_jk U_k
+//   Ht = sum_{j,k} X_jk = Y + Y^T,  Y = sum_j U_j^T W_j,
+//   W_j = sum_{k >= j} w_jk H_jk U_k  (w = 1/2 on the diagonal block, folded
+//                                      into the band copy hq of H),
+// and only the upper blocks are read.  The workgroup walks the band in chunks
+// of BWG positions, one thread per row j of the chunk; row j needs U at
+// positions [j, j + band_w], so the TV rows live in an LDS ring of R >= BWG +
+// band_w positions, component planes [v][rs][R], refilled one chunk ahead:
+// the global loads of chunk c + 1's new positions are issued before chunk c's
+// products and stored after them.  Threads of a wave take consecutive rows,
+// whose q-th upper columns are (on the structured grids) consecutive
+// positions, so the plane reads hit distinct banks and the hq loads coalesce.
+// Every H block serves the TV rows of the workgroup from registers.
+// A_i = sum_k H_ik U_i[k] comes from row i in global memory (one wave per
+// vertex; the row was just streamed through L2).
+//
+// With g given (Jacobi sweeps), b_i = U_i^T g_C is also accumulated from the
+// staged rows and stored in bout (component-major, stride n); the finish
+// kernel then writes the direction itself.
+template <typename T, int D>
+__device__ __forceinline__ void band_load(const MeshView& mv, const T* __restrict__ Ub, int row, int pos,
+                                          T (&blk)[D * D]) {
+  constexpr int DD = D * D;
+  const auto* src = gptr(Ub) + ((size_t)row * mv.nf + pos) * DD;
+#pragma unroll
+  for (int r = 0; r < DD; ++r) blk[r] = src[r];
+}
+
 template <typename T, int D, int TV>
-__device__ __forceinline__ void prep_dm_body(const MeshView& mv, int method, int i0, int nv,
-                                             const T* __restrict__ hb, T* __restrict__ KL,
-                                             unsigned long long* __restrict__ fb, T* smem,
-                                             const double* __restrict__ g, double* __restrict__ bout) {
-  constexpr int DD = D * D, NW = PWG / 64, NR = DD + D;
-  const int nf = mv.nf;
-  T* Us = smem;                                   // [TV][nf][DD]
-  T* red = smem + (size_t)TV * nf * DD;           // [NW + 1][TV][DD + D]
+__device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, int i0, int nv,
+                                               const T* __restrict__ hb, T* __restrict__ KL, T* smem,
+                                               const double* __restrict__ g, double* __restrict__ bout) {
+  constexpr int DD = D * D, NW = BWG / 64, NR = DD + D;
+  const int nf = mv.nf, n = mv.n, R = mv.ring, msk = R - 1, bw = mv.band_w;
+  T* ring = smem;                                   // [TV][DD][R]
+  T* red = smem + (size_t)TV * DD * R;              // [NW][TV][NR]
   const T* Ub = basis_of<T>(mv);
-  // stage the rows: many independent loads in flight per thread, then the
-  // LDS stores (one workgroup per CU leaves nothing else to hide the latency).
-  // Every load is unconditional and in bounds (positions past the row end
-  // and the vertex's own block read element 0 and are replaced by zero), so
-  // the loads of one batch issue back to back.  Rows of vertex slots past nv
-  // are zero.
-  constexpr int UNR = 16;
-  const int total = nf * DD;
+  const T* hq = reinterpret_cast<const T*>(mv.hq);
+  const int tid = threadIdx.x;
+  int rows[TV];
 #pragma unroll
-  for (int v = 0; v < TV; ++v) {
-    const int i = i0 + (v < nv ? v : 0);
-    const auto* src = gptr(Ub) + gptr(mv.sptr)[i] * DD;
-    T* dst = Us + (size_t)v * total;
-    const int lo = i * DD, hi = lo + DD;
-    for (int base = threadIdx.x; base < total; base += PWG * UNR) {
-      T tmp[UNR];
+  for (int v = 0; v < TV; ++v) rows[v] = i0 + (v < nv ? v : 0);
+  // stage block (row v, position pos), rotated by R_j (j at pos) when corotated
+  auto put = [&](int v, int pos, T (&blk)[DD]) {
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int q = base + u * PWG;
-        const bool zero = v >= nv || (q >= lo && q < hi) || q >= total;
-        const int sq = zero ? 0 : (q < lo ? q : q - DD);
-        const T val = src[sq];
-        tmp[u] = zero ? T(0) : val;
-      }
+    for (int r = 0; r < DD; ++r) ring[((size_t)v * DD + r) * R + (pos & msk)] = blk[r];
+  };
+  auto fetch = [&](int pos, T (&blk)[TV][DD]) {
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int q = base + u * PWG;
-        if (q < total) dst[q] = tmp[u];
-      }
-    }
+    for (int v = 0; v < TV; ++v) band_load<T, D>(mv, Ub, rows[v], pos, blk[v]);
+  };
+  auto rotate_all = [&](int pos, T (&blk)[TV][DD]) {
+    if (mv.rot == nullptr) return;
+    const int j = gptr(mv.bvert)[pos];
+#pragma unroll
+    for (int v = 0; v < TV; ++v) rotate_block<T, D>(mv.rot, j, blk[v]);
+  };
+  int lo = min(nf, BWG + bw);                       // first fill: positions [0, lo)
+  for (int pos = tid; pos < lo; pos += BWG) {
+    T blk[TV][DD];
+    fetch(pos, blk);
+    rotate_all(pos, blk);
+#pragma unroll
+    for (int v = 0; v < TV; ++v) put(v, pos, blk[v]);
   }
   __syncthreads();
-  if (mv.rot != nullptr) {                        // corotation: U_v[j] <- R_j U_v[j]
-    for (int e = threadIdx.x; e < TV * nf; e += PWG) {
-      T* u = Us + (size_t)e * DD;                 // row e / nf, block e % nf
-      T blk[DD];
+  T Y[TV][DD], Bv[TV][D];
 #pragma unroll
-      for (int r = 0; r < DD; ++r) blk[r] = u[r];
-      rotate_block<T, D>(mv.rot, e % nf, blk);
-#pragma unroll
-      for (int r = 0; r < DD; ++r) u[r] = blk[r];
-    }
-    __syncthreads();
-  }
-  T Y[TV][DD];
-#pragma unroll
-  for (int v = 0; v < TV; ++v)
+  for (int v = 0; v < TV; ++v) {
 #pragma unroll
     for (int r = 0; r < DD; ++r) Y[v][r] = T(0);
-  if (method != 0) {
-    // one segment = up to SEG_LEN blocks (j, k) of row j:
-    //   W = sum_k w_k H_jk U_k  (27 FMA per block and vertex),
-    //   Y += U_j^T W            (27 FMA per segment and vertex)
-    for (int sg = threadIdx.x; sg < mv.nseg; sg += PWG) {
-      const auto* sq = gptr(reinterpret_cast<const int*>(mv.seg)) + 8 * sg;
-      const int j = sq[0], cnt = sq[1];
-      const int slot[SEG_LEN] = {sq[2], sq[3], sq[4], sq[5]};
-      const int kk[SEG_LEN] = {sq[6] & 0xffff, sq[6] >> 16, sq[7] & 0xffff, sq[7] >> 16};
+#pragma unroll
+    for (int r = 0; r < D; ++r) Bv[v][r] = T(0);
+  }
+  const auto* bq_pos = gptr(mv.bq_pos);
+  for (int p0 = 0; p0 < nf; p0 += BWG) {
+    // chunk p0 + BWG needs positions up to p0 + 2 BWG + bw: prefetch them
+    const int nhi = min(nf, p0 + 2 * BWG + bw);
+    const int ppos = lo + tid;
+    const bool pf = ppos < nhi;
+    T pre[TV][DD];
+    if (pf) fetch(ppos, pre);
+    const int p = p0 + tid;
+    if (p < nf) {
+      const int cnt = gptr(mv.bq_cnt)[p];
       T W[TV][DD];
 #pragma unroll
       for (int v = 0; v < TV; ++v)
 #pragma unroll
         for (int r = 0; r < DD; ++r) W[v][r] = T(0);
-      // short segments are padded with a repeat of their first block at
-      // weight 0, so the loop has no branches and its loads issue together
+      for (int q = 0; q < cnt; ++q) {
+        const int kp = bq_pos[(size_t)q * nf + p] & msk;
+        T H[DD];
 #pragma unroll
-      for (int q = 0; q < SEG_LEN; ++q) {
-        const int k = kk[q];
-        const auto* H = gptr(hb) + (size_t)slot[q] * DD;
-        const T w = q < cnt ? ((j == k) ? T(0.5) : T(1)) : T(0);
-        T Hl[DD];
-#pragma unroll
-        for (int r = 0; r < DD; ++r) Hl[r] = w * H[r];
+        for (int r = 0; r < DD; ++r) H[r] = gptr(hq)[((size_t)q * DD + r) * nf + p];
 #pragma unroll
         for (int v = 0; v < TV; ++v) {
-          const T* Uk = Us + ((size_t)v * nf + k) * DD;
-          T Ukl[DD];
+          T U[DD];
 #pragma unroll
-          for (int r = 0; r < DD; ++r) Ukl[r] = Uk[r];
+          for (int r = 0; r < DD; ++r) U[r] = ring[((size_t)v * DD + r) * R + kp];
 #pragma unroll
           for (int r = 0; r < D; ++r)
 #pragma unroll
-            for (int c = 0; c < D; ++c)
+            for (int c = 0; c < D; ++c) {
+              T acc = W[v][r * D + c];
 #pragma unroll
-              for (int l = 0; l < D; ++l) W[v][r * D + c] += Hl[r * D + l] * Ukl[l * D + c];
+              for (int l = 0; l < D; ++l) acc += H[r * D + l] * U[l * D + c];
+              W[v][r * D + c] = acc;
+            }
         }
       }
+      T gj[D];
+      if (g != nullptr) {
+        const int j = gptr(mv.bvert)[p];
+#pragma unroll
+        for (int c = 0; c < D; ++c) gj[c] = T(gptr(g)[(size_t)c * n + j]);
+      }
+      const int sp = p & msk;
 #pragma unroll
       for (int v = 0; v < TV; ++v) {
-        const T* u = Us + ((size_t)v * nf + j) * DD;
         T Uj[DD];
 #pragma unroll
-        for (int r = 0; r < DD; ++r) Uj[r] = u[r];
+        for (int r = 0; r < DD; ++r) Uj[r] = ring[((size_t)v * DD + r) * R + sp];
 #pragma unroll
         for (int l = 0; l < D; ++l)
 #pragma unroll
           for (int r = 0; r < D; ++r)
 #pragma unroll
             for (int c = 0; c < D; ++c) Y[v][r * D + c] += Uj[l * D + r] * W[v][l * D + c];
+        if (g != nullptr)
+#pragma unroll
+          for (int r = 0; r < D; ++r) {
+            T acc = T(0);
+#pragma unroll
+            for (int l = 0; l < D; ++l) acc += Uj[l * D + r] * gj[l];
+            Bv[v][r] += acc;
+          }
       }
     }
-  }
-  T Bv[TV][D];
+    __syncthreads();                                // chunk p0's ring reads are done
+    if (pf) {
+      rotate_all(ppos, pre);
 #pragma unroll
-  for (int v = 0; v < TV; ++v)
-#pragma unroll
-    for (int r = 0; r < D; ++r) Bv[v][r] = T(0);
-  if (method != 0 && g != nullptr) {             // b = sum_j U_j^T g_j (U_i[i] = 0)
-    const int n = mv.n;
-    for (int j = threadIdx.x; j < nf; j += PWG) {
-      T gj[D];
-#pragma unroll
-      for (int c = 0; c < D; ++c) gj[c] = T(gptr(g)[c * n + j]);
-#pragma unroll
-      for (int v = 0; v < TV; ++v) {
-        const T* u = Us + ((size_t)v * nf + j) * DD;
-#pragma unroll
-        for (int r = 0; r < D; ++r) {
-          T acc = T(0);
-#pragma unroll
-          for (int l = 0; l < D; ++l) acc += u[l * D + r] * gj[l];
-          Bv[v][r] += acc;
-        }
-      }
+      for (int v = 0; v < TV; ++v) put(v, ppos, pre[v]);
     }
+    lo = max(lo, nhi);
+    __syncthreads();
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1)
@@ -599,7 +610,7 @@ __device__ __forceinline__ void prep_dm_body(const MeshView& mv, int method, int
 #pragma unroll
       for (int r = 0; r < D; ++r) Bv[v][r] += __shfl_xor(Bv[v][r], off, 64);
     }
-  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  const int w = tid / 64, l = tid % 64;
   if (l == 0)
 #pragma unroll
     for (int v = 0; v < TV; ++v) {
@@ -609,11 +620,12 @@ __device__ __forceinline__ void prep_dm_body(const MeshView& mv, int method, int
       for (int r = 0; r < D; ++r) red[(w * TV + v) * NR + DD + r] = Bv[v][r];
     }
   __syncthreads();
-  if (threadIdx.x < TV * NR) {
+  T* tot = ring;                                    // the ring is free now: [TV][NR]
+  if (tid < TV * NR) {
     T acc = T(0);
 #pragma unroll
-    for (int ww = 0; ww < NW; ++ww) acc += red[ww * TV * NR + threadIdx.x];
-    red[NW * TV * NR + threadIdx.x] = acc;
+    for (int ww = 0; ww < NW; ++ww) acc += red[ww * TV * NR + tid];
+    tot[tid] = acc;
   }
   __syncthreads();
   if (w >= nv) return;
@@ -621,12 +633,14 @@ __device__ __forceinline__ void prep_dm_body(const MeshView& mv, int method, int
   T A[DD];
 #pragma unroll
   for (int r = 0; r < DD; ++r) A[r] = T(0);
-  if (method != 0) {
-    const T* Ui = Us + (size_t)w * nf * DD;
+  {
     const int q1 = gptr(mv.rowptr)[i + 1];
-    for (int q = gptr(mv.rowptr)[i] + l; q < q1; q += 64) {
+    for (int q = gptr(mv.rowptr)[i] + 1 + l; q < q1; q += 64) {
+      const int k = gptr(mv.colidx)[q];
+      T Uk[DD];
+      band_load<T, D>(mv, Ub, i, gptr(mv.bpos)[k], Uk);
+      if (mv.rot != nullptr) rotate_block<T, D>(mv.rot, k, Uk);
       const auto* H = gptr(hb) + (size_t)q * DD;
-      const T* Uk = Ui + (size_t)gptr(mv.colidx)[q] * DD;
 #pragma unroll
       for (int r = 0; r < D; ++r)
 #pragma unroll
@@ -644,9 +658,8 @@ __device__ __forceinline__ void prep_dm_body(const MeshView& mv, int method, int
   }
   if (l != 0) return;
   // A and Ht go to the vertex's K, L slots; dm_finish_body turns them into
-  // K and L with one thread per vertex (the small solves are latency-bound
-  // and would otherwise serialise the single workgroup resident per CU)
-  const T* Yt = red + (NW * TV + w) * NR;
+  // K and L with one thread per vertex
+  const T* Yt = tot + w * NR;
   auto* out = gptr_w(KL) + (size_t)i * 2 * DD;
 #pragma unroll
   for (int r = 0; r < D; ++r)
@@ -712,14 +725,12 @@ __global__ void __launch_bounds__(WG) k_cc_dm_finish(MeshView mv, int method, in
 }
 
 template <typename T, int D, int TV>
-__global__ void __launch_bounds__(PWG) k_cc_prep_dm(MeshView mv, int method, int v0, int v1,
-                                                    const T* __restrict__ hb, T* __restrict__ KL,
-                                                    unsigned long long* __restrict__ fb,
-                                                    const double* __restrict__ g, double* __restrict__ bout) {
+__global__ void __launch_bounds__(BWG) k_cc_prep_band(MeshView mv, int method, int v0, int v1,
+                                                      const T* __restrict__ hb, T* __restrict__ KL,
+                                                      const double* __restrict__ g, double* __restrict__ bout) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int i0 = v0 + blockIdx.x * TV;
-  prep_dm_body<T, D, TV>(mv, method, i0, min(TV, v1 - i0), hb, KL, fb, reinterpret_cast<T*>(smem_raw),
-                         g, bout);
+  prep_band_body<T, D, TV>(mv, method, i0, min(TV, v1 - i0), hb, KL, reinterpret_cast<T*>(smem_raw), g, bout);
 }
 
 
@@ -737,9 +748,10 @@ __device__ __forceinline__ void update_body(const MeshView& mv, int method, int 
 #pragma unroll
   for (int c = 0; c < D; ++c) b[c] = T(0);
   if (active && method != 0) {
-    const int64_t sp0 = mv.sptr[i], sp1 = mv.sptr[i + 1];
+    int64_t sp0, sp1;
+    supp_range(mv, i, sp0, sp1);
     for (int64_t q = sp0 + lane; q < sp1; q += G) {
-      const int j = mv.sidx[q];
+      const int j = supp_vertex(mv, q, sp0);
       T gj[D];
 #pragma unroll
       for (int c = 0; c < D; ++c) gj[c] = T(g[c * n + j]);
@@ -1100,16 +1112,25 @@ static size_t g_lds_limit = 64 * 1024;
 
 void set_lds_limit(size_t bytes) { g_lds_limit = bytes; }
 
-size_t dense_lds_bytes(int tv, int nf, int D, int prec) {
-  const size_t S = prec == 0 ? 8 : 4;
-  return ((size_t)tv * nf * D * D + (size_t)(PWG / 64 + 1) * tv * (D * D + D)) * S;
+int band_ring(int nf, int band_w) {
+  if (nf <= 0) return 0;
+  const int need = std::min(nf, BWG + band_w);
+  int r = 64;
+  while (r < need) r *= 2;
+  return r;
 }
 
-int dense_tv(int nf, int D, int prec) {
-  if (nf < 2 || nf > 65535) return 0;
-  // four float64 vertices per workgroup exceed the register file of 2 waves/SIMD
-  for (int tv = prec == 0 ? 3 : 4; tv >= 1; --tv)
-    if (dense_lds_bytes(tv, nf, D, prec) <= g_lds_limit) return tv;
+size_t dense_lds_bytes(int tv, int ring, int D, int prec) {
+  const size_t S = prec == 0 ? 8 : 4;
+  return ((size_t)tv * ring * D * D + (size_t)(BWG / 64) * tv * (D * D + D)) * S;
+}
+
+// float64 keeps two rows per workgroup (the register file of 2 waves/SIMD
+// holds the accumulators of two float64 rows, four float32 ones)
+int dense_tv(int ring, int D, int prec) {
+  if (ring <= 0) return 0;
+  for (int tv = prec == 0 ? 2 : 4; tv >= 1; tv /= 2)
+    if (dense_lds_bytes(tv, ring, D, prec) <= g_lds_limit) return tv;
   return 0;
 }
 
@@ -1117,18 +1138,25 @@ int dense_tv(int nf, int D, int prec) {
   switch (tv) {                                              \
     case 1: { constexpr int TV = 1; __VA_ARGS__; } break;    \
     case 2: { constexpr int TV = 2; __VA_ARGS__; } break;    \
-    case 3: { constexpr int TV = 3; __VA_ARGS__; } break;    \
     default: { constexpr int TV = 4; __VA_ARGS__; } break;   \
   }
+
+// True when the mesh's dense basis can be streamed through the LDS ring in
+// this precision (float64 needs the float64 copy of the basis).
+static bool band_ok(const MeshView& mv, int prec) {
+  if (!mv.dense_supp || mv.hq == nullptr || mv.ring <= 0 || mv.nf < 2) return false;
+  if (prec == 0 && mv.U_d == nullptr) return false;
+  return dense_tv(mv.ring, mv.D, prec) > 0;
+}
 
 template <typename T, int D>
 static bool prep_dense(const MeshView& mv, int prec, int method, int v0, int v1, const void* hb,
                        void* KL, unsigned long long* fb, const double* g, double* dout, hipStream_t s) {
-  const int tv = mv.dense_supp && mv.nseg > 0 ? dense_tv(mv.nf, D, prec) : 0;
-  if (tv == 0) return false;
-  const size_t lds = dense_lds_bytes(tv, mv.nf, D, prec);
-  CC_DISPATCH_TV(tv, k_cc_prep_dm<T, D, TV><<<nblocks(v1 - v0, TV), PWG, lds, s>>>(
-                         mv, method, v0, v1, (const T*)hb, (T*)KL, fb, g, dout));
+  if (method == 0 || !band_ok(mv, prec)) return false;
+  const int tv = dense_tv(mv.ring, D, prec);
+  const size_t lds = dense_lds_bytes(tv, mv.ring, D, prec);
+  CC_DISPATCH_TV(tv, k_cc_prep_band<T, D, TV><<<nblocks(v1 - v0, TV), BWG, lds, s>>>(
+                         mv, method, v0, v1, (const T*)hb, (T*)KL, g, dout));
   k_cc_dm_finish<T, D><<<nblocks(v1 - v0, WG), WG, 0, s>>>(mv, method, v0, v1, (const T*)hb, (T*)KL, fb,
                                                           g, dout);
   return true;
@@ -1430,12 +1458,12 @@ __global__ void __launch_bounds__(WG) kb_prep(const BatchItem* __restrict__ item
                      cap > 0 ? reinterpret_cast<T*>(smem_raw) : nullptr, cap);
 }
 
-// Dense-basis meshes of a batch: TV vertices per workgroup (prep_dm_body).
+// Dense-basis meshes of a batch: TV vertices per workgroup (prep_band_body).
 template <typename T, int D, int TV>
-__global__ void __launch_bounds__(PWG) kb_prep_dm(const BatchItem* __restrict__ items,
-                                                  const BatchCtl* __restrict__ ctl,
-                                                  const int* __restrict__ boff, int nmesh,
-                                                  int method, int colour, int fuse) {
+__global__ void __launch_bounds__(BWG) kb_prep_band(const BatchItem* __restrict__ items,
+                                                    const BatchCtl* __restrict__ ctl,
+                                                    const int* __restrict__ boff, int nmesh,
+                                                    int method, int colour, int fuse) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int mi = block_mesh(boff, nmesh, blockIdx.x);
   if (!ctl[mi].active) return;
@@ -1443,9 +1471,8 @@ __global__ void __launch_bounds__(PWG) kb_prep_dm(const BatchItem* __restrict__ 
   int v0, v1;
   vertex_range(it, colour, v0, v1);
   const int i0 = v0 + (blockIdx.x - boff[mi]) * TV;
-  prep_dm_body<T, D, TV>(it.mv, method, i0, min(TV, v1 - i0), (const T*)it.hb, (T*)it.KL, it.fb,
-                         reinterpret_cast<T*>(smem_raw), fuse ? it.g : nullptr,
-                         fuse ? it.d : nullptr);
+  prep_band_body<T, D, TV>(it.mv, method, i0, min(TV, v1 - i0), (const T*)it.hb, (T*)it.KL,
+                           reinterpret_cast<T*>(smem_raw), fuse ? it.g : nullptr, fuse ? it.d : nullptr);
 }
 
 template <typename T, int D>
@@ -1851,7 +1878,7 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
   p->items_h.assign(items_host, items_host + nmesh);
   std::vector<int> cpred(nmesh), celem(nmesh), casm(nmesh), cgrad(nmesh), cen(nmesh), cax(nmesh),
       caxj(nmesh), cfeat(nmesh), crot(nmesh);
-  int dense_nf = 0, sparse_supp = 0;
+  int dense_ring = 0, sparse_supp = 0;
   for (int m = 0; m < nmesh; ++m) {
     const MeshView& mv = p->items_h[m].mv;
     cpred[m] = nblocks(mv.n, WG);
@@ -1865,14 +1892,14 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
     cfeat[m] = nblocks(mv.nf, WG / FEAT_LANES);
     crot[m] = (cfg.corotate && mv.rot) ? nblocks(mv.nf, WG) : 0;
     p->max_colours = std::max(p->max_colours, p->items_h[m].ncol);
-    if (p->items_h[m].prep_dense) dense_nf = std::max(dense_nf, mv.nf);
+    if (p->items_h[m].prep_dense) dense_ring = std::max(dense_ring, mv.ring);
     else if (mv.smap) sparse_supp = std::max(sparse_supp, mv.smap_supp);
   }
   p->scap = sparse_stage_cap(sparse_supp, cfg.G, cfg.D, cfg.prec);
   p->slds = sparse_stage_bytes(p->scap, cfg.G, cfg.D, cfg.prec);
-  if (dense_nf > 0) {
-    p->tv = dense_tv(dense_nf, cfg.D, cfg.prec);
-    p->lds = dense_lds_bytes(p->tv, dense_nf, cfg.D, cfg.prec);
+  if (dense_ring > 0) {
+    p->tv = dense_tv(dense_ring, cfg.D, cfg.prec);
+    p->lds = dense_lds_bytes(p->tv, dense_ring, cfg.D, cfg.prec);
   }
   offsets_build(p->pred, cpred, s);
   offsets_build(p->elem, celem, s);
@@ -1955,7 +1982,7 @@ static void b_prep(BatchPlan* p, int colour, hipStream_t s, int fuse = 0) {
                                                   colour, p->scap);
   if (gridn(od) > 0) {
     const Offsets& of = p->fin[colour + 1];
-    CC_DISPATCH_TV(p->tv, kb_prep_dm<T, D, TV><<<gridn(od), PWG, p->lds, s>>>(
+    CC_DISPATCH_TV(p->tv, kb_prep_band<T, D, TV><<<gridn(od), BWG, p->lds, s>>>(
                               p->items_d, p->ctl_d, od.d, p->nmesh, p->cfg.method, colour, fuse));
     kb_dm_finish<T, D><<<gridn(of), WG, 0, s>>>(p->items_d, p->ctl_d, of.d, p->nmesh, p->cfg.method,
                                                colour, fuse);

@@ -293,6 +293,19 @@ cc_status cc_mlp_forward(cc_ctx* ctx, const float* X, int32_t B, float* Y);
    CC_MLP_NPARAM floats, or NULL to keep it internal), *loss (host, or NULL). */
 cc_status cc_mlp_gradient(cc_ctx* ctx, const float* X, const float* T, const int32_t* idx, int32_t B,
                           float* grad, float* loss);
+/* cc_mlp_gradient without any device allocation, for callers that cannot
+   allocate: code under HIP graph capture, training loops that forbid it.
+   The per-wave partial gradients live in a static device array of the
+   library (about 30 MB per device, held until the process ends) instead of
+   context memory; the result equals cc_mlp_gradient's (same kernels, same
+   summation order).  grad: device, CC_MLP_NPARAM floats (required); loss:
+   device, one float (or NULL).  Nothing is copied to the host and the stream
+   is not synchronised.  B must be in 1..CC_MLP_NOALLOC_MAX_ROWS, else
+   CC_E_INVALID_ARG.  Calls that overlap on one device (other streams or
+   threads) share the array and race; calls ordered on one stream do not. */
+#define CC_MLP_NOALLOC_MAX_ROWS (1 << 26)
+cc_status cc_mlp_gradient_noalloc(cc_ctx* ctx, const float* X, const float* T, const int32_t* idx,
+                                  int32_t B, float* grad, float* loss);
 /* One Adam step (beta 0.9, 0.999, eps 1e-8) with gradient grad (device). */
 cc_status cc_mlp_adam(cc_ctx* ctx, const float* grad, float lr);
 /* cc_mlp_gradient followed by cc_mlp_adam on the same rows. */

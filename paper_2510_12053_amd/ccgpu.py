@@ -325,6 +325,7 @@ def _mlp_sig(L):
         "cc_mlp_forward": (I32, [P, P, I32, P]),
         "cc_mlp_gradient": (I32, [P, P, P, P, I32, P, ctypes.POINTER(ctypes.c_float)]),
         "cc_mlp_adam": (I32, [P, P, ctypes.c_float]),
+        "cc_mlp_gradient_noalloc": (I32, [P, P, P, P, I32, P, P]),
         "cc_mlp_train_step": (I32, [P, P, P, P, I32, ctypes.c_float, ctypes.POINTER(ctypes.c_float)]),
         "cc_mlp_targets": (I32, [P, I32, P, P, P]),
     }
@@ -392,6 +393,15 @@ def cc_mlp_gradient(ctx, X, T, idx):
                                       _dptr(idx, "int32"), idx.shape[0], _dptr(g, "float32"),
                                       ctypes.byref(loss)))
     return g, loss.value
+
+
+def cc_mlp_gradient_noalloc(ctx, X, T, idx, grad, loss=None):
+    """Gradient into the caller's device tensors grad (MLP_NPARAM float32) and
+    loss (1 float32, or None); the library allocates nothing and does not
+    synchronise the stream."""
+    _check(ctx, _ml().cc_mlp_gradient_noalloc(ctx.handle, _dptr(X, "float32"), _dptr(T, "float32"),
+                                              _dptr(idx, "int32"), idx.shape[0], _dptr(grad, "float32"),
+                                              None if loss is None else _dptr(loss, "float32")))
 
 
 def cc_mlp_adam(ctx, grad, lr):

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -156,6 +157,39 @@ void free_mesh(Mesh& M) {
 
 }  // namespace
 
+// Scratch of cc_mlp_gradient_noalloc: the per-wave partial gradients and
+// losses and the loss scalar of one gradient evaluation, in a file-scope
+// device array, so that the entry point allocates nothing.  Each device holds
+// its own copy for the life of the process; host code uses only the device
+// address resolved once per device (scratch_of), never the array's name.
+constexpr size_t NOALLOC_FLOATS = cc::MLP_PART_FLOATS + cc::MLP_LPART_FLOATS + 64;
+static __device__ __align__(256) float scratch[NOALLOC_FLOATS];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<float*> g_scratch;   // device address of `scratch`, by device id
+
+// Resolve (once per device, with that device current) the address of the
+// scratch array; false when the runtime cannot name it.
+bool resolve_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch.size() <= device) g_scratch.resize(device + 1, nullptr);
+  if (g_scratch[device]) return true;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) {
+    (void)hipGetLastError();
+    return false;
+  }
+  g_scratch[device] = static_cast<float*>(p);
+  return true;
+}
+
+float* scratch_of(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return device < (int)g_scratch.size() ? g_scratch[device] : nullptr;
+}
+}  // namespace
+
 struct cc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -286,21 +320,51 @@ bool invert(int D, const double* A, double* Ainv, double& det) {
 
 // Band order of the free vertices: breadth-first search over the free-vertex
 // graph (edge iff two free vertices share an element) from the free vertices
-// that share an element with a Dirichlet vertex, in caller-id order; the
-// unvisited neighbours of each visited vertex are appended in caller-id
-// order (a Cuthill-McKee order without the degree key, which keeps the
-// structured grids' slabs in lexicographic order).  A component with no
-// Dirichlet contact starts from its smallest caller id.  Levels are the
-// breadth-first distances, so every edge joins the same or adjacent levels.
+// that share an element with one connected piece of the Dirichlet set (the
+// piece holding its smallest caller id; several pieces, such as the two held
+// ends of a beam, would start the search from both ends and double the
+// level width), in caller-id order; the unvisited neighbours of each visited
+// vertex are appended in caller-id order (a Cuthill-McKee order without the
+// degree key, which keeps the structured grids' slabs in lexicographic
+// order).  A component reached from no start begins at its smallest caller
+// id.  Levels are the breadth-first distances, so every edge joins the same
+// or adjacent levels.
 void build_band(Mesh& M) {
-  const int nf = M.nf, n = M.n;
+  const int nf = M.nf, n = M.n, K = M.K;
+  // vertex -> elements
+  std::vector<int> vptr(n + 1, 0), vel((size_t)M.m * K);
+  for (int e = 0; e < M.m; ++e)
+    for (int a = 0; a < K; ++a) vptr[M.elems[e * K + a] + 1]++;
+  for (int v = 0; v < n; ++v) vptr[v + 1] += vptr[v];
+  {
+    std::vector<int> fill(vptr.begin(), vptr.end() - 1);
+    for (int e = 0; e < M.m; ++e)
+      for (int a = 0; a < K; ++a) vel[fill[M.elems[e * K + a]]++] = e;
+  }
+  std::vector<char> piece(n, 0);      // the chosen connected piece of the Dirichlet set
+  int f0 = -1;
+  for (int v = 0; v < n && f0 < 0; ++v)
+    if (M.fixed[v]) f0 = v;
+  if (f0 >= 0) {
+    std::vector<int> stack{f0};
+    piece[f0] = 1;
+    while (!stack.empty()) {
+      const int u = stack.back();
+      stack.pop_back();
+      for (int t = vptr[u]; t < vptr[u + 1]; ++t)
+        for (int a = 0; a < K; ++a) {
+          const int w = M.elems[vel[t] * K + a];
+          if (M.fixed[w] && !piece[w]) { piece[w] = 1; stack.push_back(w); }
+        }
+    }
+  }
   std::vector<int> adj_fixed(nf, 0);
   for (int e = 0; e < M.m; ++e) {
-    bool anyfix = false;
-    for (int a = 0; a < M.K; ++a) anyfix |= M.fixed[M.elems[e * M.K + a]] != 0;
-    if (!anyfix) continue;
-    for (int a = 0; a < M.K; ++a) {
-      const int v = M.elems[e * M.K + a];
+    bool touch = false;
+    for (int a = 0; a < K; ++a) touch |= piece[M.elems[e * K + a]] != 0;
+    if (!touch) continue;
+    for (int a = 0; a < K; ++a) {
+      const int v = M.elems[e * K + a];
       if (!M.fixed[v]) adj_fixed[M.vinv[v]] = 1;
     }
   }
@@ -1022,6 +1086,11 @@ cc_status cc_create(int32_t device, void* hip_stream, cc_ctx** out) {
   ctx->stream = (hipStream_t)hip_stream;
   if (hipSetDevice(device) != hipSuccess ||
       hipHostMalloc((void**)&ctx->pinned, 64 * 1024, hipHostMallocDefault) != hipSuccess) {
+    delete ctx;
+    return CC_E_HIP;
+  }
+  if (!resolve_scratch(device)) {   // address of this device's scratch array
+    (void)hipHostFree(ctx->pinned);
     delete ctx;
     return CC_E_HIP;
   }
@@ -1877,8 +1946,8 @@ static void mlp_alloc(cc_ctx* ctx) {
   q.m = dalloc<float>(cc::MLP_NPARAM);
   q.v = dalloc<float>(cc::MLP_NPARAM);
   q.grad = dalloc<float>(cc::MLP_NPARAM);
-  q.part = dalloc<float>((size_t)cc::MLP_MAX_BLOCKS * 4 * cc::MLP_NPARAM);
-  q.lpart = dalloc<float>((size_t)cc::MLP_MAX_BLOCKS * 4);
+  q.part = dalloc<float>(cc::MLP_PART_FLOATS);
+  q.lpart = dalloc<float>(cc::MLP_LPART_FLOATS);
   q.loss = dalloc<float>(1);
   q.W1b = dalloc<uint16_t>(cc::MLP_IN_PAD * cc::MLP_HID);
   q.W2b = dalloc<uint16_t>(cc::MLP_HID * cc::MLP_HID);
@@ -1986,6 +2055,26 @@ cc_status cc_mlp_gradient(cc_ctx* ctx, const float* X, const float* T, const int
     HIPC(hipMemcpyAsync(&l, q.loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
     HIPC(hipStreamSynchronize(ctx->stream));
     if (loss) *loss = l;
+    return CC_OK;
+  });
+}
+
+cc_status cc_mlp_gradient_noalloc(cc_ctx* ctx, const float* X, const float* T, const int32_t* idx,
+                                  int32_t B, float* grad, float* loss) {
+  return guarded(ctx, [&]() -> cc_status {
+    cc_status st = mlp_ready(ctx);
+    if (st != CC_OK) return st;
+    if (!X || !T || !idx || !grad) return fail(ctx, CC_E_INVALID_ARG, "null gradient argument");
+    if (B < 1 || B > CC_MLP_NOALLOC_MAX_ROWS)
+      return fail(ctx, CC_E_INVALID_ARG, "cc_mlp_gradient_noalloc: B must be in 1.." +
+                                             std::to_string(CC_MLP_NOALLOC_MAX_ROWS));
+    float* base = scratch_of(ctx->device);
+    if (!base) return fail(ctx, CC_E_STATE, "scratch address of this device not resolved");
+    float* part = base;
+    float* lpart = base + cc::MLP_PART_FLOATS;
+    float* lslot = lpart + cc::MLP_LPART_FLOATS;
+    cc::mlp_gradient_into(ctx->mlp, X, T, idx, B, grad, loss ? loss : lslot, part, lpart, ctx->stream);
+    HIPC(hipGetLastError());
     return CC_OK;
   });
 }

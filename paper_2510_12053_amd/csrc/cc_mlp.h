@@ -21,6 +21,11 @@ constexpr int MLP_W3 = MLP_B2 + MLP_HID;
 constexpr int MLP_B3 = MLP_W3 + MLP_HID * MLP_OUT;
 constexpr int MLP_NPARAM = MLP_B3 + MLP_OUT;
 constexpr int MLP_MAX_BLOCKS = 256;
+constexpr int MLP_WAVES = 4;           // waves per workgroup of the MLP kernels
+// per-wave partial gradients (MLP_NPARAM floats each) and losses of one
+// gradient evaluation: at most MLP_MAX_BLOCKS * MLP_WAVES waves
+constexpr size_t MLP_PART_FLOATS = (size_t)MLP_MAX_BLOCKS * MLP_WAVES * MLP_NPARAM;
+constexpr size_t MLP_LPART_FLOATS = (size_t)MLP_MAX_BLOCKS * MLP_WAVES;
 
 struct MlpState {
   float* W = nullptr;           // FP32 masters
@@ -43,6 +48,10 @@ void mlp_refresh_bf16(const MlpState& s, hipStream_t st);
 void mlp_forward(const MlpState& s, const float* X, int B, float* Y, hipStream_t st);
 void mlp_gradient(const MlpState& s, const float* X, const float* T, const int* idx, int B, float* grad,
                   float* loss, hipStream_t st);
+// The same with caller-provided partial buffers (part: MLP_PART_FLOATS,
+// lpart: MLP_LPART_FLOATS floats); every partial read is written first.
+void mlp_gradient_into(const MlpState& s, const float* X, const float* T, const int* idx, int B, float* grad,
+                       float* loss, float* part, float* lpart, hipStream_t st);
 void mlp_adam(MlpState& s, const float* grad, float lr, hipStream_t st);
 void mlp_stats(MlpState& s, const float* X, int N, hipStream_t st);
 void launch_features(const MeshView& mv, const double* xt, const double* x0, double h, double E, double mu,

@@ -89,7 +89,6 @@ struct MlpDev {
   const float* istd;    // 16 (reciprocal standard deviations)
 };
 
-constexpr int MLP_WAVES = 4;  // waves per workgroup
 
 // Normalised input tile (16 rows x 16 features) -> LDS, bf16.  Rows past
 // `rows` are zero.  src(row) returns the address of the row's raw features.
@@ -546,11 +545,16 @@ void mlp_forward(const MlpState& s, const float* X, int B, float* Y, hipStream_t
   k_mlp_forward<<<mlp_blocks(B), 64 * MLP_WAVES, 0, st>>>(netdev(s), X, B, Y);
 }
 
+void mlp_gradient_into(const MlpState& s, const float* X, const float* T, const int* idx, int B, float* grad,
+                       float* loss, float* part, float* lpart, hipStream_t st) {
+  const int nb = mlp_blocks(B);
+  k_mlp_train<<<nb, 64 * MLP_WAVES, 0, st>>>(netdev(s), X, T, idx, B, part, lpart);
+  k_mlp_sum<<<(MLP_NPARAM + 255) / 256, 256, 0, st>>>(part, nb * MLP_WAVES, grad, lpart, loss, B);
+}
+
 void mlp_gradient(const MlpState& s, const float* X, const float* T, const int* idx, int B, float* grad,
                   float* loss, hipStream_t st) {
-  const int nb = mlp_blocks(B);
-  k_mlp_train<<<nb, 64 * MLP_WAVES, 0, st>>>(netdev(s), X, T, idx, B, s.part, s.lpart);
-  k_mlp_sum<<<(MLP_NPARAM + 255) / 256, 256, 0, st>>>(s.part, nb * MLP_WAVES, grad, s.lpart, loss, B);
+  mlp_gradient_into(s, X, T, idx, B, grad, loss, s.part, s.lpart, st);
 }
 
 void mlp_adam(MlpState& s, const float* grad, float lr, hipStream_t st) {

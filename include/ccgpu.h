@@ -41,6 +41,8 @@ typedef int32_t cc_status;
 #define CC_OK                0
 #define CC_NOT_CONVERGED     1   /* iteration cap reached; outputs = last iterate   */
 #define CC_STALLED           2   /* line search and its CD fallback both failed    */
+#define CC_GRAPH_FALLBACK    3   /* cc_step_batch: graph capture failed on the stream,
+                                    the iterations ran as direct launches (outputs valid) */
 #define CC_E_INVALID_ARG    -1
 #define CC_E_MESH           -2   /* bad index or non-positive rest volume           */
 #define CC_E_SUBSPACE       -3   /* unsorted / out-of-range / Dirichlet basis index */
@@ -75,7 +77,6 @@ typedef struct {
                              iteration's displacement (Results, basis-quality study)   */
   int32_t max_iters;      /* iteration cap (>= 0)                                      */
   int32_t max_halvings;   /* line-search halvings (>= 0)                               */
-  int32_t check_interval; /* reserved, must be >= 1                                    */
   int32_t quasistatic;    /* 1: E = Psi - m g.x (no inertia, no h^2)                   */
   int32_t warm_start;     /* 0 none, 1 learned proposal set by cc_mlp_set              */
   double  gravity[3];     /* gravitational acceleration; dim 2 uses the first two      */
@@ -87,8 +88,8 @@ typedef struct {
 } cc_params;
 
 /* Fill *p with defaults: CC, Jacobi, per-colour Hessians, FP64, line search on,
-   10000 iterations, 30 halvings, check interval 1, dynamic, no warm start,
-   gravity 0, no corotation. */
+   10000 iterations, 30 halvings, dynamic, no warm start, gravity 0, no
+   corotation. */
 void cc_params_default(cc_params* p);
 
 /* Create a context on HIP device `device`, ordering work on `hip_stream`
@@ -204,12 +205,16 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
    iteration cap is masked out while the others continue.  The launches of
    `iters_per_graph` iterations (cc_batch_tuning) are captured once in a HIP
    graph and replayed, with one host synchronisation per replay; meshes whose
-   energy rises at alpha = 1 are backtracked on the host (same rule as
-   cc_step).  Arrays (host): mesh_ids[n]; x[n], v[n] and x_bc[n] hold device
+   energy rises at alpha = 1 backtrack together on the device, eight halvings
+   per launch, taking the first that does not raise E (the rule of cc_step),
+   and only a mesh whose halvings run out goes to the host for the
+   coordinate-descent fallback.  Arrays (host): mesh_ids[n]; x[n], v[n] and x_bc[n] hold device
    pointers as in cc_step (x_bc may be NULL or contain NULLs); gravity is
    n x 3 (host) or NULL to use params->gravity for every mesh.  Outputs
    (host, n each): iters, rel_grad, status (per-mesh cc_status).  The return
-   value is the worst per-mesh status (errors before warnings).  The stream
+   value is the worst per-mesh status (errors before warnings), or
+   CC_GRAPH_FALLBACK when the graph capture failed and the iterations ran
+   as direct launches (every output valid).  The stream
    given to cc_create must not be the legacy null stream for graph capture;
    with it the launches run uncaptured. */
 cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double* const* x,

@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libccgpu.so")
 
-CC_OK, CC_NOT_CONVERGED, CC_STALLED = 0, 1, 2
+CC_OK, CC_NOT_CONVERGED, CC_STALLED, CC_GRAPH_FALLBACK = 0, 1, 2, 3
 METHOD_CD, METHOD_CC, METHOD_JGS2 = 0, 1, 2
 SWEEP_JACOBI, SWEEP_COLORED_GS = 0, 1
 HESS_PER_COLOR, HESS_PER_SWEEP = 0, 1
@@ -24,7 +24,8 @@ FP64, FP32_MIXED = 0, 1
 MATERIAL_SNH, MATERIAL_FCR = 0, 1
 
 _STATUS_NAMES = {
-    0: "CC_OK", 1: "CC_NOT_CONVERGED", 2: "CC_STALLED", -1: "CC_E_INVALID_ARG", -2: "CC_E_MESH",
+    0: "CC_OK", 1: "CC_NOT_CONVERGED", 2: "CC_STALLED", 3: "CC_GRAPH_FALLBACK", -1: "CC_E_INVALID_ARG",
+    -2: "CC_E_MESH",
     -3: "CC_E_SUBSPACE", -4: "CC_E_HIP", -5: "CC_E_NONFINITE", -6: "CC_E_STATE", -7: "CC_E_NO_DEVICE",
 }
 
@@ -39,7 +40,7 @@ class cc_params(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("sweep", ctypes.c_int32),
                 ("hess_refresh", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("line_search", ctypes.c_int32), ("max_iters", ctypes.c_int32),
-                ("max_halvings", ctypes.c_int32), ("check_interval", ctypes.c_int32),
+                ("max_halvings", ctypes.c_int32),
                 ("quasistatic", ctypes.c_int32), ("warm_start", ctypes.c_int32),
                 ("gravity", ctypes.c_double * 3), ("corotate", ctypes.c_int32)]
 

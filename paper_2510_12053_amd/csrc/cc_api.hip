@@ -34,11 +34,13 @@ struct Mesh {
   // device: static mesh data
   int *ev = nullptr, *star_ptr = nullptr, *star = nullptr, *d_rowptr = nullptr, *d_colidx = nullptr,
       *blkrow = nullptr, *cptr = nullptr, *centry = nullptr, *d_vperm = nullptr, *d_vinv = nullptr,
-      *d_eperm = nullptr, *d_sorder = nullptr, *d_aorder = nullptr;
+      *d_eperm = nullptr, *d_sorder = nullptr, *d_aorder = nullptr, *d_cel_ptr = nullptr, *d_cel = nullptr,
+      *d_csl_ptr = nullptr, *d_csl = nullptr;
   // band order of the free vertices and the upper-block structure of the
   // dense condensation (MeshView::bvert ...); lev_off: breadth-first levels
   // in band positions (every block couples the same or adjacent levels)
   std::vector<int> bvert_h, bpos_h, lev_off;
+  std::vector<int> cel_ptr_h, csl_ptr_h;   // per-colour dirty element / slot list offsets
   int *d_bvert = nullptr, *d_bpos = nullptr, *d_bqcnt = nullptr, *d_bqpos = nullptr, *d_hqslot = nullptr;
   void* hq = nullptr;
   int qmax = 0, band_w = 0;
@@ -87,6 +89,7 @@ struct Mesh {
     v.smap = smap; v.smap_words = smap_words; v.smap_supp = smap_supp;
     v.sorder = d_sorder;
     v.aorder = d_aorder;
+    v.cel_ptr = d_cel_ptr; v.cel = d_cel; v.csl_ptr = d_csl_ptr; v.csl = d_csl;
     return v;
   }
 };
@@ -147,7 +150,8 @@ void free_mesh(Mesh& M) {
   dfree(M.ev); dfree(M.star_ptr); dfree(M.star); dfree(M.d_rowptr); dfree(M.d_colidx);
   dfree(M.blkrow); dfree(M.cptr); dfree(M.centry); dfree(M.d_vperm); dfree(M.d_vinv);
   dfree(M.d_bvert); dfree(M.d_bpos); dfree(M.d_bqcnt); dfree(M.d_bqpos); dfree(M.d_hqslot); dfree(M.hq);
-  dfree(M.d_eperm); dfree(M.d_sorder); dfree(M.d_aorder); dfree(M.dinv_d); dfree(M.vol_d); dfree(M.mass); dfree(M.dinv_f); dfree(M.vol_f);
+  dfree(M.d_eperm); dfree(M.d_sorder); dfree(M.d_aorder);
+  dfree(M.d_cel_ptr); dfree(M.d_cel); dfree(M.d_csl_ptr); dfree(M.d_csl); dfree(M.dinv_d); dfree(M.vol_d); dfree(M.mass); dfree(M.dinv_f); dfree(M.vol_f);
   free_basis(M);
   dfree(M.x); dfree(M.xt); dfree(M.x0); dfree(M.xtrial); dfree(M.dvec); dfree(M.g);
   dfree(M.partials); dfree(M.scal); dfree(M.estore); dfree(M.hb); dfree(M.KL); dfree(M.fb);
@@ -610,6 +614,36 @@ void build_mesh(cc_ctx* ctx, Mesh& M) {
     for (int j : so)
       for (int t = M.rowptr[j]; t < M.rowptr[j + 1]; ++t) ao.push_back(t);
     M.d_aorder = dupload(ao, s);
+    // per colour: elements with a free vertex of the colour (element order),
+    // and the block slots they contribute to (assembly order)
+    std::vector<int> slot_rank(M.nnzb);
+    for (size_t r = 0; r < ao.size(); ++r) slot_rank[ao[r]] = (int)r;
+    std::vector<int> cel_ptr(M.ncol + 1, 0), cel, csl_ptr(M.ncol + 1, 0), csl;
+    std::vector<int> emark(m, -1), smark(M.nnzb, -1);
+    for (int c = 0; c < M.ncol; ++c) {
+      for (int e = 0; e < m; ++e)
+        for (int a = 0; a < K; ++a) {
+          const int v = ev[(size_t)a * m + e];
+          if (v < nf && M.colour[M.vperm[v]] == c) { emark[e] = c; break; }
+        }
+      for (int e = 0; e < m; ++e)
+        if (emark[e] == c) cel.push_back(e);
+      cel_ptr[c + 1] = (int)cel.size();
+      std::vector<int> sl;
+      for (int t = 0; t < M.nnzb; ++t)
+        for (int q = cptr[t]; q < cptr[t + 1]; ++q)
+          if (emark[centry[q] >> 4] == c) { sl.push_back(t); break; }
+      std::sort(sl.begin(), sl.end(), [&](int a, int b) { return slot_rank[a] < slot_rank[b]; });
+      csl.insert(csl.end(), sl.begin(), sl.end());
+      csl_ptr[c + 1] = (int)csl.size();
+    }
+    (void)smark;
+    M.d_cel_ptr = dupload(cel_ptr, s);
+    M.d_cel = dupload(cel, s);
+    M.d_csl_ptr = dupload(csl_ptr, s);
+    M.d_csl = dupload(csl, s);
+    M.cel_ptr_h = cel_ptr;
+    M.csl_ptr_h = csl_ptr;
   }
   M.d_eperm = dupload(M.eperm, s);
   {  // warm-start data: all neighbours, rest positions, mean rest edge length
@@ -1005,15 +1039,23 @@ struct Stepper {
     int np = 0;
     ctx->timed(CC_K_GRADIENT, [&] { cc::launch_gradient(mv, x, M.xt, mat, M.g, M.partials, &np, s); });
   }
-  void hessian(const double* x) {
+  // Element Hessians and block rows at x: of every element (colour < 0), or
+  // only of those that the moves of colour `colour`'s vertices changed.
+  void hessian(const double* x, int colour = -1) {
     mv.rot = p.corotate ? M.rot : nullptr;   // corotation: rotations at the Hessian's positions
     if (p.corotate) {
       if (!M.rot || !M.nptr || !M.nidx || !M.Xr)
         throw ApiError{CC_E_STATE, "corotation buffers missing"};
       cc::launch_rotations(mv, x, M.nptr, M.nidx, M.Xr, M.rot, s);
     }
-    ctx->timed(CC_K_ELEM_HESS, [&] { cc::launch_elem_hess(mv, p.precision, x, mat, mat.s_el, M.estore, s); });
-    ctx->timed(CC_K_ASSEMBLE, [&] { cc::launch_assemble(mv, p.precision, M.estore, mat, M.hb, s); });
+    const int* el = colour < 0 ? nullptr : mv.cel + M.cel_ptr_h[colour];
+    const int ne = colour < 0 ? M.m : M.cel_ptr_h[colour + 1] - M.cel_ptr_h[colour];
+    const int* sl = colour < 0 ? nullptr : mv.csl + M.csl_ptr_h[colour];
+    const int ns = colour < 0 ? M.nnzb : M.csl_ptr_h[colour + 1] - M.csl_ptr_h[colour];
+    ctx->timed(CC_K_ELEM_HESS, [&] {
+      cc::launch_elem_hess_list(mv, p.precision, x, mat, mat.s_el, M.estore, s, el, ne);
+    });
+    ctx->timed(CC_K_ASSEMBLE, [&] { cc::launch_assemble_list(mv, p.precision, M.estore, mat, M.hb, s, sl, ns); });
   }
   void prep(int method, int v0, int v1) {
     ctx->timed(CC_K_CC_PREP, [&] { cc::launch_cc_prep(mv, p.precision, method, v0, v1, M.hb, M.KL, M.fb, s); });
@@ -1041,13 +1083,26 @@ struct Stepper {
       return;
     }
     HIPC(hipMemcpyAsync(out, x, (size_t)nd * sizeof(double), hipMemcpyDeviceToDevice, s));
+    int moved = -1;   // the last colour that moved in this sweep
     for (int c = 0; c < M.ncol; ++c) {
       const int v0 = M.coff[c], v1 = M.coff[c + 1];
       if (v1 <= v0) continue;
       if (p.hess_refresh == CC_HESS_PER_COLOR) {
-        hessian(out);
-        prep(method, v0, v1);
-      } else if (c == 0) {
+        // every Hessian at the sweep's start, then only what the previous
+        // colour's moves changed
+        hessian(out, moved);
+        moved = c;
+        gradient_only(out);
+        // a dense basis forms b_i from this gradient and moves the colour's
+        // vertices in the finish kernel; other bases take the update kernel
+        bool done = false;
+        ctx->timed(CC_K_CC_PREP, [&] {
+          done = cc::launch_cc_prep(mv, p.precision, method, v0, v1, M.hb, M.KL, M.fb, s, M.g, M.dvec, out);
+        });
+        if (!done) update(method, v0, v1, out, 1);
+        continue;
+      }
+      if (c == 0) {
         hessian(out);
         prep(method, 0, M.nf);
       }
@@ -1071,7 +1126,6 @@ void cc_params_default(cc_params* p) {
   p->line_search = 1;
   p->max_iters = 10000;
   p->max_halvings = 30;
-  p->check_interval = 1;
 }
 
 cc_status cc_create(int32_t device, void* hip_stream, cc_ctx** out) {
@@ -1355,7 +1409,7 @@ static cc_status check_params(cc_ctx* ctx, const cc_params* p, const Mesh& M, do
   if (!p) return fail(ctx, CC_E_INVALID_ARG, "null params");
   if (p->method < 0 || p->method > 2 || p->sweep < 0 || p->sweep > 1 || p->hess_refresh < 0 ||
       p->hess_refresh > 1 || p->precision < 0 || p->precision > 1 || p->max_iters < 0 ||
-      p->max_halvings < 0 || p->check_interval < 1)
+      p->max_halvings < 0)
     return fail(ctx, CC_E_INVALID_ARG, "bad solver parameters");
   if (!p->quasistatic && !(dt > 0)) return fail(ctx, CC_E_INVALID_ARG, "dt must be positive");
   if (p->method != CC_METHOD_CD && !M.has_basis)
@@ -1564,6 +1618,10 @@ static cc::BatchItem make_item(Mesh& M, const Material& mat) {
   it.nptr = M.nptr; it.nidx = M.nidx; it.Xr = M.Xr; it.ell = M.ell; it.youngs = M.E;
   it.ncol = M.ncol;
   for (int c = 0; c <= M.ncol && c <= cc::MAX_COLOURS; ++c) it.coff[c] = M.coff[c];
+  for (int c = 0; c < M.ncol && c < cc::MAX_COLOURS; ++c) {
+    it.cel_n[c] = M.cel_ptr_h[c + 1] - M.cel_ptr_h[c];
+    it.csl_n[c] = M.csl_ptr_h[c + 1] - M.csl_ptr_h[c];
+  }
   return it;
 }
 
@@ -1776,7 +1834,7 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
       bool any = false;
       for (auto& c : ctl) any = any || c.active;
       if (!any) break;
-      cc::batch_iterate(plan, (queue + k - 1) / k * k, s);
+      HIPC(cc::batch_iterate(plan, (queue + k - 1) / k * k, s));
       queue = k;
       if (!cc::batch_has_graph(plan) && !ctx->graph_pairs.empty()) ctx->drop_graph_pairs();
       pull_ctl();
@@ -1878,9 +1936,16 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
       if (rel_grad) rel_grad[i] = ctl[i].r;
       if (status) status[i] = stt;
       M.last_E = ctl[i].E_cur;
-      M.last_paper = 0;
+      {  // the paper's normalised residual |g| / (V n E), divided by h when dynamic
+        const double pm = ctl[i].r * ctl[i].g0 / (M.volume * M.n * M.E);
+        M.last_paper = p.quasistatic ? pm : pm / dt;
+      }
       M.last_warm = ctl[i].warm;
       if (stt < 0 ? (worst >= 0 || stt < worst) : (worst >= 0 && stt > worst)) worst = stt;
+    }
+    if (worst >= 0 && worst < CC_GRAPH_FALLBACK && cc::batch_capture_failed(plan)) {
+      ctx->err = "graph capture failed on this stream: the iterations ran as direct launches";
+      worst = CC_GRAPH_FALLBACK;
     }
     return worst;
   });

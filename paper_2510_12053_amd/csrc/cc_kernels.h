@@ -68,6 +68,14 @@ struct MeshView {
   const int* sorder;
   // block-row slots row by row in that order: the order assembly visits them
   const int* aorder;
+  // coloured sweeps: the elements with a free vertex of colour c,
+  // cel[cel_ptr[c] .. cel_ptr[c+1]), and the block slots those elements
+  // contribute to, csl[csl_ptr[c] .. csl_ptr[c+1]) (in the assembly order);
+  // after colour c moves, only these need re-evaluating
+  const int* cel_ptr;
+  const int* cel;
+  const int* csl_ptr;
+  const int* csl;
 };
 
 constexpr int SMAP_SELF = 254;
@@ -96,14 +104,22 @@ void launch_elem_hess(const MeshView& mv, int prec, const double* x, const Mater
                       double scale, void* estore, hipStream_t s);
 void launch_assemble(const MeshView& mv, int prec, const void* estore, const Material& mat,
                      void* hb, hipStream_t s);
+// The same over a list of `count` elements / block slots (device ints; null:
+// the first `count` of all), e.g. the ones a colour's moves change
+// (MeshView::cel, csl).
+void launch_elem_hess_list(const MeshView& mv, int prec, const double* x, const Material& mat,
+                           double scale, void* estore, hipStream_t s, const int* elist, int count);
+void launch_assemble_list(const MeshView& mv, int prec, const void* estore, const Material& mat, void* hb,
+                          hipStream_t s, const int* slist, int count);
 void launch_gradient(const MeshView& mv, const double* x, const double* xt, const Material& mat,
                      double* g, double* partials, int* nparts, hipStream_t s);
-// Condensation of vertices [v0, v1).  With g and dout given (a Jacobi sweep,
-// g the gradient at the same x) the dense path also writes the directions
-// into dout; the return value says whether it did (else launch_cc_update).
+// Condensation of vertices [v0, v1).  With g and dout given (g the gradient
+// at the same x) the dense path also writes the directions into dout, and
+// with xmove given (a coloured sweep) adds them to xmove in place; the
+// return value says whether it did (else launch_cc_update).
 bool launch_cc_prep(const MeshView& mv, int prec, int method, int v0, int v1, const void* hb,
                     void* KL, unsigned long long* fallbacks, hipStream_t s,
-                    const double* g = nullptr, double* dout = nullptr);
+                    const double* g = nullptr, double* dout = nullptr, double* xmove = nullptr);
 void launch_cc_update(const MeshView& mv, int prec, int method, int v0, int v1, const void* KL,
                       const double* g, double* x_or_d, int accumulate, hipStream_t s);
 void launch_energy(const MeshView& mv, const double* x, const double* xt, const Material& mat,
@@ -169,6 +185,9 @@ struct BatchItem {
   const double* Xr;
   double ell, youngs;
   int feat_off;
+  // coloured sweeps: sizes of the per-colour dirty element / slot lists
+  int cel_n[MAX_COLOURS];
+  int csl_n[MAX_COLOURS];
 };
 
 // Per-mesh iteration state, device-resident.
@@ -205,8 +224,11 @@ BatchItem* batch_items_dev(BatchPlan* p);
 BatchCtl* batch_ctl_dev(BatchPlan* p);
 // Start of a step: predictor, initial gradient norm and energy, control reset.
 void batch_begin(BatchPlan* p, hipStream_t s);
-// Run `iters` iterations (graph replay when captured).
-void batch_iterate(BatchPlan* p, int iters, hipStream_t s);
+// Run `iters` iterations (graph replay when captured); returns the first
+// launch error.  When the capture itself fails the launches run uncaptured
+// from then on and batch_capture_failed reports it.
+hipError_t batch_iterate(BatchPlan* p, int iters, hipStream_t s);
+int batch_capture_failed(BatchPlan* p);
 // Velocities and caller positions.
 void batch_finish(BatchPlan* p, hipStream_t s);
 // Learned warm start after batch_begin: feat / delta hold sum(nf) rows.

@@ -100,15 +100,23 @@ __device__ __forceinline__ void elem_hess_body(const MeshView& mv, int e, const 
 constexpr int EWG = 64;
 template <typename T> constexpr int elem_threads() { return sizeof(T) == 8 ? 2 * EWG : EWG; }
 
+// Element index of slot idx: idx itself, or entry idx of a list of ecount
+// elements (past its end: m, which the body skips).
+__device__ __forceinline__ int elem_of(const MeshView& mv, int idx, const int* elist, int ecount) {
+  if (elist == nullptr) return idx;
+  return idx < ecount ? elist[idx] : mv.m;
+}
+
 template <typename T, int D>
 __device__ __forceinline__ void elem_hess_split(const MeshView& mv, int e0, const double* __restrict__ x,
-                                                T mu, T lam, int model, T scale, T* __restrict__ out) {
+                                                T mu, T lam, int model, T scale, T* __restrict__ out,
+                                                const int* elist = nullptr, int ecount = 0) {
   if constexpr (sizeof(T) == 8) {
-    const int e = e0 + threadIdx.x % EWG;
+    const int e = elem_of(mv, e0 + threadIdx.x % EWG, elist, ecount);
     if (threadIdx.x < EWG) elem_hess_body<T, D, 1>(mv, e, x, mu, lam, model, scale, out);
     else elem_hess_body<T, D, 2>(mv, e, x, mu, lam, model, scale, out);
   } else {
-    elem_hess_body<T, D, 0>(mv, e0 + threadIdx.x, x, mu, lam, model, scale, out);
+    elem_hess_body<T, D, 0>(mv, elem_of(mv, e0 + threadIdx.x, elist, ecount), x, mu, lam, model, scale, out);
   }
 }
 constexpr int LS_WIDTH = 8;   // backtracking halvings evaluated per launch
@@ -116,20 +124,22 @@ constexpr int LS_WIDTH = 8;   // backtracking halvings evaluated per launch
 template <typename T, int D, bool FCR>
 __global__ void __launch_bounds__(elem_threads<T>()) k_elem_hess(MeshView mv, const double* __restrict__ x,
                                                                  T mu, T lam, int model, T scale,
-                                                                 T* __restrict__ out) {
-  elem_hess_split<T, D>(mv, blockIdx.x * EWG, x, mu, lam, FCR ? model : MAT_SNH, scale, out);
+                                                                 T* __restrict__ out, const int* elist,
+                                                                 int ecount) {
+  elem_hess_split<T, D>(mv, blockIdx.x * EWG, x, mu, lam, FCR ? model : MAT_SNH, scale, out, elist, ecount);
 }
 
 // Block rows: every slot sums its element contributions (fixed order), plus
 // the mass on the diagonal.
 template <typename T, int D>
 __device__ __forceinline__ void assemble_body(const MeshView& mv, int tt, const T* __restrict__ est,
-                                              T w_in, T* __restrict__ hb) {
+                                              T w_in, T* __restrict__ hb, const int* slist = nullptr,
+                                              int scount = 0) {
   constexpr int K = D + 1, DD = D * D;
-  if (tt >= mv.nnzb) return;
+  if (tt >= (slist ? scount : mv.nnzb)) return;
   // slots row by row in caller order of the rows: neighbouring threads then
-  // read the blocks of neighbouring elements
-  const int t = mv.aorder ? mv.aorder[tt] : tt;
+  // read the blocks of neighbouring elements (a colour's list keeps that order)
+  const int t = slist ? slist[tt] : (mv.aorder ? mv.aorder[tt] : tt);
   T acc[DD];
 #pragma unroll
   for (int r = 0; r < DD; ++r) acc[r] = T(0);
@@ -196,8 +206,8 @@ __device__ __forceinline__ void assemble_body(const MeshView& mv, int tt, const 
 
 template <typename T, int D>
 __global__ void __launch_bounds__(EWG) k_assemble(MeshView mv, const T* __restrict__ est, T w_in,
-                                                  T* __restrict__ hb) {
-  assemble_body<T, D>(mv, blockIdx.x * EWG + threadIdx.x, est, w_in, hb);
+                                                  T* __restrict__ hb, const int* slist, int scount) {
+  assemble_body<T, D>(mv, blockIdx.x * EWG + threadIdx.x, est, w_in, hb, slist, scount);
 }
 
 // Vertex of gradient slot idx: the free vertices in caller order, so that
@@ -543,11 +553,20 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
       for (int v = 0; v < TV; ++v)
 #pragma unroll
         for (int r = 0; r < DD; ++r) W[v][r] = T(0);
-      for (int q = 0; q < cnt; ++q) {
-        const int kp = bq_pos[(size_t)q * nf + p] & msk;
-        T H[DD];
+      // software pipeline: the column and the H block of upper block q + 1
+      // are loaded while block q's LDS reads and products run (the LDS
+      // addresses depend on a global load, whose latency would otherwise
+      // stall every block at two waves per SIMD)
+      int kp = bq_pos[p] & msk;
+      T H[DD];
 #pragma unroll
-        for (int r = 0; r < DD; ++r) H[r] = gptr(hq)[((size_t)q * DD + r) * nf + p];
+      for (int r = 0; r < DD; ++r) H[r] = gptr(hq)[(size_t)r * nf + p];
+      for (int q = 0; q < cnt; ++q) {
+        const int qn = min(q + 1, cnt - 1);   // the last block loads itself again
+        const int kpn = bq_pos[(size_t)qn * nf + p] & msk;
+        T Hn[DD];
+#pragma unroll
+        for (int r = 0; r < DD; ++r) Hn[r] = gptr(hq)[((size_t)qn * DD + r) * nf + p];
 #pragma unroll
         for (int v = 0; v < TV; ++v) {
           T U[DD];
@@ -563,6 +582,9 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
               W[v][r * D + c] = acc;
             }
         }
+        kp = kpn;
+#pragma unroll
+        for (int r = 0; r < DD; ++r) H[r] = Hn[r];
       }
       T gj[D];
       if (g != nullptr) {
@@ -680,8 +702,7 @@ __device__ __forceinline__ void dm_finish_body(const MeshView& mv, int method, i
                                                const T* __restrict__ hb, T* __restrict__ KL,
                                                unsigned long long* __restrict__ fb,
                                                const double* __restrict__ g, double* __restrict__ dout,
-                                               const double* __restrict__ x = nullptr,
-                                               double* __restrict__ xtrial = nullptr) {
+                                               const double* x = nullptr, double* xtrial = nullptr) {
   constexpr int DD = D * D;
   T A[DD], Ht[DD];
   const T* in = KL + (size_t)i * 2 * DD;
@@ -710,7 +731,8 @@ __device__ __forceinline__ void dm_finish_body(const MeshView& mv, int method, i
 #pragma unroll
     for (int l = 0; l < D; ++l) acc += kl[r * D + l] * gt[l];
     dout[(size_t)r * n + i] = -double(acc);
-    // the Jacobi trial point x + d of this vertex (the batched path's axpy)
+    // the trial point x + d of this vertex (Jacobi: the batched path's axpy;
+    // coloured sweep: x and xtrial are the same running state, moved in place)
     if (xtrial != nullptr) xtrial[(size_t)r * n + i] = x[(size_t)r * n + i] - double(acc);
   }
 }
@@ -719,9 +741,10 @@ template <typename T, int D>
 __global__ void __launch_bounds__(WG) k_cc_dm_finish(MeshView mv, int method, int v0, int v1,
                                                      const T* __restrict__ hb, T* __restrict__ KL,
                                                      unsigned long long* __restrict__ fb,
-                                                     const double* __restrict__ g, double* __restrict__ dout) {
+                                                     const double* __restrict__ g, double* __restrict__ dout,
+                                                     double* __restrict__ xmove) {
   const int i = v0 + blockIdx.x * WG + threadIdx.x;
-  if (i < v1) dm_finish_body<T, D>(mv, method, i, hb, KL, fb, g, dout);
+  if (i < v1) dm_finish_body<T, D>(mv, method, i, hb, KL, fb, g, dout, xmove, xmove);
 }
 
 template <typename T, int D, int TV>
@@ -1028,31 +1051,42 @@ void launch_finalize(const MeshView& mv, const int* vperm, const double* x, cons
                                                                     x_user, v_user));
 }
 
-void launch_elem_hess(const MeshView& mv, int prec, const double* x, const Material& mat,
-                      double scale, void* estore, hipStream_t s) {
-  if (mv.m == 0) return;
-  const int nb = nblocks(mv.m, EWG);
+void launch_elem_hess_list(const MeshView& mv, int prec, const double* x, const Material& mat,
+                           double scale, void* estore, hipStream_t s, const int* elist, int count) {
+  if (count <= 0) return;
+  const int nb = nblocks(count, EWG);
   if (prec == 0)
     CC_DISPATCH_MAT(mat.model == MAT_FCR,
                     CC_DISPATCH_D(mv.D, k_elem_hess<double, D, FCR><<<nb, elem_threads<double>(), 0, s>>>(
-                                            mv, x, mat.mu, mat.lam, mat.model, scale, (double*)estore)));
+                                            mv, x, mat.mu, mat.lam, mat.model, scale, (double*)estore, elist,
+                                            count)));
   else
     CC_DISPATCH_MAT(mat.model == MAT_FCR,
                     CC_DISPATCH_D(mv.D, k_elem_hess<float, D, FCR><<<nb, elem_threads<float>(), 0, s>>>(
                                             mv, x, (float)mat.mu, (float)mat.lam, mat.model, (float)scale,
-                                            (float*)estore)));
+                                            (float*)estore, elist, count)));
+}
+
+void launch_elem_hess(const MeshView& mv, int prec, const double* x, const Material& mat,
+                      double scale, void* estore, hipStream_t s) {
+  launch_elem_hess_list(mv, prec, x, mat, scale, estore, s, nullptr, mv.m);
 }
 
 void launch_assemble(const MeshView& mv, int prec, const void* estore, const Material& mat,
                      void* hb, hipStream_t s) {
-  if (mv.nnzb == 0) return;
-  const int nb = nblocks(mv.nnzb, EWG);
+  launch_assemble_list(mv, prec, estore, mat, hb, s, nullptr, mv.nnzb);
+}
+
+void launch_assemble_list(const MeshView& mv, int prec, const void* estore, const Material& mat, void* hb,
+                          hipStream_t s, const int* slist, int count) {
+  if (count <= 0) return;
+  const int nb = nblocks(count, EWG);
   if (prec == 0)
-    CC_DISPATCH_D(mv.D, k_assemble<double, D><<<nb, EWG, 0, s>>>(mv, (const double*)estore,
-                                                               mat.w_in, (double*)hb));
+    CC_DISPATCH_D(mv.D, k_assemble<double, D><<<nb, EWG, 0, s>>>(mv, (const double*)estore, mat.w_in,
+                                                               (double*)hb, slist, count));
   else
-    CC_DISPATCH_D(mv.D, k_assemble<float, D><<<nb, EWG, 0, s>>>(mv, (const float*)estore,
-                                                              (float)mat.w_in, (float*)hb));
+    CC_DISPATCH_D(mv.D, k_assemble<float, D><<<nb, EWG, 0, s>>>(mv, (const float*)estore, (float)mat.w_in,
+                                                              (float*)hb, slist, count));
 }
 
 constexpr int GRAD_G = 16;   // lanes per vertex of the gradient: a 3D star holds about 24 elements
@@ -1151,25 +1185,27 @@ static bool band_ok(const MeshView& mv, int prec) {
 
 template <typename T, int D>
 static bool prep_dense(const MeshView& mv, int prec, int method, int v0, int v1, const void* hb,
-                       void* KL, unsigned long long* fb, const double* g, double* dout, hipStream_t s) {
+                       void* KL, unsigned long long* fb, const double* g, double* dout, double* xmove,
+                       hipStream_t s) {
   if (method == 0 || !band_ok(mv, prec)) return false;
   const int tv = dense_tv(mv.ring, D, prec);
   const size_t lds = dense_lds_bytes(tv, mv.ring, D, prec);
   CC_DISPATCH_TV(tv, k_cc_prep_band<T, D, TV><<<nblocks(v1 - v0, TV), BWG, lds, s>>>(
                          mv, method, v0, v1, (const T*)hb, (T*)KL, g, dout));
   k_cc_dm_finish<T, D><<<nblocks(v1 - v0, WG), WG, 0, s>>>(mv, method, v0, v1, (const T*)hb, (T*)KL, fb,
-                                                          g, dout);
+                                                          g, dout, g != nullptr ? xmove : nullptr);
   return true;
 }
 
 bool launch_cc_prep(const MeshView& mv, int prec, int method, int v0, int v1, const void* hb,
-                    void* KL, unsigned long long* fb, hipStream_t s, const double* g, double* dout) {
+                    void* KL, unsigned long long* fb, hipStream_t s, const double* g, double* dout,
+                    double* xmove) {
   if (v1 <= v0) return g != nullptr;
   bool done = false;
   if (prec == 0)
-    CC_DISPATCH_D(mv.D, done = prep_dense<double, D>(mv, prec, method, v0, v1, hb, KL, fb, g, dout, s));
+    CC_DISPATCH_D(mv.D, done = prep_dense<double, D>(mv, prec, method, v0, v1, hb, KL, fb, g, dout, xmove, s));
   else
-    CC_DISPATCH_D(mv.D, done = prep_dense<float, D>(mv, prec, method, v0, v1, hb, KL, fb, g, dout, s));
+    CC_DISPATCH_D(mv.D, done = prep_dense<float, D>(mv, prec, method, v0, v1, hb, KL, fb, g, dout, xmove, s));
   if (done) return g != nullptr;
   const int G = support_lanes(mv);
   if (prec == 0) CC_DISPATCH_D(mv.D, prep_g<double, D>(mv, method, v0, v1, hb, KL, fb, G, s));
@@ -1389,13 +1425,18 @@ __global__ void __launch_bounds__(WG) kb_finalize(const BatchItem* __restrict__ 
 template <typename T, int D, bool FCR>
 __global__ void __launch_bounds__(elem_threads<T>()) kb_elem_hess(const BatchItem* __restrict__ items,
                                                    const BatchCtl* __restrict__ ctl,
-                                                   const int* __restrict__ boff, int nmesh, int which) {
+                                                   const int* __restrict__ boff, int nmesh, int which,
+                                                   int colour) {
   const int mi = block_mesh(boff, nmesh, blockIdx.x);
   if (!ctl[mi].active) return;
   const BatchItem& it = items[mi];
   const MeshView mv = it.mv;
+  // colour >= 0: only the elements that colour's moves changed
+  const bool lst = colour >= 0 && colour < it.ncol;
+  const int* el = lst ? mv.cel + mv.cel_ptr[colour] : nullptr;
+  const int cnt = lst ? mv.cel_ptr[colour + 1] - mv.cel_ptr[colour] : mv.m;
   elem_hess_split<T, D>(mv, (blockIdx.x - boff[mi]) * EWG, pick(it, which), T(it.mat.mu), T(it.mat.lam),
-                        FCR ? it.mat.model : MAT_SNH, T(it.mat.s_el), (T*)it.estore);
+                        FCR ? it.mat.model : MAT_SNH, T(it.mat.s_el), (T*)it.estore, el, cnt);
 }
 
 // Corotation: vertex rotations of every mesh at positions `which`.
@@ -1414,13 +1455,16 @@ __global__ void __launch_bounds__(WG) kb_rotations(const BatchItem* __restrict__
 template <typename T, int D>
 __global__ void __launch_bounds__(EWG) kb_assemble(const BatchItem* __restrict__ items,
                                                   const BatchCtl* __restrict__ ctl,
-                                                  const int* __restrict__ boff, int nmesh) {
+                                                  const int* __restrict__ boff, int nmesh, int colour) {
   const int mi = block_mesh(boff, nmesh, blockIdx.x);
   if (!ctl[mi].active) return;
   const BatchItem& it = items[mi];
   const MeshView mv = it.mv;
+  const bool lst = colour >= 0 && colour < it.ncol;
+  const int* sl = lst ? mv.csl + mv.csl_ptr[colour] : nullptr;
+  const int cnt = lst ? mv.csl_ptr[colour + 1] - mv.csl_ptr[colour] : mv.nnzb;
   assemble_body<T, D>(mv, (blockIdx.x - boff[mi]) * EWG + threadIdx.x, (const T*)it.estore,
-                      T(it.mat.w_in), (T*)it.hb);
+                      T(it.mat.w_in), (T*)it.hb, sl, cnt);
 }
 
 template <int D, int G, bool FCR>
@@ -1486,9 +1530,11 @@ __global__ void __launch_bounds__(WG) kb_dm_finish(const BatchItem* __restrict__
   int v0, v1;
   vertex_range(it, colour, v0, v1);
   const int i = v0 + (blockIdx.x - boff[mi]) * WG + threadIdx.x;
+  // fuse 1 (Jacobi): xtrial = x + d; fuse 2 (coloured sweep): the colour's
+  // vertices move in place in the sweep's running state xtrial
   if (i < v1)
     dm_finish_body<T, D>(it.mv, method, i, (const T*)it.hb, (T*)it.KL, it.fb, fuse ? it.g : nullptr,
-                         fuse ? it.d : nullptr, it.x, fuse ? it.xtrial : nullptr);
+                         fuse ? it.d : nullptr, fuse == 2 ? it.xtrial : it.x, fuse ? it.xtrial : nullptr);
 }
 
 template <typename T, int D, int G>
@@ -1798,6 +1844,7 @@ struct BatchPlan {
   BatchCtl* ctl_d = nullptr;
   Offsets pred, elem, asmb, grad, energy, axpy, axpyj, feat, rotn;   // axpyj: Jacobi trial points
   Offsets eg;       // energy then gradient blocks of each mesh (kb_energy_grad)
+  std::vector<Offsets> elemc, asmbc;   // element / slot blocks of colour c's dirty lists
   std::vector<Offsets> prep, prepd, fin, upd;   // index 0: all free vertices, c+1: colour c
   int max_colours = 0;
   int tv = 0;       // vertices per workgroup of the dense condensation (0: no dense mesh)
@@ -1811,6 +1858,7 @@ struct BatchPlan {
   BatchHook hook = nullptr;
   void* hook_user = nullptr;
   int capturing = 0;
+  int capture_failed = 0;   // graph capture failed: the iterations run uncaptured
   void mark(int kid, int begin) { if (hook) hook(hook_user, kid, begin); }
 };
 
@@ -1860,13 +1908,28 @@ static void plan_vertex_offsets(BatchPlan* p, hipStream_t s) {
       cp[m] = it.prep_dense ? 0 : nblocks(cnt, WG / G);
       cd[m] = it.prep_dense ? nblocks(cnt, p->tv) : 0;
       cf[m] = it.prep_dense ? nblocks(cnt, WG) : 0;
-      // Jacobi: dense meshes get their direction from the fused condensation
-      cu[m] = (c < 0 && p->cfg.sweep == 0 && it.prep_dense) ? 0 : nblocks(cnt, WG / G);
+      // dense meshes get their direction from the fused condensation: in a
+      // Jacobi sweep, and per colour in a coloured sweep with per-colour Hessians
+      const bool fused = it.prep_dense && ((c < 0 && p->cfg.sweep == 0) ||
+                                           (c >= 0 && p->cfg.sweep == 1 && p->cfg.hess_refresh == 0));
+      cu[m] = fused ? 0 : nblocks(cnt, WG / G);
     }
     offsets_build(p->prep[c + 1], cp, s);
     offsets_build(p->prepd[c + 1], cd, s);
     offsets_build(p->fin[c + 1], cf, s);
     offsets_build(p->upd[c + 1], cu, s);
+  }
+  p->elemc.assign(p->max_colours, Offsets{});
+  p->asmbc.assign(p->max_colours, Offsets{});
+  for (int c = 0; c < p->max_colours; ++c) {
+    std::vector<int> ce(p->nmesh), cs(p->nmesh);
+    for (int m = 0; m < p->nmesh; ++m) {
+      const BatchItem& it = p->items_h[m];
+      ce[m] = c < it.ncol ? nblocks(it.cel_n[c], EWG) : 0;
+      cs[m] = c < it.ncol ? nblocks(it.csl_n[c], EWG) : 0;
+    }
+    offsets_build(p->elemc[c], ce, s);
+    offsets_build(p->asmbc[c], cs, s);
   }
 }
 
@@ -1938,6 +2001,8 @@ void batch_plan_destroy(BatchPlan* p) {
   for (auto& o : p->prepd) offsets_free(o);
   for (auto& o : p->fin) offsets_free(o);
   for (auto& o : p->upd) offsets_free(o);
+  for (auto& o : p->elemc) offsets_free(o);
+  for (auto& o : p->asmbc) offsets_free(o);
   if (p->wpart) (void)hipFree(p->wpart);
   if (p->items_d) (void)hipFree(p->items_d);
   if (p->ctl_d) (void)hipFree(p->ctl_d);
@@ -2000,19 +2065,23 @@ static void b_update(BatchPlan* p, int colour, int into_trial, hipStream_t s) {
   p->mark(4, 0);
 }
 
+// Element Hessians and block rows at positions `which`: of every element
+// (colour < 0), or only those that colour's moves changed.
 template <typename T, int D>
-static void b_hessian(BatchPlan* p, int which, hipStream_t s) {
+static void b_hessian(BatchPlan* p, int which, hipStream_t s, int colour = -1) {
   if (gridn(p->rotn) > 0)   // corotation: rotations at the positions of the Hessian
     kb_rotations<D><<<gridn(p->rotn), WG, 0, s>>>(p->items_d, p->ctl_d, p->rotn.d, p->nmesh, which);
-  if (gridn(p->elem) > 0) {
+  const Offsets& oe = colour < 0 ? p->elem : p->elemc[colour];
+  const Offsets& oa = colour < 0 ? p->asmb : p->asmbc[colour];
+  if (gridn(oe) > 0) {
     p->mark(0, 1);
-    CC_DISPATCH_MAT(p->cfg.any_fcr, kb_elem_hess<T, D, FCR><<<gridn(p->elem), elem_threads<T>(), 0, s>>>(
-                                        p->items_d, p->ctl_d, p->elem.d, p->nmesh, which));
+    CC_DISPATCH_MAT(p->cfg.any_fcr, kb_elem_hess<T, D, FCR><<<gridn(oe), elem_threads<T>(), 0, s>>>(
+                                        p->items_d, p->ctl_d, oe.d, p->nmesh, which, colour));
     p->mark(0, 0);
   }
-  if (gridn(p->asmb) > 0) {
+  if (gridn(oa) > 0) {
     p->mark(1, 1);
-    kb_assemble<T, D><<<gridn(p->asmb), EWG, 0, s>>>(p->items_d, p->ctl_d, p->asmb.d, p->nmesh);
+    kb_assemble<T, D><<<gridn(oa), EWG, 0, s>>>(p->items_d, p->ctl_d, oa.d, p->nmesh, colour);
     p->mark(1, 0);
   }
 }
@@ -2033,10 +2102,10 @@ static void b_iteration(BatchPlan* p, hipStream_t s) {
     if (gridn(p->axpy) > 0)
       kb_axpy<<<gridn(p->axpy), WG, 0, s>>>(p->items_d, p->ctl_d, p->axpy.d, nm, 0.0, 1);
     for (int col = 0; col < p->max_colours; ++col) {
-      if (c.hess_refresh == 0) {
-        b_hessian<T, D>(p, 1, s);
-        b_prep<T, D, G>(p, col, s);
-      } else if (col == 0) {
+      // per-colour Hessians: all of them at the sweep's start, then only the
+      // elements and block slots the previous colour's moves changed
+      if (c.hess_refresh == 0) b_hessian<T, D>(p, 1, s, col == 0 ? -1 : col - 1);
+      else if (col == 0) {
         b_hessian<T, D>(p, 1, s);
         b_prep<T, D, G>(p, -1, s);
       }
@@ -2046,6 +2115,9 @@ static void b_iteration(BatchPlan* p, hipStream_t s) {
                                        p->items_d, p->ctl_d, p->grad.d, nm, 1, 0));
         p->mark(2, 0);
       }
+      // dense meshes form b_i from the fresh gradient and move the colour's
+      // vertices in the finish kernel; sparse ones take the update kernel
+      if (c.hess_refresh == 0) b_prep<T, D, G>(p, col, s, 2);
       b_update<T, D, G>(p, col, 1, s);
     }
   }
@@ -2092,13 +2164,13 @@ void batch_begin(BatchPlan* p, hipStream_t s) {
   }
 }
 
-void batch_iterate(BatchPlan* p, int iters, hipStream_t s) {
+hipError_t batch_iterate(BatchPlan* p, int iters, hipStream_t s) {
   const int k = p->cfg.iters_per_graph;
   // with a timing hook the launches run uncaptured: event pairs recorded as
   // graph nodes do not give per-launch durations
   if (k <= 0 || p->hook) {
     for (int i = 0; i < iters; ++i) one_iteration(p, s);
-    return;
+    return hipGetLastError();
   }
   if (!p->exec) {
     bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
@@ -2109,17 +2181,24 @@ void batch_iterate(BatchPlan* p, int iters, hipStream_t s) {
       ok = hipStreamEndCapture(s, &p->graph) == hipSuccess;
     }
     if (ok) ok = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
-    if (!ok) {  // capture unsupported on this stream: run the launches directly
+    if (!ok) {  // capture unsupported on this stream: run the launches directly (reported)
       (void)hipGetLastError();
       if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
       p->exec = nullptr;
       p->cfg.iters_per_graph = 0;
+      p->capture_failed = 1;
       for (int i = 0; i < iters; ++i) one_iteration(p, s);
-      return;
+      return hipGetLastError();
     }
   }
-  for (int done = 0; done < iters; done += k) (void)hipGraphLaunch(p->exec, s);
+  for (int done = 0; done < iters; done += k) {
+    const hipError_t e = hipGraphLaunch(p->exec, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
+
+int batch_capture_failed(BatchPlan* p) { return p->capture_failed; }
 
 // Pieces of the batched path used by the warm start (cc_mlp.hip).
 void batch_energy_trial(BatchPlan* p, hipStream_t s, int post) {
@@ -2187,6 +2266,8 @@ void batch_set_lanes(BatchPlan* p, int G) {
   for (auto& o : p->prepd) offsets_free(o);
   for (auto& o : p->fin) offsets_free(o);
   for (auto& o : p->upd) offsets_free(o);
+  for (auto& o : p->elemc) offsets_free(o);
+  for (auto& o : p->asmbc) offsets_free(o);
   plan_vertex_offsets(p, nullptr);
   (void)hipDeviceSynchronize();
 }

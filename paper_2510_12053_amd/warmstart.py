@@ -25,21 +25,25 @@ def _upload(ctx, scenes, dev):
     return out
 
 
-def _params(precision, warm):
+def _params(precision, warm, corotate=0):
     return cg.cc_params_default(method=cg.METHOD_CC, sweep=cg.SWEEP_JACOBI, line_search=1,
-                                max_iters=10000, precision=precision, warm_start=int(warm))
+                                max_iters=10000, precision=precision, warm_start=int(warm),
+                                corotate=int(corotate))
 
 
-def generate(ctx, scenes, steps, dev, tol=1e-6, precision=cg.FP64):
-    """Step `scenes` together with plain CC; record for every free vertex of
-    every step the features at the predictor and the target (x* - x~)/l.
-    Returns (X (N,16) float32, T (N,3) float32, iterations per step)."""
+def generate(ctx, scenes, steps, dev, tol=1e-6, precision=cg.FP64, corotate=1):
+    """Step `scenes` together with CC (corotated by default: the training
+    scenes twist, and a rest-frame basis needs hundreds of iterations per
+    step there, while the step's solution is the same); record for every
+    free vertex of every step the features at the predictor and the target
+    (x* - x~)/l.  Returns (X (N,16) float32, T (N,3) float32, iterations per
+    step)."""
     import torch
     ms = _upload(ctx, scenes, dev)
     rows = sum(m["nf"] for m in ms)
     X = torch.zeros((steps * rows, cg.MLP_NFEAT), dtype=torch.float32, device=dev)
     T = torch.zeros((steps * rows, 3), dtype=torch.float32, device=dev)
-    par = _params(precision, False)
+    par = _params(precision, False, corotate)
     grav = np.stack([m["s"].gravity for m in ms])
     iters = []
     r0 = 0

@@ -127,6 +127,7 @@ def test_batch64_equals_single_mesh(cg, ctx, prec):
     xs1 = [x.clone() for x in xs]
     vs1 = [v.clone() for v in vs]
     grav = np.stack([s.gravity for s in scenes])
+    compared, total = 0, 0
     for t in (1, 2):
         bcs = [_t(s.targets(t)) for s in scenes]
         worst, its, rgs, sts = cg.cc_step_batch(ctx, mids, xs, vs, bcs, scenes[0].dt, par, 1e-6,
@@ -144,7 +145,15 @@ def test_batch64_equals_single_mesh(cg, ctx, prec):
             else:
                 # float32 local arithmetic: lane counts may differ between the paths, so a
                 # borderline line-search decision may differ too; resynchronise then
+                total += 1
                 if sts[k] == st and its[k] == it:
                     assert np.linalg.norm(a - b) <= 1e-4 * np.linalg.norm(b - s.X), (k, t)
+                    compared += 1
+                else:
+                    assert abs(int(its[k]) - it) <= 1, (k, t, its[k], it)
                 xs[k].copy_(xs1[k])
                 vs[k].copy_(vs1[k])
+    # at least 90% of the float32 mesh-steps take the same decisions and are compared
+    if prec == 1:
+        assert compared >= 0.9 * total, (compared, total)
+

@@ -175,6 +175,7 @@ def test_warm_step_matches_oracle(cg, ctx, trained):
     op = S.Params(method=S.CC, sweep=S.JACOBI, line_search=True, max_iters=200)
     theta = _oracle_bf16_params(trained["params"])
     accepted = []
+    compared = 0
     for t in range(1, 4):
         tg = s.targets(t)
         par = cg.cc_params_default(warm_start=1, gravity=s.gravity, max_iters=200)
@@ -191,10 +192,14 @@ def test_warm_step_matches_oracle(cg, ctx, trained):
         if acc == acc_o:
             xr = xg.cpu().numpy()
             assert np.linalg.norm(xr - x) / np.linalg.norm(x - s.X) <= 1e-6
+            compared += 1
         else:                      # borderline decisions may differ: resynchronise
             xg.copy_(torch.tensor(x, device=DEV))
             vg.copy_(torch.tensor(v, device=DEV))
     assert any(accepted)
+    # a differing decision is a rounding-level tie of the two FP64 energies:
+    # at least two of the three steps take the same decision and are compared
+    assert compared >= 2, compared
 
 
 def test_trained_network_gain_on_held_out(cg, ctx, trained):

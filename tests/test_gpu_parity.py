@@ -11,6 +11,7 @@ torch = pytest.importorskip("torch")
 
 from ccscenes import batch_bars, stretch2d, tet_bar, twist_beam
 from oracle import solvers as S
+from oracle.solvers import paper_measure
 from oracle.basis import basis_matrix, exact_basis, patch_basis
 from oracle.colour import greedy_colour, layout
 from oracle.fem import Problem
@@ -226,6 +227,114 @@ def test_coloured_sweep(cg, ctx, refresh, kind):
     for res, st, it, rg, xo, xg, vo, vg in out:
         assert it == res.iters
         assert _rel(xg, xo, s.X) <= 1e-6
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("E", [1e5, 1e7])
+def test_coloured_sweep_line_search(cg, ctx, prec, E):
+    """Coloured Gauss-Seidel with the global backtracking search, exact basis,
+    three steps of a sagging bar to rel|g| <= 1e-6: equal iterations in FP64
+    (+-2 in FP32-mixed) and the converged states of the oracle (1e-6 / 1e-4)."""
+    s = tet_bar(11, 4, 4, E=E)
+    p = Problem.from_scene(s)
+    B = exact_basis(p)
+    col = greedy_colour(s.n, s.elems, s.fixed)
+    par = cg.cc_params_default(method=cg.METHOD_CC, sweep=cg.SWEEP_COLORED_GS, line_search=1,
+                               precision=prec, max_iters=200, gravity=s.gravity)
+    op = S.Params(method=S.CC, sweep=S.GS, line_search=True, max_iters=200)
+    _, out = _run_steps(cg, ctx, s, B, par, 1e-6, 3, op, colours=col)
+    for res, st, it, rg, xo, xg, vo, vg in out:
+        assert st == cg.CC_OK and res.status == S.OK and rg <= 1e-6
+        if prec == 0:
+            assert it == res.iters
+            assert _rel(xg, xo, s.X) <= 1e-6
+        else:
+            assert abs(it - res.iters) <= 2
+            assert _rel(xg, xo, s.X) <= 1e-4
+
+
+@pytest.mark.parametrize("kind", ["exact", "R2"])
+def test_coloured_sweep_fp32(cg, ctx, kind):
+    """FP32-mixed coloured sweeps (per-colour Hessians, no search) against the
+    FP64 oracle: two steps to 1e-6, rel|dx| <= 1e-4, iterations within 2."""
+    s = tet_bar(11, 4, 4, E=1e5)
+    p = Problem.from_scene(s)
+    B = _basis(p, kind)
+    col = greedy_colour(s.n, s.elems, s.fixed)
+    par = cg.cc_params_default(method=cg.METHOD_CC, sweep=cg.SWEEP_COLORED_GS, precision=1,
+                               line_search=0, max_iters=100, gravity=s.gravity)
+    op = S.Params(method=S.CC, sweep=S.GS, line_search=False, max_iters=100)
+    _, out = _run_steps(cg, ctx, s, B, par, 1e-6, 2, op, colours=col)
+    for res, st, it, rg, xo, xg, vo, vg in out:
+        assert abs(it - res.iters) <= 2
+        assert _rel(xg, xo, s.X) <= 1e-4
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_bar_ten_steps_e_sweep(cg, ctx, prec):
+    """The whole 10-step trajectory of the stiffness-sweep bar at E = 1e6
+    (exact basis, Jacobi CC with line search) against the oracle."""
+    s = tet_bar(E=1e6)
+    p = Problem.from_scene(s)
+    B = exact_basis(p)
+    par = cg.cc_params_default(method=cg.METHOD_CC, sweep=cg.SWEEP_JACOBI, line_search=1,
+                               precision=prec, max_iters=200, gravity=s.gravity)
+    op = S.Params(method=S.CC, sweep=S.JACOBI, line_search=True, max_iters=200)
+    _, out = _run_steps(cg, ctx, s, B, par, 1e-6, 10, op)
+    assert len(out) == 10
+    for res, st, it, rg, xo, xg, vo, vg in out:
+        assert st == cg.CC_OK and rg <= 1e-6
+        if prec == 0:
+            assert it == res.iters
+            assert _rel(xg, xo, s.X) <= 1e-6
+        else:
+            assert abs(it - res.iters) <= 2
+            assert _rel(xg, xo, s.X) <= 1e-4
+
+
+@pytest.mark.parametrize("method", [S.CC, S.CD])
+def test_stretch2d_200_iterations(cg, ctx, method):
+    """The 17x17 stretch's own configuration: 200 plain Jacobi iterations of CC
+    and of CD, FP64, against the oracle."""
+    s = stretch2d()
+    p = Problem.from_scene(s)
+    B = exact_basis(p)
+    par = cg.cc_params_default(method=method, sweep=cg.SWEEP_JACOBI, line_search=0, max_iters=200,
+                               quasistatic=1)
+    op = S.Params(method=method, sweep=S.JACOBI, line_search=False, max_iters=200)
+    _, out = _run_steps(cg, ctx, s, B, par, 0.0, 1, op)
+    res, st, it, rg, xo, xg, _, _ = out[0]
+    assert it == 200 == res.iters
+    assert _rel(xg, xo, s.X) <= 1e-6
+    assert abs(rg - res.rel_grad) <= 1e-6 * max(res.rel_grad, 1e-12) + 1e-13
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_paper_residual_matches_oracle(cg, ctx, batched):
+    """cc_step_info's |g| / (V n E h) after a step against the oracle's measure
+    (Results, Termination criteria) of the oracle gradient at the GPU's
+    final positions, with the step's inertial target."""
+    s = tet_bar(9, 4, 4, E=1e6)
+    p = Problem.from_scene(s)
+    B = exact_basis(p)
+    mid = _upload(cg, ctx, s)
+    cg.cc_subspace_upload(ctx, mid, *B, s.dt)
+    x, v = s.initial_state()
+    xg, vg = _t(x), _t(v)
+    par = cg.cc_params_default(method=cg.METHOD_CC, sweep=cg.SWEEP_JACOBI, line_search=1, max_iters=200,
+                               gravity=s.gravity)
+    # stop early so that the residual is well above rounding
+    if batched:
+        cg.cc_step_batch(ctx, [mid], [xg], [vg], [_t(s.targets(1))], s.dt, par, 1e-3,
+                         gravity=s.gravity[None, :])
+    else:
+        cg.cc_step(ctx, mid, xg, vg, _t(s.targets(1)), s.dt, par, 1e-3)
+    info = cg.cc_step_info(ctx, mid)
+    xt = predictor(p, x, v, s.targets(1))
+    p.set_inertial_target(xt)
+    want = paper_measure(p, p.gradient(xg.cpu().numpy()))
+    assert want > 0
+    assert abs(info["paper_residual"] - want) <= 1e-7 * want
 
 
 def test_error_paths(cg, ctx):

@@ -207,10 +207,10 @@ def trace_summary(folder, bench_log):
               f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
               f"{float(r['Percentage']):.2f}% |")
     # the profiled (uncaptured) learned+batched region holds the last
-    # `launches` dispatches of kb_prep_band before the beam section starts:
-    # the beam's own dispatches follow them, so take the window that ends
-    # where the beam's begin (the first dispatch on a single-mesh launch of
-    # the beam is not separable by name; use the counts bench.py printed)
+    # `launches` float32 dispatches of kb_prep_band before the beam section
+    # (the float64 bars come later under another name); the beam's float32
+    # dispatches follow them, one per iteration, so the window ends that many
+    # dispatches before the last
     n = ro["launches"]
     nb = b.get("beam81x21x21_twist", {}).get("roofline", {}).get("launches", 0)
     nbeam_all = 0
@@ -223,13 +223,28 @@ def trace_summary(folder, bench_log):
              for r in disp if key in r["Kernel_Name"]]
         end = len(v) - nbeam_all
         return v[max(end - n, 0):end]
-    lp, lf = window("kb_prep_band"), window("kb_dm_finish")
+    lp, lf = window("kb_prep_band<float"), window("kb_dm_finish<float")
     mp = sum(lp) / max(len(lp), 1)
     mf = sum(lf) / max(len(lf), 1)
     print(f"\nDominant kernels of the timed path: `kb_prep_band` + `kb_dm_finish` (exact-basis "
           f"condensation).  The {len(lp)} dispatches of the uncaptured learned+batched region average "
           f"{mp:.1f} + {mf:.1f} = {mp + mf:.1f} us per pair; bench.py's HIP-event average of the "
           f"same launches in this run: {ro['avg_launch_us']} us.\n")
+    # idle time between consecutive batched dispatches on the device: the
+    # cost a persistent kernel with grid barriers could remove.  Pairs closer
+    # than 50 us belong to one queued stretch of work (graph replays or
+    # uncaptured launch sequences); longer gaps are host round trips.
+    kb = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]) for r in disp
+                if "cc::kb_" in r["Kernel_Name"] or "kb_" in r["Kernel_Name"][:40])
+    gaps = [(kb[i + 1][0] - kb[i][1]) / 1e3 for i in range(len(kb) - 1)]
+    inner = sorted(g for g in gaps if 0 <= g < 50)
+    busy = sum((e - a) / 1e3 for a, e, _ in kb)
+    if inner:
+        med = inner[len(inner) // 2]
+        p90 = inner[int(0.9 * (len(inner) - 1))]
+        print(f"Gaps between consecutive batched (`kb_*`) dispatches inside queued stretches (< 50 us): "
+              f"{len(inner)} pairs, median {med:.2f} us, p90 {p90:.2f} us, total {sum(inner) / 1e3:.1f} ms "
+              f"against {busy / 1e3:.1f} ms of `kb_*` kernel time ({100 * sum(inner) / max(busy, 1e-9):.1f}%).\n")
     sel = {k: b[k] for k in ("value", "ms_per_step", "learned_batched", "batched", "plain_cc", "roofline")
            if k in b}
     print("bench.py line of the profiled run (selected fields):\n\n```\n" + json.dumps(sel, indent=1)

@@ -15,13 +15,19 @@ subspace:   the quasistatic cantilever (21 x 6 x 6 vertices, E = --cantilever-E,
   Quality): CC with the basis fixed at rest, restarted (rebuilt from the
   current configuration every 5 steps) and corotated; Jacobi with line
   search; rel|grad E| <= 1e-6 or 5,000 iterations per step.
+warmstart:  the learned warm start evaluated at beam size: the network is
+  trained on 50 solver-generated episodes of 21 x 6 x 6 bars (seeds
+  1000-1049, 10 steps each), then held-out episodes drawn the same way at
+  81 x 21 x 21 (seeds 2000-2004, 30 steps each, exact corotated basis,
+  float32 local arithmetic) are stepped with and without the proposal, CC to
+  rel|grad E| <= 1e-6: iterations, acceptance and time per step.
 
 The material is the paper's Fixed Corotational model by default (--material
 snh for stable neo-Hookean).  A relative termination test replaces the
 paper's absolute measures (see the package's design notes).  Prints a
 Markdown table and one JSON line per sweep.
 
-    python experiments.py [--sweep resolution|stiffness|subspace|all] [--material fcr|snh]
+    python experiments.py [--sweep resolution|stiffness|subspace|warmstart|all] [--material fcr|snh]
 """
 import argparse
 import json
@@ -74,7 +80,10 @@ def _table(rows, key, label, methods, extra):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--sweep", choices=("resolution", "stiffness", "subspace", "all"), default="all")
+    ap.add_argument("--sweep", choices=("resolution", "stiffness", "subspace", "warmstart", "all"),
+                    default="all")
+    ap.add_argument("--eval-seeds", type=int, nargs="+", default=[2000, 2001, 2002, 2003, 2004])
+    ap.add_argument("--eval-steps", type=int, default=30)
     ap.add_argument("--material", choices=("fcr", "snh"), default="fcr")
     ap.add_argument("--cantilever-E", type=float, default=1e7)
     args = ap.parse_args()
@@ -153,7 +162,68 @@ def main():
         print(json.dumps({"experiment": "subspace_quality_cantilever", "material": args.material,
                           "E": args.cantilever_E, "tol": tol,
                           "max_iters": cap, "restart_every": every, "rows": rows}), flush=True)
+    if args.sweep in ("warmstart", "all"):
+        warm_start_beam(cg, ctx, dev, args.eval_seeds, args.eval_steps)
     cg.cc_destroy(ctx)
+
+
+def warm_start_beam(cg, ctx, dev, seeds, steps, tol=1e-6):
+    """Held-out evaluation of the learned warm start at 81 x 21 x 21."""
+    import torch
+    from paper_2510_12053_amd import warmstart as W
+    from ccscenes import mlp_init, warm_start_eval_scene, warm_start_train_scene
+    train = [warm_start_train_scene(sd) for sd in range(1000, 1050)]
+    X, T, _ = W.generate(ctx, train, 10, dev, precision=cg.FP32_MIXED)
+    losses, _ = W.train(ctx, X, T, mlp_init(7), epochs=40, batch=4096, lr=2e-3)
+    del X, T
+    print(f"warmstart: trained, loss {losses[0]:.4f} -> {losses[-1]:.4f}", flush=True)
+    rows = []
+    for sd in seeds:
+        s = warm_start_eval_scene(sd, n_steps=steps)
+        t0 = time.perf_counter()
+        mid = cg.cc_mesh_upload(ctx, s.X, s.elems, s.fixed, s.E, s.nu, s.rho)
+        cg.cc_subspace_build(ctx, mid, 0, s.dt, False)
+        torch.cuda.synchronize()
+        build = time.perf_counter() - t0
+        row = {"seed": sd, "E": s.E, "gravity": [round(float(g), 3) for g in s.gravity],
+               "twist_deg_per_step": round(float(np.rad2deg(s.meta["twist_per_step"])), 3),
+               "basis_build_s": round(build, 2)}
+        for name, warm in (("plain", 0), ("learned", 1)):
+            x, v = s.initial_state()
+            xg = torch.tensor(x, dtype=torch.float64, device=dev)
+            vg = torch.tensor(v, dtype=torch.float64, device=dev)
+            par = cg.cc_params_default(method=cg.METHOD_CC, sweep=cg.SWEEP_JACOBI, precision=cg.FP32_MIXED,
+                                       line_search=1, max_iters=10000, gravity=s.gravity,
+                                       warm_start=warm, corotate=1)
+            its, acc, ms, bad = [], 0, [], 0
+            for t in range(1, steps + 1):
+                bc = torch.tensor(s.targets(t), dtype=torch.float64, device=dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, it, rg = cg.cc_step(ctx, mid, xg, vg, bc, s.dt, par, tol)
+                torch.cuda.synchronize()
+                ms.append((time.perf_counter() - t0) * 1e3)
+                its.append(int(it))
+                bad += int(st != cg.CC_OK)
+                acc += int(cg.cc_step_info(ctx, mid)["warm_accepted"])
+            row[name] = {"iters_mean": round(float(np.mean(its)), 3), "iters_median": float(np.median(its)),
+                         "ms_per_step_median": round(float(np.median(ms)), 2),
+                         "ms_per_step_mean": round(float(np.mean(ms)), 2), "not_ok": bad,
+                         "accepted": acc, "steps": steps, "iters": its}
+        rows.append(row)
+        print(f"warmstart seed {sd}: E {s.E:.3g}, plain {row['plain']['iters_mean']} it "
+              f"{row['plain']['ms_per_step_median']} ms, learned {row['learned']['iters_mean']} it "
+              f"{row['learned']['ms_per_step_median']} ms, accepted {row['learned']['accepted']}/{steps}",
+              flush=True)
+    print("| seed | E | plain: iterations (mean) | plain: ms/step (median) | learned: iterations (mean) "
+          "| learned: ms/step (median) | proposals taken |")
+    print("|---|---|---|---|---|---|---|")
+    for r in rows:
+        print(f"| {r['seed']} | {r['E']:.3g} | {r['plain']['iters_mean']} | {r['plain']['ms_per_step_median']} | "
+              f"{r['learned']['iters_mean']} | {r['learned']['ms_per_step_median']} | "
+              f"{r['learned']['accepted']}/{steps} |")
+    print(json.dumps({"experiment": "warm_start_held_out_beam81x21x21", "tol": tol, "precision": "fp32",
+                      "basis": "exact, corotated", "rows": rows}), flush=True)
 
 
 if __name__ == "__main__":

@@ -214,7 +214,8 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
    (host, n each): iters, rel_grad, status (per-mesh cc_status).  The return
    value is the worst per-mesh status (errors before warnings), or
    CC_GRAPH_FALLBACK when the graph capture failed and the iterations ran
-   as direct launches (every output valid).  The stream
+   as direct launches (every output valid).  On the legacy null stream no
+   capture is attempted (see below) and nothing is reported.  The stream
    given to cc_create must not be the legacy null stream for graph capture;
    with it the launches run uncaptured. */
 cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double* const* x,

@@ -1693,7 +1693,10 @@ static cc::BatchPlan* batch_plan_for(cc_ctx* ctx, const std::vector<Mesh*>& ms, 
   cfg.D = ms[0]->D; cfg.prec = p.precision; cfg.method = p.method; cfg.sweep = p.sweep;
   cfg.hess_refresh = p.hess_refresh; cfg.line_search = p.line_search; cfg.max_iters = p.max_iters;
   cfg.quasistatic = p.quasistatic; cfg.tol = tol; cfg.h = p.quasistatic ? 1.0 : dt;
-  cfg.G = ctx->batch_lanes; cfg.iters_per_graph = ctx->batch_iters_per_graph;
+  // the legacy null stream cannot be captured: its launches run uncaptured
+  // (documented behaviour, not a fallback)
+  cfg.G = ctx->batch_lanes;
+  cfg.iters_per_graph = ctx->stream != nullptr ? ctx->batch_iters_per_graph : 0;
   cfg.corotate = p.corotate;
   cfg.any_fcr = any_fcr;
   ctx->plan = cc::batch_plan_create(items.data(), n, cfg, ctx->stream);

@@ -232,6 +232,11 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
    keeps the fastest and returns it with the per-choice milliseconds
    (ms_out: 3 values for 16, 32, 64; may be NULL). */
 cc_status cc_batch_tuning(cc_ctx* ctx, int32_t lanes, int32_t iters_per_graph);
+/* Rows per workgroup of the exact-basis condensation (every basis row it
+   stages serves that many vertices per H block it loads): 0 = the most whose
+   LDS ring fits (4 in float32, 2 in float64 on MI355X), or a cap of 1, 2 or
+   4.  Applies to later cc_step, cc_probe_sweep and cc_step_batch calls. */
+cc_status cc_dense_tuning(cc_ctx* ctx, int32_t rows_per_workgroup);
 cc_status cc_autotune_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, const cc_params* params,
                             int32_t* lanes_out, double* ms_out);
 

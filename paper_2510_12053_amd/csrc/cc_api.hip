@@ -213,6 +213,7 @@ struct cc_ctx {
   // batched stepping: tuning and the cached plan of the last batch
   int batch_lanes = 16;
   int batch_iters_per_graph = 4;
+  int dense_rows = 0;        // rows per workgroup of the dense condensation (0: most that fit)
   // kernel timing inside the batched path: event pairs of uncaptured launches
   // go to `pending`; pairs captured into the graph stay registered and are
   // read after every replay
@@ -1058,14 +1059,18 @@ struct Stepper {
     ctx->timed(CC_K_ASSEMBLE, [&] { cc::launch_assemble_list(mv, p.precision, M.estore, mat, M.hb, s, sl, ns); });
   }
   void prep(int method, int v0, int v1) {
-    ctx->timed(CC_K_CC_PREP, [&] { cc::launch_cc_prep(mv, p.precision, method, v0, v1, M.hb, M.KL, M.fb, s); });
+    ctx->timed(CC_K_CC_PREP, [&] {
+      cc::launch_cc_prep(mv, p.precision, method, v0, v1, M.hb, M.KL, M.fb, s, nullptr, nullptr, nullptr,
+                         ctx->dense_rows);
+    });
   }
   // Condensation that also writes the Jacobi directions into out when the
   // dense path can (g must hold the gradient at the same x); false: call update.
   bool prep_direction(int method, double* out) {
     bool done = false;
     ctx->timed(CC_K_CC_PREP, [&] {
-      done = cc::launch_cc_prep(mv, p.precision, method, 0, M.nf, M.hb, M.KL, M.fb, s, M.g, out);
+      done = cc::launch_cc_prep(mv, p.precision, method, 0, M.nf, M.hb, M.KL, M.fb, s, M.g, out, nullptr,
+                                ctx->dense_rows);
     });
     return done;
   }
@@ -1097,7 +1102,8 @@ struct Stepper {
         // vertices in the finish kernel; other bases take the update kernel
         bool done = false;
         ctx->timed(CC_K_CC_PREP, [&] {
-          done = cc::launch_cc_prep(mv, p.precision, method, v0, v1, M.hb, M.KL, M.fb, s, M.g, M.dvec, out);
+          done = cc::launch_cc_prep(mv, p.precision, method, v0, v1, M.hb, M.KL, M.fb, s, M.g, M.dvec, out,
+                                    ctx->dense_rows);
         });
         if (!done) update(method, v0, v1, out, 1);
         continue;
@@ -1670,7 +1676,8 @@ static cc::BatchPlan* batch_plan_for(cc_ctx* ctx, const std::vector<Mesh*>& ms, 
   std::vector<double> key = {(double)p.method, (double)p.sweep, (double)p.hess_refresh,
                              (double)p.precision, (double)p.line_search, (double)p.max_iters,
                              (double)p.quasistatic, dt, tol, (double)ctx->batch_lanes,
-                             (double)ctx->batch_iters_per_graph, (double)p.corotate};
+                             (double)ctx->batch_iters_per_graph, (double)p.corotate,
+                             (double)ctx->dense_rows};
   int any_fcr = 0;
   for (int i = 0; i < n; ++i) {
     key.push_back((double)(ms[i]->has_basis ? ms[i]->dense : -1));
@@ -1699,6 +1706,7 @@ static cc::BatchPlan* batch_plan_for(cc_ctx* ctx, const std::vector<Mesh*>& ms, 
   cfg.iters_per_graph = ctx->stream != nullptr ? ctx->batch_iters_per_graph : 0;
   cfg.corotate = p.corotate;
   cfg.any_fcr = any_fcr;
+  cfg.tv_cap = ctx->dense_rows;
   ctx->plan = cc::batch_plan_create(items.data(), n, cfg, ctx->stream);
   ctx->plan_ids = idv;
   ctx->plan_prev_iters = 0;
@@ -1960,6 +1968,16 @@ cc_status cc_batch_tuning(cc_ctx* ctx, int32_t lanes, int32_t iters_per_graph) {
       return fail(ctx, CC_E_INVALID_ARG, "lanes must be 16, 32 or 64; iters_per_graph 0..64");
     ctx->batch_lanes = lanes;
     ctx->batch_iters_per_graph = iters_per_graph;
+    return CC_OK;
+  });
+}
+
+cc_status cc_dense_tuning(cc_ctx* ctx, int32_t rows_per_workgroup) {
+  return guarded(ctx, [&]() -> cc_status {
+    if (rows_per_workgroup != 0 && rows_per_workgroup != 1 && rows_per_workgroup != 2 &&
+        rows_per_workgroup != 4)
+      return fail(ctx, CC_E_INVALID_ARG, "rows per workgroup must be 0 (automatic), 1, 2 or 4");
+    ctx->dense_rows = rows_per_workgroup;
     return CC_OK;
   });
 }

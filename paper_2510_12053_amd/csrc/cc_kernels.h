@@ -119,7 +119,8 @@ void launch_gradient(const MeshView& mv, const double* x, const double* xt, cons
 // return value says whether it did (else launch_cc_update).
 bool launch_cc_prep(const MeshView& mv, int prec, int method, int v0, int v1, const void* hb,
                     void* KL, unsigned long long* fallbacks, hipStream_t s,
-                    const double* g = nullptr, double* dout = nullptr, double* xmove = nullptr);
+                    const double* g = nullptr, double* dout = nullptr, double* xmove = nullptr,
+                    int tv_cap = 0);
 void launch_cc_update(const MeshView& mv, int prec, int method, int v0, int v1, const void* KL,
                       const double* g, double* x_or_d, int accumulate, hipStream_t s);
 void launch_energy(const MeshView& mv, const double* x, const double* xt, const Material& mat,
@@ -147,7 +148,8 @@ int reduce_partials_capacity(const MeshView& mv);
 constexpr int BWG = 512;
 void set_lds_limit(size_t bytes);
 int band_ring(int nf, int band_w);
-int dense_tv(int ring, int D, int prec);
+// cap > 0 limits the rows per workgroup (tuning); 0 takes the most that fit.
+int dense_tv(int ring, int D, int prec, int cap = 0);
 size_t dense_lds_bytes(int tv, int ring, int D, int prec);
 
 // Exact basis U_i[j] = (H^{-1})_ji ((H^{-1})_ii)^{-1} from float64 block rows
@@ -214,6 +216,7 @@ struct BatchConfig {
   int iters_per_graph; // iterations captured per graph replay (0: no graph)
   int dense_lds;       // max dynamic LDS of the dense condensation path (bytes)
   int corotate;        // rotations re-estimated wherever the Hessian is
+  int tv_cap;          // rows per workgroup of the dense condensation (0: most that fit)
   int any_fcr;         // some mesh of the batch uses the Fixed Corotational model
 };
 

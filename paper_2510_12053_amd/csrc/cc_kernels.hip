@@ -1161,9 +1161,11 @@ size_t dense_lds_bytes(int tv, int ring, int D, int prec) {
 
 // float64 keeps two rows per workgroup (the register file of 2 waves/SIMD
 // holds the accumulators of two float64 rows, four float32 ones)
-int dense_tv(int ring, int D, int prec) {
+int dense_tv(int ring, int D, int prec, int cap) {
   if (ring <= 0) return 0;
-  for (int tv = prec == 0 ? 2 : 4; tv >= 1; tv /= 2)
+  int top = prec == 0 ? 2 : 4;
+  while (cap > 0 && top > cap) top /= 2;
+  for (int tv = top; tv >= 1; tv /= 2)
     if (dense_lds_bytes(tv, ring, D, prec) <= g_lds_limit) return tv;
   return 0;
 }
@@ -1186,9 +1188,9 @@ static bool band_ok(const MeshView& mv, int prec) {
 template <typename T, int D>
 static bool prep_dense(const MeshView& mv, int prec, int method, int v0, int v1, const void* hb,
                        void* KL, unsigned long long* fb, const double* g, double* dout, double* xmove,
-                       hipStream_t s) {
+                       int tv_cap, hipStream_t s) {
   if (method == 0 || !band_ok(mv, prec)) return false;
-  const int tv = dense_tv(mv.ring, D, prec);
+  const int tv = dense_tv(mv.ring, D, prec, tv_cap);
   const size_t lds = dense_lds_bytes(tv, mv.ring, D, prec);
   CC_DISPATCH_TV(tv, k_cc_prep_band<T, D, TV><<<nblocks(v1 - v0, TV), BWG, lds, s>>>(
                          mv, method, v0, v1, (const T*)hb, (T*)KL, g, dout));
@@ -1199,13 +1201,15 @@ static bool prep_dense(const MeshView& mv, int prec, int method, int v0, int v1,
 
 bool launch_cc_prep(const MeshView& mv, int prec, int method, int v0, int v1, const void* hb,
                     void* KL, unsigned long long* fb, hipStream_t s, const double* g, double* dout,
-                    double* xmove) {
+                    double* xmove, int tv_cap) {
   if (v1 <= v0) return g != nullptr;
   bool done = false;
   if (prec == 0)
-    CC_DISPATCH_D(mv.D, done = prep_dense<double, D>(mv, prec, method, v0, v1, hb, KL, fb, g, dout, xmove, s));
+    CC_DISPATCH_D(mv.D, done = prep_dense<double, D>(mv, prec, method, v0, v1, hb, KL, fb, g, dout, xmove,
+                                                     tv_cap, s));
   else
-    CC_DISPATCH_D(mv.D, done = prep_dense<float, D>(mv, prec, method, v0, v1, hb, KL, fb, g, dout, xmove, s));
+    CC_DISPATCH_D(mv.D, done = prep_dense<float, D>(mv, prec, method, v0, v1, hb, KL, fb, g, dout, xmove,
+                                                    tv_cap, s));
   if (done) return g != nullptr;
   const int G = support_lanes(mv);
   if (prec == 0) CC_DISPATCH_D(mv.D, prep_g<double, D>(mv, method, v0, v1, hb, KL, fb, G, s));
@@ -1961,7 +1965,7 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
   p->scap = sparse_stage_cap(sparse_supp, cfg.G, cfg.D, cfg.prec);
   p->slds = sparse_stage_bytes(p->scap, cfg.G, cfg.D, cfg.prec);
   if (dense_ring > 0) {
-    p->tv = dense_tv(dense_ring, cfg.D, cfg.prec);
+    p->tv = dense_tv(dense_ring, cfg.D, cfg.prec, cfg.tv_cap);
     p->lds = dense_lds_bytes(p->tv, dense_ring, cfg.D, cfg.prec);
   }
   offsets_build(p->pred, cpred, s);

@@ -109,6 +109,12 @@ class Problem:
         """Gradient restricted to free vertices, (n_free, d)."""
         return self.gradient_full(x)[self.free]
 
+    def load_norm(self):
+        """Norm over free DOFs of the gravity load's part of the gradient,
+        |s_el m_i grav| (the scale of the force balance a loaded body holds)."""
+        f = self.free
+        return self.s_el * float(np.linalg.norm(self.mass[f])) * float(np.linalg.norm(self.grav))
+
     def hessian(self, x, project=True):
         """Sparse (CSR) Hessian over free DOFs: w_in M + s_el sum_e H_e."""
         d = self.d

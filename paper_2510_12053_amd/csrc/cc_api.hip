@@ -30,6 +30,7 @@ struct Mesh {
   std::vector<int> vperm, vinv, eperm, coff;
   std::vector<int> rowptr, colidx; // host copy of the block-row pattern (internal ids)
   std::vector<double> mass_int;    // internal order
+  double mass_free_norm = 0;       // |m| over free vertices (the gravity load's scale)
   int nnzb = 0;
   // device: static mesh data
   int *ev = nullptr, *star_ptr = nullptr, *star = nullptr, *d_rowptr = nullptr, *d_colidx = nullptr,
@@ -502,6 +503,12 @@ void build_mesh(cc_ctx* ctx, Mesh& M) {
   }
   M.mass_int.resize(n);
   for (int v = 0; v < n; ++v) M.mass_int[v] = mass_u[M.vperm[v]];
+  {
+    double m2 = 0;
+    for (int v = 0; v < n; ++v)
+      if (!M.fixed[M.vperm[v]]) m2 += M.mass_int[v] * M.mass_int[v];
+    M.mass_free_norm = std::sqrt(m2);
+  }
   // star of every free vertex (internal), in element order
   const int nf = M.nf;
   std::vector<int> star_ptr(nf + 1, 0);
@@ -1008,6 +1015,14 @@ void build_basis(cc_ctx* ctx, Mesh& M, int radius, double dt, int quasi, const d
   upload_basis(ctx, M, ptr.data(), idx.data(), U.data());
 }
 
+// |s_el m_i grav| over the free degrees of freedom: the gravity load's part
+// of the step gradient, the floor of the convergence test's denominator.
+double load_norm(const Mesh& M, const Material& mat) {
+  double g2 = 0;
+  for (int c = 0; c < M.D; ++c) g2 += mat.grav[c] * mat.grav[c];
+  return mat.s_el * M.mass_free_norm * std::sqrt(g2);
+}
+
 // ---- step driver ---------------------------------------------------------
 struct Stepper {
   cc_ctx* ctx;
@@ -1455,7 +1470,10 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
     HIPC(hipMemcpyAsync(&bad, M.bad, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     if (bad) return fail(ctx, CC_E_NONFINITE, "non-finite x, v or x_bc");
-    const double g0 = std::sqrt(S.grad_norm2(M.x));
+    // the convergence test is relative to the larger of the predictor's
+    // gradient and the gravity load's part of it (s_el |m_i g| over free DOFs)
+    const double gstart = std::sqrt(S.grad_norm2(M.x));
+    const double g0 = std::max(gstart, load_norm(M, mat));
     const int nd = M.D * M.n;
     double r = 0.0, Ecur = 0.0;
     int k = 0;
@@ -1463,7 +1481,7 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
     cc_status result = CC_OK;
     int warm = 0;
     if (g0 > 0) {
-      r = 1.0;
+      r = gstart / g0;
       if (p.warm_start) {
         // learned proposal at the predictor, kept only if it lowers E
         cc::launch_features(S.mv, M.x, M.x0, h, M.E, M.mu, M.lam, M.model, M.ell, M.nptr, M.nidx, M.Xr, M.feat, nullptr,
@@ -1793,6 +1811,7 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
       items[i].xu = x[i];
       items[i].vu = v[i];
       items[i].xbc = x_bc ? x_bc[i] : nullptr;
+      items[i].load = load_norm(M, mat);
       M.last_halvings = 0;          // fallback counters are cleared by batch_begin
     }
     cc::BatchItem* items_d = cc::batch_items_dev(plan);

@@ -178,6 +178,7 @@ struct BatchItem {
   double* vu;          // caller velocities
   const double* xbc;   // caller Dirichlet targets or null
   int prep_dense;      // 1: exact-basis condensation streamed through the LDS ring
+  double load;         // floor of the convergence test's denominator (gravity load norm)
   int ncol;
   int coff[MAX_COLOURS + 1];
   // warm start: mesh neighbours (all vertices), rest positions, scales and

@@ -1812,14 +1812,14 @@ __global__ void __launch_bounds__(WG) kb_reduce_eg(BatchItem* __restrict__ items
   }
 }
 
-__global__ void kb_init(BatchCtl* ctl, int nmesh, double tol, int max_iters) {
+__global__ void kb_init(const BatchItem* items, BatchCtl* ctl, int nmesh, double tol, int max_iters) {
   const int m = blockIdx.x * WG + threadIdx.x;
   if (m >= nmesh) return;
   BatchCtl& c = ctl[m];
   if (c.bad) { c.status = -5; c.active = 0; return; }
-  c.g0 = sqrt(c.gn2);
+  c.g0 = fmax(sqrt(c.gn2), items[m].load);   // relative to the larger of |g(x^0)| and the load
   if (c.g0 == 0.0) { c.r = 0.0; c.status = 0; c.active = 0; return; }
-  c.r = 1.0;
+  c.r = sqrt(c.gn2) / c.g0;
   if (c.r <= tol) { c.status = 0; c.active = 0; }
   else if (max_iters <= 0) { c.status = 1; c.active = 0; }
 }
@@ -2162,7 +2162,7 @@ void batch_begin(BatchPlan* p, hipStream_t s) {
   if (D == 2) kb_predict<2><<<gridn(p->pred), WG, 0, s>>>(p->items_d, p->ctl_d, p->pred.d, nm, p->cfg.h, p->cfg.quasistatic);
   else kb_predict<3><<<gridn(p->pred), WG, 0, s>>>(p->items_d, p->ctl_d, p->pred.d, nm, p->cfg.h, p->cfg.quasistatic);
   if (D == 2) b_gradient<2>(p, 0, s); else b_gradient<3>(p, 0, s);
-  kb_init<<<gb, WG, 0, s>>>(p->ctl_d, nm, p->cfg.tol, p->cfg.max_iters);
+  kb_init<<<gb, WG, 0, s>>>(p->items_d, p->ctl_d, nm, p->cfg.tol, p->cfg.max_iters);
   if (p->cfg.line_search) {
     if (D == 2) b_energy<2>(p, 0, 2, s); else b_energy<3>(p, 0, 2, s);
   }

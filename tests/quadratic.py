@@ -43,6 +43,10 @@ class QuadraticProblem:
     def hessian(self, x, project=True):
         return self.K.copy()
 
+    def load_norm(self):
+        """No gravity load: the residual is relative to the start gradient."""
+        return 0.0
+
     def adjacency(self):
         K = self.K.tocoo()
         nbr = [set() for _ in range(self.n)]

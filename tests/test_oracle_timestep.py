@@ -51,3 +51,46 @@ def test_warm_start_acceptance_rule():
     bad = p.X + 0.3 * np.random.default_rng(0).normal(size=p.X.shape)
     _, _, r2, acc2 = step(p, x, v, s.targets(1), B, prm, 1e-8, proposal=bad)
     assert not acc2 and r2.iters == r0.iters
+
+
+def test_load_norm_closed_form():
+    """|s_el m_i g| over free vertices for one unit right tet, rho = 6, h = 0.1:
+    V = 1/6, every lumped mass = rho V / 4 = 1/4; three free vertices."""
+    import numpy as np
+    from oracle.fem import Problem
+    X = np.array([[0.0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]])
+    fixed = np.array([True, False, False, False])
+    p = Problem(X, np.array([[0, 1, 2, 3]]), fixed, 1e3, 0.3, 6.0, np.array([0.0, -9.81, 0.0]), 0.1, False)
+    assert abs(p.load_norm() - 0.01 * np.sqrt(3 * 0.25 ** 2) * 9.81) <= 1e-15
+    q = Problem(X, np.array([[0, 1, 2, 3]]), fixed, 1e3, 0.3, 6.0, np.array([0.0, -9.81, 0.0]), 0.1, True)
+    assert abs(q.load_norm() - np.sqrt(3 * 0.25 ** 2) * 9.81) <= 1e-14
+
+
+def test_settled_loaded_body_converges():
+    """A bar at its static equilibrium under gravity, at rest: the predictor
+    is the solution, its gradient is rounding-sized, and the step converges
+    at once because the test is relative to the gravity load (a test
+    relative to the predictor's gradient alone could not be met)."""
+    import numpy as np
+    from ccscenes import tet_bar
+    from oracle import solvers as S
+    from oracle.basis import exact_basis
+    from oracle.fem import Problem
+    from oracle.timestep import predictor, step
+    s = tet_bar(7, 3, 3, E=1e6)
+    qs = Problem(s.X, s.elems, s.fixed, s.E, s.nu, s.rho, s.gravity, s.dt, True)
+    xs = S.newton(qs, s.X.copy(), tol=1e-12).x                 # static equilibrium
+    p = Problem.from_scene(s)
+    B = exact_basis(p)
+    v0 = np.zeros_like(xs)
+    xh = predictor(p, xs, v0, s.targets(1))
+    g0 = np.linalg.norm(p.gradient(xh))
+    assert g0 <= 1e-6 * p.load_norm()
+    prm = S.Params(method=S.CC, sweep=S.JACOBI, line_search=True, max_iters=50)
+    x1, _, res, _ = step(p, xs, v0, s.targets(1), B, prm, 1e-6)
+    assert res.status == S.OK and res.iters <= 1
+    assert np.linalg.norm(x1 - xs) <= 1e-6 * np.linalg.norm(xs - s.X)
+    # relative to its own start gradient instead, the same step asks for a
+    # residual of 1e-6 * g0: below the level the iteration reaches
+    res2 = S.solve(p, xh, B, prm, 1e-6 * g0 / p.load_norm())
+    assert res2.status != S.OK or res2.iters > 1

@@ -6,9 +6,12 @@ Run mode (under rocprofv3 --pmc): steps a workload with one Jacobi iteration
 per step, so that every launch of the iteration covers the whole workload,
 then copies a buffer of known size (the calibration kernel):
   batch64  the 64 seed-drawn bars of the benchmark with their exact bases,
-           float32 local arithmetic (kernel of record: kb_prep_band);
+           corotated, float32 local arithmetic (kernel of record:
+           kb_prep_band);
   beam     the 81x21x21 twisted beam with its exact, corotated basis,
            float32 local arithmetic.
+--dense-rows sets the rows per workgroup of the condensation (the
+autotuner's choice in bench.py; 0: the most that fit).
 
 Summarize mode: reads the counter CSVs of a FETCH_SIZE run and a WRITE_SIZE
 run, scales each counter by the ratio of known to counted bytes of the copy
@@ -57,7 +60,7 @@ def scenes_of(workload):
     return batch_bars(64) if workload == "batch64" else [twist_beam()]
 
 
-def run(workload, steps):
+def run(workload, steps, dense_rows=0):
     import numpy as np
     import torch
     import paper_2510_12053_amd.ccgpu as cg
@@ -76,8 +79,9 @@ def run(workload, steps):
         vs.append(torch.tensor(v, device=dev))
     print("bases built", flush=True)
     cg.cc_batch_tuning(ctx, 16, 0)
+    cg.cc_dense_tuning(ctx, dense_rows)
     par = cg.cc_params_default(method=cg.METHOD_CC, sweep=cg.SWEEP_JACOBI, line_search=1, max_iters=1,
-                               precision=cg.FP32_MIXED, corotate=int(workload == "beam"))
+                               precision=cg.FP32_MIXED, corotate=1)
     grav = np.stack([s.gravity for s in scenes])
     for t in range(1, steps + 1):
         bcs = [torch.tensor(s.targets(t), device=dev) for s in scenes]
@@ -142,7 +146,7 @@ def summarize(fetch_dir, write_dir, workload):
     # the first dispatches of a class can run before the graph warms up; the
     # iteration launches of every step are alike, so take the mean of all
     alg = algorithmic(workload)
-    name = {"batch64": "the 64 seed-drawn bars of the benchmark, exact bases",
+    name = {"batch64": "the 64 seed-drawn bars of the benchmark, exact corotated bases",
             "beam": "the 81x21x21 twisted beam, exact corotated basis"}[workload]
     flag = "" if workload == "batch64" else " --workload beam"
     tag = "batch64" if workload == "batch64" else "beam81x21x21"
@@ -255,6 +259,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--workload", choices=("batch64", "beam"), default="batch64")
+    ap.add_argument("--dense-rows", type=int, default=0)
     ap.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "BENCH_LOG"))
     a = ap.parse_args()
@@ -263,7 +268,7 @@ def main():
     elif a.trace_summary:
         trace_summary(*a.trace_summary)
     else:
-        run(a.workload, a.steps)
+        run(a.workload, a.steps, a.dense_rows)
 
 
 if __name__ == "__main__":

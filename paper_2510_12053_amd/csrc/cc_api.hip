@@ -42,7 +42,7 @@ struct Mesh {
   // in band positions (every block couples the same or adjacent levels)
   std::vector<int> bvert_h, bpos_h, lev_off;
   std::vector<int> cel_ptr_h, csl_ptr_h;   // per-colour dirty element / slot list offsets
-  int *d_bvert = nullptr, *d_bpos = nullptr, *d_bqcnt = nullptr, *d_bqpos = nullptr, *d_hqslot = nullptr;
+  int *d_bvert = nullptr, *d_bpos = nullptr, *d_bqcnt = nullptr, *d_hqslot = nullptr;
   void* hq = nullptr;
   int qmax = 0, band_w = 0;
 
@@ -83,7 +83,7 @@ struct Mesh {
     v.ev = ev; v.dinv_d = dinv_d; v.dinv_f = dinv_f; v.vol_d = vol_d; v.vol_f = vol_f;
     v.mass = mass; v.vperm = d_vperm; v.star_ptr = star_ptr; v.star = star; v.rowptr = d_rowptr;
     v.colidx = d_colidx; v.blkrow = blkrow; v.cptr = cptr; v.centry = centry; v.nnzb = nnzb;
-    v.bvert = d_bvert; v.bpos = d_bpos; v.bq_cnt = d_bqcnt; v.bq_pos = d_bqpos; v.hq_slot = d_hqslot;
+    v.bvert = d_bvert; v.bpos = d_bpos; v.bq_cnt = d_bqcnt; v.hq_slot = d_hqslot;
     v.hq = dense ? hq : nullptr;   // the assembly writes the band copy only for dense bases
     v.qmax = qmax; v.band_w = band_w; v.ring = cc::band_ring(nf, band_w);
     v.sptr = sptr; v.sidx = sidx; v.U_d = U_d; v.U_f = U_f; v.dense_supp = dense;
@@ -150,7 +150,7 @@ void free_basis(Mesh& M) {
 void free_mesh(Mesh& M) {
   dfree(M.ev); dfree(M.star_ptr); dfree(M.star); dfree(M.d_rowptr); dfree(M.d_colidx);
   dfree(M.blkrow); dfree(M.cptr); dfree(M.centry); dfree(M.d_vperm); dfree(M.d_vinv);
-  dfree(M.d_bvert); dfree(M.d_bpos); dfree(M.d_bqcnt); dfree(M.d_bqpos); dfree(M.d_hqslot); dfree(M.hq);
+  dfree(M.d_bvert); dfree(M.d_bpos); dfree(M.d_bqcnt); dfree(M.d_hqslot); dfree(M.hq);
   dfree(M.d_eperm); dfree(M.d_sorder); dfree(M.d_aorder);
   dfree(M.d_cel_ptr); dfree(M.d_cel); dfree(M.d_csl_ptr); dfree(M.d_csl); dfree(M.dinv_d); dfree(M.vol_d); dfree(M.mass); dfree(M.dinv_f); dfree(M.vol_f);
   free_basis(M);
@@ -593,19 +593,16 @@ void build_mesh(cc_ctx* ctx, Mesh& M) {
       M.qmax = std::max(M.qmax, cnt[p]);
       if (!up[p].empty()) M.band_w = std::max(M.band_w, up[p].back().first - p);
     }
-    std::vector<int> qpos((size_t)M.qmax * nf);
     for (int p = 0; p < nf; ++p)
-      for (int q = 0; q < M.qmax; ++q) {
-        const bool in = q < cnt[p];
-        qpos[(size_t)q * nf + p] = in ? up[p][q].first : p;
-        if (in) hslot[up[p][q].second] = q * nf + p;
-      }
+      for (int q = 0; q < cnt[p]; ++q) hslot[up[p][q].second] = q * nf + p;
     M.d_bqcnt = dupload(cnt, s);
-    M.d_bqpos = dupload(qpos, s);
     M.d_hqslot = dupload(hslot, s);
-    const size_t hqn = (size_t)std::max(M.qmax, 1) * D * D * std::max(nf, 1);
-    M.hq = dalloc<double>(hqn);
-    HIPC(hipMemsetAsync(M.hq, 0, hqn * sizeof(double), s));   // padding blocks stay zero
+    // one BandRec per (q, p), sized for float64 (float32 records are smaller);
+    // records past a row's count are never read
+    const size_t rec = D == 2 ? sizeof(cc::BandRec<double, 2>) : sizeof(cc::BandRec<double, 3>);
+    const size_t hqb = (size_t)std::max(M.qmax, 1) * std::max(nf, 1) * rec;
+    M.hq = dalloc<double>(hqb / sizeof(double));
+    HIPC(hipMemsetAsync(M.hq, 0, hqb, s));
   }
   M.cptr = dupload(cptr, s);
   M.centry = dupload(centry, s);
@@ -1071,7 +1068,12 @@ struct Stepper {
     ctx->timed(CC_K_ELEM_HESS, [&] {
       cc::launch_elem_hess_list(mv, p.precision, x, mat, mat.s_el, M.estore, s, el, ne);
     });
-    ctx->timed(CC_K_ASSEMBLE, [&] { cc::launch_assemble_list(mv, p.precision, M.estore, mat, M.hb, s, sl, ns); });
+    ctx->timed(CC_K_ASSEMBLE, [&] {
+      cc::launch_assemble_list(mv, p.precision, M.estore, mat, M.hb, s, sl, ns);
+      // a partial assembly leaves band records of unchanged blocks whose
+      // rotations did change
+      if (colour >= 0 && mv.rot != nullptr) cc::launch_band_copy(mv, p.precision, M.hb, s);
+    });
   }
   void prep(int method, int v0, int v1) {
     ctx->timed(CC_K_CC_PREP, [&] {

@@ -30,15 +30,13 @@ struct MeshView {
   // order): bvert[p] = internal id at band position p, bpos = its inverse.
   // Every neighbour k of a vertex j lies within band_w positions after it
   // (when k comes later).  Row p's blocks (j, k) with bpos[k] >= bpos[j]
-  // ("upper" blocks, the diagonal first) number bq_cnt[p] <= qmax; bq_pos
-  // [q * nf + p] holds the band position of the q-th one's column.  The
-  // assembly kernel also writes those blocks, the diagonal at half weight,
-  // into hq [(q * D*D + rs) * nf + p] (precision of hb) when hq is set:
+  // ("upper" blocks, the diagonal first) number bq_cnt[p] <= qmax.  When hq
+  // is set (dense bases), hq[q * nf + p] is the BandRec (precision of hb) of
+  // the q-th of them, written by the assembly and band-copy kernels:
   // hq_slot[t] = q * nf + p for an upper slot t of hb, -1 otherwise.
   const int* bvert;
   const int* bpos;
   const int* bq_cnt;
-  const int* bq_pos;
   const int* hq_slot;
   void* hq;
   int qmax, band_w;
@@ -111,6 +109,10 @@ void launch_elem_hess_list(const MeshView& mv, int prec, const double* x, const 
                            double scale, void* estore, hipStream_t s, const int* elist, int count);
 void launch_assemble_list(const MeshView& mv, int prec, const void* estore, const Material& mat, void* hb,
                           hipStream_t s, const int* slist, int count);
+// Rewrites every BandRec of a dense-basis mesh (hq set) from the block rows
+// hb and the current rotations: after a partial assembly whose rotations
+// changed everywhere (a coloured sweep of a corotated mesh).
+void launch_band_copy(const MeshView& mv, int prec, const void* hb, hipStream_t s);
 void launch_gradient(const MeshView& mv, const double* x, const double* xt, const Material& mat,
                      double* g, double* partials, int* nparts, hipStream_t s);
 // Condensation of vertices [v0, v1).  With g and dout given (g the gradient
@@ -147,6 +149,33 @@ int reduce_partials_capacity(const MeshView& mv);
 // number of vertices one workgroup takes (0: the ring does not fit).
 constexpr int BWG = 512;
 void set_lds_limit(size_t bytes);
+// One upper block (j, k) of H in band order, as the dense condensation reads
+// it: h = w R_j^T H_jk R_k (w = 1/2 on the diagonal block; R = I without
+// corotation, else the vertex rotations at the Hessian's positions), pos =
+// the band position of k.  Rotating H instead of the basis blocks keeps the
+// condensation free of per-row rotations:
+//   (R_j U_j)^T H_jk (R_k U_k) = U_j^T (R_j^T H_jk R_k) U_k.
+template <typename T, int D>
+struct alignas(16) BandRec {
+  T h[D * D];
+  int pos;
+};
+
+// Access unit (bytes) and 32-bit words of one slot of the dense
+// condensation's LDS ring: tv blocks of D*D values of tsize bytes, read and
+// written in the widest unit (16, 8 or 4 bytes) that divides them, padded to
+// an odd number of units, so that consecutive slots read one unit each from
+// distinct banks.
+__host__ __device__ constexpr int ring_slot_unit(int tv, int D, int tsize) {
+  return (tv * D * D * tsize) % 16 == 0 ? 16 : (tv * D * D * tsize) % 8 == 0 ? 8 : 4;
+}
+__host__ __device__ constexpr int ring_slot_words(int tv, int D, int tsize) {
+  const int unit = ring_slot_unit(tv, D, tsize);
+  int u = tv * D * D * tsize / unit;
+  if (u % 2 == 0) ++u;
+  return u * unit / 4;
+}
+
 int band_ring(int nf, int band_w);
 // cap > 0 limits the rows per workgroup (tuning); 0 takes the most that fit.
 int dense_tv(int ring, int D, int prec, int cap = 0);

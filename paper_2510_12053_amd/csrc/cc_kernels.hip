@@ -131,6 +131,50 @@ __global__ void __launch_bounds__(elem_threads<T>()) k_elem_hess(MeshView mv, co
 
 // Block rows: every slot sums its element contributions (fixed order), plus
 // the mass on the diagonal.
+// The BandRec of block slot t (row j) of a dense-basis mesh, when t is an
+// upper slot: w R_j^T H_jk R_k and the band position of k.
+template <typename T, int D>
+__device__ __forceinline__ void band_rec_write(const MeshView& mv, int t, int j, const T* blk) {
+  constexpr int DD = D * D;
+  const int qp = mv.hq_slot[t];
+  if (qp < 0) return;
+  const int k = mv.colidx[t];
+  const T w = k == j ? T(0.5) : T(1);
+  T b[DD];
+#pragma unroll
+  for (int r = 0; r < DD; ++r) b[r] = w * blk[r];
+  if (mv.rot != nullptr) {
+    T Rj[DD], Rk[DD], tmp[DD];
+#pragma unroll
+    for (int r = 0; r < DD; ++r) {
+      Rj[r] = T(mv.rot[(size_t)j * DD + r]);
+      Rk[r] = T(mv.rot[(size_t)k * DD + r]);
+    }
+#pragma unroll
+    for (int r = 0; r < D; ++r)               // tmp = B R_k
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        T acc = T(0);
+#pragma unroll
+        for (int l = 0; l < D; ++l) acc += b[r * D + l] * Rk[l * D + c];
+        tmp[r * D + c] = acc;
+      }
+#pragma unroll
+    for (int r = 0; r < D; ++r)               // b = R_j^T tmp
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        T acc = T(0);
+#pragma unroll
+        for (int l = 0; l < D; ++l) acc += Rj[l * D + r] * tmp[l * D + c];
+        b[r * D + c] = acc;
+      }
+  }
+  auto* rec = reinterpret_cast<BandRec<T, D>*>(mv.hq) + qp;
+#pragma unroll
+  for (int r = 0; r < DD; ++r) rec->h[r] = b[r];
+  rec->pos = mv.bpos[k];
+}
+
 template <typename T, int D>
 __device__ __forceinline__ void assemble_body(const MeshView& mv, int tt, const T* __restrict__ est,
                                               T w_in, T* __restrict__ hb, const int* slist = nullptr,
@@ -192,16 +236,13 @@ __device__ __forceinline__ void assemble_body(const MeshView& mv, int tt, const 
   }
 #pragma unroll
   for (int r = 0; r < DD; ++r) hb[(size_t)t * DD + r] = acc[r];
-  if (mv.hq != nullptr) {                 // band copy of an upper block for the dense condensation
-    const int qp = mv.hq_slot[t];
-    if (qp >= 0) {
-      const int nf = mv.nf, q = qp / nf, pp = qp - q * nf;
-      const T w = mv.colidx[t] == j ? T(0.5) : T(1);
-      T* hq = reinterpret_cast<T*>(mv.hq);
-#pragma unroll
-      for (int r = 0; r < DD; ++r) hq[((size_t)q * DD + r) * nf + pp] = w * acc[r];
-    }
-  }
+  if (mv.hq != nullptr) band_rec_write<T, D>(mv, t, j, acc);
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(EWG) k_band_copy(MeshView mv, const T* __restrict__ hb) {
+  const int t = blockIdx.x * EWG + threadIdx.x;
+  if (t < mv.nnzb) band_rec_write<T, D>(mv, t, mv.blkrow[t], hb + (size_t)t * D * D);
 }
 
 template <typename T, int D>
@@ -459,29 +500,32 @@ __global__ void __launch_bounds__(WG) k_cc_prep(MeshView mv, int method, int v0,
 }
 
 // Exact-basis condensation of TV vertices per workgroup (Method, Eqs. block
-// and schur: A_i = H_iC U_i, Ht_i = U_i^T H_CC U_i, b_i = U_i^T g_C).
+// and schur: A_i = H_iC U_i, Ht_i = U_i^T H_CC U_i, b_i = U_i^T g_C; with
+// corotation every U_i[j] is R_j U_i[j], Eq. rotation).
 //
 // The basis rows are stored in band order (MeshView::bvert), in which every
 // block (j, k) of H with k after j has k within band_w positions of j.  H is
-// symmetric, so with X_jk = U_j^T H_jk U_k
+// symmetric, so with X_jk = U_j^T H''_jk U_k, H''_jk = R_j^T H_jk R_k,
 //   Ht = sum_{j,k} X_jk = Y + Y^T,  Y = sum_j U_j^T W_j,
-//   W_j = sum_{k >= j} w_jk H_jk U_k  (w = 1/2 on the diagonal block, folded
-//                                      into the band copy hq of H),
-// and only the upper blocks are read.  The workgroup walks the band in chunks
-// of BWG positions, one thread per row j of the chunk; row j needs U at
-// positions [j, j + band_w], so the TV rows live in an LDS ring of R >= BWG +
-// band_w positions, component planes [v][rs][R], refilled one chunk ahead:
-// the global loads of chunk c + 1's new positions are issued before chunk c's
-// products and stored after them.  Threads of a wave take consecutive rows,
-// whose q-th upper columns are (on the structured grids) consecutive
-// positions, so the plane reads hit distinct banks and the hq loads coalesce.
-// Every H block serves the TV rows of the workgroup from registers.
-// A_i = sum_k H_ik U_i[k] comes from row i in global memory (one wave per
-// vertex; the row was just streamed through L2).
+//   W_j = sum_{k >= j} w_jk H''_jk U_k  (w = 1/2 on the diagonal block),
+// and only the upper blocks are read, from the BandRec list hq (rotated and
+// weighted there once per Hessian, not once per basis row).  The workgroup
+// walks the band in chunks of BWG positions, one thread per row j of the
+// chunk; row j needs U at positions [j, j + band_w], so the TV rows live in
+// an LDS ring of R >= BWG + band_w positions, refilled one chunk ahead: the
+// global loads of chunk c + 1's new positions are issued before chunk c's
+// products and stored after them.  A ring slot holds the TV blocks of one
+// position contiguously, padded to an odd number of words, so a block read
+// is one address and constant offsets, and the threads of a wave, which
+// take consecutive positions (whose columns are, on structured grids,
+// consecutive too), hit distinct banks.  Every H block serves the TV rows of
+// the workgroup from registers.
+// A_i = sum_k H_ik R_k U_i[k] comes from row i in global memory (one wave
+// per vertex; the row was just streamed through L2).
 //
-// With g given (Jacobi sweeps), b_i = U_i^T g_C is also accumulated from the
-// staged rows and stored in bout (component-major, stride n); the finish
-// kernel then writes the direction itself.
+// With g given (Jacobi sweeps), b_i = U_i^T (R^T g)_C is also accumulated
+// from the staged rows and stored in bout (component-major, stride n); the
+// finish kernel then writes the direction itself.
 template <typename T, int D>
 __device__ __forceinline__ void band_load(const MeshView& mv, const T* __restrict__ Ub, int row, int pos,
                                           T (&blk)[D * D]) {
@@ -491,42 +535,168 @@ __device__ __forceinline__ void band_load(const MeshView& mv, const T* __restric
   for (int r = 0; r < DD; ++r) blk[r] = src[r];
 }
 
+// Raw buffer resource over `bytes` bytes at p (offsets past the end read
+// as zero).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+// A BandRec as raw dwords, loaded 16 bytes at a time from byte offset off.
+template <typename T, int D>
+struct RecWords {
+  static constexpr int N = sizeof(BandRec<T, D>) / 4;
+  uint32_t w[N];
+  __device__ __forceinline__ void fetch(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+#pragma unroll
+    for (int c = 0; c < N / 4; ++c) {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16u * c, 0, 0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) w[4 * c + e] = v[e];
+    }
+  }
+  __device__ __forceinline__ T h(int r) const {
+    if constexpr (sizeof(T) == 4) {
+      return __builtin_bit_cast(float, w[r]);
+    } else {
+      return __builtin_bit_cast(double, (uint64_t)w[2 * r] | ((uint64_t)w[2 * r + 1] << 32));
+    }
+  }
+  __device__ __forceinline__ int pos() const { return (int)w[D * D * sizeof(T) / 4]; }
+};
+
+// Sum over the 64 lanes of a wave, valid in lane 63: rotations within each
+// row of 16 lanes leave the row sum in every lane of the row, then two row
+// broadcasts add rows 0-1 into row 3 (DPP, no LDS traffic).
+__device__ __forceinline__ float dpp_step(float x, int y) { return x + __builtin_bit_cast(float, y); }
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_add(float x) {
+  const int y = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROWS, 0xf, false);
+  return dpp_step(x, y);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_add(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWS, 0xf, false);
+  return x + __builtin_bit_cast(double, (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32));
+}
+template <typename T>
+__device__ __forceinline__ T wave_sum63(T x) {
+  x = dpp_add<0x128, 0xf>(x);   // row_ror:8
+  x = dpp_add<0x124, 0xf>(x);   // row_ror:4
+  x = dpp_add<0x122, 0xf>(x);   // row_ror:2
+  x = dpp_add<0x121, 0xf>(x);   // row_ror:1
+  x = dpp_add<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+  x = dpp_add<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+template <int W> struct UnitVec;
+template <> struct UnitVec<1> { typedef uint32_t type; };
+template <> struct UnitVec<2> { typedef uint32_t type __attribute__((ext_vector_type(2))); };
+template <> struct UnitVec<4> { typedef uint32_t type __attribute__((ext_vector_type(4))); };
+
+// The TV blocks of one ring slot in registers, read and written one access
+// unit at a time (ring_slot_unit).
+template <typename T, int D, int TV>
+struct SlotRegs {
+  static constexpr int NW = TV * D * D * (int)sizeof(T) / 4;              // data words
+  static constexpr int UW = ring_slot_unit(TV, D, (int)sizeof(T)) / 4;   // words per unit
+  typedef typename UnitVec<UW>::type unit_t;
+  uint32_t w[NW];
+  __device__ __forceinline__ void load(const uint32_t* slot) {
+    const unit_t* src = reinterpret_cast<const unit_t*>(slot);
+#pragma unroll
+    for (int c = 0; c < NW / UW; ++c) {
+      const unit_t u = src[c];
+      if constexpr (UW == 1) {
+        w[c] = u;
+      } else {
+#pragma unroll
+        for (int e = 0; e < UW; ++e) w[c * UW + e] = u[e];
+      }
+    }
+  }
+  __device__ __forceinline__ void store(uint32_t* slot) const {
+    unit_t* dst = reinterpret_cast<unit_t*>(slot);
+#pragma unroll
+    for (int c = 0; c < NW / UW; ++c) {
+      unit_t u;
+      if constexpr (UW == 1) {
+        u = w[c];
+      } else {
+#pragma unroll
+        for (int e = 0; e < UW; ++e) u[e] = w[c * UW + e];
+      }
+      dst[c] = u;
+    }
+  }
+  __device__ __forceinline__ T get(int idx) const {        // idx = v * D*D + r
+    if constexpr (sizeof(T) == 4) {
+      return __builtin_bit_cast(float, w[idx]);
+    } else {
+      return __builtin_bit_cast(double, (uint64_t)w[2 * idx] | ((uint64_t)w[2 * idx + 1] << 32));
+    }
+  }
+  __device__ __forceinline__ void set(int idx, T x) {
+    if constexpr (sizeof(T) == 4) {
+      w[idx] = __builtin_bit_cast(uint32_t, x);
+    } else {
+      const uint64_t b = __builtin_bit_cast(uint64_t, x);
+      w[2 * idx] = (uint32_t)b;
+      w[2 * idx + 1] = (uint32_t)(b >> 32);
+    }
+  }
+};
+
 template <typename T, int D, int TV>
 __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, int i0, int nv,
                                                const T* __restrict__ hb, T* __restrict__ KL, T* smem,
                                                const double* __restrict__ g, double* __restrict__ bout) {
-  constexpr int DD = D * D, NW = BWG / 64, NR = DD + D;
+  constexpr int DD = D * D, NW = BWG / 64, NR = DD + D, SLW = ring_slot_words(TV, D, sizeof(T));
   const int nf = mv.nf, n = mv.n, R = mv.ring, msk = R - 1, bw = mv.band_w;
-  T* ring = smem;                                   // [TV][DD][R]
-  T* red = smem + (size_t)TV * DD * R;              // [NW][TV][NR]
+  uint32_t* ring = reinterpret_cast<uint32_t*>(smem);              // [R][SLW] words
+  T* red = reinterpret_cast<T*>(ring + (size_t)R * SLW);          // [NW][TV][NR]
   const T* Ub = basis_of<T>(mv);
-  const T* hq = reinterpret_cast<const T*>(mv.hq);
+  constexpr uint32_t RB = sizeof(BandRec<T, D>);
+  const __amdgpu_buffer_rsrc_t hrs = buf_rsrc(mv.hq, (uint32_t)((size_t)mv.qmax * nf * RB));
   const int tid = threadIdx.x;
   int rows[TV];
 #pragma unroll
   for (int v = 0; v < TV; ++v) rows[v] = i0 + (v < nv ? v : 0);
-  // stage block (row v, position pos), rotated by R_j (j at pos) when corotated
-  auto put = [&](int v, int pos, T (&blk)[DD]) {
+  auto put = [&](int pos, T (&blk)[TV][DD]) {
+    SlotRegs<T, D, TV> sr;
 #pragma unroll
-    for (int r = 0; r < DD; ++r) ring[((size_t)v * DD + r) * R + (pos & msk)] = blk[r];
+    for (int v = 0; v < TV; ++v)
+#pragma unroll
+      for (int r = 0; r < DD; ++r) sr.set(v * DD + r, blk[v][r]);
+    sr.store(ring + (size_t)(pos & msk) * SLW);
   };
+  // one buffer resource per basis row (a dense basis can pass 4 GiB, one
+  // row cannot), so a block's offset is pos * D*D * sizeof(T)
+  __amdgpu_buffer_rsrc_t urs[TV];
+#pragma unroll
+  for (int v = 0; v < TV; ++v)
+    urs[v] = buf_rsrc(Ub + (size_t)rows[v] * nf * DD, (uint32_t)((size_t)nf * DD * sizeof(T)));
   auto fetch = [&](int pos, T (&blk)[TV][DD]) {
+    const uint32_t off = (uint32_t)pos * (uint32_t)(DD * sizeof(T));
 #pragma unroll
-    for (int v = 0; v < TV; ++v) band_load<T, D>(mv, Ub, rows[v], pos, blk[v]);
-  };
-  auto rotate_all = [&](int pos, T (&blk)[TV][DD]) {
-    if (mv.rot == nullptr) return;
-    const int j = gptr(mv.bvert)[pos];
+    for (int v = 0; v < TV; ++v)
 #pragma unroll
-    for (int v = 0; v < TV; ++v) rotate_block<T, D>(mv.rot, j, blk[v]);
+      for (int r = 0; r < DD; ++r) {
+        if constexpr (sizeof(T) == 4) {
+          blk[v][r] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(urs[v], off + 4u * r, 0, 0));
+        } else {
+          const auto u = __builtin_amdgcn_raw_buffer_load_b64(urs[v], off + 8u * r, 0, 0);
+          blk[v][r] = __builtin_bit_cast(double, u);
+        }
+      }
   };
   int lo = min(nf, BWG + bw);                       // first fill: positions [0, lo)
   for (int pos = tid; pos < lo; pos += BWG) {
     T blk[TV][DD];
     fetch(pos, blk);
-    rotate_all(pos, blk);
-#pragma unroll
-    for (int v = 0; v < TV; ++v) put(v, pos, blk[v]);
+    put(pos, blk);
   }
   __syncthreads();
   T Y[TV][DD], Bv[TV][D];
@@ -537,7 +707,6 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
 #pragma unroll
     for (int r = 0; r < D; ++r) Bv[v][r] = T(0);
   }
-  const auto* bq_pos = gptr(mv.bq_pos);
   for (int p0 = 0; p0 < nf; p0 += BWG) {
     // chunk p0 + BWG needs positions up to p0 + 2 BWG + bw: prefetch them
     const int nhi = min(nf, p0 + 2 * BWG + bw);
@@ -553,51 +722,69 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
       for (int v = 0; v < TV; ++v)
 #pragma unroll
         for (int r = 0; r < DD; ++r) W[v][r] = T(0);
-      // software pipeline: the column and the H block of upper block q + 1
-      // are loaded while block q's LDS reads and products run (the LDS
-      // addresses depend on a global load, whose latency would otherwise
-      // stall every block at two waves per SIMD)
-      int kp = bq_pos[p] & msk;
-      T H[DD];
-#pragma unroll
-      for (int r = 0; r < DD; ++r) H[r] = gptr(hq)[(size_t)r * nf + p];
-      for (int q = 0; q < cnt; ++q) {
-        const int qn = min(q + 1, cnt - 1);   // the last block loads itself again
-        const int kpn = bq_pos[(size_t)qn * nf + p] & msk;
-        T Hn[DD];
-#pragma unroll
-        for (int r = 0; r < DD; ++r) Hn[r] = gptr(hq)[((size_t)qn * DD + r) * nf + p];
+      // software pipeline, unrolled by two: upper block q + 1 (its H and
+      // column) is loaded while block q's LDS reads and products run.
+      // Records past the row's count are zero padding or past the end of
+      // the buffer (read as zero) and are never used.
+      auto consume = [&](const RecWords<T, D>& rc) {
+        SlotRegs<T, D, TV> sr;
+        sr.load(ring + (size_t)(rc.pos() & msk) * SLW);
 #pragma unroll
         for (int v = 0; v < TV; ++v) {
           T U[DD];
 #pragma unroll
-          for (int r = 0; r < DD; ++r) U[r] = ring[((size_t)v * DD + r) * R + kp];
+          for (int r = 0; r < DD; ++r) U[r] = sr.get(v * DD + r);
 #pragma unroll
           for (int r = 0; r < D; ++r)
 #pragma unroll
             for (int c = 0; c < D; ++c) {
               T acc = W[v][r * D + c];
 #pragma unroll
-              for (int l = 0; l < D; ++l) acc += H[r * D + l] * U[l * D + c];
+              for (int l = 0; l < D; ++l) acc += rc.h(r * D + l) * U[l * D + c];
               W[v][r * D + c] = acc;
             }
         }
-        kp = kpn;
-#pragma unroll
-        for (int r = 0; r < DD; ++r) H[r] = Hn[r];
+      };
+      const uint32_t step = (uint32_t)nf * RB;
+      uint32_t off = (uint32_t)p * RB;
+      RecWords<T, D> ra, rb;
+      ra.fetch(hrs, off);
+      int q = 0;
+      for (; q + 1 < cnt; q += 2) {
+        rb.fetch(hrs, off + step);
+        consume(ra);
+        ra.fetch(hrs, off + 2 * step);
+        consume(rb);
+        off += 2 * step;
       }
+      if (q < cnt) consume(ra);
       T gj[D];
       if (g != nullptr) {
         const int j = gptr(mv.bvert)[p];
+        double gd[D];
 #pragma unroll
-        for (int c = 0; c < D; ++c) gj[c] = T(gptr(g)[(size_t)c * n + j]);
+        for (int c = 0; c < D; ++c) gd[c] = gptr(g)[(size_t)c * n + j];
+        if (mv.rot != nullptr) {              // R_j^T g_j
+          const auto* Rj = gptr(mv.rot) + (size_t)j * DD;
+#pragma unroll
+          for (int c = 0; c < D; ++c) {
+            double acc = 0.0;
+#pragma unroll
+            for (int l = 0; l < D; ++l) acc += Rj[l * D + c] * gd[l];
+            gj[c] = T(acc);
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < D; ++c) gj[c] = T(gd[c]);
+        }
       }
-      const int sp = p & msk;
+      SlotRegs<T, D, TV> sj;
+      sj.load(ring + (size_t)(p & msk) * SLW);
 #pragma unroll
       for (int v = 0; v < TV; ++v) {
         T Uj[DD];
 #pragma unroll
-        for (int r = 0; r < DD; ++r) Uj[r] = ring[((size_t)v * DD + r) * R + sp];
+        for (int r = 0; r < DD; ++r) Uj[r] = sj.get(v * DD + r);
 #pragma unroll
         for (int l = 0; l < D; ++l)
 #pragma unroll
@@ -615,25 +802,19 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
       }
     }
     __syncthreads();                                // chunk p0's ring reads are done
-    if (pf) {
-      rotate_all(ppos, pre);
-#pragma unroll
-      for (int v = 0; v < TV; ++v) put(v, ppos, pre[v]);
-    }
+    if (pf) put(ppos, pre);
     lo = max(lo, nhi);
     __syncthreads();
   }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
+  for (int v = 0; v < TV; ++v) {
 #pragma unroll
-    for (int v = 0; v < TV; ++v) {
+    for (int r = 0; r < DD; ++r) Y[v][r] = wave_sum63(Y[v][r]);
 #pragma unroll
-      for (int r = 0; r < DD; ++r) Y[v][r] += __shfl_xor(Y[v][r], off, 64);
-#pragma unroll
-      for (int r = 0; r < D; ++r) Bv[v][r] += __shfl_xor(Bv[v][r], off, 64);
-    }
+    for (int r = 0; r < D; ++r) Bv[v][r] = wave_sum63(Bv[v][r]);
+  }
   const int w = tid / 64, l = tid % 64;
-  if (l == 0)
+  if (l == 63)
 #pragma unroll
     for (int v = 0; v < TV; ++v) {
 #pragma unroll
@@ -642,7 +823,7 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
       for (int r = 0; r < D; ++r) red[(w * TV + v) * NR + DD + r] = Bv[v][r];
     }
   __syncthreads();
-  T* tot = ring;                                    // the ring is free now: [TV][NR]
+  T* tot = smem;                                    // the ring is free now: [TV][NR]
   if (tid < TV * NR) {
     T acc = T(0);
 #pragma unroll
@@ -674,13 +855,12 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
         }
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-      for (int r = 0; r < DD; ++r) A[r] += __shfl_xor(A[r], off, 64);
+    for (int r = 0; r < DD; ++r) A[r] = wave_sum63(A[r]);
   }
-  if (l != 0) return;
+  if (l != 63) return;
   // A and Ht go to the vertex's K, L slots; dm_finish_body turns them into
-  // K and L with one thread per vertex
+  // K and L with one thread per vertex.  b_i = U_i^T (R^T g)_C, the
+  // corotated basis's U_i^T g_C.
   const T* Yt = tot + w * NR;
   auto* out = gptr_w(KL) + (size_t)i * 2 * DD;
 #pragma unroll
@@ -1077,6 +1257,13 @@ void launch_assemble(const MeshView& mv, int prec, const void* estore, const Mat
   launch_assemble_list(mv, prec, estore, mat, hb, s, nullptr, mv.nnzb);
 }
 
+void launch_band_copy(const MeshView& mv, int prec, const void* hb, hipStream_t s) {
+  if (mv.hq == nullptr || mv.nnzb <= 0) return;
+  const int nb = nblocks(mv.nnzb, EWG);
+  if (prec == 0) CC_DISPATCH_D(mv.D, k_band_copy<double, D><<<nb, EWG, 0, s>>>(mv, (const double*)hb));
+  else CC_DISPATCH_D(mv.D, k_band_copy<float, D><<<nb, EWG, 0, s>>>(mv, (const float*)hb));
+}
+
 void launch_assemble_list(const MeshView& mv, int prec, const void* estore, const Material& mat, void* hb,
                           hipStream_t s, const int* slist, int count) {
   if (count <= 0) return;
@@ -1156,7 +1343,8 @@ int band_ring(int nf, int band_w) {
 
 size_t dense_lds_bytes(int tv, int ring, int D, int prec) {
   const size_t S = prec == 0 ? 8 : 4;
-  return ((size_t)tv * ring * D * D + (size_t)(BWG / 64) * tv * (D * D + D)) * S;
+  // ring slots (ring_slot_words), then the per-wave partial sums
+  return (size_t)ring * ring_slot_words(tv, D, (int)S) * 4 + (size_t)(BWG / 64) * tv * (D * D + D) * S;
 }
 
 // float64 keeps two rows per workgroup (the register file of 2 waves/SIMD
@@ -1469,6 +1657,21 @@ __global__ void __launch_bounds__(EWG) kb_assemble(const BatchItem* __restrict__
   const int cnt = lst ? mv.csl_ptr[colour + 1] - mv.csl_ptr[colour] : mv.nnzb;
   assemble_body<T, D>(mv, (blockIdx.x - boff[mi]) * EWG + threadIdx.x, (const T*)it.estore,
                       T(it.mat.w_in), (T*)it.hb, sl, cnt);
+}
+
+// Every BandRec of the dense-basis meshes from their block rows and current
+// rotations (after a partial assembly of corotated meshes).
+template <typename T, int D>
+__global__ void __launch_bounds__(EWG) kb_band_copy(const BatchItem* __restrict__ items,
+                                                   const BatchCtl* __restrict__ ctl,
+                                                   const int* __restrict__ boff, int nmesh) {
+  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  if (!ctl[mi].active) return;
+  const BatchItem& it = items[mi];
+  const MeshView& mv = it.mv;
+  if (mv.hq == nullptr) return;
+  const int t = (blockIdx.x - boff[mi]) * EWG + threadIdx.x;
+  if (t < mv.nnzb) band_rec_write<T, D>(mv, t, mv.blkrow[t], (const T*)it.hb + (size_t)t * D * D);
 }
 
 template <int D, int G, bool FCR>
@@ -2086,6 +2289,10 @@ static void b_hessian(BatchPlan* p, int which, hipStream_t s, int colour = -1) {
   if (gridn(oa) > 0) {
     p->mark(1, 1);
     kb_assemble<T, D><<<gridn(oa), EWG, 0, s>>>(p->items_d, p->ctl_d, oa.d, p->nmesh, colour);
+    // the band records of blocks the partial assembly left alone still
+    // carry the previous rotations
+    if (colour >= 0 && gridn(p->rotn) > 0 && p->tv > 0)
+      kb_band_copy<T, D><<<gridn(p->asmb), EWG, 0, s>>>(p->items_d, p->ctl_d, p->asmb.d, p->nmesh);
     p->mark(1, 0);
   }
 }

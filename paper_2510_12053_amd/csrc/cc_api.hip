@@ -85,7 +85,7 @@ struct Mesh {
     v.colidx = d_colidx; v.blkrow = blkrow; v.cptr = cptr; v.centry = centry; v.nnzb = nnzb;
     v.bvert = d_bvert; v.bpos = d_bpos; v.bq_cnt = d_bqcnt; v.hq_slot = d_hqslot;
     v.hq = dense ? hq : nullptr;   // the assembly writes the band copy only for dense bases
-    v.qmax = qmax; v.band_w = band_w; v.ring = cc::band_ring(nf, band_w);
+    v.qmax = qmax; v.band_w = band_w;
     v.sptr = sptr; v.sidx = sidx; v.U_d = U_d; v.U_f = U_f; v.dense_supp = dense;
     v.smap = smap; v.smap_words = smap_words; v.smap_supp = smap_supp;
     v.sorder = d_sorder;
@@ -335,8 +335,17 @@ bool invert(int D, const double* A, double* Ainv, double& det) {
 // order).  A component reached from no start begins at its smallest caller
 // id.  Levels are the breadth-first distances, so every edge joins the same
 // or adjacent levels.
+// Band order of the free vertices: breadth-first levels from a start set,
+// restarted at the smallest caller id left over when the free vertices fall
+// apart; within a level, vertices in caller-id order.  Three start sets are
+// tried and the order with the smallest band width kept (the ring of the
+// dense condensation holds chunk + band width positions): the free vertices
+// next to the connected piece of the Dirichlet set holding its smallest id,
+// and the free vertices at either end of the rest shape's longest bounding-box
+// axis (whose levels, on a bar clamped along a long side, are its short cross
+// sections instead of its long ones).
 void build_band(Mesh& M) {
-  const int nf = M.nf, n = M.n, K = M.K;
+  const int nf = M.nf, n = M.n, K = M.K, D = M.D;
   // vertex -> elements
   std::vector<int> vptr(n + 1, 0), vel((size_t)M.m * K);
   for (int e = 0; e < M.m; ++e)
@@ -347,69 +356,117 @@ void build_band(Mesh& M) {
     for (int e = 0; e < M.m; ++e)
       for (int a = 0; a < K; ++a) vel[fill[M.elems[e * K + a]]++] = e;
   }
-  std::vector<char> piece(n, 0);      // the chosen connected piece of the Dirichlet set
-  int f0 = -1;
-  for (int v = 0; v < n && f0 < 0; ++v)
-    if (M.fixed[v]) f0 = v;
-  if (f0 >= 0) {
-    std::vector<int> stack{f0};
-    piece[f0] = 1;
-    while (!stack.empty()) {
-      const int u = stack.back();
-      stack.pop_back();
-      for (int t = vptr[u]; t < vptr[u + 1]; ++t)
-        for (int a = 0; a < K; ++a) {
-          const int w = M.elems[vel[t] * K + a];
-          if (M.fixed[w] && !piece[w]) { piece[w] = 1; stack.push_back(w); }
-        }
+  std::vector<std::vector<int>> start_sets;
+  {
+    std::vector<char> piece(n, 0);      // the chosen connected piece of the Dirichlet set
+    int f0 = -1;
+    for (int v = 0; v < n && f0 < 0; ++v)
+      if (M.fixed[v]) f0 = v;
+    if (f0 >= 0) {
+      std::vector<int> stack{f0};
+      piece[f0] = 1;
+      while (!stack.empty()) {
+        const int u = stack.back();
+        stack.pop_back();
+        for (int t = vptr[u]; t < vptr[u + 1]; ++t)
+          for (int a = 0; a < K; ++a) {
+            const int w = M.elems[vel[t] * K + a];
+            if (M.fixed[w] && !piece[w]) { piece[w] = 1; stack.push_back(w); }
+          }
+      }
     }
-  }
-  std::vector<int> adj_fixed(nf, 0);
-  for (int e = 0; e < M.m; ++e) {
-    bool touch = false;
-    for (int a = 0; a < K; ++a) touch |= piece[M.elems[e * K + a]] != 0;
-    if (!touch) continue;
-    for (int a = 0; a < K; ++a) {
-      const int v = M.elems[e * K + a];
-      if (!M.fixed[v]) adj_fixed[M.vinv[v]] = 1;
+    std::vector<char> adj_fixed(nf, 0);
+    for (int e = 0; e < M.m; ++e) {
+      bool touch = false;
+      for (int a = 0; a < K; ++a) touch |= piece[M.elems[e * K + a]] != 0;
+      if (!touch) continue;
+      for (int a = 0; a < K; ++a) {
+        const int v = M.elems[e * K + a];
+        if (!M.fixed[v]) adj_fixed[M.vinv[v]] = 1;
+      }
     }
-  }
-  std::vector<int> lev(nf, -1), order;
-  order.reserve(nf);
-  M.lev_off.assign(1, 0);
-  int level_base = 0;
-  auto bfs = [&](std::vector<int> starts) {
-    std::sort(starts.begin(), starts.end(), [&](int a, int b) { return M.vperm[a] < M.vperm[b]; });
-    size_t head = order.size();
-    for (int v : starts) { lev[v] = level_base; order.push_back(v); }
-    std::vector<int> nb;
-    int top = level_base;
-    while (head < order.size()) {
-      const int u = order[head++];
-      nb.clear();
-      for (int t = M.rowptr[u] + 1; t < M.rowptr[u + 1]; ++t)
-        if (lev[M.colidx[t]] < 0) nb.push_back(M.colidx[t]);
-      std::sort(nb.begin(), nb.end(), [&](int a, int b) { return M.vperm[a] < M.vperm[b]; });
-      for (int w : nb) { lev[w] = lev[u] + 1; top = std::max(top, lev[w]); order.push_back(w); }
-    }
-    level_base = top + 1;
-  };
-  std::vector<int> starts;
-  for (int j = 0; j < nf; ++j)
-    if (adj_fixed[j]) starts.push_back(j);
-  if (!starts.empty()) bfs(starts);
-  while ((int)order.size() < nf) {
-    int best = -1;
+    std::vector<int> st;
     for (int j = 0; j < nf; ++j)
-      if (lev[j] < 0 && (best < 0 || M.vperm[j] < M.vperm[best])) best = j;
-    bfs({best});
+      if (adj_fixed[j]) st.push_back(j);
+    start_sets.push_back(st);
   }
-  M.bvert_h = order;
+  if (nf > 0) {
+    std::vector<double> lo(D, 1e300), hi(D, -1e300);
+    for (int v = 0; v < n; ++v)
+      for (int c = 0; c < D; ++c) {
+        lo[c] = std::min(lo[c], M.X[(size_t)v * D + c]);
+        hi[c] = std::max(hi[c], M.X[(size_t)v * D + c]);
+      }
+    int ax = 0;
+    for (int c = 1; c < D; ++c)
+      if (hi[c] - lo[c] > hi[ax] - lo[ax]) ax = c;
+    double cmin = 1e300, cmax = -1e300;
+    for (int j = 0; j < nf; ++j) {
+      const double c = M.X[(size_t)M.vperm[j] * D + ax];
+      cmin = std::min(cmin, c);
+      cmax = std::max(cmax, c);
+    }
+    const double tol = 1e-6 * (hi[ax] - lo[ax]);
+    std::vector<int> s0, s1;
+    for (int j = 0; j < nf; ++j) {
+      const double c = M.X[(size_t)M.vperm[j] * D + ax];
+      if (c <= cmin + tol) s0.push_back(j);
+      if (c >= cmax - tol) s1.push_back(j);
+    }
+    start_sets.push_back(s0);
+    start_sets.push_back(s1);
+  }
+  auto by_caller = [&](int a, int b) { return M.vperm[a] < M.vperm[b]; };
+  struct Band { std::vector<int> order, lev; int bw = 0; };
+  auto run = [&](std::vector<int> starts) {
+    Band B;
+    B.lev.assign(nf, -1);
+    B.order.reserve(nf);
+    int level_base = 0;
+    std::vector<int> nb;
+    auto bfs = [&](std::vector<int> st) {
+      std::sort(st.begin(), st.end(), by_caller);
+      size_t head = B.order.size();
+      for (int v : st) { B.lev[v] = level_base; B.order.push_back(v); }
+      int top = level_base;
+      while (head < B.order.size()) {
+        const int u = B.order[head++];
+        nb.clear();
+        for (int t = M.rowptr[u] + 1; t < M.rowptr[u + 1]; ++t)
+          if (B.lev[M.colidx[t]] < 0) nb.push_back(M.colidx[t]);
+        std::sort(nb.begin(), nb.end(), by_caller);
+        for (int w : nb) { B.lev[w] = B.lev[u] + 1; top = std::max(top, B.lev[w]); B.order.push_back(w); }
+      }
+      level_base = top + 1;
+    };
+    if (!starts.empty()) bfs(starts);
+    while ((int)B.order.size() < nf) {
+      int best = -1;
+      for (int j = 0; j < nf; ++j)
+        if (B.lev[j] < 0 && (best < 0 || M.vperm[j] < M.vperm[best])) best = j;
+      bfs({best});
+    }
+    std::vector<int> pos(nf);
+    for (int p = 0; p < nf; ++p) pos[B.order[p]] = p;
+    for (int p = 0; p < nf; ++p) {
+      const int j = B.order[p];
+      for (int t = M.rowptr[j] + 1; t < M.rowptr[j + 1]; ++t) B.bw = std::max(B.bw, pos[M.colidx[t]] - p);
+    }
+    return B;
+  };
+  Band best;
+  bool have = false;
+  for (const auto& st : start_sets) {
+    Band B = run(st);
+    if (!have || B.bw < best.bw) { best = std::move(B); have = true; }
+  }
+  if (!have) best = run({});
+  M.bvert_h = best.order;
   M.bpos_h.assign(nf, 0);
-  for (int p = 0; p < nf; ++p) M.bpos_h[order[p]] = p;
+  for (int p = 0; p < nf; ++p) M.bpos_h[best.order[p]] = p;
+  M.lev_off.assign(1, 0);
   for (int p = 1; p <= nf; ++p)
-    if (p == nf || lev[order[p]] != lev[order[p - 1]]) M.lev_off.push_back(p);
-  (void)n;
+    if (p == nf || best.lev[best.order[p]] != best.lev[best.order[p - 1]]) M.lev_off.push_back(p);
 }
 
 void build_mesh(cc_ctx* ctx, Mesh& M) {
@@ -1669,8 +1726,8 @@ static cc_status batch_validate(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids,
 }
 
 static bool use_dense_band(const Mesh& M, int prec) {
-  const int ring = cc::band_ring(M.nf, M.band_w);
-  return M.dense && M.nf > 1 && cc::dense_tv(ring, M.D, prec) > 0 && (prec != CC_FP64 || M.U_d != nullptr);
+  return M.dense && M.nf > 1 && cc::dense_config(&M.nf, &M.band_w, 1, M.D, prec).tv > 0 &&
+         (prec != CC_FP64 || M.U_d != nullptr);
 }
 
 static void ctx_batch_hook(void* user, int kid, int begin) {

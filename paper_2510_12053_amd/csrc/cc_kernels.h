@@ -40,7 +40,6 @@ struct MeshView {
   const int* hq_slot;
   void* hq;
   int qmax, band_w;
-  int ring;              // LDS ring length (power of two) of the dense condensation
   // perturbation basis, internal ids.  Sparse bases: CSR rows sorted by
   // internal id (sptr, sidx).  Dense (exact) bases: row i holds nf blocks
   // at (i * nf + p) * D*D, column p = band position, the block at the
@@ -144,9 +143,9 @@ void launch_scatter_user(const MeshView& mv, const int* vperm, const double* src
 
 int reduce_partials_capacity(const MeshView& mv);
 
-// Dense condensation: workgroup size, the per-workgroup LDS limit of the
-// device (bytes, set once per process), the LDS ring length of a mesh and the
-// number of vertices one workgroup takes (0: the ring does not fit).
+// Dense condensation: the largest chunk of band positions per pass (= its
+// workgroup size) and the per-workgroup LDS limit of the device (bytes, set
+// once per process).
 constexpr int BWG = 512;
 void set_lds_limit(size_t bytes);
 // One upper block (j, k) of H in band order, as the dense condensation reads
@@ -176,10 +175,21 @@ __host__ __device__ constexpr int ring_slot_words(int tv, int D, int tsize) {
   return u * unit / 4;
 }
 
-int band_ring(int nf, int band_w);
-// cap > 0 limits the rows per workgroup (tuning); 0 takes the most that fit.
-int dense_tv(int ring, int D, int prec, int cap = 0);
-size_t dense_lds_bytes(int tv, int ring, int D, int prec);
+// LDS ring length (power of two) of a mesh for chunks of ch positions, and
+// the dynamic LDS of a workgroup of tv rows.
+int band_ring(int nf, int band_w, int ch);
+size_t dense_lds_bytes(int tv, int ring, int D, int prec, int ch);
+// Rows per workgroup (tv) and chunk (ch, the workgroup size) of the dense
+// condensation for meshes with the given free-vertex counts and band widths:
+// the most rows whose ring fits (at most cap when cap > 0), then the chunk
+// (256 or 512) with more resident waves per CU, ties to the smaller chunk,
+// whose workgroups overlap one another's ring fill and final sums.  tv = 0:
+// no configuration fits.
+struct DenseCfg {
+  int tv = 0, ch = 0;
+  size_t lds = 0;
+};
+DenseCfg dense_config(const int* nf, const int* band_w, int count, int D, int prec, int cap = 0);
 
 // Exact basis U_i[j] = (H^{-1})_ji ((H^{-1})_ii)^{-1} from float64 block rows
 // hb (cc_basis.hip), through the block-tridiagonal structure of H in band

@@ -510,9 +510,9 @@ __global__ void __launch_bounds__(WG) k_cc_prep(MeshView mv, int method, int v0,
 //   W_j = sum_{k >= j} w_jk H''_jk U_k  (w = 1/2 on the diagonal block),
 // and only the upper blocks are read, from the BandRec list hq (rotated and
 // weighted there once per Hessian, not once per basis row).  The workgroup
-// walks the band in chunks of BWG positions, one thread per row j of the
+// walks the band in chunks of CH positions, one thread per row j of the
 // chunk; row j needs U at positions [j, j + band_w], so the TV rows live in
-// an LDS ring of R >= BWG + band_w positions, refilled one chunk ahead: the
+// an LDS ring of R >= CH + band_w positions, refilled one chunk ahead: the
 // global loads of chunk c + 1's new positions are issued before chunk c's
 // products and stored after them.  A ring slot holds the TV blocks of one
 // position contiguously, padded to an odd number of words, so a block read
@@ -649,12 +649,15 @@ struct SlotRegs {
   }
 };
 
-template <typename T, int D, int TV>
+template <typename T, int D, int TV, int CH>
 __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, int i0, int nv,
                                                const T* __restrict__ hb, T* __restrict__ KL, T* smem,
                                                const double* __restrict__ g, double* __restrict__ bout) {
-  constexpr int DD = D * D, NW = BWG / 64, NR = DD + D, SLW = ring_slot_words(TV, D, sizeof(T));
-  const int nf = mv.nf, n = mv.n, R = mv.ring, msk = R - 1, bw = mv.band_w;
+  constexpr int DD = D * D, NW = CH / 64, NR = DD + D, SLW = ring_slot_words(TV, D, sizeof(T));
+  const int nf = mv.nf, n = mv.n, bw = mv.band_w;
+  int R = 64;                                       // band_ring(nf, bw, CH)
+  while (R < min(nf, CH + bw)) R *= 2;
+  const int msk = R - 1;
   uint32_t* ring = reinterpret_cast<uint32_t*>(smem);              // [R][SLW] words
   T* red = reinterpret_cast<T*>(ring + (size_t)R * SLW);          // [NW][TV][NR]
   const T* Ub = basis_of<T>(mv);
@@ -692,8 +695,8 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
         }
       }
   };
-  int lo = min(nf, BWG + bw);                       // first fill: positions [0, lo)
-  for (int pos = tid; pos < lo; pos += BWG) {
+  int lo = min(nf, CH + bw);                        // first fill: positions [0, lo)
+  for (int pos = tid; pos < lo; pos += CH) {
     T blk[TV][DD];
     fetch(pos, blk);
     put(pos, blk);
@@ -707,9 +710,9 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
 #pragma unroll
     for (int r = 0; r < D; ++r) Bv[v][r] = T(0);
   }
-  for (int p0 = 0; p0 < nf; p0 += BWG) {
-    // chunk p0 + BWG needs positions up to p0 + 2 BWG + bw: prefetch them
-    const int nhi = min(nf, p0 + 2 * BWG + bw);
+  for (int p0 = 0; p0 < nf; p0 += CH) {
+    // chunk p0 + CH needs positions up to p0 + 2 CH + bw: prefetch them
+    const int nhi = min(nf, p0 + 2 * CH + bw);
     const int ppos = lo + tid;
     const bool pf = ppos < nhi;
     T pre[TV][DD];
@@ -927,13 +930,14 @@ __global__ void __launch_bounds__(WG) k_cc_dm_finish(MeshView mv, int method, in
   if (i < v1) dm_finish_body<T, D>(mv, method, i, hb, KL, fb, g, dout, xmove, xmove);
 }
 
-template <typename T, int D, int TV>
-__global__ void __launch_bounds__(BWG) k_cc_prep_band(MeshView mv, int method, int v0, int v1,
+template <typename T, int D, int TV, int CH>
+__global__ void __launch_bounds__(CH) k_cc_prep_band(MeshView mv, int method, int v0, int v1,
                                                       const T* __restrict__ hb, T* __restrict__ KL,
                                                       const double* __restrict__ g, double* __restrict__ bout) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int i0 = v0 + blockIdx.x * TV;
-  prep_band_body<T, D, TV>(mv, method, i0, min(TV, v1 - i0), hb, KL, reinterpret_cast<T*>(smem_raw), g, bout);
+  prep_band_body<T, D, TV, CH>(mv, method, i0, min(TV, v1 - i0), hb, KL, reinterpret_cast<T*>(smem_raw), g,
+                               bout);
 }
 
 
@@ -1333,44 +1337,62 @@ static size_t g_lds_limit = 64 * 1024;
 
 void set_lds_limit(size_t bytes) { g_lds_limit = bytes; }
 
-int band_ring(int nf, int band_w) {
+int band_ring(int nf, int band_w, int ch) {
   if (nf <= 0) return 0;
-  const int need = std::min(nf, BWG + band_w);
+  const int need = std::min(nf, ch + band_w);
   int r = 64;
   while (r < need) r *= 2;
   return r;
 }
 
-size_t dense_lds_bytes(int tv, int ring, int D, int prec) {
+size_t dense_lds_bytes(int tv, int ring, int D, int prec, int ch) {
   const size_t S = prec == 0 ? 8 : 4;
   // ring slots (ring_slot_words), then the per-wave partial sums
-  return (size_t)ring * ring_slot_words(tv, D, (int)S) * 4 + (size_t)(BWG / 64) * tv * (D * D + D) * S;
+  return (size_t)ring * ring_slot_words(tv, D, (int)S) * 4 + (size_t)(ch / 64) * tv * (D * D + D) * S;
 }
 
-// float64 keeps two rows per workgroup (the register file of 2 waves/SIMD
-// holds the accumulators of two float64 rows, four float32 ones)
-int dense_tv(int ring, int D, int prec, int cap) {
-  if (ring <= 0) return 0;
+// float64 keeps at most two rows per workgroup (the register file of 2
+// waves/SIMD holds the accumulators of two float64 rows, four float32 ones)
+DenseCfg dense_config(const int* nf, const int* band_w, int count, int D, int prec, int cap) {
+  DenseCfg best;
   int top = prec == 0 ? 2 : 4;
   while (cap > 0 && top > cap) top /= 2;
-  for (int tv = top; tv >= 1; tv /= 2)
-    if (dense_lds_bytes(tv, ring, D, prec) <= g_lds_limit) return tv;
-  return 0;
+  for (int tv = top; tv >= 1 && best.tv == 0; tv /= 2) {
+    int best_waves = 0;
+    for (int ch : {256, BWG}) {
+      int ring = 0;
+      for (int m = 0; m < count; ++m) ring = std::max(ring, band_ring(nf[m], band_w[m], ch));
+      if (ring <= 0) continue;
+      const size_t lds = dense_lds_bytes(tv, ring, D, prec, ch);
+      if (lds > g_lds_limit) continue;
+      const int waves = std::min((int)(g_lds_limit / lds) * (ch / 64), 32);
+      if (waves > best_waves) {
+        best_waves = waves;
+        best.tv = tv;
+        best.ch = ch;
+        best.lds = lds;
+      }
+    }
+  }
+  return best;
 }
 
-#define CC_DISPATCH_TV(tv, ...)                              \
-  switch (tv) {                                              \
-    case 1: { constexpr int TV = 1; __VA_ARGS__; } break;    \
-    case 2: { constexpr int TV = 2; __VA_ARGS__; } break;    \
-    default: { constexpr int TV = 4; __VA_ARGS__; } break;   \
+#define CC_DISPATCH_TVCH(tv, ch, ...)                                                 \
+  switch ((tv) * 1000 + (ch)) {                                                       \
+    case 1256: { constexpr int TV = 1, CH = 256; __VA_ARGS__; } break;                \
+    case 2256: { constexpr int TV = 2, CH = 256; __VA_ARGS__; } break;                \
+    case 4256: { constexpr int TV = 4, CH = 256; __VA_ARGS__; } break;                \
+    case 1512: { constexpr int TV = 1, CH = 512; __VA_ARGS__; } break;                \
+    case 2512: { constexpr int TV = 2, CH = 512; __VA_ARGS__; } break;                \
+    default: { constexpr int TV = 4, CH = 512; __VA_ARGS__; } break;                  \
   }
 
 // True when the mesh's dense basis can be streamed through the LDS ring in
 // this precision (float64 needs the float64 copy of the basis).
 static bool band_ok(const MeshView& mv, int prec) {
-  if (!mv.dense_supp || mv.hq == nullptr || mv.ring <= 0 || mv.nf < 2) return false;
+  if (!mv.dense_supp || mv.hq == nullptr || mv.nf < 2) return false;
   if (prec == 0 && mv.U_d == nullptr) return false;
-  return dense_tv(mv.ring, mv.D, prec) > 0;
+  return dense_config(&mv.nf, &mv.band_w, 1, mv.D, prec).tv > 0;
 }
 
 template <typename T, int D>
@@ -1378,10 +1400,9 @@ static bool prep_dense(const MeshView& mv, int prec, int method, int v0, int v1,
                        void* KL, unsigned long long* fb, const double* g, double* dout, double* xmove,
                        int tv_cap, hipStream_t s) {
   if (method == 0 || !band_ok(mv, prec)) return false;
-  const int tv = dense_tv(mv.ring, D, prec, tv_cap);
-  const size_t lds = dense_lds_bytes(tv, mv.ring, D, prec);
-  CC_DISPATCH_TV(tv, k_cc_prep_band<T, D, TV><<<nblocks(v1 - v0, TV), BWG, lds, s>>>(
-                         mv, method, v0, v1, (const T*)hb, (T*)KL, g, dout));
+  const DenseCfg dc = dense_config(&mv.nf, &mv.band_w, 1, D, prec, tv_cap);
+  CC_DISPATCH_TVCH(dc.tv, dc.ch, k_cc_prep_band<T, D, TV, CH><<<nblocks(v1 - v0, TV), CH, dc.lds, s>>>(
+                                     mv, method, v0, v1, (const T*)hb, (T*)KL, g, dout));
   k_cc_dm_finish<T, D><<<nblocks(v1 - v0, WG), WG, 0, s>>>(mv, method, v0, v1, (const T*)hb, (T*)KL, fb,
                                                           g, dout, g != nullptr ? xmove : nullptr);
   return true;
@@ -1710,8 +1731,8 @@ __global__ void __launch_bounds__(WG) kb_prep(const BatchItem* __restrict__ item
 }
 
 // Dense-basis meshes of a batch: TV vertices per workgroup (prep_band_body).
-template <typename T, int D, int TV>
-__global__ void __launch_bounds__(BWG) kb_prep_band(const BatchItem* __restrict__ items,
+template <typename T, int D, int TV, int CH>
+__global__ void __launch_bounds__(CH) kb_prep_band(const BatchItem* __restrict__ items,
                                                     const BatchCtl* __restrict__ ctl,
                                                     const int* __restrict__ boff, int nmesh,
                                                     int method, int colour, int fuse) {
@@ -1722,7 +1743,7 @@ __global__ void __launch_bounds__(BWG) kb_prep_band(const BatchItem* __restrict_
   int v0, v1;
   vertex_range(it, colour, v0, v1);
   const int i0 = v0 + (blockIdx.x - boff[mi]) * TV;
-  prep_band_body<T, D, TV>(it.mv, method, i0, min(TV, v1 - i0), (const T*)it.hb, (T*)it.KL,
+  prep_band_body<T, D, TV, CH>(it.mv, method, i0, min(TV, v1 - i0), (const T*)it.hb, (T*)it.KL,
                            reinterpret_cast<T*>(smem_raw), fuse ? it.g : nullptr, fuse ? it.d : nullptr);
 }
 
@@ -2055,6 +2076,7 @@ struct BatchPlan {
   std::vector<Offsets> prep, prepd, fin, upd;   // index 0: all free vertices, c+1: colour c
   int max_colours = 0;
   int tv = 0;       // vertices per workgroup of the dense condensation (0: no dense mesh)
+  int ch = 0;       // its chunk of band positions (= workgroup size)
   size_t lds = 0;   // its dynamic LDS
   int scap = 0;     // staged support blocks per vertex of the sparse condensation (0: none)
   size_t slds = 0;  // its dynamic LDS
@@ -2148,7 +2170,8 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
   p->items_h.assign(items_host, items_host + nmesh);
   std::vector<int> cpred(nmesh), celem(nmesh), casm(nmesh), cgrad(nmesh), cen(nmesh), cax(nmesh),
       caxj(nmesh), cfeat(nmesh), crot(nmesh);
-  int dense_ring = 0, sparse_supp = 0;
+  std::vector<int> dense_nf, dense_bw;
+  int sparse_supp = 0;
   for (int m = 0; m < nmesh; ++m) {
     const MeshView& mv = p->items_h[m].mv;
     cpred[m] = nblocks(mv.n, WG);
@@ -2162,14 +2185,20 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
     cfeat[m] = nblocks(mv.nf, WG / FEAT_LANES);
     crot[m] = (cfg.corotate && mv.rot) ? nblocks(mv.nf, WG) : 0;
     p->max_colours = std::max(p->max_colours, p->items_h[m].ncol);
-    if (p->items_h[m].prep_dense) dense_ring = std::max(dense_ring, mv.ring);
+    if (p->items_h[m].prep_dense) {
+      dense_nf.push_back(mv.nf);
+      dense_bw.push_back(mv.band_w);
+    }
     else if (mv.smap) sparse_supp = std::max(sparse_supp, mv.smap_supp);
   }
   p->scap = sparse_stage_cap(sparse_supp, cfg.G, cfg.D, cfg.prec);
   p->slds = sparse_stage_bytes(p->scap, cfg.G, cfg.D, cfg.prec);
-  if (dense_ring > 0) {
-    p->tv = dense_tv(dense_ring, cfg.D, cfg.prec, cfg.tv_cap);
-    p->lds = dense_lds_bytes(p->tv, dense_ring, cfg.D, cfg.prec);
+  if (!dense_nf.empty()) {
+    const DenseCfg dc = dense_config(dense_nf.data(), dense_bw.data(), (int)dense_nf.size(), cfg.D, cfg.prec,
+                                     cfg.tv_cap);
+    p->tv = dc.tv;
+    p->ch = dc.ch;
+    p->lds = dc.lds;
   }
   offsets_build(p->pred, cpred, s);
   offsets_build(p->elem, celem, s);
@@ -2254,7 +2283,7 @@ static void b_prep(BatchPlan* p, int colour, hipStream_t s, int fuse = 0) {
                                                   colour, p->scap);
   if (gridn(od) > 0) {
     const Offsets& of = p->fin[colour + 1];
-    CC_DISPATCH_TV(p->tv, kb_prep_band<T, D, TV><<<gridn(od), BWG, p->lds, s>>>(
+    CC_DISPATCH_TVCH(p->tv, p->ch, kb_prep_band<T, D, TV, CH><<<gridn(od), CH, p->lds, s>>>(
                               p->items_d, p->ctl_d, od.d, p->nmesh, p->cfg.method, colour, fuse));
     kb_dm_finish<T, D><<<gridn(of), WG, 0, s>>>(p->items_d, p->ctl_d, of.d, p->nmesh, p->cfg.method,
                                                colour, fuse);

@@ -210,23 +210,16 @@ def trace_summary(folder, bench_log):
         print(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
               f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
               f"{float(r['Percentage']):.2f}% |")
-    # the profiled (uncaptured) learned+batched region holds the last
-    # `launches` float32 dispatches of kb_prep_band before the beam section
-    # (the float64 bars come later under another name); the beam's float32
-    # dispatches follow them, one per iteration, so the window ends that many
-    # dispatches before the last
+    # the profiled (uncaptured) learned+batched region lies between the
+    # first two k_profile_mark dispatches (cc_profile_enable marks where a
+    # recording starts and stops; the beam's profiled steps come later)
     n = ro["launches"]
-    nb = b.get("beam81x21x21_twist", {}).get("roofline", {}).get("launches", 0)
-    nbeam_all = 0
-    if "beam81x21x21_twist" in b:
-        bb = b["beam81x21x21_twist"]
-        nbeam_all = sum(sum(bb[k]["iters_per_step"]) for k in ("batched", "learned_batched")) + nb
+    marks = sorted(int(r["Start_Timestamp"]) for r in disp if "k_profile_mark" in r["Kernel_Name"])
+    t0, t1 = (marks[0], marks[1]) if len(marks) >= 2 else (0, 1 << 62)
 
     def window(key):
-        v = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
-             for r in disp if key in r["Kernel_Name"]]
-        end = len(v) - nbeam_all
-        return v[max(end - n, 0):end]
+        return [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+                for r in disp if key in r["Kernel_Name"] and t0 < int(r["Start_Timestamp"]) < t1]
     lp, lf = window("kb_prep_band<float"), window("kb_dm_finish<float")
     mp = sum(lp) / max(len(lp), 1)
     mf = sum(lf) / max(len(lf), 1)
@@ -255,6 +248,56 @@ def trace_summary(folder, bench_log):
           + "\n```")
 
 
+SQ_PASSES = ("SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_BUSY_CU_CYCLES SQ_INSTS_VALU SQ_INSTS_LDS "
+             "SQ_INSTS_VMEM_RD SQ_WAIT_INST_ANY",
+             "SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_WAIT_INST_LDS SQ_WAIT_ANY SQ_LDS_IDX_ACTIVE "
+             "SQ_LDS_BANK_CONFLICT SQ_LDS_ADDR_CONFLICT SQ_INSTS_SALU",
+             "TCC_HIT_sum TCC_MISS_sum TCC_EA0_RDREQ_sum TCP_TCC_READ_REQ_sum")
+
+
+def counters_summary(dirs, workload):
+    """Markdown summary of SQ / cache counter passes on the condensation
+    kernel: per-dispatch sums over the device, and the ratios the kernel's
+    design is judged by."""
+    tot, ndisp = {}, {}
+    for d in dirs:
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            continue
+        for row in csv.DictReader(open(files[0])):
+            if "kb_prep_band<" not in row["Kernel_Name"]:
+                continue
+            c = row["Counter_Name"]
+            tot[c] = tot.get(c, 0.0) + float(row["Counter_Value"])
+            ndisp.setdefault(c, set()).add(row["Dispatch_Id"])
+    per = {c: tot[c] / max(len(ndisp[c]), 1) for c in tot}
+    name = {"batch64": "the 64 seed-drawn bars of the benchmark, exact corotated bases",
+            "beam": "the 81x21x21 twisted beam, exact corotated basis"}[workload]
+    flag = "" if workload == "batch64" else " --workload beam"
+    print(f"# Shader and cache counters of kb_prep_band: {name}, float32 local arithmetic\n")
+    print("Commands (repo root `$R`, output folder `$OUT`, one MI355X; one pass per counter group):\n")
+    print("```")
+    print("cd /tmp && export TMPDIR=/tmp")
+    for i, grp in enumerate(SQ_PASSES):
+        print(f"timeout -s KILL 240 rocprofv3 --pmc {grp} --output-format csv -d $OUT/sq{i} -o run -- "
+              f"python -u $R/bench_counters.py{flag}")
+    print(f"python $R/bench_counters.py{flag} --counters $OUT/sq0 $OUT/sq1 $OUT/sq2")
+    print("```\n")
+    print("| counter | per dispatch | dispatches |")
+    print("|---|---|---|")
+    for c in sorted(per):
+        print(f"| {c} | {per[c]:.4g} | {len(ndisp[c])} |")
+    g = lambda c: per.get(c, float("nan"))
+    print("\nDerived (sums over all shader engines; SQ cycle counters tick once per four cycles "
+          "per wave or per CU as their names say):\n")
+    print(f"- LDS bank-conflict cycles / LDS active cycles: {g('SQ_LDS_BANK_CONFLICT') / g('SQ_LDS_IDX_ACTIVE'):.3f}")
+    print(f"- VALU instructions per busy CU cycle: {g('SQ_INSTS_VALU') / g('SQ_BUSY_CU_CYCLES'):.3f} "
+          "(one CU issues at most one wave64 VALU instruction per cycle over its four SIMDs)")
+    print(f"- LDS instructions per VALU instruction: {g('SQ_INSTS_LDS') / g('SQ_INSTS_VALU'):.3f}")
+    print(f"- wave cycles waiting on any dependency / wave cycles: {g('SQ_WAIT_INST_ANY') / g('SQ_WAVE_CYCLES'):.3f}")
+    print(f"- L2 hit rate: {g('TCC_HIT_sum') / (g('TCC_HIT_sum') + g('TCC_MISS_sum')):.3f}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=3)
@@ -262,11 +305,14 @@ def main():
     ap.add_argument("--dense-rows", type=int, default=0)
     ap.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "BENCH_LOG"))
+    ap.add_argument("--counters", nargs="+", metavar="PASS_DIR")
     a = ap.parse_args()
     if a.summarize:
         summarize(*a.summarize, a.workload)
     elif a.trace_summary:
         trace_summary(*a.trace_summary)
+    elif a.counters:
+        counters_summary(a.counters, a.workload)
     else:
         run(a.workload, a.steps, a.dense_rows)
 

@@ -167,6 +167,9 @@ def main():
     cg.cc_destroy(ctx)
 
 
+WARM_MAX_ITERS = 200     # per step; a step that needs more is reported as not converged
+
+
 def warm_start_beam(cg, ctx, dev, seeds, steps, tol=1e-6):
     """Held-out evaluation of the learned warm start at 81 x 21 x 21."""
     import torch
@@ -193,7 +196,7 @@ def warm_start_beam(cg, ctx, dev, seeds, steps, tol=1e-6):
             xg = torch.tensor(x, dtype=torch.float64, device=dev)
             vg = torch.tensor(v, dtype=torch.float64, device=dev)
             par = cg.cc_params_default(method=cg.METHOD_CC, sweep=cg.SWEEP_JACOBI, precision=cg.FP32_MIXED,
-                                       line_search=1, max_iters=10000, gravity=s.gravity,
+                                       line_search=1, max_iters=WARM_MAX_ITERS, gravity=s.gravity,
                                        warm_start=warm, corotate=1)
             its, acc, ms, bad = [], 0, [], 0
             for t in range(1, steps + 1):
@@ -206,6 +209,7 @@ def warm_start_beam(cg, ctx, dev, seeds, steps, tol=1e-6):
                 its.append(int(it))
                 bad += int(st != cg.CC_OK)
                 acc += int(cg.cc_step_info(ctx, mid)["warm_accepted"])
+                print(f"  seed {sd} {name} step {t}: {it} iterations, {ms[-1]:.1f} ms, status {st}", flush=True)
             row[name] = {"iters_mean": round(float(np.mean(its)), 3), "iters_median": float(np.median(its)),
                          "ms_per_step_median": round(float(np.median(ms)), 2),
                          "ms_per_step_mean": round(float(np.mean(ms)), 2), "not_ok": bad,

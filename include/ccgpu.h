@@ -339,7 +339,9 @@ cc_status cc_mlp_train_step(cc_ctx* ctx, const float* X, const float* T, const i
 /* Record the duration of every launch of the kernels whose bit is set in
    `mask` (bit k = kernel id k) with HIP events on the context's stream;
    mask = 0 stops recording.  Enabling clears the accumulators.  Timing adds
-   two event records per timed launch. */
+   two event records per timed launch.  Enabling, and stopping a recording,
+   also launch an empty kernel `k_profile_mark` on the context's stream, the
+   region's boundary in a kernel trace. */
 cc_status cc_profile_enable(cc_ctx* ctx, int32_t mask);
 /* Accumulated device milliseconds and launch count of kernel `kernel_id`
    since the last cc_profile_enable (host outputs). */

@@ -1194,6 +1194,10 @@ struct Stepper {
 
 }  // namespace
 
+// Empty kernel: the boundary of a timed region in a kernel trace
+// (cc_profile_enable).
+__global__ void k_profile_mark() {}
+
 extern "C" {
 
 void cc_params_default(cc_params* p) {
@@ -1263,6 +1267,12 @@ cc_status cc_profile_enable(cc_ctx* ctx, int32_t mask) {
   return guarded(ctx, [&]() -> cc_status {
     HIPC(hipStreamSynchronize(ctx->stream));
     ctx->harvest();
+    // an empty kernel marks where a timed region starts and ends in a
+    // kernel trace
+    if (mask != 0 || ctx->prof_mask != 0) {
+      k_profile_mark<<<1, 64, 0, ctx->stream>>>();
+      HIPC(hipGetLastError());
+    }
     ctx->prof_mask = mask;
     for (int k = 0; k < CC_K_COUNT; ++k) { ctx->prof_ms[k] = 0; ctx->prof_n[k] = 0; }
     return CC_OK;

@@ -79,7 +79,7 @@ def run(workload, steps, dense_rows=0):
         vs.append(torch.tensor(v, device=dev))
     print("bases built", flush=True)
     cg.cc_batch_tuning(ctx, 16, 0)
-    cg.cc_dense_tuning(ctx, dense_rows)
+    cg.cc_dense_tuning(ctx, dense_rows, 0)
     par = cg.cc_params_default(method=cg.METHOD_CC, sweep=cg.SWEEP_JACOBI, line_search=1, max_iters=1,
                                precision=cg.FP32_MIXED, corotate=1)
     grav = np.stack([s.gravity for s in scenes])

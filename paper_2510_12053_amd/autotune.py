@@ -61,7 +61,7 @@ def _save(path, table):
 
 def apply(ctx, choice):
     cg.cc_batch_tuning(ctx, int(choice["lanes"]), int(choice["iters_per_graph"]))
-    cg.cc_dense_tuning(ctx, int(choice["dense_rows"]))
+    cg.cc_dense_tuning(ctx, int(choice["dense_rows"]), int(choice.get("dense_chunk", 0)))
 
 
 def tune(ctx, mesh_ids, xs, vs, bcs, dt, params, tol, gravity, n_free, any_dense, any_sparse, steps=2,

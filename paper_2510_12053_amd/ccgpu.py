@@ -77,7 +77,7 @@ def lib():
             "cc_probe_sweep": (I32, [P, I32, P, P, D, ctypes.POINTER(cc_params), pD, P, P]),
             "cc_step_batch": (I32, [P, I32, P, P, P, P, P, D, ctypes.POINTER(cc_params), D, P, P, P]),
             "cc_batch_tuning": (I32, [P, I32, I32]),
-            "cc_dense_tuning": (I32, [P, I32]),
+            "cc_dense_tuning": (I32, [P, I32, I32]),
             "cc_autotune_batch": (I32, [P, I32, P, ctypes.POINTER(cc_params), pI32, P]),
             "cc_profile_enable": (I32, [P, I32]),
             "cc_profile_read": (I32, [P, I32, pD, pI64]),
@@ -303,8 +303,8 @@ def cc_batch_tuning(ctx, lanes, iters_per_graph):
     _check(ctx, lib().cc_batch_tuning(ctx.handle, lanes, iters_per_graph))
 
 
-def cc_dense_tuning(ctx, rows_per_workgroup):
-    _check(ctx, lib().cc_dense_tuning(ctx.handle, rows_per_workgroup))
+def cc_dense_tuning(ctx, rows_per_workgroup, chunk=0):
+    _check(ctx, lib().cc_dense_tuning(ctx.handle, rows_per_workgroup, chunk))
 
 
 def cc_autotune_batch(ctx, mesh_ids, params):

@@ -215,6 +215,7 @@ struct cc_ctx {
   int batch_lanes = 16;
   int batch_iters_per_graph = 4;
   int dense_rows = 0;        // rows per workgroup of the dense condensation (0: most that fit)
+  int dense_chunk = 0;       // its chunk of band positions (0: automatic)
   // kernel timing inside the batched path: event pairs of uncaptured launches
   // go to `pending`; pairs captured into the graph stay registered and are
   // read after every replay
@@ -1135,7 +1136,7 @@ struct Stepper {
   void prep(int method, int v0, int v1) {
     ctx->timed(CC_K_CC_PREP, [&] {
       cc::launch_cc_prep(mv, p.precision, method, v0, v1, M.hb, M.KL, M.fb, s, nullptr, nullptr, nullptr,
-                         ctx->dense_rows);
+                         ctx->dense_rows, ctx->dense_chunk);
     });
   }
   // Condensation that also writes the Jacobi directions into out when the
@@ -1144,7 +1145,7 @@ struct Stepper {
     bool done = false;
     ctx->timed(CC_K_CC_PREP, [&] {
       done = cc::launch_cc_prep(mv, p.precision, method, 0, M.nf, M.hb, M.KL, M.fb, s, M.g, out, nullptr,
-                                ctx->dense_rows);
+                                ctx->dense_rows, ctx->dense_chunk);
     });
     return done;
   }
@@ -1177,7 +1178,7 @@ struct Stepper {
         bool done = false;
         ctx->timed(CC_K_CC_PREP, [&] {
           done = cc::launch_cc_prep(mv, p.precision, method, v0, v1, M.hb, M.KL, M.fb, s, M.g, M.dvec, out,
-                                    ctx->dense_rows);
+                                    ctx->dense_rows, ctx->dense_chunk);
         });
         if (!done) update(method, v0, v1, out, 1);
         continue;
@@ -1735,8 +1736,9 @@ static cc_status batch_validate(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids,
   return CC_OK;
 }
 
-static bool use_dense_band(const Mesh& M, int prec) {
-  return M.dense && M.nf > 1 && cc::dense_config(&M.nf, &M.band_w, 1, M.D, prec).tv > 0 &&
+static bool use_dense_band(const cc_ctx* ctx, const Mesh& M, int prec) {
+  return M.dense && M.nf > 1 &&
+         cc::dense_config(&M.nf, &M.band_w, 1, M.D, prec, ctx->dense_rows, ctx->dense_chunk).tv > 0 &&
          (prec != CC_FP64 || M.U_d != nullptr);
 }
 
@@ -1764,7 +1766,7 @@ static cc::BatchPlan* batch_plan_for(cc_ctx* ctx, const std::vector<Mesh*>& ms, 
                              (double)p.precision, (double)p.line_search, (double)p.max_iters,
                              (double)p.quasistatic, dt, tol, (double)ctx->batch_lanes,
                              (double)ctx->batch_iters_per_graph, (double)p.corotate,
-                             (double)ctx->dense_rows};
+                             (double)ctx->dense_rows, (double)ctx->dense_chunk};
   int any_fcr = 0;
   for (int i = 0; i < n; ++i) {
     key.push_back((double)(ms[i]->has_basis ? ms[i]->dense : -1));
@@ -1780,7 +1782,7 @@ static cc::BatchPlan* batch_plan_for(cc_ctx* ctx, const std::vector<Mesh*>& ms, 
   for (int i = 0; i < n; ++i) {
     Material mat{};
     items[i] = make_item(*ms[i], mat);
-    items[i].prep_dense = (p.method != CC_METHOD_CD && use_dense_band(*ms[i], p.precision)) ? 1 : 0;
+    items[i].prep_dense = (p.method != CC_METHOD_CD && use_dense_band(ctx, *ms[i], p.precision)) ? 1 : 0;
     items[i].mv.rot = p.corotate ? ms[i]->rot : nullptr;
   }
   cc::BatchConfig cfg{};
@@ -1794,6 +1796,7 @@ static cc::BatchPlan* batch_plan_for(cc_ctx* ctx, const std::vector<Mesh*>& ms, 
   cfg.corotate = p.corotate;
   cfg.any_fcr = any_fcr;
   cfg.tv_cap = ctx->dense_rows;
+  cfg.chunk = ctx->dense_chunk;
   ctx->plan = cc::batch_plan_create(items.data(), n, cfg, ctx->stream);
   ctx->plan_ids = idv;
   ctx->plan_prev_iters = 0;
@@ -1873,7 +1876,7 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
       mat.s_el = p.quasistatic ? 1.0 : dt * dt;
       for (int c = 0; c < 3; ++c) mat.grav[c] = gravity ? gravity[3 * i + c] : p.gravity[c];
       items[i] = make_item(M, mat);
-      items[i].prep_dense = (p.method != CC_METHOD_CD && use_dense_band(M, p.precision)) ? 1 : 0;
+      items[i].prep_dense = (p.method != CC_METHOD_CD && use_dense_band(ctx, M, p.precision)) ? 1 : 0;
       items[i].mv.rot = p.corotate ? M.rot : nullptr;
       items[i].feat_off = 0;
       for (int q = 0; q < i; ++q) items[i].feat_off += ms[q]->nf;
@@ -2060,12 +2063,15 @@ cc_status cc_batch_tuning(cc_ctx* ctx, int32_t lanes, int32_t iters_per_graph) {
   });
 }
 
-cc_status cc_dense_tuning(cc_ctx* ctx, int32_t rows_per_workgroup) {
+cc_status cc_dense_tuning(cc_ctx* ctx, int32_t rows_per_workgroup, int32_t chunk) {
   return guarded(ctx, [&]() -> cc_status {
     if (rows_per_workgroup != 0 && rows_per_workgroup != 1 && rows_per_workgroup != 2 &&
         rows_per_workgroup != 4)
       return fail(ctx, CC_E_INVALID_ARG, "rows per workgroup must be 0 (automatic), 1, 2 or 4");
+    if (chunk != 0 && chunk != 256 && chunk != 512)
+      return fail(ctx, CC_E_INVALID_ARG, "chunk must be 0 (automatic), 256 or 512");
     ctx->dense_rows = rows_per_workgroup;
+    ctx->dense_chunk = chunk;
     return CC_OK;
   });
 }
@@ -2083,7 +2089,7 @@ cc_status cc_autotune_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, con
       Material mat{};
       mat.mu = ms[i]->mu; mat.lam = ms[i]->lam; mat.model = ms[i]->model;
       items[i] = make_item(*ms[i], mat);
-      items[i].prep_dense = (params->method != CC_METHOD_CD && use_dense_band(*ms[i], params->precision)) ? 1 : 0;
+      items[i].prep_dense = (params->method != CC_METHOD_CD && use_dense_band(ctx, *ms[i], params->precision)) ? 1 : 0;
       items[i].mv.rot = params->corotate ? ms[i]->rot : nullptr;
     }
     HIPC(hipMemcpyAsync(cc::batch_items_dev(plan), items.data(), n * sizeof(cc::BatchItem),

@@ -121,7 +121,7 @@ void launch_gradient(const MeshView& mv, const double* x, const double* xt, cons
 bool launch_cc_prep(const MeshView& mv, int prec, int method, int v0, int v1, const void* hb,
                     void* KL, unsigned long long* fallbacks, hipStream_t s,
                     const double* g = nullptr, double* dout = nullptr, double* xmove = nullptr,
-                    int tv_cap = 0);
+                    int tv_cap = 0, int chunk = 0);
 void launch_cc_update(const MeshView& mv, int prec, int method, int v0, int v1, const void* KL,
                       const double* g, double* x_or_d, int accumulate, hipStream_t s);
 void launch_energy(const MeshView& mv, const double* x, const double* xt, const Material& mat,
@@ -183,13 +183,14 @@ size_t dense_lds_bytes(int tv, int ring, int D, int prec, int ch);
 // condensation for meshes with the given free-vertex counts and band widths:
 // the most rows whose ring fits (at most cap when cap > 0), then the chunk
 // (256 or 512) with more resident waves per CU, ties to the smaller chunk,
-// whose workgroups overlap one another's ring fill and final sums.  tv = 0:
-// no configuration fits.
+// whose workgroups overlap one another's ring fill and final sums (chunk > 0
+// forces that chunk).  tv = 0: no configuration fits.
 struct DenseCfg {
   int tv = 0, ch = 0;
   size_t lds = 0;
 };
-DenseCfg dense_config(const int* nf, const int* band_w, int count, int D, int prec, int cap = 0);
+DenseCfg dense_config(const int* nf, const int* band_w, int count, int D, int prec, int cap = 0,
+                      int chunk = 0);
 
 // Exact basis U_i[j] = (H^{-1})_ji ((H^{-1})_ii)^{-1} from float64 block rows
 // hb (cc_basis.hip), through the block-tridiagonal structure of H in band
@@ -257,6 +258,7 @@ struct BatchConfig {
   int dense_lds;       // max dynamic LDS of the dense condensation path (bytes)
   int corotate;        // rotations re-estimated wherever the Hessian is
   int tv_cap;          // rows per workgroup of the dense condensation (0: most that fit)
+  int chunk;           // its chunk of band positions (0: automatic, else 256 or 512)
   int any_fcr;         // some mesh of the batch uses the Fixed Corotational model
 };
 

@@ -1353,13 +1353,14 @@ size_t dense_lds_bytes(int tv, int ring, int D, int prec, int ch) {
 
 // float64 keeps at most two rows per workgroup (the register file of 2
 // waves/SIMD holds the accumulators of two float64 rows, four float32 ones)
-DenseCfg dense_config(const int* nf, const int* band_w, int count, int D, int prec, int cap) {
+DenseCfg dense_config(const int* nf, const int* band_w, int count, int D, int prec, int cap, int chunk) {
   DenseCfg best;
   int top = prec == 0 ? 2 : 4;
   while (cap > 0 && top > cap) top /= 2;
   for (int tv = top; tv >= 1 && best.tv == 0; tv /= 2) {
     int best_waves = 0;
     for (int ch : {256, BWG}) {
+      if (chunk > 0 && ch != chunk) continue;
       int ring = 0;
       for (int m = 0; m < count; ++m) ring = std::max(ring, band_ring(nf[m], band_w[m], ch));
       if (ring <= 0) continue;
@@ -1398,9 +1399,10 @@ static bool band_ok(const MeshView& mv, int prec) {
 template <typename T, int D>
 static bool prep_dense(const MeshView& mv, int prec, int method, int v0, int v1, const void* hb,
                        void* KL, unsigned long long* fb, const double* g, double* dout, double* xmove,
-                       int tv_cap, hipStream_t s) {
+                       int tv_cap, int chunk, hipStream_t s) {
   if (method == 0 || !band_ok(mv, prec)) return false;
-  const DenseCfg dc = dense_config(&mv.nf, &mv.band_w, 1, D, prec, tv_cap);
+  const DenseCfg dc = dense_config(&mv.nf, &mv.band_w, 1, D, prec, tv_cap, chunk);
+  if (dc.tv == 0) return false;
   CC_DISPATCH_TVCH(dc.tv, dc.ch, k_cc_prep_band<T, D, TV, CH><<<nblocks(v1 - v0, TV), CH, dc.lds, s>>>(
                                      mv, method, v0, v1, (const T*)hb, (T*)KL, g, dout));
   k_cc_dm_finish<T, D><<<nblocks(v1 - v0, WG), WG, 0, s>>>(mv, method, v0, v1, (const T*)hb, (T*)KL, fb,
@@ -1410,15 +1412,15 @@ static bool prep_dense(const MeshView& mv, int prec, int method, int v0, int v1,
 
 bool launch_cc_prep(const MeshView& mv, int prec, int method, int v0, int v1, const void* hb,
                     void* KL, unsigned long long* fb, hipStream_t s, const double* g, double* dout,
-                    double* xmove, int tv_cap) {
+                    double* xmove, int tv_cap, int chunk) {
   if (v1 <= v0) return g != nullptr;
   bool done = false;
   if (prec == 0)
     CC_DISPATCH_D(mv.D, done = prep_dense<double, D>(mv, prec, method, v0, v1, hb, KL, fb, g, dout, xmove,
-                                                     tv_cap, s));
+                                                     tv_cap, chunk, s));
   else
     CC_DISPATCH_D(mv.D, done = prep_dense<float, D>(mv, prec, method, v0, v1, hb, KL, fb, g, dout, xmove,
-                                                    tv_cap, s));
+                                                    tv_cap, chunk, s));
   if (done) return g != nullptr;
   const int G = support_lanes(mv);
   if (prec == 0) CC_DISPATCH_D(mv.D, prep_g<double, D>(mv, method, v0, v1, hb, KL, fb, G, s));
@@ -2170,7 +2172,25 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
   p->items_h.assign(items_host, items_host + nmesh);
   std::vector<int> cpred(nmesh), celem(nmesh), casm(nmesh), cgrad(nmesh), cen(nmesh), cax(nmesh),
       caxj(nmesh), cfeat(nmesh), crot(nmesh);
-  std::vector<int> dense_nf, dense_bw;
+  {
+    // one dense configuration (rows per workgroup, chunk, LDS) for every
+    // dense-basis mesh; none fitting sends them to the sparse-row kernel
+    std::vector<int> dense_nf, dense_bw;
+    for (int m = 0; m < nmesh; ++m)
+      if (p->items_h[m].prep_dense) {
+        dense_nf.push_back(p->items_h[m].mv.nf);
+        dense_bw.push_back(p->items_h[m].mv.band_w);
+      }
+    if (!dense_nf.empty()) {
+      const DenseCfg dc = dense_config(dense_nf.data(), dense_bw.data(), (int)dense_nf.size(), cfg.D, cfg.prec,
+                                       cfg.tv_cap, cfg.chunk);
+      p->tv = dc.tv;
+      p->ch = dc.ch;
+      p->lds = dc.lds;
+      if (dc.tv == 0)
+        for (int m = 0; m < nmesh; ++m) p->items_h[m].prep_dense = 0;
+    }
+  }
   int sparse_supp = 0;
   for (int m = 0; m < nmesh; ++m) {
     const MeshView& mv = p->items_h[m].mv;
@@ -2185,21 +2205,11 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
     cfeat[m] = nblocks(mv.nf, WG / FEAT_LANES);
     crot[m] = (cfg.corotate && mv.rot) ? nblocks(mv.nf, WG) : 0;
     p->max_colours = std::max(p->max_colours, p->items_h[m].ncol);
-    if (p->items_h[m].prep_dense) {
-      dense_nf.push_back(mv.nf);
-      dense_bw.push_back(mv.band_w);
-    }
-    else if (mv.smap) sparse_supp = std::max(sparse_supp, mv.smap_supp);
+    if (!p->items_h[m].prep_dense && mv.smap) sparse_supp = std::max(sparse_supp, mv.smap_supp);
   }
   p->scap = sparse_stage_cap(sparse_supp, cfg.G, cfg.D, cfg.prec);
   p->slds = sparse_stage_bytes(p->scap, cfg.G, cfg.D, cfg.prec);
-  if (!dense_nf.empty()) {
-    const DenseCfg dc = dense_config(dense_nf.data(), dense_bw.data(), (int)dense_nf.size(), cfg.D, cfg.prec,
-                                     cfg.tv_cap);
-    p->tv = dc.tv;
-    p->ch = dc.ch;
-    p->lds = dc.lds;
-  }
+
   offsets_build(p->pred, cpred, s);
   offsets_build(p->elem, celem, s);
   offsets_build(p->asmb, casm, s);

@@ -1,14 +1,15 @@
-"""The exact-basis condensation at the mesh sizes where fewer basis rows fit
-in a workgroup's LDS (Method, Eqs. update and schur; Algorithm 1): one
-Jacobi sweep's CC directions against the oracle on sampled vertices, for
-every vertices-per-workgroup count the kernel instantiates, and a batch of
-the largest bars against single-mesh steps.
+"""Every configuration of the exact-basis condensation (Method, Eqs. block,
+update and schur; Eq. rotation; Algorithm 1): one Jacobi sweep's CC
+directions against the oracle on sampled vertices, with the rows per
+workgroup and the chunk of band positions forced through cc_dense_tuning,
+and a batch of the largest bars against single-mesh steps.
 
-Rows per workgroup (160 KB of LDS, 512 threads):
-  31x6x6 bar, 1,080 free vertices: float64 2, float32-mixed 4;
-  35x6x6 bar, 1,224 free vertices: float64 1, float32-mixed 3;
-  41x7x7 bar, 1,960 free vertices: float64 1 (near its limit), float32-mixed 2.
-Tolerances: float64 1e-9, float32-mixed 1e-4 of the largest direction."""
+The 41x7x7 bar has 1,960 free vertices: 8 chunks of 256 positions (the last
+holding 168) or 4 of 512 (the last 424), so the ring wraps several times and
+the tail is ragged.  Rows per workgroup: float64 1 and 2, float32-mixed 1, 2
+and 4; chunks 256 and 512; with and without corotation (rotated band
+records and R^T g).  Tolerances: float64 1e-9, float32-mixed 1e-4 of the
+largest direction."""
 import numpy as np
 import pytest
 
@@ -42,27 +43,49 @@ def _t(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
 
 
-@pytest.mark.parametrize("shape", [(31, 6, 6), (35, 6, 6), (41, 7, 7)])
-@pytest.mark.parametrize("prec", [0, 1])
-def test_directions_at_large_sizes(cg, ctx, shape, prec):
-    s = tet_bar(*shape, E=1e6)
+@pytest.fixture(scope="module")
+def bar(cg, ctx):
+    s = tet_bar(41, 7, 7, E=1e6, twist_per_step=0.15)
     p = Problem.from_scene(s)
     mid = cg.cc_mesh_upload(ctx, s.X, s.elems, s.fixed, s.E, s.nu, s.rho)
     cg.cc_subspace_build(ctx, mid, 0, s.dt, False)
     x0, v0 = s.initial_state()
-    xh = predictor(p, x0, v0 + 0.3, s.targets(1))
+    xh = predictor(p, x0, v0 + 0.3, s.targets(3))       # far face turned by 0.45 rad
     x = xh + 0.01 * np.random.default_rng(3).normal(size=xh.shape)
     x[p.fixed] = xh[p.fixed]
-    par = cg.cc_params_default(method=cg.METHOD_CC, precision=prec, gravity=s.gravity)
-    E, g, dx = cg.cc_probe_sweep(ctx, mid, _t(x), _t(p.x_tilde), s.dt, par)
-    dx = dx.cpu().numpy()
-    # sampled free vertices, the first and the last included
     rng = np.random.default_rng(17)
     ranks = np.unique(np.concatenate([[0, p.free.size - 1], rng.choice(p.free.size, 22, replace=False)]))
-    B = exact_basis(p, verts=p.free[ranks])
-    dxo, _ = S.local_directions(p, basis_matrix(p, *B), p.hessian(x), p.gradient(x), ranks, S.CC)
+    Um = basis_matrix(p, *exact_basis(p, verts=p.free[ranks]))
+    return dict(s=s, p=p, mid=mid, x=x, ranks=ranks, Um=Um)
+
+
+CONFIGS = [(0, 1, 256), (0, 1, 512), (0, 2, 256), (0, 2, 512),
+           (1, 1, 256), (1, 1, 512), (1, 2, 256), (1, 2, 512), (1, 4, 256), (1, 4, 512)]
+
+
+@pytest.mark.parametrize("corot", [0, 1])
+@pytest.mark.parametrize("prec,rows,chunk", CONFIGS)
+def test_directions_every_configuration(cg, ctx, bar, prec, rows, chunk, corot):
+    s, p, x, ranks = bar["s"], bar["p"], bar["x"], bar["ranks"]
+    par = cg.cc_params_default(method=cg.METHOD_CC, precision=prec, gravity=s.gravity, corotate=corot)
+    cg.cc_dense_tuning(ctx, rows, chunk)
+    try:
+        _, _, dx = cg.cc_probe_sweep(ctx, bar["mid"], _t(x), _t(p.x_tilde), s.dt, par)
+    finally:
+        cg.cc_dense_tuning(ctx, 0, 0)
+    dx = dx.cpu().numpy()
+    Ur = S._basis_at(p, bar["Um"], x, S.Params(method=S.CC, corotate=bool(corot)))
+    dxo, _ = S.local_directions(p, Ur, p.hessian(x), p.gradient(x), ranks, S.CC)
     tol = 1e-9 if prec == 0 else 1e-4
     assert np.max(np.abs(dx[p.free[ranks]] - dxo)) <= tol * np.max(np.abs(dxo))
+
+
+def test_dense_tuning_rejects_bad_values(cg, ctx):
+    with pytest.raises(cg.CCError):
+        cg.cc_dense_tuning(ctx, 3, 0)
+    with pytest.raises(cg.CCError):
+        cg.cc_dense_tuning(ctx, 0, 384)
+    cg.cc_dense_tuning(ctx, 0, 0)
 
 
 def test_batch_of_largest_bars(cg, ctx):

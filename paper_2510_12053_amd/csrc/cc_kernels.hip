@@ -1642,7 +1642,10 @@ __global__ void __launch_bounds__(elem_threads<T>()) kb_elem_hess(const BatchIte
                                                    const BatchCtl* __restrict__ ctl,
                                                    const int* __restrict__ boff, int nmesh, int which,
                                                    int colour) {
-  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  // blocks of one XCD take a contiguous range of the launch (one mesh, or
+  // neighbouring ones), so each mesh's data stays in one L2
+  const int bx = xcd_block(blockIdx.x, gridDim.x);
+  const int mi = block_mesh(boff, nmesh, bx);
   if (!ctl[mi].active) return;
   const BatchItem& it = items[mi];
   const MeshView mv = it.mv;
@@ -1650,7 +1653,7 @@ __global__ void __launch_bounds__(elem_threads<T>()) kb_elem_hess(const BatchIte
   const bool lst = colour >= 0 && colour < it.ncol;
   const int* el = lst ? mv.cel + mv.cel_ptr[colour] : nullptr;
   const int cnt = lst ? mv.cel_ptr[colour + 1] - mv.cel_ptr[colour] : mv.m;
-  elem_hess_split<T, D>(mv, (blockIdx.x - boff[mi]) * EWG, pick(it, which), T(it.mat.mu), T(it.mat.lam),
+  elem_hess_split<T, D>(mv, (bx - boff[mi]) * EWG, pick(it, which), T(it.mat.mu), T(it.mat.lam),
                         FCR ? it.mat.model : MAT_SNH, T(it.mat.s_el), (T*)it.estore, el, cnt);
 }
 
@@ -1659,11 +1662,14 @@ template <int D>
 __global__ void __launch_bounds__(WG) kb_rotations(const BatchItem* __restrict__ items,
                                                    const BatchCtl* __restrict__ ctl,
                                                    const int* __restrict__ boff, int nmesh, int which) {
-  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  // blocks of one XCD take a contiguous range of the launch (one mesh, or
+  // neighbouring ones), so each mesh's data stays in one L2
+  const int bx = xcd_block(blockIdx.x, gridDim.x);
+  const int mi = block_mesh(boff, nmesh, bx);
   if (!ctl[mi].active) return;
   const BatchItem& it = items[mi];
   if (it.mv.rot == nullptr) return;
-  rotation_body<D>(it.mv, (blockIdx.x - boff[mi]) * WG + threadIdx.x, pick(it, which), it.nptr, it.nidx,
+  rotation_body<D>(it.mv, (bx - boff[mi]) * WG + threadIdx.x, pick(it, which), it.nptr, it.nidx,
                    it.Xr, const_cast<double*>(it.mv.rot));
 }
 
@@ -1671,14 +1677,17 @@ template <typename T, int D>
 __global__ void __launch_bounds__(EWG) kb_assemble(const BatchItem* __restrict__ items,
                                                   const BatchCtl* __restrict__ ctl,
                                                   const int* __restrict__ boff, int nmesh, int colour) {
-  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  // blocks of one XCD take a contiguous range of the launch (one mesh, or
+  // neighbouring ones), so each mesh's data stays in one L2
+  const int bx = xcd_block(blockIdx.x, gridDim.x);
+  const int mi = block_mesh(boff, nmesh, bx);
   if (!ctl[mi].active) return;
   const BatchItem& it = items[mi];
   const MeshView mv = it.mv;
   const bool lst = colour >= 0 && colour < it.ncol;
   const int* sl = lst ? mv.csl + mv.csl_ptr[colour] : nullptr;
   const int cnt = lst ? mv.csl_ptr[colour + 1] - mv.csl_ptr[colour] : mv.nnzb;
-  assemble_body<T, D>(mv, (blockIdx.x - boff[mi]) * EWG + threadIdx.x, (const T*)it.estore,
+  assemble_body<T, D>(mv, (bx - boff[mi]) * EWG + threadIdx.x, (const T*)it.estore,
                       T(it.mat.w_in), (T*)it.hb, sl, cnt);
 }
 
@@ -1688,12 +1697,15 @@ template <typename T, int D>
 __global__ void __launch_bounds__(EWG) kb_band_copy(const BatchItem* __restrict__ items,
                                                    const BatchCtl* __restrict__ ctl,
                                                    const int* __restrict__ boff, int nmesh) {
-  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  // blocks of one XCD take a contiguous range of the launch (one mesh, or
+  // neighbouring ones), so each mesh's data stays in one L2
+  const int bx = xcd_block(blockIdx.x, gridDim.x);
+  const int mi = block_mesh(boff, nmesh, bx);
   if (!ctl[mi].active) return;
   const BatchItem& it = items[mi];
   const MeshView& mv = it.mv;
   if (mv.hq == nullptr) return;
-  const int t = (blockIdx.x - boff[mi]) * EWG + threadIdx.x;
+  const int t = (bx - boff[mi]) * EWG + threadIdx.x;
   if (t < mv.nnzb) band_rec_write<T, D>(mv, t, mv.blkrow[t], (const T*)it.hb + (size_t)t * D * D);
 }
 
@@ -1702,12 +1714,15 @@ __global__ void __launch_bounds__(WG) kb_gradient(const BatchItem* __restrict__ 
                                                   const BatchCtl* __restrict__ ctl,
                                                   const int* __restrict__ boff, int nmesh, int which,
                                                   int only_warm) {
+  // blocks of one XCD take a contiguous range of the launch (one mesh, or
+  // neighbouring ones), so each mesh's data stays in one L2
+  const int bx = xcd_block(blockIdx.x, gridDim.x);
   __shared__ double red[WG];
-  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  const int mi = block_mesh(boff, nmesh, bx);
   if (!ctl[mi].active || (only_warm && !ctl[mi].warm)) return;
   const BatchItem& it = items[mi];
   const MeshView mv = it.mv;
-  const int lb = blockIdx.x - boff[mi];
+  const int lb = bx - boff[mi];
   const double gsq = gradient_body<D, G, FCR>(mv, grad_vertex(mv, lb * (WG / G) + threadIdx.x / G), threadIdx.x % G,
                                          pick(it, which), it.xt, it.mat, it.g);
   const double tot = block_sum<WG>(gsq, red);
@@ -1719,13 +1734,16 @@ __global__ void __launch_bounds__(WG) kb_prep(const BatchItem* __restrict__ item
                                               const BatchCtl* __restrict__ ctl,
                                               const int* __restrict__ boff, int nmesh, int method,
                                               int colour, int cap) {
+  // blocks of one XCD take a contiguous range of the launch (one mesh, or
+  // neighbouring ones), so each mesh's data stays in one L2
+  const int bx = xcd_block(blockIdx.x, gridDim.x);
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  const int mi = block_mesh(boff, nmesh, bx);
   if (!ctl[mi].active) return;
   const BatchItem& it = items[mi];
   int v0, v1;
   vertex_range(it, colour, v0, v1);
-  const int idx = xcd_block(blockIdx.x - boff[mi], boff[mi + 1] - boff[mi]) * (WG / G) + threadIdx.x / G;
+  const int idx = (bx - boff[mi]) * (WG / G) + threadIdx.x / G;
   const bool act = idx < v1 - v0;
   prep_body<T, D, G>(it.mv, method, act ? sweep_vertex(it.mv, v0, v1, idx) : v0, act, threadIdx.x % G,
                      (const T*)it.hb, (T*)it.KL, it.fb,
@@ -1772,13 +1790,16 @@ __global__ void __launch_bounds__(WG) kb_update(const BatchItem* __restrict__ it
                                                 const BatchCtl* __restrict__ ctl,
                                                 const int* __restrict__ boff, int nmesh, int method,
                                                 int colour, int into_trial) {
-  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  // blocks of one XCD take a contiguous range of the launch (one mesh, or
+  // neighbouring ones), so each mesh's data stays in one L2
+  const int bx = xcd_block(blockIdx.x, gridDim.x);
+  const int mi = block_mesh(boff, nmesh, bx);
   if (!ctl[mi].active) return;
   const BatchItem& it = items[mi];
   const MeshView mv = it.mv;
   int v0, v1;
   vertex_range(it, colour, v0, v1);
-  const int i = v0 + (blockIdx.x - boff[mi]) * (WG / G) + threadIdx.x / G;
+  const int i = v0 + (bx - boff[mi]) * (WG / G) + threadIdx.x / G;
   update_body<T, D, G>(mv, method, i, i < v1, threadIdx.x % G, (const T*)it.KL, it.g,
                        into_trial ? it.xtrial : it.d, into_trial);
 }
@@ -1806,12 +1827,15 @@ template <int D, bool FCR>
 __global__ void __launch_bounds__(WG) kb_energy_grad(const BatchItem* __restrict__ items,
                                                      const BatchCtl* __restrict__ ctl,
                                                      const int* __restrict__ boff, int nmesh) {
+  // blocks of one XCD take a contiguous range of the launch (one mesh, or
+  // neighbouring ones), so each mesh's data stays in one L2
+  const int bx = xcd_block(blockIdx.x, gridDim.x);
   __shared__ double red[WG];
-  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  const int mi = block_mesh(boff, nmesh, bx);
   if (!ctl[mi].active) return;
   const BatchItem& it = items[mi];
   const MeshView mv = it.mv;
-  const int lb = blockIdx.x - boff[mi];
+  const int lb = bx - boff[mi];
   const int nbe = (mv.m + WG - 1) / WG;
   const int ne = nbe + (mv.nf + WG - 1) / WG;
   double v;
@@ -1828,12 +1852,15 @@ template <int D, bool FCR>
 __global__ void __launch_bounds__(WG) kb_energy(const BatchItem* __restrict__ items,
                                                 const BatchCtl* __restrict__ ctl,
                                                 const int* __restrict__ boff, int nmesh, int which) {
+  // blocks of one XCD take a contiguous range of the launch (one mesh, or
+  // neighbouring ones), so each mesh's data stays in one L2
+  const int bx = xcd_block(blockIdx.x, gridDim.x);
   __shared__ double red[WG];
-  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  const int mi = block_mesh(boff, nmesh, bx);
   if (!ctl[mi].active) return;
   const BatchItem& it = items[mi];
   const MeshView mv = it.mv;
-  const int lb = blockIdx.x - boff[mi];
+  const int lb = bx - boff[mi];
   const int nbe = (mv.m + WG - 1) / WG;
   const double v = energy_body<D, FCR>(mv, lb, nbe, pick(it, which), it.xt, it.mat);
   const double tot = block_sum<WG>(v, red);
@@ -1946,8 +1973,11 @@ __global__ void __launch_bounds__(WG) kb_energy_wide(const BatchItem* __restrict
                                                      const int* __restrict__ boff, int nmesh,
                                                      int total, int max_halvings,
                                                      double* __restrict__ wpart) {
+  // blocks of one XCD take a contiguous range of the launch (one mesh, or
+  // neighbouring ones), so each mesh's data stays in one L2
+  const int bx = xcd_block(blockIdx.x, gridDim.x);
   __shared__ double red[WG];
-  const int mi = block_mesh(boff, nmesh, blockIdx.x);
+  const int mi = block_mesh(boff, nmesh, bx);
   const BatchCtl& c = ctl[mi];
   const int k = blockIdx.y;
   if (!c.active || c.ls != 0 || c.halvings + k > max_halvings) return;
@@ -1955,11 +1985,11 @@ __global__ void __launch_bounds__(WG) kb_energy_wide(const BatchItem* __restrict
   for (int q = 0; q < k; ++q) alpha *= 0.5;
   const BatchItem& it = items[mi];
   const MeshView mv = it.mv;
-  const int lb = blockIdx.x - boff[mi];
+  const int lb = bx - boff[mi];
   const int nbe = (mv.m + WG - 1) / WG;
   const double v = energy_body_along<D, FCR>(mv, lb, nbe, it.x, it.d, alpha, it.xt, it.mat);
   const double tot = block_sum<WG>(v, red);
-  if (threadIdx.x == 0) wpart[(size_t)k * total + blockIdx.x] = tot;
+  if (threadIdx.x == 0) wpart[(size_t)k * total + bx] = tot;
 }
 
 // Per mesh, in halving order: E at alpha_k (partials summed as kb_reduce

@@ -236,7 +236,7 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
 cc_status cc_batch_tuning(cc_ctx* ctx, int32_t lanes, int32_t iters_per_graph);
 /* Rows per workgroup of the exact-basis condensation (every basis row it
    stages serves that many vertices per H block it loads): 0 = the most whose
-   LDS ring fits (4 in float32, 2 in float64 on MI355X), or a cap of 1, 2 or
+   LDS ring fits (4 in float32, 2 in float64 on MI355X), or a cap of 1 to
    4; and its chunk of band positions per pass, which is also its workgroup
    size: 0 = the one that leaves more waves resident per CU, or 256 / 512.
    A forced chunk whose ring does not fit sends the mesh to the sparse-row

@@ -5,7 +5,7 @@ The tunables, all set through the C ABI:
     (16, 32, 64; cc_batch_tuning);
   * iterations captured per graph replay, i.e. per host check (1, 2, 4;
     cc_batch_tuning);
-  * rows per workgroup of the exact-basis condensation (1, 2, 4 or the most
+  * rows per workgroup of the exact-basis condensation (1, 2, 3 or the most
     that fit; cc_dense_tuning).
 A candidate is timed by stepping the real batch for a few implicit steps
 from copies of the given state (the caller's state is not changed); the
@@ -27,7 +27,7 @@ from . import ccgpu as cg
 
 LANES = (16, 32, 64)
 ITERS_PER_GRAPH = (1, 2, 4)
-DENSE_ROWS = (0, 2, 1)          # 0: the most whose LDS ring fits
+DENSE_ROWS = (0, 3, 2, 1)       # 0: the most whose LDS ring fits
 
 
 def default_cache_path():

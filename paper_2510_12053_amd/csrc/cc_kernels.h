@@ -162,27 +162,32 @@ struct alignas(16) BandRec {
 
 // Access unit (bytes) and 32-bit words of one slot of the dense
 // condensation's LDS ring: tv blocks of D*D values of tsize bytes, read and
-// written in the widest unit (16, 8 or 4 bytes) that divides them, padded to
-// an odd number of units, so that consecutive slots read one unit each from
-// distinct banks.
+// written in 16-byte units (padded when that costs at most an eighth more),
+// else in the widest unit (8 or 4 bytes) that divides them, the slot padded
+// to an odd number of units, so that consecutive slots read one unit each
+// from distinct banks.
 __host__ __device__ constexpr int ring_slot_unit(int tv, int D, int tsize) {
-  return (tv * D * D * tsize) % 16 == 0 ? 16 : (tv * D * D * tsize) % 8 == 0 ? 8 : 4;
+  return (tv * D * D * tsize) % 16 == 0 || (16 - (tv * D * D * tsize) % 16) * 8 <= tv * D * D * tsize ? 16
+         : (tv * D * D * tsize) % 8 == 0                                                              ? 8
+                                                                                                        : 4;
 }
 __host__ __device__ constexpr int ring_slot_words(int tv, int D, int tsize) {
   const int unit = ring_slot_unit(tv, D, tsize);
-  int u = tv * D * D * tsize / unit;
+  int u = (tv * D * D * tsize + unit - 1) / unit;
   if (u % 2 == 0) ++u;
   return u * unit / 4;
 }
 
-// LDS ring length (power of two) of a mesh for chunks of ch positions, and
-// the dynamic LDS of a workgroup of tv rows.
+// LDS ring length of a mesh for chunks of ch positions (min(nf, ch +
+// band_w): every position a chunk's rows read), and the dynamic LDS of a
+// workgroup of tv rows.
 int band_ring(int nf, int band_w, int ch);
 size_t dense_lds_bytes(int tv, int ring, int D, int prec, int ch);
 // Rows per workgroup (tv) and chunk (ch, the workgroup size) of the dense
 // condensation for meshes with the given free-vertex counts and band widths:
-// the most rows whose ring fits (at most cap when cap > 0), then the chunk
-// (256 or 512) with more resident waves per CU, ties to the smaller chunk,
+// the most rows (4, 3, 2 or 1; at most 2 in float64) whose ring fits, at
+// most cap when cap > 0, then the chunk (256 or 512) with more resident
+// waves per CU (LDS and an estimate of the registers), ties to the smaller chunk,
 // whose workgroups overlap one another's ring fill and final sums (chunk > 0
 // forces that chunk).  tv = 0: no configuration fits.
 struct DenseCfg {

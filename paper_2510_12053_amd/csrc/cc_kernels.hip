@@ -600,8 +600,8 @@ template <> struct UnitVec<4> { typedef uint32_t type __attribute__((ext_vector_
 // unit at a time (ring_slot_unit).
 template <typename T, int D, int TV>
 struct SlotRegs {
-  static constexpr int NW = TV * D * D * (int)sizeof(T) / 4;              // data words
   static constexpr int UW = ring_slot_unit(TV, D, (int)sizeof(T)) / 4;   // words per unit
+  static constexpr int NW = (TV * D * D * (int)sizeof(T) / 4 + UW - 1) / UW * UW;   // data words, whole units
   typedef typename UnitVec<UW>::type unit_t;
   uint32_t w[NW];
   __device__ __forceinline__ void load(const uint32_t* slot) {
@@ -655,9 +655,11 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
                                                const double* __restrict__ g, double* __restrict__ bout) {
   constexpr int DD = D * D, NW = CH / 64, NR = DD + D, SLW = ring_slot_words(TV, D, sizeof(T));
   const int nf = mv.nf, n = mv.n, bw = mv.band_w;
-  int R = 64;                                       // band_ring(nf, bw, CH)
-  while (R < min(nf, CH + bw)) R *= 2;
-  const int msk = R - 1;
+  const int R = min(nf, CH + bw);                   // ring length (band_ring)
+  // position pos >= p0 (the current chunk's start) lives in slot
+  // (pos - p0 + p0 % R) mod R; pos - p0 < CH + bw, so one conditional
+  // subtraction of R reduces it
+  auto wrap = [&](int t) { return (int)min((unsigned)t, (unsigned)(t - R)); };
   uint32_t* ring = reinterpret_cast<uint32_t*>(smem);              // [R][SLW] words
   T* red = reinterpret_cast<T*>(ring + (size_t)R * SLW);          // [NW][TV][NR]
   const T* Ub = basis_of<T>(mv);
@@ -673,7 +675,7 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
     for (int v = 0; v < TV; ++v)
 #pragma unroll
       for (int r = 0; r < DD; ++r) sr.set(v * DD + r, blk[v][r]);
-    sr.store(ring + (size_t)(pos & msk) * SLW);
+    sr.store(ring + (size_t)pos * SLW);            // pos: a slot
   };
   // one buffer resource per basis row (a dense basis can pass 4 GiB, one
   // row cannot), so a block's offset is pos * D*D * sizeof(T)
@@ -695,12 +697,14 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
         }
       }
   };
-  int lo = min(nf, CH + bw);                        // first fill: positions [0, lo)
+  int lo = R;                                       // first fill: positions [0, R) in slots [0, R)
   for (int pos = tid; pos < lo; pos += CH) {
     T blk[TV][DD];
     fetch(pos, blk);
     put(pos, blk);
   }
+  int lo_slot = 0;                                  // lo % R
+  int p0_slot = 0;                                  // p0 % R
   __syncthreads();
   T Y[TV][DD], Bv[TV][D];
 #pragma unroll
@@ -718,6 +722,7 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
     T pre[TV][DD];
     if (pf) fetch(ppos, pre);
     const int p = p0 + tid;
+    const int cshift = p0_slot - p0;                // slot = wrap(pos + cshift)
     if (p < nf) {
       const int cnt = gptr(mv.bq_cnt)[p];
       T W[TV][DD];
@@ -731,7 +736,7 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
       // the buffer (read as zero) and are never used.
       auto consume = [&](const RecWords<T, D>& rc) {
         SlotRegs<T, D, TV> sr;
-        sr.load(ring + (size_t)(rc.pos() & msk) * SLW);
+        sr.load(ring + (size_t)wrap(rc.pos() + cshift) * SLW);
 #pragma unroll
         for (int v = 0; v < TV; ++v) {
           T U[DD];
@@ -782,7 +787,7 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
         }
       }
       SlotRegs<T, D, TV> sj;
-      sj.load(ring + (size_t)(p & msk) * SLW);
+      sj.load(ring + (size_t)wrap(p + cshift) * SLW);
 #pragma unroll
       for (int v = 0; v < TV; ++v) {
         T Uj[DD];
@@ -805,8 +810,12 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
       }
     }
     __syncthreads();                                // chunk p0's ring reads are done
-    if (pf) put(ppos, pre);
-    lo = max(lo, nhi);
+    if (pf) put(wrap(lo_slot + tid), pre);
+    if (nhi > lo) {
+      lo_slot = wrap(lo_slot + (nhi - lo));
+      lo = nhi;
+    }
+    p0_slot = wrap(p0_slot + CH);
     __syncthreads();
   }
 #pragma unroll
@@ -1339,10 +1348,15 @@ void set_lds_limit(size_t bytes) { g_lds_limit = bytes; }
 
 int band_ring(int nf, int band_w, int ch) {
   if (nf <= 0) return 0;
-  const int need = std::min(nf, ch + band_w);
-  int r = 64;
-  while (r < need) r *= 2;
-  return r;
+  return std::min(nf, ch + band_w);
+}
+
+// Resident waves per SIMD that the registers of the dense condensation allow
+// (gfx950 builds of prep_band_body: float32 196 / 154 / 112 / 70 VGPRs for
+// 4 / 3 / 2 / 1 rows, float64 210 / 131 for 2 / 1 rows)
+static int dense_reg_waves(int prec, int tv) {
+  if (prec == 0) return tv >= 2 ? 2 : 3;
+  return tv >= 4 ? 2 : tv == 3 ? 3 : tv == 2 ? 4 : 7;
 }
 
 size_t dense_lds_bytes(int tv, int ring, int D, int prec, int ch) {
@@ -1355,9 +1369,8 @@ size_t dense_lds_bytes(int tv, int ring, int D, int prec, int ch) {
 // waves/SIMD holds the accumulators of two float64 rows, four float32 ones)
 DenseCfg dense_config(const int* nf, const int* band_w, int count, int D, int prec, int cap, int chunk) {
   DenseCfg best;
-  int top = prec == 0 ? 2 : 4;
-  while (cap > 0 && top > cap) top /= 2;
-  for (int tv = top; tv >= 1 && best.tv == 0; tv /= 2) {
+  const int top = std::min(prec == 0 ? 2 : 4, cap > 0 ? cap : 4);
+  for (int tv = top; tv >= 1 && best.tv == 0; --tv) {
     int best_waves = 0;
     for (int ch : {256, BWG}) {
       if (chunk > 0 && ch != chunk) continue;
@@ -1366,7 +1379,7 @@ DenseCfg dense_config(const int* nf, const int* band_w, int count, int D, int pr
       if (ring <= 0) continue;
       const size_t lds = dense_lds_bytes(tv, ring, D, prec, ch);
       if (lds > g_lds_limit) continue;
-      const int waves = std::min((int)(g_lds_limit / lds) * (ch / 64), 32);
+      const int waves = std::min((int)(g_lds_limit / lds) * (ch / 64), 4 * dense_reg_waves(prec, tv));
       if (waves > best_waves) {
         best_waves = waves;
         best.tv = tv;
@@ -1382,9 +1395,11 @@ DenseCfg dense_config(const int* nf, const int* band_w, int count, int D, int pr
   switch ((tv) * 1000 + (ch)) {                                                       \
     case 1256: { constexpr int TV = 1, CH = 256; __VA_ARGS__; } break;                \
     case 2256: { constexpr int TV = 2, CH = 256; __VA_ARGS__; } break;                \
+    case 3256: { constexpr int TV = 3, CH = 256; __VA_ARGS__; } break;                \
     case 4256: { constexpr int TV = 4, CH = 256; __VA_ARGS__; } break;                \
     case 1512: { constexpr int TV = 1, CH = 512; __VA_ARGS__; } break;                \
     case 2512: { constexpr int TV = 2, CH = 512; __VA_ARGS__; } break;                \
+    case 3512: { constexpr int TV = 3, CH = 512; __VA_ARGS__; } break;                \
     default: { constexpr int TV = 4, CH = 512; __VA_ARGS__; } break;                  \
   }
 

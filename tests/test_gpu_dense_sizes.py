@@ -5,9 +5,9 @@ workgroup and the chunk of band positions forced through cc_dense_tuning,
 and a batch of the largest bars against single-mesh steps.
 
 The 41x7x7 bar has 1,960 free vertices: 8 chunks of 256 positions (the last
-holding 168) or 4 of 512 (the last 424), so the ring wraps several times and
-the tail is ragged.  Rows per workgroup: float64 1 and 2, float32-mixed 1, 2
-and 4; chunks 256 and 512; with and without corotation (rotated band
+holding 168) or 4 of 512 (the last 424), so the ring (chunk + band width
+positions) wraps several times and the tail is ragged.  Rows per workgroup:
+float64 1 and 2, float32-mixed 1 to 4; chunks 256 and 512; with and without corotation (rotated band
 records and R^T g).  Tolerances: float64 1e-9, float32-mixed 1e-4 of the
 largest direction."""
 import numpy as np
@@ -60,7 +60,8 @@ def bar(cg, ctx):
 
 
 CONFIGS = [(0, 1, 256), (0, 1, 512), (0, 2, 256), (0, 2, 512),
-           (1, 1, 256), (1, 1, 512), (1, 2, 256), (1, 2, 512), (1, 4, 256), (1, 4, 512)]
+           (1, 1, 256), (1, 1, 512), (1, 2, 256), (1, 2, 512), (1, 3, 256), (1, 3, 512),
+           (1, 4, 256), (1, 4, 512)]
 
 
 @pytest.mark.parametrize("corot", [0, 1])
@@ -82,7 +83,7 @@ def test_directions_every_configuration(cg, ctx, bar, prec, rows, chunk, corot):
 
 def test_dense_tuning_rejects_bad_values(cg, ctx):
     with pytest.raises(cg.CCError):
-        cg.cc_dense_tuning(ctx, 3, 0)
+        cg.cc_dense_tuning(ctx, 5, 0)
     with pytest.raises(cg.CCError):
         cg.cc_dense_tuning(ctx, 0, 384)
     cg.cc_dense_tuning(ctx, 0, 0)

@@ -249,7 +249,8 @@ cc_status cc_autotune_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, con
 /* Extra results of the last cc_step on a mesh (host outputs, any may be NULL):
    final step energy, the paper's normalised residual |g|/(V n E) (divided by
    h when dynamic), fallback counters (Ht or empty support, Schur, H_ii),
-   line-search halvings taken, and whether a warm-start proposal was accepted. */
+   line-search halvings taken, and which warm-start proposal was accepted
+   (0 none, 1 the network's x~ + c + l Delta, 2 the correction alone x~ + c). */
 cc_status cc_step_info(cc_ctx* ctx, int32_t mesh_id, double* energy, double* paper_residual,
                        int64_t* fallbacks3, int64_t* halvings, int32_t* warm_accepted);
 
@@ -276,11 +277,14 @@ cc_status cc_probe_sweep(cc_ctx* ctx, int32_t mesh_id, const double* x, const do
    predictor displacement, h v, the step-Hessian diagonal block and strain
    statistics of the incident elements), z-scored with stored statistics,
    pass through a 32-64-64-16 SiLU network (BF16 MFMA products, FP32
-   accumulation) whose first three outputs Delta_i give x_i = x~_i + l Delta_i
-   (l: mean rest edge length).  With cc_params.warm_start = 1 cc_step and
-   cc_step_batch use the proposal only when E(proposal) < E(x~) (float64);
-   the convergence denominator stays |g(x~)|.  Not part of the paper: an
-   extension evaluated against plain CC. */
+   accumulation) whose first three outputs Delta_i give
+   x_i = x~_i + c_i + l Delta_i (l: mean rest edge length; c_i: the vertex's
+   correction x_end - x~ of the mesh's last step, zero before the first, so
+   the network learns how the correction changes from step to step).  With
+   cc_params.warm_start = 1 cc_step and cc_step_batch use the proposal only
+   when E(proposal) < E(x~) (float64); the convergence denominator stays
+   |g(x~)|.  Not part of the paper: an extension evaluated against plain
+   CC. */
 #define CC_MLP_NPARAM 7312  /* packed float32 W1 32x64, b1 64, W2 64x64, b2 64,
                                W3 64x16, b3 16, row-major ([in][out])             */
 #define CC_MLP_NFEAT  16
@@ -295,13 +299,16 @@ cc_status cc_mlp_get(cc_ctx* ctx, float* params, float* mean, float* istd);
 cc_status cc_mlp_norm_from_data(cc_ctx* ctx, const float* X, int32_t N);
 /* Features of a 3D mesh for the step that starts at x, v (device n x 3) with
    targets x_bc (device or NULL): feat (device, n_free x 16, one row per free
-   vertex in ascending caller id), x_tilde (device n x 3 predictor with
-   targets, or NULL), *ell (host, or NULL). */
+   vertex in ascending caller id), x_base (device n x 3, or NULL): the base
+   the warm start adds l * Delta to, the predictor with targets plus, on free
+   vertices, the mesh's last step correction x_end - x~ (zero before the
+   mesh's first step; every cc_step / cc_step_batch on the mesh updates it),
+   *ell (host, or NULL). */
 cc_status cc_mlp_features(cc_ctx* ctx, int32_t mesh_id, const double* x, const double* v,
-                          const double* x_bc, double dt, float* feat, double* x_tilde, double* ell);
+                          const double* x_bc, double dt, float* feat, double* x_base, double* ell);
 /* Training targets T (device, n_free x 3, rows as in cc_mlp_features):
-   (x_new - x_tilde) / l for the free vertices (x_new, x_tilde: device n x 3). */
-cc_status cc_mlp_targets(cc_ctx* ctx, int32_t mesh_id, const double* x_new, const double* x_tilde,
+   (x_new - x_base) / l for the free vertices (x_new, x_base: device n x 3). */
+cc_status cc_mlp_targets(cc_ctx* ctx, int32_t mesh_id, const double* x_new, const double* x_base,
                          float* T);
 /* Network outputs Y (device, B x 3) for raw feature rows X (device, B x 16). */
 cc_status cc_mlp_forward(cc_ctx* ctx, const float* X, int32_t B, float* Y);

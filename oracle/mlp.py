@@ -146,7 +146,11 @@ def adam(theta, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     return theta - lr * mhat / (np.sqrt(vhat) + eps), m, v
 
 
-def proposal(prob, x_tilde, Delta, ell):
+def proposal(prob, x_tilde, Delta, ell, corr=None):
+    """x~ + c + l Delta on free vertices, x~ on Dirichlet ones; c (n x d, or
+    None for zero) is the previous step's correction x_end - x~."""
     xp = x_tilde.copy()
     xp[prob.free] += ell * Delta[:, :N_OUT]
+    if corr is not None:
+        xp[prob.free] += corr[prob.free]
     return xp

@@ -240,7 +240,7 @@ def cc_step_info(ctx, mesh_id):
     _check(ctx, lib().cc_step_info(ctx.handle, mesh_id, ctypes.byref(e), ctypes.byref(pr), _ptr(fb),
                                    ctypes.byref(hv), ctypes.byref(wa)))
     return dict(energy=e.value, paper_residual=pr.value, fallbacks=fb, halvings=hv.value,
-                warm_accepted=bool(wa.value))
+                warm_accepted=int(wa.value))
 
 
 def cc_probe_element(ctx, mesh_id, x, precision, n_elems):
@@ -371,7 +371,9 @@ def cc_mlp_norm_from_data(ctx, X):
 
 
 def cc_mlp_features(ctx, mesh_id, x, v, x_bc, dt, n_free, out=None):
-    """Returns (feat (n_free,16) float32 CUDA tensor, x_tilde (n,3) float64, ell).
+    """Returns (feat (n_free,16) float32 CUDA tensor, x_base (n,3) float64, ell):
+    x_base is the predictor plus the mesh's last step correction on free
+    vertices, the point the warm start adds ell * Delta to.
     out: optional preallocated (n_free,16) float32 tensor (e.g. a view into a
     dataset)."""
     import torch
@@ -421,7 +423,7 @@ def cc_mlp_train_step(ctx, X, T, idx, lr):
     return loss.value
 
 
-def cc_mlp_targets(ctx, mesh_id, x_new, x_tilde, n_free, out=None):
+def cc_mlp_targets(ctx, mesh_id, x_new, x_base, n_free, out=None):
     import torch
     T = out if out is not None else torch.zeros((n_free, 3), dtype=torch.float32, device=x_new.device)
     L = _ml()
@@ -430,5 +432,5 @@ def cc_mlp_targets(ctx, mesh_id, x_new, x_tilde, n_free, out=None):
         L.cc_mlp_targets.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p]
         L._tgt_sig = True
-    _check(ctx, L.cc_mlp_targets(ctx.handle, mesh_id, _dptr(x_new), _dptr(x_tilde), _dptr(T, "float32")))
+    _check(ctx, L.cc_mlp_targets(ctx.handle, mesh_id, _dptr(x_new), _dptr(x_base), _dptr(T, "float32")))
     return T

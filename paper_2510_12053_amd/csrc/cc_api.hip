@@ -62,6 +62,7 @@ struct Mesh {
   double *x = nullptr, *xt = nullptr, *x0 = nullptr, *xtrial = nullptr, *dvec = nullptr,
          *g = nullptr, *partials = nullptr, *scal = nullptr;
   double* rot = nullptr;  // corotation: rotation of every free vertex (D*D each)
+  double* corr = nullptr; // last step's correction x - x~ (MeshView::corr)
   void *estore = nullptr, *hb = nullptr, *KL = nullptr;
   unsigned long long* fb = nullptr;
   int* bad = nullptr;
@@ -91,6 +92,7 @@ struct Mesh {
     v.sorder = d_sorder;
     v.aorder = d_aorder;
     v.cel_ptr = d_cel_ptr; v.cel = d_cel; v.csl_ptr = d_csl_ptr; v.csl = d_csl;
+    v.corr = corr;
     return v;
   }
 };
@@ -156,7 +158,7 @@ void free_mesh(Mesh& M) {
   free_basis(M);
   dfree(M.x); dfree(M.xt); dfree(M.x0); dfree(M.xtrial); dfree(M.dvec); dfree(M.g);
   dfree(M.partials); dfree(M.scal); dfree(M.estore); dfree(M.hb); dfree(M.KL); dfree(M.fb);
-  dfree(M.bad); dfree(M.rot);
+  dfree(M.bad); dfree(M.rot); dfree(M.corr);
   dfree(M.nptr); dfree(M.nidx); dfree(M.frank); dfree(M.Xr); dfree(M.feat); dfree(M.delta);
 }
 
@@ -767,6 +769,8 @@ void build_mesh(cc_ctx* ctx, Mesh& M) {
   M.hb = dalloc<double>((size_t)M.nnzb * D * D);
   M.KL = dalloc<double>((size_t)nf * 2 * D * D);
   M.rot = dalloc<double>((size_t)std::max(nf, 1) * D * D);
+  M.corr = dalloc<double>((size_t)D * n);
+  HIPC(hipMemsetAsync(M.corr, 0, (size_t)D * n * sizeof(double), s));
   M.fb = dalloc<unsigned long long>(4);
   M.bad = dalloc<int>(1);
   HIPC(hipStreamSynchronize(s));
@@ -1554,18 +1558,25 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
       r = gstart / g0;
       if (p.warm_start) {
         // learned proposal at the predictor, kept only if it lowers E
-        cc::launch_features(S.mv, M.x, M.x0, h, M.E, M.mu, M.lam, M.model, M.ell, M.nptr, M.nidx, M.Xr, M.feat, nullptr,
+        cc::launch_elem_hess_list(S.mv, p.precision, M.x, mat, mat.s_el, M.estore, s, nullptr, M.m);
+        cc::launch_features(S.mv, M.x, M.x0, h, M.E, p.precision, M.estore, mat.s_el, M.ell, M.nptr, M.nidx, M.Xr,
+                            M.feat, nullptr,
                             s);
         cc::mlp_forward(ctx->mlp, M.feat, M.nf, M.delta, s);
-        cc::launch_proposal(M.n, M.nf, M.x, M.delta, M.ell, M.xtrial, s);
-        const double E0 = S.energy(M.x), Ep = S.energy(M.xtrial);
-        if (Ep < E0) {
-          std::swap(M.x, M.xtrial);
-          warm = 1;
-          r = std::sqrt(S.grad_norm2(M.x)) / g0;
-        } else {
-          (void)S.grad_norm2(M.x);  // g at the predictor for the first iteration
+        // x~ + c + l Delta, then x~ + c alone (c: the last step's
+        // correction), each kept only below the start's energy so far
+        double Ebest = S.energy(M.x);
+        for (int cand = 1; cand <= 2; ++cand) {
+          cc::launch_proposal(M.n, M.nf, M.xt, M.corr, M.delta, M.ell, cand == 1 ? 1.0 : 0.0, M.xtrial, s);
+          const double Ep = S.energy(M.xtrial);
+          if (Ep < Ebest) {
+            std::swap(M.x, M.xtrial);
+            Ebest = Ep;
+            warm = cand;
+          }
         }
+        if (warm) r = std::sqrt(S.grad_norm2(M.x)) / g0;
+        else (void)S.grad_norm2(M.x);  // g at the predictor for the first iteration
       }
       if (p.line_search) Ecur = S.energy(M.x);
       while (r > tol && k < p.max_iters) {
@@ -1623,7 +1634,7 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
     }
     unsigned long long fbh[4];
     HIPC(hipMemcpyAsync(fbh, M.fb, sizeof(fbh), hipMemcpyDeviceToHost, s));
-    cc::launch_finalize(S.mv, M.d_vperm, M.x, M.x0, h, p.quasistatic, x, v, s);
+    cc::launch_finalize(S.mv, M.d_vperm, M.x, M.xt, M.x0, h, p.quasistatic, x, v, s);
     HIPC(hipStreamSynchronize(s));
     ctx->harvest();
     for (int c = 0; c < 3; ++c) M.last_fb[c] = (long long)fbh[c];
@@ -2190,7 +2201,7 @@ cc_status cc_mlp_norm_from_data(cc_ctx* ctx, const float* X, int32_t N) {
 }
 
 cc_status cc_mlp_features(cc_ctx* ctx, int32_t mesh_id, const double* x, const double* v, const double* x_bc,
-                          double dt, float* feat, double* x_tilde, double* ell) {
+                          double dt, float* feat, double* x_base, double* ell) {
   return guarded(ctx, [&]() -> cc_status {
     Mesh& M = get_mesh(ctx, mesh_id);
     if (M.D != 3) return fail(ctx, CC_E_INVALID_ARG, "features are defined for 3D meshes");
@@ -2199,9 +2210,14 @@ cc_status cc_mlp_features(cc_ctx* ctx, int32_t mesh_id, const double* x, const d
     MeshView mv = M.view();
     HIPC(hipMemsetAsync(M.bad, 0, sizeof(int), s));
     cc::launch_predict(mv, M.d_vperm, x, v, x_bc, dt, 0, M.x, M.xt, M.x0, M.bad, s);
-    cc::launch_features(mv, M.x, M.x0, dt, M.E, M.mu, M.lam, M.model, M.ell, M.nptr, M.nidx, M.Xr, feat, M.frank,
+    cc::Material mat{};
+    mat.mu = M.mu; mat.lam = M.lam; mat.model = M.model;
+    mat.w_in = 1.0;
+    mat.s_el = dt * dt;
+    cc::launch_elem_hess_list(mv, 0, M.x, mat, mat.s_el, M.estore, s, nullptr, M.m);
+    cc::launch_features(mv, M.x, M.x0, dt, M.E, 0, M.estore, mat.s_el, M.ell, M.nptr, M.nidx, M.Xr, feat, M.frank,
                         s);
-    if (x_tilde) cc::launch_scatter_user(mv, M.d_vperm, M.x, x_tilde, 0, s);
+    if (x_base) cc::launch_base_user(mv, M.d_vperm, M.x, x_base, s);
     if (ell) *ell = M.ell;
     int bad = 0;
     HIPC(hipMemcpyAsync(&bad, M.bad, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -2287,11 +2303,11 @@ cc_status cc_mlp_train_step(cc_ctx* ctx, const float* X, const float* T, const i
 }
 
 
-cc_status cc_mlp_targets(cc_ctx* ctx, int32_t mesh_id, const double* x_new, const double* x_tilde, float* T) {
+cc_status cc_mlp_targets(cc_ctx* ctx, int32_t mesh_id, const double* x_new, const double* x_base, float* T) {
   return guarded(ctx, [&]() -> cc_status {
     Mesh& M = get_mesh(ctx, mesh_id);
-    if (M.D != 3 || !x_new || !x_tilde || !T) return fail(ctx, CC_E_INVALID_ARG, "bad target arguments");
-    cc::launch_targets(M.view(), x_new, x_tilde, M.ell, M.frank, T, ctx->stream);
+    if (M.D != 3 || !x_new || !x_base || !T) return fail(ctx, CC_E_INVALID_ARG, "bad target arguments");
+    cc::launch_targets(M.view(), x_new, x_base, M.ell, M.frank, T, ctx->stream);
     HIPC(hipStreamSynchronize(ctx->stream));
     return CC_OK;
   });

@@ -60,6 +60,10 @@ struct MeshView {
   int smap_supp;         // longest support row of the slot-mapped basis
   // corotation: per free vertex rotation R_j (row-major D*D), or null = off
   const double* rot;
+  // the last finished step's correction x - x~ (free vertices, component-major
+  // like x; zero on Dirichlet vertices and before the first step): the base
+  // the learned warm start adds its prediction to
+  double* corr;
   // free internal ids in caller order (spatially coherent on the structured
   // grids): the order in which a whole-mesh Jacobi condensation visits them
   const int* sorder;
@@ -95,7 +99,7 @@ struct Material {
 void launch_predict(const MeshView& mv, const int* vperm, const double* x_user,
                     const double* v_user, const double* x_bc, double h, int quasi,
                     double* x, double* xt, double* x0, int* bad, hipStream_t s);
-void launch_finalize(const MeshView& mv, const int* vperm, const double* x, const double* x0,
+void launch_finalize(const MeshView& mv, const int* vperm, const double* x, const double* xt, const double* x0,
                      double h, int quasi, double* x_user, double* v_user, hipStream_t s);
 void launch_elem_hess(const MeshView& mv, int prec, const double* x, const Material& mat,
                       double scale, void* estore, hipStream_t s);
@@ -292,11 +296,14 @@ struct BatchGrid {
   int max_iters;
   int any_fcr;          // some mesh uses the Fixed Corotational model
   int line_search;      // E at the predictor is already in ctl.E_cur
+  int prec;             // 0 float64, 1 float32 local arithmetic
 };
 BatchGrid batch_grid(BatchPlan* p);
 // ctl.E_trial = E(xtrial); post 3: then the warm start's accept rule
 void batch_energy_trial(BatchPlan* p, hipStream_t s, int post = 0);
 void batch_energy_x(BatchPlan* p, hipStream_t s);       // ctl.E_cur = E(x)
+// element Hessians of every active mesh at x into its element store
+void batch_elem_hess_x(BatchPlan* p, hipStream_t s);
 // g(x), ctl.gn2; only_warm: only meshes whose learned proposal was accepted
 // gradient at x; post 4 (with only_warm): then the residual test of an
 // accepted proposal

@@ -1148,7 +1148,7 @@ __global__ void k_predict(MeshView mv, const int* __restrict__ vperm,
 
 template <int D>
 __global__ void k_finalize(MeshView mv, const int* __restrict__ vperm, const double* __restrict__ x,
-                           const double* __restrict__ x0, double h, int quasi,
+                           const double* __restrict__ xt, const double* __restrict__ x0, double h, int quasi,
                            double* __restrict__ xu, double* __restrict__ vu) {
   const int v = blockIdx.x * WG + threadIdx.x;
   if (v >= mv.n) return;
@@ -1158,6 +1158,7 @@ __global__ void k_finalize(MeshView mv, const int* __restrict__ vperm, const dou
     const double xn = x[c * n + v];
     xu[u * D + c] = xn;
     vu[u * D + c] = quasi ? 0.0 : (xn - x0[c * n + v]) / h;
+    if (mv.corr) mv.corr[c * n + v] = v < mv.nf ? xn - xt[c * n + v] : 0.0;
   }
 }
 
@@ -1238,9 +1239,9 @@ void launch_predict(const MeshView& mv, const int* vperm, const double* x_user, 
                                                                    h, quasi, x, xt, x0, bad));
 }
 
-void launch_finalize(const MeshView& mv, const int* vperm, const double* x, const double* x0,
+void launch_finalize(const MeshView& mv, const int* vperm, const double* x, const double* xt, const double* x0,
                      double h, int quasi, double* x_user, double* v_user, hipStream_t s) {
-  CC_DISPATCH_D(mv.D, k_finalize<D><<<nblocks(mv.n, WG), WG, 0, s>>>(mv, vperm, x, x0, h, quasi,
+  CC_DISPATCH_D(mv.D, k_finalize<D><<<nblocks(mv.n, WG), WG, 0, s>>>(mv, vperm, x, xt, x0, h, quasi,
                                                                     x_user, v_user));
 }
 
@@ -1649,6 +1650,7 @@ __global__ void __launch_bounds__(WG) kb_finalize(const BatchItem* __restrict__ 
     const double xn = it.x[c * n + v];
     it.xu[u * D + c] = xn;
     it.vu[u * D + c] = quasi ? 0.0 : (xn - it.x0[c * n + v]) / h;
+    if (mv.corr) mv.corr[c * n + v] = v < mv.nf ? xn - it.xt[c * n + v] : 0.0;
   }
 }
 
@@ -1901,13 +1903,14 @@ __device__ __forceinline__ void accept_mesh(BatchItem& item, BatchCtl& c, int li
 
 // Learned warm start: the proposal (in xtrial, its energy in E_trial)
 // replaces the predictor when it has the lower step energy.
-__device__ __forceinline__ void warm_accept_mesh(BatchItem& item, BatchCtl& c) {
+// tag: 1 the network's proposal, 2 the previous correction alone
+__device__ __forceinline__ void warm_accept_mesh(BatchItem& item, BatchCtl& c, int tag) {
   if (c.E_trial < c.E_cur) {
     double* t = item.x;
     item.x = item.xtrial;
     item.xtrial = t;
     c.E_cur = c.E_trial;
-    c.warm = 1;
+    c.warm = tag;
   }
 }
 
@@ -1953,7 +1956,8 @@ __global__ void __launch_bounds__(WG) kb_reduce(BatchItem* __restrict__ items, B
     else c.E_cur = tot;
     if (post == 1) accept_mesh(items[mi], c, 1);
     else if (post == 2) converged_mesh(c, tol, max_iters);
-    else if (post == 3) warm_accept_mesh(items[mi], c);
+    else if (post == 3) warm_accept_mesh(items[mi], c, 1);
+    else if (post == 5) warm_accept_mesh(items[mi], c, 2);
     else if (post == 4) warm_check_mesh(c, tol);
   }
 }
@@ -2503,6 +2507,16 @@ void batch_gradient_x(BatchPlan* p, hipStream_t s, int only_warm, int post) {
   if (p->cfg.D == 3) b_gradient<3>(p, 0, s, post, only_warm);
   else b_gradient<2>(p, 0, s, post, only_warm);
 }
+void batch_elem_hess_x(BatchPlan* p, hipStream_t s) {
+  const Offsets& oe = p->elem;
+  if (gridn(oe) == 0) return;
+  if (p->cfg.prec == 0)
+    CC_DISPATCH_MAT(p->cfg.any_fcr, kb_elem_hess<double, 3, FCR><<<gridn(oe), elem_threads<double>(), 0, s>>>(
+                                        p->items_d, p->ctl_d, oe.d, p->nmesh, 0, -1));
+  else
+    CC_DISPATCH_MAT(p->cfg.any_fcr, kb_elem_hess<float, 3, FCR><<<gridn(oe), elem_threads<float>(), 0, s>>>(
+                                        p->items_d, p->ctl_d, oe.d, p->nmesh, 0, -1));
+}
 void batch_energy_x(BatchPlan* p, hipStream_t s) {
   if (p->cfg.D == 3) b_energy<3>(p, 0, 2, s); else b_energy<2>(p, 0, 2, s);
 }
@@ -2544,6 +2558,7 @@ BatchGrid batch_grid(BatchPlan* p) {
   g.max_iters = p->cfg.max_iters;
   g.any_fcr = p->cfg.any_fcr;
   g.line_search = p->cfg.line_search;
+  g.prec = p->cfg.prec;
   return g;
 }
 

@@ -54,12 +54,19 @@ void mlp_gradient_into(const MlpState& s, const float* X, const float* T, const 
                        float* loss, float* part, float* lpart, hipStream_t st);
 void mlp_adam(MlpState& s, const float* grad, float lr, hipStream_t st);
 void mlp_stats(MlpState& s, const float* X, int N, hipStream_t st);
-void launch_features(const MeshView& mv, const double* xt, const double* x0, double h, double E, double mu,
-                     double lam, int model, double ell, const int* nptr, const int* nidx, const double* Xr,
-                     float* out, const int* rowmap, hipStream_t st);
+// Features at the predictor xt; estore: the element store of an element-
+// Hessian pass at xt in precision prec (0 float64, 1 float32) with scale s_el.
+void launch_features(const MeshView& mv, const double* xt, const double* x0, double h, double E, int prec,
+                     const void* estore, double s_el, double ell, const int* nptr, const int* nidx,
+                     const double* Xr, float* out, const int* rowmap, hipStream_t st);
 void launch_targets(const MeshView& mv, const double* xn, const double* xt, double ell, const int* rowmap,
                     float* T, hipStream_t st);
-void launch_proposal(int n, int nf, const double* xt, const float* delta, double ell, double* xp,
-                     hipStream_t st);
+// The learned proposal: x~ + corr + ds * ell * Delta on free vertices (corr:
+// the mesh's last step correction, MeshView::corr; ds = 0: the correction
+// alone).
+void launch_proposal(int n, int nf, const double* xt, const double* corr, const float* delta, double ell,
+                     double ds, double* xp, hipStream_t st);
+// x~ + corr in caller order (n x 3), the base the proposal adds ell * Delta to.
+void launch_base_user(const MeshView& mv, const int* vperm, const double* xt, double* x_user, hipStream_t st);
 
 }  // namespace cc

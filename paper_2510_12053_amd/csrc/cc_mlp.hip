@@ -384,14 +384,16 @@ constexpr int FEAT_G = FEAT_LANES;
 
 // Features of free vertex j of one mesh at the predictor xt (internal order)
 // with x0 the start-of-step positions, computed by G lanes that share j: the
-// lanes split
-// the neighbour list and the incident elements, then combine by shuffles.
-// Every lane of the group must call it (j may be past the free range: the
-// group then contributes nothing and writes nothing).
-template <int G, bool FCR>
+// lanes split the neighbour list and the incident elements, then combine by
+// shuffles.  The diagonal Hessian block comes from the element store of an
+// element-Hessian pass at xt (estore, s_el times each element's packed
+// blocks, in the step's precision T), so no projected Hessian is evaluated
+// here.  Every lane of the group must call it (j may be past the free range:
+// the group then contributes nothing and writes nothing).
+template <int G, typename T>
 __device__ __forceinline__ void features_group(const MeshView& mv, int j, int lane,
                                                const double* __restrict__ xt, const double* __restrict__ x0,
-                                               double h, double E, double mu, double lam, int model,
+                                               double h, double E, const T* __restrict__ estore, double s_el,
                                                double ell, const int* __restrict__ nptr,
                                                const int* __restrict__ nidx,
                                                const double* __restrict__ Xr, float* __restrict__ out) {
@@ -417,36 +419,11 @@ __device__ __forceinline__ void features_group(const MeshView& mv, int j, int la
     const int e = mv.star[t] >> 2, a = mv.star[t] & 3;
     double F[3][3], beta[4][3], vol;
     load_element<double, 3>(mv, e, xt, F, beta, vol);
-    // vertex a's row of a mode matrix M: M beta_a (beta_0 = -(beta_1 + beta_2 + beta_3))
-    auto row = [&](const double (&M)[3][3], double (&y)[3]) {
+    const T* blk = estore + ((size_t)pidx<4>(a, a) * mv.m + e) * 9;
 #pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        double s = 0.0;
-        if (a == 0) {
+    for (int r = 0; r < 3; ++r)
 #pragma unroll
-          for (int q = 0; q < 3; ++q) s -= M[r][q] * (beta[1][q] + beta[2][q] + beta[3][q]);
-        } else {
-#pragma unroll
-          for (int q = 0; q < 3; ++q) s += M[r][q] * beta[a][q];
-        }
-        y[r] = s;
-      }
-    };
-    projected_eigs<double, 3>(F, mu, lam, FCR ? model : MAT_SNH,
-                              [&](double w, const double (&Q)[3][3], const double (&P)[3][3], bool same) {
-      double y[3], z[3];
-      row(Q, y);
-      if (same) {
-#pragma unroll
-        for (int r = 0; r < 3; ++r) z[r] = y[r];
-      } else {
-        row(P, z);
-      }
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int s2 = 0; s2 < 3; ++s2) Hd[r][s2] += vol * w * y[r] * z[s2];
-    });
+      for (int c = 0; c < 3; ++c) Hd[r][c] += (double)blk[r * 3 + c];
     double ic = 0.0;
 #pragma unroll
     for (int r = 0; r < 3; ++r)
@@ -485,11 +462,12 @@ __device__ __forceinline__ void features_group(const MeshView& mv, int j, int la
   }
   const double mj = mv.mass[j];
   const double scale = mj + h * h * E * ell;
+  const double hs = h * h / s_el;                 // h^2 H_e from the stored s_el H_e
   const int up[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     const int r = up[q][0], c = up[q][1];
-    f[6 + q] = ((r == c ? mj : 0.0) + h * h * Hd[r][c]) / scale;
+    f[6 + q] = ((r == c ? mj : 0.0) + hs * Hd[r][c]) / scale;
   }
   f[12] = ic_m / wsum;
   f[13] = j_m / wsum;
@@ -500,27 +478,46 @@ __device__ __forceinline__ void features_group(const MeshView& mv, int j, int la
 }
 
 // rowmap: null -> row j (internal order), else row rowmap[j]
-template <bool FCR>
+template <typename T>
 __global__ void __launch_bounds__(WG) k_features(MeshView mv, const double* __restrict__ xt,
                                                  const double* __restrict__ x0, double h, double E,
-                                                 double mu, double lam, int model, double ell,
+                                                 const T* __restrict__ estore, double s_el, double ell,
                                                  const int* __restrict__ nptr, const int* __restrict__ nidx,
                                                  const double* __restrict__ Xr, float* __restrict__ out,
                                                  const int* __restrict__ rowmap) {
   const int j = blockIdx.x * (WG / FEAT_G) + threadIdx.x / FEAT_G;
   const int row = (j < mv.nf) ? (rowmap ? rowmap[j] : j) : 0;
-  features_group<FEAT_G, FCR>(mv, j, threadIdx.x % FEAT_G, xt, x0, h, E, mu, lam, model, ell, nptr, nidx, Xr,
-                         out + (size_t)row * 16);
+  features_group<FEAT_G, T>(mv, j, threadIdx.x % FEAT_G, xt, x0, h, E, estore, s_el, ell, nptr, nidx, Xr,
+                            out + (size_t)row * 16);
 }
 
-// x_prop = xt + ell * Delta on free vertices, xt on Dirichlet ones.
-__global__ void k_proposal(int n, int nf, const double* __restrict__ xt, const float* __restrict__ delta,
-                           double ell, double* __restrict__ xp) {
+// x_prop = xt + corr + ds * ell * Delta on free vertices (corr: the last
+// step's correction; ds = 1 the network's proposal, 0 the correction alone),
+// xt on Dirichlet ones.
+__global__ void k_proposal(int n, int nf, const double* __restrict__ xt, const double* __restrict__ corr,
+                           const float* __restrict__ delta, double ell, double ds, double* __restrict__ xp) {
   const int v = blockIdx.x * WG + threadIdx.x;
   if (v >= n) return;
 #pragma unroll
   for (int c = 0; c < 3; ++c)
-    xp[c * n + v] = xt[c * n + v] + (v < nf ? ell * (double)delta[(size_t)v * MLP_NOUT + c] : 0.0);
+    xp[c * n + v] = xt[c * n + v] +
+        (v < nf ? corr[c * n + v] + (ds != 0.0 ? ds * ell * (double)delta[(size_t)v * MLP_NOUT + c] : 0.0)
+                : 0.0);
+}
+
+// The proposal's base x~ + corr (free vertices; x~ on Dirichlet ones), in
+// caller order n x 3.
+__global__ void k_base_user(MeshView mv, const int* __restrict__ vperm, const double* __restrict__ xt,
+                            const double* __restrict__ corr, double* __restrict__ xu) {
+  const int v = blockIdx.x * WG + threadIdx.x;
+  if (v >= mv.n) return;
+  const int u = vperm[v], n = mv.n;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) xu[u * 3 + c] = xt[c * n + v] + (v < mv.nf ? corr[c * n + v] : 0.0);
+}
+
+void launch_base_user(const MeshView& mv, const int* vperm, const double* xt, double* x_user, hipStream_t st) {
+  k_base_user<<<(mv.n + WG - 1) / WG, WG, 0, st>>>(mv, vperm, xt, mv.corr, x_user);
 }
 
 // ---- launchers -----------------------------------------------------------
@@ -567,15 +564,17 @@ void mlp_stats(MlpState& s, const float* X, int N, hipStream_t st) {
   k_mlp_stats<<<MLP_IN, WG, 0, st>>>(X, N, s.mean, s.istd);
 }
 
-void launch_features(const MeshView& mv, const double* xt, const double* x0, double h, double E, double mu,
-                     double lam, int model, double ell, const int* nptr, const int* nidx, const double* Xr,
-                     float* out, const int* rowmap, hipStream_t st) {
+void launch_features(const MeshView& mv, const double* xt, const double* x0, double h, double E, int prec,
+                     const void* estore, double s_el, double ell, const int* nptr, const int* nidx,
+                     const double* Xr, float* out, const int* rowmap, hipStream_t st) {
   if (mv.nf <= 0) return;
   const int nb = (mv.nf + WG / FEAT_G - 1) / (WG / FEAT_G);
-  if (model == MAT_FCR)
-    k_features<true><<<nb, WG, 0, st>>>(mv, xt, x0, h, E, mu, lam, model, ell, nptr, nidx, Xr, out, rowmap);
+  if (prec == 0)
+    k_features<double><<<nb, WG, 0, st>>>(mv, xt, x0, h, E, (const double*)estore, s_el, ell, nptr, nidx, Xr,
+                                          out, rowmap);
   else
-    k_features<false><<<nb, WG, 0, st>>>(mv, xt, x0, h, E, mu, lam, model, ell, nptr, nidx, Xr, out, rowmap);
+    k_features<float><<<nb, WG, 0, st>>>(mv, xt, x0, h, E, (const float*)estore, s_el, ell, nptr, nidx, Xr,
+                                         out, rowmap);
 }
 
 // Training targets (x_new - x_tilde) / ell of the free vertices, caller-order
@@ -595,13 +594,13 @@ void launch_targets(const MeshView& mv, const double* xn, const double* xt, doub
   k_targets<<<(mv.nf + WG - 1) / WG, WG, 0, st>>>(mv, xn, xt, ell, rowmap, T);
 }
 
-void launch_proposal(int n, int nf, const double* xt, const float* delta, double ell, double* xp,
-                     hipStream_t st) {
-  k_proposal<<<(n + WG - 1) / WG, WG, 0, st>>>(n, nf, xt, delta, ell, xp);
+void launch_proposal(int n, int nf, const double* xt, const double* corr, const float* delta, double ell,
+                     double ds, double* xp, hipStream_t st) {
+  k_proposal<<<(n + WG - 1) / WG, WG, 0, st>>>(n, nf, xt, corr, delta, ell, ds, xp);
 }
 
 // ---- warm start of a batch (all meshes per launch, no host round trip) ------
-template <bool FCR>
+template <typename T>
 __global__ void __launch_bounds__(WG) kb_features(const BatchItem* __restrict__ items,
                                                   const BatchCtl* __restrict__ ctl,
                                                   const int* __restrict__ boff, int nmesh,
@@ -611,15 +610,15 @@ __global__ void __launch_bounds__(WG) kb_features(const BatchItem* __restrict__ 
   const BatchItem& it = items[mi];
   const MeshView mv = it.mv;
   const int j = (blockIdx.x - boff[mi]) * (WG / FEAT_G) + threadIdx.x / FEAT_G;
-  features_group<FEAT_G, FCR>(mv, j, threadIdx.x % FEAT_G, it.x, it.x0, sqrt(it.mat.s_el), it.youngs, it.mat.mu,
-                         it.mat.lam, it.mat.model, it.ell, it.nptr, it.nidx, it.Xr,
-                         feat + (size_t)(it.feat_off + (j < mv.nf ? j : 0)) * MLP_IN);
+  features_group<FEAT_G, T>(mv, j, threadIdx.x % FEAT_G, it.x, it.x0, sqrt(it.mat.s_el), it.youngs,
+                            (const T*)it.estore, it.mat.s_el, it.ell, it.nptr, it.nidx, it.Xr,
+                            feat + (size_t)(it.feat_off + (j < mv.nf ? j : 0)) * MLP_IN);
 }
 
 __global__ void __launch_bounds__(WG) kb_proposal(const BatchItem* __restrict__ items,
                                                   const BatchCtl* __restrict__ ctl,
                                                   const int* __restrict__ boff, int nmesh,
-                                                  const float* __restrict__ delta) {
+                                                  const float* __restrict__ delta, double ds) {
   const int mi = block_mesh(boff, nmesh, blockIdx.x);
   if (!ctl[mi].active) return;
   const BatchItem& it = items[mi];
@@ -628,14 +627,18 @@ __global__ void __launch_bounds__(WG) kb_proposal(const BatchItem* __restrict__ 
   if (v >= n) return;
 #pragma unroll
   for (int c = 0; c < 3; ++c)
-    it.xtrial[c * n + v] = it.x[c * n + v] +
-        (v < nf ? it.ell * (double)delta[(size_t)(it.feat_off + v) * MLP_NOUT + c] : 0.0);
+    it.xtrial[c * n + v] = it.xt[c * n + v] +
+        (v < nf ? it.mv.corr[c * n + v] +
+                      (ds != 0.0 ? ds * it.ell * (double)delta[(size_t)(it.feat_off + v) * MLP_NOUT + c] : 0.0)
+                : 0.0);
 }
 
 // Learned warm start of every mesh of the batch: features, the network, the
-// proposal, then its energy with the accept rule (it replaces the predictor
-// only at a lower step energy) and, where accepted, its gradient and
-// residual test.
+// proposal x~ + c + l Delta, then its energy with the accept rule (it
+// replaces the predictor only at a lower step energy); then the previous
+// correction alone, x~ + c, which replaces the start only below the energy
+// of the start so far; where either was accepted, the gradient and residual
+// test.
 void batch_warm_start(BatchPlan* p, const MlpState& net, float* feat, float* delta, int rows,
                       hipStream_t s) {
   const BatchGrid g = batch_grid(p);
@@ -643,15 +646,20 @@ void batch_warm_start(BatchPlan* p, const MlpState& net, float* feat, float* del
   BatchCtl* ctl = batch_ctl_dev(p);
   if (g.pred_blocks == 0) return;
   if (g.feat_blocks > 0) {
-    if (g.any_fcr)
-      kb_features<true><<<g.feat_blocks, WG, 0, s>>>(items, ctl, g.feat_off, g.nmesh, feat);
+    // element Hessians at the predictor: the features' diagonal blocks (the
+    // first iteration evaluates them again at its start)
+    batch_elem_hess_x(p, s);
+    if (g.prec == 0)
+      kb_features<double><<<g.feat_blocks, WG, 0, s>>>(items, ctl, g.feat_off, g.nmesh, feat);
     else
-      kb_features<false><<<g.feat_blocks, WG, 0, s>>>(items, ctl, g.feat_off, g.nmesh, feat);
+      kb_features<float><<<g.feat_blocks, WG, 0, s>>>(items, ctl, g.feat_off, g.nmesh, feat);
   }
   mlp_forward(net, feat, rows, delta, s);
-  kb_proposal<<<g.pred_blocks, WG, 0, s>>>(items, ctl, g.pred_off, g.nmesh, delta);
+  kb_proposal<<<g.pred_blocks, WG, 0, s>>>(items, ctl, g.pred_off, g.nmesh, delta, 1.0);
   if (!g.line_search) batch_energy_x(p, s);   // with line search batch_begin computed it
   batch_energy_trial(p, s, 3);     // E(proposal), then the accept rule
+  kb_proposal<<<g.pred_blocks, WG, 0, s>>>(items, ctl, g.pred_off, g.nmesh, delta, 0.0);
+  batch_energy_trial(p, s, 5);     // E(x~ + c) against the start so far
   // gradient and residual test at an accepted proposal; a rejected one
   // leaves x, g and |g| at the predictor (r = 1 from the step start)
   batch_gradient_x(p, s, 1, 4);

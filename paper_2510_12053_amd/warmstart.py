@@ -36,8 +36,9 @@ def generate(ctx, scenes, steps, dev, tol=1e-6, precision=cg.FP64, corotate=1):
     scenes twist, and a rest-frame basis needs hundreds of iterations per
     step there, while the step's solution is the same); record for every
     free vertex of every step the features at the predictor and the target
-    (x* - x~)/l.  Returns (X (N,16) float32, T (N,3) float32, iterations per
-    step)."""
+    (x* - x_base)/l, x_base the predictor plus the mesh's previous step
+    correction (the base of the warm start's proposal).  Returns (X (N,16)
+    float32, T (N,3) float32, iterations per step)."""
     import torch
     ms = _upload(ctx, scenes, dev)
     rows = sum(m["nf"] for m in ms)
@@ -49,17 +50,17 @@ def generate(ctx, scenes, steps, dev, tol=1e-6, precision=cg.FP64, corotate=1):
     r0 = 0
     for t in range(1, steps + 1):
         bcs = [torch.tensor(m["s"].targets(t), dtype=torch.float64, device=dev) for m in ms]
-        xts, offs = [], []
+        bases, offs = [], []
         for m, bc in zip(ms, bcs):
             _, xt, _ = cg.cc_mlp_features(ctx, m["mid"], m["x"], m["v"], bc, m["s"].dt, m["nf"],
                                           out=X[r0:r0 + m["nf"]])
-            xts.append(xt)
+            bases.append(xt)
             offs.append(r0)
             r0 += m["nf"]
         _, its, _, _ = cg.cc_step_batch(ctx, [m["mid"] for m in ms], [m["x"] for m in ms],
                                         [m["v"] for m in ms], bcs, ms[0]["s"].dt, par, tol, gravity=grav)
         iters.extend(int(i) for i in its)
-        for m, xt, o in zip(ms, xts, offs):
+        for m, xt, o in zip(ms, bases, offs):
             cg.cc_mlp_targets(ctx, m["mid"], m["x"], xt, m["nf"], out=T[o:o + m["nf"]])
     return X, T, iters
 

@@ -156,7 +156,7 @@ def test_random_network_is_rejected_and_step_unchanged(cg, ctx):
         par = cg.cc_params_default(warm_start=warm, gravity=s.gravity)
         st, it, rg = cg.cc_step(ctx, mid, xg, vg, None, s.dt, par, 1e-8)
         res[warm] = (it, xg.cpu().numpy(), cg.cc_step_info(ctx, mid)["warm_accepted"])
-    assert res[1][2] is False
+    assert res[1][2] == 0
     assert res[0][0] == res[1][0] and np.array_equal(res[0][1], res[1][1])
 
 
@@ -176,6 +176,7 @@ def test_warm_step_matches_oracle(cg, ctx, trained):
     theta = _oracle_bf16_params(trained["params"])
     accepted = []
     compared = 0
+    corr = np.zeros_like(x)          # the previous step's correction x_end - x~
     for t in range(1, 4):
         tg = s.targets(t)
         par = cg.cc_params_default(warm_start=1, gravity=s.gravity, max_iters=200)
@@ -186,8 +187,11 @@ def test_warm_step_matches_oracle(cg, ctx, trained):
         Xn = np.zeros((f.shape[0], 32))
         Xn[:, :16] = bf16((f - trained["mean"]) * trained["istd"])
         Y, _ = M.forward(theta, Xn)
-        prop = M.proposal(p, xh, Y, ell)
-        x, v, res, acc_o = step(p, x, v, tg, Bs, op, 1e-8, proposal=prop)
+        prop = M.proposal(p, xh, Y, ell, corr)
+        base = M.proposal(p, xh, 0.0 * Y, ell, corr)
+        x, v, res, acc_o = step(p, x, v, tg, Bs, op, 1e-8, proposal=[prop, base])
+        corr = x - xh
+        corr[p.fixed] = 0.0
         accepted.append(acc)
         if acc == acc_o:
             xr = xg.cpu().numpy()
@@ -215,7 +219,7 @@ def test_trained_network_gain_on_held_out(cg, ctx, trained):
     near-Newton from the predictor, and this small network trained on 36
     steps does not move the start closer to the solution."""
     cg.cc_mlp_set(ctx, trained["params"], trained["mean"], trained["istd"])
-    ratios, it_plain, it_warm, accepted = [], [], [], []
+    ratios, base_ratios, it_plain, it_warm, accepted = [], [], [], [], []
     for seed in (2001, 2002):
         s = warm_start_train_scene(seed)
         nf = int((~s.fixed.astype(bool)).sum())
@@ -225,14 +229,16 @@ def test_trained_network_gain_on_held_out(cg, ctx, trained):
             mid = cg.cc_mesh_upload(ctx, s.X, s.elems, s.fixed, s.E, s.nu, s.rho)
             cg.cc_subspace_build(ctx, mid, 0, s.dt, False)
             mids.append(mid)
+        p = Problem.from_scene(s)
         x, v = s.initial_state()
         xg, vg = torch.tensor(x, device=DEV), torch.tensor(v, device=DEV)
         for t in range(1, 6):
             tg = torch.tensor(s.targets(t), device=DEV)
-            feat, xt, ell = cg.cc_mlp_features(ctx, mids[0], xg, vg, tg, s.dt, nf)
+            xpred = torch.tensor(predictor(p, xg.cpu().numpy(), vg.cpu().numpy(), s.targets(t)), device=DEV)
+            feat, xbase, ell = cg.cc_mlp_features(ctx, mids[1], xg, vg, tg, s.dt, nf)
             delta = cg.cc_mlp_forward(ctx, feat)[:, :3].double()
-            xprop = xt.clone()
-            xprop[free] = xt[free] + ell * delta
+            xprop = xbase.clone()
+            xprop[free] = xbase[free] + ell * delta
             xw, vw = xg.clone(), vg.clone()
             par0 = cg.cc_params_default(warm_start=0, gravity=s.gravity, max_iters=10000)
             par1 = cg.cc_params_default(warm_start=1, gravity=s.gravity, max_iters=10000)
@@ -240,12 +246,15 @@ def test_trained_network_gain_on_held_out(cg, ctx, trained):
             st1, i1, _ = cg.cc_step(ctx, mids[1], xw, vw, tg, s.dt, par1, 1e-6)
             assert st0 == cg.CC_OK and st1 == cg.CC_OK
             xs = xg[free]
-            ratios.append(float(torch.linalg.norm(xprop[free] - xs) / torch.linalg.norm(xt[free] - xs)))
+            den = torch.linalg.norm(xpred[free] - xs)
+            ratios.append(float(torch.linalg.norm(xprop[free] - xs) / den))
+            base_ratios.append(float(torch.linalg.norm(xbase[free] - xs) / den))
             it_plain.append(i0)
             it_warm.append(i1)
-            accepted.append(cg.cc_step_info(ctx, mids[1])["warm_accepted"])
+            accepted.append(int(cg.cc_step_info(ctx, mids[1])["warm_accepted"] != 0))
     ratios = np.array(ratios)
-    print(f"\nheld-out steps {len(ratios)}: |x_prop - x*| / |x_pred - x*| median {np.median(ratios):.3f}, "
+    print(f"\nheld-out steps {len(ratios)}: |x_prop - x*| / |x_pred - x*| median {np.median(ratios):.3f} "
+          f"(base x~ + c: {np.median(base_ratios):.3f}), "
           f"iterations plain {np.mean(it_plain):.2f} warm {np.mean(it_warm):.2f}, "
           f"accepted {sum(accepted)}/{len(accepted)}")
     assert np.all(np.isfinite(ratios)) and sum(accepted) >= 1

@@ -69,3 +69,19 @@ def test_features_at_rest_and_affine():
     p.h = 1e-9
     f, _ = M.features(p, p.X, p.X)
     assert np.allclose(f[:, 6:12], [1, 0, 0, 1, 0, 1], atol=1e-9)
+
+
+def test_proposal_adds_previous_correction_on_free_vertices():
+    """x_p = x~ + c + l Delta on free vertices, x~ on Dirichlet ones."""
+    from ccscenes import tet_bar
+    from oracle.fem import Problem
+    s = tet_bar(5, 3, 3)
+    p = Problem.from_scene(s)
+    rng = np.random.default_rng(2)
+    xt = s.X + 0.01 * rng.normal(size=s.X.shape)
+    corr = rng.normal(size=s.X.shape)
+    Delta = rng.normal(size=(p.free.size, 16))
+    xp = M.proposal(p, xt, Delta, 0.5, corr)
+    np.testing.assert_array_equal(xp[p.fixed], xt[p.fixed])
+    np.testing.assert_allclose(xp[p.free], xt[p.free] + corr[p.free] + 0.5 * Delta[:, :3], rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(M.proposal(p, xt, Delta, 0.5), M.proposal(p, xt, Delta, 0.5, np.zeros_like(xt)))

@@ -5,7 +5,7 @@ from ccscenes import tet_bar
 from oracle import solvers as S
 from oracle.basis import exact_basis
 from oracle.fem import Problem
-from oracle.timestep import newton_step, step
+from oracle.timestep import newton_step, predictor, step
 
 
 def _free_body(E=1e5, grav=(0.0, -9.81, 0.0)):
@@ -51,6 +51,14 @@ def test_warm_start_acceptance_rule():
     bad = p.X + 0.3 * np.random.default_rng(0).normal(size=p.X.shape)
     _, _, r2, acc2 = step(p, x, v, s.targets(1), B, prm, 1e-8, proposal=bad)
     assert not acc2 and r2.iters == r0.iters
+    # several proposals: the start is the one of least energy below the
+    # predictor's, reported by its 1-based position
+    xh = predictor(p, x, v, s.targets(1))
+    mid = 0.5 * (xh + xs)                  # between the predictor and the solution: E in between
+    assert p.energy(xs) < p.energy(mid) < p.energy(xh)
+    for props, want in (([bad, mid, xs], 3), ([xs, mid], 1), ([bad, mid], 2), ([bad], 0)):
+        _, _, _, acc = step(p, x, v, s.targets(1), B, prm, 1e-8, proposal=props)
+        assert acc == want, (want, acc)
 
 
 def test_load_norm_closed_form():

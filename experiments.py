@@ -198,7 +198,7 @@ def warm_start_beam(cg, ctx, dev, seeds, steps, tol=1e-6):
             par = cg.cc_params_default(method=cg.METHOD_CC, sweep=cg.SWEEP_JACOBI, precision=cg.FP32_MIXED,
                                        line_search=1, max_iters=WARM_MAX_ITERS, gravity=s.gravity,
                                        warm_start=warm, corotate=1)
-            its, acc, ms, bad = [], 0, [], 0
+            its, acc, acc_net, ms, bad = [], 0, 0, [], 0
             for t in range(1, steps + 1):
                 bc = torch.tensor(s.targets(t), dtype=torch.float64, device=dev)
                 torch.cuda.synchronize()
@@ -208,16 +208,19 @@ def warm_start_beam(cg, ctx, dev, seeds, steps, tol=1e-6):
                 ms.append((time.perf_counter() - t0) * 1e3)
                 its.append(int(it))
                 bad += int(st != cg.CC_OK)
-                acc += int(cg.cc_step_info(ctx, mid)["warm_accepted"])
+                tag = int(cg.cc_step_info(ctx, mid)["warm_accepted"])   # 1 network, 2 correction alone
+                acc += int(tag != 0)
+                acc_net += int(tag == 1)
                 print(f"  seed {sd} {name} step {t}: {it} iterations, {ms[-1]:.1f} ms, status {st}", flush=True)
             row[name] = {"iters_mean": round(float(np.mean(its)), 3), "iters_median": float(np.median(its)),
                          "ms_per_step_median": round(float(np.median(ms)), 2),
                          "ms_per_step_mean": round(float(np.mean(ms)), 2), "not_ok": bad,
-                         "accepted": acc, "steps": steps, "iters": its}
+                         "accepted": acc, "network_taken": acc_net, "steps": steps, "iters": its}
         rows.append(row)
         print(f"warmstart seed {sd}: E {s.E:.3g}, plain {row['plain']['iters_mean']} it "
               f"{row['plain']['ms_per_step_median']} ms, learned {row['learned']['iters_mean']} it "
-              f"{row['learned']['ms_per_step_median']} ms, accepted {row['learned']['accepted']}/{steps}",
+              f"{row['learned']['ms_per_step_median']} ms, accepted {row['learned']['accepted']}/{steps} "
+              f"(network {row['learned']['network_taken']})",
               flush=True)
     print("| seed | E | plain: iterations (mean) | plain: ms/step (median) | learned: iterations (mean) "
           "| learned: ms/step (median) | proposals taken |")
@@ -225,7 +228,7 @@ def warm_start_beam(cg, ctx, dev, seeds, steps, tol=1e-6):
     for r in rows:
         print(f"| {r['seed']} | {r['E']:.3g} | {r['plain']['iters_mean']} | {r['plain']['ms_per_step_median']} | "
               f"{r['learned']['iters_mean']} | {r['learned']['ms_per_step_median']} | "
-              f"{r['learned']['accepted']}/{steps} |")
+              f"{r['learned']['accepted']}/{steps} ({r['learned']['network_taken']} the network's) |")
     print(json.dumps({"experiment": "warm_start_held_out_beam81x21x21", "tol": tol, "precision": "fp32",
                       "basis": "exact, corotated", "rows": rows}), flush=True)
 

@@ -74,7 +74,12 @@ typedef struct {
   int32_t hess_refresh;   /* CC_HESS_*                                                 */
   int32_t precision;      /* CC_FP64 / CC_FP32_MIXED                                   */
   int32_t line_search;    /* 0 off (Algorithm 1), 1 global backtracking along the
-                             iteration's displacement (Results, basis-quality study)   */
+                             iteration's displacement (Results, basis-quality study):
+                             alpha halved while E rises above E + 1e-12 max(|E|, 1);
+                             when max_halvings do not find a step, a Jacobi sweep of
+                             the same method (coloured sweeps of CC or JGS2), then a
+                             coordinate-descent sweep, each with the same search;
+                             none found: CC_STALLED                                    */
   int32_t max_iters;      /* iteration cap (>= 0)                                      */
   int32_t max_halvings;   /* line-search halvings (>= 0)                               */
   int32_t quasistatic;    /* 1: E = Psi - m g.x (no inertia, no h^2)                   */
@@ -88,7 +93,7 @@ typedef struct {
 } cc_params;
 
 /* Fill *p with defaults: CC, Jacobi, per-colour Hessians, FP64, line search on,
-   10000 iterations, 30 halvings, dynamic, no warm start, gravity 0, no
+   10000 iterations, 20 halvings, dynamic, no warm start, gravity 0, no
    corotation. */
 void cc_params_default(cc_params* p);
 

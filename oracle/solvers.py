@@ -48,8 +48,13 @@ Readings taken where the paper is silent:
 * global backtracking line search along the sweep's displacement d (Results,
   Sensitivity to basis quality): alpha = 1, halved while
   E(x + alpha d) > E(x) + tau with tau = 1e-12 max(|E(x)|, 1), at most
-  max_halvings times; on failure one coordinate-descent sweep with the same
-  search; on failure again the solve stops with status STALLED;
+  max_halvings (20: alpha >= 2^-20, below which a step moves x by less than
+  the rounding of its coordinates' changes) times; on failure, for a
+  coloured sweep of CC or JGS2, one Jacobi sweep of the same method with the
+  same search (a coloured sweep's displacement can stop being a descent
+  direction where the Jacobi one still is), then one coordinate-descent
+  sweep with the same search; on failure again the solve stops with status
+  STALLED;
 * termination: r_k = |g(x_k)|_2 / max(|g(x^_0)|_2, |f_g|_2) <= tol, where
   x^_0 is the inertial predictor with boundary targets (dynamic) or the
   initial guess (quasistatic), and f_g = s_el m_i grav is the gravity load's
@@ -69,7 +74,7 @@ coupled block system; CD equals textbook block Jacobi / block Gauss-Seidel;
 the line search never raises E by more than tau; converged CC states equal
 Newton's minimiser on small meshes.
 """
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 import scipy.sparse as sp
@@ -93,7 +98,7 @@ class Params:
     hess_refresh: int = HESS_COLOUR
     line_search: bool = True
     max_iters: int = 10000
-    max_halvings: int = 30
+    max_halvings: int = 20
     corotate: bool = False      # rotate the basis blocks by per-vertex rotations
 
 
@@ -307,12 +312,17 @@ def solve(prob, x0, basis, params, tol, colours=None, x_hat0=None, record=False)
         if params.line_search:
             ok, alpha, _ = _line_search(prob, x, x_new - x, params)
             if not ok:
-                x_cd, _ = sweep(prob, x, Umat, cf, params, method=CD)
-                ok, alpha, _ = _line_search(prob, x, x_cd - x, params)
+                tries = [(replace(params, sweep=JACOBI), None)] if params.sweep == GS and params.method != CD else []
+                tries.append((params, CD))
+                for prm_fb, meth in tries:
+                    x_fb, _ = sweep(prob, x, Umat, cf, prm_fb, method=meth)
+                    ok, alpha, _ = _line_search(prob, x, x_fb - x, params)
+                    if ok:
+                        x_new = x_fb
+                        break
                 if not ok:
                     res.status = STALLED
                     break
-                x_new = x_cd
             x = x + alpha * (x_new - x)
         else:
             x = x_new

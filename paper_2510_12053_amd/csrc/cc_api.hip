@@ -1157,9 +1157,11 @@ struct Stepper {
     ctx->timed(CC_K_CC_UPDATE, [&] { cc::launch_cc_update(mv, p.precision, method, v0, v1, M.KL, M.g, out, acc, s); });
   }
   // One sweep from x into out (x unchanged).  method as requested.
-  void sweep(const double* x, double* out, int method) {
+  // sweep_kind: CC_SWEEP_* to override p.sweep (the line search's Jacobi
+  // fallback of a coloured sweep), -1 for p.sweep
+  void sweep(const double* x, double* out, int method, int sweep_kind = -1) {
     const int nd = M.D * M.n;
-    if (p.sweep == CC_SWEEP_JACOBI) {
+    if ((sweep_kind < 0 ? p.sweep : sweep_kind) == CC_SWEEP_JACOBI) {
       hessian(x);
       gradient_only(x);
       if (!prep_direction(method, M.dvec)) update(method, 0, M.nf, M.dvec, 0);
@@ -1214,7 +1216,7 @@ void cc_params_default(cc_params* p) {
   p->precision = CC_FP64;
   p->line_search = 1;
   p->max_iters = 10000;
-  p->max_halvings = 30;
+  p->max_halvings = 20;
 }
 
 cc_status cc_create(int32_t device, void* hip_stream, cc_ctx** out) {
@@ -1594,16 +1596,22 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
             Et = S.energy(M.xtrial);
           }
           if (!(Et <= Ecur + tau)) {
-            S.sweep(M.x, M.xtrial, CC_METHOD_CD);
-            cc::launch_axpy(nd, M.xtrial, M.x, -1.0, M.dvec, s);
-            alpha = 1.0;
-            Et = S.energy(M.xtrial);
-            hv = 0;
-            while (!(Et <= Ecur + tau) && hv < p.max_halvings) {
-              alpha *= 0.5;
-              ++hv;
-              cc::launch_axpy(nd, M.x, M.dvec, alpha, M.xtrial, s);
+            // fallbacks: a Jacobi sweep of the same method (coloured sweeps
+            // of CC or JGS2), then coordinate descent, each with the search
+            const int nfb = (p.sweep != CC_SWEEP_JACOBI && p.method != CC_METHOD_CD) ? 2 : 1;
+            for (int f = 0; f < nfb && !(Et <= Ecur + tau); ++f) {
+              const bool jac = nfb == 2 && f == 0;
+              S.sweep(M.x, M.xtrial, jac ? p.method : CC_METHOD_CD, jac ? CC_SWEEP_JACOBI : -1);
+              cc::launch_axpy(nd, M.xtrial, M.x, -1.0, M.dvec, s);
+              alpha = 1.0;
               Et = S.energy(M.xtrial);
+              hv = 0;
+              while (!(Et <= Ecur + tau) && hv < p.max_halvings) {
+                alpha *= 0.5;
+                ++hv;
+                cc::launch_axpy(nd, M.x, M.dvec, alpha, M.xtrial, s);
+                Et = S.energy(M.xtrial);
+              }
             }
             if (!(Et <= Ecur + tau)) {
               result = CC_STALLED;
@@ -1827,16 +1835,25 @@ static void batch_host_cd_fallback(cc_ctx* ctx, Mesh& M, cc::BatchItem& it, cc::
   Stepper S{ctx, M, M.view(), it.mat, p, s};
   const int nd = M.D * M.n;
   const double tau = 1e-12 * std::max(std::fabs(c.E_cur), 1.0);
-  S.sweep(M.x, M.xtrial, CC_METHOD_CD);
-  cc::launch_axpy(nd, M.xtrial, M.x, -1.0, M.dvec, s);
-  double alpha = 1.0;
-  double Et = S.energy(M.xtrial);
+  // a Jacobi sweep of the same method (coloured sweeps of CC or JGS2), then
+  // coordinate descent, each with the search
+  const int nfb = (p.sweep != CC_SWEEP_JACOBI && p.method != CC_METHOD_CD) ? 2 : 1;
+  double alpha = 1.0, Et = 0.0;
   int hv = 0;
-  while (!(Et <= c.E_cur + tau) && hv < p.max_halvings) {
-    alpha *= 0.5;
-    ++hv;
-    cc::launch_axpy(nd, M.x, M.dvec, alpha, M.xtrial, s);
+  for (int f = 0; f < nfb; ++f) {
+    const bool jac = nfb == 2 && f == 0;
+    S.sweep(M.x, M.xtrial, jac ? p.method : CC_METHOD_CD, jac ? CC_SWEEP_JACOBI : -1);
+    cc::launch_axpy(nd, M.xtrial, M.x, -1.0, M.dvec, s);
+    alpha = 1.0;
     Et = S.energy(M.xtrial);
+    hv = 0;
+    while (!(Et <= c.E_cur + tau) && hv < p.max_halvings) {
+      alpha *= 0.5;
+      ++hv;
+      cc::launch_axpy(nd, M.x, M.dvec, alpha, M.xtrial, s);
+      Et = S.energy(M.xtrial);
+    }
+    if (Et <= c.E_cur + tau) break;
   }
   if (!(Et <= c.E_cur + tau)) {
     c.status = CC_STALLED;

@@ -48,7 +48,7 @@ def test_params_default(lib):
     import paper_2510_12053_amd.ccgpu as cg
     p = cg.cc_params_default()
     assert (p.method, p.sweep, p.precision, p.line_search, p.max_iters, p.max_halvings,
-            p.corotate) == (cg.METHOD_CC, cg.SWEEP_JACOBI, cg.FP64, 1, 10000, 30, 0)
+            p.corotate) == (cg.METHOD_CC, cg.SWEEP_JACOBI, cg.FP64, 1, 10000, 20, 0)
     # the binding's struct has the size of the C struct (the header's field list)
     assert ctypes.sizeof(cg.cc_params) == 4 * 9 + 4 + 8 * 3 + 4 + 4
 

@@ -253,6 +253,52 @@ def test_coloured_sweep_line_search(cg, ctx, prec, E):
             assert _rel(xg, xo, s.X) <= 1e-4
 
 
+@pytest.fixture(scope="module")
+def bar37_gs_oracle():
+    """Bar 37 of the 64-bar batch (34x6x6, E = 2.2e6), first step, corotated
+    coloured GS with the search and its Jacobi fallback (oracle, float64)."""
+    s = batch_bars(64)[37]
+    p = Problem.from_scene(s)
+    B = exact_basis(p)
+    col = greedy_colour(s.n, s.elems, s.fixed)
+    x, v = s.initial_state()
+    op = S.Params(method=S.CC, sweep=S.GS, line_search=True, max_iters=60, corotate=True)
+    xo, vo, res, _ = step(p, x, v, s.targets(1), B, op, 1e-6, colours=col)
+    return dict(s=s, p=p, B=B, xo=xo, res=res)
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_coloured_sweep_jacobi_fallback(cg, ctx, bar37_gs_oracle, batched):
+    """A coloured sweep whose displacement stops being a descent direction
+    (the first GS step of bar 37 rises to r = 9.5; without a fallback the
+    search then accepts only vanishing steps): the search's Jacobi fallback
+    converges in the oracle's 4 iterations; single mesh in float64 (equal
+    iterations, 1e-6) and batched in float32-mixed (+-2, 1e-4), both through
+    their own fallback code."""
+    d = bar37_gs_oracle
+    s, res = d["s"], d["res"]
+    assert res.status == S.OK and res.iters <= 6
+    mid = cg.cc_mesh_upload(ctx, s.X, s.elems, s.fixed, s.E, s.nu, s.rho)
+    cg.cc_subspace_build(ctx, mid, 0, s.dt, False)
+    x, v = s.initial_state()
+    xg, vg = _t(x), _t(v)
+    prec = 1 if batched else 0
+    par = cg.cc_params_default(method=cg.METHOD_CC, sweep=cg.SWEEP_COLORED_GS, line_search=1, precision=prec,
+                               max_iters=60, gravity=s.gravity, corotate=1)
+    if batched:
+        _, its, rgs, sts = cg.cc_step_batch(ctx, [mid], [xg], [vg], [_t(s.targets(1))], s.dt, par, 1e-6,
+                                            gravity=np.stack([s.gravity]))
+        st, it, rg = int(sts[0]), int(its[0]), float(rgs[0])
+    else:
+        st, it, rg = cg.cc_step(ctx, mid, xg, vg, _t(s.targets(1)), s.dt, par, 1e-6)
+    assert st == cg.CC_OK and rg <= 1e-6, (st, it, rg)
+    xr = xg.cpu().numpy()
+    if batched:
+        assert abs(it - res.iters) <= 2 and _rel(xr, d["xo"], s.X) <= 1e-4
+    else:
+        assert it == res.iters and _rel(xr, d["xo"], s.X) <= 1e-6
+
+
 @pytest.mark.parametrize("kind", ["exact", "R2"])
 def test_coloured_sweep_fp32(cg, ctx, kind):
     """FP32-mixed coloured sweeps (per-colour Hessians, no search) against the

@@ -76,10 +76,12 @@ typedef struct {
   int32_t line_search;    /* 0 off (Algorithm 1), 1 global backtracking along the
                              iteration's displacement (Results, basis-quality study):
                              alpha halved while E rises above E + 1e-12 max(|E|, 1);
-                             when max_halvings do not find a step, a Jacobi sweep of
-                             the same method (coloured sweeps of CC or JGS2), then a
-                             coordinate-descent sweep, each with the same search;
-                             none found: CC_STALLED                                    */
+                             when max_halvings do not find a step, a coordinate-
+                             descent sweep with the same search; none found:
+                             CC_STALLED.  A coloured sweep of CC or JGS2 is taken at
+                             its full step only: if that raises E, the iteration
+                             takes a Jacobi sweep of the same method with the
+                             search, then the coordinate-descent fallback            */
   int32_t max_iters;      /* iteration cap (>= 0)                                      */
   int32_t max_halvings;   /* line-search halvings (>= 0)                               */
   int32_t quasistatic;    /* 1: E = Psi - m g.x (no inertia, no h^2)                   */
@@ -254,10 +256,14 @@ cc_status cc_autotune_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, con
 /* Extra results of the last cc_step on a mesh (host outputs, any may be NULL):
    final step energy, the paper's normalised residual |g|/(V n E) (divided by
    h when dynamic), fallback counters (Ht or empty support, Schur, H_ii),
-   line-search halvings taken, and which warm-start proposal was accepted
-   (0 none, 1 the network's x~ + c + l Delta, 2 the correction alone x~ + c). */
+   line-search halvings taken, which warm-start proposal was accepted
+   (0 none, 1 the network's x~ + c + l Delta, 2 the correction alone x~ + c),
+   and the iterations whose displacement came from a fallback sweep (Jacobi
+   or coordinate descent, see line_search).  Filled by cc_step and by
+   cc_step_batch for each of its meshes. */
 cc_status cc_step_info(cc_ctx* ctx, int32_t mesh_id, double* energy, double* paper_residual,
-                       int64_t* fallbacks3, int64_t* halvings, int32_t* warm_accepted);
+                       int64_t* fallbacks3, int64_t* halvings, int32_t* warm_accepted,
+                       int64_t* sweep_fallbacks);
 
 /* ---- parity probes: single kernels on caller device buffers ------------- */
 

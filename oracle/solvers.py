@@ -49,12 +49,17 @@ Readings taken where the paper is silent:
   Sensitivity to basis quality): alpha = 1, halved while
   E(x + alpha d) > E(x) + tau with tau = 1e-12 max(|E(x)|, 1), at most
   max_halvings (20: alpha >= 2^-20, below which a step moves x by less than
-  the rounding of its coordinates' changes) times; on failure, for a
-  coloured sweep of CC or JGS2, one Jacobi sweep of the same method with the
-  same search (a coloured sweep's displacement can stop being a descent
-  direction where the Jacobi one still is), then one coordinate-descent
-  sweep with the same search; on failure again the solve stops with status
-  STALLED;
+  the rounding of its coordinates' changes) times; on failure, one
+  coordinate-descent sweep with the same search; on failure again the solve
+  stops with status STALLED.  A coloured sweep of CC or JGS2 is taken only
+  at its full step (no halvings): when that raises E by more than tau, the
+  iteration takes a Jacobi sweep of the same method with the search, and
+  then the coordinate-descent fallback.  Each colour's condensed step assumes
+  the colours after it follow through the basis; once the intermediate state
+  is strained, the sweep's displacement can point almost nowhere downhill,
+  and halving it then makes vanishing progress per iteration where the
+  Jacobi (near-Newton) step does not.  SolveResult.sweep_fallbacks counts
+  the iterations whose displacement came from a fallback sweep;
 * termination: r_k = |g(x_k)|_2 / max(|g(x^_0)|_2, |f_g|_2) <= tol, where
   x^_0 is the inertial predictor with boundary targets (dynamic) or the
   initial guess (quasistatic), and f_g = s_el m_i grav is the gravity load's
@@ -110,6 +115,7 @@ class SolveResult:
     status: int
     history: list = field(default_factory=list)   # per iteration (r, E, alpha, paper_measure)
     fallbacks: np.ndarray = field(default_factory=lambda: np.zeros(3, dtype=np.int64))
+    sweep_fallbacks: int = 0   # iterations that took a Jacobi or CD fallback sweep
 
 
 def chol_solve(M, B):
@@ -276,13 +282,13 @@ def paper_measure(prob, g):
     return val if prob.quasistatic else val / prob.h
 
 
-def _line_search(prob, x, d, params):
+def _line_search(prob, x, d, max_halvings):
     E0 = prob.energy(x)
     tau = 1e-12 * max(abs(E0), 1.0)
     alpha = 1.0
     Ek = prob.energy(x + d)
     halvings = 0
-    while Ek > E0 + tau and halvings < params.max_halvings:
+    while Ek > E0 + tau and halvings < max_halvings:
         alpha *= 0.5
         Ek = prob.energy(x + alpha * d)
         halvings += 1
@@ -310,15 +316,17 @@ def solve(prob, x0, basis, params, tol, colours=None, x_hat0=None, record=False)
         res.fallbacks += c
         alpha = 1.0
         if params.line_search:
-            ok, alpha, _ = _line_search(prob, x, x_new - x, params)
+            coloured = params.sweep == GS and params.method != CD
+            ok, alpha, _ = _line_search(prob, x, x_new - x, 0 if coloured else params.max_halvings)
             if not ok:
-                tries = [(replace(params, sweep=JACOBI), None)] if params.sweep == GS and params.method != CD else []
+                tries = [(replace(params, sweep=JACOBI), None)] if coloured else []
                 tries.append((params, CD))
                 for prm_fb, meth in tries:
                     x_fb, _ = sweep(prob, x, Umat, cf, prm_fb, method=meth)
-                    ok, alpha, _ = _line_search(prob, x, x_fb - x, params)
+                    ok, alpha, _ = _line_search(prob, x, x_fb - x, params.max_halvings)
                     if ok:
                         x_new = x_fb
+                        res.sweep_fallbacks += 1
                         break
                 if not ok:
                     res.status = STALLED

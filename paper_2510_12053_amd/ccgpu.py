@@ -72,7 +72,7 @@ def lib():
             "cc_subspace_download": (I32, [P, I32, P, P, P]),
             "cc_subspace_row": (I32, [P, I32, I32, pI64, P, P]),
             "cc_step": (I32, [P, I32, P, P, P, D, ctypes.POINTER(cc_params), D, pI32, pD]),
-            "cc_step_info": (I32, [P, I32, pD, pD, P, pI64, pI32]),
+            "cc_step_info": (I32, [P, I32, pD, pD, P, pI64, pI32, pI64]),
             "cc_probe_element": (I32, [P, I32, P, I32, P, P]),
             "cc_probe_sweep": (I32, [P, I32, P, P, D, ctypes.POINTER(cc_params), pD, P, P]),
             "cc_step_batch": (I32, [P, I32, P, P, P, P, P, D, ctypes.POINTER(cc_params), D, P, P, P]),
@@ -237,10 +237,11 @@ def cc_step_info(ctx, mesh_id):
     fb = np.zeros(3, dtype=np.int64)
     hv = ctypes.c_int64(0)
     wa = ctypes.c_int32(0)
+    sf = ctypes.c_int64(0)
     _check(ctx, lib().cc_step_info(ctx.handle, mesh_id, ctypes.byref(e), ctypes.byref(pr), _ptr(fb),
-                                   ctypes.byref(hv), ctypes.byref(wa)))
+                                   ctypes.byref(hv), ctypes.byref(wa), ctypes.byref(sf)))
     return dict(energy=e.value, paper_residual=pr.value, fallbacks=fb, halvings=hv.value,
-                warm_accepted=int(wa.value))
+                warm_accepted=int(wa.value), sweep_fallbacks=sf.value)
 
 
 def cc_probe_element(ctx, mesh_id, x, precision, n_elems):

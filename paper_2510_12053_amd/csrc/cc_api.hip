@@ -68,7 +68,7 @@ struct Mesh {
   int* bad = nullptr;
   // last-step info
   double last_E = 0, last_paper = 0;
-  long long last_fb[3] = {0, 0, 0}, last_halvings = 0;
+  long long last_fb[3] = {0, 0, 0}, last_halvings = 0, last_sweep_fb = 0;
   int last_warm = 0;
   // warm start: all mesh neighbours of free vertices (internal ids), rest
   // positions (SoA), mean rest edge length, feature and output scratch
@@ -1553,9 +1553,13 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
     const int nd = M.D * M.n;
     double r = 0.0, Ecur = 0.0;
     int k = 0;
-    long long halvings = 0;
+    long long halvings = 0, sweep_fb = 0;
     cc_status result = CC_OK;
     int warm = 0;
+    // a coloured sweep of CC or JGS2 is taken at its full step only; when
+    // that raises E the iteration falls back to a Jacobi sweep
+    const bool coloured = p.sweep != CC_SWEEP_JACOBI && p.method != CC_METHOD_CD;
+    const int lim0 = coloured ? 0 : p.max_halvings;
     if (g0 > 0) {
       r = gstart / g0;
       if (p.warm_start) {
@@ -1589,7 +1593,7 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
           cc::launch_axpy(nd, M.xtrial, M.x, -1.0, M.dvec, s);
           double alpha = 1.0, Et = S.energy(M.xtrial);
           int hv = 0;
-          while (!(Et <= Ecur + tau) && hv < p.max_halvings) {
+          while (!(Et <= Ecur + tau) && hv < lim0) {
             alpha *= 0.5;
             ++hv;
             cc::launch_axpy(nd, M.x, M.dvec, alpha, M.xtrial, s);
@@ -1598,7 +1602,7 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
           if (!(Et <= Ecur + tau)) {
             // fallbacks: a Jacobi sweep of the same method (coloured sweeps
             // of CC or JGS2), then coordinate descent, each with the search
-            const int nfb = (p.sweep != CC_SWEEP_JACOBI && p.method != CC_METHOD_CD) ? 2 : 1;
+            const int nfb = coloured ? 2 : 1;
             for (int f = 0; f < nfb && !(Et <= Ecur + tau); ++f) {
               const bool jac = nfb == 2 && f == 0;
               S.sweep(M.x, M.xtrial, jac ? p.method : CC_METHOD_CD, jac ? CC_SWEEP_JACOBI : -1);
@@ -1617,6 +1621,7 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
               result = CC_STALLED;
               break;
             }
+            ++sweep_fb;
           }
           halvings += hv;
           Ecur = Et;
@@ -1635,6 +1640,7 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
     }
     M.last_E = S.energy(M.x);
     M.last_halvings = halvings;
+    M.last_sweep_fb = sweep_fb;
     {
       const double gn = r * g0;
       const double pm = gn / (M.volume * M.n * M.E);
@@ -1654,7 +1660,8 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
 }
 
 cc_status cc_step_info(cc_ctx* ctx, int32_t mesh_id, double* energy, double* paper_residual,
-                       int64_t* fallbacks3, int64_t* halvings, int32_t* warm_accepted) {
+                       int64_t* fallbacks3, int64_t* halvings, int32_t* warm_accepted,
+                       int64_t* sweep_fallbacks) {
   return guarded(ctx, [&]() -> cc_status {
     Mesh& M = get_mesh(ctx, mesh_id);
     if (energy) *energy = M.last_E;
@@ -1662,6 +1669,7 @@ cc_status cc_step_info(cc_ctx* ctx, int32_t mesh_id, double* energy, double* pap
     if (fallbacks3) for (int c = 0; c < 3; ++c) fallbacks3[c] = M.last_fb[c];
     if (halvings) *halvings = M.last_halvings;
     if (warm_accepted) *warm_accepted = M.last_warm;
+    if (sweep_fallbacks) *sweep_fallbacks = M.last_sweep_fb;
     return CC_OK;
   });
 }
@@ -1824,10 +1832,12 @@ static cc::BatchPlan* batch_plan_for(cc_ctx* ctx, const std::vector<Mesh*>& ms, 
   return ctx->plan;
 }
 
-// Coordinate-descent fallback of mesh m of the plan after the batched
-// backtracking rounds exhausted their halvings along the CC direction: a CD
-// sweep from x and a host line search along it, as in the single-mesh path.
-static void batch_host_cd_fallback(cc_ctx* ctx, Mesh& M, cc::BatchItem& it, cc::BatchCtl& c,
+// Fallback sweeps of mesh m of the plan after the batched backtracking
+// rounds exhausted their halvings along the sweep's displacement (a coloured
+// sweep of CC or JGS2 gets none): a Jacobi sweep of the same method for a
+// coloured sweep, then a CD sweep, each from x with a host line search along
+// it, as in the single-mesh path.
+static void batch_host_fallback(cc_ctx* ctx, Mesh& M, cc::BatchItem& it, cc::BatchCtl& c,
                                    const cc_params& p, double tol) {
   hipStream_t s = ctx->stream;
   M.x = it.x;
@@ -1863,6 +1873,7 @@ static void batch_host_cd_fallback(cc_ctx* ctx, Mesh& M, cc::BatchItem& it, cc::
     return;
   }
   M.last_halvings += hv;
+  ++M.last_sweep_fb;
   std::swap(M.x, M.xtrial);
   c.E_cur = Et;
   c.iters += 1;
@@ -1913,6 +1924,7 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
       items[i].xbc = x_bc ? x_bc[i] : nullptr;
       items[i].load = load_norm(M, mat);
       M.last_halvings = 0;          // fallback counters are cleared by batch_begin
+      M.last_sweep_fb = 0;
     }
     cc::BatchItem* items_d = cc::batch_items_dev(plan);
     cc::BatchCtl* ctl_d = cc::batch_ctl_dev(plan);
@@ -1994,13 +2006,17 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
         // round evaluates the next eight halvings of every searching mesh at
         // once and takes the first that does not raise E.  Two rounds are
         // queued per read-back; a mesh that has decided skips the second.
+        // A coloured sweep of CC or JGS2 takes no halvings: its meshes go
+        // straight to the host fallback, which starts with a Jacobi sweep.
+        const bool coloured = p.sweep != CC_SWEEP_JACOBI && p.method != CC_METHOD_CD;
+        const int lim0 = coloured ? 0 : p.max_halvings;
         std::vector<int> was_active(n);
         for (int i = 0; i < n; ++i) {
           was_active[i] = ctl[i].active;
           ctl[i].active = ctl[i].needs_host;
           ctl[i].alpha = 0.5;
           ctl[i].halvings = 1;
-          ctl[i].ls = ctl[i].needs_host && p.max_halvings < 1 ? 2 : 0;
+          ctl[i].ls = ctl[i].needs_host && lim0 < 1 ? 2 : 0;
           if (ctl[i].ls == 2) ctl[i].active = 0;
         }
         push_ctl();
@@ -2009,10 +2025,10 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
           for (auto& c : ctl) searching = searching || c.active;
           if (!searching) break;
           // every round decides a mesh or takes it eight halvings further
-          if (r > p.max_halvings + 1)
+          if (r > lim0 + 1)
             throw ApiError{CC_E_HIP, "batched line search did not finish"};
           for (int q = 0; q < 2; ++q)
-            if (!cc::batch_ls_round(plan, r == 0 && q == 0, p.max_halvings, s))
+            if (!cc::batch_ls_round(plan, r == 0 && q == 0, lim0, s))
               throw ApiError{CC_E_HIP, "no device memory for the batched line search"};
           pull_ctl();
         }
@@ -2028,7 +2044,7 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
           cc::batch_gradient_converge(plan, s);
           pull_ctl();
         }
-        // exhausted halvings: the coordinate-descent fallback on the host,
+        // exhausted halvings: the fallback sweeps on the host,
         // which needs the meshes' current buffer roles from the device
         bool any_cd = false;
         for (int i = 0; i < n; ++i) any_cd = any_cd || (ctl[i].needs_host && ctl[i].ls == 2);
@@ -2038,7 +2054,7 @@ cc_status cc_step_batch(cc_ctx* ctx, int32_t n, const int32_t* mesh_ids, double*
         }
         for (int i = 0; i < n; ++i) {
           if (ctl[i].needs_host && ctl[i].ls == 2) {
-            batch_host_cd_fallback(ctx, *ms[i], items[i], ctl[i], p, tol);
+            batch_host_fallback(ctx, *ms[i], items[i], ctl[i], p, tol);
             HIPC(hipMemcpyAsync(items_d + i, &items[i], sizeof(cc::BatchItem), hipMemcpyHostToDevice, s));
             HIPC(hipStreamSynchronize(s));   // items[i] is pageable host memory
           }

@@ -19,6 +19,10 @@ kernel, and prints a Markdown summary: for every sweep kernel the scaled
 bytes per dispatch beside its algorithmic bytes (bench.kernel_model), and a
 `traffic_json` line for the condensation with the hash of the kernel source it
 was measured on (bench.py reports the traffic only while that hash matches).
+An optional third run of the read-request counters by size adds the fetched
+bytes counted request by request, a check of the copy's factor for each
+kernel (that factor comes from 128-byte requests, which FETCH_SIZE counts as
+64 bytes here).
 
     cd /tmp && export TMPDIR=/tmp          # R: repository root, OUT: an output folder
     timeout -s KILL 240 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/ctr_fetch -o run -- python -u $R/bench_counters.py
@@ -103,8 +107,9 @@ def copy_calibration(dev):
     print("copy done", flush=True)
 
 
-def _per_dispatch(folder, counter):
-    """{kernel key: [bytes per dispatch]} from a counter CSV (KiB -> bytes)."""
+def _per_dispatch(folder, counter, unit=1024.0):
+    """{kernel key: [value per dispatch]} from a counter CSV (KiB -> bytes by
+    default; unit=1 keeps counts)."""
     out = {}
     files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
     if not files:
@@ -118,7 +123,29 @@ def _per_dispatch(folder, counter):
             key = "copy"
         if key is None:
             continue
-        out.setdefault(key, []).append(float(row["Counter_Value"]) * 1024.0)
+        out.setdefault(key, []).append(float(row["Counter_Value"]) * unit)
+    return out
+
+
+REQ_COUNTERS = ("TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum", "TCC_EA0_RDREQ_sum")
+
+
+def request_bytes(req_dir):
+    """{kernel key: (bytes fetched per dispatch counted by request size,
+    share of read requests the three sizes account for)} from a pass of
+    REQ_COUNTERS; for the copy, its COPY_REPS largest dispatches."""
+    c = {n: _per_dispatch(req_dir, n, 1.0) for n in REQ_COUNTERS}
+    out = {}
+    for k, tot in c["TCC_EA0_RDREQ_sum"].items():
+        per = []
+        for i in range(len(tot)):
+            n32, n64, n128 = (c[n].get(k, [0.0] * len(tot))[i] for n in REQ_COUNTERS[:3])
+            per.append((32.0 * n32 + 64.0 * n64 + 128.0 * n128, n32 + n64 + n128, tot[i]))
+        if k == "copy":
+            per = sorted(per)[-COPY_REPS:]
+        byts = sum(p[0] for p in per) / len(per)
+        cover = sum(p[1] for p in per) / max(sum(p[2] for p in per), 1.0)
+        out[k] = (byts, cover)
     return out
 
 
@@ -135,8 +162,9 @@ def algorithmic(workload):
     return tot
 
 
-def summarize(fetch_dir, write_dir, workload):
+def summarize(fetch_dir, write_dir, workload, req_dir=None):
     fe = _per_dispatch(fetch_dir, "FETCH_SIZE")
+    rq = request_bytes(req_dir) if req_dir else None
     wr = _per_dispatch(write_dir, "WRITE_SIZE")
     cf = sorted(fe.get("copy", []))[-COPY_REPS:]
     cw = sorted(wr.get("copy", []))[-COPY_REPS:]
@@ -156,14 +184,32 @@ def summarize(fetch_dir, write_dir, workload):
     print("cd /tmp && export TMPDIR=/tmp")
     print(f"timeout -s KILL 240 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/ctr_fetch_{tag} -o run -- python -u $R/bench_counters.py{flag}")
     print(f"timeout -s KILL 240 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/ctr_write_{tag} -o run -- python -u $R/bench_counters.py{flag}")
-    print(f"python $R/bench_counters.py{flag} --summarize $OUT/ctr_fetch_{tag} $OUT/ctr_write_{tag}")
+    if rq is not None:
+        print(f"timeout -s KILL 240 rocprofv3 --pmc {' '.join(REQ_COUNTERS)} --output-format csv "
+              f"-d $OUT/ctr_req_{tag} -o run -- python -u $R/bench_counters.py{flag}")
+        print(f"python $R/bench_counters.py{flag} --summarize $OUT/ctr_fetch_{tag} $OUT/ctr_write_{tag} "
+              f"$OUT/ctr_req_{tag}")
+    else:
+        print(f"python $R/bench_counters.py{flag} --summarize $OUT/ctr_fetch_{tag} $OUT/ctr_write_{tag}")
     print("```\n")
     print("One line-searched Jacobi iteration per step, so every launch covers the whole workload.  "
           f"Counters are scaled by the calibration copy of {COPY_BYTES >> 20} MiB (known bytes / "
           f"counted bytes): FETCH_SIZE x {sf:.4f}, WRITE_SIZE x {sw:.4f}.  Algorithmic bytes: "
           "`bench.kernel_model` (compulsory bytes of one launch over the workload).\n")
-    print("| kernel | dispatches | fetch (MB) | write (MB) | scaled fetch + write (MB) | algorithmic (MB) | ratio |")
-    print("|---|---|---|---|---|---|---|")
+    if rq is not None:
+        print("The last two columns count the fetched bytes by read-request size instead "
+              "(32 x TCC_EA0_RDREQ_32B + 64 x TCC_EA0_RDREQ_64B + 128 x TCC_EA0_RDREQ_128B, the "
+              "three sizes covering the share of TCC_EA0_RDREQ given in brackets) plus the scaled "
+              "write bytes. This count needs no calibration: FETCH_SIZE's expression counts a "
+              "128-byte request as 64 bytes unless TCC_BUBBLE counts it, and the copy's factor of 2 "
+              "shows that it does not here. Where the two fetch columns agree, the kernel's reads are "
+              "128-byte requests and the copy's factor applies to it as well.\n")
+        print("| kernel | dispatches | fetch (MB) | write (MB) | scaled fetch + write (MB) | algorithmic (MB) "
+              "| ratio | fetch by request size (MB) | ratio by request size |")
+        print("|---|---|---|---|---|---|---|---|---|")
+    else:
+        print("| kernel | dispatches | fetch (MB) | write (MB) | scaled fetch + write (MB) | algorithmic (MB) | ratio |")
+        print("|---|---|---|---|---|---|---|")
     rows = {}
     for k, cls in KERNELS.items():
         if k not in fe or k not in wr:
@@ -172,9 +218,17 @@ def summarize(fetch_dir, write_dir, workload):
         rows[k] = (f, w)
         a = alg.get(cls, 0.0) if k != "kb_dm_finish<" else 0.0
         ratio = f"{(f + w) / a:.2f}" if a > 0 else "—"
-        print(f"| {k.rstrip('<')} | {len(fe[k])} | {mean(fe[k]) / 1e6:.2f} | {mean(wr[k]) / 1e6:.3f} | "
-              f"{(f + w) / 1e6:.2f} | {a / 1e6 if a else 0:.2f} | {ratio} |")
-    print(f"| copy (calibration) | {len(cf)} | {mean(cf) / 1e6:.1f} | {mean(cw) / 1e6:.1f} | | | |")
+        line = (f"| {k.rstrip('<')} | {len(fe[k])} | {mean(fe[k]) / 1e6:.2f} | {mean(wr[k]) / 1e6:.3f} | "
+                f"{(f + w) / 1e6:.2f} | {a / 1e6 if a else 0:.2f} | {ratio} |")
+        if rq is not None:
+            rb, cov = rq.get(k, (float("nan"), 0.0))
+            rr = f"{(rb + w) / a:.2f}" if a > 0 else "—"
+            line += f" {rb / 1e6:.2f} ({cov:.3f}) | {rr} |"
+        print(line)
+    line = f"| copy (calibration) | {len(cf)} | {mean(cf) / 1e6:.1f} | {mean(cw) / 1e6:.1f} | | | |"
+    if rq is not None and "copy" in rq:
+        line += f" {rq['copy'][0] / 1e6:.1f} ({rq['copy'][1]:.3f}) | |"
+    print(line)
     pf, pw = rows["kb_prep_band<"]
     ff, fw = rows.get("kb_dm_finish<", (0.0, 0.0))
     fetch, write = pf + ff, pw + fw
@@ -303,12 +357,15 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--workload", choices=("batch64", "beam"), default="batch64")
     ap.add_argument("--dense-rows", type=int, default=0)
-    ap.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summarize", nargs="+", metavar="DIR",
+                    help="FETCH_DIR WRITE_DIR [REQUEST_SIZE_DIR]")
     ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "BENCH_LOG"))
     ap.add_argument("--counters", nargs="+", metavar="PASS_DIR")
     a = ap.parse_args()
     if a.summarize:
-        summarize(*a.summarize, a.workload)
+        if len(a.summarize) not in (2, 3):
+            ap.error("--summarize takes FETCH_DIR WRITE_DIR [REQUEST_SIZE_DIR]")
+        summarize(a.summarize[0], a.summarize[1], a.workload, *a.summarize[2:])
     elif a.trace_summary:
         trace_summary(*a.trace_summary)
     elif a.counters:

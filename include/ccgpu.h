@@ -140,7 +140,7 @@ cc_status cc_color(cc_ctx* ctx, int32_t mesh_id, int32_t* colors, int32_t* n_col
 
 /* Internal orderings (host outputs): vperm[new] = caller vertex id, sorted by
    (colour, id) with Dirichlet vertices last; eperm[new] = caller element id,
-   sorted by (smallest new index among the element's free vertices, id) with
+   sorted by (smallest caller id among the element's free vertices, id) with
    all-Dirichlet elements last. */
 cc_status cc_layout(cc_ctx* ctx, int32_t mesh_id, int32_t* vperm, int32_t* eperm);
 

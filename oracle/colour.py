@@ -10,8 +10,9 @@ does not specify one; this package's reading:
 * visit free vertices in increasing id and give each the smallest colour not
   used by an already-coloured neighbour;
 * vertex order: sorted by (colour, id), Dirichlet vertices last by id;
-* element order: sorted by (smallest new index among the element's free
-  vertices, id); elements with no free vertex last by id.
+* element order: sorted by (smallest caller id among the element's free
+  vertices, id); elements with no free vertex last by id (the elements of
+  neighbouring vertices then sit together in memory).
 
 Pins: tests/test_oracle_basis_colour.py -- validity on every scene, the colour
 counts and class sizes of the structured grids, and agreement with a
@@ -57,10 +58,8 @@ def layout(colours, elems):
     free = colours >= 0
     key_c = np.where(free, colours, np.iinfo(np.int32).max)
     vperm = np.lexsort((np.arange(n), key_c)).astype(np.int32)
-    new_of = np.empty(n, dtype=np.int64)
-    new_of[vperm] = np.arange(n)
     big = np.iinfo(np.int64).max
-    ne = np.where(free[elems], new_of[elems], big)
+    ne = np.where(free[elems], np.asarray(elems, dtype=np.int64), big)
     first = ne.min(axis=1)
     m = elems.shape[0]
     eperm = np.lexsort((np.arange(m), first)).astype(np.int32)

@@ -524,7 +524,8 @@ void build_mesh(cc_ctx* ctx, Mesh& M) {
     M.ncol = std::max(M.ncol, c + 1);
   }
   // layouts: vertices by (colour, id), Dirichlet last; elements by (smallest
-  // new index among free vertices, id), all-Dirichlet elements last
+  // caller id among free vertices, id), all-Dirichlet elements last, so that
+  // the elements of neighbouring vertices (in caller order) sit together
   M.vperm.resize(n);
   for (int i = 0; i < n; ++i) M.vperm[i] = i;
   std::stable_sort(M.vperm.begin(), M.vperm.end(), [&](int a, int b) {
@@ -545,7 +546,7 @@ void build_mesh(cc_ctx* ctx, Mesh& M) {
     long long k = 1LL << 40;
     for (int a = 0; a < K; ++a) {
       const int v = M.elems[e * K + a];
-      if (!M.fixed[v]) k = std::min<long long>(k, M.vinv[v]);
+      if (!M.fixed[v]) k = std::min<long long>(k, v);
     }
     ekey[e] = k;
   }

@@ -90,6 +90,43 @@ def test_batch_equals_single_mesh(cg, ctx, prec, sweep, graph):
             assert np.linalg.norm(a - b) <= tol * np.linalg.norm(b - s.X)
 
 
+def test_batch_gs_fallback_equals_single_mesh(cg, ctx):
+    """Corotated coloured GS with the energy test, exact bases, float64, on
+    stiff cantilevers whose coloured sweeps raise E at their full step (and one
+    whose sweeps do not): the batched path sends those meshes to its host
+    fallback and takes the single-mesh decisions, equal status, iterations,
+    halvings and fallback sweeps, positions to rounding."""
+    scenes = [tet_bar(8, 4, 4, E=1e7, length=(0.7, 0.3, 0.3), clamp_face=0),
+              tet_bar(10, 4, 4, E=3e6, length=(0.9, 0.3, 0.3), clamp_face=0),
+              tet_bar(8, 4, 4, E=1e7, length=(0.7, 0.3, 0.3), clamp_face=2),
+              tet_bar(12, 4, 4, E=1e7, length=(1.1, 0.3, 0.3), clamp_face=0)]
+    mids, _ = _setup(cg, ctx, scenes, "exact")
+    mids1, _ = _setup(cg, ctx, scenes, "exact")
+    cg.cc_batch_tuning(ctx, 16, 2)
+    par = cg.cc_params_default(method=cg.METHOD_CC, sweep=1, line_search=1, max_iters=60, corotate=1)
+    xs = [_t(s.initial_state()[0]) for s in scenes]
+    vs = [_t(s.initial_state()[1]) for s in scenes]
+    xs1 = [x.clone() for x in xs]
+    vs1 = [v.clone() for v in vs]
+    grav = np.stack([s.gravity for s in scenes])
+    fallbacks = 0
+    for t in range(1, 3):
+        bcs = [_t(s.targets(t)) for s in scenes]
+        _, its, _, sts = cg.cc_step_batch(ctx, mids, xs, vs, bcs, scenes[0].dt, par, 1e-7, gravity=grav)
+        for k, s in enumerate(scenes):
+            par1 = cg.cc_params_default(method=cg.METHOD_CC, sweep=1, line_search=1, max_iters=60,
+                                        corotate=1, gravity=s.gravity)
+            st, it, _ = cg.cc_step(ctx, mids1[k], xs1[k], vs1[k], bcs[k], s.dt, par1, 1e-7)
+            ib, i1 = cg.cc_step_info(ctx, mids[k]), cg.cc_step_info(ctx, mids1[k])
+            assert st == cg.CC_OK, (k, t, st)
+            assert (sts[k], int(its[k]), ib["halvings"], ib["sweep_fallbacks"]) == \
+                (st, it, i1["halvings"], i1["sweep_fallbacks"]), (k, t)
+            fallbacks += ib["sweep_fallbacks"]
+            a, b = xs[k].cpu().numpy(), xs1[k].cpu().numpy()
+            assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(b - s.X), (k, t)
+    assert fallbacks > 0                        # the fallback was exercised
+
+
 @pytest.mark.parametrize("max_halvings", [0, 2, 30])
 def test_batch_backtracking_equals_single_mesh(cg, ctx, max_halvings):
     """Line-searched Jacobi CC with R = 1 bases on the uneven bars, where the

@@ -730,13 +730,15 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
       for (int v = 0; v < TV; ++v)
 #pragma unroll
         for (int r = 0; r < DD; ++r) W[v][r] = T(0);
-      // software pipeline, unrolled by two: upper block q + 1 (its H and
-      // column) is loaded while block q's LDS reads and products run.
-      // Records past the row's count are zero padding or past the end of
-      // the buffer (read as zero) and are never used.
-      auto consume = [&](const RecWords<T, D>& rc) {
-        SlotRegs<T, D, TV> sr;
-        sr.load(ring + (size_t)wrap(rc.pos() + cshift) * SLW);
+      // W_j = sum_q H''_{j,q} U_{k(q)}.  Record 0 is the diagonal block
+      // (always present): it is applied last, with the row's own U_j, which
+      // the Y update below reads from the ring anyway, so that it costs no
+      // ring read of its own.  The other upper blocks run in a software
+      // pipeline unrolled by two: block q + 1 (its H and column) is loaded
+      // while block q's LDS reads and products run.  Records past the row's
+      // count are zero padding or past the end of the buffer (read as zero)
+      // and are never used.
+      auto product = [&](const RecWords<T, D>& rc, const SlotRegs<T, D, TV>& sr) {
 #pragma unroll
         for (int v = 0; v < TV; ++v) {
           T U[DD];
@@ -753,11 +755,18 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
             }
         }
       };
+      auto consume = [&](const RecWords<T, D>& rc) {
+        SlotRegs<T, D, TV> sr;
+        sr.load(ring + (size_t)wrap(rc.pos() + cshift) * SLW);
+        product(rc, sr);
+      };
       const uint32_t step = (uint32_t)nf * RB;
       uint32_t off = (uint32_t)p * RB;
-      RecWords<T, D> ra, rb;
+      RecWords<T, D> rd, ra, rb;
+      rd.fetch(hrs, off);                           // the diagonal block
+      off += step;
       ra.fetch(hrs, off);
-      int q = 0;
+      int q = 1;
       for (; q + 1 < cnt; q += 2) {
         rb.fetch(hrs, off + step);
         consume(ra);
@@ -788,6 +797,7 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
       }
       SlotRegs<T, D, TV> sj;
       sj.load(ring + (size_t)wrap(p + cshift) * SLW);
+      product(rd, sj);
 #pragma unroll
       for (int v = 0; v < TV; ++v) {
         T Uj[DD];
@@ -1353,11 +1363,11 @@ int band_ring(int nf, int band_w, int ch) {
 }
 
 // Resident waves per SIMD that the registers of the dense condensation allow
-// (gfx950 builds of prep_band_body: float32 196 / 154 / 112 / 70 VGPRs for
-// 4 / 3 / 2 / 1 rows, float64 210 / 131 for 2 / 1 rows)
+// (gfx950 builds of prep_band_body, 3D: float32 204 / 164 / 122 / 79 VGPRs
+// for 4 / 3 / 2 / 1 rows, float64 226 / 149 for 2 / 1 rows)
 static int dense_reg_waves(int prec, int tv) {
   if (prec == 0) return tv >= 2 ? 2 : 3;
-  return tv >= 4 ? 2 : tv == 3 ? 3 : tv == 2 ? 4 : 7;
+  return tv >= 4 ? 2 : tv == 3 ? 3 : tv == 2 ? 4 : 6;
 }
 
 size_t dense_lds_bytes(int tv, int ring, int D, int prec, int ch) {

@@ -198,10 +198,12 @@ cc_status cc_subspace_row(cc_ctx* ctx, int32_t mesh_id, int32_t vertex, int64_t*
    x_bc: device (n_verts x dim) targets for the Dirichlet vertices, or NULL to
          keep their current positions.
    The predictor is x~ = x^t + h v^t with Dirichlet targets imposed; the
-   iteration stops when |g(x_k)|_2 <= tol max(|g(x^_0)|_2, |f_g|_2) over free
-   DOFs, with x^_0 the predictor (quasistatic: the start state with targets)
-   and f_g = h^2 m_i g (quasistatic: m_i g) the gravity load's part of the
-   gradient, which keeps the test reachable for a loaded body at rest.
+   iteration stops when |g(x_k)|_2 <= tol max(|g(x^_0)|_2, |f_g|_2, f_min)
+   over free DOFs, with x^_0 the predictor (quasistatic: the start state with
+   targets), f_g = h^2 m_i g (quasistatic: m_i g) the gravity load's part of
+   the gradient, which keeps the test reachable for a loaded body at rest, and
+   f_min = 1e-8 h^2 E V^((dim-1)/dim) (quasistatic: without h^2; V the rest
+   volume), which does the same for an unloaded body at rest.
    *iters receives the iteration count, *rel_grad the final ratio.
    Returns CC_OK, CC_NOT_CONVERGED, CC_STALLED or an error. */
 cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const double* x_bc,

@@ -115,6 +115,14 @@ class Problem:
         f = self.free
         return self.s_el * float(np.linalg.norm(self.mass[f])) * float(np.linalg.norm(self.grav))
 
+    def residual_floor(self):
+        """1e-8 of the elastic force scale s_el E V^((d-1)/d) (V the rest
+        volume): the least gradient norm the convergence test divides by.  A
+        body at rest with no load has a start gradient at the rounding level
+        of its element forces, relative to which no iterate can pass."""
+        V = float(np.sum(self.vol))
+        return 1e-8 * self.s_el * self.E * V ** ((self.d - 1) / self.d)
+
     def hessian(self, x, project=True):
         """Sparse (CSR) Hessian over free DOFs: w_in M + s_el sum_e H_e."""
         d = self.d

@@ -60,15 +60,18 @@ Readings taken where the paper is silent:
   and halving it then makes vanishing progress per iteration where the
   Jacobi (near-Newton) step does not.  SolveResult.sweep_fallbacks counts
   the iterations whose displacement came from a fallback sweep;
-* termination: r_k = |g(x_k)|_2 / max(|g(x^_0)|_2, |f_g|_2) <= tol, where
-  x^_0 is the inertial predictor with boundary targets (dynamic) or the
-  initial guess (quasistatic), and f_g = s_el m_i grav is the gravity load's
-  part of the gradient over free DOFs.  The load term keeps the test
-  reachable for a loaded body that has settled: there |g(x^_0)| falls
-  towards the rounding level of the force balance the body holds (the
-  elastic forces cancelling the load), which a fixed fraction of it would
-  ask the iteration to undercut.  Without gravity the denominator is
-  |g(x^_0)|.  The paper's own measure |g|/(V n E) (divided by h for
+* termination: r_k = |g(x_k)|_2 / max(|g(x^_0)|_2, |f_g|_2, f_min) <= tol,
+  where x^_0 is the inertial predictor with boundary targets (dynamic) or the
+  initial guess (quasistatic), f_g = s_el m_i grav is the gravity load's part
+  of the gradient over free DOFs, and f_min = 1e-8 s_el E V^((d-1)/d) (V the
+  rest volume) is a floor at 1e-8 of the elastic force scale.  The load term
+  keeps the test reachable for a loaded body that has settled: there
+  |g(x^_0)| falls towards the rounding level of the force balance the body
+  holds (the elastic forces cancelling the load), which a fixed fraction of
+  it would ask the iteration to undercut.  The floor does the same for an
+  unloaded body at rest, whose start gradient is only the rounding of its
+  element forces; for any loaded or driven step it lies far below the other
+  two terms.  The paper's own measure |g|/(V n E) (divided by h for
   dynamics) is also recorded.
 
 Pins: tests/test_oracle_solvers.py -- with the exact basis one Jacobi
@@ -301,7 +304,8 @@ def solve(prob, x0, basis, params, tol, colours=None, x_hat0=None, record=False)
     Umat = basis_matrix(prob, *basis) if basis is not None else None
     cf = (np.zeros(prob.free.size, dtype=np.int64) if colours is None
           else np.asarray(colours)[prob.free])
-    g0 = max(np.linalg.norm(prob.gradient(x if x_hat0 is None else x_hat0)), prob.load_norm())
+    g0 = max(np.linalg.norm(prob.gradient(x if x_hat0 is None else x_hat0)), prob.load_norm(),
+             prob.residual_floor())
     res = SolveResult(x=x, iters=0, rel_grad=0.0, status=OK)
     gx = prob.gradient(x)
     if g0 == 0.0:
@@ -352,7 +356,8 @@ def newton(prob, x0, tol=1e-10, max_iters=100, x_hat0=None, c_armijo=1e-4, recor
     """Projected Newton with a sparse direct solve and Armijo backtracking."""
     x = np.array(x0, dtype=np.float64, copy=True)
     f = prob.free
-    g0 = max(np.linalg.norm(prob.gradient(x if x_hat0 is None else x_hat0)), prob.load_norm())
+    g0 = max(np.linalg.norm(prob.gradient(x if x_hat0 is None else x_hat0)), prob.load_norm(),
+             prob.residual_floor())
     hist = []
     g = prob.gradient(x)
     r = np.linalg.norm(g) / g0 if g0 > 0 else 0.0

@@ -1075,12 +1075,17 @@ void build_basis(cc_ctx* ctx, Mesh& M, int radius, double dt, int quasi, const d
   upload_basis(ctx, M, ptr.data(), idx.data(), U.data());
 }
 
-// |s_el m_i grav| over the free degrees of freedom: the gravity load's part
-// of the step gradient, the floor of the convergence test's denominator.
+// The floor of the convergence test's denominator: the larger of
+// |s_el m_i grav| over the free degrees of freedom (the gravity load's part of
+// the step gradient, which keeps the test reachable for a loaded body that has
+// settled) and 1e-8 s_el E V^((D-1)/D) (V the rest volume: 1e-8 of the elastic
+// force scale, which does the same for an unloaded body at rest, whose start
+// gradient is only the rounding of its element forces).
 double load_norm(const Mesh& M, const Material& mat) {
   double g2 = 0;
   for (int c = 0; c < M.D; ++c) g2 += mat.grav[c] * mat.grav[c];
-  return mat.s_el * M.mass_free_norm * std::sqrt(g2);
+  const double floor = 1e-8 * mat.s_el * M.E * std::pow(M.volume, (M.D - 1.0) / M.D);
+  return std::max(mat.s_el * M.mass_free_norm * std::sqrt(g2), floor);
 }
 
 // ---- step driver ---------------------------------------------------------
@@ -1548,7 +1553,8 @@ cc_status cc_step(cc_ctx* ctx, int32_t mesh_id, double* x, double* v, const doub
     HIPC(hipStreamSynchronize(s));
     if (bad) return fail(ctx, CC_E_NONFINITE, "non-finite x, v or x_bc");
     // the convergence test is relative to the larger of the predictor's
-    // gradient and the gravity load's part of it (s_el |m_i g| over free DOFs)
+    // gradient and the floor (the gravity load's part of it, s_el |m_i g| over
+    // free DOFs, or 1e-8 of the elastic force scale)
     const double gstart = std::sqrt(S.grad_norm2(M.x));
     const double g0 = std::max(gstart, load_norm(M, mat));
     const int nd = M.D * M.n;

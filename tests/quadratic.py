@@ -47,6 +47,10 @@ class QuadraticProblem:
         """No gravity load: the residual is relative to the start gradient."""
         return 0.0
 
+    def residual_floor(self):
+        """No elastic force scale: the residual is relative to the start gradient."""
+        return 0.0
+
     def adjacency(self):
         K = self.K.tocoo()
         nbr = [set() for _ in range(self.n)]

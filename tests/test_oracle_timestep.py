@@ -102,3 +102,31 @@ def test_settled_loaded_body_converges():
     # residual of 1e-6 * g0: below the level the iteration reaches
     res2 = S.solve(p, xh, B, prm, 1e-6 * g0 / p.load_norm())
     assert res2.status != S.OK or res2.iters > 1
+
+
+def test_unloaded_body_at_rest_converges_at_once():
+    """No gravity, at rest, targets at rest: the predictor is the minimiser and
+    its gradient is the rounding of the element forces (nonzero with spacings
+    of 0.1, far below any force the body holds).  The floor 1e-8 s_el E V^(2/3) of the test's
+    denominator makes the step converge with no iteration; without it the
+    test is relative to that rounding and no iterate can pass."""
+    import numpy as np
+    from ccscenes import tet_bar
+    from oracle import solvers as S
+    from oracle.basis import exact_basis
+    from oracle.fem import Problem
+    from oracle.timestep import predictor, step
+    s = tet_bar(7, 3, 3, E=1e6, gravity=(0.0, 0.0, 0.0), length=(0.7, 0.3, 0.3))
+    p = Problem.from_scene(s)
+    B = exact_basis(p)
+    x0, v0 = s.initial_state()
+    xh = predictor(p, x0, v0, s.targets(1))
+    gn = np.linalg.norm(p.gradient(xh))
+    V = float(np.sum(p.vol))
+    assert p.load_norm() == 0.0
+    assert abs(p.residual_floor() - 1e-8 * p.h ** 2 * 1e6 * V ** (2.0 / 3.0)) <= 1e-15 * p.residual_floor()
+    assert 0.0 < gn <= 1e-6 * p.residual_floor()
+    prm = S.Params(method=S.CC, sweep=S.JACOBI, line_search=True, max_iters=20)
+    x1, _, res, _ = step(p, x0, v0, s.targets(1), B, prm, 1e-6)
+    assert res.status == S.OK and res.iters == 0
+    assert np.array_equal(x1, x0)

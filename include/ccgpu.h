@@ -247,7 +247,8 @@ cc_status cc_batch_tuning(cc_ctx* ctx, int32_t lanes, int32_t iters_per_graph);
    stages serves that many vertices per H block it loads): 0 = the most whose
    LDS ring fits (4 in float32, 2 in float64 on MI355X), or a cap of 1 to
    4; and its chunk of band positions per pass, which is also its workgroup
-   size: 0 = the one that leaves more waves resident per CU, or 256 / 512.
+   size: 0 = the one that leaves more waves resident per CU, or 128 / 256 /
+   512.
    A forced chunk whose ring does not fit sends the mesh to the sparse-row
    kernel.  Applies to later cc_step, cc_probe_sweep and cc_step_batch calls;
    invalid values return CC_E_INVALID_ARG. */

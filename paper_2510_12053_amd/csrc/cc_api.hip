@@ -2118,8 +2118,8 @@ cc_status cc_dense_tuning(cc_ctx* ctx, int32_t rows_per_workgroup, int32_t chunk
   return guarded(ctx, [&]() -> cc_status {
     if (rows_per_workgroup < 0 || rows_per_workgroup > 4)
       return fail(ctx, CC_E_INVALID_ARG, "rows per workgroup must be 0 (automatic), 1, 2, 3 or 4");
-    if (chunk != 0 && chunk != 256 && chunk != 512)
-      return fail(ctx, CC_E_INVALID_ARG, "chunk must be 0 (automatic), 256 or 512");
+    if (chunk != 0 && chunk != 128 && chunk != 256 && chunk != 512)
+      return fail(ctx, CC_E_INVALID_ARG, "chunk must be 0 (automatic), 128, 256 or 512");
     ctx->dense_rows = rows_per_workgroup;
     ctx->dense_chunk = chunk;
     return CC_OK;

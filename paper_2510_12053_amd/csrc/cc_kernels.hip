@@ -853,12 +853,13 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
     tot[tid] = acc;
   }
   __syncthreads();
-  if (w >= nv) return;
-  const int i = i0 + w;
-  T A[DD];
+  // one wave per row (rows w, w + NW, ... when the chunk has fewer waves
+  // than rows)
+  for (int v = w; v < nv; v += NW) {
+    const int i = i0 + v;
+    T A[DD];
 #pragma unroll
-  for (int r = 0; r < DD; ++r) A[r] = T(0);
-  {
+    for (int r = 0; r < DD; ++r) A[r] = T(0);
     const int q1 = gptr(mv.rowptr)[i + 1];
     for (int q = gptr(mv.rowptr)[i] + 1 + l; q < q1; q += 64) {
       const int k = gptr(mv.colidx)[q];
@@ -878,23 +879,23 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
     }
 #pragma unroll
     for (int r = 0; r < DD; ++r) A[r] = wave_sum63(A[r]);
+    if (l != 63) continue;
+    // A and Ht go to the vertex's K, L slots; dm_finish_body turns them into
+    // K and L with one thread per vertex.  b_i = U_i^T (R^T g)_C, the
+    // corotated basis's U_i^T g_C.
+    const T* Yt = tot + v * NR;
+    auto* out = gptr_w(KL) + (size_t)i * 2 * DD;
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        out[r * D + c] = A[r * D + c];
+        out[DD + r * D + c] = Yt[r * D + c] + Yt[c * D + r];
+      }
+    if (bout != nullptr)
+#pragma unroll
+      for (int r = 0; r < D; ++r) gptr_w(bout)[(size_t)r * mv.n + i] = double(Yt[DD + r]);
   }
-  if (l != 63) return;
-  // A and Ht go to the vertex's K, L slots; dm_finish_body turns them into
-  // K and L with one thread per vertex.  b_i = U_i^T (R^T g)_C, the
-  // corotated basis's U_i^T g_C.
-  const T* Yt = tot + w * NR;
-  auto* out = gptr_w(KL) + (size_t)i * 2 * DD;
-#pragma unroll
-  for (int r = 0; r < D; ++r)
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-      out[r * D + c] = A[r * D + c];
-      out[DD + r * D + c] = Yt[r * D + c] + Yt[c * D + r];
-    }
-  if (bout != nullptr)
-#pragma unroll
-    for (int r = 0; r < D; ++r) gptr_w(bout)[(size_t)r * mv.n + i] = double(Yt[DD + r]);
 }
 
 // With dout given, dout holds b_i on entry and receives dx_i = -K (g_i - L b_i)
@@ -1377,13 +1378,15 @@ size_t dense_lds_bytes(int tv, int ring, int D, int prec, int ch) {
 }
 
 // float64 keeps at most two rows per workgroup (the register file of 2
-// waves/SIMD holds the accumulators of two float64 rows, four float32 ones)
+// waves/SIMD holds the accumulators of two float64 rows, four float32 ones).
+// Among chunks that leave as many waves resident, the smallest wins: more,
+// shorter workgroups fill the last round of a launch better.
 DenseCfg dense_config(const int* nf, const int* band_w, int count, int D, int prec, int cap, int chunk) {
   DenseCfg best;
   const int top = std::min(prec == 0 ? 2 : 4, cap > 0 ? cap : 4);
   for (int tv = top; tv >= 1 && best.tv == 0; --tv) {
     int best_waves = 0;
-    for (int ch : {256, BWG}) {
+    for (int ch : {128, 256, BWG}) {
       if (chunk > 0 && ch != chunk) continue;
       int ring = 0;
       for (int m = 0; m < count; ++m) ring = std::max(ring, band_ring(nf[m], band_w[m], ch));
@@ -1404,6 +1407,10 @@ DenseCfg dense_config(const int* nf, const int* band_w, int count, int D, int pr
 
 #define CC_DISPATCH_TVCH(tv, ch, ...)                                                 \
   switch ((tv) * 1000 + (ch)) {                                                       \
+    case 1128: { constexpr int TV = 1, CH = 128; __VA_ARGS__; } break;                \
+    case 2128: { constexpr int TV = 2, CH = 128; __VA_ARGS__; } break;                \
+    case 3128: { constexpr int TV = 3, CH = 128; __VA_ARGS__; } break;                \
+    case 4128: { constexpr int TV = 4, CH = 128; __VA_ARGS__; } break;                \
     case 1256: { constexpr int TV = 1, CH = 256; __VA_ARGS__; } break;                \
     case 2256: { constexpr int TV = 2, CH = 256; __VA_ARGS__; } break;                \
     case 3256: { constexpr int TV = 3, CH = 256; __VA_ARGS__; } break;                \

@@ -4,10 +4,12 @@ directions against the oracle on sampled vertices, with the rows per
 workgroup and the chunk of band positions forced through cc_dense_tuning,
 and a batch of the largest bars against single-mesh steps.
 
-The 41x7x7 bar has 1,960 free vertices: 8 chunks of 256 positions (the last
-holding 168) or 4 of 512 (the last 424), so the ring (chunk + band width
-positions) wraps several times and the tail is ragged.  Rows per workgroup:
-float64 1 and 2, float32-mixed 1 to 4; chunks 256 and 512; with and without corotation (rotated band
+The 41x7x7 bar has 1,960 free vertices: 16 chunks of 128 positions (the last
+holding 40), 8 of 256 (the last 168) or 4 of 512 (the last 424), so the ring
+(chunk + band width positions) wraps several times and the tail is ragged.
+Rows per workgroup: float64 1 and 2, float32-mixed 1 to 4 (with chunks of
+128, two waves take four rows' final sums in turn); chunks 128, 256 and 512;
+with and without corotation (rotated band
 records and R^T g).  Tolerances: float64 1e-9, float32-mixed 1e-4 of the
 largest direction."""
 import numpy as np
@@ -59,9 +61,9 @@ def bar(cg, ctx):
     return dict(s=s, p=p, mid=mid, x=x, ranks=ranks, Um=Um)
 
 
-CONFIGS = [(0, 1, 256), (0, 1, 512), (0, 2, 256), (0, 2, 512),
-           (1, 1, 256), (1, 1, 512), (1, 2, 256), (1, 2, 512), (1, 3, 256), (1, 3, 512),
-           (1, 4, 256), (1, 4, 512)]
+CONFIGS = [(0, 1, 128), (0, 1, 256), (0, 1, 512), (0, 2, 128), (0, 2, 256), (0, 2, 512),
+           (1, 1, 128), (1, 1, 256), (1, 1, 512), (1, 2, 128), (1, 2, 256), (1, 2, 512),
+           (1, 3, 128), (1, 3, 256), (1, 3, 512), (1, 4, 128), (1, 4, 256), (1, 4, 512)]
 
 
 @pytest.mark.parametrize("corot", [0, 1])

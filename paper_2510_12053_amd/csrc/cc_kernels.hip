@@ -1380,28 +1380,32 @@ size_t dense_lds_bytes(int tv, int ring, int D, int prec, int ch) {
 // float64 keeps at most two rows per workgroup (the register file of 2
 // waves/SIMD holds the accumulators of two float64 rows, four float32 ones).
 // Among chunks that leave as many waves resident, the smallest wins: more,
-// shorter workgroups fill the last round of a launch better.
+// shorter workgroups fill the last round of a launch better.  With the rows
+// chosen automatically, the most rows that still let two workgroups share a
+// CU come first (one workgroup's barriers and ring fill then overlap the
+// other's products); only when no row count allows two does one per CU do.
 DenseCfg dense_config(const int* nf, const int* band_w, int count, int D, int prec, int cap, int chunk) {
   DenseCfg best;
   const int top = std::min(prec == 0 ? 2 : 4, cap > 0 ? cap : 4);
-  for (int tv = top; tv >= 1 && best.tv == 0; --tv) {
-    int best_waves = 0;
-    for (int ch : {128, 256, BWG}) {
-      if (chunk > 0 && ch != chunk) continue;
-      int ring = 0;
-      for (int m = 0; m < count; ++m) ring = std::max(ring, band_ring(nf[m], band_w[m], ch));
-      if (ring <= 0) continue;
-      const size_t lds = dense_lds_bytes(tv, ring, D, prec, ch);
-      if (lds > g_lds_limit) continue;
-      const int waves = std::min((int)(g_lds_limit / lds) * (ch / 64), 4 * dense_reg_waves(prec, tv));
-      if (waves > best_waves) {
-        best_waves = waves;
-        best.tv = tv;
-        best.ch = ch;
-        best.lds = lds;
+  for (int pass = cap > 0 ? 1 : 0; pass < 2 && best.tv == 0; ++pass)
+    for (int tv = top; tv >= 1 && best.tv == 0; --tv) {
+      int best_waves = 0;
+      for (int ch : {128, 256, BWG}) {
+        if (chunk > 0 && ch != chunk) continue;
+        int ring = 0;
+        for (int m = 0; m < count; ++m) ring = std::max(ring, band_ring(nf[m], band_w[m], ch));
+        if (ring <= 0) continue;
+        const size_t lds = dense_lds_bytes(tv, ring, D, prec, ch);
+        if (lds > g_lds_limit || (pass == 0 && 2 * lds > g_lds_limit)) continue;
+        const int waves = std::min((int)(g_lds_limit / lds) * (ch / 64), 4 * dense_reg_waves(prec, tv));
+        if (waves > best_waves) {
+          best_waves = waves;
+          best.tv = tv;
+          best.ch = ch;
+          best.lds = lds;
+        }
       }
     }
-  }
   return best;
 }
 

@@ -159,6 +159,53 @@ def test_batch64_equals_single_mesh(cg, ctx, prec):
 
 
 
+def test_batch64_exact_equals_single_mesh(cg, ctx):
+    """The benchmark's configuration at full size: the 64 bars with exact
+    corotated bases, float32-mixed, Jacobi CC with the search, three steps to
+    1e-6, in one batched call per step (the dense condensation's automatic
+    rows and chunk) against each bar stepped alone.  A borderline decision may
+    differ between the paths (float32 lane counts), so such a mesh-step is
+    resynchronised; at least 90% of the mesh-steps must take the same
+    decisions and agree to 1e-4, and every one must converge."""
+    scenes = batch_bars(64)
+    mids, mids1 = [], []
+    for s in scenes:
+        for lst in (mids, mids1):
+            mid = cg.cc_mesh_upload(ctx, s.X, s.elems, s.fixed, s.E, s.nu, s.rho)
+            cg.cc_subspace_build(ctx, mid, 0, s.dt, False)
+            lst.append(mid)
+    cg.cc_batch_tuning(ctx, 16, 4)
+    par = cg.cc_params_default(method=cg.METHOD_CC, sweep=cg.SWEEP_JACOBI, precision=1,
+                               line_search=1, max_iters=60, corotate=1)
+    xs = [_t(s.initial_state()[0]) for s in scenes]
+    vs = [_t(s.initial_state()[1]) for s in scenes]
+    xs1 = [x.clone() for x in xs]
+    vs1 = [v.clone() for v in vs]
+    grav = np.stack([s.gravity for s in scenes])
+    compared, total = 0, 0
+    for t in (1, 2, 3):
+        bcs = [_t(s.targets(t)) for s in scenes]
+        worst, its, rgs, sts = cg.cc_step_batch(ctx, mids, xs, vs, bcs, scenes[0].dt, par, 1e-6,
+                                                gravity=grav)
+        assert worst == cg.CC_OK
+        for k, s in enumerate(scenes):
+            par1 = cg.cc_params_default(method=cg.METHOD_CC, sweep=cg.SWEEP_JACOBI, precision=1,
+                                        line_search=1, max_iters=60, corotate=1, gravity=s.gravity)
+            st, it, rg = cg.cc_step(ctx, mids1[k], xs1[k], vs1[k], bcs[k], s.dt, par1, 1e-6)
+            assert st == cg.CC_OK and rg <= 1e-6 and rgs[k] <= 1e-6, (k, t, st, rg, rgs[k])
+            a, b = xs[k].cpu().numpy(), xs1[k].cpu().numpy()
+            assert np.all(np.isfinite(a))
+            total += 1
+            if sts[k] == st and its[k] == it:
+                assert np.linalg.norm(a - b) <= 1e-4 * np.linalg.norm(b - s.X), (k, t)
+                compared += 1
+            else:
+                assert abs(int(its[k]) - it) <= 2, (k, t, its[k], it)
+            xs[k].copy_(xs1[k])
+            vs[k].copy_(vs1[k])
+    assert compared >= 0.9 * total, (compared, total)
+
+
 def test_batch64_gs_equals_single_mesh(cg, ctx):
     """The benchmark's coloured Gauss-Seidel configuration at full size: the
     64 bars with exact corotated bases, float32-mixed, the energy test with

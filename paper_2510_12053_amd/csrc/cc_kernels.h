@@ -190,10 +190,11 @@ size_t dense_lds_bytes(int tv, int ring, int D, int prec, int ch);
 // Rows per workgroup (tv) and chunk (ch, the workgroup size) of the dense
 // condensation for meshes with the given free-vertex counts and band widths:
 // the most rows (4, 3, 2 or 1; at most 2 in float64) whose ring fits, at
-// most cap when cap > 0, then the chunk (256 or 512) with more resident
-// waves per CU (LDS and an estimate of the registers), ties to the smaller chunk,
-// whose workgroups overlap one another's ring fill and final sums (chunk > 0
-// forces that chunk).  tv = 0: no configuration fits.
+// most cap when cap > 0 (with cap = 0, first the most rows whose ring lets
+// two workgroups share a CU), then the chunk (128, 256 or 512) with more
+// resident waves per CU (LDS and an estimate of the registers), ties to the
+// smaller chunk, whose workgroups overlap one another's ring fill and final
+// sums (chunk > 0 forces that chunk).  tv = 0: no configuration fits.
 struct DenseCfg {
   int tv = 0, ch = 0;
   size_t lds = 0;
@@ -227,7 +228,8 @@ struct BatchItem {
   double* vu;          // caller velocities
   const double* xbc;   // caller Dirichlet targets or null
   int prep_dense;      // 1: exact-basis condensation streamed through the LDS ring
-  double load;         // floor of the convergence test's denominator (gravity load norm)
+  double load;         // floor of the convergence test's denominator (the gravity
+                       // load's norm, or 1e-8 of the elastic force scale)
   int ncol;
   int coff[MAX_COLOURS + 1];
   // warm start: mesh neighbours (all vertices), rest positions, scales and
@@ -267,7 +269,7 @@ struct BatchConfig {
   int dense_lds;       // max dynamic LDS of the dense condensation path (bytes)
   int corotate;        // rotations re-estimated wherever the Hessian is
   int tv_cap;          // rows per workgroup of the dense condensation (0: most that fit)
-  int chunk;           // its chunk of band positions (0: automatic, else 256 or 512)
+  int chunk;           // its chunk of band positions (0: automatic, else 128, 256 or 512)
   int any_fcr;         // some mesh of the batch uses the Fixed Corotational model
 };
 

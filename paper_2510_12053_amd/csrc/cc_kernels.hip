@@ -2113,7 +2113,7 @@ __global__ void kb_init(const BatchItem* items, BatchCtl* ctl, int nmesh, double
   if (m >= nmesh) return;
   BatchCtl& c = ctl[m];
   if (c.bad) { c.status = -5; c.active = 0; return; }
-  c.g0 = fmax(sqrt(c.gn2), items[m].load);   // relative to the larger of |g(x^0)| and the load
+  c.g0 = fmax(sqrt(c.gn2), items[m].load);   // relative to the larger of |g(x^0)| and the floor
   if (c.g0 == 0.0) { c.r = 0.0; c.status = 0; c.active = 0; return; }
   c.r = sqrt(c.gn2) / c.g0;
   if (c.r <= tol) { c.status = 0; c.active = 0; }

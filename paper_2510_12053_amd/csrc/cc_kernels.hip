@@ -726,19 +726,20 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
     if (p < nf) {
       const int cnt = gptr(mv.bq_cnt)[p];
       T W[TV][DD];
-#pragma unroll
-      for (int v = 0; v < TV; ++v)
-#pragma unroll
-        for (int r = 0; r < DD; ++r) W[v][r] = T(0);
       // W_j = sum_q H''_{j,q} U_{k(q)}.  Record 0 is the diagonal block
-      // (always present): it is applied last, with the row's own U_j, which
-      // the Y update below reads from the ring anyway, so that it costs no
-      // ring read of its own.  The other upper blocks run in a software
-      // pipeline unrolled by two: block q + 1 (its H and column) is loaded
-      // while block q's LDS reads and products run.  Records past the row's
-      // count are zero padding or past the end of the buffer (read as zero)
-      // and are never used.
-      auto product = [&](const RecWords<T, D>& rc, const SlotRegs<T, D, TV>& sr) {
+      // (always present), applied with the row's own U_j, which the Y update
+      // below needs anyway, so that it costs no ring read of its own.  With
+      // four float32 rows U_j is read first and the diagonal product sets W
+      // (no clearing of the accumulators, which the compiler emits twice
+      // around the loop's guard); with fewer rows, whose occupancy the extra
+      // live registers would cut, W is cleared and the diagonal block comes
+      // last.  The other upper blocks run in a software pipeline unrolled by
+      // two: block q + 1 (its H and column) is loaded while block q's LDS
+      // reads and products run.  Records past the row's count are zero
+      // padding or past the end of the buffer (read as zero) and are never
+      // used.
+      constexpr bool own_first = sizeof(T) == 4 && TV == 4;
+      auto product = [&](const RecWords<T, D>& rc, const SlotRegs<T, D, TV>& sr, bool first) {
 #pragma unroll
         for (int v = 0; v < TV; ++v) {
           T U[DD];
@@ -748,9 +749,9 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
           for (int r = 0; r < D; ++r)
 #pragma unroll
             for (int c = 0; c < D; ++c) {
-              T acc = W[v][r * D + c];
+              T acc = first ? rc.h(r * D) * U[c] : W[v][r * D + c] + rc.h(r * D) * U[c];
 #pragma unroll
-              for (int l = 0; l < D; ++l) acc += rc.h(r * D + l) * U[l * D + c];
+              for (int l = 1; l < D; ++l) acc += rc.h(r * D + l) * U[l * D + c];
               W[v][r * D + c] = acc;
             }
         }
@@ -758,14 +759,24 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
       auto consume = [&](const RecWords<T, D>& rc) {
         SlotRegs<T, D, TV> sr;
         sr.load(ring + (size_t)wrap(rc.pos() + cshift) * SLW);
-        product(rc, sr);
+        product(rc, sr, false);
       };
       const uint32_t step = (uint32_t)nf * RB;
       uint32_t off = (uint32_t)p * RB;
       RecWords<T, D> rd, ra, rb;
+      SlotRegs<T, D, TV> sj;
       rd.fetch(hrs, off);                           // the diagonal block
       off += step;
       ra.fetch(hrs, off);
+      if constexpr (own_first) {
+        sj.load(ring + (size_t)wrap(p + cshift) * SLW);
+        product(rd, sj, true);
+      } else {
+#pragma unroll
+        for (int v = 0; v < TV; ++v)
+#pragma unroll
+          for (int r = 0; r < DD; ++r) W[v][r] = T(0);
+      }
       int q = 1;
       for (; q + 1 < cnt; q += 2) {
         rb.fetch(hrs, off + step);
@@ -795,9 +806,10 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
           for (int c = 0; c < D; ++c) gj[c] = T(gd[c]);
         }
       }
-      SlotRegs<T, D, TV> sj;
-      sj.load(ring + (size_t)wrap(p + cshift) * SLW);
-      product(rd, sj);
+      if constexpr (!own_first) {
+        sj.load(ring + (size_t)wrap(p + cshift) * SLW);
+        product(rd, sj, false);
+      }
 #pragma unroll
       for (int v = 0; v < TV; ++v) {
         T Uj[DD];
@@ -1364,7 +1376,7 @@ int band_ring(int nf, int band_w, int ch) {
 }
 
 // Resident waves per SIMD that the registers of the dense condensation allow
-// (gfx950 builds of prep_band_body, 3D: float32 204 / 164 / 122 / 79 VGPRs
+// (gfx950 builds of prep_band_body, 3D: float32 228 / 164 / 122 / 79 VGPRs
 // for 4 / 3 / 2 / 1 rows, float64 226 / 149 for 2 / 1 rows)
 static int dense_reg_waves(int prec, int tv) {
   if (prec == 0) return tv >= 2 ? 2 : 3;

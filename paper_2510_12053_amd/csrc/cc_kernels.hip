@@ -2264,8 +2264,14 @@ BatchPlan* batch_plan_create(const BatchItem* items_host, int nmesh, const Batch
         dense_bw.push_back(p->items_h[m].mv.band_w);
       }
     if (!dense_nf.empty()) {
-      const DenseCfg dc = dense_config(dense_nf.data(), dense_bw.data(), (int)dense_nf.size(), cfg.D, cfg.prec,
-                                       cfg.tv_cap, cfg.chunk);
+      // a coloured sweep launches one colour's rows at a time; there chunks of
+      // 256 measured faster than the 128 that tie with them on the full mesh
+      DenseCfg dc{};
+      if (cfg.sweep == 1 && cfg.chunk == 0)
+        dc = dense_config(dense_nf.data(), dense_bw.data(), (int)dense_nf.size(), cfg.D, cfg.prec, cfg.tv_cap, 256);
+      if (dc.tv == 0)
+        dc = dense_config(dense_nf.data(), dense_bw.data(), (int)dense_nf.size(), cfg.D, cfg.prec, cfg.tv_cap,
+                          cfg.chunk);
       p->tv = dc.tv;
       p->ch = dc.ch;
       p->lds = dc.lds;

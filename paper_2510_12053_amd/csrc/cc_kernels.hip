@@ -729,16 +729,18 @@ __device__ __forceinline__ void prep_band_body(const MeshView& mv, int method, i
       // W_j = sum_q H''_{j,q} U_{k(q)}.  Record 0 is the diagonal block
       // (always present), applied with the row's own U_j, which the Y update
       // below needs anyway, so that it costs no ring read of its own.  With
-      // four float32 rows U_j is read first and the diagonal product sets W
-      // (no clearing of the accumulators, which the compiler emits twice
-      // around the loop's guard); with fewer rows, whose occupancy the extra
-      // live registers would cut, W is cleared and the diagonal block comes
-      // last.  The other upper blocks run in a software pipeline unrolled by
+      // three or four float32 rows U_j is read first and the diagonal product
+      // sets W (no clearing of the accumulators, which the compiler emits
+      // twice around the loop's guard; three rows then hold two waves per
+      // SIMD instead of three, which their LDS ring allows anyway on the
+      // meshes whose band sends them there); with fewer rows, whose occupancy
+      // the extra live registers would cut, W is cleared and the diagonal
+      // block comes last.  The other upper blocks run in a software pipeline unrolled by
       // two: block q + 1 (its H and column) is loaded while block q's LDS
       // reads and products run.  Records past the row's count are zero
       // padding or past the end of the buffer (read as zero) and are never
       // used.
-      constexpr bool own_first = sizeof(T) == 4 && TV == 4;
+      constexpr bool own_first = sizeof(T) == 4 && TV >= 3;
       auto product = [&](const RecWords<T, D>& rc, const SlotRegs<T, D, TV>& sr, bool first) {
 #pragma unroll
         for (int v = 0; v < TV; ++v) {
@@ -1376,11 +1378,11 @@ int band_ring(int nf, int band_w, int ch) {
 }
 
 // Resident waves per SIMD that the registers of the dense condensation allow
-// (gfx950 builds of prep_band_body, 3D: float32 228 / 164 / 122 / 79 VGPRs
+// (gfx950 builds of prep_band_body, 3D: float32 228 / 182 / 122 / 79 VGPRs
 // for 4 / 3 / 2 / 1 rows, float64 226 / 149 for 2 / 1 rows)
 static int dense_reg_waves(int prec, int tv) {
   if (prec == 0) return tv >= 2 ? 2 : 3;
-  return tv >= 4 ? 2 : tv == 3 ? 3 : tv == 2 ? 4 : 6;
+  return tv >= 3 ? 2 : tv == 2 ? 4 : 6;
 }
 
 size_t dense_lds_bytes(int tv, int ring, int D, int prec, int ch) {

@@ -93,3 +93,44 @@ def test_summary_scales_by_the_copy_and_stamps_the_source(tmp_path, monkeypatch,
     stale = out.replace(BC.source_hash(), "0" * 16)
     path.write_text(stale)
     assert bench.measured_traffic(str(path)) is None
+
+
+def test_trace_summary_windows_the_profiled_region(tmp_path, capsys):
+    """The kernel-trace summary averages the condensation dispatches that lie
+    between the first two profile marks only, and measures the idle gaps
+    between consecutive batched dispatches."""
+    kt = tmp_path / "kt" / "host"
+    kt.mkdir(parents=True)
+    with open(kt / "run_kernel_stats.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage",
+                                          "MinNs", "MaxNs", "StdDev"])
+        w.writeheader()
+        w.writerow({"Name": PREP, "Calls": 5, "TotalDurationNs": 5000, "AverageNs": 1000, "Percentage": 90,
+                    "MinNs": 900, "MaxNs": 1100, "StdDev": 10})
+    # a prep at t = 0 (before the region), two marks around three prep/finish
+    # pairs, and a prep after the region: only the three inside count
+    disp = [("cc::kb_prep_band<float, 3, 4, 128>", 0, 5000)]
+    disp.append(("cc::k_profile_mark()", 10000, 10001))
+    t = 20000
+    for dur in (1000, 2000, 3000):
+        disp.append(("cc::kb_prep_band<float, 3, 4, 128>", t, t + dur * 1000))
+        disp.append(("cc::kb_dm_finish<float, 3>", t + dur * 1000 + 2000, t + dur * 1000 + 12000))
+        t += dur * 1000 + 20000
+    disp.append(("cc::k_profile_mark()", t, t + 1))
+    disp.append(("cc::kb_prep_band<float, 3, 4, 128>", t + 10000, t + 10000 + 9000000))
+    with open(kt / "run_kernel_trace.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for name, a, e in disp:
+            w.writerow({"Kernel_Name": name, "Start_Timestamp": a, "End_Timestamp": e})
+    log = tmp_path / "bench.log"
+    log.write_text("[bench] progress\n" + json.dumps({"value": 1.0, "roofline": {"launches": 3,
+                                                                               "avg_launch_us": 2010.0}}) + "\n")
+    BC.trace_summary(str(tmp_path / "kt"), str(log))
+    out = capsys.readouterr().out
+    # (1000 + 2000 + 3000) / 3 us of prep, 10 us of finish
+    assert "The 3 dispatches of the uncaptured learned+batched region average 2000.0 + 10.0 = 2010.0 us" in out
+    assert "HIP-event average of the same launches in this run: 2010.0 us" in out
+    # gaps between consecutive kb_ dispatches: 15 us into the region, 2 us
+    # prep -> finish three times, 8 us finish -> next prep twice, 18 us out
+    assert "(< 50 us): 7 pairs, median 8.00 us" in out
